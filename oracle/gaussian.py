@@ -1,0 +1,229 @@
+"""Gaussian layer: covariance checks, Williamson form, Bogoliubov matrices,
+paired forms and the iterative Gaussian SVD (GSVD).
+
+Follows Sec. II.A (covariance formalism, Williamson's theorem, Eq. MUV,
+Eq. bmode, the mode-wise Schmidt form Eq. SchmidtD/SVD1), Sec. II.B
+(Eqs. SVD2-SVD3, bond state, the iterative decomposition for the first,
+bulk and last modes) and App. A (Eq. UV, Eq. M2UV, Eq. matrix_Q and the
+regularised Q_L).
+
+Conventions: xxpp ordering, vacuum Gamma = I/2; Williamson
+Gamma_AA = M (D + D) M^T / 2 with D descending, D_q >= 1 (Eq. symDiag).
+
+Readings of the paper taken here (each listed in the design doc):
+
+* The covariance of the residual state phi_R^m that the next GSVD step needs
+  is not written out.  phi_R^m is the original state with each active
+  Bogoliubov mode b_{L,q} relabelled as the virtual mode r_q (Eqs. SVD2-SVD3
+  and the footnote on absorbing Lambda into phi_R), with frozen b-modes in
+  vacuum.  Its covariance is therefore T Gamma T^T restricted to the active
+  b-quadratures and the right block, where T maps the L quadratures to the
+  b quadratures defined by Eq. bmode.
+* D* (the frozen-mode tolerance) is an argument; modes with D_q < D* are
+  frozen.
+* U is always invertible: U^dag U = 1 + V^dag V (Eq. UV).
+
+Parity: pinned in tests against closed forms (two-mode squeezed vacuum
+D = cosh 2r, symplecticity, reconstruction, Eq. UV residuals), against
+Williamson of the original principal blocks for every cut, and end to end
+through hafnian amplitudes.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+
+def omega(n: int) -> np.ndarray:
+    """Symplectic form [[0, 1], [-1, 0]] in xxpp order ([x_j, p_k] = i delta)."""
+    z = np.zeros((n, n))
+    e = np.eye(n)
+    return np.block([[z, e], [-e, z]])
+
+
+class GaussianInputError(ValueError):
+    def __init__(self, code: str, msg: str):
+        super().__init__(msg)
+        self.code = code
+
+
+def validate_gamma(gamma: np.ndarray, sym_tol=1e-10, pure_tol=1e-8) -> None:
+    """Check Gamma is real symmetric positive definite and pure (Sec. II.A).
+
+    Purity: Gamma = S S^T / 2 with S symplectic  <=>  (2 Gamma Omega)^2 = -1.
+    Tolerances are relative to max(1, |2 Gamma|_max)^2.
+    """
+    g = np.asarray(gamma, dtype=np.float64)
+    if g.ndim != 2 or g.shape[0] != g.shape[1] or g.shape[0] % 2:
+        raise GaussianInputError("INVAL", "Gamma must be 2M x 2M")
+    scale = max(1.0, float(np.max(np.abs(2 * g))))
+    if np.max(np.abs(g - g.T)) > sym_tol * scale:
+        raise GaussianInputError("NOT_PD", "Gamma is not symmetric")
+    try:
+        np.linalg.cholesky(g)
+    except np.linalg.LinAlgError:
+        raise GaussianInputError("NOT_PD", "Gamma is not positive definite")
+    n = g.shape[0] // 2
+    m = 2 * g @ omega(n)
+    res = np.max(np.abs(m @ m + np.eye(2 * n)))
+    if res > pure_tol * scale * scale:
+        raise GaussianInputError("NOT_PURE", f"Gamma is not pure (residual {res:.3e})")
+
+
+def williamson(gamma: np.ndarray):
+    """Williamson form Gamma = M (D + D) M^T / 2, D descending (Eq. symDiag).
+
+    Method: 2 Gamma = L L^T (Cholesky); A = L^T Omega L is antisymmetric with
+    eigenvalues of i A equal to +-D.  For the eigenvector w of i A with
+    eigenvalue D_k, u = sqrt2 Re w and v = sqrt2 Im w are orthonormal with
+    A u = D v, A v = -D u.  With O = [u_1..u_n, -v_1..-v_n] one has
+    O^T A O = [[0, D], [-D, 0]] and M = L O diag(D, D)^(-1/2) is symplectic
+    with 2 Gamma = M diag(D, D) M^T.
+    Returns (D, M).
+    """
+    g = np.asarray(gamma, dtype=np.float64)
+    n = g.shape[0] // 2
+    l = np.linalg.cholesky(2.0 * g)
+    a = l.T @ omega(n) @ l
+    w, vec = np.linalg.eigh(1j * a)
+    order = np.argsort(-w)[:n]          # the n positive eigenvalues, descending
+    dvals = w[order]
+    wv = vec[:, order]
+    u = np.sqrt(2.0) * wv.real
+    v = np.sqrt(2.0) * wv.imag
+    o = np.concatenate([u, -v], axis=1)
+    dg = np.concatenate([dvals, dvals])
+    m = l @ o @ np.diag(dg ** -0.5)
+    return dvals, m
+
+
+def bogoliubov_from_symplectic(m: np.ndarray):
+    """Invert Eq. MUV: M = [[-Im(U+V), -Re(U+V)], [Re(U-V), -Im(U-V)]]."""
+    n = m.shape[0] // 2
+    m11, m12, m21, m22 = m[:n, :n], m[:n, n:], m[n:, :n], m[n:, n:]
+    upv = -m12 - 1j * m11
+    umv = m21 - 1j * m22
+    return 0.5 * (upv + umv), 0.5 * (upv - umv)
+
+
+def bmode_quadrature_map(u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """T with xi_b = T xi_a for the b-modes of Eq. bmode.
+
+    b = U^dag a - V^dag a^dag with a = (x + i p)/sqrt2 and
+    b = (x_b + i p_b)/sqrt2 gives
+        x_b =  Re(U - V)^T x + Im(U + V)^T p
+        p_b = -Im(U - V)^T x + Re(U + V)^T p.
+    """
+    return np.block([[(u - v).real.T, (u + v).imag.T],
+                     [-(u - v).imag.T, (u + v).real.T]])
+
+
+def paired_q(u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Q = (U^dag)^-1 V^dag of a state annihilated by all b (Eq. matrix_Q)."""
+    return np.linalg.solve(u.conj().T, v.conj().T)
+
+
+def paired_q_left(u: np.ndarray, v: np.ndarray, n_active: int) -> np.ndarray:
+    """Paired-form matrix of phi_L = prod_q exp(b_q^dag l_q^dag)|0> (App. A):
+
+        Q_L = [[(U^dag)^-1 V^dag, (U^dag)^-1], [(U^*)^-1, -V^T (U^dag)^-1]]
+
+    restricted to the physical modes and the first n_active virtual modes
+    (projection of the auxiliary virtual modes onto their vacuum).
+    """
+    n = u.shape[0]
+    uinv_dag = np.linalg.inv(u.conj().T)
+    q = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    q[:n, :n] = uinv_dag @ v.conj().T
+    q[:n, n:] = uinv_dag
+    q[n:, :n] = np.linalg.inv(u.conj())
+    q[n:, n:] = -v.T @ uinv_dag
+    k = n + n_active
+    return q[:k, :k]
+
+
+@dataclasses.dataclass
+class Cut:
+    """Result of the GSVD at cut m (between site m and m+1, 1-based m)."""
+    D: np.ndarray            # all symplectic eigenvalues of the L block, descending
+    n_e: int                 # number of active (entangled) modes, D_q >= D*
+    Lam: np.ndarray          # Lambda_q = sqrt((D_q - 1)/(D_q + 1)), active only
+    frozen_weight: float     # sum over frozen q with D_q > 1 of Lambda_q^2
+
+
+@dataclasses.dataclass
+class GSVDResult:
+    Q: list                  # Q^m for sites m = 1..M, modes (r_{m-1}, a_m, l_m)
+    cuts: list               # Cut for m = 1..M-1
+    n_in: list               # n_e^{m-1} per site
+    n_out: list              # n_e^m per site
+
+
+def schmidt_lambda(d: np.ndarray) -> np.ndarray:
+    """Lambda_q = sqrt((D_q - 1)/(D_q + 1)) (Eq. SVD1)."""
+    d = np.asarray(d, dtype=np.float64)
+    return np.sqrt(np.clip((d - 1.0) / (d + 1.0), 0.0, None))
+
+
+def entropy(lam: np.ndarray) -> float:
+    """S = sum_q [-log(1-L^2) - L^2/(1-L^2) log L^2] (Sec. II.A)."""
+    l2 = np.asarray(lam, dtype=np.float64) ** 2
+    l2 = l2[l2 > 0]
+    return float(np.sum(-np.log1p(-l2) - l2 / (1 - l2) * np.log(l2)))
+
+
+def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10) -> GSVDResult:
+    """Iterative GSVD (Sec. II.B.2): first mode, bulk modes, last mode.
+
+    At step m the residual state lives on (r_{m-1}, a_m, ..., a_N).  The left
+    block L = (r_{m-1}, a_m) is brought to Williamson form; its active modes
+    (D_q >= D*) define the outgoing virtual modes l_m; the local state A^m has
+    pair matrix Q_L restricted to (r_{m-1}, a_m, l_m); the next residual has
+    the active b_L modes relabelled r_m.  The last site takes the pure
+    residual's own pair matrix (U^dag)^-1 V^dag.
+    """
+    g = np.asarray(gamma, dtype=np.float64)
+    N = g.shape[0] // 2
+    res = g.copy()           # residual covariance on (r_prev, a_m..a_N), xxpp
+    n_prev = 0
+    Qs, cuts, n_in, n_out = [], [], [], []
+    for m in range(1, N + 1):
+        n_tot = n_prev + (N - m + 1)
+        n_l = n_prev + 1
+        idx_l = np.r_[0:n_l, n_tot:n_tot + n_l]
+        g_ll = res[np.ix_(idx_l, idx_l)]
+        dvals, msym = williamson(g_ll)
+        u, v = bogoliubov_from_symplectic(msym)
+        if m == N:
+            Qs.append(paired_q(u, v))
+            n_in.append(n_prev)
+            n_out.append(0)
+            break
+        n_r = N - m
+        active = dvals >= dstar
+        n_e = int(min(np.count_nonzero(active), n_r))
+        lam = schmidt_lambda(dvals[:n_e])
+        fro = schmidt_lambda(dvals[n_e:])
+        cuts.append(Cut(D=dvals, n_e=n_e, Lam=lam, frozen_weight=float(np.sum(fro ** 2))))
+        Qs.append(paired_q_left(u, v, n_e))
+        n_in.append(n_prev)
+        n_out.append(n_e)
+        # Next residual: quadratures (x_b active, x_R, p_b active, p_R).
+        t = bmode_quadrature_map(u, v)                      # 2 n_l x 2 n_l
+        f = np.zeros((2 * (n_e + n_r), 2 * n_tot))
+        lcols = idx_l
+        f[np.ix_(np.arange(n_e), lcols)] = t[:n_e, :]
+        f[np.ix_(n_e + n_r + np.arange(n_e), lcols)] = t[n_l:n_l + n_e, :]
+        f[n_e + np.arange(n_r), n_l + np.arange(n_r)] = 1.0
+        f[2 * n_e + n_r + np.arange(n_r), n_tot + n_l + np.arange(n_r)] = 1.0
+        res = f @ res @ f.T
+        res = 0.5 * (res + res.T)
+        n_prev = n_e
+    return GSVDResult(Q=Qs, cuts=cuts, n_in=n_in, n_out=n_out)
+
+
+def mean_photons(gamma: np.ndarray) -> np.ndarray:
+    """<n_j> = (Gamma_xjxj + Gamma_pjpj - 1)/2 for vacuum = I/2."""
+    g = np.asarray(gamma)
+    n = g.shape[0] // 2
+    return 0.5 * (np.diag(g)[:n] + np.diag(g)[n:] - 1.0)

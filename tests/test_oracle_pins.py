@@ -1,0 +1,365 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, brute force on tiny inputs, invariants and library routines on special
+cases.  No test here needs a GPU.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import build, gaussian as G, hafnian as H, kept as K, mps as P, pco, recurrence as R
+
+
+def perm(b):
+    n = b.shape[0]
+    return sum(np.prod([b[i, s[i]] for i in range(n)]) for s in itertools.permutations(range(n)))
+
+
+def tmsv(r):
+    """Two-mode squeezed vacuum: squeezers (r, -r) through a 50:50 beamsplitter."""
+    u = np.array([[1, -1], [1, 1]], dtype=np.complex128) / np.sqrt(2)
+    return np.array([r, -r]), u
+
+
+# ---------------------------------------------------------------- hafnian
+
+def test_hafnian_closed_forms():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    a = a + a.T
+    assert H.hafnian(a[:2, :2]) == pytest.approx(a[0, 1])
+    want = a[0, 1] * a[2, 3] + a[0, 2] * a[1, 3] + a[0, 3] * a[1, 2]
+    assert H.hafnian(a) == pytest.approx(want)
+    for n in range(1, 5):  # all-ones 2n x 2n: (2n-1)!!
+        assert H.hafnian(np.ones((2 * n, 2 * n))).real == pytest.approx(math.prod(range(1, 2 * n, 2)))
+    assert H.hafnian(np.ones((3, 3))) == 0
+    b = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    blk = np.block([[np.zeros((3, 3)), b], [b.T, np.zeros((3, 3))]])
+    assert H.hafnian(blk) == pytest.approx(perm(b))
+
+
+def test_single_mode_squeezed_vacuum_closed_form():
+    r = 0.7
+    t = np.tanh(r)
+    q = np.array([[t]])
+    assert H.vacuum_amplitude(q) == pytest.approx(np.cosh(r) ** -0.5)
+    tot = 0.0
+    for k in range(0, 40):
+        want = t ** k * math.sqrt(math.factorial(2 * k)) / (2 ** k * math.factorial(k))
+        assert H.fock_amplitude(q, (2 * k,)).real == pytest.approx(want, rel=1e-12) if k < 8 else True
+        assert H.fock_amplitude(q, (2 * k + 1,)) == 0 if k < 8 else True
+        tot += np.cosh(r) ** -1 * want ** 2
+    assert tot == pytest.approx(1.0, abs=1e-9)
+
+
+# ------------------------------------------------------- Gaussian layer
+
+def test_gamma_of_circuit_matches_second_moments():
+    """Gamma from the circuit's symplectic equals the one from <a^dag a>, <a a>."""
+    w = W.workload("c1")
+    sh, ch = np.sinh(w.r), np.cosh(w.r)
+    n = w.U.conj() @ np.diag(sh ** 2) @ w.U.T
+    a = w.U @ np.diag(sh * ch) @ w.U.T
+    gxx = (a + n).real + 0.5 * np.eye(w.M)
+    gpp = (n - a).real + 0.5 * np.eye(w.M)
+    gxp = (a + n).imag
+    g2 = np.block([[gxx, gxp], [gxp.T, gpp]])
+    assert np.max(np.abs(g2 - w.gamma)) < 1e-12
+    assert np.sum(G.mean_photons(w.gamma)) == pytest.approx(w.mean_photons)
+
+
+def test_williamson_two_mode_squeezed_vacuum():
+    r = 0.45
+    rr, u = tmsv(r)
+    g = W.gamma_of_circuit(rr, u)
+    d1, m1 = G.williamson(g[np.ix_([0, 2], [0, 2])])
+    assert d1[0] == pytest.approx(np.cosh(2 * r), rel=1e-13)
+    d, m = G.williamson(g)
+    assert np.allclose(d, 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_williamson_reconstruction_and_symplectic(seed):
+    rng = np.random.default_rng(seed)
+    w = W.custom(6, 4, 8, (0.2, 0.9), "haar", seed)
+    g = w.gamma
+    for k in range(1, 6):
+        idx = np.r_[0:k, 6:6 + k]
+        gb = g[np.ix_(idx, idx)]
+        d, m = G.williamson(gb)
+        om = G.omega(k)
+        assert np.max(np.abs(m @ om @ m.T - om)) < 1e-11
+        assert np.max(np.abs(0.5 * m @ np.diag(np.r_[d, d]) @ m.T - gb)) < 1e-11
+        assert np.all(np.diff(d) <= 1e-12) and np.all(d >= 1 - 1e-12)
+        # symplectic eigenvalues from the spectrum of i Omega (2 Gamma)
+        ev = np.sort(np.abs(np.linalg.eigvals(1j * om @ (2 * gb))))[::-1][::2]
+        assert np.allclose(ev, d, rtol=1e-10)
+
+
+def test_bogoliubov_constraints_and_pair_matrix():
+    w = W.workload("c1")
+    d, m = G.williamson(w.gamma)
+    u, v = G.bogoliubov_from_symplectic(m)
+    e = np.eye(w.M)
+    assert np.max(np.abs(u.conj() @ u.T - v @ v.conj().T - e)) < 1e-12
+    assert np.max(np.abs(v.conj() @ u.T - u @ v.conj().T)) < 1e-12
+    assert np.max(np.abs(u.conj().T @ u - v.conj().T @ v - e)) < 1e-12
+    assert np.max(np.abs(u.T @ v - v.T @ u)) < 1e-12
+    q = G.paired_q(u, v)
+    assert np.max(np.abs(q - q.T)) < 1e-12
+    assert np.max(np.abs(q - w.Q)) < 1e-12        # the circuit's own pair matrix
+    # b-mode quadrature map: the b-modes are in Williamson form (pure: vacuum)
+    t = G.bmode_quadrature_map(u, v)
+    assert np.max(np.abs(t @ w.gamma @ t.T - 0.5 * np.eye(2 * w.M))) < 1e-11
+
+
+def test_validate_gamma_rejects():
+    w = W.workload("c1")
+    G.validate_gamma(w.gamma)
+    bad = w.gamma.copy()
+    bad[0, 1] += 1e-3
+    with pytest.raises(G.GaussianInputError) as e:
+        G.validate_gamma(bad)
+    assert e.value.code == "NOT_PD"
+    with pytest.raises(G.GaussianInputError) as e:
+        G.validate_gamma(-w.gamma)
+    assert e.value.code == "NOT_PD"
+    with pytest.raises(G.GaussianInputError) as e:
+        G.validate_gamma(w.gamma + 0.1 * np.eye(16))   # thermal noise: mixed
+    assert e.value.code == "NOT_PURE"
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_gsvd_cut_spectra_match_direct_williamson(name):
+    """P4a: the chain's spectrum at cut m equals Williamson of Gamma_[1..m]."""
+    w = W.workload(name)
+    g = w.gamma
+    gs = G.gsvd(g)
+    for m, cut in enumerate(gs.cuts, start=1):
+        idx = np.r_[0:m, w.M:w.M + m]
+        d, _ = G.williamson(g[np.ix_(idx, idx)])
+        k = cut.n_e
+        assert np.allclose(cut.D[:k], d[:k], rtol=1e-10, atol=1e-10), m
+        assert np.all(d[k:] < 1 + 1e-9)
+        lam2 = (d[:k] - 1) / (d[:k] + 1)
+        assert np.allclose(cut.Lam ** 2, lam2, rtol=1e-9, atol=1e-10)
+
+
+def test_gaussian_reconstruction_two_sites():
+    """P4b: contracting the untruncated local Gaussians of a 2-mode state
+    over the bond reproduces the global pair matrix (Eq. GMPS)."""
+    rr = np.array([0.6, 0.3])
+    u = W.haar_unitary(2, np.random.default_rng(5))
+    g = W.gamma_of_circuit(rr, u)
+    gs = G.gsvd(g)
+    q1, q2 = gs.Q                     # q1 on (a1, l1); q2 on (r1, a2)
+    # <I| contraction: integrate the shared virtual pair; Gaussian formula
+    bmat = np.array([[q1[0, 1], 0], [0, q2[1, 0]]])
+    inner = np.array([[-q1[1, 1], 1.0], [1.0, -q2[0, 0]]])
+    q = np.diag([q1[0, 0], q2[1, 1]]) + bmat @ np.linalg.solve(inner, bmat.T)
+    assert np.max(np.abs(q - W.pair_matrix_of_circuit(rr, u))) < 1e-12
+
+
+def test_entropy_closed_form():
+    lam = np.array([0.3, 0.55])
+    s = 0.0
+    for l in lam:
+        p = (1 - l ** 2) * l ** (2 * np.arange(400))
+        s += -np.sum(p[p > 0] * np.log(p[p > 0]))
+    assert G.entropy(lam) == pytest.approx(s, rel=1e-12)
+
+
+# --------------------------------------------------------- kept subspace
+
+def test_tmsv_chain_closed_form():
+    """P3: two-mode squeezed vacuum: one entangled pair with Lambda = tanh r,
+    kept set {0..chi-1}, eps = Lambda^(2 chi), |A^1| = delta_{p beta},
+    |A^2_{alpha p}| = Lambda^alpha delta_{alpha p}."""
+    r, chi, d = 0.5, 6, 8
+    rr, u = tmsv(r)
+    o = build.build_mps(W.gamma_of_circuit(rr, u), d, chi)
+    assert o.n_e == [1]
+    assert o.Lam[0][0] == pytest.approx(np.tanh(r), rel=1e-12)
+    assert o.bases[1] == [(k,) for k in range(chi)]
+    assert o.eps[0] == pytest.approx(np.tanh(r) ** (2 * chi), rel=1e-9)
+    a1, a2 = np.abs(o.raw[0][0]), np.abs(o.raw[1][:, :, 0])
+    assert np.allclose(a1, np.eye(d, chi), atol=1e-12)
+    lam = np.tanh(r)
+    want = np.zeros((chi, d))
+    for k in range(chi):
+        want[k, k] = lam ** k
+    assert np.allclose(a2, want, atol=1e-12)
+
+
+def test_kept_basis_product_of_pairs_and_closure():
+    lam = np.array([0.6, 0.5, 0.2])
+    states, en = K.kept_basis(lam, 25)
+    e = -2 * np.log(lam)
+    allst = sorted(itertools.product(range(12), repeat=3), key=lambda s: (float(np.dot(s, e)), s))
+    assert states == [tuple(s) for s in allst[:25]]
+    assert np.allclose(en, [np.dot(s, e) for s in states])
+    sset = set(states)
+    for s in states:                       # downward closure
+        for q in range(3):
+            if s[q]:
+                assert s[:q] + (s[q] - 1,) + s[q + 1:] in sset
+    # tie-break: equal Lambdas are ordered by ascending occupation tuple
+    st, _ = K.kept_basis(np.array([0.5, 0.5]), 3)
+    assert st == [(0, 0), (0, 1), (1, 0)]
+    # eps from its definition against the geometric closed form for one mode
+    s1, e1 = K.kept_basis(np.array([0.4]), 7)
+    assert K.truncation_error(np.array([0.4]), e1) == pytest.approx(0.4 ** 14, rel=1e-10)
+    assert K.bond_dimension_for(np.array([0.4]), 0.4 ** 14 * 1.01) == 7
+
+
+# ------------------------------------------------------------- tensors
+
+def _check_tensor_vs_hafnian(q, bl, br, d, a, max_photons=10):
+    err = 0.0
+    for i, sa in enumerate(bl):
+        for p in range(d):
+            for j, sb in enumerate(br):
+                n = tuple(sa) + (p,) + tuple(sb)
+                if sum(n) > max_photons:
+                    continue
+                err = max(err, abs(H.fock_amplitude(q, n) - a[i, p, j]))
+    return err
+
+
+def test_pco_tensor_entries_equal_hafnians():
+    """P1: every entry A_{alpha p beta} equals haf(Q_[n]) / sqrt(n!)."""
+    w = W.workload("c1")
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    for m in range(1, w.M + 1):
+        err = _check_tensor_vs_hafnian(o.Q[m - 1], o.bases[m - 1], o.bases[m], w.d, o.raw[m - 1])
+        assert err < 1e-13, (m, err)
+
+
+def test_pco_equals_independent_recurrence():
+    """P9 on a larger case (brick-wall, 8 layers)."""
+    w = W.custom(12, 5, 24, (0.3, 1.0), ("brick", 6), 7)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    for m in range(1, w.M + 1):
+        ref = R.tensor_by_recurrence(o.Q[m - 1], o.bases[m - 1], o.bases[m], w.d)
+        assert np.max(np.abs(ref - o.raw[m - 1])) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_parity_of_tensors_and_amplitudes():
+    """P5: entries with odd total photon number vanish."""
+    w = W.workload("c1")
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    for m in range(1, w.M + 1):
+        bl, br = o.bases[m - 1], o.bases[m]
+        a = o.raw[m - 1]
+        for i, sa in enumerate(bl):
+            for p in range(w.d):
+                for j, sb in enumerate(br):
+                    if (sum(sa) + p + sum(sb)) % 2:
+                        assert a[i, p, j] == 0
+
+
+def test_norm_by_brute_force():
+    """P6: sum |amplitude|^2 over all d^M patterns is 1 after normalisation."""
+    w = W.custom(5, 3, 8, (0.3, 0.9), "haar", 11)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    pats = list(itertools.product(range(w.d), repeat=w.M))
+    amps = P.amplitudes(o.tensors, pats)
+    assert np.sum(np.abs(amps) ** 2) == pytest.approx(1.0, abs=1e-12)
+    assert P.amplitude(o.tensors, [0] * w.M).real > 0
+    assert abs(P.amplitude(o.tensors, [0] * w.M).imag) < 1e-15
+    # odd totals are exactly zero
+    odd = [p for p in pats if sum(p) % 2]
+    assert np.max(np.abs(P.amplitudes(o.tensors, odd))) == 0
+
+
+def test_product_of_squeezers_closed_form():
+    """P2: U = identity: every cut unentangled, bond dimension 1, and
+    A^m[2k] proportional to tanh(r)^k sqrt((2k)!)/(2^k k!)."""
+    rr = np.array([0.3, 0.8, 0.5])
+    o = build.build_mps(W.gamma_of_circuit(rr, np.eye(3)), 7, 4)
+    assert o.n_e == [0, 0]
+    for m, r in enumerate(rr):
+        a = o.raw[m]
+        assert a.shape == (1, 7, 1)
+        t = np.tanh(r)
+        want = np.zeros(7)
+        for k in range(4):
+            want[2 * k] = t ** k * math.sqrt(math.factorial(2 * k)) / (2 ** k * math.factorial(k))
+        got = a[0, :, 0] / a[0, 0, 0]
+        assert np.allclose(np.abs(got), want, atol=1e-13)
+
+
+def test_vacuum_ratio_converges_to_hafnians():
+    """P8 / S20(iii): psi(n)/psi(0) -> haf(Q_n)/sqrt(n!) as chi grows."""
+    w = W.workload("c1")
+    pats = [p for p in itertools.product(range(w.d), repeat=w.M) if sum(p) <= 4][::7]
+    exact = np.array([H.fock_amplitude(w.Q, p) for p in pats])
+    errs = []
+    for chi in (8, 32, 128):
+        o = build.build_mps(w.gamma, w.d, chi)
+        amp = P.amplitudes(o.tensors, pats)
+        errs.append(np.max(np.abs(amp / amp[0] - exact)))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-2
+
+
+def test_mean_photon_number_approaches_gaussian_value():
+    """P7: MPS mean photon number vs the exact Gaussian one, close for a
+    weakly squeezed chain (small cutoff effects)."""
+    w = W.custom(10, 6, 64, (0.1, 0.3), ("brick", 4), 3)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    got = np.sum(P.mean_photons(o.tensors))
+    assert got == pytest.approx(w.mean_photons, rel=2e-3)
+
+
+def test_exact_marginals_against_brute_force():
+    w = W.custom(5, 3, 8, (0.3, 0.9), "haar", 11)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    pats = np.array(list(itertools.product(range(w.d), repeat=w.M)))
+    prob = np.abs(P.amplitudes(o.tensors, pats)) ** 2
+    pm = P.site_marginals(o.tensors)
+    for m in range(w.M):
+        for p in range(w.d):
+            assert pm[m, p] == pytest.approx(prob[pats[:, m] == p].sum(), abs=1e-12)
+    tot = P.total_photon_distribution(o.tensors)
+    for n in range(len(tot)):
+        assert tot[n] == pytest.approx(prob[pats.sum(1) == n].sum(), abs=1e-12)
+
+
+def test_sampler_statistics():
+    w = W.custom(6, 4, 16, (0.3, 0.8), "haar", 12)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    shots = 4000
+    s = P.sample(o.tensors, shots, np.random.default_rng(0))
+    assert np.all(s.sum(1) % 2 == 0)
+    pm = P.site_marginals(o.tensors)
+    for m in range(w.M):
+        emp = np.bincount(s[:, m], minlength=w.d) / shots
+        floor = 0.5 * np.sum(np.sqrt(2 * pm[m] / (np.pi * shots)))
+        assert 0.5 * np.abs(emp - pm[m]).sum() < 4 * floor + 1e-3
+
+
+def test_fidelity_overlap_and_svd_truncation():
+    w = W.workload("c1")
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    t = o.tensors
+    assert P.fidelity(t, t) == pytest.approx(1.0, abs=1e-13)
+    # gauge transform on one bond leaves the state unchanged
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((t[2].shape[2],) * 2) + 1j * rng.standard_normal((t[2].shape[2],) * 2)
+    t2 = [a.copy() for a in t]
+    t2[2] = np.einsum("apb,bc->apc", t2[2], x)
+    t2[3] = np.einsum("cb,bpd->cpd", np.linalg.inv(x), t2[3])
+    assert P.fidelity(t, t2) == pytest.approx(1.0, abs=1e-12)
+    tt, sv = P.svd_truncate(t, w.chi)
+    pats = [p for p in itertools.product(range(w.d), repeat=w.M) if sum(p) <= 6]
+    assert np.max(np.abs(P.amplitudes(tt, pats) - P.amplitudes(t, pats))) < 1e-12
+    # right-canonical after the sweep
+    for a in tt[1:]:
+        mat = a.reshape(a.shape[0], -1)
+        assert np.max(np.abs(mat @ mat.conj().T - np.eye(a.shape[0]))) < 1e-12
+    assert tt[0].shape[2] <= w.d                       # edge rank cut to d
