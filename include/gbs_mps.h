@@ -1,0 +1,139 @@
+/* gbs_mps.h -- C ABI of the MI355X Gaussian-state -> MPS library.
+ *
+ * Converts a pure M-mode bosonic Gaussian state, given by its covariance
+ * matrix, into a matrix product state with photon cutoff d and bond
+ * dimension chi, following arXiv 2512.10643 (Liu, Jin, Xiang, Tu):
+ * per-cut Gaussian SVD (Sec. II.B), kept virtual bases by entanglement
+ * energy (Sec. II.C.1), local tensors by projected creation operators
+ * (Sec. II.C.2, App. B), then SVD truncation / canonicalisation, and the MPS
+ * consumers: amplitudes and photon-number samples (Sec. I, Sec. III).
+ *
+ * Conventions
+ *   - All array arguments are DEVICE pointers on the current HIP device
+ *     unless marked "host".  `stream` is a hipStream_t (may be NULL for the
+ *     default stream).
+ *   - Matrices are row-major.  Complex outputs are interleaved (re, im).
+ *   - Return value: GBS_OK (0) or a negative GBS_E_* code; the library never
+ *     aborts and never throws across this boundary.  gbs_last_error() gives a
+ *     thread-local message for the last failure.
+ *   - Thread safety: distinct handles may be used concurrently; one handle
+ *     is read-only after gbs_mps_build and may serve concurrent
+ *     amplitude/sample calls on different streams.
+ */
+#ifndef GBS_MPS_H
+#define GBS_MPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gbs_mps_s* gbs_mps;
+
+enum {
+  GBS_OK = 0,
+  GBS_E_INVAL = -1,     /* bad argument: M<1, d<1, chi<1 or > 4096, dstar<=1, NULL pointer, pattern outside [0,d) */
+  GBS_E_NOT_PD = -2,    /* Gamma not symmetric positive definite (Sec. II.A) */
+  GBS_E_NOT_PURE = -3,  /* Gamma is not the covariance of a pure state: (2 Gamma Omega)^2 != -1 */
+  GBS_E_NOMEM = -4,     /* device allocation failed or footprint above budget */
+  GBS_E_DEVICE = -5,    /* HIP runtime error */
+  GBS_E_BUSY = -6,      /* serving queue full */
+  GBS_E_INTERNAL = -7   /* numerical failure (Jacobi non-convergence, index map) */
+};
+
+typedef enum {
+  GBS_FP64 = 0,   /* complex FP64 tensors and contractions */
+  GBS_FP32 = 1,   /* complex FP32 tensors and contractions; FP64 Gaussian SVD and singular values */
+  GBS_BF16X3 = 2  /* FP32 tensors; bond contractions by split-BF16x3 compensated products */
+} gbs_precision;
+
+/* Build options.  d: photon cutoff (p <= d-1 per mode, Sec. II.C.1);
+ * chi: bond dimension D (Sec. II.C, Eq. Am_definition); dstar: frozen-mode
+ * tolerance D* > 1 (Sec. II.A; modes with symplectic eigenvalue below it are
+ * treated as unentangled); trunc_rel: singular values below
+ * trunc_rel * sigma_max are dropped by the truncation sweep (0 selects the
+ * default, 1e-12 for FP64 and 1e-6 for FP32 builds); flags: GBS_KEEP_RAW keeps
+ * the PCO tensors for gbs_mps_export. */
+#define GBS_KEEP_RAW 1u
+typedef struct {
+  int32_t d;
+  int32_t chi;
+  double dstar;
+  int32_t prec;      /* gbs_precision */
+  uint32_t flags;
+  double trunc_rel;
+} gbs_build_opts;
+
+/* Build the MPS of the pure state with covariance `gamma`.
+ *   gamma : device, 2M x 2M FP64, row-major, quadratures ordered
+ *           (x_1..x_M, p_1..p_M), vacuum = identity/2 (Sec. II.A, Eq. GammaMat;
+ *           App. A, Gamma = M M^T / 2).  Read during the call only.
+ *   opt   : host pointer to options.
+ *   out   : host pointer receiving the handle (NULL on failure).
+ * Validates Gamma (symmetric, positive definite, pure), runs the Gaussian SVD
+ * chain (Sec. II.B.2), the kept-basis selection (Sec. II.C.1), the PCO
+ * tensor construction (Sec. II.C.2) and the truncation sweep, and leaves a
+ * right-canonical, unit-norm MPS whose vacuum amplitude is real > 0.
+ * Synchronises `stream` internally (buffer sizes depend on the spectra). */
+int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out);
+
+/* Amplitudes <n|psi> of the normalised MPS for B occupation patterns.
+ *   patterns : device, B x M int32, 0 <= n < d.
+ *   out      : device, B x 2 FP64 (re, im).
+ * Synchronises `stream` to report invalid patterns (GBS_E_INVAL; their
+ * outputs are NaN). */
+int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out, void* stream);
+
+/* Draw `shots` photon-number samples by sequential conditional sampling on
+ * the right-canonical MPS (the "standard MPS sampling" the paper defers to,
+ * Sec. I).  Random numbers: Philox-4x32-10 keyed by `seed`, counter (shot,
+ * site), so results do not depend on batching.
+ *   out : device, shots x M int32.  Asynchronous on `stream`. */
+int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
+
+/* Scalar information about a handle (host struct). */
+typedef struct {
+  int32_t M, d, chi, prec;
+  int32_t max_bond;        /* largest bond dimension after truncation */
+  int32_t max_ne;          /* largest number of entangled mode pairs at a cut */
+  double eps_max;          /* max over cuts of the discarded weight eps_m (Sec. III.A) */
+  double norm_raw;         /* norm of the MPS before normalisation */
+  int64_t bytes;           /* device bytes held by the handle */
+  int64_t pco_updates;     /* tensor elements produced by the PCO level gather */
+  double t_gsvd_ms, t_kept_ms, t_pco_ms, t_svd_ms;  /* build phase times */
+} gbs_mps_info_t;
+
+/* Fill `info`; optional host arrays (may be NULL):
+ *   bond  : M+1 int32, bond dimensions after truncation (bond[0] = bond[M] = 1);
+ *   ne    : M+1 int32, entangled pairs n_e^m per cut (ne[0] = ne[M] = 0);
+ *   eps   : M+1 FP64, discarded weight per cut (Sec. III.A);
+ *   entropy: M+1 FP64, entanglement entropy per cut (Sec. II.A). */
+int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, double* eps, double* entropy);
+
+/* Copy diagnostic data to host memory (tests).  what:
+ *   GBS_EXPORT_TENSOR : canonical tensor of site m (1-based), complex FP64,
+ *                       bond[m-1] x d x bond[m];
+ *   GBS_EXPORT_RAW    : PCO tensor of site m before truncation, complex FP64,
+ *                       kept[m-1] x d x kept[m] (needs GBS_KEEP_RAW);
+ *   GBS_EXPORT_Q      : pair matrix Q^m of site m, complex FP64, n x n with
+ *                       n = ne[m-1] + 1 + ne[m];
+ *   GBS_EXPORT_BASIS  : kept basis of cut m (0..M), int32 kept[m] x ne[m];
+ *   GBS_EXPORT_LAMBDA : Lambda_q of cut m (1..M-1), FP64, ne[m] values;
+ *   GBS_EXPORT_SVALS  : singular values of bond m after truncation, FP64.
+ * `dst` is a host buffer of `cap` bytes; the number of bytes written is
+ * returned through *written (host, may be NULL). */
+enum { GBS_EXPORT_TENSOR = 0, GBS_EXPORT_RAW = 1, GBS_EXPORT_Q = 2, GBS_EXPORT_BASIS = 3, GBS_EXPORT_LAMBDA = 4,
+       GBS_EXPORT_SVALS = 5 };
+int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, int64_t* written);
+
+/* Release every device buffer of the handle. NULL is ignored. */
+void gbs_mps_free(gbs_mps h);
+
+/* Thread-local message for the last failing call on this thread. */
+const char* gbs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBS_MPS_H */

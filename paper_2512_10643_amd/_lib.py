@@ -1,0 +1,82 @@
+"""ctypes binding of the C ABI in include/gbs_mps.h (argument marshalling only).
+
+Every step of the conversion runs inside libgbs_mps.so on the GPU; PyTorch
+provides device memory and the current stream.  Importing this module never
+falls back to a CPU implementation: if the shared library is missing the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgbs_mps.so")
+
+GBS_OK, GBS_E_INVAL, GBS_E_NOT_PD, GBS_E_NOT_PURE, GBS_E_NOMEM, GBS_E_DEVICE, GBS_E_BUSY, GBS_E_INTERNAL = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+ERROR_NAMES = {0: "OK", -1: "INVAL", -2: "NOT_PD", -3: "NOT_PURE", -4: "NOMEM", -5: "DEVICE", -6: "BUSY",
+               -7: "INTERNAL"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+GBS_KEEP_RAW = 1
+EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5}
+
+# Symbols declared in include/gbs_mps.h (checked by the CPU tests).
+EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_info", "gbs_mps_export",
+                    "gbs_mps_free", "gbs_last_error")
+
+
+class GbsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERROR_NAMES.get(code, str(code))
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("chi", ctypes.c_int32), ("dstar", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32), ("trunc_rel", ctypes.c_double)]
+
+
+class InfoT(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("d", ctypes.c_int32), ("chi", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_bond", ctypes.c_int32), ("max_ne", ctypes.c_int32), ("eps_max", ctypes.c_double),
+                ("norm_raw", ctypes.c_double), ("bytes", ctypes.c_int64), ("pco_updates", ctypes.c_int64),
+                ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
+                ("t_svd_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgbs_mps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build the HIP library first "
+                              "(python -m paper_2512_10643_amd.build_lib)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+        L.gbs_mps_build.argtypes = [dp, i32, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
+        L.gbs_mps_build.restype = ctypes.c_int
+        L.gbs_mps_amplitude.argtypes = [vp, dp, i64, dp, vp]
+        L.gbs_mps_amplitude.restype = ctypes.c_int
+        L.gbs_mps_sample.argtypes = [vp, i64, u64, dp, vp]
+        L.gbs_mps_sample.restype = ctypes.c_int
+        L.gbs_mps_info.argtypes = [vp, ctypes.POINTER(InfoT), dp, dp, dp, dp]
+        L.gbs_mps_info.restype = ctypes.c_int
+        L.gbs_mps_export.argtypes = [vp, i32, i32, dp, i64, ctypes.POINTER(i64)]
+        L.gbs_mps_export.restype = ctypes.c_int
+        L.gbs_mps_free.argtypes = [vp]
+        L.gbs_mps_free.restype = None
+        L.gbs_last_error.argtypes = []
+        L.gbs_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != GBS_OK:
+        msg = lib().gbs_last_error()
+        raise GbsError(rc, msg.decode() if msg else "")

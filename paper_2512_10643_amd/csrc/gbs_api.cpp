@@ -1,0 +1,822 @@
+// Host orchestration of the build, amplitude and sampling paths behind the
+// C ABI declared in include/gbs_mps.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gbs_mps.h"
+#include "gbs_common.h"
+#include "gbs_gsvd.h"
+#include "gbs_kept.h"
+#include "gbs_linalg.h"
+#include "gbs_mpsops.h"
+#include "gbs_pco.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int set_hip_error(hipError_t e, const char* what) {
+  (void)hipGetLastError();
+  return fail(e == hipErrorOutOfMemory ? GBS_E_NOMEM : GBS_E_DEVICE,
+              std::string("HIP error '") + hipGetErrorString(e) + "' in " + what);
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Owning device allocation list.
+struct DevArena {
+  std::vector<void*> ptrs;
+  int64_t bytes = 0;
+  hipError_t alloc(void** p, size_t n) {
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(p, n);
+    if (e == hipSuccess) {
+      ptrs.push_back(*p);
+      bytes += (int64_t)n;
+    }
+    return e;
+  }
+  void release_all() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  ~DevArena() { release_all(); }
+};
+
+template <typename T>
+hipError_t dalloc(DevArena& ar, T** p, size_t count) {
+  return ar.alloc((void**)p, count * sizeof(T));
+}
+
+const char* deverr_msg(int code) {
+  switch (code) {
+    case GBS_DEVERR_NOT_PD: return "covariance block not positive definite (Cholesky pivot <= 0)";
+    case GBS_DEVERR_NOT_PURE: return "covariance matrix is not pure";
+    case GBS_DEVERR_WILLIAMSON: return "symplectic pairing of the Williamson form failed";
+    case GBS_DEVERR_SINGULAR: return "Bogoliubov matrix U is singular";
+    case GBS_DEVERR_HASH: return "kept-basis index lookup failed";
+    case GBS_DEVERR_KMAX: return "size limit exceeded (too many occupied modes or entangled pairs)";
+    case GBS_DEVERR_JACOBI: return "Jacobi eigensolver did not converge";
+    default: return "unknown device error";
+  }
+}
+
+}  // namespace
+
+struct gbs_mps_s {
+  int M = 0, d = 0, chi = 0, prec = 0;
+  double dstar = 0, trunc_rel = 0;
+  uint32_t flags = 0;
+  DevArena keep;                 // buffers that live with the handle
+  std::vector<int> ne, kept, bond;
+  std::vector<double> eps, entropy;
+  std::vector<std::vector<double>> lam;   // active Lambda per cut
+  std::vector<std::vector<double>> svals; // singular values per bond
+  double norm_raw = 0;
+  int64_t pco_updates = 0;
+  double t_gsvd = 0, t_kept = 0, t_pco = 0, t_svd = 0;
+  // canonical tensors
+  void* tens = nullptr;          // contiguous, element size esz
+  size_t esz = 16;
+  std::vector<long> toff;        // per site offset (elements)
+  void** site_ptrs = nullptr;    // device array of per-site pointers
+  int* bond_dev = nullptr;
+  int maxbond = 1;
+  // diagnostics
+  cplx64* Q = nullptr;
+  long q_stride = 0, ld_q = 0;
+  cplx64* raw = nullptr;         // PCO tensors (GBS_KEEP_RAW)
+  std::vector<long> raw_off;
+  short* occ = nullptr;
+  std::vector<long> occ_off;
+  int* err = nullptr;
+};
+
+namespace {
+
+template <typename C>
+C cone() {
+  return cmake<C>(1, 0);
+}
+template <typename C>
+C czero() {
+  return cmake<C>(0, 0);
+}
+
+// Canonicalisation and truncation (precision C for contractions; FP64 eigen).
+template <typename C>
+int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64, const std::vector<long>& t64off) {
+  const int M = h->M, d = h->d;
+  const double tau = h->trunc_rel > 0 ? h->trunc_rel * h->trunc_rel : (std::is_same<C, cplx64>::value ? 1e-24 : 1e-12);
+  // working tensors A^m in precision C, dims (cl, d, cr)
+  std::vector<int> cl(M + 1), cr(M + 1);
+  std::vector<C*> A(M + 1, nullptr);
+  for (int m = 1; m <= M; ++m) {
+    cl[m] = h->kept[m - 1];
+    cr[m] = h->kept[m];
+    long n = (long)cl[m] * d * cr[m];
+    HIP_CHECK_RET(dalloc(tmp, &A[m], n));
+    HIP_CHECK_RET(convert<C, cplx64>(st, A[m], T64 + t64off[m], n));
+  }
+  const int chi_ld = *std::max_element(h->kept.begin(), h->kept.end()) * d + 1;
+  cplx64 *G64, *Vtmp, *Vec;
+  double* w64;
+  int* jerr = h->err;
+  HIP_CHECK_RET(dalloc(tmp, &G64, (size_t)chi_ld * chi_ld));
+  HIP_CHECK_RET(dalloc(tmp, &Vtmp, (size_t)chi_ld * chi_ld));
+  HIP_CHECK_RET(dalloc(tmp, &Vec, (size_t)chi_ld * chi_ld));
+  HIP_CHECK_RET(dalloc(tmp, &w64, (size_t)chi_ld));
+  C *Gc, *Uc, *Xc;
+  HIP_CHECK_RET(dalloc(tmp, &Gc, (size_t)chi_ld * chi_ld));
+  HIP_CHECK_RET(dalloc(tmp, &Uc, (size_t)chi_ld * chi_ld));
+  HIP_CHECK_RET(dalloc(tmp, &Xc, (size_t)chi_ld * chi_ld * d));
+  std::vector<double> wh(chi_ld);
+
+  // small Hermitian eigenproblem: Gc (n x n, ld n) -> w (desc), Vec (ld n)
+  auto eig_small = [&](int n) -> int {
+    HIP_CHECK_RET(convert<cplx64, C>(st, G64, Gc, (long)n * n));
+    HIP_CHECK_RET(jacobi_herm(st, G64, Vtmp, w64, nullptr, n, 0, 1, jerr, Vec));
+    HIP_CHECK_RET(hipMemcpyAsync(wh.data(), w64, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK_RET(hipStreamSynchronize(st));
+    return 0;
+  };
+  auto keep_count = [&](int n) {
+    int r = 0;
+    for (int k = 0; k < n; ++k)
+      if (wh[k] > tau * wh[0] && wh[k] > 0.0) ++r;
+    return std::max(r, 1);
+  };
+  double* wdev;  // per-eigenproblem weights
+  HIP_CHECK_RET(dalloc(tmp, &wdev, (size_t)chi_ld));
+
+  // (1) left edge: bond m may be cut to rank(A^m as (cl d) x cr) when cl d < cr.
+  for (int m = 1; m < M; ++m) {
+    int rows = cl[m] * d, cols = cr[m];
+    if (rows >= cols) break;
+    // G = M M^H (rows x rows)
+    HIP_CHECK_RET(zgemm<C>(st, rows, rows, cols, cone<C>(), A[m], cols, 0, 0, A[m], cols, 0, 2, czero<C>(), Gc, rows,
+                           0, 1));
+    if (int rc = eig_small(rows)) return rc;
+    int r = keep_count(rows);
+    HIP_CHECK_RET(hipMemcpyAsync(wdev, w64, r * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // X = U_r^H M (r x cols); new A^m = U_r S (rows x r); A^{m+1} <- S^-1 X A^{m+1}
+    HIP_CHECK_RET(scaled_copy<C>(st, Uc, r, Vec, rows, rows, r, nullptr, 0, 0));      // U_r (rows x r)
+    HIP_CHECK_RET(zgemm<C>(st, r, cols, rows, cone<C>(), Uc, r, 0, 2, A[m], cols, 0, 0, czero<C>(), Xc, cols, 0, 1));
+    C* An;
+    HIP_CHECK_RET(dalloc(tmp, &An, (size_t)rows * r));
+    HIP_CHECK_RET(hipMemcpyAsync(An, Uc, sizeof(C) * rows * r, hipMemcpyDeviceToDevice, st));
+    HIP_CHECK_RET(gauge_scale<C>(st, An, rows, 1, r, nullptr, wdev));                // * S
+    HIP_CHECK_RET(gauge_scale<C>(st, Xc, r, 1, cols, wdev, nullptr));                // S^-1 *
+    int n2 = d * cr[m + 1];
+    C* Bn;
+    HIP_CHECK_RET(dalloc(tmp, &Bn, (size_t)r * n2));
+    HIP_CHECK_RET(zgemm<C>(st, r, n2, cols, cone<C>(), Xc, cols, 0, 0, A[m + 1], n2, 0, 0, czero<C>(), Bn, n2, 0, 1));
+    A[m] = An;
+    A[m + 1] = Bn;
+    cr[m] = r;
+    cl[m + 1] = r;
+  }
+  // (2) right edge: bond m-1 may be cut when d cr < cl.
+  for (int m = M; m > 1; --m) {
+    int rows = cl[m], cols = d * cr[m];
+    if (cols >= rows) break;
+    // G = M^H M (cols x cols)
+    HIP_CHECK_RET(zgemm<C>(st, cols, cols, rows, cone<C>(), A[m], cols, 0, 2, A[m], cols, 0, 0, czero<C>(), Gc, cols,
+                           0, 1));
+    if (int rc = eig_small(cols)) return rc;
+    int r = keep_count(cols);
+    HIP_CHECK_RET(hipMemcpyAsync(wdev, w64, r * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // new A^m = S U_r^H (r x cols); X = M U_r S^-1 (rows x r); A^{m-1} <- A^{m-1} X
+    C* An;
+    HIP_CHECK_RET(dalloc(tmp, &An, (size_t)r * cols));
+    HIP_CHECK_RET(scaled_copy<C>(st, An, cols, Vec, cols, r, cols, nullptr, 0, 1));   // U_r^H
+    HIP_CHECK_RET(scaled_copy<C>(st, Uc, r, Vec, cols, cols, r, nullptr, 0, 0));      // U_r (cols x r)
+    HIP_CHECK_RET(zgemm<C>(st, rows, r, cols, cone<C>(), A[m], cols, 0, 0, Uc, r, 0, 0, czero<C>(), Xc, r, 0, 1));
+    {
+      // rows of An times S = sqrt(w), columns of X times S^-1 (weights 1/w)
+      std::vector<double> wi(r);
+      for (int k = 0; k < r; ++k) wi[k] = 1.0 / wh[k];
+      double* winv;
+      HIP_CHECK_RET(dalloc(tmp, &winv, r));
+      HIP_CHECK_RET(hipMemcpyAsync(winv, wi.data(), r * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_CHECK_RET(gauge_scale<C>(st, Xc, rows, 1, r, nullptr, winv));
+      HIP_CHECK_RET(gauge_scale<C>(st, An, r, 1, cols, winv, nullptr));
+      HIP_CHECK_RET(hipStreamSynchronize(st));
+    }
+    int nl = cl[m - 1] * d;
+    C* Bn;
+    HIP_CHECK_RET(dalloc(tmp, &Bn, (size_t)nl * r));
+    HIP_CHECK_RET(zgemm<C>(st, nl, r, rows, cone<C>(), A[m - 1], rows, 0, 0, Xc, r, 0, 0, czero<C>(), Bn, r, 0, 1));
+    A[m] = An;
+    A[m - 1] = Bn;
+    cl[m] = r;
+    cr[m - 1] = r;
+  }
+  // (3) right environments E_{m-1} = sum_p A^m[p] E_m A^m[p]^H, bonds 1..M-1.
+  int emax = 1;
+  for (int m = 1; m < M; ++m) emax = std::max(emax, cr[m]);
+  const long eld = emax;
+  cplx64 *E64, *EV64, *EVt;
+  double* W64;
+  C* Ec;
+  C* Tb;
+  HIP_CHECK_RET(dalloc(tmp, &E64, (size_t)(M + 1) * eld * eld));
+  HIP_CHECK_RET(dalloc(tmp, &EV64, (size_t)(M + 1) * eld * eld));
+  HIP_CHECK_RET(dalloc(tmp, &EVt, (size_t)(M + 1) * eld * eld));
+  HIP_CHECK_RET(dalloc(tmp, &W64, (size_t)(M + 1) * eld));
+  HIP_CHECK_RET(dalloc(tmp, &Ec, (size_t)2 * eld * eld));
+  HIP_CHECK_RET(dalloc(tmp, &Tb, (size_t)eld * d * eld));
+  std::vector<int> edim(M + 1, 1);
+  {
+    C one = cone<C>();
+    HIP_CHECK_RET(hipMemcpyAsync(Ec, &one, sizeof(C), hipMemcpyHostToDevice, st));
+    int cur = 0;
+    for (int m = M; m >= 2; --m) {
+      int a = cl[m], b = cr[m];
+      C* Ein = Ec + (long)cur * eld * eld;
+      C* Eout = Ec + (long)(1 - cur) * eld * eld;
+      // Tb[:, p, :] = A^m[:, p, :] E_m   (batched over p)
+      HIP_CHECK_RET(zgemm<C>(st, a, b, b, cone<C>(), A[m], (long)d * b, b, 0, Ein, eld, 0, 0, czero<C>(), Tb,
+                             (long)d * b, b, d));
+      // E_{m-1} = Tb (a x d b) * A^m^H, stored with leading dimension eld
+      HIP_CHECK_RET(zgemm<C>(st, a, a, d * b, cone<C>(), Tb, (long)d * b, 0, 0, A[m], (long)d * b, 0, 2, czero<C>(),
+                             Eout, eld, 0, 1));
+      HIP_CHECK_RET(convert<cplx64, C>(st, E64 + (long)(m - 1) * eld * eld, Eout, (long)a * eld));
+      edim[m - 1] = a;
+      cur = 1 - cur;
+    }
+  }
+  // (4) all bond eigenproblems in parallel (FP64 Jacobi), bonds 1..M-1
+  int* edim_dev;
+  HIP_CHECK_RET(dalloc(tmp, &edim_dev, M + 1));
+  {
+    // the Jacobi kernel needs a contiguous square leading dimension per matrix:
+    // matrices are stored with leading dimension eld (row stride) already.
+    HIP_CHECK_RET(hipMemcpyAsync(edim_dev, edim.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    if (M > 1)
+      HIP_CHECK_RET(jacobi_herm(st, E64 + eld * eld, EVt, W64 + eld, edim_dev + 1, eld, eld * eld, M - 1, jerr,
+                                EV64 + eld * eld));
+  }
+  std::vector<double> wall((size_t)(M + 1) * eld);
+  HIP_CHECK_RET(hipMemcpyAsync(wall.data(), W64, wall.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  int herr = 0;
+  HIP_CHECK_RET(hipMemcpyAsync(&herr, jerr, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  if (herr) return fail(GBS_E_INTERNAL, deverr_msg(herr));
+  std::vector<int> r(M + 1, 1);
+  h->svals.assign(M + 1, {});
+  for (int m = 1; m < M; ++m) {
+    const double* w = &wall[(size_t)m * eld];
+    int n = edim[m], k = 0;
+    for (int i = 0; i < n; ++i)
+      if (w[i] > tau * w[0] && w[i] > 0.0) ++k;
+    k = std::max(1, std::min(k, h->chi));
+    r[m] = k;
+    h->svals[m].resize(k);
+    for (int i = 0; i < k; ++i) h->svals[m][i] = std::sqrt(w[i]);
+  }
+  // (5) B^m = S_{m-1}^-1 U_{m-1}^H A^m[p] U_m S_m
+  long total = 0;
+  h->toff.assign(M + 1, 0);
+  for (int m = 1; m <= M; ++m) {
+    h->toff[m] = total;
+    total += (long)r[m - 1] * d * r[m];
+  }
+  C* out;
+  HIP_CHECK_RET(dalloc(h->keep, &out, (size_t)total));
+  h->tens = out;
+  h->esz = sizeof(C);
+  C* Ub;   // U_m in precision C, (eld x eld)
+  HIP_CHECK_RET(dalloc(tmp, &Ub, (size_t)(M + 1) * eld * eld));
+  for (int m = 1; m < M; ++m)
+    HIP_CHECK_RET(scaled_copy<C>(st, Ub + (long)m * eld * eld, eld, EV64 + (long)m * eld * eld, eld, edim[m], r[m],
+                                 nullptr, 0, 0));
+  for (int m = 1; m <= M; ++m) {
+    int a = cl[m], b = cr[m], ra = r[m - 1], rb = r[m];
+    // Y = A^m[p] U_m  (a x d x rb)
+    const C* Y = A[m];
+    if (m < M) {
+      HIP_CHECK_RET(zgemm<C>(st, a, rb, b, cone<C>(), A[m], (long)d * b, b, 0, Ub + (long)m * eld * eld, eld, 0, 0,
+                             czero<C>(), Tb, (long)d * rb, rb, d));
+      Y = Tb;
+    }
+    C* Bm = out + h->toff[m];
+    if (m > 1) {
+      HIP_CHECK_RET(zgemm<C>(st, ra, d * rb, a, cone<C>(), Ub + (long)(m - 1) * eld * eld, eld, 0, 2, Y, (long)d * rb, 0,
+                             0, czero<C>(), Bm, (long)d * rb, 0, 1));
+    } else {
+      HIP_CHECK_RET(hipMemcpyAsync(Bm, Y, sizeof(C) * (long)a * d * rb, hipMemcpyDeviceToDevice, st));
+    }
+    const double* wl = m > 1 ? W64 + (long)(m - 1) * eld : nullptr;
+    const double* wr = m < M ? W64 + (long)m * eld : nullptr;
+    HIP_CHECK_RET(gauge_scale<C>(st, Bm, ra, d, rb, wl, wr));
+  }
+  // (6) normalise and fix the phase
+  h->bond = r;
+  h->maxbond = *std::max_element(r.begin(), r.end());
+  HIP_CHECK_RET(dalloc(h->keep, &h->bond_dev, M + 1));
+  HIP_CHECK_RET(hipMemcpyAsync(h->bond_dev, r.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  std::vector<void*> ptrs(M);
+  for (int m = 1; m <= M; ++m) ptrs[m - 1] = out + h->toff[m];
+  HIP_CHECK_RET(dalloc(h->keep, &h->site_ptrs, M));
+  HIP_CHECK_RET(hipMemcpyAsync(h->site_ptrs, ptrs.data(), M * sizeof(void*), hipMemcpyHostToDevice, st));
+  cplx64* vbuf;
+  double* nrm;
+  HIP_CHECK_RET(dalloc(tmp, &vbuf, 2 * GBS_CHI_MAX));
+  HIP_CHECK_RET(dalloc(tmp, &nrm, 1));
+  HIP_CHECK_RET(normalize_mps<C>(st, (C**)h->site_ptrs, h->bond_dev, M, d, vbuf, nrm));
+  HIP_CHECK_RET(hipMemcpyAsync(&h->norm_raw, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  return GBS_OK;
+}
+
+int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t st, gbs_mps_s* h) {
+  const int d = opt->d, chi = opt->chi;
+  DevArena tmp;
+  int* err;
+  HIP_CHECK_RET(dalloc(h->keep, &err, 4));
+  h->err = err;
+  HIP_CHECK_RET(hipMemsetAsync(err, 0, 4 * sizeof(int), st));
+  // ---- validation
+  {
+    double* scal;
+    double* wsM;
+    HIP_CHECK_RET(dalloc(tmp, &scal, 4));
+    HIP_CHECK_RET(dalloc(tmp, &wsM, (size_t)M * M));
+    HIP_CHECK_RET(launch_validate(st, gamma, M, scal, wsM, err));
+    double hs[3];
+    int herr = 0;
+    HIP_CHECK_RET(hipMemcpyAsync(hs, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK_RET(hipStreamSynchronize(st));
+    double scale = std::max(1.0, 2.0 * hs[1]);
+    if (!(hs[0] <= 1e-10 * scale)) return fail(GBS_E_NOT_PD, "Gamma is not symmetric");
+    if (herr) return fail(GBS_E_NOT_PD, "Gamma is not positive definite");
+    if (!(hs[2] <= 1e-8 * scale * scale)) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "Gamma is not pure: |(2 Gamma Omega)^2 + 1|_max = %.3e", hs[2]);
+      return fail(GBS_E_NOT_PURE, buf);
+    }
+  }
+  // ---- Gaussian SVD chain
+  double t0 = now_ms();
+  const int n2max = std::min(GBS_GSVD_N2_MAX, M + 2);
+  GsvdArgs ga{};
+  ga.M = M;
+  ga.dstar = opt->dstar;
+  ga.gamma = gamma;
+  ga.err = err;
+  HIP_CHECK_RET(dalloc(tmp, &ga.ne, M + 1));
+  HIP_CHECK_RET(hipMemsetAsync(ga.ne, 0, (M + 1) * sizeof(int), st));
+  ga.ld_dsym = n2max / 2 + 1;
+  HIP_CHECK_RET(dalloc(tmp, &ga.dsym, (size_t)(M + 1) * ga.ld_dsym));
+  HIP_CHECK_RET(dalloc(tmp, &ga.lam, (size_t)(M + 1) * ga.ld_dsym));
+  ga.ld_drr = n2max;
+  ga.ld_cr = 2 * M;
+  double *drr[2], *cr[2];
+  for (int i = 0; i < 2; ++i) {
+    HIP_CHECK_RET(dalloc(tmp, &drr[i], (size_t)n2max * n2max));
+    HIP_CHECK_RET(dalloc(tmp, &cr[i], (size_t)n2max * 2 * M));
+  }
+  h->ld_q = n2max;  // n_modes <= nL + ne <= n2max
+  h->q_stride = (long)h->ld_q * h->ld_q;
+  HIP_CHECK_RET(dalloc(h->keep, &h->Q, (size_t)M * h->q_stride));
+  ga.Q = h->Q;
+  ga.q_stride = h->q_stride;
+  ga.ld_q = h->ld_q;
+  ga.ld_ws = n2max;
+  const size_t wsz = (size_t)n2max * n2max;
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_G, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_L, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_A, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_B, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_E, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_O, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_S, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_vec, (size_t)3 * n2max));
+  ga.ld_u = n2max / 2 + 1;
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_U, (size_t)ga.ld_u * ga.ld_u));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_V, (size_t)ga.ld_u * ga.ld_u));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_aug, (size_t)ga.ld_u * 2 * ga.ld_u));
+  for (int m = 1; m <= M; ++m) {
+    ga.drr_in = drr[(m + 1) & 1];
+    ga.drr_out = drr[m & 1];
+    ga.cr_in = cr[(m + 1) & 1];
+    ga.cr_out = cr[m & 1];
+    HIP_CHECK_RET(launch_gsvd_cut(st, ga, m));
+  }
+  std::vector<int> ne(M + 1);
+  std::vector<double> lamh((size_t)(M + 1) * ga.ld_dsym);
+  int herr = 0;
+  HIP_CHECK_RET(hipMemcpyAsync(ne.data(), ga.ne, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(lamh.data(), ga.lam, lamh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  if (herr) return fail(herr == GBS_DEVERR_NOT_PD ? GBS_E_NOT_PD : GBS_E_INTERNAL, deverr_msg(herr));
+  h->ne = ne;
+  h->lam.assign(M + 1, {});
+  h->entropy.assign(M + 1, 0.0);
+  for (int m = 1; m < M; ++m) {
+    h->lam[m].assign(&lamh[(size_t)m * ga.ld_dsym], &lamh[(size_t)m * ga.ld_dsym] + ne[m]);
+    double s = 0;
+    for (double l : h->lam[m]) {
+      double l2 = l * l;
+      if (l2 > 0) s += -std::log1p(-l2) - l2 / (1 - l2) * std::log(l2);
+    }
+    h->entropy[m] = s;
+  }
+  double t1 = now_ms();
+  h->t_gsvd = t1 - t0;
+  // ---- kept bases and maps
+  std::vector<CutDesc> cuts(M + 1);
+  long off_state = 0, off_occ = 0;
+  for (int m = 0; m <= M; ++m) {
+    cuts[m].ne = ne[m];
+    cuts[m].chi = ne[m] > 0 ? chi : 1;
+    cuts[m].off_state = off_state;
+    cuts[m].off_occ = off_occ;
+    off_state += cuts[m].chi;
+    off_occ += (long)cuts[m].chi * ne[m];
+  }
+  KeptArgs ka{};
+  CutDesc* cuts_dev;
+  HIP_CHECK_RET(dalloc(tmp, &cuts_dev, M + 1));
+  HIP_CHECK_RET(hipMemcpyAsync(cuts_dev, cuts.data(), (M + 1) * sizeof(CutDesc), hipMemcpyHostToDevice, st));
+  ka.cuts = cuts_dev;
+  ka.lam = ga.lam;
+  ka.ld_lam = ga.ld_dsym;
+  HIP_CHECK_RET(dalloc(tmp, &ka.E, off_state));
+  HIP_CHECK_RET(dalloc(tmp, &ka.parent, off_state));
+  HIP_CHECK_RET(dalloc(tmp, &ka.pmode, off_state));
+  HIP_CHECK_RET(dalloc(tmp, &ka.ntot, off_state));
+  HIP_CHECK_RET(dalloc(tmp, &ka.nocc, off_state));
+  HIP_CHECK_RET(dalloc(tmp, &ka.hash, off_state));
+  HIP_CHECK_RET(dalloc(h->keep, &ka.occ, std::max(off_occ, 1L)));
+  HIP_CHECK_RET(dalloc(tmp, &ka.low, std::max(off_occ, 1L)));
+  HIP_CHECK_RET(dalloc(tmp, &ka.olist, (size_t)off_state * GBS_K_MAX));
+  HIP_CHECK_RET(dalloc(tmp, &ka.chi_out, M + 1));
+  ka.err = err;
+  h->occ = ka.occ;
+  // vacuum cuts report one state
+  {
+    std::vector<int> ones(M + 1, 1);
+    HIP_CHECK_RET(hipMemcpyAsync(ka.chi_out, ones.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  HIP_CHECK_RET(launch_kept(st, ka, M + 1, chi));
+  std::vector<int> kept(M + 1), ntot(off_state);
+  std::vector<double> Eh(off_state);
+  HIP_CHECK_RET(hipMemcpyAsync(kept.data(), ka.chi_out, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(ntot.data(), ka.ntot, off_state * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(Eh.data(), ka.E, off_state * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  if (herr) return fail(herr == GBS_DEVERR_KMAX ? GBS_E_INVAL : GBS_E_INTERNAL, deverr_msg(herr));
+  for (int m = 0; m <= M; ++m) kept[m] = ne[m] > 0 ? kept[m] : 1;
+  h->kept = kept;
+  h->occ_off.resize(M + 1);
+  for (int m = 0; m <= M; ++m) h->occ_off[m] = cuts[m].off_occ;
+  // truncation error per cut: eps_m = 1 - (1/Z) sum_kept exp(-E)
+  h->eps.assign(M + 1, 0.0);
+  for (int m = 1; m < M; ++m) {
+    if (ne[m] == 0) continue;
+    double logz = 0;
+    for (double l : h->lam[m]) logz += -std::log1p(-l * l);
+    double acc = 0;
+    for (int b = 0; b < kept[m]; ++b) acc += std::exp(-Eh[cuts[m].off_state + b] - logz);
+    h->eps[m] = std::max(0.0, 1.0 - acc);
+  }
+  double t2 = now_ms();
+  h->t_kept = t2 - t1;
+  // ---- PCO schedule: states of each cut grouped by total photon number
+  std::vector<int> perm(off_state);
+  std::vector<std::vector<int>> grp_off(M + 1), grp_cnt(M + 1), grp_n(M + 1);
+  for (int m = 0; m <= M; ++m) {
+    const long o = cuts[m].off_state;
+    const int nk = kept[m];
+    int nmax = 0;
+    for (int b = 0; b < nk; ++b) nmax = std::max(nmax, ntot[o + b]);
+    std::vector<int> cnt(nmax + 1, 0);
+    for (int b = 0; b < nk; ++b) cnt[ntot[o + b]]++;
+    std::vector<int> start(nmax + 2, 0);
+    for (int n = 0; n <= nmax; ++n) start[n + 1] = start[n] + cnt[n];
+    std::vector<int> pos(start.begin(), start.end() - 1);
+    for (int b = 0; b < nk; ++b) perm[o + pos[ntot[o + b]]++] = b;
+    for (int n = 0; n <= nmax; ++n)
+      if (cnt[n]) {
+        grp_off[m].push_back(start[n]);
+        grp_cnt[m].push_back(cnt[n]);
+        grp_n[m].push_back(n);
+      }
+  }
+  std::vector<SiteDesc> sites(M);
+  std::vector<long> t64off(M + 1, 0);
+  long ttot = 0;
+  for (int m = 1; m <= M; ++m) {
+    SiteDesc& s = sites[m - 1];
+    s.nl = ne[m - 1];
+    s.nr = ne[m];
+    s.d = d;
+    s.chiL = kept[m - 1];
+    s.chiR = kept[m];
+    s.off_state_l = cuts[m - 1].off_state;
+    s.off_state_r = cuts[m].off_state;
+    s.off_occ_l = cuts[m - 1].off_occ;
+    s.off_occ_r = cuts[m].off_occ;
+    s.off_q = (long)(m - 1) * h->q_stride;
+    s.off_t = ttot;
+    t64off[m] = ttot;
+    ttot += (long)s.chiL * d * s.chiR;
+  }
+  // blocks per level
+  std::vector<std::vector<LevelBlock>> lv;
+  for (int m = 1; m <= M; ++m) {
+    for (size_t ia = 0; ia < grp_n[m - 1].size(); ++ia)
+      for (size_t ib = 0; ib < grp_n[m].size(); ++ib)
+        for (int p = 0; p < d; ++p) {
+          int tot = grp_n[m - 1][ia] + p + grp_n[m][ib];
+          if (tot == 0 || (tot & 1)) continue;
+          int k = tot / 2;
+          if ((int)lv.size() <= k) lv.resize(k + 1);
+          LevelBlock b;
+          b.site = m - 1;
+          b.p = p;
+          b.a_off = grp_off[m - 1][ia];
+          b.a_cnt = grp_cnt[m - 1][ia];
+          b.b_off = grp_off[m][ib];
+          b.b_cnt = grp_cnt[m][ib];
+          b.elem_start = 0;
+          lv[k].push_back(b);
+        }
+  }
+  std::vector<LevelBlock> allb;
+  std::vector<size_t> lv_first(lv.size() + 1, 0);
+  std::vector<long> lv_nelem(lv.size(), 0);
+  int64_t updates = 0;
+  for (size_t k = 0; k < lv.size(); ++k) {
+    lv_first[k] = allb.size();
+    long acc = 0;
+    for (auto& b : lv[k]) {
+      b.elem_start = acc;
+      acc += (long)b.a_cnt * b.b_cnt;
+      allb.push_back(b);
+    }
+    lv_nelem[k] = acc;
+  }
+  lv_first[lv.size()] = allb.size();
+  cplx64* T64;
+  HIP_CHECK_RET(dalloc(h->flags & GBS_KEEP_RAW ? h->keep : tmp, &T64, (size_t)std::max(ttot, 1L)));
+  HIP_CHECK_RET(hipMemsetAsync(T64, 0, sizeof(cplx64) * ttot, st));
+  PcoArgs pa{};
+  SiteDesc* sites_dev;
+  int* perm_dev;
+  LevelBlock* blk_dev;
+  HIP_CHECK_RET(dalloc(tmp, &sites_dev, M));
+  HIP_CHECK_RET(dalloc(tmp, &perm_dev, off_state));
+  HIP_CHECK_RET(dalloc(tmp, &blk_dev, std::max<size_t>(allb.size(), 1)));
+  HIP_CHECK_RET(hipMemcpyAsync(sites_dev, sites.data(), M * sizeof(SiteDesc), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(perm_dev, perm.data(), off_state * sizeof(int), hipMemcpyHostToDevice, st));
+  if (!allb.empty())
+    HIP_CHECK_RET(hipMemcpyAsync(blk_dev, allb.data(), allb.size() * sizeof(LevelBlock), hipMemcpyHostToDevice, st));
+  pa.sites = sites_dev;
+  pa.perm = perm_dev;
+  pa.olist = ka.olist;
+  pa.nocc = ka.nocc;
+  pa.low = ka.low;
+  pa.Q = h->Q;
+  pa.ld_q = h->ld_q;
+  pa.T = T64;
+  HIP_CHECK_RET(launch_pco_init(st, pa, M));
+  for (size_t k = 1; k < lv.size(); ++k) {
+    int nb = (int)(lv_first[k + 1] - lv_first[k]);
+    if (nb == 0) continue;
+    HIP_CHECK_RET(launch_pco_level(st, pa, blk_dev + lv_first[k], nb, lv_nelem[k], (int)k));
+    updates += lv_nelem[k];
+  }
+  h->pco_updates = updates;
+  if (h->flags & GBS_KEEP_RAW) {
+    h->raw = T64;
+    h->raw_off = t64off;
+  }
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  double t3 = now_ms();
+  h->t_pco = t3 - t2;
+  // ---- truncation sweep and canonical form
+  int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off)
+                                 : canonicalize<cplx32>(h, st, tmp, T64, t64off);
+  if (rc) return rc;
+  h->t_svd = now_ms() - t3;
+  return GBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out) {
+  if (!out) return fail(GBS_E_INVAL, "out_handle is NULL");
+  *out = nullptr;
+  if (!gamma || !opt) return fail(GBS_E_INVAL, "NULL gamma or options");
+  if (M < 1) return fail(GBS_E_INVAL, "M must be >= 1");
+  if (opt->d < 1) return fail(GBS_E_INVAL, "d must be >= 1");
+  if (opt->chi < 1 || opt->chi > GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi must be in [1, 4096]");
+  if (!(opt->dstar > 1.0)) return fail(GBS_E_INVAL, "dstar must be > 1");
+  if (opt->prec != GBS_FP64 && opt->prec != GBS_FP32 && opt->prec != GBS_BF16X3)
+    return fail(GBS_E_INVAL, "unknown precision");
+  if ((long)opt->chi * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi * d too large");
+  gbs_mps_s* h = new (std::nothrow) gbs_mps_s();
+  if (!h) return fail(GBS_E_NOMEM, "host allocation failed");
+  h->M = M;
+  h->d = opt->d;
+  h->chi = opt->chi;
+  h->prec = opt->prec;
+  h->dstar = opt->dstar;
+  h->flags = opt->flags;
+  h->trunc_rel = opt->trunc_rel;
+  int rc;
+  try {
+    rc = build_impl(gamma, M, opt, (hipStream_t)stream, h);
+  } catch (...) {
+    rc = fail(GBS_E_INTERNAL, "unexpected host exception");
+  }
+  if (rc != GBS_OK) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return GBS_OK;
+}
+
+int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out, void* stream) {
+  if (!h) return fail(GBS_E_INVAL, "NULL handle");
+  if (B < 0) return fail(GBS_E_INVAL, "B < 0");
+  if (B == 0) return GBS_OK;
+  if (!patterns || !out) return fail(GBS_E_INVAL, "NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  int* bad;
+  DevArena tmp;
+  HIP_CHECK_RET(dalloc(tmp, &bad, 1));
+  HIP_CHECK_RET(hipMemsetAsync(bad, 0, sizeof(int), st));
+  if (h->esz == sizeof(cplx64))
+    HIP_CHECK_RET(launch_amplitude<cplx64>(st, (cplx64* const*)h->site_ptrs, h->bond_dev, h->M, h->d, patterns, B, out,
+                                           bad, h->maxbond));
+  else
+    HIP_CHECK_RET(launch_amplitude<cplx32>(st, (cplx32* const*)h->site_ptrs, h->bond_dev, h->M, h->d, patterns, B, out,
+                                           bad, h->maxbond));
+  int hb = 0;
+  HIP_CHECK_RET(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  if (hb) return fail(GBS_E_INVAL, "pattern entry outside [0, d)");
+  return GBS_OK;
+}
+
+int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream) {
+  if (!h) return fail(GBS_E_INVAL, "NULL handle");
+  if (shots < 0) return fail(GBS_E_INVAL, "shots < 0");
+  if (shots == 0) return GBS_OK;
+  if (!out) return fail(GBS_E_INVAL, "NULL output");
+  if (h->maxbond > 1024) return fail(GBS_E_INVAL, "sampler supports bond dimension <= 1024");
+  hipStream_t st = (hipStream_t)stream;
+  const int M = h->M, d = h->d;
+  const long ldl = h->maxbond;
+  const int64_t chunk = std::min<int64_t>(shots, (int64_t)1 << 18);
+  DevArena tmp;
+  void* lbuf[2];
+  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * ldl * h->esz));
+  for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
+    const int64_t n = std::min(chunk, shots - s0);
+    int cur = 0;
+    if (h->esz == sizeof(cplx64)) {
+      HIP_CHECK_RET(launch_fill_first<cplx64>(st, (cplx64*)lbuf[0], ldl, n));
+      for (int m = 1; m <= M; ++m) {
+        const cplx64* Bm = (const cplx64*)h->tens + h->toff[m];
+        HIP_CHECK_RET(launch_sample_site<cplx64>(st, Bm, h->bond[m - 1], d, h->bond[m], (const cplx64*)lbuf[cur],
+                                                 (cplx64*)lbuf[1 - cur], ldl, s0, n, m, seed, out, M));
+        cur = 1 - cur;
+      }
+    } else {
+      HIP_CHECK_RET(launch_fill_first<cplx32>(st, (cplx32*)lbuf[0], ldl, n));
+      for (int m = 1; m <= M; ++m) {
+        const cplx32* Bm = (const cplx32*)h->tens + h->toff[m];
+        HIP_CHECK_RET(launch_sample_site<cplx32>(st, Bm, h->bond[m - 1], d, h->bond[m], (const cplx32*)lbuf[cur],
+                                                 (cplx32*)lbuf[1 - cur], ldl, s0, n, m, seed, out, M));
+        cur = 1 - cur;
+      }
+    }
+  }
+  // temporaries are released when `tmp` goes out of scope: wait for the work
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  return GBS_OK;
+}
+
+int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, double* eps, double* entropy) {
+  if (!h || !info) return fail(GBS_E_INVAL, "NULL argument");
+  info->M = h->M;
+  info->d = h->d;
+  info->chi = h->chi;
+  info->prec = h->prec;
+  info->max_bond = h->maxbond;
+  info->max_ne = *std::max_element(h->ne.begin(), h->ne.end());
+  info->eps_max = *std::max_element(h->eps.begin(), h->eps.end());
+  info->norm_raw = h->norm_raw;
+  info->bytes = h->keep.bytes;
+  info->pco_updates = h->pco_updates;
+  info->t_gsvd_ms = h->t_gsvd;
+  info->t_kept_ms = h->t_kept;
+  info->t_pco_ms = h->t_pco;
+  info->t_svd_ms = h->t_svd;
+  for (int m = 0; m <= h->M; ++m) {
+    if (bond) bond[m] = h->bond[m];
+    if (ne) ne[m] = h->ne[m];
+    if (eps) eps[m] = h->eps[m];
+    if (entropy) entropy[m] = h->entropy[m];
+  }
+  return GBS_OK;
+}
+
+int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, int64_t* written) {
+  if (!h || !dst) return fail(GBS_E_INVAL, "NULL argument");
+  const int M = h->M, d = h->d;
+  std::vector<char> buf;
+  auto put = [&](const void* p, size_t n) -> int {
+    if ((int64_t)n > cap) return fail(GBS_E_INVAL, "export buffer too small");
+    std::memcpy(dst, p, n);
+    if (written) *written = (int64_t)n;
+    return GBS_OK;
+  };
+  if (what == GBS_EXPORT_TENSOR) {
+    if (m < 1 || m > M) return fail(GBS_E_INVAL, "site out of range");
+    long n = (long)h->bond[m - 1] * d * h->bond[m];
+    std::vector<cplx64> out(n);
+    if (h->esz == sizeof(cplx64)) {
+      HIP_CHECK_RET(hipMemcpy(out.data(), (cplx64*)h->tens + h->toff[m], n * sizeof(cplx64), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<cplx32> tmp(n);
+      HIP_CHECK_RET(hipMemcpy(tmp.data(), (cplx32*)h->tens + h->toff[m], n * sizeof(cplx32), hipMemcpyDeviceToHost));
+      for (long i = 0; i < n; ++i) out[i] = cmake<cplx64>(tmp[i].re, tmp[i].im);
+    }
+    return put(out.data(), n * sizeof(cplx64));
+  }
+  if (what == GBS_EXPORT_RAW) {
+    if (!h->raw) return fail(GBS_E_INVAL, "raw tensors not kept (build with GBS_KEEP_RAW)");
+    if (m < 1 || m > M) return fail(GBS_E_INVAL, "site out of range");
+    long n = (long)h->kept[m - 1] * d * h->kept[m];
+    std::vector<cplx64> out(n);
+    HIP_CHECK_RET(hipMemcpy(out.data(), h->raw + h->raw_off[m], n * sizeof(cplx64), hipMemcpyDeviceToHost));
+    return put(out.data(), n * sizeof(cplx64));
+  }
+  if (what == GBS_EXPORT_Q) {
+    if (m < 1 || m > M) return fail(GBS_E_INVAL, "site out of range");
+    int n = h->ne[m - 1] + 1 + h->ne[m];
+    std::vector<cplx64> full((size_t)h->q_stride), out((size_t)n * n);
+    HIP_CHECK_RET(hipMemcpy(full.data(), h->Q + (long)(m - 1) * h->q_stride, h->q_stride * sizeof(cplx64),
+                            hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) out[(size_t)i * n + j] = full[(size_t)i * h->ld_q + j];
+    return put(out.data(), out.size() * sizeof(cplx64));
+  }
+  if (what == GBS_EXPORT_BASIS) {
+    if (m < 0 || m > M) return fail(GBS_E_INVAL, "cut out of range");
+    long n = (long)h->kept[m] * h->ne[m];
+    std::vector<short> tmp(std::max(n, 1L));
+    std::vector<int32_t> out(n);
+    if (n) HIP_CHECK_RET(hipMemcpy(tmp.data(), h->occ + h->occ_off[m], n * sizeof(short), hipMemcpyDeviceToHost));
+    for (long i = 0; i < n; ++i) out[i] = tmp[i];
+    if (written) *written = 0;
+    return n ? put(out.data(), n * sizeof(int32_t)) : GBS_OK;
+  }
+  if (what == GBS_EXPORT_LAMBDA) {
+    if (m < 1 || m >= M) return fail(GBS_E_INVAL, "cut out of range");
+    if (written) *written = 0;
+    return h->lam[m].empty() ? GBS_OK : put(h->lam[m].data(), h->lam[m].size() * sizeof(double));
+  }
+  if (what == GBS_EXPORT_SVALS) {
+    if (m < 1 || m >= M) return fail(GBS_E_INVAL, "bond out of range");
+    return put(h->svals[m].data(), h->svals[m].size() * sizeof(double));
+  }
+  return fail(GBS_E_INVAL, "unknown export kind");
+}
+
+void gbs_mps_free(gbs_mps h) {
+  if (!h) return;
+  delete h;
+}
+
+const char* gbs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

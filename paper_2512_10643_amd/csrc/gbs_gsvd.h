@@ -1,0 +1,32 @@
+// Validation and Gaussian-SVD launch interfaces.
+#pragma once
+#include "gbs_common.h"
+
+#define GBS_GSVD_N2_MAX 600   // 2 * (n_e^{m-1} + 1) handled by one workgroup
+
+struct GsvdArgs {
+  int M;
+  double dstar;
+  const double* gamma;   // 2M x 2M, row-major
+  int* ne;               // ne[0..M]
+  int* err;
+  double* dsym;          // (M+1) x ld_dsym: symplectic eigenvalues per cut
+  double* lam;           // (M+1) x ld_dsym: Lambda per cut (all L modes)
+  long ld_dsym;
+  const double* drr_in;  // r-r block of the residual, ld_drr
+  double* drr_out;
+  long ld_drr;
+  const double* cr_in;   // r - a cross block, rows = r quadratures, cols indexed as Gamma's
+  double* cr_out;
+  long ld_cr;
+  cplx64* Q;             // per-site pair matrices
+  long q_stride, ld_q;
+  // workspace
+  double *ws_G, *ws_L, *ws_A, *ws_B, *ws_E, *ws_O, *ws_S, *ws_vec;
+  long ld_ws;
+  cplx64 *ws_U, *ws_V, *ws_aug;
+  long ld_u;
+};
+
+hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* scal, double* wsM, int* err);
+hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m);

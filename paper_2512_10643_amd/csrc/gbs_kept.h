@@ -1,0 +1,26 @@
+// Kept-basis and index-map launch interface.
+#pragma once
+#include "gbs_common.h"
+
+struct CutDesc {
+  int ne;          // active virtual modes at this cut
+  int chi;         // requested basis size (1 when ne == 0)
+  long off_state;  // offset into per-state arrays
+  long off_occ;    // offset into occupation / lowering tables (chi * ne)
+};
+
+struct KeptArgs {
+  const CutDesc* cuts;   // index 0..M
+  const double* lam;     // Lambda per cut, row m, leading dimension ld_lam
+  long ld_lam;
+  double* E;
+  int *parent, *pmode, *ntot, *nocc;
+  unsigned long long* hash;
+  short* occ;            // chi x ne per cut
+  int* low;              // ne x chi per cut
+  int4* olist;           // chi x GBS_K_MAX per cut: (mode, count, low index, 0)
+  int* chi_out;          // kept count per cut
+  int* err;
+};
+
+hipError_t launch_kept(hipStream_t st, const KeptArgs& a, int ncuts, int chi);

@@ -1,0 +1,266 @@
+// Dense building blocks: complex GEMM (FP32/FP64) and batched Hermitian
+// Jacobi eigensolver (FP64), both row-major.
+#include "gbs_linalg.h"
+
+// ---------------------------------------------------------------------------
+// Complex GEMM  C = alpha * op(A) * op(B) + beta * C, strided-batched.
+// op: 0 = none, 1 = transpose, 2 = conjugate transpose.  64x64 output tile per
+// 256-thread workgroup, 4x4 outputs per thread, K staged through LDS in 16s.
+template <typename C>
+__device__ inline C load_op(const C* p, long ld, int op, long i, long k) {
+  if (op == 0) return p[i * ld + k];
+  C v = p[k * ld + i];
+  if (op == 2) v.im = -v.im;
+  return v;
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void zgemm_tiled(int M, int N, int K, C alpha, const C* __restrict__ A, long lda,
+                                                   long sA, int opA, const C* __restrict__ B, long ldb, long sB,
+                                                   int opB, C beta, C* __restrict__ Cm, long ldc, long sC) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ C As[TK][TM + 1];
+  __shared__ C Bs[TK][TN + 1];
+  const int bz = blockIdx.z;
+  A += (long)bz * sA;
+  B += (long)bz * sB;
+  Cm += (long)bz * sC;
+  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;   // 16x16 thread grid, 4x4 each
+  typedef typename real_of<C>::type R;
+  C acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = cmake<C>((R)0, (R)0);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    for (int e = tid; e < TM * TK; e += 256) {
+      int kk = e % TK, ii = e / TK;
+      long gi = row0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < M && gk < K) ? load_op(A, lda, opA, gi, gk) : cmake<C>((R)0, (R)0);
+    }
+    for (int e = tid; e < TN * TK; e += 256) {
+      int jj = e % TN, kk = e / TN;
+      long gj = col0 + jj, gk = k0 + kk;
+      // op(B)(k, j): opB == 0 -> B[k*ldb + j]; else B[j*ldb + k] (conj for 2)
+      C v = cmake<C>((R)0, (R)0);
+      if (gj < N && gk < K) {
+        if (opB == 0) v = B[gk * ldb + gj];
+        else {
+          v = B[gj * ldb + gk];
+          if (opB == 2) v.im = -v.im;
+        }
+      }
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      C a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    long gi = row0 + tr * 4 + i;
+    if (gi >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      long gj = col0 + tc * 4 + j;
+      if (gj >= N) continue;
+      C v = cmul(alpha, acc[i][j]);
+      if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, Cm[gi * ldc + gj]));
+      Cm[gi * ldc + gj] = v;
+    }
+  }
+}
+
+template <typename C>
+hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long lda, long sA, int opA, const C* B,
+                 long ldb, long sB, int opB, C beta, C* Cm, long ldc, long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+  hipLaunchKernelGGL(zgemm_tiled<C>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB, beta,
+                     Cm, ldc, sC);
+  return hipGetLastError();
+}
+template hipError_t zgemm<cplx64>(hipStream_t, int, int, int, cplx64, const cplx64*, long, long, int, const cplx64*,
+                                  long, long, int, cplx64, cplx64*, long, long, int);
+template hipError_t zgemm<cplx32>(hipStream_t, int, int, int, cplx32, const cplx32*, long, long, int, const cplx32*,
+                                  long, long, int, cplx32, cplx32*, long, long, int);
+
+// ---------------------------------------------------------------------------
+// Batched Hermitian Jacobi (FP64), one 1024-thread workgroup per matrix.
+// Matrix b has size n = dims[b] (<= ld), stored at A + b*sA with leading
+// dimension ld.  On exit: w[b*ld + k] eigenvalues in descending order,
+// V[b*sA + i*ld + k] the matching eigenvectors as columns.  A is destroyed.
+// Parallel cyclic ordering (round robin), two-sided rotations on 2x2 blocks.
+__device__ inline void rr_pair(int npad, int s, int i, int& p, int& q) {
+  int m = npad - 1;
+  if (i == 0) {
+    p = 0;
+    q = 1 + (s % m);
+  } else {
+    p = 1 + ((s + i) % m);
+    q = 1 + (((s - i) % m + m) % m);
+  }
+}
+
+__global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__ A, cplx64* __restrict__ V,
+                                                            double* __restrict__ w, const int* __restrict__ dims,
+                                                            long ld, long sA, int max_sweeps, double tol,
+                                                            int* __restrict__ err, cplx64* __restrict__ Vout) {
+  const int b = blockIdx.x;
+  const int n = dims ? dims[b] : (int)ld;
+  cplx64* a = A + (long)b * sA;
+  cplx64* v = V + (long)b * sA;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double rc[GBS_CHI_MAX / 2 + 1], rs[GBS_CHI_MAX / 2 + 1];
+  __shared__ cplx64 rph[GBS_CHI_MAX / 2 + 1];
+  __shared__ int rp[GBS_CHI_MAX / 2 + 1], rq[GBS_CHI_MAX / 2 + 1];
+  __shared__ int any_rot;
+  if (n <= 0) return;
+  for (long e = tid; e < (long)n * n; e += nt) {
+    long i = e / n, j = e % n;
+    v[i * ld + j] = cmake<cplx64>(i == j ? 1.0 : 0.0, 0.0);
+  }
+  // make the diagonal exactly real
+  for (int i = tid; i < n; i += nt) a[(long)i * ld + i].im = 0.0;
+  __syncthreads();
+  const int npad = n + (n & 1);
+  const int half = npad / 2;
+  bool converged = (n == 1);
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int s = 0; s < npad - 1; ++s) {
+      for (int i = tid; i < half; i += nt) {
+        int p, q;
+        rr_pair(npad, s, i, p, q);
+        double c = 1.0, sn = 0.0;
+        cplx64 ph = cmake<cplx64>(1.0, 0.0);
+        if (p < n && q < n) {
+          double app = a[(long)p * ld + p].re, aqq = a[(long)q * ld + q].re;
+          cplx64 bpq = a[(long)p * ld + q];
+          double ab = sqrt(cabs2(bpq));
+          if (ab > tol * sqrt(fabs(app * aqq)) && ab > 1e-300) {
+            ph = cmake<cplx64>(bpq.re / ab, bpq.im / ab);
+            double th = (aqq - app) / (2.0 * ab);
+            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            any_rot = 1;
+          }
+        }
+        rp[i] = p;
+        rq[i] = q;
+        rc[i] = c;
+        rs[i] = sn;
+        rph[i] = ph;
+      }
+      __syncthreads();
+      // 2x2 block updates (P <= Q) and eigenvector updates.
+      const long nblk = (long)half * (half + 1) / 2;
+      for (long e = tid; e < nblk + (long)n * half; e += nt) {
+        if (e < nblk) {
+          // unrank (P, Q) with P <= Q
+          int P = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+          while ((long)(P + 1) * (P + 2) / 2 <= e) ++P;
+          while ((long)P * (P + 1) / 2 > e) --P;
+          int Q = (int)(e - (long)P * (P + 1) / 2);  // Q <= P
+          int p1 = rp[P], q1 = rq[P], p2 = rp[Q], q2 = rq[Q];
+          bool va = p1 < n && q1 < n, vb = p2 < n && q2 < n;
+          if (P == Q) {
+            if (!va || rs[P] == 0.0) continue;
+            double c = rc[P], sn = rs[P];
+            double app = a[(long)p1 * ld + p1].re, aqq = a[(long)q1 * ld + q1].re;
+            cplx64 bpq = a[(long)p1 * ld + q1];
+            double ab = sqrt(cabs2(bpq));
+            double t = sn / c;
+            a[(long)p1 * ld + p1] = cmake<cplx64>(app - t * ab, 0.0);
+            a[(long)q1 * ld + q1] = cmake<cplx64>(aqq + t * ab, 0.0);
+            a[(long)p1 * ld + q1] = cmake<cplx64>(0.0, 0.0);
+            a[(long)q1 * ld + p1] = cmake<cplx64>(0.0, 0.0);
+            continue;
+          }
+          // rows {p1,q1} (pair P) x cols {p2,q2} (pair Q); P != Q
+          // J = [[c, s], [-s e^{-i ph}, c e^{-i ph}]];  X' = J_P^H X J_Q
+          int r0 = p1, r1 = q1, c0 = p2, c1 = q2;
+          if (!va && !vb) continue;
+          cplx64 x00 = cmake<cplx64>(0, 0), x01 = x00, x10 = x00, x11 = x00;
+          bool r0v = r0 < n, r1v = r1 < n, c0v = c0 < n, c1v = c1 < n;
+          if (r0v && c0v) x00 = a[(long)r0 * ld + c0];
+          if (r0v && c1v) x01 = a[(long)r0 * ld + c1];
+          if (r1v && c0v) x10 = a[(long)r1 * ld + c0];
+          if (r1v && c1v) x11 = a[(long)r1 * ld + c1];
+          // right multiply by J_Q
+          double cq = rc[Q], sq = rs[Q];
+          cplx64 pq = cconj(rph[Q]);  // e^{-i ph}
+          if (vb && sq != 0.0) {
+            cplx64 y00 = csub(cscale(x00, cq), cmul(cscale(x01, sq), pq));
+            cplx64 y01 = cadd(cscale(x00, sq), cmul(cscale(x01, cq), pq));
+            cplx64 y10 = csub(cscale(x10, cq), cmul(cscale(x11, sq), pq));
+            cplx64 y11 = cadd(cscale(x10, sq), cmul(cscale(x11, cq), pq));
+            x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+          }
+          // left multiply by J_P^H = [[c, -s e^{i ph}], [s, c e^{i ph}]]
+          double cp = rc[P], sp = rs[P];
+          cplx64 pp = rph[P];  // e^{i ph}
+          if (va && sp != 0.0) {
+            cplx64 y00 = csub(cscale(x00, cp), cmul(cscale(x10, sp), pp));
+            cplx64 y01 = csub(cscale(x01, cp), cmul(cscale(x11, sp), pp));
+            cplx64 y10 = cadd(cscale(x00, sp), cmul(cscale(x10, cp), pp));
+            cplx64 y11 = cadd(cscale(x01, sp), cmul(cscale(x11, cp), pp));
+            x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+          }
+          if (r0v && c0v) { a[(long)r0 * ld + c0] = x00; a[(long)c0 * ld + r0] = cconj(x00); }
+          if (r0v && c1v) { a[(long)r0 * ld + c1] = x01; a[(long)c1 * ld + r0] = cconj(x01); }
+          if (r1v && c0v) { a[(long)r1 * ld + c0] = x10; a[(long)c0 * ld + r1] = cconj(x10); }
+          if (r1v && c1v) { a[(long)r1 * ld + c1] = x11; a[(long)c1 * ld + r1] = cconj(x11); }
+        } else {
+          long f = e - nblk;
+          int k = (int)(f / half), P = (int)(f % half);
+          int p1 = rp[P], q1 = rq[P];
+          if (p1 >= n || q1 >= n || rs[P] == 0.0) continue;
+          double c = rc[P], sn = rs[P];
+          cplx64 pq = cconj(rph[P]);
+          cplx64 vp = v[(long)k * ld + p1], vq = v[(long)k * ld + q1];
+          v[(long)k * ld + p1] = csub(cscale(vp, c), cmul(cscale(vq, sn), pq));
+          v[(long)k * ld + q1] = cadd(cscale(vp, sn), cmul(cscale(vq, c), pq));
+        }
+      }
+      __syncthreads();
+    }
+    converged = (any_rot == 0);
+    __syncthreads();
+  }
+  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI);
+  // sort descending: rank of each eigenvalue
+  for (int i = tid; i < n; i += nt) {
+    double wi = a[(long)i * ld + i].re;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double wj = a[(long)j * ld + j].re;
+      rank += (wj > wi) || (wj == wi && j < i);
+    }
+    w[(long)b * ld + rank] = wi;
+    for (int k = 0; k < n; ++k) Vout[(long)b * sA + (long)k * ld + rank] = v[(long)k * ld + i];
+  }
+}
+
+hipError_t jacobi_herm(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, long ld, long sA,
+                       int batch, int* err, cplx64* Vout) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_herm_batched, dim3(batch), dim3(1024), 0, st, A, Vtmp, w, dims, ld, sA, 60, 1e-15, err,
+                     Vout);
+  return hipGetLastError();
+}

@@ -1,0 +1,117 @@
+"""Python-facing API: build an MPS from a covariance matrix on the GPU and
+query amplitudes and samples.  Thin wrapper over the C ABI (see _lib)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BuildOpts, GbsError, InfoT, check, lib
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class GaussianMPS:
+    """Handle to a device-resident MPS built by gbs_mps_build."""
+
+    def __init__(self, handle: ctypes.c_void_p, M: int, d: int):
+        self._h = handle
+        self.M = M
+        self.d = d
+
+    # -- lifetime
+    def free(self) -> None:
+        if self._h:
+            lib().gbs_mps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- consumers
+    def amplitude(self, patterns: torch.Tensor, stream=None) -> torch.Tensor:
+        """Complex128 amplitudes <n|psi> for a (B, M) int32 CUDA tensor."""
+        if patterns.dtype != torch.int32 or not patterns.is_cuda or patterns.dim() != 2 or patterns.shape[1] != self.M:
+            raise ValueError("patterns must be a CUDA int32 tensor of shape (B, M)")
+        patterns = patterns.contiguous()
+        out = torch.empty((patterns.shape[0], 2), dtype=torch.float64, device=patterns.device)
+        check(lib().gbs_mps_amplitude(self._h, ctypes.c_void_p(patterns.data_ptr()), patterns.shape[0],
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return torch.view_as_complex(out)
+
+    def sample(self, shots: int, seed: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """(shots, M) int32 photon-number samples on the GPU."""
+        if out is None:
+            out = torch.empty((shots, self.M), dtype=torch.int32, device="cuda")
+        check(lib().gbs_mps_sample(self._h, int(shots), ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    # -- diagnostics
+    def info(self) -> dict:
+        inf = InfoT()
+        M = self.M
+        bond = (ctypes.c_int32 * (M + 1))()
+        ne = (ctypes.c_int32 * (M + 1))()
+        eps = (ctypes.c_double * (M + 1))()
+        ent = (ctypes.c_double * (M + 1))()
+        check(lib().gbs_mps_info(self._h, ctypes.byref(inf), bond, ne, eps, ent))
+        d = {f: getattr(inf, f) for f, _ in InfoT._fields_}
+        d["bond"] = list(bond)
+        d["ne"] = list(ne)
+        d["eps"] = list(eps)
+        d["entropy"] = list(ent)
+        return d
+
+    def export(self, m: int, what: str) -> np.ndarray:
+        inf = self.info()
+        d = self.d
+        kind = _lib.EXPORT[what]
+        if what in ("tensor", "raw", "Q"):
+            cap = 16 * (4097 * 4097 * max(1, d))
+            buf = np.empty(cap // 16, dtype=np.complex128)
+        else:
+            buf = np.empty(4097 * 4097 * 2, dtype=np.int32 if what == "basis" else np.float64)
+        written = ctypes.c_int64(0)
+        check(lib().gbs_mps_export(self._h, m, kind, ctypes.c_void_p(buf.ctypes.data), buf.nbytes,
+                                   ctypes.byref(written)))
+        n = written.value // buf.itemsize
+        arr = buf[:n].copy()
+        bond, ne = inf["bond"], inf["ne"]
+        if what == "tensor":
+            return arr.reshape(bond[m - 1], d, bond[m])
+        if what == "Q":
+            k = ne[m - 1] + 1 + ne[m]
+            return arr.reshape(k, k)
+        if what == "raw":
+            return arr.reshape(-1, d, arr.size // max(1, d) // max(1, arr.size // max(1, d)) or 1) if False else arr
+        if what == "basis":
+            return arr.reshape(-1, ne[m]) if ne[m] else np.zeros((1, 0), dtype=np.int32)
+        return arr
+
+
+def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, precision: str = "fp64",
+          keep_raw: bool = False, trunc_rel: float = 0.0, stream=None) -> GaussianMPS:
+    """Convert the pure Gaussian state with covariance `gamma` (2M x 2M FP64
+    CUDA tensor, xxpp, vacuum = I/2) into an MPS with cutoff d and bond chi."""
+    if not isinstance(gamma, torch.Tensor) or not gamma.is_cuda or gamma.dtype != torch.float64:
+        raise ValueError("gamma must be a CUDA float64 tensor")
+    if gamma.dim() != 2 or gamma.shape[0] != gamma.shape[1] or gamma.shape[0] % 2:
+        raise GbsError(_lib.GBS_E_INVAL, "gamma must be 2M x 2M")
+    gamma = gamma.contiguous()
+    M = gamma.shape[0] // 2
+    opts = BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS[precision],
+                     flags=_lib.GBS_KEEP_RAW if keep_raw else 0, trunc_rel=trunc_rel)
+    h = ctypes.c_void_p()
+    check(lib().gbs_mps_build(ctypes.c_void_p(gamma.data_ptr()), M, ctypes.byref(opts), _stream_handle(stream),
+                              ctypes.byref(h)))
+    return GaussianMPS(h, M, d)
