@@ -1,0 +1,163 @@
+"""Benchmark: Gaussian state -> MPS build plus photon-number sampling on one MI355X.
+
+One step = the whole hot path on the 144-mode workload (M=144, d=8, chi=256;
+144 squeezed vacua r ~ U[0.1, 0.4] through a Haar-random interferometer):
+validation, Gaussian SVD chain, kept bases, PCO tensors, truncation sweep,
+then 10^6 samples.  Prints one JSON line (rank 0, N=1).
+
+    python bench.py [--steps K] [--warmup W] [--shots S] [--precision fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MPS sites/s and samples/s at χ=256, 1−fidelity vs FP64; p50/p99 request latency"
+FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def sampling_flops_per_shot(bonds, d):
+    """Algorithmic flops of one shot: sum_m 8 d chi_{m-1} chi_m (complex MACs)."""
+    return sum(8.0 * d * bonds[m - 1] * bonds[m] for m in range(1, len(bonds)))
+
+
+def cpu_baseline(workload, budget_s=20.0):
+    """Time the CPU oracle on a bounded sample of the same workload and scale
+    it to samples/s of the whole step (build + shots)."""
+    import numpy as np
+    import oracle.build as ob
+    import oracle.gaussian as og
+    import oracle.mps as om
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    w = workload
+    t0 = time.perf_counter()
+    og.gsvd(w.gamma)
+    t_gsvd = time.perf_counter() - t0
+    mid = w.M // 2
+    sites = [mid, mid + 1]
+    t0 = time.perf_counter()
+    o = ob.build_mps(w.gamma, w.d, w.chi, sites=sites, validate=False)
+    t_pco = (time.perf_counter() - t0) - t_gsvd
+    t_site = max(t_pco, 1e-9) / len(sites)
+    # sampling cost per shot-site, measured on a chain made of the central tensors
+    chain = [o.raw[mid - 1][:1]] + [o.raw[mid - 1]] * 2 + [o.raw[mid][:, :, :1]]
+    chain = om.normalize(chain)
+    nshot = 60
+    t0 = time.perf_counter()
+    om.sample(chain, nshot, np.random.default_rng(0))
+    t_shot_site = (time.perf_counter() - t0) / (nshot * len(chain))
+    t_build = t_gsvd + w.M * t_site
+    return dict(t_build_s=t_build, t_shot_s=t_shot_site * w.M, threads=threads,
+                sample=(f"oracle Gaussian SVD of all {w.M} cuts ({t_gsvd:.2f}s) + PCO tensors of central sites "
+                        f"{sites} ({t_pco:.2f}s), extrapolated to {w.M} sites; oracle sampler on a 4-site chain of "
+                        f"the central {w.chi}x{w.d}x{w.chi} tensors, {nshot} shots, scaled to {w.M} sites"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=1_000_000)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=12345)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2512_10643_amd import mps as gmps
+
+    w = workloads.workload(args.workload)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    gamma = torch.tensor(w.gamma, dtype=torch.float64, device=dev)
+    out = torch.empty((args.shots, w.M), dtype=torch.int32, device=dev)
+
+    def step(seed):
+        t0 = time.perf_counter()
+        h = gmps.build(gamma, w.d, w.chi, precision=args.precision)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.sample(args.shots, seed, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        inf = h.info()
+        h.free()
+        return dict(build_s=t1 - t0, sample_s=t2 - t1, sample_ev_ms=e0.elapsed_time(e1), info=inf)
+
+    for i in range(args.warmup):
+        step(args.seed + 1000 + i)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        recs.append(step(args.seed + i))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = 1000.0 * total / args.steps
+    inf = recs[-1]["info"]
+    bonds = inf["bond"]
+    fl_shot = sampling_flops_per_shot(bonds, w.d)
+    samp_ms = sum(r["sample_ev_ms"] for r in recs) / len(recs)
+    build_s = sum(r["build_s"] for r in recs) / len(recs)
+    achieved = fl_shot * args.shots / (samp_ms / 1000.0) / 1e12
+    peak = FP32_MFMA_PEAK_TFLOPS if args.precision != "fp64" else FP64_PEAK_TFLOPS
+    res = {
+        "metric": METRIC,
+        "value": args.shots / (ms_per_step / 1000.0),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "complex-f32", "fp64": "complex-f64", "bf16x3": "bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: M={w.M} d={w.d} chi={w.chi}, squeezed vacua through an "
+                               f"interferometer; build + {args.shots} samples per step",
+                   "M": w.M, "d": w.d, "chi": w.chi, "shots": args.shots, "precision": args.precision},
+        "sites_per_s": w.M / build_s,
+        "build_ms": 1000 * build_s,
+        "build_phase_ms": {k: inf[k] for k in ("t_gsvd_ms", "t_kept_ms", "t_pco_ms", "t_svd_ms")},
+        "samples_per_s_sampling_only": args.shots / (samp_ms / 1000.0),
+        "eps_max": inf["eps_max"],
+        "max_bond": inf["max_bond"],
+        "flops_per_sample": fl_shot,
+        "roofline": {"bound": "mfma", "kernel": "sampling sweep (all sites)", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w)
+        t_step = cb["t_build_s"] + args.shots * cb["t_shot_s"]
+        res["cpu_baseline"] = {"value": args.shots / t_step, "unit": "samples/s", "cores": cb["threads"],
+                               "kind": "oracle", "sample": cb["sample"],
+                               "sites_per_s": w.M / cb["t_build_s"], "samples_per_s_sampling_only": 1.0 / cb["t_shot_s"]}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
