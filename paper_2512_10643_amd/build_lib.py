@@ -21,6 +21,7 @@ SOURCES = [
     "gbs_kept.hip",
     "gbs_pco.hip",
     "gbs_mpsops.hip",
+    "gbs_sampler.hip",
     "gbs_api.cpp",
 ]
 

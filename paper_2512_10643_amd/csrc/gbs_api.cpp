@@ -17,6 +17,7 @@
 #include "gbs_linalg.h"
 #include "gbs_mpsops.h"
 #include "gbs_pco.h"
+#include "gbs_sampler.h"
 
 namespace {
 
@@ -100,6 +101,8 @@ struct gbs_mps_s {
   // diagnostics
   cplx64* Q = nullptr;
   long q_stride = 0, ld_q = 0;
+  float* packed = nullptr;       // MFMA sampler operand layout (FP32 builds)
+  std::vector<long> poff;        // per site offset into `packed` (floats)
   cplx64* raw = nullptr;         // PCO tensors (GBS_KEEP_RAW)
   std::vector<long> raw_off;
   short* occ = nullptr;
@@ -118,20 +121,22 @@ C czero() {
   return cmake<C>(0, 0);
 }
 
-// Canonicalisation and truncation (precision C for contractions; FP64 eigen).
-template <typename C>
+// Truncation sweep and canonical form.  The Gram / environment matrices whose
+// eigenvalues are the squared singular values, and their eigen-decompositions,
+// are FP64; the gauge transforms that produce the stored tensors run in the
+// build precision CT.
+template <typename CT>
 int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64, const std::vector<long>& t64off) {
+  typedef cplx64 C;
   const int M = h->M, d = h->d;
-  const double tau = h->trunc_rel > 0 ? h->trunc_rel * h->trunc_rel : (std::is_same<C, cplx64>::value ? 1e-24 : 1e-12);
-  // working tensors A^m in precision C, dims (cl, d, cr)
+  const double tau = h->trunc_rel > 0 ? h->trunc_rel * h->trunc_rel : (std::is_same<CT, cplx64>::value ? 1e-24 : 1e-16);
+  // working tensors A^m (FP64), dims (cl, d, cr)
   std::vector<int> cl(M + 1), cr(M + 1);
   std::vector<C*> A(M + 1, nullptr);
   for (int m = 1; m <= M; ++m) {
     cl[m] = h->kept[m - 1];
     cr[m] = h->kept[m];
-    long n = (long)cl[m] * d * cr[m];
-    HIP_CHECK_RET(dalloc(tmp, &A[m], n));
-    HIP_CHECK_RET(convert<C, cplx64>(st, A[m], T64 + t64off[m], n));
+    A[m] = (C*)(T64 + t64off[m]);
   }
   const int chi_ld = *std::max_element(h->kept.begin(), h->kept.end()) * d + 1;
   cplx64 *G64, *Vtmp, *Vec;
@@ -290,41 +295,44 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
     h->svals[m].resize(k);
     for (int i = 0; i < k; ++i) h->svals[m][i] = std::sqrt(w[i]);
   }
-  // (5) B^m = S_{m-1}^-1 U_{m-1}^H A^m[p] U_m S_m
+  // (5) B^m = S_{m-1}^-1 U_{m-1}^H A^m[p] U_m S_m, in the build precision
   long total = 0;
   h->toff.assign(M + 1, 0);
   for (int m = 1; m <= M; ++m) {
     h->toff[m] = total;
     total += (long)r[m - 1] * d * r[m];
   }
-  C* out;
+  CT* out;
   HIP_CHECK_RET(dalloc(h->keep, &out, (size_t)total));
   h->tens = out;
-  h->esz = sizeof(C);
-  C* Ub;   // U_m in precision C, (eld x eld)
+  h->esz = sizeof(CT);
+  CT *Ub, *Am, *Tc;  // U_m in precision CT (eld x eld), one site tensor, scratch
   HIP_CHECK_RET(dalloc(tmp, &Ub, (size_t)(M + 1) * eld * eld));
+  HIP_CHECK_RET(dalloc(tmp, &Am, (size_t)eld * d * eld + d));
+  HIP_CHECK_RET(dalloc(tmp, &Tc, (size_t)eld * d * eld + d));
   for (int m = 1; m < M; ++m)
-    HIP_CHECK_RET(scaled_copy<C>(st, Ub + (long)m * eld * eld, eld, EV64 + (long)m * eld * eld, eld, edim[m], r[m],
-                                 nullptr, 0, 0));
+    HIP_CHECK_RET(scaled_copy<CT>(st, Ub + (long)m * eld * eld, eld, EV64 + (long)m * eld * eld, eld, edim[m], r[m],
+                                  nullptr, 0, 0));
   for (int m = 1; m <= M; ++m) {
     int a = cl[m], b = cr[m], ra = r[m - 1], rb = r[m];
+    HIP_CHECK_RET(convert<CT, cplx64>(st, Am, A[m], (long)a * d * b));
     // Y = A^m[p] U_m  (a x d x rb)
-    const C* Y = A[m];
+    const CT* Y = Am;
     if (m < M) {
-      HIP_CHECK_RET(zgemm<C>(st, a, rb, b, cone<C>(), A[m], (long)d * b, b, 0, Ub + (long)m * eld * eld, eld, 0, 0,
-                             czero<C>(), Tb, (long)d * rb, rb, d));
-      Y = Tb;
+      HIP_CHECK_RET(zgemm<CT>(st, a, rb, b, cone<CT>(), Am, (long)d * b, b, 0, Ub + (long)m * eld * eld, eld, 0, 0,
+                              czero<CT>(), Tc, (long)d * rb, rb, d));
+      Y = Tc;
     }
-    C* Bm = out + h->toff[m];
+    CT* Bm = out + h->toff[m];
     if (m > 1) {
-      HIP_CHECK_RET(zgemm<C>(st, ra, d * rb, a, cone<C>(), Ub + (long)(m - 1) * eld * eld, eld, 0, 2, Y, (long)d * rb, 0,
-                             0, czero<C>(), Bm, (long)d * rb, 0, 1));
+      HIP_CHECK_RET(zgemm<CT>(st, ra, d * rb, a, cone<CT>(), Ub + (long)(m - 1) * eld * eld, eld, 0, 2, Y,
+                              (long)d * rb, 0, 0, czero<CT>(), Bm, (long)d * rb, 0, 1));
     } else {
-      HIP_CHECK_RET(hipMemcpyAsync(Bm, Y, sizeof(C) * (long)a * d * rb, hipMemcpyDeviceToDevice, st));
+      HIP_CHECK_RET(hipMemcpyAsync(Bm, Y, sizeof(CT) * (long)a * d * rb, hipMemcpyDeviceToDevice, st));
     }
     const double* wl = m > 1 ? W64 + (long)(m - 1) * eld : nullptr;
     const double* wr = m < M ? W64 + (long)m * eld : nullptr;
-    HIP_CHECK_RET(gauge_scale<C>(st, Bm, ra, d, rb, wl, wr));
+    HIP_CHECK_RET(gauge_scale<CT>(st, Bm, ra, d, rb, wl, wr));
   }
   // (6) normalise and fix the phase
   h->bond = r;
@@ -339,7 +347,7 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   double* nrm;
   HIP_CHECK_RET(dalloc(tmp, &vbuf, 2 * GBS_CHI_MAX));
   HIP_CHECK_RET(dalloc(tmp, &nrm, 1));
-  HIP_CHECK_RET(normalize_mps<C>(st, (C**)h->site_ptrs, h->bond_dev, M, d, vbuf, nrm));
+  HIP_CHECK_RET(normalize_mps<CT>(st, (CT**)h->site_ptrs, h->bond_dev, M, d, vbuf, nrm));
   HIP_CHECK_RET(hipMemcpyAsync(&h->norm_raw, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK_RET(hipStreamSynchronize(st));
   return GBS_OK;
@@ -619,6 +627,20 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off)
                                  : canonicalize<cplx32>(h, st, tmp, T64, t64off);
   if (rc) return rc;
+  if (h->prec != GBS_FP64 && h->maxbond <= 256) {
+    // sampler operand layout
+    h->poff.assign(M + 1, 0);
+    long tot = 0;
+    for (int m = 1; m <= M; ++m) {
+      h->poff[m] = tot;
+      tot += (long)d * 2 * sampler_pad(h->bond[m - 1]) * 2 * sampler_pad(h->bond[m]);
+    }
+    HIP_CHECK_RET(dalloc(h->keep, &h->packed, (size_t)tot));
+    for (int m = 1; m <= M; ++m)
+      HIP_CHECK_RET(launch_pack(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
+                                h->packed + h->poff[m]));
+    HIP_CHECK_RET(hipStreamSynchronize(st));
+  }
   h->t_svd = now_ms() - t3;
   return GBS_OK;
 }
@@ -697,7 +719,26 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   const int64_t chunk = std::min<int64_t>(shots, (int64_t)1 << 18);
   DevArena tmp;
   void* lbuf[2];
-  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * ldl * h->esz));
+  const size_t rowbytes = std::max((size_t)ldl * h->esz, (size_t)2 * sampler_pad(h->maxbond) * sizeof(float));
+  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * rowbytes));
+  if (h->packed) {
+    // MFMA path: left vectors as interleaved floats, rows padded to 16 complex
+    const long ldl2 = 2L * sampler_pad(h->maxbond);
+    float* fb[2] = {(float*)lbuf[0], (float*)lbuf[1]};
+    for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
+      const int64_t n = std::min(chunk, shots - s0);
+      HIP_CHECK_RET(hipMemsetAsync(fb[0], 0, (size_t)n * ldl2 * sizeof(float), st));
+      HIP_CHECK_RET(launch_fill_first<cplx32>(st, (cplx32*)fb[0], ldl2 / 2, n));
+      int cur = 0;
+      for (int m = 1; m <= M; ++m) {
+        HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], h->bond[m - 1], d, h->bond[m], fb[cur],
+                                         fb[1 - cur], ldl2, s0, n, m, seed, out, M));
+        cur = 1 - cur;
+      }
+    }
+    HIP_CHECK_RET(hipStreamSynchronize(st));
+    return GBS_OK;
+  }
   for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
     const int64_t n = std::min(chunk, shots - s0);
     int cur = 0;

@@ -209,3 +209,28 @@ def test_error_paths(torch_cuda):
         h.amplitude(p)
     assert e.value.name == "INVAL"
     h.free()
+
+
+def test_sampling_fp32_mfma_c2(torch_cuda):
+    """FP32 build -> MFMA sampler: per-mode marginals vs the oracle's exact ones,
+    seed determinism and independence from batching."""
+    _say("case: c2 fp32 MFMA sampling, 200000 shots")
+    w = W.workload("c2")
+    o = obuild.build_mps(w.gamma, w.d, w.chi)
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
+    shots = 200_000
+    s = h.sample(shots, seed=5).cpu().numpy()
+    assert np.all((s >= 0) & (s < w.d))
+    assert np.all(s.sum(1) % 2 == 0)
+    pm = omps.site_marginals(o.tensors)
+    worst = 0.0
+    for m in range(w.M):
+        emp = np.bincount(s[:, m], minlength=w.d) / shots
+        tvd = 0.5 * np.abs(emp - pm[m]).sum()
+        floor = 0.5 * np.sum(np.sqrt(2 * pm[m] / (np.pi * shots)))
+        worst = max(worst, tvd / floor)
+        assert tvd < 5 * floor + 1e-4, (m, tvd, floor)
+    _say(f"  worst per-mode TVD / noise floor = {worst:.2f}")
+    s2 = h.sample(777, seed=5).cpu().numpy()
+    assert np.array_equal(s2, s[:777])
+    h.free()
