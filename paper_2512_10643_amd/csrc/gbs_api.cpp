@@ -417,6 +417,14 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_O, wsz));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_S, wsz));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_vec, (size_t)3 * n2max));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_W, wsz));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_pack, (size_t)n2max * (n2max + 1) / 2));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_w, (size_t)n2max));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_ord, (size_t)n2max));
+  ga.ld_glr = 2 * M;
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_glr, (size_t)n2max * 2 * M));
+  HIP_CHECK_RET(dalloc(tmp, &ga.rot_log, (size_t)GBS_GSVD_MAX_SWEEPS * n2max * (n2max / 2 + 1)));
+  HIP_CHECK_RET(dalloc(tmp, &ga.nsweep, 1));
   ga.ld_u = n2max / 2 + 1;
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_U, (size_t)ga.ld_u * ga.ld_u));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_V, (size_t)ga.ld_u * ga.ld_u));
@@ -426,7 +434,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     ga.drr_out = drr[m & 1];
     ga.cr_in = cr[(m + 1) & 1];
     ga.cr_out = cr[m & 1];
-    HIP_CHECK_RET(launch_gsvd_cut(st, ga, m));
+    HIP_CHECK_RET(launch_gsvd_cut(st, ga, m, n2max));
   }
   std::vector<int> ne(M + 1);
   std::vector<double> lamh((size_t)(M + 1) * ga.ld_dsym);

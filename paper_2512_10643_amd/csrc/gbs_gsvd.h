@@ -2,7 +2,10 @@
 #pragma once
 #include "gbs_common.h"
 
-#define GBS_GSVD_N2_MAX 600   // 2 * (n_e^{m-1} + 1) handled by one workgroup
+#define GBS_GSVD_N2_MAX 600      // 2 * (n_e^{m-1} + 1) handled by one workgroup
+#define GBS_GSVD_LDS_N2 176      // packed symmetric working matrix kept in LDS up to this size
+#define GBS_GSVD_MAX_SWEEPS 40   // Jacobi sweep limit
+#define GBS_GSVD_VROWS 16        // eigenvector rows per workgroup in the replay pass
 
 struct GsvdArgs {
   int M;
@@ -22,11 +25,14 @@ struct GsvdArgs {
   cplx64* Q;             // per-site pair matrices
   long q_stride, ld_q;
   // workspace
-  double *ws_G, *ws_L, *ws_A, *ws_B, *ws_E, *ws_O, *ws_S, *ws_vec;
-  long ld_ws;
+  double *ws_G, *ws_L, *ws_A, *ws_B, *ws_E, *ws_O, *ws_S, *ws_vec, *ws_W, *ws_pack, *ws_w, *ws_glr;
+  int* ws_ord;
+  double2* rot_log;
+  int* nsweep;
+  long ld_ws, ld_glr;
   cplx64 *ws_U, *ws_V, *ws_aug;
   long ld_u;
 };
 
 hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* scal, double* wsM, int* err);
-hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m);
+hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max);

@@ -1,12 +1,12 @@
 // Input validation and the iterative Gaussian SVD (Sec. II.A-B, App. A), FP64.
 //
-// One 1024-thread workgroup handles one cut; cuts run in order on the
-// stream because each consumes the residual the previous one produced.
-// Williamson form of the left block L = (r_{m-1}, a_m):
+// Cuts run in order on the stream because each consumes the residual the
+// previous one produced.  Williamson form of the left block L = (r_{m-1}, a_m):
 //   2 Gamma_LL = L L^T (Cholesky), A = L^T Omega L (antisymmetric),
 //   B = A^T A (symmetric, eigenvalues D_q^2 twice) by Jacobi rotations,
-//   symplectic pairs (u, v = -A u / D) by Gram-Schmidt over the sorted
-//   eigenvectors, S = L [u.., v..] diag(D, D)^(-1/2).
+//   symplectic pairs (u, v = -A u / D) from the sorted eigenvectors (within
+//   a cluster of equal eigenvalues by Gram-Schmidt), and
+//   S = L [u.., v..] diag(D, D)^(-1/2).
 // Bogoliubov matrices follow from Eq. MUV, the paired form of the local
 // state from the regularised Q_L of App. A, and the next residual from the
 // b-mode quadrature map T = -S^T Omega restricted to the active modes.
@@ -26,102 +26,6 @@ __device__ inline void rr_pair_s(int npad, int s, int i, int& p, int& q) {
     p = 1 + ((s + i) % m);
     q = 1 + (((s - i) % m + m) % m);
   }
-}
-
-// Real symmetric Jacobi by one workgroup.  a (n x n, ld) is diagonalised in
-// place, v receives the eigenvectors as columns.  Returns false if it did not
-// converge within max_sweeps.
-__device__ bool jacobi_sym_wg(double* a, double* v, int n, long ld, int max_sweeps, double* rc, double* rs, int* rp,
-                              int* rq, int* flag) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (long e = tid; e < (long)n * n; e += nt) {
-    long i = e / n, j = e % n;
-    v[i * ld + j] = (i == j) ? 1.0 : 0.0;
-  }
-  wg_sync();
-  if (n == 1) return true;
-  const int npad = n + (n & 1), half = npad / 2;
-  const long nblk = (long)half * (half + 1) / 2;
-  bool converged = false;
-  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-    if (tid == 0) *flag = 0;
-    wg_sync();
-    for (int s = 0; s < npad - 1; ++s) {
-      for (int i = tid; i < half; i += nt) {
-        int p, q;
-        rr_pair_s(npad, s, i, p, q);
-        double c = 1.0, sn = 0.0;
-        if (p < n && q < n) {
-          double app = a[(long)p * ld + p], aqq = a[(long)q * ld + q], apq = a[(long)p * ld + q];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-            double th = (aqq - app) / (2.0 * apq);
-            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            sn = t * c;
-            *flag = 1;
-          }
-        }
-        rp[i] = p;
-        rq[i] = q;
-        rc[i] = c;
-        rs[i] = sn;
-      }
-      wg_sync();
-      for (long e = tid; e < nblk + (long)n * half; e += nt) {
-        if (e < nblk) {
-          int P = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-          while ((long)(P + 1) * (P + 2) / 2 <= e) ++P;
-          while ((long)P * (P + 1) / 2 > e) --P;
-          int Q = (int)(e - (long)P * (P + 1) / 2);
-          int p1 = rp[P], q1 = rq[P], p2 = rp[Q], q2 = rq[Q];
-          if (P == Q) {
-            if (p1 >= n || q1 >= n || rs[P] == 0.0) continue;
-            double t = rs[P] / rc[P];
-            double apq = a[(long)p1 * ld + q1];
-            a[(long)p1 * ld + p1] -= t * apq;
-            a[(long)q1 * ld + q1] += t * apq;
-            a[(long)p1 * ld + q1] = 0.0;
-            a[(long)q1 * ld + p1] = 0.0;
-            continue;
-          }
-          bool r0v = p1 < n, r1v = q1 < n, c0v = p2 < n, c1v = q2 < n;
-          double x00 = (r0v && c0v) ? a[(long)p1 * ld + p2] : 0.0;
-          double x01 = (r0v && c1v) ? a[(long)p1 * ld + q2] : 0.0;
-          double x10 = (r1v && c0v) ? a[(long)q1 * ld + p2] : 0.0;
-          double x11 = (r1v && c1v) ? a[(long)q1 * ld + q2] : 0.0;
-          double cq = rc[Q], sq = rs[Q];
-          if (sq != 0.0) {  // X J_Q, J = [[c, s], [-s, c]]
-            double y00 = cq * x00 - sq * x01, y01 = sq * x00 + cq * x01;
-            double y10 = cq * x10 - sq * x11, y11 = sq * x10 + cq * x11;
-            x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-          }
-          double cp = rc[P], sp = rs[P];
-          if (sp != 0.0) {  // J_P^T X
-            double y00 = cp * x00 - sp * x10, y01 = cp * x01 - sp * x11;
-            double y10 = sp * x00 + cp * x10, y11 = sp * x01 + cp * x11;
-            x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-          }
-          if (r0v && c0v) { a[(long)p1 * ld + p2] = x00; a[(long)p2 * ld + p1] = x00; }
-          if (r0v && c1v) { a[(long)p1 * ld + q2] = x01; a[(long)q2 * ld + p1] = x01; }
-          if (r1v && c0v) { a[(long)q1 * ld + p2] = x10; a[(long)p2 * ld + q1] = x10; }
-          if (r1v && c1v) { a[(long)q1 * ld + q2] = x11; a[(long)q2 * ld + q1] = x11; }
-        } else {
-          long f = e - nblk;
-          int k = (int)(f / half), P = (int)(f % half);
-          int p1 = rp[P], q1 = rq[P];
-          if (p1 >= n || q1 >= n || rs[P] == 0.0) continue;
-          double c = rc[P], sn = rs[P];
-          double vp = v[(long)k * ld + p1], vq = v[(long)k * ld + q1];
-          v[(long)k * ld + p1] = c * vp - sn * vq;
-          v[(long)k * ld + q1] = sn * vp + c * vq;
-        }
-      }
-      wg_sync();
-    }
-    converged = (*flag == 0);
-    wg_sync();
-  }
-  return converged;
 }
 
 // Parallel reduction of one value per thread into red[0] (block of 1024).
@@ -214,214 +118,472 @@ __global__ __launch_bounds__(1024) void chol_xx_kernel(const double* g, int M, d
 }
 
 // ---------------------------------------------------------------------------
-// One GSVD step.  Dimensions read from device state so the host can enqueue
-// every cut without synchronising.
-__global__ __launch_bounds__(1024) void gsvd_cut_kernel(GsvdArgs a, int m) {
+// Gaussian SVD chain, three launches per cut (all sizes read from device
+// state so the host enqueues every cut without synchronising):
+//   stage 1 (one workgroup): Gamma_LL, Cholesky, A = L^T Omega L, B = A^T A,
+//            Jacobi on B packed in LDS; every rotation (c, s) is logged;
+//   V-apply (several workgroups): eigenvectors of B by replaying the log on
+//            row blocks of the identity (rows are independent);
+//   stage 2 (one workgroup): symplectic pairs, S, U, V, (U^dag)^-1, Q^m and
+//            the next residual.
+namespace {
+
+constexpr int TILE = 32;
+
+// C (M x N, ldc) = alpha op(A) op(B) + beta C by one 1024-thread workgroup.
+// op(X) = X^T when the flag is set.  32x32 output tiles staged through LDS.
+__device__ void wg_dgemm(int M, int N, int K, double alpha, const double* A, long lda, bool tA, const double* B,
+                         long ldb, bool tB, double beta, double* C, long ldc, double* smem) {
+  double* As = smem;                       // [k][i], TILE x (TILE + 1)
+  double* Bs = smem + TILE * (TILE + 1);   // [k][j]
+  const int tid = threadIdx.x;
+  const int ty = tid / TILE, tx = tid % TILE;
+  const int ti = (M + TILE - 1) / TILE, tj = (N + TILE - 1) / TILE;
+  for (int t = 0; t < ti * tj; ++t) {
+    const int i0 = (t / tj) * TILE, j0 = (t % tj) * TILE;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < K; k0 += TILE) {
+      if (tA) {  // op(A)(i,k) = A[k][i]
+        int k = k0 + ty, i = i0 + tx;
+        As[ty * (TILE + 1) + tx] = (k < K && i < M) ? A[(long)k * lda + i] : 0.0;
+      } else {
+        int i = i0 + ty, k = k0 + tx;
+        As[tx * (TILE + 1) + ty] = (k < K && i < M) ? A[(long)i * lda + k] : 0.0;
+      }
+      if (tB) {  // op(B)(k,j) = B[j][k]
+        int j = j0 + ty, k = k0 + tx;
+        Bs[tx * (TILE + 1) + ty] = (k < K && j < N) ? B[(long)j * ldb + k] : 0.0;
+      } else {
+        int k = k0 + ty, j = j0 + tx;
+        Bs[ty * (TILE + 1) + tx] = (k < K && j < N) ? B[(long)k * ldb + j] : 0.0;
+      }
+      wg_sync();
+#pragma unroll 8
+      for (int kk = 0; kk < TILE; ++kk) acc += As[kk * (TILE + 1) + ty] * Bs[kk * (TILE + 1) + tx];
+      wg_sync();
+    }
+    const int i = i0 + ty, j = j0 + tx;
+    if (i < M && j < N) {
+      double v = alpha * acc;
+      if (beta != 0.0) v += beta * C[(long)i * ldc + j];
+      C[(long)i * ldc + j] = v;
+    }
+  }
+}
+
+__device__ inline long pk(int i, int j) {  // packed lower triangle, any order
+  return i >= j ? (long)i * (i + 1) / 2 + j : (long)j * (j + 1) / 2 + i;
+}
+
+}  // namespace
+
+// Stage 1.
+__global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int M = a.M;
   if (*a.err) return;
   const int n_prev = a.ne[m - 1];
-  const int nL = n_prev + 1, N2 = 2 * nL, nR = M - m;
+  const int nL = n_prev + 1, N2 = 2 * nL;
   if (N2 > GBS_GSVD_N2_MAX) {
     if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_KMAX);
     return;
   }
+  extern __shared__ double lds[];
+  __shared__ double rc[GBS_GSVD_N2_MAX / 2 + 1], rs[GBS_GSVD_N2_MAX / 2 + 1];
+  __shared__ int rp[GBS_GSVD_N2_MAX / 2 + 1], rq[GBS_GSVD_N2_MAX / 2 + 1];
+  __shared__ int flag, bad;
   const long ld = a.ld_ws;
-  double* G = a.ws_G;     // Gamma_LL (kept)
-  double* Lm = a.ws_L;    // Cholesky factor of 2 Gamma_LL
-  double* Am = a.ws_A;    // L^T Omega L
-  double* Bm = a.ws_B;    // A^T A -> diagonalised
-  double* Ev = a.ws_E;    // eigenvectors of B
-  double* Om = a.ws_O;    // symplectic pairs [u.., v..]
-  double* Sm = a.ws_S;    // symplectic M of the Williamson form
-  double* vec = a.ws_vec; // scratch vectors (3 * ld)
+  const long npk = (long)N2 * (N2 + 1) / 2;
+  const bool in_lds = N2 <= GBS_GSVD_LDS_N2;
+  double* P = in_lds ? lds : a.ws_pack;        // packed symmetric working matrix
+  double* tiles = lds + (long)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2;
+  double* G = a.ws_G;
+  double* Lm = a.ws_L;
+  double* W = a.ws_W;
+  double* Am = a.ws_A;
   const double* g = a.gamma;
   const int n2g = 2 * M;
   const double* Drr = a.drr_in;
   const double* CR = a.cr_in;
   const long ldd = a.ld_drr, ldc = a.ld_cr;
-  __shared__ double rc[600], rs[600], red[40];
-  __shared__ int rp[600], rq[600], flag, npairs, bad;
-  __shared__ double dsel[600];
+  const int gxa = m - 1, gpa = M + m - 1;
 
-  // 1. Gamma_LL in the xxpp order of (r_1..r_nprev, a_m).
-  const int gxa = m - 1, gpa = M + m - 1;  // rows of a_m in Gamma
+  // Gamma_LL in the xxpp order of (r_1..r_nprev, a_m); 2 Gamma_LL packed.
   for (long e = tid; e < (long)N2 * N2; e += nt) {
     int i = (int)(e / N2), j = (int)(e % N2);
     int ii = i % nL, jj = j % nL;
     bool ip = i >= nL, jp = j >= nL;
     double val;
-    if (ii < n_prev && jj < n_prev) {
-      val = Drr[(long)(ip ? n_prev + ii : ii) * ldd + (jp ? n_prev + jj : jj)];
-    } else if (ii < n_prev) {  // r row, a_m column
-      val = CR[(long)(ip ? n_prev + ii : ii) * ldc + (jp ? gpa : gxa)];
-    } else if (jj < n_prev) {
-      val = CR[(long)(jp ? n_prev + jj : jj) * ldc + (ip ? gpa : gxa)];
-    } else {
-      val = g[(long)(ip ? gpa : gxa) * n2g + (jp ? gpa : gxa)];
-    }
+    if (ii < n_prev && jj < n_prev) val = Drr[(long)(ip ? n_prev + ii : ii) * ldd + (jp ? n_prev + jj : jj)];
+    else if (ii < n_prev) val = CR[(long)(ip ? n_prev + ii : ii) * ldc + (jp ? gpa : gxa)];
+    else if (jj < n_prev) val = CR[(long)(jp ? n_prev + jj : jj) * ldc + (ip ? gpa : gxa)];
+    else val = g[(long)(ip ? gpa : gxa) * n2g + (jp ? gpa : gxa)];
     G[(long)i * ld + j] = val;
-    Lm[(long)i * ld + j] = 2.0 * val;
+    if (j <= i) P[pk(i, j)] = 2.0 * val;
   }
   wg_sync();
-  // 2. Cholesky 2 Gamma_LL = L L^T (lower, in place in Lm).
+  // Cholesky (right looking, packed lower triangle).
   for (int j = 0; j < N2; ++j) {
     if (tid == 0) {
-      double d = Lm[(long)j * ld + j];
-      bad = !(d > 0.0);
-      Lm[(long)j * ld + j] = d > 0.0 ? sqrt(d) : 1.0;
+      double dj = P[pk(j, j)];
+      bad = !(dj > 0.0);
+      P[pk(j, j)] = dj > 0.0 ? sqrt(dj) : 1.0;
     }
     wg_sync();
     if (bad) {
       if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_NOT_PD);
       return;
     }
-    double piv = Lm[(long)j * ld + j];
-    for (int i = j + 1 + tid; i < N2; i += nt) Lm[(long)i * ld + j] /= piv;
+    const double piv = P[pk(j, j)];
+    for (int i = j + 1 + tid; i < N2; i += nt) P[pk(i, j)] /= piv;
     wg_sync();
-    const long rem = N2 - j - 1;
-    for (long e = tid; e < rem * rem; e += nt) {
-      long i = j + 1 + e / rem, k = j + 1 + e % rem;
-      if (k <= i) Lm[i * ld + k] -= Lm[i * ld + j] * Lm[k * ld + j];
+    const int rem = N2 - j - 1;
+    const long ntri = (long)rem * (rem + 1) / 2;
+    for (long e = tid; e < ntri; e += nt) {
+      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+      while ((long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      while ((long)ii * (ii + 1) / 2 > e) --ii;
+      int kk = (int)(e - (long)ii * (ii + 1) / 2);
+      int i = j + 1 + ii, k = j + 1 + kk;
+      P[pk(i, k)] -= P[pk(i, j)] * P[pk(k, j)];
     }
     wg_sync();
   }
-  for (long e = tid; e < (long)N2 * N2; e += nt) {
-    long i = e / N2, j = e % N2;
-    if (j > i) Lm[i * ld + j] = 0.0;
-  }
-  wg_sync();
-  // 3. A = L^T (Omega L); (Omega L)_k = L_{k+nL} for k < nL, -L_{k-nL} otherwise.
+  // L (full, row-major) and W = Omega L: W_k = L_{k+nL} (k < nL), -L_{k-nL} (k >= nL).
   for (long e = tid; e < (long)N2 * N2; e += nt) {
     int i = (int)(e / N2), j = (int)(e % N2);
-    double s = 0.0;
-    for (int k = 0; k < N2; ++k) {
-      double ol = k < nL ? Lm[(long)(k + nL) * ld + j] : -Lm[(long)(k - nL) * ld + j];
-      s += Lm[(long)k * ld + i] * ol;
+    Lm[(long)i * ld + j] = j <= i ? P[pk(i, j)] : 0.0;
+  }
+  wg_sync();
+  for (long e = tid; e < (long)N2 * N2; e += nt) {
+    int k = (int)(e / N2), j = (int)(e % N2);
+    W[(long)k * ld + j] = k < nL ? Lm[(long)(k + nL) * ld + j] : -Lm[(long)(k - nL) * ld + j];
+  }
+  wg_sync();
+  // A = L^T W;  B = A^T A (packed into P).
+  wg_dgemm(N2, N2, N2, 1.0, Lm, ld, true, W, ld, false, 0.0, Am, ld, tiles);
+  wg_sync();
+  wg_dgemm(N2, N2, N2, 1.0, Am, ld, true, Am, ld, false, 0.0, a.ws_B, ld, tiles);
+  wg_sync();
+  for (long e = tid; e < npk; e += nt) {
+    int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+    while ((long)(i + 1) * (i + 2) / 2 <= e) ++i;
+    while ((long)i * (i + 1) / 2 > e) --i;
+    int j = (int)(e - (long)i * (i + 1) / 2);
+    P[e] = 0.5 * (a.ws_B[(long)i * ld + j] + a.ws_B[(long)j * ld + i]);
+  }
+  wg_sync();
+  // Jacobi on the packed matrix; rotations logged for the eigenvector pass.
+  const int npad = N2 + (N2 & 1), half = npad / 2;
+  const long nblk = (long)half * (half + 1) / 2;
+  double2* log = a.rot_log;
+  int sweeps = 0;
+  bool converged = false;
+  for (int sweep = 0; sweep < GBS_GSVD_MAX_SWEEPS && !converged; ++sweep) {
+    if (tid == 0) flag = 0;
+    wg_sync();
+    for (int s = 0; s < npad - 1; ++s) {
+      for (int i = tid; i < half; i += nt) {
+        int p, q;
+        rr_pair_s(npad, s, i, p, q);
+        double c = 1.0, sn = 0.0;
+        if (p < N2 && q < N2) {
+          double app = P[pk(p, p)], aqq = P[pk(q, q)], apq = P[pk(p, q)];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+            double th = (aqq - app) / (2.0 * apq);
+            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            flag = 1;
+          }
+        }
+        rp[i] = p;
+        rq[i] = q;
+        rc[i] = c;
+        rs[i] = sn;
+        log[((long)sweep * (npad - 1) + s) * half + i] = make_double2(c, sn);
+      }
+      wg_sync();
+      for (long e = tid; e < nblk; e += nt) {
+        int PP = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+        while ((long)(PP + 1) * (PP + 2) / 2 <= e) ++PP;
+        while ((long)PP * (PP + 1) / 2 > e) --PP;
+        int QQ = (int)(e - (long)PP * (PP + 1) / 2);
+        int p1 = rp[PP], q1 = rq[PP], p2 = rp[QQ], q2 = rq[QQ];
+        if (PP == QQ) {
+          if (p1 >= N2 || q1 >= N2 || rs[PP] == 0.0) continue;
+          double t = rs[PP] / rc[PP];
+          double apq = P[pk(p1, q1)];
+          P[pk(p1, p1)] -= t * apq;
+          P[pk(q1, q1)] += t * apq;
+          P[pk(p1, q1)] = 0.0;
+          continue;
+        }
+        bool r0v = p1 < N2, r1v = q1 < N2, c0v = p2 < N2, c1v = q2 < N2;
+        double x00 = (r0v && c0v) ? P[pk(p1, p2)] : 0.0;
+        double x01 = (r0v && c1v) ? P[pk(p1, q2)] : 0.0;
+        double x10 = (r1v && c0v) ? P[pk(q1, p2)] : 0.0;
+        double x11 = (r1v && c1v) ? P[pk(q1, q2)] : 0.0;
+        double cq = rc[QQ], sq = rs[QQ];
+        if (sq != 0.0) {
+          double y00 = cq * x00 - sq * x01, y01 = sq * x00 + cq * x01;
+          double y10 = cq * x10 - sq * x11, y11 = sq * x10 + cq * x11;
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        double cp = rc[PP], sp = rs[PP];
+        if (sp != 0.0) {
+          double y00 = cp * x00 - sp * x10, y01 = cp * x01 - sp * x11;
+          double y10 = sp * x00 + cp * x10, y11 = sp * x01 + cp * x11;
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        if (r0v && c0v) P[pk(p1, p2)] = x00;
+        if (r0v && c1v) P[pk(p1, q2)] = x01;
+        if (r1v && c0v) P[pk(q1, p2)] = x10;
+        if (r1v && c1v) P[pk(q1, q2)] = x11;
+      }
+      wg_sync();
     }
-    Am[(long)i * ld + j] = s;
+    ++sweeps;
+    converged = (flag == 0);
+    wg_sync();
   }
-  wg_sync();
-  // 4. B = A^T A.
-  for (long e = tid; e < (long)N2 * N2; e += nt) {
-    int i = (int)(e / N2), j = (int)(e % N2);
-    double s = 0.0;
-    for (int k = 0; k < N2; ++k) s += Am[(long)k * ld + i] * Am[(long)k * ld + j];
-    Bm[(long)i * ld + j] = s;
-  }
-  wg_sync();
-  for (long e = tid; e < (long)N2 * N2; e += nt) {  // exact symmetry
-    long i = e / N2, j = e % N2;
-    if (j > i) Bm[j * ld + i] = Bm[i * ld + j];
-  }
-  wg_sync();
-  // 5. Jacobi.
-  bool conv = jacobi_sym_wg(Bm, Ev, N2, ld, 60, rc, rs, rp, rq, &flag);
-  if (!conv) {
+  if (!converged) {
     if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_JACOBI);
     return;
   }
-  // order of eigenvalues (descending): rank sort into rp[] (index by rank)
+  // eigenvalues and their descending order
+  for (int i = tid; i < N2; i += nt) a.ws_w[i] = P[pk(i, i)];
+  wg_sync();
   for (int i = tid; i < N2; i += nt) {
-    double wi = Bm[(long)i * ld + i];
+    double wi = a.ws_w[i];
     int rank = 0;
     for (int j = 0; j < N2; ++j) {
-      double wj = Bm[(long)j * ld + j];
+      double wj = a.ws_w[j];
       rank += (wj > wi) || (wj == wi && j < i);
     }
-    rq[rank] = i;
+    a.ws_ord[rank] = i;
   }
-  if (tid == 0) npairs = 0;
-  wg_sync();
-  // 6. Symplectic pairing by Gram-Schmidt over eigenvectors in order.
-  double* e_v = vec;
-  double* au = vec + ld;
-  for (int jr = 0; jr < N2; ++jr) {
-    if (npairs >= nL) break;
-    int col = rq[jr];
-    for (int k = tid; k < N2; k += nt) e_v[k] = Ev[(long)k * ld + col];
-    wg_sync();
-    for (int pass = 0; pass < 2; ++pass) {
-      const int nc = npairs;
-      // project out chosen columns u_c = Om[:, c], v_c = Om[:, nL + c]
-      for (int c = 0; c < 2 * nc; ++c) {
-        int cc = c < nc ? c : nL + (c - nc);
-        double part = 0.0;
-        for (int k = tid; k < N2; k += nt) part += Om[(long)k * ld + cc] * e_v[k];
-        double dot = wg_sum(part, red);
-        for (int k = tid; k < N2; k += nt) e_v[k] -= dot * Om[(long)k * ld + cc];
-        wg_sync();
+  if (tid == 0) *a.nsweep = sweeps;
+}
+
+// Eigenvectors: rows [r0, r0 + ROWS) of V = J_1 J_2 ... (product of the logged
+// rotations); V starts as the identity.
+__global__ __launch_bounds__(256) void gsvd_vapply_kernel(GsvdArgs a, int m) {
+  constexpr int ROWS = GBS_GSVD_VROWS;
+  if (*a.err) return;
+  const int n_prev = a.ne[m - 1];
+  const int N2 = 2 * (n_prev + 1);
+  const int r0 = blockIdx.x * ROWS;
+  if (r0 >= N2) return;
+  const int nrow = min(ROWS, N2 - r0);
+  extern __shared__ double vs[];  // ROWS x N2
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < ROWS * N2; e += nt) {
+    int r = e / N2, c = e % N2;
+    vs[e] = (r0 + r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int npad = N2 + (N2 & 1), half = npad / 2;
+  const int sweeps = *a.nsweep;
+  const double2* log = a.rot_log;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int s = 0; s < npad - 1; ++s) {
+      const double2* lg = log + ((long)sw * (npad - 1) + s) * half;
+      for (int e = tid; e < nrow * half; e += nt) {
+        int r = e / half, i = e % half;
+        double2 cs = lg[i];
+        if (cs.y == 0.0) continue;
+        int p, q;
+        rr_pair_s(npad, s, i, p, q);
+        if (p >= N2 || q >= N2) continue;
+        double vp = vs[r * N2 + p], vq = vs[r * N2 + q];
+        vs[r * N2 + p] = cs.x * vp - cs.y * vq;
+        vs[r * N2 + q] = cs.y * vp + cs.x * vq;
       }
+      __syncthreads();
     }
-    double part = 0.0;
-    for (int k = tid; k < N2; k += nt) part += e_v[k] * e_v[k];
-    double nrm = sqrt(wg_sum(part, red));
-    if (nrm < 0.5) continue;
-    for (int k = tid; k < N2; k += nt) e_v[k] /= nrm;
-    wg_sync();
-    for (int i = tid; i < N2; i += nt) {
-      double s = 0.0;
-      for (int k = 0; k < N2; ++k) s += Am[(long)i * ld + k] * e_v[k];
-      au[i] = s;
-    }
-    wg_sync();
-    part = 0.0;
-    for (int k = tid; k < N2; k += nt) part += au[k] * au[k];
-    double dlt = sqrt(wg_sum(part, red));
-    const int c = npairs;
-    for (int k = tid; k < N2; k += nt) {
-      Om[(long)k * ld + c] = e_v[k];
-      Om[(long)k * ld + nL + c] = -au[k] / dlt;
-    }
-    if (tid == 0) {
-      dsel[c] = dlt;
-      npairs = c + 1;
-    }
-    wg_sync();
   }
-  if (npairs < nL) {
+  const long ld = a.ld_ws;
+  for (int e = tid; e < nrow * N2; e += nt) {
+    int r = e / N2, c = e % N2;
+    a.ws_E[(long)(r0 + r) * ld + c] = vs[r * N2 + c];
+  }
+}
+
+// Stage 2.
+__global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+  const int M = a.M;
+  if (*a.err) return;
+  const int n_prev = a.ne[m - 1];
+  const int nL = n_prev + 1, N2 = 2 * nL, nR = M - m;
+  const long ld = a.ld_ws;
+  extern __shared__ double lds[];
+  double* tiles = lds;
+  __shared__ double red[40];
+  __shared__ double dsel[GBS_GSVD_N2_MAX / 2 + 1];
+  __shared__ int cl_start[GBS_GSVD_N2_MAX + 1], pair_src[GBS_GSVD_N2_MAX + 1];
+  __shared__ int ncl, npairs, bad, flag;
+  double* G = a.ws_G;
+  double* Lm = a.ws_L;
+  double* Am = a.ws_A;
+  double* Ev = a.ws_E;
+  double* AE = a.ws_B;   // A E
+  double* Om = a.ws_O;   // pairs [u.., v..] (unscaled, unsorted)
+  double* Op = a.ws_W;   // sorted, scaled pairs
+  double* Sm = a.ws_S;
+  const double* w = a.ws_w;
+  const int* ord = a.ws_ord;
+  const double* g = a.gamma;
+  const int n2g = 2 * M;
+  const double* CR = a.cr_in;
+  const long ldd = a.ld_drr, ldc = a.ld_cr;
+  const int gxa = m - 1, gpa = M + m - 1;
+
+  // A E (all eigenvectors; columns in original order)
+  wg_dgemm(N2, N2, N2, 1.0, Am, ld, false, Ev, ld, false, 0.0, AE, ld, tiles);
+  // eigenvalue clusters in descending order (relative gap 1e-6)
+  if (tid == 0) {
+    int nc = 0;
+    cl_start[nc++] = 0;
+    for (int j = 1; j < N2; ++j) {
+      double hi = w[ord[j - 1]], lo = w[ord[j]];
+      if (hi - lo > 1e-6 * fabs(hi)) cl_start[nc++] = j;
+    }
+    cl_start[nc] = N2;
+    ncl = nc;
+    npairs = 0;
+  }
+  wg_sync();
+  // clusters of exactly two eigenvectors: u = e, v = -A u / |A u| (one wave each)
+  // larger clusters: Gram-Schmidt within the cluster (whole workgroup)
+  // pass 1: count pairs per cluster to assign slots
+  if (tid == 0) {
+    int k = 0;
+    for (int c = 0; c < ncl; ++c) {
+      int sz = cl_start[c + 1] - cl_start[c];
+      pair_src[c] = k;  // first pair slot of this cluster
+      k += sz / 2;
+    }
+    npairs = k;
+    bad = (k != nL);
+  }
+  wg_sync();
+  if (bad) {
     if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_WILLIAMSON);
     return;
   }
-  // Order pairs by D descending (stable); rp[k] = source pair of slot k.
+  for (int c = wv; c < ncl; c += nwv) {
+    const int j0 = cl_start[c], sz = cl_start[c + 1] - j0;
+    if (sz != 2) continue;
+    const int col = ord[j0], slot = pair_src[c];
+    double s = 0.0;
+    for (int k = lane; k < N2; k += 64) s += AE[(long)k * ld + col] * AE[(long)k * ld + col];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double dl = sqrt(s);
+    for (int k = lane; k < N2; k += 64) {
+      Om[(long)k * ld + slot] = Ev[(long)k * ld + col];
+      Om[(long)k * ld + nL + slot] = -AE[(long)k * ld + col] / dl;
+    }
+    if (lane == 0) dsel[slot] = dl;
+  }
+  wg_sync();
+  double* e_v = a.ws_vec;
+  double* au = a.ws_vec + ld;
+  double* dots = lds + 2 * TILE * (TILE + 1);  // up to N2 dot products
+  for (int c = 0; c < ncl; ++c) {
+    const int j0 = cl_start[c], sz = cl_start[c + 1] - j0;
+    if (sz == 2) continue;
+    const int slot0 = pair_src[c], want = sz / 2;
+    int found = 0;
+    for (int jj = 0; jj < sz && found < want; ++jj) {
+      const int col = ord[j0 + jj];
+      for (int k = tid; k < N2; k += nt) e_v[k] = Ev[(long)k * ld + col];
+      wg_sync();
+      for (int pass = 0; pass < 2; ++pass) {
+        const int nch = 2 * found;  // chosen columns of this cluster
+        for (int q = wv; q < nch; q += nwv) {
+          const int cc = q < found ? slot0 + q : nL + slot0 + (q - found);
+          double s = 0.0;
+          for (int k = lane; k < N2; k += 64) s += Om[(long)k * ld + cc] * e_v[k];
+          for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+          if (lane == 0) dots[q] = s;
+        }
+        wg_sync();
+        for (int k = tid; k < N2; k += nt) {
+          double v = e_v[k];
+          for (int q = 0; q < nch; ++q) {
+            const int cc = q < found ? slot0 + q : nL + slot0 + (q - found);
+            v -= dots[q] * Om[(long)k * ld + cc];
+          }
+          e_v[k] = v;
+        }
+        wg_sync();
+      }
+      double part = 0.0;
+      for (int k = tid; k < N2; k += nt) part += e_v[k] * e_v[k];
+      const double nrm = sqrt(wg_sum(part, red));
+      if (nrm < 0.5) continue;
+      for (int k = tid; k < N2; k += nt) e_v[k] /= nrm;
+      wg_sync();
+      for (int i = tid; i < N2; i += nt) {
+        double s = 0.0;
+        for (int k = 0; k < N2; ++k) s += Am[(long)i * ld + k] * e_v[k];
+        au[i] = s;
+      }
+      wg_sync();
+      part = 0.0;
+      for (int k = tid; k < N2; k += nt) part += au[k] * au[k];
+      const double dl = sqrt(wg_sum(part, red));
+      const int slot = slot0 + found;
+      for (int k = tid; k < N2; k += nt) {
+        Om[(long)k * ld + slot] = e_v[k];
+        Om[(long)k * ld + nL + slot] = -au[k] / dl;
+      }
+      if (tid == 0) dsel[slot] = dl;
+      ++found;
+      wg_sync();
+    }
+    if (found < want) {
+      if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_WILLIAMSON);
+      return;
+    }
+  }
+  wg_sync();
+  // pairs by D descending (stable): pair_src[rank] = slot
   for (int i = tid; i < nL; i += nt) {
     int rank = 0;
     for (int j = 0; j < nL; ++j) rank += (dsel[j] > dsel[i]) || (dsel[j] == dsel[i] && j < i);
-    rp[rank] = i;
+    cl_start[rank] = i;
   }
   wg_sync();
-  // 7. S = L O diag(D, D)^(-1/2) with permuted pairs.
+  // O' = sorted pairs scaled by D^(-1/2); S = L O'
   for (long e = tid; e < (long)N2 * N2; e += nt) {
-    int i = (int)(e / N2), j = (int)(e % N2);
-    int jj = j % nL;
-    int src = rp[jj] + (j >= nL ? nL : 0);
-    double s = 0.0;
-    for (int k = 0; k <= i; ++k) s += Lm[(long)i * ld + k] * Om[(long)k * ld + src];
-    Sm[(long)i * ld + j] = s / sqrt(dsel[rp[jj]]);
+    int k = (int)(e / N2), j = (int)(e % N2);
+    int src = cl_start[j % nL];
+    Op[(long)k * ld + j] = Om[(long)k * ld + src + (j >= nL ? nL : 0)] / sqrt(dsel[src]);
   }
   wg_sync();
-  // D values (descending) and active count.
+  wg_dgemm(N2, N2, N2, 1.0, Lm, ld, false, Op, ld, false, 0.0, Sm, ld, tiles);
   if (tid == 0) {
     int ne = 0;
     for (int k = 0; k < nL; ++k) {
-      double d = dsel[rp[k]];
-      a.dsym[(long)m * a.ld_dsym + k] = d;
-      if (d >= a.dstar) ++ne;
+      double dv = dsel[cl_start[k]];
+      a.dsym[(long)m * a.ld_dsym + k] = dv;
+      a.lam[(long)m * a.ld_dsym + k] = dv > 1.0 ? sqrt((dv - 1.0) / (dv + 1.0)) : 0.0;
+      if (dv >= a.dstar) ++ne;
     }
     if (ne > nR) ne = nR;
     a.ne[m] = (m == M) ? 0 : ne;
     flag = (m == M) ? 0 : ne;
-    for (int k = 0; k < nL; ++k) {
-      double d = dsel[rp[k]];
-      a.lam[(long)m * a.ld_dsym + k] = d > 1.0 ? sqrt((d - 1.0) / (d + 1.0)) : 0.0;
-    }
   }
   wg_sync();
   const int ne = flag;
-  // 8. U, V from S (Eq. MUV): U = ((S21 - S12) - i (S11 + S22)) / 2, V = ((-S12 - S21) - i (S11 - S22)) / 2.
+  // U, V from S (Eq. MUV)
   cplx64* U = a.ws_U;
   cplx64* V = a.ws_V;
-  cplx64* Aug = a.ws_aug;  // nL x 2nL
+  cplx64* Aug = a.ws_aug;
   const long ldu = a.ld_u;
   for (long e = tid; e < (long)nL * nL; e += nt) {
     int i = (int)(e / nL), j = (int)(e % nL);
@@ -431,29 +593,38 @@ __global__ __launch_bounds__(1024) void gsvd_cut_kernel(GsvdArgs a, int m) {
     V[i * ldu + j] = cmake<cplx64>(0.5 * (-s12 - s21), -0.5 * (s11 - s22));
   }
   wg_sync();
-  // 9. (U^dag)^-1 by Gauss-Jordan with partial pivoting on [U^dag | I].
+  // (U^dag)^-1 by Gauss-Jordan with partial pivoting on [U^dag | I]
   for (long e = tid; e < (long)nL * 2 * nL; e += nt) {
     int i = (int)(e / (2 * nL)), j = (int)(e % (2 * nL));
     Aug[i * 2 * ldu + j] = j < nL ? cconj(U[(long)j * ldu + i]) : cmake<cplx64>(j - nL == i ? 1.0 : 0.0, 0.0);
   }
   wg_sync();
+  __shared__ int piv_row;
   for (int col = 0; col < nL; ++col) {
-    if (tid == 0) {
+    // pivot search by wave 0
+    if (wv == 0) {
+      double bv = -1.0;
       int best = col;
-      double bv = cabs2(Aug[(long)col * 2 * ldu + col]);
-      for (int r = col + 1; r < nL; ++r) {
+      for (int r = col + lane; r < nL; r += 64) {
         double v = cabs2(Aug[(long)r * 2 * ldu + col]);
         if (v > bv) { bv = v; best = r; }
       }
-      rp[0] = best;
-      bad = !(bv > 1e-280);
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(bv, off, 64);
+        int ob = __shfl_xor(best, off, 64);
+        if (ov > bv || (ov == bv && ob < best)) { bv = ov; best = ob; }
+      }
+      if (lane == 0) {
+        piv_row = best;
+        bad = !(bv > 1e-280);
+      }
     }
     wg_sync();
     if (bad) {
       if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_SINGULAR);
       return;
     }
-    const int pr = rp[0];
+    const int pr = piv_row;
     if (pr != col) {
       for (int j = tid; j < 2 * nL; j += nt) {
         cplx64 t = Aug[(long)col * 2 * ldu + j];
@@ -479,8 +650,7 @@ __global__ __launch_bounds__(1024) void gsvd_cut_kernel(GsvdArgs a, int m) {
       if (r != col) Aug[(long)r * 2 * ldu + col] = cmake<cplx64>(0.0, 0.0);
     wg_sync();
   }
-  // Uih(i, j) = Aug[i][nL + j]
-  // 10. Q^m on (r_{m-1}, a_m, l_m): [[Uih V^dag, Uih[:, :ne]], [.^T, -V^T Uih restricted]].
+  // Q^m on (r_{m-1}, a_m, l_m): [[Uih V^dag, Uih[:, :ne]], [.^T, -V^T Uih]]
   const int nmod = nL + ne;
   cplx64* Q = a.Q + (long)(m - 1) * a.q_stride;
   const long ldq = a.ld_q;
@@ -502,49 +672,41 @@ __global__ __launch_bounds__(1024) void gsvd_cut_kernel(GsvdArgs a, int m) {
   }
   if (m == M) return;
   wg_sync();
-  // 11. Next residual: T = -S^T Omega; T[r][c] = c < nL ? S[c+nL][r] : -S[c-nL][r].
-  // Active rows: x_b,q -> r = q, p_b,q -> r = nL + q (q < ne).
-  // Drr' = T_act Gamma_LL T_act^T (2ne x 2ne); CR' = T_act Gamma_{L, R}.
-  double* Dn = a.drr_out;
-  double* CRn = a.cr_out;
-  double* TG = a.ws_B;  // reuse: T_act Gamma_LL (2ne x N2)
+  // Next residual.  T = -S^T Omega; T_act rows: x_b,q -> q, p_b,q -> nL + q.
+  double* Ta = a.ws_A;   // reuse: T_act (2ne x N2)
+  double* TG = a.ws_B;   // T_act Gamma_LL
+  double* GLR = a.ws_glr;  // Gamma_{L,R} (N2 x 2 nR)
   for (long e = tid; e < (long)2 * ne * N2; e += nt) {
-    int r = (int)(e / N2), j = (int)(e % N2);
+    int r = (int)(e / N2), c = (int)(e % N2);
     int rr = r < ne ? r : nL + (r - ne);
-    double s = 0.0;
-    for (int c = 0; c < N2; ++c) {
-      double t = c < nL ? Sm[(long)(c + nL) * ld + rr] : -Sm[(long)(c - nL) * ld + rr];
-      s += t * G[(long)c * ld + j];
-    }
-    TG[(long)r * ld + j] = s;
+    Ta[(long)r * ld + c] = c < nL ? Sm[(long)(c + nL) * ld + rr] : -Sm[(long)(c - nL) * ld + rr];
+  }
+  for (long e = tid; e < (long)N2 * 2 * nR; e += nt) {
+    int c = (int)(e / (2 * nR)), cc = (int)(e % (2 * nR));
+    int gcol = cc < nR ? m + cc : M + m + (cc - nR);
+    int ci = c % nL;
+    bool cp = c >= nL;
+    GLR[(long)c * a.ld_glr + cc] = ci < n_prev ? CR[(long)(cp ? n_prev + ci : ci) * ldc + gcol]
+                                              : g[(long)(cp ? gpa : gxa) * n2g + gcol];
   }
   wg_sync();
-  for (long e = tid; e < (long)2 * ne * 2 * ne; e += nt) {
-    int r = (int)(e / (2 * ne)), r2 = (int)(e % (2 * ne));
-    int rr2 = r2 < ne ? r2 : nL + (r2 - ne);
-    double s = 0.0;
-    for (int c = 0; c < N2; ++c) {
-      double t = c < nL ? Sm[(long)(c + nL) * ld + rr2] : -Sm[(long)(c - nL) * ld + rr2];
-      s += TG[(long)r * ld + c] * t;
-    }
-    Dn[(long)r * ldd + r2] = s;
-  }
-  // CR' columns: x of a_{m+1..M} at Gamma column j (j >= m), p at M + j.
-  for (long e = tid; e < (long)2 * ne * 2 * nR; e += nt) {
-    int r = (int)(e / (2 * nR)), cc = (int)(e % (2 * nR));
-    int gcol = cc < nR ? m + cc : M + m + (cc - nR);
-    int rr = r < ne ? r : nL + (r - ne);
-    double s = 0.0;
-    for (int c = 0; c < N2; ++c) {
-      double t = c < nL ? Sm[(long)(c + nL) * ld + rr] : -Sm[(long)(c - nL) * ld + rr];
-      int ci = c % nL;
-      bool cp = c >= nL;
-      double gv = ci < n_prev ? CR[(long)(cp ? n_prev + ci : ci) * ldc + gcol]
-                              : g[(long)(cp ? gpa : gxa) * n2g + gcol];
-      s += t * gv;
-    }
-    CRn[(long)r * ldc + gcol] = s;
-  }
+  wg_dgemm(2 * ne, N2, N2, 1.0, Ta, ld, false, G, ld, false, 0.0, TG, ld, tiles);
+  wg_sync();
+  wg_dgemm(2 * ne, 2 * ne, N2, 1.0, TG, ld, false, Ta, ld, true, 0.0, a.drr_out, ldd, tiles);
+  // CR' columns m..M-1 (x of a_{m+1..M}) and M+m..2M-1 (p)
+  wg_dgemm(2 * ne, nR, N2, 1.0, Ta, ld, false, GLR, a.ld_glr, false, 0.0, a.cr_out + m, ldc, tiles);
+  wg_dgemm(2 * ne, nR, N2, 1.0, Ta, ld, false, GLR + nR, a.ld_glr, false, 0.0, a.cr_out + M + m, ldc, tiles);
+}
+
+hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max) {
+  const size_t lds1 = sizeof(double) * ((size_t)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2 + 2 * 32 * 33);
+  hipLaunchKernelGGL(gsvd_stage1_kernel, dim3(1), dim3(1024), lds1, st, a, m);
+  const int nblk = (n2max + GBS_GSVD_VROWS - 1) / GBS_GSVD_VROWS;
+  const size_t lds2 = sizeof(double) * (size_t)GBS_GSVD_VROWS * n2max;
+  hipLaunchKernelGGL(gsvd_vapply_kernel, dim3(nblk), dim3(256), lds2, st, a, m);
+  const size_t lds3 = sizeof(double) * ((size_t)2 * 32 * 33 + GBS_GSVD_N2_MAX + 8);
+  hipLaunchKernelGGL(gsvd_stage2_kernel, dim3(1), dim3(1024), lds3, st, a, m);
+  return hipGetLastError();
 }
 
 hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* scal, double* wsM, int* err) {
@@ -554,10 +716,5 @@ hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* s
   hipLaunchKernelGGL(validate_sym_kernel, dim3(64), dim3(256), 0, st, gamma, n2, scal + 0, scal + 1);
   hipLaunchKernelGGL(purity_kernel, dim3((n2 + 15) / 16, (n2 + 15) / 16), dim3(256), 0, st, gamma, M, scal + 2);
   hipLaunchKernelGGL(chol_xx_kernel, dim3(1), dim3(1024), 0, st, gamma, M, wsM, err);
-  return hipGetLastError();
-}
-
-hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m) {
-  hipLaunchKernelGGL(gsvd_cut_kernel, dim3(1), dim3(1024), 0, st, a, m);
   return hipGetLastError();
 }
