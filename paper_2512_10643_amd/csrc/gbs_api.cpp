@@ -273,9 +273,23 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
     // the Jacobi kernel needs a contiguous square leading dimension per matrix:
     // matrices are stored with leading dimension eld (row stride) already.
     HIP_CHECK_RET(hipMemcpyAsync(edim_dev, edim.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
-    if (M > 1)
-      HIP_CHECK_RET(jacobi_herm(st, E64 + eld * eld, EVt, W64 + eld, edim_dev + 1, eld, eld * eld, M - 1, jerr,
-                                EV64 + eld * eld));
+    if (M > 1) {
+      // logged Jacobi in groups bounded by the rotation-log size
+      const int max_sw = 30;
+      const long per = jacobi_log_entries((int)eld, max_sw);
+      const long cap = std::max<long>(1, (4L << 30) / (per * (long)sizeof(double2)));
+      const int group = (int)std::min<long>(M - 1, cap);
+      double2* logz;
+      int* nsw;
+      HIP_CHECK_RET(dalloc(tmp, &logz, (size_t)group * per));
+      HIP_CHECK_RET(dalloc(tmp, &nsw, group));
+      for (int b0 = 1; b0 < M; b0 += group) {
+        const int nb = std::min(group, M - b0);
+        const long off = (long)b0 * eld * eld;
+        HIP_CHECK_RET(jacobi_herm_logged(st, E64 + off, EVt + off, W64 + (long)b0 * eld, edim_dev + b0, (int)eld, eld,
+                                         eld * eld, nb, jerr, EV64 + off, logz, per, nsw, max_sw));
+      }
+    }
   }
   std::vector<double> wall((size_t)(M + 1) * eld);
   HIP_CHECK_RET(hipMemcpyAsync(wall.data(), W64, wall.size() * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -15,3 +15,11 @@ hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long 
 // A and Vtmp are overwritten.
 hipError_t jacobi_herm(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, long ld, long sA,
                        int batch, int* err, cplx64* Vout);
+
+// Same problem, faster for large batches: rotations are logged (log_stride
+// entries per matrix, see jacobi_log_entries) and the eigenvectors rebuilt by
+// a replay pass spread over many workgroups.  nsw: per-matrix sweep counts.
+long jacobi_log_entries(int n, int max_sweeps);
+hipError_t jacobi_herm_logged(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax, long ld,
+                              long sA, int batch, int* err, cplx64* Vout, double2* logz, long log_stride,
+                              int* nsw, int max_sweeps);

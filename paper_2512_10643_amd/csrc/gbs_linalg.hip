@@ -2,6 +2,8 @@
 // Jacobi eigensolver (FP64), both row-major.
 #include "gbs_linalg.h"
 
+#include <algorithm>
+
 // ---------------------------------------------------------------------------
 // Complex GEMM  C = alpha * op(A) * op(B) + beta * C, strided-batched.
 // op: 0 = none, 1 = transpose, 2 = conjugate transpose.  64x64 output tile per
@@ -255,6 +257,230 @@ __global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__
     w[(long)b * ld + rank] = wi;
     for (int k = 0; k < n; ++k) Vout[(long)b * sA + (long)k * ld + rank] = v[(long)k * ld + i];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Batched Hermitian Jacobi, two passes.  The sweep kernel (one workgroup per
+// matrix) rotates only the upper triangle of A and logs (s, phi) for every
+// rotation (c = sqrt(1 - s^2) since |t| <= 1; the sign of s is kept, as
+// (s, phi) and (-s, phi + pi) give different rotations); the replay kernel
+// rebuilds the eigenvector matrix from the identity, row blocks in parallel
+// across many workgroups; a sort pass orders eigenpairs descending.
+namespace {
+
+__device__ inline cplx64 uget(const cplx64* a, long ld, int r, int c) {
+  return r <= c ? a[(long)r * ld + c] : cconj(a[(long)c * ld + r]);
+}
+__device__ inline void uset(cplx64* a, long ld, int r, int c, cplx64 v) {
+  if (r <= c) a[(long)r * ld + c] = v;
+  else a[(long)c * ld + r] = cconj(v);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(1024) void jacobi_herm_sweep_kernel(cplx64* __restrict__ A, const int* __restrict__ dims,
+                                                                 long ld, long sA, int max_sweeps, double tol,
+                                                                 int* __restrict__ err, double2* __restrict__ logz,
+                                                                 long log_stride, int* __restrict__ nsw,
+                                                                 double* __restrict__ w) {
+  const int b = blockIdx.x;
+  const int n = dims ? dims[b] : (int)ld;
+  cplx64* a = A + (long)b * sA;
+  double2* lg = logz + (long)b * log_stride;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double rc[GBS_CHI_MAX / 2 + 1], rs[GBS_CHI_MAX / 2 + 1];
+  __shared__ cplx64 rz[GBS_CHI_MAX / 2 + 1];  // e^{-i phi}
+  __shared__ int rp[GBS_CHI_MAX / 2 + 1], rq[GBS_CHI_MAX / 2 + 1];
+  __shared__ int any_rot;
+  if (n <= 0) return;
+  for (int i = tid; i < n; i += nt) a[(long)i * ld + i].im = 0.0;
+  __syncthreads();
+  const int npad = n + (n & 1), half = npad / 2;
+  const long nblk = (long)half * (half + 1) / 2;
+  int sweeps = 0;
+  bool converged = (n == 1);
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int s = 0; s < npad - 1; ++s) {
+      for (int i = tid; i < half; i += nt) {
+        int p, q;
+        rr_pair(npad, s, i, p, q);
+        double c = 1.0, sn = 0.0, phi = 0.0;
+        cplx64 z = cmake<cplx64>(1.0, 0.0);
+        if (p < n && q < n) {
+          double app = a[(long)p * ld + p].re, aqq = a[(long)q * ld + q].re;
+          cplx64 bpq = uget(a, ld, p, q);
+          double ab = sqrt(cabs2(bpq));
+          if (ab > tol * sqrt(fabs(app * aqq)) && ab > 1e-300) {
+            double th = (aqq - app) / (2.0 * ab);
+            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            z = cmake<cplx64>(bpq.re / ab, -bpq.im / ab);  // e^{-i phi}
+            phi = atan2(bpq.im, bpq.re);
+            any_rot = 1;
+          }
+        }
+        rp[i] = p;
+        rq[i] = q;
+        rc[i] = c;
+        rs[i] = sn;
+        rz[i] = z;
+        lg[((long)sweep * (npad - 1) + s) * half + i] = make_double2(sn, phi);
+      }
+      __syncthreads();
+      for (long e = tid; e < nblk; e += nt) {
+        int P = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+        while ((long)(P + 1) * (P + 2) / 2 <= e) ++P;
+        while ((long)P * (P + 1) / 2 > e) --P;
+        int Q = (int)(e - (long)P * (P + 1) / 2);
+        int p1 = rp[P], q1 = rq[P], p2 = rp[Q], q2 = rq[Q];
+        if (P == Q) {
+          if (p1 >= n || q1 >= n) continue;
+          if (rs[P] == 0.0) continue;
+          double t = rs[P] / rc[P];
+          cplx64 bpq = uget(a, ld, p1, q1);
+          double ab = sqrt(cabs2(bpq));
+          a[(long)p1 * ld + p1] = cmake<cplx64>(a[(long)p1 * ld + p1].re - t * ab, 0.0);
+          a[(long)q1 * ld + q1] = cmake<cplx64>(a[(long)q1 * ld + q1].re + t * ab, 0.0);
+          uset(a, ld, p1, q1, cmake<cplx64>(0.0, 0.0));
+          continue;
+        }
+        const bool r0v = p1 < n, r1v = q1 < n, c0v = p2 < n, c1v = q2 < n;
+        cplx64 x00 = cmake<cplx64>(0, 0), x01 = x00, x10 = x00, x11 = x00;
+        if (r0v && c0v) x00 = uget(a, ld, p1, p2);
+        if (r0v && c1v) x01 = uget(a, ld, p1, q2);
+        if (r1v && c0v) x10 = uget(a, ld, q1, p2);
+        if (r1v && c1v) x11 = uget(a, ld, q1, q2);
+        // X J_Q with J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+        if (c0v && c1v && rs[Q] != 0.0) {
+          double cq = rc[Q], sq = rs[Q];
+          cplx64 eq = rz[Q];  // e^{-i phi}
+          cplx64 y00 = csub(cscale(x00, cq), cmul(cscale(x01, sq), eq));
+          cplx64 y01 = cadd(cscale(x00, sq), cmul(cscale(x01, cq), eq));
+          cplx64 y10 = csub(cscale(x10, cq), cmul(cscale(x11, sq), eq));
+          cplx64 y11 = cadd(cscale(x10, sq), cmul(cscale(x11, cq), eq));
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        // J_P^H X with J_P^H = [[c, -s e^{i phi}], [s, c e^{i phi}]]
+        if (r0v && r1v && rs[P] != 0.0) {
+          double cp = rc[P], sp = rs[P];
+          cplx64 ep = cconj(rz[P]);  // e^{i phi}
+          cplx64 y00 = csub(cscale(x00, cp), cmul(cscale(x10, sp), ep));
+          cplx64 y01 = csub(cscale(x01, cp), cmul(cscale(x11, sp), ep));
+          cplx64 y10 = cadd(cscale(x00, sp), cmul(cscale(x10, cp), ep));
+          cplx64 y11 = cadd(cscale(x01, sp), cmul(cscale(x11, cp), ep));
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        if (r0v && c0v) uset(a, ld, p1, p2, x00);
+        if (r0v && c1v) uset(a, ld, p1, q2, x01);
+        if (r1v && c0v) uset(a, ld, q1, p2, x10);
+        if (r1v && c1v) uset(a, ld, q1, q2, x11);
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    converged = (any_rot == 0);
+    __syncthreads();
+  }
+  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI);
+  if (tid == 0) nsw[b] = sweeps;
+  for (int i = tid; i < n; i += nt) w[(long)b * ld + i] = a[(long)i * ld + i].re;
+}
+
+// V rows [r0, r0 + rows) of matrix b, from the identity, by replaying the log.
+__global__ __launch_bounds__(256) void jacobi_herm_replay_kernel(const int* __restrict__ dims, long ld, long sA,
+                                                                  int rows, const double2* __restrict__ logz,
+                                                                  long log_stride, const int* __restrict__ nsw,
+                                                                  cplx64* __restrict__ V) {
+  const int b = blockIdx.y;
+  const int n = dims ? dims[b] : (int)ld;
+  const int r0 = blockIdx.x * rows;
+  if (r0 >= n) return;
+  const int nrow = min(rows, n - r0);
+  extern __shared__ cplx64 vs[];  // rows x n
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < rows * n; e += nt) {
+    int r = e / n, c = e % n;
+    vs[e] = cmake<cplx64>((r0 + r == c) ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int npad = n + (n & 1), half = npad / 2;
+  const int sweeps = nsw[b];
+  const double2* lg = logz + (long)b * log_stride;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int s = 0; s < npad - 1; ++s) {
+      const double2* ls = lg + ((long)sw * (npad - 1) + s) * half;
+      for (int e = tid; e < nrow * half; e += nt) {
+        int r = e / half, i = e % half;
+        const double2 sp = ls[i];
+        if (sp.x == 0.0) continue;
+        int p, q;
+        rr_pair(npad, s, i, p, q);
+        if (p >= n || q >= n) continue;
+        const double sn = sp.x, c = sqrt(fmax(0.0, 1.0 - sn * sn));
+        double sph, cph;
+        sincos(sp.y, &sph, &cph);
+        const cplx64 e_m = cmake<cplx64>(cph, -sph);  // e^{-i phi}
+        cplx64 vp = vs[r * n + p], vq = vs[r * n + q];
+        // V' = V J: v_p' = c v_p - s e^{-i phi} v_q ; v_q' = s v_p + c e^{-i phi} v_q
+        vs[r * n + p] = csub(cscale(vp, c), cscale(cmul(vq, e_m), sn));
+        vs[r * n + q] = cadd(cscale(vp, sn), cscale(cmul(vq, e_m), c));
+      }
+      __syncthreads();
+    }
+  }
+  cplx64* v = V + (long)b * sA;
+  for (int e = tid; e < nrow * n; e += nt) {
+    int r = e / n, c = e % n;
+    v[(long)(r0 + r) * ld + c] = vs[r * n + c];
+  }
+}
+
+// Sort eigenpairs of matrix b descending: w (in place) and Vout columns.
+__global__ __launch_bounds__(256) void jacobi_herm_sort_kernel(const int* __restrict__ dims, long ld, long sA,
+                                                               double* __restrict__ w, const cplx64* __restrict__ V,
+                                                               cplx64* __restrict__ Vout) {
+  const int b = blockIdx.x;
+  const int n = dims ? dims[b] : (int)ld;
+  extern __shared__ double ws[];
+  int* rk = (int*)(ws + n);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < n; i += nt) ws[i] = w[(long)b * ld + i];
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    double wi = ws[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (ws[j] > wi) || (ws[j] == wi && j < i);
+    rk[i] = rank;
+    w[(long)b * ld + rank] = wi;
+  }
+  __syncthreads();
+  for (long e = tid; e < (long)n * n; e += nt) {
+    int k = (int)(e / n), i = (int)(e % n);
+    Vout[(long)b * sA + (long)k * ld + rk[i]] = V[(long)b * sA + (long)k * ld + i];
+  }
+}
+
+long jacobi_log_entries(int n, int max_sweeps) {
+  const long npad = n + (n & 1);
+  return (long)max_sweeps * (npad - 1) * (npad / 2);
+}
+
+hipError_t jacobi_herm_logged(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax, long ld,
+                              long sA, int batch, int* err, cplx64* Vout, double2* logz, long log_stride,
+                              int* nsw, int max_sweeps) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_herm_sweep_kernel, dim3(batch), dim3(1024), 0, st, A, dims, ld, sA, max_sweeps, 1e-15,
+                     err, logz, log_stride, nsw, w);
+  int rows = (int)std::max<long>(1, std::min<long>(32, 65536 / ((long)nmax * (long)sizeof(cplx64))));
+  dim3 g2((nmax + rows - 1) / rows, batch);
+  hipLaunchKernelGGL(jacobi_herm_replay_kernel, g2, dim3(256), (size_t)rows * nmax * sizeof(cplx64), st, dims, ld,
+                     sA, rows, logz, log_stride, nsw, Vtmp);
+  hipLaunchKernelGGL(jacobi_herm_sort_kernel, dim3(batch), dim3(256),
+                     (size_t)nmax * (sizeof(double) + sizeof(int)), st, dims, ld, sA, w, Vtmp, Vout);
+  return hipGetLastError();
 }
 
 hipError_t jacobi_herm(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, long ld, long sA,
