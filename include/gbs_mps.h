@@ -92,6 +92,13 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
  *   out : device, shots x M int32.  Asynchronous on `stream`. */
 int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
 
+/* Overlap <psi1|psi2> of two MPS over the same M and d, by an FP64 transfer
+ * contraction on the GPU (E <- sum_p A1[p]^dag E A2[p]).  Both states are
+ * normalised by gbs_mps_build, so |<psi1|psi2>|^2 is the wavefunction
+ * fidelity used to compare builds (Sec. III.A compares MPS by fidelity).
+ *   out : host, 2 FP64 (re, im).  Synchronises `stream`. */
+int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream);
+
 /* Scalar information about a handle (host struct). */
 typedef struct {
   int32_t M, d, chi, prec;

@@ -361,7 +361,33 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   double* nrm;
   HIP_CHECK_RET(dalloc(tmp, &vbuf, 2 * GBS_CHI_MAX));
   HIP_CHECK_RET(dalloc(tmp, &nrm, 1));
-  HIP_CHECK_RET(normalize_mps<CT>(st, (CT**)h->site_ptrs, h->bond_dev, M, d, vbuf, nrm));
+  // Reduced-precision tensors are right-canonical only to their rounding
+  // level, and those deviations add up along the chain; their squared norm is
+  // therefore taken from the full FP64 transfer chain
+  //   L_m = sum_p B^m[p]^H L_{m-1} B^m[p],  L_0 = 1,  norm^2 = L_M.
+  const double* nrm2_dev = nullptr;
+  if (!std::is_same<CT, cplx64>::value) {
+    C *Lb, *B64, *X64;
+    HIP_CHECK_RET(dalloc(tmp, &Lb, (size_t)2 * eld * eld));
+    HIP_CHECK_RET(dalloc(tmp, &B64, (size_t)eld * d * eld + d));
+    HIP_CHECK_RET(dalloc(tmp, &X64, (size_t)eld * d * eld + d));
+    C one = cone<C>();
+    HIP_CHECK_RET(hipMemcpyAsync(Lb, &one, sizeof(C), hipMemcpyHostToDevice, st));
+    int cur = 0;
+    for (int m = 1; m <= M; ++m) {
+      const int a = r[m - 1], b = r[m];
+      C* Lin = Lb + (long)cur * eld * eld;
+      C* Lout = Lb + (long)(1 - cur) * eld * eld;
+      HIP_CHECK_RET(convert<cplx64, CT>(st, B64, out + h->toff[m], (long)a * d * b));
+      // X = L_{m-1} B (a x d b), then L_m = B^H X over the (a, p) rows
+      HIP_CHECK_RET(zgemm<C>(st, a, d * b, a, one, Lin, eld, 0, 0, B64, (long)d * b, 0, 0, czero<C>(), X64,
+                             (long)d * b, 0, 1));
+      HIP_CHECK_RET(zgemm<C>(st, b, b, a * d, one, B64, b, 0, 2, X64, b, 0, 0, czero<C>(), Lout, eld, 0, 1));
+      cur = 1 - cur;
+    }
+    nrm2_dev = (const double*)(Lb + (long)cur * eld * eld);  // real part of the 1 x 1 L_M
+  }
+  HIP_CHECK_RET(normalize_mps<CT>(st, (CT**)h->site_ptrs, h->bond_dev, M, d, vbuf, nrm2_dev, nrm));
   HIP_CHECK_RET(hipMemcpyAsync(&h->norm_raw, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK_RET(hipStreamSynchronize(st));
   return GBS_OK;
@@ -784,6 +810,46 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   }
   // temporaries are released when `tmp` goes out of scope: wait for the work
   HIP_CHECK_RET(hipStreamSynchronize(st));
+  return GBS_OK;
+}
+
+int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream) {
+  if (!h1 || !h2 || !out) return fail(GBS_E_INVAL, "NULL argument");
+  if (h1->M != h2->M || h1->d != h2->d) return fail(GBS_E_INVAL, "overlap needs equal M and d");
+  hipStream_t st = (hipStream_t)stream;
+  const int M = h1->M, d = h1->d;
+  const int rmax = std::max(h1->maxbond, h2->maxbond);
+  DevArena tmp;
+  cplx64 *E[2], *X, *A1, *A2;
+  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(dalloc(tmp, &E[i], (size_t)rmax * rmax));
+  HIP_CHECK_RET(dalloc(tmp, &X, (size_t)rmax * d * rmax));
+  HIP_CHECK_RET(dalloc(tmp, &A1, (size_t)rmax * d * rmax));
+  HIP_CHECK_RET(dalloc(tmp, &A2, (size_t)rmax * d * rmax));
+  auto site64 = [&](gbs_mps_s* h, int m, cplx64* dst) -> hipError_t {
+    long n = (long)h->bond[m - 1] * d * h->bond[m];
+    if (h->esz == sizeof(cplx64))
+      return hipMemcpyAsync(dst, (cplx64*)h->tens + h->toff[m], n * sizeof(cplx64), hipMemcpyDeviceToDevice, st);
+    return convert<cplx64, cplx32>(st, dst, (cplx32*)h->tens + h->toff[m], n);
+  };
+  const cplx64 one = cmake<cplx64>(1.0, 0.0), zero = cmake<cplx64>(0.0, 0.0);
+  HIP_CHECK_RET(hipMemcpyAsync(E[0], &one, sizeof(cplx64), hipMemcpyHostToDevice, st));
+  int cur = 0;
+  for (int m = 1; m <= M; ++m) {
+    const int a1 = h1->bond[m - 1], b1 = h1->bond[m], a2 = h2->bond[m - 1], b2 = h2->bond[m];
+    HIP_CHECK_RET(site64(h1, m, A1));
+    HIP_CHECK_RET(site64(h2, m, A2));
+    // X = E (a1 x a2) * A2 (a2 x d b2)
+    HIP_CHECK_RET(zgemm<cplx64>(st, a1, d * b2, a2, one, E[cur], a2, 0, 0, A2, (long)d * b2, 0, 0, zero, X,
+                                (long)d * b2, 0, 1));
+    // E' = A1^H ((a1 d) x b1)^H * X ((a1 d) x b2)
+    HIP_CHECK_RET(zgemm<cplx64>(st, b1, b2, a1 * d, one, A1, b1, 0, 2, X, b2, 0, 0, zero, E[1 - cur], b2, 0, 1));
+    cur = 1 - cur;
+  }
+  cplx64 r;
+  HIP_CHECK_RET(hipMemcpyAsync(&r, E[cur], sizeof(cplx64), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  out[0] = r.re;
+  out[1] = r.im;
   return GBS_OK;
 }
 

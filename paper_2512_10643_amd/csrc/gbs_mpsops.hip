@@ -86,7 +86,7 @@ template hipError_t gauge_scale<cplx64>(hipStream_t, cplx64*, int, int, int, con
 // workgroup; the MPS is right-canonical so the norm sits in site 1.
 template <typename C>
 __global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* bond, int M, int d, cplx64* vbuf,
-                                                          double* out_norm) {
+                                                          const double* nrm2_in, double* out_norm) {
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double red[64];
   __shared__ double s_re, s_im;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* b
     red[40] = s;
   }
   __syncthreads();
-  const double nrm2 = red[40];
+  const double nrm2 = nrm2_in ? *nrm2_in : red[40];
   // vacuum chain: v = B1[0, :], v <- v B^m[:, 0, :]
   cplx64* v = vbuf;
   cplx64* w = vbuf + GBS_CHI_MAX;
@@ -152,12 +152,13 @@ __global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* b
 
 template <typename C>
 hipError_t normalize_mps(hipStream_t st, C** sites_dev, const int* bond_dev, int M, int d, cplx64* vbuf,
-                         double* out_norm) {
-  hipLaunchKernelGGL((normalize_kernel<C>), dim3(1), dim3(1024), 0, st, sites_dev, bond_dev, M, d, vbuf, out_norm);
+                         const double* nrm2_in, double* out_norm) {
+  hipLaunchKernelGGL((normalize_kernel<C>), dim3(1), dim3(1024), 0, st, sites_dev, bond_dev, M, d, vbuf, nrm2_in,
+                     out_norm);
   return hipGetLastError();
 }
-template hipError_t normalize_mps<cplx32>(hipStream_t, cplx32**, const int*, int, int, cplx64*, double*);
-template hipError_t normalize_mps<cplx64>(hipStream_t, cplx64**, const int*, int, int, cplx64*, double*);
+template hipError_t normalize_mps<cplx32>(hipStream_t, cplx32**, const int*, int, int, cplx64*, const double*, double*);
+template hipError_t normalize_mps<cplx64>(hipStream_t, cplx64**, const int*, int, int, cplx64*, const double*, double*);
 
 // ---------------------------------------------------------------------------
 // Amplitudes: one workgroup per pattern, FP64 accumulation.

@@ -56,6 +56,19 @@ class GaussianMPS:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
+    def overlap(self, other: "GaussianMPS", stream=None) -> complex:
+        """<self|other> by an FP64 transfer contraction on the GPU."""
+        out = (ctypes.c_double * 2)()
+        check(lib().gbs_mps_overlap(self._h, other._h, out, _stream_handle(stream)))
+        return complex(out[0], out[1])
+
+    def fidelity(self, other: "GaussianMPS", stream=None) -> float:
+        """|<a|b>|^2 / (<a|a><b|b>), each term by the FP64 transfer contraction."""
+        ab = self.overlap(other, stream)
+        aa = self.overlap(self, stream).real
+        bb = other.overlap(other, stream).real
+        return abs(ab) ** 2 / (aa * bb)
+
     # -- diagnostics
     def info(self) -> dict:
         inf = InfoT()

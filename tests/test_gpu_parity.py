@@ -234,3 +234,75 @@ def test_sampling_fp32_mfma_c2(torch_cuda):
     s2 = h.sample(777, seed=5).cpu().numpy()
     assert np.array_equal(s2, s[:777])
     h.free()
+
+
+# ---------------------------------------------------------- full size (C3)
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_oracle.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c3_full_size_against_oracle_reference(torch_cuda, precision):
+    """M=144, d=8, chi=256 in the configuration bench.py times: spectra,
+    truncation errors and amplitudes on seeded patterns against values written
+    by tests/golden/make_golden.py (oracle only)."""
+    _say(f"case: c3 full size {precision} (M=144, d=8, chi=256)")
+    g = _golden("c3")
+    w = W.workload("c3")
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision=precision)
+    inf = h.info()
+    assert inf["ne"][1:w.M] == g["n_e"]
+    assert np.max(np.abs(np.array(inf["eps"][1:w.M]) - np.array(g["eps"]))) < 1e-9
+    for m in range(1, w.M):
+        lam = h.export(m, "lambda")
+        assert np.allclose(lam, g["lam"][m - 1], rtol=1e-8, atol=1e-10), m
+    ref = np.array(g["amp_re"]) + 1j * np.array(g["amp_im"])
+    got = gpu_amps(torch_cuda, h, g["patterns"])
+    err = np.max(np.abs(got - ref))
+    rel = np.max(np.abs(got - ref) / np.abs(ref))
+    _say(f"  {len(ref)} amplitudes: max |delta| = {err:.3e}, max relative = {rel:.3e}")
+    if precision == "fp64":
+        assert err <= 1e-10
+    else:
+        assert rel <= 1e-3
+        # fidelity of the FP32 build against the FP64 build (which matches the
+        # oracle's amplitudes to <= 1e-10 above)
+        h64 = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+        f = h.fidelity(h64)
+        _say(f"  1 - F(fp32 build, fp64 build) = {1 - f:.3e}")
+        assert 1 - f <= 1e-6
+        # both states carry unit norm (the FP32 one up to the rounding of site 1)
+        assert abs(h64.overlap(h64) - 1) <= 1e-10
+        assert abs(h.overlap(h) - 1) <= 1e-6
+        h64.free()
+    h.free()
+
+
+def test_c3_sampling_tvd_1e6_shots(torch_cuda):
+    """10^6 FP32-MFMA samples at C3: per-mode marginal TVD against the oracle's
+    exact marginals <= 1e-3 (and within 5x the statistical floor)."""
+    _say("case: c3 sampling, 1e6 shots, fp32")
+    g = _golden("c3")
+    w = W.workload("c3")
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
+    shots = 1_000_000
+    s = h.sample(shots, seed=2024).cpu().numpy()
+    assert np.all(s.sum(1) % 2 == 0)
+    pm = np.array(g["marginals"])
+    worst, worst_ratio = 0.0, 0.0
+    for m in range(w.M):
+        emp = np.bincount(s[:, m], minlength=w.d)[:w.d] / shots
+        tvd = 0.5 * np.abs(emp - pm[m]).sum()
+        floor = 0.5 * np.sum(np.sqrt(2 * pm[m] / (np.pi * shots)))
+        worst = max(worst, tvd)
+        worst_ratio = max(worst_ratio, tvd / floor)
+        assert tvd <= 1e-3 and tvd < 5 * floor + 1e-5, (m, tvd, floor)
+    mean = float(s.sum(1).mean())
+    _say(f"  max per-mode TVD = {worst:.2e} (max TVD/floor {worst_ratio:.2f}); "
+         f"mean photons {mean:.4f} vs exact {g['mean_photons']:.4f}")
+    h.free()
