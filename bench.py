@@ -78,7 +78,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "(the kernels run on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

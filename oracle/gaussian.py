@@ -10,7 +10,7 @@ regularised Q_L).
 Conventions: xxpp ordering, vacuum Gamma = I/2; Williamson
 Gamma_AA = M (D + D) M^T / 2 with D descending, D_q >= 1 (Eq. symDiag).
 
-Readings of the paper taken here (each listed in the design doc):
+Readings of the paper taken here:
 
 * The covariance of the residual state phi_R^m that the next GSVD step needs
   is not written out.  phi_R^m is the original state with each active

@@ -5,7 +5,7 @@ chi_0 = chi_M = 1.  Bond contraction through <I_m| is the identity on the
 shared kept Fock basis (Eq. bond: <0|exp(l r)|n>_l|n>_r = 1), so the MPS
 amplitude is the plain matrix product A^1[n_1] ... A^M[n_M].
 
-Readings (listed in the design doc): the paper leaves the normalisation free; the
+Readings: the paper leaves the normalisation free; the
 MPS is rescaled to unit norm and its global phase chosen so that the vacuum
 amplitude is real and positive.  Fidelity is |<psi1|psi2>|^2/(|psi1|^2|psi2|^2).
 Sampling is sequential conditional sampling, P(p_m | p_<m) from the left
