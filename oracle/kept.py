@@ -9,8 +9,10 @@ states of lowest energy.
 Enumeration: the states are visited best-first from the vacuum with a heap
 (every neighbour s + e_q of a popped state is pushed once), which yields them
 in ascending order of the sort key; the first D popped are kept.  The key is
-(E_beta, occupation tuple), i.e. ties in energy are broken by the occupation
-tuple in ascending lexicographic order (a reading: the paper does not say).
+E_beta, with ties in energy broken by the occupation tuple in descending
+lexicographic order (a reading: the paper does not say how ties are broken;
+with Lambda descending, this order puts n + e_q before n + e_q' for q < q' when
+the two energies are equal).
 E_beta is computed from its definition, summing n_q * e_q over q in mode order.
 
 Parity: pinned in tests by the two-mode squeezed vacuum (kept set
@@ -49,18 +51,18 @@ def kept_basis(lam: np.ndarray, D: int):
     if n == 0:
         return [vac], np.zeros(1)
     e = mode_energies(lam)
-    heap = [(0.0, vac)]
+    heap = [(0.0, tuple(-k for k in vac), vac)]
     seen = {vac}
     out, en = [], []
     while heap and len(out) < D:
-        E, s = heapq.heappop(heap)
+        E, _, s = heapq.heappop(heap)
         out.append(s)
         en.append(E)
         for q in range(n):
             t = s[:q] + (s[q] + 1,) + s[q + 1:]
             if t not in seen:
                 seen.add(t)
-                heapq.heappush(heap, (state_energy(e, t), t))
+                heapq.heappush(heap, (state_energy(e, t), tuple(-k for k in t), t))
     return out, np.asarray(en)
 
 

@@ -199,7 +199,7 @@ def test_kept_basis_product_of_pairs_and_closure():
     lam = np.array([0.6, 0.5, 0.2])
     states, en = K.kept_basis(lam, 25)
     e = -2 * np.log(lam)
-    allst = sorted(itertools.product(range(12), repeat=3), key=lambda s: (float(np.dot(s, e)), s))
+    allst = sorted(itertools.product(range(12), repeat=3), key=lambda s: (float(np.dot(s, e)), tuple(-k for k in s)))
     assert states == [tuple(s) for s in allst[:25]]
     assert np.allclose(en, [np.dot(s, e) for s in states])
     sset = set(states)
@@ -207,9 +207,11 @@ def test_kept_basis_product_of_pairs_and_closure():
         for q in range(3):
             if s[q]:
                 assert s[:q] + (s[q] - 1,) + s[q + 1:] in sset
-    # tie-break: equal Lambdas are ordered by ascending occupation tuple
+    # tie-break: equal energies are ordered by descending occupation tuple
     st, _ = K.kept_basis(np.array([0.5, 0.5]), 3)
-    assert st == [(0, 0), (0, 1), (1, 0)]
+    assert st == [(0, 0), (1, 0), (0, 1)]
+    st, _ = K.kept_basis(np.array([0.5, 0.5, 0.25]), 6)
+    assert st == [(0, 0, 0), (1, 0, 0), (0, 1, 0), (2, 0, 0), (1, 1, 0), (0, 2, 0)]
     # eps from its definition against the geometric closed form for one mode
     s1, e1 = K.kept_basis(np.array([0.4]), 7)
     assert K.truncation_error(np.array([0.4]), e1) == pytest.approx(0.4 ** 14, rel=1e-10)
