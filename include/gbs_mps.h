@@ -53,7 +53,7 @@ typedef enum {
  * tolerance D* > 1 (Sec. II.A; modes with symplectic eigenvalue below it are
  * treated as unentangled); trunc_rel: singular values below
  * trunc_rel * sigma_max are dropped by the truncation sweep (0 selects the
- * default, 1e-12 for FP64 and 1e-6 for FP32 builds); flags: GBS_KEEP_RAW keeps
+ * default, 1e-12 for FP64 and 1e-8 for FP32 builds); flags: GBS_KEEP_RAW keeps
  * the PCO tensors for gbs_mps_export. */
 #define GBS_KEEP_RAW 1u
 typedef struct {
@@ -93,9 +93,9 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
 int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
 
 /* Overlap <psi1|psi2> of two MPS over the same M and d, by an FP64 transfer
- * contraction on the GPU (E <- sum_p A1[p]^dag E A2[p]).  Both states are
- * normalised by gbs_mps_build, so |<psi1|psi2>|^2 is the wavefunction
- * fidelity used to compare builds (Sec. III.A compares MPS by fidelity).
+ * contraction on the GPU (E <- sum_p A1[p]^dag E A2[p]).  The wavefunction
+ * fidelity used to compare builds (Sec. III.A) is
+ * |<psi1|psi2>|^2 / (<psi1|psi1> <psi2|psi2>), three calls of this function.
  *   out : host, 2 FP64 (re, im).  Synchronises `stream`. */
 int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream);
 
