@@ -64,6 +64,39 @@ def cpu_baseline(workload, budget_s=20.0):
                         f"the central {w.chi}x{w.d}x{w.chi} tensors, {nshot} shots, scaled to {w.M} sites"))
 
 
+def serving_mix(n, slots, loads=(0.7, 1.2), probe=64):
+    """Request mix of n requests (build + 10^4 samples each): capacity from a
+    burst of the first `probe` requests, then Poisson arrivals at the given
+    fractions of that capacity; p50/p99 latency and throughput per load."""
+    import torch
+    import workloads
+    from paper_2512_10643_amd import serving as S
+    base = workloads.serving_requests(n)
+    gam = [torch.tensor(r["workload"].gamma, device="cuda") for r in base]
+    torch.cuda.synchronize()
+    out = {"requests": n, "shots_per_request": base[0]["shots"], "slots": slots,
+           "mix": "M~U{16..144}, d in {4,6,8}, chi in {32..256}, brick-wall depth 4..16, r~U[0.1,0.8], fp32"}
+    with S.Server(slots=slots) as srv:
+        w0 = base[0]["workload"]
+        srv.wait(srv.submit(gam[0], w0.d, w0.chi, 1000, 1))   # warm-up
+        k = min(probe, n)
+        t0 = time.perf_counter()
+        _, _, st = S.run_mix(srv, [dict(r, arrival=0.0) for r in base[:k]], gam[:k])
+        cap = k / (time.perf_counter() - t0)
+        out["capacity_rps"] = cap
+        for load in loads:
+            reqs = workloads.serving_requests(n, rate=load * cap)
+            _, res, st = S.run_mix(srv, reqs, gam)
+            out[f"load_{load}"] = {"offered_rps": load * cap, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                   "mean_ms": st["mean_ms"], "throughput_rps": st["throughput_rps"],
+                                   "failed": st["failed"],
+                                   "mean_build_ms": sum(r["build_ms"] for r in res) / len(res),
+                                   "mean_queue_ms": sum(r["queue_ms"] for r in res) / len(res)}
+            print(f"serving load {load}: p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms", file=sys.stderr,
+                  flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +107,9 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=12345)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -150,6 +186,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "sampling sweep (all sites)", "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
     }
+    if not args.no_serving:
+        res["serving"] = serving_mix(args.serving_requests, args.slots)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w)
         t_step = cb["t_build_s"] + args.shots * cb["t_shot_s"]

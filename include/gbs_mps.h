@@ -137,6 +137,70 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
 /* Release every device buffer of the handle. NULL is ignored. */
 void gbs_mps_free(gbs_mps h);
 
+/* Upper estimate of the device bytes that one gbs_mps_build with these
+ * options, followed by one gbs_mps_sample of `shots`, holds at its peak
+ * (buffers sized from M, d and chi alone).  Returns -1 for invalid options.
+ * Used for admission control by the server below. */
+int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots);
+
+/* ---- Serving: many build + sample requests on one GPU ------------------
+ * The consumer the paper names for its MPS is sampling (Sec. I); a server
+ * takes requests "convert this state, then draw `shots` samples" from many
+ * callers.  Requests queue in FIFO order.  `slots` worker threads, each with
+ * its own HIP stream, start the head of the queue as soon as one is free and
+ * the head's footprint (gbs_mps_footprint) fits `budget_bytes` beside the
+ * requests in service, so requests enter and leave service continuously and
+ * the kernels of up to `slots` requests run on the GPU at the same time.
+ * A request's samples are identical whether it runs alone or in a mix: the
+ * build is deterministic and the random numbers are keyed by (seed, shot,
+ * site). */
+typedef struct gbs_server_s* gbs_server;
+
+typedef struct {
+  const double* gamma; /* device, 2M x 2M FP64 as for gbs_mps_build; caller keeps it valid until the request is done */
+  int32_t M;
+  gbs_build_opts opt;
+  int64_t shots;       /* >= 0 */
+  uint64_t seed;
+  int32_t* out;        /* device, shots x M int32; written when the request is done */
+} gbs_request;
+
+typedef struct {
+  int32_t status;      /* GBS_OK or the build / sample error code */
+  int32_t max_bond;
+  double eps_max;
+  double queue_ms;     /* submit -> start of service */
+  double build_ms;     /* gbs_mps_build */
+  double sample_ms;    /* sampling, up to samples ready on the device */
+  double latency_ms;   /* submit -> samples ready */
+} gbs_result;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed requests, nearest-rank percentiles */
+  double wall_s;                          /* first submit -> last completion */
+  double throughput_rps;                  /* completed / wall_s */
+  int64_t peak_bytes;                     /* largest admitted footprint sum */
+} gbs_server_stats_t;
+
+/* Create a server on the current device.  slots in [1, 64]; budget_bytes:
+ * device memory the admitted requests may hold together (a request larger
+ * than the budget is rejected at submit with GBS_E_NOMEM); max_queue: queued
+ * requests beyond which submit returns GBS_E_BUSY.  out: host. */
+int gbs_server_create(int32_t slots, int64_t budget_bytes, int32_t max_queue, gbs_server* out);
+/* Queue a request (host struct, copied).  *id (host) receives its id. */
+int gbs_server_submit(gbs_server s, const gbs_request* req, int64_t* id);
+/* *done (host) = 1 once the request's samples are ready. */
+int gbs_server_poll(gbs_server s, int64_t id, int32_t* done);
+/* Block until the request is done, fill *res (host, may be NULL), forget the
+ * id, and return the request's status. */
+int gbs_server_wait(gbs_server s, int64_t id, gbs_result* res);
+/* Latency and throughput over the requests completed since the last reset. */
+int gbs_server_stats(gbs_server s, gbs_server_stats_t* out);
+int gbs_server_reset_stats(gbs_server s);
+/* Finish every queued request, then stop the workers and free the server. */
+void gbs_server_destroy(gbs_server s);
+
 /* Thread-local message for the last failing call on this thread. */
 const char* gbs_last_error(void);
 

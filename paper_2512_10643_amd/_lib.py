@@ -23,7 +23,9 @@ EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5}
 
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
 EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_overlap", "gbs_mps_info",
-                    "gbs_mps_export", "gbs_mps_free", "gbs_last_error")
+                    "gbs_mps_export", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
+                    "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
+                    "gbs_server_stats", "gbs_server_reset_stats", "gbs_server_destroy")
 
 
 class GbsError(RuntimeError):
@@ -44,6 +46,24 @@ class InfoT(ctypes.Structure):
                 ("norm_raw", ctypes.c_double), ("bytes", ctypes.c_int64), ("pco_updates", ctypes.c_int64),
                 ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
                 ("t_svd_ms", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_void_p), ("M", ctypes.c_int32), ("opt", BuildOpts), ("shots", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("max_bond", ctypes.c_int32), ("eps_max", ctypes.c_double),
+                ("queue_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("throughput_rps", ctypes.c_double),
+                ("peak_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -74,6 +94,22 @@ def lib():
         L.gbs_mps_free.restype = None
         L.gbs_last_error.argtypes = []
         L.gbs_last_error.restype = ctypes.c_char_p
+        L.gbs_mps_footprint.argtypes = [i32, ctypes.POINTER(BuildOpts), i64]
+        L.gbs_mps_footprint.restype = ctypes.c_int64
+        L.gbs_server_create.argtypes = [i32, i64, i32, ctypes.POINTER(vp)]
+        L.gbs_server_create.restype = ctypes.c_int
+        L.gbs_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]
+        L.gbs_server_submit.restype = ctypes.c_int
+        L.gbs_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32)]
+        L.gbs_server_poll.restype = ctypes.c_int
+        L.gbs_server_wait.argtypes = [vp, i64, ctypes.POINTER(Result)]
+        L.gbs_server_wait.restype = ctypes.c_int
+        L.gbs_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.gbs_server_stats.restype = ctypes.c_int
+        L.gbs_server_reset_stats.argtypes = [vp]
+        L.gbs_server_reset_stats.restype = ctypes.c_int
+        L.gbs_server_destroy.argtypes = [vp]
+        L.gbs_server_destroy.restype = None
         _lib = L
     return _lib
 

@@ -7,12 +7,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/gbs_mps.h"
 #include "gbs_common.h"
 #include "gbs_gsvd.h"
+#include "gbs_internal.h"
 #include "gbs_kept.h"
 #include "gbs_linalg.h"
 #include "gbs_mpsops.h"
@@ -38,13 +40,47 @@ double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Owning device allocation list.
+// Stream-ordered allocations come from the device's default memory pool,
+// which keeps up to this many freed bytes cached instead of returning them to
+// the driver (repeated builds then allocate without a driver call).
+constexpr uint64_t kPoolKeepBytes = 32ull << 30;
+
+hipError_t ensure_pool(hipStream_t st) {
+  static std::mutex mu;
+  static std::vector<int> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  (void)st;
+  std::lock_guard<std::mutex> lk(mu);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return hipSuccess;
+  hipMemPool_t pool;
+  e = hipDeviceGetDefaultMemPool(&pool, dev);
+  if (e != hipSuccess) return e;
+  uint64_t keep = kPoolKeepBytes;
+  e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) return e;
+  done.push_back(dev);
+  return hipSuccess;
+}
+
+// Owning device allocation list.  With a stream, allocations are stream
+// ordered (hipMallocAsync / hipFreeAsync on that stream), so releasing a
+// temporary arena never waits for other streams; without one they are plain
+// hipMalloc / hipFree (buffers owned by a handle).
 struct DevArena {
   std::vector<void*> ptrs;
   int64_t bytes = 0;
+  hipStream_t st = nullptr;
+  bool ordered = false;
+  DevArena() = default;
+  explicit DevArena(hipStream_t s) : st(s), ordered(true) {}
+  DevArena(const DevArena&) = delete;
+  DevArena& operator=(const DevArena&) = delete;
   hipError_t alloc(void** p, size_t n) {
     if (n == 0) n = 16;
-    hipError_t e = hipMalloc(p, n);
+    n = (n + 255) & ~(size_t)255;
+    hipError_t e = ordered ? hipMallocAsync(p, n, st) : hipMalloc(p, n);
     if (e == hipSuccess) {
       ptrs.push_back(*p);
       bytes += (int64_t)n;
@@ -52,7 +88,7 @@ struct DevArena {
     return e;
   }
   void release_all() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)(ordered ? hipFreeAsync(p, st) : hipFree(p));
     ptrs.clear();
     bytes = 0;
   }
@@ -395,7 +431,8 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
 
 int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t st, gbs_mps_s* h) {
   const int d = opt->d, chi = opt->chi;
-  DevArena tmp;
+  HIP_CHECK_RET(ensure_pool(st));
+  DevArena tmp(st);
   int* err;
   HIP_CHECK_RET(dalloc(h->keep, &err, 4));
   h->err = err;
@@ -695,9 +732,10 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
 
 }  // namespace
 
-extern "C" {
+__attribute__((visibility("hidden"))) int gbs_fail(int code, const std::string& msg) { return fail(code, msg); }
 
-int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out) {
+__attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t stream, bool ordered_keep,
+                     gbs_mps* out) {
   if (!out) return fail(GBS_E_INVAL, "out_handle is NULL");
   *out = nullptr;
   if (!gamma || !opt) return fail(GBS_E_INVAL, "NULL gamma or options");
@@ -717,20 +755,31 @@ int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, voi
   h->dstar = opt->dstar;
   h->flags = opt->flags;
   h->trunc_rel = opt->trunc_rel;
+  if (ordered_keep) {
+    h->keep.st = stream;
+    h->keep.ordered = true;
+  }
   int rc;
   try {
-    rc = build_impl(gamma, M, opt, (hipStream_t)stream, h);
+    rc = build_impl(gamma, M, opt, stream, h);
   } catch (...) {
     rc = fail(GBS_E_INTERNAL, "unexpected host exception");
   }
   if (rc != GBS_OK) {
-    (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipStreamSynchronize(stream);
     delete h;
     return rc;
   }
   *out = h;
   return GBS_OK;
 }
+
+extern "C" {
+
+int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out) {
+  return gbs_build_handle(gamma, M, opt, (hipStream_t)stream, false, out);
+}
+
 
 int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out, void* stream) {
   if (!h) return fail(GBS_E_INVAL, "NULL handle");
@@ -739,7 +788,7 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
   if (!patterns || !out) return fail(GBS_E_INVAL, "NULL pointer");
   hipStream_t st = (hipStream_t)stream;
   int* bad;
-  DevArena tmp;
+  DevArena tmp(st);
   HIP_CHECK_RET(dalloc(tmp, &bad, 1));
   HIP_CHECK_RET(hipMemsetAsync(bad, 0, sizeof(int), st));
   if (h->esz == sizeof(cplx64))
@@ -762,10 +811,11 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   if (!out) return fail(GBS_E_INVAL, "NULL output");
   if (h->maxbond > 1024) return fail(GBS_E_INVAL, "sampler supports bond dimension <= 1024");
   hipStream_t st = (hipStream_t)stream;
+  HIP_CHECK_RET(ensure_pool(st));
   const int M = h->M, d = h->d;
   const long ldl = h->maxbond;
   const int64_t chunk = std::min<int64_t>(shots, (int64_t)1 << 18);
-  DevArena tmp;
+  DevArena tmp(st);
   void* lbuf[2];
   const size_t rowbytes = std::max((size_t)ldl * h->esz, (size_t)2 * sampler_pad(h->maxbond) * sizeof(float));
   for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * rowbytes));
@@ -784,8 +834,7 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
         cur = 1 - cur;
       }
     }
-    HIP_CHECK_RET(hipStreamSynchronize(st));
-    return GBS_OK;
+    return GBS_OK;  // the temporaries are freed in stream order
   }
   for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
     const int64_t n = std::min(chunk, shots - s0);
@@ -808,9 +857,7 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
       }
     }
   }
-  // temporaries are released when `tmp` goes out of scope: wait for the work
-  HIP_CHECK_RET(hipStreamSynchronize(st));
-  return GBS_OK;
+  return GBS_OK;  // the temporaries are freed in stream order
 }
 
 int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream) {
@@ -819,7 +866,7 @@ int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int M = h1->M, d = h1->d;
   const int rmax = std::max(h1->maxbond, h2->maxbond);
-  DevArena tmp;
+  DevArena tmp(st);
   cplx64 *E[2], *X, *A1, *A2;
   for (int i = 0; i < 2; ++i) HIP_CHECK_RET(dalloc(tmp, &E[i], (size_t)rmax * rmax));
   HIP_CHECK_RET(dalloc(tmp, &X, (size_t)rmax * d * rmax));
@@ -944,6 +991,35 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
 void gbs_mps_free(gbs_mps h) {
   if (!h) return;
   delete h;
+}
+
+// Upper estimate of the device bytes one build (plus one sampling call of
+// `shots`) holds at its peak: every buffer is sized from M, d and chi alone.
+int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
+  if (!opt || M < 1 || opt->d < 1 || opt->chi < 1) return -1;
+  const int64_t d = opt->d, chi = std::min<int64_t>(opt->chi, GBS_CHI_MAX), m = M;
+  const int64_t esz = opt->prec == GBS_FP64 ? 16 : 8;
+  const int64_t n2 = std::min<int64_t>(m + 2, GBS_GSVD_N2_MAX);
+  int64_t b = 0;
+  // Gaussian SVD chain: residual blocks, stage workspaces, rotation log, Q^m
+  b += 2 * (n2 * n2 + n2 * 2 * m) * 8 + 10 * n2 * n2 * 8 + (int64_t)GBS_GSVD_MAX_SWEEPS * n2 * (n2 / 2 + 1) * 16;
+  b += m * (n2 / 2 + 2) * (n2 / 2 + 2) * 16 * 2;
+  // kept bases and maps
+  b += (m + 1) * chi * (40 + 16 * GBS_K_MAX + 6 * (n2 / 2 + 1));
+  // PCO tensors (FP64) and the truncation sweep
+  const int64_t site = d * chi * chi;
+  const int64_t chld = chi * d + 1;
+  b += m * site * 16;
+  b += 5 * chld * chld * 16 + chld * chld * d * 16;
+  b += 3 * (m + 1) * chi * chi * 16 + 3 * site * 16;
+  b += std::min<int64_t>(4LL << 30, (m - 1 > 0 ? m - 1 : 1) * jacobi_log_entries((int)chi, 30) * 16);
+  b += m * site * esz + (m + 1) * chi * chi * esz + 2 * site * esz;
+  if (opt->prec != GBS_FP64 && chi <= 256) b += m * 16 * site;  // sampler operand
+  // sampling buffers
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 0), 1 << 18);
+  const int64_t pad = (chi + 15) / 16 * 16;
+  b += 2 * chunk * std::max<int64_t>(chi * esz, 8 * pad);
+  return b + b / 8 + (64LL << 20);
 }
 
 const char* gbs_last_error(void) { return g_last_error.c_str(); }

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "gbs_mps.h")
 
 def declared_functions():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(gbs_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(gbs_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -49,3 +49,25 @@ def test_invalid_arguments_rejected_on_host():
     assert L.gbs_mps_amplitude(None, None, 1, None, None) == _lib.GBS_E_INVAL
     assert L.gbs_mps_sample(None, 1, 0, None, None) == _lib.GBS_E_INVAL
     L.gbs_mps_free(None)
+
+
+def test_server_and_footprint_host_checks():
+    """Server creation arguments and the footprint estimate are validated on
+    the host; the estimate grows with chi and with the shot count."""
+    from paper_2512_10643_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.gbs_server_create(0, 1 << 30, 16, ctypes.byref(h)) == _lib.GBS_E_INVAL
+    assert L.gbs_server_create(4, 0, 16, ctypes.byref(h)) == _lib.GBS_E_INVAL
+    assert L.gbs_server_create(4, 1 << 30, 0, ctypes.byref(h)) == _lib.GBS_E_INVAL
+    assert not h.value
+    o = _lib.BuildOpts(d=8, chi=256, dstar=1.0 + 1e-10, prec=1, flags=0, trunc_rel=0.0)
+    f1 = L.gbs_mps_footprint(144, ctypes.byref(o), 0)
+    f2 = L.gbs_mps_footprint(144, ctypes.byref(o), 10_000)
+    o.chi = 64
+    f3 = L.gbs_mps_footprint(144, ctypes.byref(o), 0)
+    assert 0 < f3 < f1 < f2
+    # the C3 build holds its PCO tensors (144 x 8 x 256^2 complex FP64) at least
+    assert f1 > 144 * 8 * 256 * 256 * 16
+    o.d = 0
+    assert L.gbs_mps_footprint(144, ctypes.byref(o), 0) == -1

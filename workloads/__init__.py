@@ -133,9 +133,12 @@ def custom(M: int, d: int, chi: int, r_range, circuit, seed: int, name="custom")
 def serving_requests(n: int = 512, seed: int = 3, rate: float | None = None):
     """Request mix: M ~ U{16..144}, d in {4,6,8}, chi in {32,64,128,256},
     r ~ U[0.1,0.8], brick-wall depth ~ U{4..16}; Poisson arrival offsets
-    (exponential gaps, mean 1/rate seconds) when a rate is given.
+    (exponential gaps, mean 1/rate seconds) when a rate is given.  The gaps
+    come from their own stream of random numbers, drawn as unit exponentials
+    and scaled by 1/rate, so the request contents do not depend on the rate.
     Request i's state uses seed 1000 + i."""
     rng = np.random.default_rng(seed)
+    gaps = np.random.default_rng([seed, 1]).exponential(1.0, size=n)
     reqs = []
     t = 0.0
     for i in range(n):
@@ -144,7 +147,7 @@ def serving_requests(n: int = 512, seed: int = 3, rate: float | None = None):
         chi = int(rng.choice([32, 64, 128, 256]))
         depth = int(rng.integers(4, 17))
         if rate:
-            t += float(rng.exponential(1.0 / rate))
+            t += float(gaps[i]) / rate
         w = _make(f"req{i}", M, d, chi, (0.1, 0.8), ("brick", depth), 1000 + i)
         reqs.append(dict(id=i, workload=w, arrival=t, shots=10_000, seed=1000 + i))
     return reqs
