@@ -108,7 +108,8 @@ const char* deverr_msg(int code) {
     case GBS_DEVERR_SINGULAR: return "Bogoliubov matrix U is singular";
     case GBS_DEVERR_HASH: return "kept-basis index lookup failed";
     case GBS_DEVERR_KMAX: return "size limit exceeded (too many occupied modes or entangled pairs)";
-    case GBS_DEVERR_JACOBI: return "Jacobi eigensolver did not converge";
+    case GBS_DEVERR_JACOBI: return "Jacobi eigensolver of a Williamson form did not converge";
+    case GBS_DEVERR_JACOBI_BOND: return "Hermitian Jacobi eigensolver of a bond environment did not converge";
     default: return "unknown device error";
   }
 }

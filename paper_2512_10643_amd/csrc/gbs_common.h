@@ -15,7 +15,8 @@ enum {
   GBS_DEVERR_SINGULAR = 4,     // U not invertible (cannot happen for valid input)
   GBS_DEVERR_HASH = 5,         // kept-set index lookup failed
   GBS_DEVERR_KMAX = 6,         // too many occupied modes in a kept state
-  GBS_DEVERR_JACOBI = 7,       // Jacobi did not converge
+  GBS_DEVERR_JACOBI = 7,       // Jacobi of a Williamson form did not converge
+  GBS_DEVERR_JACOBI_BOND = 8,  // Hermitian Jacobi of a bond environment did not converge
 };
 
 struct cplx64 { double re, im; };

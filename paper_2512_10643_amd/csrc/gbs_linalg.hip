@@ -117,6 +117,26 @@ __device__ inline void rr_pair(int npad, int s, int i, int& p, int& q) {
   }
 }
 
+// Largest |a_ii| of an n x n matrix, reduced over the workgroup (<= 1024
+// threads).  Sets the absolute floor below which the Hermitian Jacobi kernels
+// leave an off-diagonal entry alone: dropping entries of size <= 1e-18 max|a_ii|
+// moves no eigenvalue by more than n * 1e-18 max|a_ii|, far below the FP64
+// error of the matrices they receive, and rank-deficient matrices (whose
+// tiny diagonal entries make the relative test 1e-15 sqrt(|a_pp a_qq|)
+// unreachable at the rounding floor) then converge.
+__device__ double diag_absmax(const cplx64* a, long ld, int n, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double m = 0.0;
+  for (int i = tid; i < n; i += nt) m = fmax(m, fabs(a[(long)i * ld + i].re));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < (nt + 63) / 64; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
 __global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__ A, cplx64* __restrict__ V,
                                                             double* __restrict__ w, const int* __restrict__ dims,
                                                             long ld, long sA, int max_sweeps, double tol,
@@ -138,6 +158,8 @@ __global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__
   // make the diagonal exactly real
   for (int i = tid; i < n; i += nt) a[(long)i * ld + i].im = 0.0;
   __syncthreads();
+  __shared__ double red[16];
+  const double floor_abs = fmax(1e-18 * diag_absmax(a, ld, n, red), 1e-300);
   const int npad = n + (n & 1);
   const int half = npad / 2;
   bool converged = (n == 1);
@@ -154,7 +176,7 @@ __global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__
           double app = a[(long)p * ld + p].re, aqq = a[(long)q * ld + q].re;
           cplx64 bpq = a[(long)p * ld + q];
           double ab = sqrt(cabs2(bpq));
-          if (ab > tol * sqrt(fabs(app * aqq)) && ab > 1e-300) {
+          if (ab > tol * sqrt(fabs(app * aqq)) && ab > floor_abs) {
             ph = cmake<cplx64>(bpq.re / ab, bpq.im / ab);
             double th = (aqq - app) / (2.0 * ab);
             double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
@@ -245,7 +267,7 @@ __global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__
     converged = (any_rot == 0);
     __syncthreads();
   }
-  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI);
+  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI_BOND);
   // sort descending: rank of each eigenvalue
   for (int i = tid; i < n; i += nt) {
     double wi = a[(long)i * ld + i].re;
@@ -295,6 +317,8 @@ __global__ __launch_bounds__(1024) void jacobi_herm_sweep_kernel(cplx64* __restr
   if (n <= 0) return;
   for (int i = tid; i < n; i += nt) a[(long)i * ld + i].im = 0.0;
   __syncthreads();
+  __shared__ double red[16];
+  const double floor_abs = fmax(1e-18 * diag_absmax(a, ld, n, red), 1e-300);
   const int npad = n + (n & 1), half = npad / 2;
   const long nblk = (long)half * (half + 1) / 2;
   int sweeps = 0;
@@ -312,7 +336,7 @@ __global__ __launch_bounds__(1024) void jacobi_herm_sweep_kernel(cplx64* __restr
           double app = a[(long)p * ld + p].re, aqq = a[(long)q * ld + q].re;
           cplx64 bpq = uget(a, ld, p, q);
           double ab = sqrt(cabs2(bpq));
-          if (ab > tol * sqrt(fabs(app * aqq)) && ab > 1e-300) {
+          if (ab > tol * sqrt(fabs(app * aqq)) && ab > floor_abs) {
             double th = (aqq - app) / (2.0 * ab);
             double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -384,7 +408,7 @@ __global__ __launch_bounds__(1024) void jacobi_herm_sweep_kernel(cplx64* __restr
     converged = (any_rot == 0);
     __syncthreads();
   }
-  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI);
+  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI_BOND);
   if (tid == 0) nsw[b] = sweeps;
   for (int i = tid; i < n; i += nt) w[(long)b * ld + i] = a[(long)i * ld + i].re;
 }

@@ -58,12 +58,19 @@ class Server:
         check(lib().gbs_server_poll(self._h, t.id, ctypes.byref(done)))
         return bool(done.value)
 
-    def wait(self, t: Ticket) -> dict:
-        """Block until the request is done; returns its timings (ms).  The
-        samples are in t.out."""
+    def wait(self, t: Ticket, raise_on_error: bool = True) -> dict:
+        """Block until the request is done; returns its timings (ms) and
+        status.  The samples are in t.out.  A failed request raises GbsError
+        unless raise_on_error is False (then status < 0 and "error" is set)."""
         r = Result()
-        check(lib().gbs_server_wait(self._h, t.id, ctypes.byref(r)))
-        return {f: getattr(r, f) for f, _ in Result._fields_}
+        rc = lib().gbs_server_wait(self._h, t.id, ctypes.byref(r))
+        if rc != 0 and raise_on_error:
+            check(rc)
+        out = {f: getattr(r, f) for f, _ in Result._fields_}
+        if rc != 0:
+            msg = lib().gbs_last_error()
+            out["error"] = msg.decode() if msg else ""
+        return out
 
     def stats(self) -> dict:
         s = ServerStats()
@@ -111,5 +118,5 @@ def run_mix(server: Server, requests, gammas, precision: str = "fp32", time_scal
             time.sleep(delay)
         w = r["workload"]
         tickets.append(server.submit(g, w.d, w.chi, r["shots"], r["seed"], precision=precision))
-    results = [server.wait(t) for t in tickets]
+    results = [server.wait(t, raise_on_error=False) for t in tickets]
     return tickets, results, server.stats()

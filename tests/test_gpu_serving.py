@@ -104,3 +104,22 @@ def test_admission_limits(torch_cuda):
     assert ra["status"] == 0 and rb["status"] == 0
     assert st["peak_bytes"] <= int(fp * 1.5)
     assert not torch.equal(a.out, b.out)  # different seeds
+
+
+def test_full_mix_builds_every_request(torch_cuda):
+    """All 512 requests of the serving mix (M 16..144, d 4..8, chi 32..256,
+    brick-wall depth 4..16) build and sample without error.  Some of their
+    bond environments are rank deficient, which the Hermitian Jacobi solver
+    must converge on."""
+    torch = torch_cuda
+    from paper_2512_10643_amd import serving as S
+    reqs = W.serving_requests(512)
+    _say("case: serving mix, 512 requests at once, fp32")
+    gam = [torch.tensor(r["workload"].gamma, device="cuda") for r in reqs]
+    with S.Server(slots=8) as srv:
+        tickets, res, st = S.run_mix(srv, [dict(r, arrival=0.0) for r in reqs], gam)
+    bad = [(i, r.get("error")) for i, r in enumerate(res) if r["status"] != 0]
+    assert not bad, bad[:5]
+    assert st["completed"] == 512
+    for t in tickets[:64]:
+        assert int((t.out.sum(1) % 2).abs().sum()) == 0
