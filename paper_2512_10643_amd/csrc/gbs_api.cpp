@@ -821,17 +821,20 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   const size_t rowbytes = std::max((size_t)ldl * h->esz, (size_t)2 * sampler_pad(h->maxbond) * sizeof(float));
   for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * rowbytes));
   if (h->packed) {
-    // MFMA path: left vectors as interleaved floats, rows padded to 16 complex
+    // MFMA path: left vectors as interleaved floats, rows padded to 16 complex,
+    // plus one inverse row norm per shot
     const long ldl2 = 2L * sampler_pad(h->maxbond);
     float* fb[2] = {(float*)lbuf[0], (float*)lbuf[1]};
+    float* sb[2];
+    for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc((void**)&sb[i], (size_t)chunk * sizeof(float)));
     for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
       const int64_t n = std::min(chunk, shots - s0);
-      HIP_CHECK_RET(hipMemsetAsync(fb[0], 0, (size_t)n * ldl2 * sizeof(float), st));
-      HIP_CHECK_RET(launch_fill_first<cplx32>(st, (cplx32*)fb[0], ldl2 / 2, n));
+      HIP_CHECK_RET(launch_sampler_init(st, fb[0], ldl2, h->bond[0], n));
       int cur = 0;
       for (int m = 1; m <= M; ++m) {
         HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], h->bond[m - 1], d, h->bond[m], fb[cur],
-                                         fb[1 - cur], ldl2, s0, n, m, seed, out, M));
+                                         m == 1 ? nullptr : sb[cur], fb[1 - cur], sb[1 - cur], ldl2, s0, n, m, seed,
+                                         out, M));
         cur = 1 - cur;
       }
     }
