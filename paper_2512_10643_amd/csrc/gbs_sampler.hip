@@ -98,31 +98,34 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     a[0] = a0.x * ascale; a[1] = a0.y * ascale; a[2] = a0.z * ascale; a[3] = a0.w * ascale;
     a[4] = a1.x * ascale; a[5] = a1.y * ascale; a[6] = a1.z * ascale; a[7] = a1.w * ascale;
   };
+  // global -> LDS by the DMA path: lane l carries 16 bytes to block base + 16 l.
+  // Chunks run as one sequence over (p, c), so the first chunk of p + 1 is in
+  // flight while p's draw is made.
+  auto issue = [&](int g, int buf) {
+    const float* src = P + (long)g * CHUNK;
+#pragma unroll
+    for (int q = 0; q < BPW; ++q) {
+      const int blk = w + kWaves * q;  // uniform per wave
+      if (BLOCKS % kWaves != 0 && blk >= BLOCKS) break;
+      __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
+                                       (void __attribute__((address_space(3)))*)(&Bs[buf][blk * 256]), 16, 0, 0);
+    }
+  };
+  const int total = d * nchunk;
+  float a[8], an[8];
+  issue(0, 0);
+  load_a(0, a);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
   for (int p = 0; p < d; ++p) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float* pbase = P + (long)p * nchunk * CHUNK;
-    // global -> LDS by the DMA path: lane l carries 16 bytes to block base + 16 l
-    auto issue = [&](int c, int buf) {
-      const float* src = pbase + (long)c * CHUNK;
-#pragma unroll
-      for (int q = 0; q < BPW; ++q) {
-        const int blk = w + kWaves * q;  // uniform per wave
-        if (BLOCKS % kWaves != 0 && blk >= BLOCKS) break;
-        __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
-                                         (void __attribute__((address_space(3)))*)(&Bs[buf][blk * 256]), 16, 0, 0);
-      }
-    };
-    float a[8], an[8];
-    issue(0, 0);
-    load_a(0, a);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
     for (int c = 0; c < nchunk; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < nchunk) {
-        issue(c + 1, buf ^ 1);
-        load_a(c + 1, an);
+      const int g = p * nchunk + c;
+      const int buf = g & 1;
+      if (g + 1 < total) {
+        issue(g + 1, buf ^ 1);
+        load_a(c + 1 < nchunk ? c + 1 : 0, an);
       }
       const float4* bsrc = (const float4*)Bs[buf];
 #pragma unroll
@@ -141,10 +144,10 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
           acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b1.w, acc[t0 + 1], 0, 0, 0);
         }
       }
-      // chunk c+1 (B' in LDS, A in registers) was issued a whole chunk ago
+      // the next chunk (B' in LDS, A in registers) was issued a whole chunk ago
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (c + 1 < nchunk) {
+      if (g + 1 < total) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = an[i];
       }
