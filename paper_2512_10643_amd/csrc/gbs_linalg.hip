@@ -5,84 +5,185 @@
 #include <algorithm>
 
 // ---------------------------------------------------------------------------
-// Complex GEMM  C = alpha * op(A) * op(B) + beta * C, strided-batched.
-// op: 0 = none, 1 = transpose, 2 = conjugate transpose.  64x64 output tile per
-// 256-thread workgroup, 4x4 outputs per thread, K staged through LDS in 16s.
-template <typename C>
-__device__ inline C load_op(const C* p, long ld, int op, long i, long k) {
-  if (op == 0) return p[i * ld + k];
-  C v = p[k * ld + i];
-  if (op == 2) v.im = -v.im;
-  return v;
-}
+// Complex GEMM  C = alpha * op(A) * op(B) + beta * C, strided-batched, on the
+// matrix cores (v_mfma_f64_16x16x4f64 for FP64, v_mfma_f32_16x16x4f32 for
+// FP32).  op: 0 = none, 1 = transpose, 2 = conjugate transpose.
+//
+// A workgroup owns a 32 x 32 complex output tile; its four waves split K in
+// four contiguous ranges and each accumulates the whole tile over its range
+// (the chain contractions have K = d chi >> M, N), then the four partial tiles
+// are summed through LDS in a fixed order, so results are deterministic.
+// A wave stages 16-deep K blocks of op(A) (32 x 16) and op(B) (16 x 32)
+// through its own LDS region with coalesced loads (the next block is held in
+// registers while the current one is multiplied).  Each complex product is
+// four real MFMAs: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// MFMA 16x16x4 operand layout (both types): A[i = lane % 16][k = lane / 16],
+// B[k = lane / 16][j = lane % 16].  Accumulator v of a lane holds
+// D[4 (lane / 16) + v][lane % 16] for FP32 and D[4 v + lane / 16][lane % 16]
+// for FP64 (mma_traits::row).
+template <typename C> struct mma_traits;
+template <> struct mma_traits<cplx64> {
+  typedef double R;
+  typedef double R4 __attribute__((ext_vector_type(4)));
+  typedef double2 V2;
+  static __device__ R4 mma(R a, R b, R4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct mma_traits<cplx32> {
+  typedef float R;
+  typedef float R4 __attribute__((ext_vector_type(4)));
+  typedef float2 V2;
+  static __device__ R4 mma(R a, R b, R4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+namespace {
+constexpr int kGT = 32;   // output tile (complex) per workgroup
+constexpr int kGK = 16;   // K block per stage
+}  // namespace
 
 template <typename C>
-__global__ __launch_bounds__(256) void zgemm_tiled(int M, int N, int K, C alpha, const C* __restrict__ A, long lda,
-                                                   long sA, int opA, const C* __restrict__ B, long ldb, long sB,
-                                                   int opB, C beta, C* __restrict__ Cm, long ldc, long sC) {
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ C As[TK][TM + 1];
-  __shared__ C Bs[TK][TN + 1];
+__global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C alpha, const C* __restrict__ A,
+                                                         long lda, long sA, int opA, const C* __restrict__ B,
+                                                         long ldb, long sB, int opB, C beta, C* __restrict__ Cm,
+                                                         long ldc, long sC) {
+  typedef mma_traits<C> T;
+  typedef typename T::R R;
+  typedef typename T::R4 R4;
+  typedef typename T::V2 V2;
+  // per wave: As[kGK][kGT] and Bs[kGK][kGT]; reused for the 4 partial tiles
+  __shared__ V2 lds[4 * 2 * kGK * kGT];
   const int bz = blockIdx.z;
   A += (long)bz * sA;
   B += (long)bz * sB;
   Cm += (long)bz * sC;
-  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;   // 16x16 thread grid, 4x4 each
-  typedef typename real_of<C>::type R;
-  C acc[4][4];
+  const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  V2* As = lds + w * 2 * kGK * kGT;
+  V2* Bs = As + kGK * kGT;
+  // this wave's K range
+  const int kq = ((K + 4 * kGK - 1) / (4 * kGK)) * kGK;
+  const int kb = w * kq, ke = min(K, kb + kq);
+  R4 cre[2][2], cim[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = cmake<C>((R)0, (R)0);
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    for (int e = tid; e < TM * TK; e += 256) {
-      int kk = e % TK, ii = e / TK;
-      long gi = row0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < M && gk < K) ? load_op(A, lda, opA, gi, gk) : cmake<C>((R)0, (R)0);
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = R4{0, 0, 0, 0};
+      cim[a][b] = R4{0, 0, 0, 0};
     }
-    for (int e = tid; e < TN * TK; e += 256) {
-      int jj = e % TN, kk = e / TN;
-      long gj = col0 + jj, gk = k0 + kk;
-      // op(B)(k, j): opB == 0 -> B[k*ldb + j]; else B[j*ldb + k] (conj for 2)
-      C v = cmake<C>((R)0, (R)0);
-      if (gj < N && gk < K) {
-        if (opB == 0) v = B[gk * ldb + gj];
-        else {
-          v = B[gj * ldb + gk];
-          if (opB == 2) v.im = -v.im;
-        }
+  // staging: 512 complex of each operand per block, 8 per lane
+  V2 ra[8], rb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = lane + 64 * r;
+      int ii, kk;
+      if (opA == 0) { ii = e / kGK; kk = e % kGK; } else { kk = e / kGT; ii = e % kGT; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      V2 v;
+      v.x = 0;
+      v.y = 0;
+      if (gi < M && gk < ke) {
+        const C z = opA == 0 ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi];
+        v.x = z.re;
+        v.y = opA == 2 ? -z.im : z.im;
       }
-      Bs[kk][jj] = v;
+      ra[r] = v;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < TK; ++kk) {
-      C a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
+    for (int r = 0; r < 8; ++r) {
+      const int e = lane + 64 * r;
+      int jj, kk;
+      if (opB == 0) { kk = e / kGT; jj = e % kGT; } else { jj = e / kGK; kk = e % kGK; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      V2 v;
+      v.x = 0;
+      v.y = 0;
+      if (gj < N && gk < ke) {
+        const C z = opB == 0 ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk];
+        v.x = z.re;
+        v.y = opB == 2 ? -z.im : z.im;
+      }
+      rb[r] = v;
     }
-    __syncthreads();
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = lane + 64 * r;
+      int ii, kk;
+      if (opA == 0) { ii = e / kGK; kk = e % kGK; } else { kk = e / kGT; ii = e % kGT; }
+      As[kk * kGT + ii] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = lane + 64 * r;
+      int jj, kk;
+      if (opB == 0) { kk = e / kGT; jj = e % kGT; } else { jj = e / kGK; kk = e % kGK; }
+      Bs[kk * kGT + jj] = rb[r];
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += kGK) {
+    stage();
+    // the wave's own LDS writes complete before its lanes read each other's
+    // entries (lgkmcnt(0); the loop trip count differs between waves, so no
+    // workgroup barrier here)
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    if (k0 + kGK < ke) fetch(k0 + kGK);
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const int kk = 4 * ks + (lane >> 4);
+      V2 av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = As[kk * kGT + 16 * t + (lane & 15)];
+        bv[t] = Bs[kk * kGT + 16 * t + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cre[a][b] = T::mma(av[a].x, bv[b].x, cre[a][b]);
+          cre[a][b] = T::mma(-av[a].y, bv[b].y, cre[a][b]);
+          cim[a][b] = T::mma(av[a].x, bv[b].y, cim[a][b]);
+          cim[a][b] = T::mma(av[a].y, bv[b].x, cim[a][b]);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // keep this block's reads before the next block's stage
   }
+  // sum the four partial tiles in a fixed order
+  __syncthreads();
+  V2* part = lds + w * kGT * kGT;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    long gi = row0 + tr * 4 + i;
-    if (gi >= M) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      long gj = col0 + tc * 4 + j;
-      if (gj >= N) continue;
-      C v = cmul(alpha, acc[i][j]);
-      if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, Cm[gi * ldc + gj]));
-      Cm[gi * ldc + gj] = v;
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = 16 * a + T::row(lane, v), jj = 16 * b + (lane & 15);
+        V2 z;
+        z.x = cre[a][b][v];
+        z.y = cim[a][b][v];
+        part[ii * kGT + jj] = z;
+      }
+  __syncthreads();
+  for (int e = tid; e < kGT * kGT; e += 256) {
+    const int ii = e / kGT, jj = e % kGT;
+    const int gi = i0 + ii, gj = j0 + jj;
+    if (gi >= M || gj >= N) continue;
+    R sr = 0, si = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const V2 z = lds[q * kGT * kGT + e];
+      sr += z.x;
+      si += z.y;
     }
+    C v = cmul(alpha, cmake<C>(sr, si));
+    if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, Cm[(long)gi * ldc + gj]));
+    Cm[(long)gi * ldc + gj] = v;
   }
 }
 
@@ -90,9 +191,9 @@ template <typename C>
 hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long lda, long sA, int opA, const C* B,
                  long ldb, long sB, int opB, C beta, C* Cm, long ldc, long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
-  hipLaunchKernelGGL(zgemm_tiled<C>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB, beta,
-                     Cm, ldc, sC);
+  dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch);
+  hipLaunchKernelGGL(zgemm_mfma_kernel<C>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB,
+                     beta, Cm, ldc, sC);
   return hipGetLastError();
 }
 template hipError_t zgemm<cplx64>(hipStream_t, int, int, int, cplx64, const cplx64*, long, long, int, const cplx64*,
