@@ -109,6 +109,7 @@ typedef struct {
   int64_t bytes;           /* device bytes held by the handle */
   int64_t pco_updates;     /* tensor elements produced by the PCO level gather */
   double t_gsvd_ms, t_kept_ms, t_pco_ms, t_svd_ms;  /* build phase times */
+  int32_t eig_sweeps;      /* sweeps of the bond eigensolver in the truncation step */
 } gbs_mps_info_t;
 
 /* Fill `info`; optional host arrays (may be NULL):

@@ -45,7 +45,7 @@ class InfoT(ctypes.Structure):
                 ("max_bond", ctypes.c_int32), ("max_ne", ctypes.c_int32), ("eps_max", ctypes.c_double),
                 ("norm_raw", ctypes.c_double), ("bytes", ctypes.c_int64), ("pco_updates", ctypes.c_int64),
                 ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
-                ("t_svd_ms", ctypes.c_double)]
+                ("t_svd_ms", ctypes.c_double), ("eig_sweeps", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

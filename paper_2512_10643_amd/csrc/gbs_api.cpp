@@ -128,6 +128,7 @@ struct gbs_mps_s {
   double norm_raw = 0;
   int64_t pco_updates = 0;
   double t_gsvd = 0, t_kept = 0, t_pco = 0, t_svd = 0;
+  int eig_sweeps = 0;            // sweeps of the bond eigensolver
   // canonical tensors
   void* tens = nullptr;          // contiguous, element size esz
   size_t esz = 16;
@@ -311,21 +312,20 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
     // matrices are stored with leading dimension eld (row stride) already.
     HIP_CHECK_RET(hipMemcpyAsync(edim_dev, edim.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
     if (M > 1) {
-      // logged Jacobi in groups bounded by the rotation-log size
-      const int max_sw = 30;
-      const long per = jacobi_log_entries((int)eld, max_sw);
-      const long cap = std::max<long>(1, (4L << 30) / (per * (long)sizeof(double2)));
-      const int group = (int)std::min<long>(M - 1, cap);
-      double2* logz;
-      int* nsw;
-      HIP_CHECK_RET(dalloc(tmp, &logz, (size_t)group * per));
-      HIP_CHECK_RET(dalloc(tmp, &nsw, group));
-      for (int b0 = 1; b0 < M; b0 += group) {
-        const int nb = std::min(group, M - b0);
-        const long off = (long)b0 * eld * eld;
-        HIP_CHECK_RET(jacobi_herm_logged(st, E64 + off, EVt + off, W64 + (long)b0 * eld, edim_dev + b0, (int)eld, eld,
-                                         eld * eld, nb, jerr, EV64 + off, logz, per, nsw, max_sw));
-      }
+      // blocked Jacobi over all bonds at once
+      const int nb = M - 1;
+      const long off = eld * eld;
+      cplx64* vsub;
+      int* active;
+      double* dmx;
+      HIP_CHECK_RET(dalloc(tmp, &vsub, (size_t)jacobi_blocked_ws_elems((int)eld, nb)));
+      HIP_CHECK_RET(dalloc(tmp, &active, nb));
+      HIP_CHECK_RET(dalloc(tmp, &dmx, nb));
+      int sweeps = 0;
+      HIP_CHECK_RET(jacobi_herm_blocked(st, E64 + off, EVt + off, W64 + eld, edim_dev + 1, (int)eld, eld, eld * eld, nb,
+                                        jerr, EV64 + off, vsub, active, dmx, 60, &sweeps));
+      if (sweeps < 0) return fail(GBS_E_INTERNAL, deverr_msg(GBS_DEVERR_JACOBI_BOND));
+      h->eig_sweeps = sweeps;
     }
   }
   std::vector<double> wall((size_t)(M + 1) * eld);
@@ -920,6 +920,7 @@ int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, do
   info->t_kept_ms = h->t_kept;
   info->t_pco_ms = h->t_pco;
   info->t_svd_ms = h->t_svd;
+  info->eig_sweeps = h->eig_sweeps;
   for (int m = 0; m <= h->M; ++m) {
     if (bond) bond[m] = h->bond[m];
     if (ne) ne[m] = h->ne[m];
@@ -1016,7 +1017,7 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   b += m * site * 16;
   b += 5 * chld * chld * 16 + chld * chld * d * 16;
   b += 3 * (m + 1) * chi * chi * 16 + 3 * site * 16;
-  b += std::min<int64_t>(4LL << 30, (m - 1 > 0 ? m - 1 : 1) * jacobi_log_entries((int)chi, 30) * 16);
+  b += (int64_t)jacobi_blocked_ws_elems((int)chi, (int)std::max<int64_t>(m - 1, 1)) * 16 + 16 * m;
   b += m * site * esz + (m + 1) * chi * chi * esz + 2 * site * esz;
   if (opt->prec != GBS_FP64 && chi <= 256) b += m * 16 * site;  // sampler operand
   // sampling buffers

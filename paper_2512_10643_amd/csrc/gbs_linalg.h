@@ -16,10 +16,13 @@ hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long 
 hipError_t jacobi_herm(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, long ld, long sA,
                        int batch, int* err, cplx64* Vout);
 
-// Same problem, faster for large batches: rotations are logged (log_stride
-// entries per matrix, see jacobi_log_entries) and the eigenvectors rebuilt by
-// a replay pass spread over many workgroups.  nsw: per-matrix sweep counts.
-long jacobi_log_entries(int n, int max_sweeps);
-hipError_t jacobi_herm_logged(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax, long ld,
-                              long sA, int batch, int* err, cplx64* Vout, double2* logz, long log_stride,
-                              int* nsw, int max_sweeps);
+// Same problem by blocked Jacobi (32 x 32 subproblems per round, see the
+// kernels): workspace Vs of jacobi_blocked_ws_elems(nmax, batch) complex,
+// `active` (batch ints) and `dm` (batch doubles).  Runs sweeps until a whole
+// sweep needs no rotation or max_sweeps is reached; synchronises `st` once per
+// sweep.  *sweeps_done receives the number of sweeps run, or -1 when the
+// last allowed sweep still rotated (not converged).
+long jacobi_blocked_ws_elems(int nmax, int batch);
+hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax,
+                               long ld, long sA, int batch, int* err, cplx64* Vout, cplx64* Vs, int* active,
+                               double* dm, int max_sweeps, int* sweeps_done);

@@ -3,6 +3,7 @@
 #include "gbs_linalg.h"
 
 #include <algorithm>
+#include <vector>
 
 // ---------------------------------------------------------------------------
 // Complex GEMM  C = alpha * op(A) * op(B) + beta * C, strided-batched, on the
@@ -382,187 +383,6 @@ __global__ __launch_bounds__(1024) void jacobi_herm_batched(cplx64* __restrict__
   }
 }
 
-// ---------------------------------------------------------------------------
-// Batched Hermitian Jacobi, two passes.  The sweep kernel (one workgroup per
-// matrix) rotates only the upper triangle of A and logs (s, phi) for every
-// rotation (c = sqrt(1 - s^2) since |t| <= 1; the sign of s is kept, as
-// (s, phi) and (-s, phi + pi) give different rotations); the replay kernel
-// rebuilds the eigenvector matrix from the identity, row blocks in parallel
-// across many workgroups; a sort pass orders eigenpairs descending.
-namespace {
-
-__device__ inline cplx64 uget(const cplx64* a, long ld, int r, int c) {
-  return r <= c ? a[(long)r * ld + c] : cconj(a[(long)c * ld + r]);
-}
-__device__ inline void uset(cplx64* a, long ld, int r, int c, cplx64 v) {
-  if (r <= c) a[(long)r * ld + c] = v;
-  else a[(long)c * ld + r] = cconj(v);
-}
-
-}  // namespace
-
-__global__ __launch_bounds__(1024) void jacobi_herm_sweep_kernel(cplx64* __restrict__ A, const int* __restrict__ dims,
-                                                                 long ld, long sA, int max_sweeps, double tol,
-                                                                 int* __restrict__ err, double2* __restrict__ logz,
-                                                                 long log_stride, int* __restrict__ nsw,
-                                                                 double* __restrict__ w) {
-  const int b = blockIdx.x;
-  const int n = dims ? dims[b] : (int)ld;
-  cplx64* a = A + (long)b * sA;
-  double2* lg = logz + (long)b * log_stride;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double rc[GBS_CHI_MAX / 2 + 1], rs[GBS_CHI_MAX / 2 + 1];
-  __shared__ cplx64 rz[GBS_CHI_MAX / 2 + 1];  // e^{-i phi}
-  __shared__ int rp[GBS_CHI_MAX / 2 + 1], rq[GBS_CHI_MAX / 2 + 1];
-  __shared__ int any_rot;
-  if (n <= 0) return;
-  for (int i = tid; i < n; i += nt) a[(long)i * ld + i].im = 0.0;
-  __syncthreads();
-  __shared__ double red[16];
-  const double floor_abs = fmax(1e-18 * diag_absmax(a, ld, n, red), 1e-300);
-  const int npad = n + (n & 1), half = npad / 2;
-  const long nblk = (long)half * (half + 1) / 2;
-  int sweeps = 0;
-  bool converged = (n == 1);
-  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-    if (tid == 0) any_rot = 0;
-    __syncthreads();
-    for (int s = 0; s < npad - 1; ++s) {
-      for (int i = tid; i < half; i += nt) {
-        int p, q;
-        rr_pair(npad, s, i, p, q);
-        double c = 1.0, sn = 0.0, phi = 0.0;
-        cplx64 z = cmake<cplx64>(1.0, 0.0);
-        if (p < n && q < n) {
-          double app = a[(long)p * ld + p].re, aqq = a[(long)q * ld + q].re;
-          cplx64 bpq = uget(a, ld, p, q);
-          double ab = sqrt(cabs2(bpq));
-          if (ab > tol * sqrt(fabs(app * aqq)) && ab > floor_abs) {
-            double th = (aqq - app) / (2.0 * ab);
-            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            sn = t * c;
-            z = cmake<cplx64>(bpq.re / ab, -bpq.im / ab);  // e^{-i phi}
-            phi = atan2(bpq.im, bpq.re);
-            any_rot = 1;
-          }
-        }
-        rp[i] = p;
-        rq[i] = q;
-        rc[i] = c;
-        rs[i] = sn;
-        rz[i] = z;
-        lg[((long)sweep * (npad - 1) + s) * half + i] = make_double2(sn, phi);
-      }
-      __syncthreads();
-      for (long e = tid; e < nblk; e += nt) {
-        int P = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-        while ((long)(P + 1) * (P + 2) / 2 <= e) ++P;
-        while ((long)P * (P + 1) / 2 > e) --P;
-        int Q = (int)(e - (long)P * (P + 1) / 2);
-        int p1 = rp[P], q1 = rq[P], p2 = rp[Q], q2 = rq[Q];
-        if (P == Q) {
-          if (p1 >= n || q1 >= n) continue;
-          if (rs[P] == 0.0) continue;
-          double t = rs[P] / rc[P];
-          cplx64 bpq = uget(a, ld, p1, q1);
-          double ab = sqrt(cabs2(bpq));
-          a[(long)p1 * ld + p1] = cmake<cplx64>(a[(long)p1 * ld + p1].re - t * ab, 0.0);
-          a[(long)q1 * ld + q1] = cmake<cplx64>(a[(long)q1 * ld + q1].re + t * ab, 0.0);
-          uset(a, ld, p1, q1, cmake<cplx64>(0.0, 0.0));
-          continue;
-        }
-        const bool r0v = p1 < n, r1v = q1 < n, c0v = p2 < n, c1v = q2 < n;
-        cplx64 x00 = cmake<cplx64>(0, 0), x01 = x00, x10 = x00, x11 = x00;
-        if (r0v && c0v) x00 = uget(a, ld, p1, p2);
-        if (r0v && c1v) x01 = uget(a, ld, p1, q2);
-        if (r1v && c0v) x10 = uget(a, ld, q1, p2);
-        if (r1v && c1v) x11 = uget(a, ld, q1, q2);
-        // X J_Q with J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
-        if (c0v && c1v && rs[Q] != 0.0) {
-          double cq = rc[Q], sq = rs[Q];
-          cplx64 eq = rz[Q];  // e^{-i phi}
-          cplx64 y00 = csub(cscale(x00, cq), cmul(cscale(x01, sq), eq));
-          cplx64 y01 = cadd(cscale(x00, sq), cmul(cscale(x01, cq), eq));
-          cplx64 y10 = csub(cscale(x10, cq), cmul(cscale(x11, sq), eq));
-          cplx64 y11 = cadd(cscale(x10, sq), cmul(cscale(x11, cq), eq));
-          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-        }
-        // J_P^H X with J_P^H = [[c, -s e^{i phi}], [s, c e^{i phi}]]
-        if (r0v && r1v && rs[P] != 0.0) {
-          double cp = rc[P], sp = rs[P];
-          cplx64 ep = cconj(rz[P]);  // e^{i phi}
-          cplx64 y00 = csub(cscale(x00, cp), cmul(cscale(x10, sp), ep));
-          cplx64 y01 = csub(cscale(x01, cp), cmul(cscale(x11, sp), ep));
-          cplx64 y10 = cadd(cscale(x00, sp), cmul(cscale(x10, cp), ep));
-          cplx64 y11 = cadd(cscale(x01, sp), cmul(cscale(x11, cp), ep));
-          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-        }
-        if (r0v && c0v) uset(a, ld, p1, p2, x00);
-        if (r0v && c1v) uset(a, ld, p1, q2, x01);
-        if (r1v && c0v) uset(a, ld, q1, p2, x10);
-        if (r1v && c1v) uset(a, ld, q1, q2, x11);
-      }
-      __syncthreads();
-    }
-    ++sweeps;
-    converged = (any_rot == 0);
-    __syncthreads();
-  }
-  if (!converged && tid == 0 && err) gbs_set_error(err, GBS_DEVERR_JACOBI_BOND);
-  if (tid == 0) nsw[b] = sweeps;
-  for (int i = tid; i < n; i += nt) w[(long)b * ld + i] = a[(long)i * ld + i].re;
-}
-
-// V rows [r0, r0 + rows) of matrix b, from the identity, by replaying the log.
-__global__ __launch_bounds__(256) void jacobi_herm_replay_kernel(const int* __restrict__ dims, long ld, long sA,
-                                                                  int rows, const double2* __restrict__ logz,
-                                                                  long log_stride, const int* __restrict__ nsw,
-                                                                  cplx64* __restrict__ V) {
-  const int b = blockIdx.y;
-  const int n = dims ? dims[b] : (int)ld;
-  const int r0 = blockIdx.x * rows;
-  if (r0 >= n) return;
-  const int nrow = min(rows, n - r0);
-  extern __shared__ cplx64 vs[];  // rows x n
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < rows * n; e += nt) {
-    int r = e / n, c = e % n;
-    vs[e] = cmake<cplx64>((r0 + r == c) ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  const int npad = n + (n & 1), half = npad / 2;
-  const int sweeps = nsw[b];
-  const double2* lg = logz + (long)b * log_stride;
-  for (int sw = 0; sw < sweeps; ++sw) {
-    for (int s = 0; s < npad - 1; ++s) {
-      const double2* ls = lg + ((long)sw * (npad - 1) + s) * half;
-      for (int e = tid; e < nrow * half; e += nt) {
-        int r = e / half, i = e % half;
-        const double2 sp = ls[i];
-        if (sp.x == 0.0) continue;
-        int p, q;
-        rr_pair(npad, s, i, p, q);
-        if (p >= n || q >= n) continue;
-        const double sn = sp.x, c = sqrt(fmax(0.0, 1.0 - sn * sn));
-        double sph, cph;
-        sincos(sp.y, &sph, &cph);
-        const cplx64 e_m = cmake<cplx64>(cph, -sph);  // e^{-i phi}
-        cplx64 vp = vs[r * n + p], vq = vs[r * n + q];
-        // V' = V J: v_p' = c v_p - s e^{-i phi} v_q ; v_q' = s v_p + c e^{-i phi} v_q
-        vs[r * n + p] = csub(cscale(vp, c), cscale(cmul(vq, e_m), sn));
-        vs[r * n + q] = cadd(cscale(vp, sn), cscale(cmul(vq, e_m), c));
-      }
-      __syncthreads();
-    }
-  }
-  cplx64* v = V + (long)b * sA;
-  for (int e = tid; e < nrow * n; e += nt) {
-    int r = e / n, c = e % n;
-    v[(long)(r0 + r) * ld + c] = vs[r * n + c];
-  }
-}
-
 // Sort eigenpairs of matrix b descending: w (in place) and Vout columns.
 __global__ __launch_bounds__(256) void jacobi_herm_sort_kernel(const int* __restrict__ dims, long ld, long sA,
                                                                double* __restrict__ w, const cplx64* __restrict__ V,
@@ -588,21 +408,268 @@ __global__ __launch_bounds__(256) void jacobi_herm_sort_kernel(const int* __rest
   }
 }
 
-long jacobi_log_entries(int n, int max_sweeps) {
-  const long npad = n + (n & 1);
-  return (long)max_sweeps * (npad - 1) * (npad / 2);
+// ---------------------------------------------------------------------------
+// Blocked two-sided Jacobi for batches of Hermitian matrices (FP64).
+//
+// Indices are grouped in blocks of 16; a round pairs the blocks round robin
+// (as the scalar method pairs indices) and for every pair solves the 32 x 32
+// Hermitian subproblem on its rows and columns to full convergence (one wave
+// per subproblem, in LDS), giving a unitary V_P.  The round then applies
+// A <- V^H A V and W <- W V with V block diagonal over the pairs, as 32 x 32
+// tile products spread over many workgroups.  A sweep visits every block pair
+// once, so the matrix is read and written once per round instead of once per
+// scalar rotation round (16x fewer passes over memory than the scalar
+// method).  The sweep loop stops when no subproblem of a whole sweep needed a
+// rotation on its first inner sweep.
+namespace {
+constexpr int kBJ = 16;        // block size
+constexpr int kBP = 2 * kBJ;   // subproblem size
+
+__device__ inline void bj_pair_idx(int npb, int round, int pr, int n, int* idx) {
+  int pb, qb;
+  rr_pair(npb, round, pr, pb, qb);
+  for (int k = 0; k < kBP; ++k) {
+    const int g = k < kBJ ? pb * kBJ + k : qb * kBJ + (k - kBJ);
+    idx[k] = g < n ? g : -1;
+  }
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void bj_init_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
+                                                      long ld, long sA, cplx64* __restrict__ Vt,
+                                                      double* __restrict__ dm) {
+  const int b = blockIdx.y;
+  const int n = dims ? dims[b] : (int)ld;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < (long)n * n) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    Vt[(long)b * sA + (long)i * ld + j] = cmake<cplx64>(i == j ? 1.0 : 0.0, 0.0);
+  }
+  if (blockIdx.x == 0) {
+    __shared__ double red[16];
+    const double m = diag_absmax(A + (long)b * sA, ld, n, red);
+    if (threadIdx.x == 0) dm[b] = m;
+  }
 }
 
-hipError_t jacobi_herm_logged(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax, long ld,
-                              long sA, int batch, int* err, cplx64* Vout, double2* logz, long log_stride,
-                              int* nsw, int max_sweeps) {
-  if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_herm_sweep_kernel, dim3(batch), dim3(1024), 0, st, A, dims, ld, sA, max_sweeps, 1e-15,
-                     err, logz, log_stride, nsw, w);
-  int rows = (int)std::max<long>(1, std::min<long>(32, 65536 / ((long)nmax * (long)sizeof(cplx64))));
-  dim3 g2((nmax + rows - 1) / rows, batch);
-  hipLaunchKernelGGL(jacobi_herm_replay_kernel, g2, dim3(256), (size_t)rows * nmax * sizeof(cplx64), st, dims, ld,
-                     sA, rows, logz, log_stride, nsw, Vtmp);
+__global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
+                                                      long ld, long sA, int npb, int round,
+                                                      const double* __restrict__ dm, double tol, int inner_sweeps,
+                                                      cplx64* __restrict__ Vs, int* __restrict__ active) {
+  const int pr = blockIdx.x, b = blockIdx.y, lane = threadIdx.x;
+  const int n = dims ? dims[b] : (int)ld;
+  const int npairs = npb / 2;
+  __shared__ cplx64 S[kBP][kBP + 1], V[kBP][kBP + 1];
+  __shared__ int idx[kBP];
+  __shared__ int rp[kBP / 2], rq[kBP / 2];
+  __shared__ double rc[kBP / 2], rs[kBP / 2];
+  __shared__ cplx64 rz[kBP / 2];
+  __shared__ int anyrot;
+  if (lane == 0) bj_pair_idx(npb, round, pr, n, idx);
+  __syncthreads();
+  const cplx64* a = A + (long)b * sA;
+  for (int e = lane; e < kBP * kBP; e += 64) {
+    const int i = e / kBP, j = e % kBP, gi = idx[i], gj = idx[j];
+    S[i][j] = (gi >= 0 && gj >= 0) ? a[(long)gi * ld + gj] : cmake<cplx64>(0.0, 0.0);
+    V[i][j] = cmake<cplx64>(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (lane < kBP) S[lane][lane].im = 0.0;
+  __syncthreads();
+  // entries below ~8 ulp of the largest diagonal entry are at the rounding
+  // level of the tile products that update A between rounds
+  const double floor_abs = fmax(1.8e-15 * dm[b], 1e-300);
+  bool converged = false;
+  for (int sweep = 0; sweep < inner_sweeps && !converged; ++sweep) {
+    if (lane == 0) anyrot = 0;
+    __syncthreads();
+    for (int r = 0; r < kBP - 1; ++r) {
+      if (lane < kBP / 2) {
+        int p, q;
+        rr_pair(kBP, r, lane, p, q);
+        double c = 1.0, sn = 0.0;
+        cplx64 z = cmake<cplx64>(1.0, 0.0);
+        if (idx[p] >= 0 && idx[q] >= 0) {
+          const double app = S[p][p].re, aqq = S[q][q].re;
+          const cplx64 bpq = S[p][q];
+          const double ab = sqrt(cabs2(bpq));
+          if (ab > tol * sqrt(fabs(app * aqq)) && ab > floor_abs) {
+            const double th = (aqq - app) / (2.0 * ab);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            z = cmake<cplx64>(bpq.re / ab, -bpq.im / ab);  // e^{-i phi}
+            anyrot = 1;
+          }
+        }
+        rp[lane] = p;
+        rq[lane] = q;
+        rc[lane] = c;
+        rs[lane] = sn;
+        rz[lane] = z;
+      }
+      __syncthreads();
+      // rows: S <- J^H S   (y_p = c x_p - s e^{i phi} x_q, y_q = s x_p + c e^{i phi} x_q)
+      for (int e = lane; e < (kBP / 2) * kBP; e += 64) {
+        const int pi = e / kBP, j = e % kBP;
+        const double sn = rs[pi];
+        if (sn == 0.0) continue;
+        const double c = rc[pi];
+        const cplx64 ep = cconj(rz[pi]);
+        const int p = rp[pi], q = rq[pi];
+        const cplx64 xp = S[p][j], xq = S[q][j];
+        S[p][j] = csub(cscale(xp, c), cmul(cscale(xq, sn), ep));
+        S[q][j] = cadd(cscale(xp, sn), cmul(cscale(xq, c), ep));
+      }
+      __syncthreads();
+      // columns: S <- S J and V <- V J   (y_p = c x_p - s e^{-i phi} x_q, y_q = s x_p + c e^{-i phi} x_q)
+      for (int e = lane; e < 2 * (kBP / 2) * kBP; e += 64) {
+        const int mat = e / ((kBP / 2) * kBP), rem = e % ((kBP / 2) * kBP);
+        const int pi = rem / kBP, i = rem % kBP;
+        const double sn = rs[pi];
+        if (sn == 0.0) continue;
+        const double c = rc[pi];
+        const cplx64 em = rz[pi];
+        const int p = rp[pi], q = rq[pi];
+        cplx64(*X)[kBP + 1] = mat ? V : S;
+        const cplx64 xp = X[i][p], xq = X[i][q];
+        X[i][p] = csub(cscale(xp, c), cmul(cscale(xq, sn), em));
+        X[i][q] = cadd(cscale(xp, sn), cmul(cscale(xq, c), em));
+      }
+      __syncthreads();
+      if (lane < kBP / 2 && rs[lane] != 0.0) {
+        const int p = rp[lane], q = rq[lane];
+        S[p][q] = cmake<cplx64>(0.0, 0.0);
+        S[q][p] = cmake<cplx64>(0.0, 0.0);
+        S[p][p].im = 0.0;
+        S[q][q].im = 0.0;
+      }
+      __syncthreads();
+    }
+    converged = (anyrot == 0);
+    if (sweep == 0 && !converged && lane == 0) active[b] = 1;
+    __syncthreads();
+  }
+  // an unconverged subproblem is fine: later rounds keep rotating its indices
+  cplx64* vo = Vs + ((long)b * npairs + pr) * kBP * kBP;
+  for (int e = lane; e < kBP * kBP; e += 64) vo[e] = V[e / kBP][e % kBP];
+}
+
+// One half of the round's update, on FP64 matrix cores.  ROWS: the rows of
+// pair P of A, 32 columns at a time: A[P, c] <- V_P^H A[P, c].  COLS: the
+// columns of pair P, 32 rows at a time: A[c, P] <- A[c, P] V_P for y < nch,
+// and the same on the eigenvector matrix W for y >= nch.  Each wave forms one
+// 16 x 16 quadrant of the 32 x 32 complex tile (4 real MFMAs per complex
+// k-step).
+template <bool ROWS>
+__global__ __launch_bounds__(256) void bj_pass_kernel(cplx64* __restrict__ A, cplx64* __restrict__ Wv,
+                                                      const int* __restrict__ dims, long ld, long sA, int npb,
+                                                      int round, const cplx64* __restrict__ Vs, int nch) {
+  typedef mma_traits<cplx64> T;
+  const int P = blockIdx.x, y = blockIdx.y, b = blockIdx.z;
+  const int n = dims ? dims[b] : (int)ld;
+  const int npairs = npb / 2;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  __shared__ cplx64 X[kBP][kBP + 1], VP[kBP][kBP + 1];
+  __shared__ int ip[kBP];
+  const bool onW = !ROWS && y >= nch;
+  const int c0 = kBP * (onW ? y - nch : y);
+  if (c0 >= n) return;
+  if (tid == 0) bj_pair_idx(npb, round, P, n, ip);
+  __syncthreads();
+  if (ip[0] < 0 && ip[kBJ] < 0) return;  // pair entirely beyond n (uniform)
+  cplx64* m = (onW ? Wv : A) + (long)b * sA;
+  const cplx64* vp = Vs + ((long)b * npairs + P) * kBP * kBP;
+  for (int e = tid; e < kBP * kBP; e += 256) {
+    const int i = e / kBP, j = e % kBP;
+    VP[i][j] = vp[e];
+    int gi, gj;
+    if (ROWS) { gi = ip[i]; gj = c0 + j; } else { gi = c0 + i; gj = ip[j]; }
+    X[i][j] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? m[(long)gi * ld + gj] : cmake<cplx64>(0.0, 0.0);
+  }
+  __syncthreads();
+  const int qi = w >> 1, qj = w & 1;
+  T::R4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll
+  for (int k0 = 0; k0 < kBP; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    cplx64 av, bv;
+    if (ROWS) {
+      av = cconj(VP[k][16 * qi + (lane & 15)]);   // (V_P^H)[i][k]
+      bv = X[k][16 * qj + (lane & 15)];
+    } else {
+      av = X[16 * qi + (lane & 15)][k];
+      bv = VP[k][16 * qj + (lane & 15)];
+    }
+    re = T::mma(av.re, bv.re, re);
+    re = T::mma(-av.im, bv.im, re);
+    im = T::mma(av.re, bv.im, im);
+    im = T::mma(av.im, bv.re, im);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * qi + T::row(lane, v), j = 16 * qj + (lane & 15);
+    int gi, gj;
+    if (ROWS) { gi = ip[i]; gj = c0 + j; } else { gi = c0 + i; gj = ip[j]; }
+    if (gi >= 0 && gi < n && gj >= 0 && gj < n) m[(long)gi * ld + gj] = cmake<cplx64>(re[v], im[v]);
+  }
+}
+
+__global__ void bj_diag_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims, long ld, long sA,
+                               double* __restrict__ w) {
+  const int b = blockIdx.x;
+  const int n = dims ? dims[b] : (int)ld;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) w[(long)b * ld + i] = A[(long)b * sA + (long)i * ld + i].re;
+}
+
+long jacobi_blocked_ws_elems(int nmax, int batch) {
+  const int nb = (nmax + kBJ - 1) / kBJ;
+  const int npb = nb + (nb & 1);
+  return (long)batch * (npb / 2) * kBP * kBP;
+}
+
+hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax,
+                               long ld, long sA, int batch, int* err, cplx64* Vout, cplx64* Vs, int* active,
+                               double* dm, int max_sweeps, int* sweeps_done) {
+  if (batch <= 0 || nmax <= 0) return hipSuccess;
+  const int nb = (nmax + kBJ - 1) / kBJ;
+  const int npb = std::max(2, nb + (nb & 1));
+  const int npairs = npb / 2;
+  const long nn = (long)nmax * nmax;
+  hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((nn + 255) / 256), batch), dim3(256), 0, st, A, dims, ld, sA,
+                     Vtmp, dm);
+  std::vector<int> act(batch);
+  int sw = 0;
+  for (; sw < max_sweeps; ++sw) {
+    hipError_t e = hipMemsetAsync(active, 0, batch * sizeof(int), st);
+    if (e != hipSuccess) return e;
+    for (int r = 0; r < npb - 1; ++r) {
+      hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(64), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
+                         4, Vs, active);
+      const int nch = (nmax + kBP - 1) / kBP;
+      hipLaunchKernelGGL(bj_pass_kernel<true>, dim3(npairs, nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld, sA,
+                         npb, r, Vs, nch);
+      hipLaunchKernelGGL(bj_pass_kernel<false>, dim3(npairs, 2 * nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld,
+                         sA, npb, r, Vs, nch);
+    }
+    e = hipMemcpyAsync(act.data(), active, batch * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    bool any = false;
+    for (int v : act) any = any || v;
+    if (!any) {
+      ++sw;
+      break;
+    }
+  }
+  if (sweeps_done) *sweeps_done = sw;
+  if (sw == max_sweeps) {  // the last sweep still rotated
+    (void)err;
+    if (sweeps_done) *sweeps_done = -1;
+  }
+  hipLaunchKernelGGL(bj_diag_kernel, dim3(batch), dim3(256), 0, st, A, dims, ld, sA, w);
   hipLaunchKernelGGL(jacobi_herm_sort_kernel, dim3(batch), dim3(256),
                      (size_t)nmax * (sizeof(double) + sizeof(int)), st, dims, ld, sA, w, Vtmp, Vout);
   return hipGetLastError();
