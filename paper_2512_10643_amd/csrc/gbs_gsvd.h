@@ -5,7 +5,7 @@
 #define GBS_GSVD_N2_MAX 600      // 2 * (n_e^{m-1} + 1) handled by one workgroup
 #define GBS_GSVD_LDS_N2 176      // packed symmetric working matrix kept in LDS up to this size
 #define GBS_GSVD_MAX_SWEEPS 40   // Jacobi sweep limit
-#define GBS_GSVD_VROWS 16        // eigenvector rows per workgroup in the replay pass
+#define GBS_GSVD_VROWS 4         // eigenvector rows per workgroup in the replay pass
 
 struct GsvdArgs {
   int M;

@@ -130,43 +130,36 @@ namespace {
 
 constexpr int TILE = 32;
 
-// C (M x N, ldc) = alpha op(A) op(B) + beta C by one 1024-thread workgroup.
-// op(X) = X^T when the flag is set.  32x32 output tiles staged through LDS.
+// C (M x N, ldc) = alpha op(A) op(B) + beta C by one workgroup on the FP64
+// matrix cores: each wave owns 16 x 16 output tiles (v_mfma_f64_16x16x4f64,
+// operands read straight from the L2-resident workspaces).  op(X) = X^T when
+// the flag is set.  C must not alias A or B.  Callers synchronise afterwards.
 __device__ void wg_dgemm(int M, int N, int K, double alpha, const double* A, long lda, bool tA, const double* B,
-                         long ldb, bool tB, double beta, double* C, long ldc, double* smem) {
-  double* As = smem;                       // [k][i], TILE x (TILE + 1)
-  double* Bs = smem + TILE * (TILE + 1);   // [k][j]
-  const int tid = threadIdx.x;
-  const int ty = tid / TILE, tx = tid % TILE;
-  const int ti = (M + TILE - 1) / TILE, tj = (N + TILE - 1) / TILE;
-  for (int t = 0; t < ti * tj; ++t) {
-    const int i0 = (t / tj) * TILE, j0 = (t % tj) * TILE;
-    double acc = 0.0;
-    for (int k0 = 0; k0 < K; k0 += TILE) {
-      if (tA) {  // op(A)(i,k) = A[k][i]
-        int k = k0 + ty, i = i0 + tx;
-        As[ty * (TILE + 1) + tx] = (k < K && i < M) ? A[(long)k * lda + i] : 0.0;
-      } else {
-        int i = i0 + ty, k = k0 + tx;
-        As[tx * (TILE + 1) + ty] = (k < K && i < M) ? A[(long)i * lda + k] : 0.0;
-      }
-      if (tB) {  // op(B)(k,j) = B[j][k]
-        int j = j0 + ty, k = k0 + tx;
-        Bs[tx * (TILE + 1) + ty] = (k < K && j < N) ? B[(long)j * ldb + k] : 0.0;
-      } else {
-        int k = k0 + ty, j = j0 + tx;
-        Bs[ty * (TILE + 1) + tx] = (k < K && j < N) ? B[(long)k * ldb + j] : 0.0;
-      }
-      wg_sync();
-#pragma unroll 8
-      for (int kk = 0; kk < TILE; ++kk) acc += As[kk * (TILE + 1) + ty] * Bs[kk * (TILE + 1) + tx];
-      wg_sync();
+                         long ldb, bool tB, double beta, double* C, long ldc, double* /*smem*/) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ti = (M + 15) / 16, tj = (N + 15) / 16;
+  const int r = lane & 15, kk = lane >> 4;
+  for (int t = wv; t < ti * tj; t += nw) {
+    const int i0 = (t / tj) * 16, j0 = (t % tj) * 16;
+    const int i = i0 + r, j = j0 + r;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + kk;
+      double av = 0.0, bv = 0.0;
+      if (i < M && k < K) av = tA ? A[(long)k * lda + i] : A[(long)i * lda + k];
+      if (j < N && k < K) bv = tB ? B[(long)j * ldb + k] : B[(long)k * ldb + j];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
-    const int i = i0 + ty, j = j0 + tx;
-    if (i < M && j < N) {
-      double v = alpha * acc;
-      if (beta != 0.0) v += beta * C[(long)i * ldc + j];
-      C[(long)i * ldc + j] = v;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + 4 * v + kk, col = j0 + r;  // FP64 accumulator layout
+      if (row < M && col < N) {
+        double x = alpha * acc[v];
+        if (beta != 0.0) x += beta * C[(long)row * ldc + col];
+        C[(long)row * ldc + col] = x;
+      }
     }
   }
 }
