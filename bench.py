@@ -97,6 +97,53 @@ def serving_mix(n, slots, loads=(0.7, 1.2), probe=64):
     return out
 
 
+def contractions(name):
+    """Bond contractions by precision on one workload: the truncation sweep of
+    the build (site transforms in the build precision; environments, their
+    eigenproblems and the norm chain in FP64) and the fidelity transfer
+    E <- sum_p A1[p]^H E A2[p].  Errors against the FP64 build / transfer."""
+    import torch
+    import workloads
+    from paper_2512_10643_amd import mps as gmps
+    w = workloads.workload(name)
+    g = torch.tensor(w.gamma, dtype=torch.float64, device="cuda")
+    out = {"metric": "bond contractions by precision", "workload": f"{name}: M={w.M} d={w.d} chi={w.chi}",
+           "builds": {}, "transfer": {}}
+    hs = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = gmps.build(g, w.d, w.chi, precision=prec)
+        torch.cuda.synchronize()
+        inf = h.info()
+        hs[prec] = h
+        out["builds"][prec] = {"build_s": time.perf_counter() - t0, "truncation_sweep_ms": inf["t_svd_ms"],
+                               "gsvd_ms": inf["t_gsvd_ms"], "max_bond": inf["max_bond"],
+                               "eig_sweeps": inf["eig_sweeps"]}
+        print(f"built {prec}", file=sys.stderr, flush=True)
+    for prec in ("fp32", "bf16x3"):
+        out["builds"][prec]["one_minus_fidelity_vs_fp64"] = 1.0 - hs[prec].fidelity(hs["fp64"])
+    # transfer <psi_fp64 | psi_fp32> in each arithmetic; the flop count is the
+    # algorithmic 16 d chi_{m-1} chi_m chi' per site summed over the chain
+    b64, b32 = hs["fp64"].info()["bond"], hs["fp32"].info()["bond"]
+    flops = sum(8.0 * w.d * (b64[m - 1] * b32[m - 1] * b32[m] + b64[m - 1] * b64[m] * b32[m])
+                for m in range(1, w.M + 1))
+    ref = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        hs["fp64"].overlap(hs["fp32"], precision=prec)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v = hs["fp64"].overlap(hs["fp32"], precision=prec)
+        dt = time.perf_counter() - t0
+        if ref is None:
+            ref = v
+        out["transfer"][prec] = {"ms": 1000 * dt, "tflops": flops / dt / 1e12, "value": [v.real, v.imag],
+                                 "abs_error_vs_fp64": abs(v - ref)}
+    for h in hs.values():
+        h.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +157,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--contractions", metavar="WORKLOAD", default=None,
+                    help="instead of the step: compare bond contractions (truncation sweep and fidelity "
+                         "transfer) in fp64 / fp32 / bf16x3 on a workload (e.g. c5)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -121,6 +171,9 @@ def main():
     import workloads
     from paper_2512_10643_amd import mps as gmps
 
+    if args.contractions:
+        print(json.dumps(contractions(args.contractions)))
+        return
     w = workloads.workload(args.workload)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()

@@ -99,6 +99,12 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
  *   out : host, 2 FP64 (re, im).  Synchronises `stream`. */
 int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream);
 
+/* The same transfer contraction in a chosen arithmetic: GBS_FP64, GBS_FP32
+ * (tensors rounded to FP32, FP32 matrix cores) or GBS_BF16X3 (FP32 tensors,
+ * split-BF16x3 products on the BF16 matrix cores).  Used to compare the cost
+ * and error of bond contractions by precision.  out: host, 2 FP64. */
+int gbs_mps_overlap_prec(gbs_mps h1, gbs_mps h2, int32_t prec, double* out, void* stream);
+
 /* Scalar information about a handle (host struct). */
 typedef struct {
   int32_t M, d, chi, prec;

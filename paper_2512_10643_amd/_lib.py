@@ -22,7 +22,8 @@ GBS_KEEP_RAW = 1
 EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5}
 
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
-EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_overlap", "gbs_mps_info",
+EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_overlap", "gbs_mps_overlap_prec",
+                    "gbs_mps_info",
                     "gbs_mps_export", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
                     "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
                     "gbs_server_stats", "gbs_server_reset_stats", "gbs_server_destroy")
@@ -86,6 +87,8 @@ def lib():
         L.gbs_mps_sample.restype = ctypes.c_int
         L.gbs_mps_overlap.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         L.gbs_mps_overlap.restype = ctypes.c_int
+        L.gbs_mps_overlap_prec.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp]
+        L.gbs_mps_overlap_prec.restype = ctypes.c_int
         L.gbs_mps_info.argtypes = [vp, ctypes.POINTER(InfoT), dp, dp, dp, dp]
         L.gbs_mps_info.restype = ctypes.c_int
         L.gbs_mps_export.argtypes = [vp, i32, i32, dp, i64, ctypes.POINTER(i64)]

@@ -364,20 +364,28 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   for (int m = 1; m < M; ++m)
     HIP_CHECK_RET(scaled_copy<CT>(st, Ub + (long)m * eld * eld, eld, EV64 + (long)m * eld * eld, eld, edim[m], r[m],
                                   nullptr, 0, 0));
+  // site transforms in the build precision: FP64 or FP32 MFMA, or split-BF16x3
+  auto gemm_ct = [&](int Mr, int Nc, int K, const CT* Ap, long lda, long sAp, int opA, const CT* Bp, long ldb,
+                     long sBp, CT* Cp, long ldc, long sCp, int batch) -> hipError_t {
+    if (h->prec == GBS_BF16X3)
+      return zgemm_bf16x3(st, Mr, Nc, K, cone<cplx32>(), (const cplx32*)Ap, lda, sAp, opA, (const cplx32*)Bp, ldb,
+                          sBp, 0, czero<cplx32>(), (cplx32*)Cp, ldc, sCp, batch);
+    return zgemm<CT>(st, Mr, Nc, K, cone<CT>(), Ap, lda, sAp, opA, Bp, ldb, sBp, 0, czero<CT>(), Cp, ldc, sCp, batch);
+  };
   for (int m = 1; m <= M; ++m) {
     int a = cl[m], b = cr[m], ra = r[m - 1], rb = r[m];
     HIP_CHECK_RET(convert<CT, cplx64>(st, Am, A[m], (long)a * d * b));
     // Y = A^m[p] U_m  (a x d x rb)
     const CT* Y = Am;
     if (m < M) {
-      HIP_CHECK_RET(zgemm<CT>(st, a, rb, b, cone<CT>(), Am, (long)d * b, b, 0, Ub + (long)m * eld * eld, eld, 0, 0,
-                              czero<CT>(), Tc, (long)d * rb, rb, d));
+      HIP_CHECK_RET(gemm_ct(a, rb, b, Am, (long)d * b, b, 0, Ub + (long)m * eld * eld, eld, 0, Tc, (long)d * rb, rb,
+                            d));
       Y = Tc;
     }
     CT* Bm = out + h->toff[m];
     if (m > 1) {
-      HIP_CHECK_RET(zgemm<CT>(st, ra, d * rb, a, cone<CT>(), Ub + (long)(m - 1) * eld * eld, eld, 0, 2, Y,
-                              (long)d * rb, 0, 0, czero<CT>(), Bm, (long)d * rb, 0, 1));
+      HIP_CHECK_RET(gemm_ct(ra, d * rb, a, Ub + (long)(m - 1) * eld * eld, eld, 0, 2, Y, (long)d * rb, 0, Bm,
+                            (long)d * rb, 0, 1));
     } else {
       HIP_CHECK_RET(hipMemcpyAsync(Bm, Y, sizeof(CT) * (long)a * d * rb, hipMemcpyDeviceToDevice, st));
     }
@@ -733,6 +741,50 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
 
 }  // namespace
 
+// <psi1|psi2> by the transfer chain E <- sum_p A1[p]^H E A2[p], E_0 = 1, in
+// arithmetic C (FP64, FP32 MFMA, or split-BF16x3 on FP32 data).
+template <typename C>
+int overlap_impl(gbs_mps_s* h1, gbs_mps_s* h2, hipStream_t st, int prec, double* out) {
+  const int M = h1->M, d = h1->d;
+  const int rmax = std::max(h1->maxbond, h2->maxbond);
+  DevArena tmp(st);
+  C *E[2], *X, *A1, *A2;
+  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(dalloc(tmp, &E[i], (size_t)rmax * rmax));
+  HIP_CHECK_RET(dalloc(tmp, &X, (size_t)rmax * d * rmax));
+  HIP_CHECK_RET(dalloc(tmp, &A1, (size_t)rmax * d * rmax));
+  HIP_CHECK_RET(dalloc(tmp, &A2, (size_t)rmax * d * rmax));
+  auto site = [&](gbs_mps_s* h, int m, C* dst) -> hipError_t {
+    long n = (long)h->bond[m - 1] * d * h->bond[m];
+    if (h->esz == sizeof(cplx64)) return convert<C, cplx64>(st, dst, (cplx64*)h->tens + h->toff[m], n);
+    return convert<C, cplx32>(st, dst, (cplx32*)h->tens + h->toff[m], n);
+  };
+  auto gemm = [&](int Mr, int Nc, int K, const C* A, long lda, int opA, const C* B, long ldb, C* Cm,
+                  long ldc) -> hipError_t {
+    if (prec == GBS_BF16X3)
+      return zgemm_bf16x3(st, Mr, Nc, K, cone<cplx32>(), (const cplx32*)A, lda, 0, opA, (const cplx32*)B, ldb, 0, 0,
+                          czero<cplx32>(), (cplx32*)Cm, ldc, 0, 1);
+    return zgemm<C>(st, Mr, Nc, K, cone<C>(), A, lda, 0, opA, B, ldb, 0, 0, czero<C>(), Cm, ldc, 0, 1);
+  };
+  const C one = cone<C>();
+  HIP_CHECK_RET(hipMemcpyAsync(E[0], &one, sizeof(C), hipMemcpyHostToDevice, st));
+  int cur = 0;
+  for (int m = 1; m <= M; ++m) {
+    const int a1 = h1->bond[m - 1], b1 = h1->bond[m], a2 = h2->bond[m - 1], b2 = h2->bond[m];
+    HIP_CHECK_RET(site(h1, m, A1));
+    HIP_CHECK_RET(site(h2, m, A2));
+    // X = E (a1 x a2) * A2 (a2 x d b2);  E' = A1^H ((a1 d) x b1)^H * X ((a1 d) x b2)
+    HIP_CHECK_RET(gemm(a1, d * b2, a2, E[cur], a2, 0, A2, (long)d * b2, X, (long)d * b2));
+    HIP_CHECK_RET(gemm(b1, b2, a1 * d, A1, b1, 2, X, b2, E[1 - cur], b2));
+    cur = 1 - cur;
+  }
+  C r;
+  HIP_CHECK_RET(hipMemcpyAsync(&r, E[cur], sizeof(C), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  out[0] = (double)r.re;
+  out[1] = (double)r.im;
+  return GBS_OK;
+}
+
 __attribute__((visibility("hidden"))) int gbs_fail(int code, const std::string& msg) { return fail(code, msg); }
 
 __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t stream, bool ordered_keep,
@@ -865,42 +917,19 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
 }
 
 int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream) {
+  return gbs_mps_overlap_prec(h1, h2, GBS_FP64, out, stream);
+}
+
+int gbs_mps_overlap_prec(gbs_mps h1, gbs_mps h2, int32_t prec, double* out, void* stream) {
   if (!h1 || !h2 || !out) return fail(GBS_E_INVAL, "NULL argument");
   if (h1->M != h2->M || h1->d != h2->d) return fail(GBS_E_INVAL, "overlap needs equal M and d");
+  if (prec != GBS_FP64 && prec != GBS_FP32 && prec != GBS_BF16X3) return fail(GBS_E_INVAL, "unknown precision");
   hipStream_t st = (hipStream_t)stream;
-  const int M = h1->M, d = h1->d;
-  const int rmax = std::max(h1->maxbond, h2->maxbond);
-  DevArena tmp(st);
-  cplx64 *E[2], *X, *A1, *A2;
-  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(dalloc(tmp, &E[i], (size_t)rmax * rmax));
-  HIP_CHECK_RET(dalloc(tmp, &X, (size_t)rmax * d * rmax));
-  HIP_CHECK_RET(dalloc(tmp, &A1, (size_t)rmax * d * rmax));
-  HIP_CHECK_RET(dalloc(tmp, &A2, (size_t)rmax * d * rmax));
-  auto site64 = [&](gbs_mps_s* h, int m, cplx64* dst) -> hipError_t {
-    long n = (long)h->bond[m - 1] * d * h->bond[m];
-    if (h->esz == sizeof(cplx64))
-      return hipMemcpyAsync(dst, (cplx64*)h->tens + h->toff[m], n * sizeof(cplx64), hipMemcpyDeviceToDevice, st);
-    return convert<cplx64, cplx32>(st, dst, (cplx32*)h->tens + h->toff[m], n);
-  };
-  const cplx64 one = cmake<cplx64>(1.0, 0.0), zero = cmake<cplx64>(0.0, 0.0);
-  HIP_CHECK_RET(hipMemcpyAsync(E[0], &one, sizeof(cplx64), hipMemcpyHostToDevice, st));
-  int cur = 0;
-  for (int m = 1; m <= M; ++m) {
-    const int a1 = h1->bond[m - 1], b1 = h1->bond[m], a2 = h2->bond[m - 1], b2 = h2->bond[m];
-    HIP_CHECK_RET(site64(h1, m, A1));
-    HIP_CHECK_RET(site64(h2, m, A2));
-    // X = E (a1 x a2) * A2 (a2 x d b2)
-    HIP_CHECK_RET(zgemm<cplx64>(st, a1, d * b2, a2, one, E[cur], a2, 0, 0, A2, (long)d * b2, 0, 0, zero, X,
-                                (long)d * b2, 0, 1));
-    // E' = A1^H ((a1 d) x b1)^H * X ((a1 d) x b2)
-    HIP_CHECK_RET(zgemm<cplx64>(st, b1, b2, a1 * d, one, A1, b1, 0, 2, X, b2, 0, 0, zero, E[1 - cur], b2, 0, 1));
-    cur = 1 - cur;
-  }
-  cplx64 r;
-  HIP_CHECK_RET(hipMemcpyAsync(&r, E[cur], sizeof(cplx64), hipMemcpyDeviceToHost, st));
-  HIP_CHECK_RET(hipStreamSynchronize(st));
-  out[0] = r.re;
-  out[1] = r.im;
+  double r[2];
+  int rc = prec == GBS_FP64 ? overlap_impl<cplx64>(h1, h2, st, prec, r) : overlap_impl<cplx32>(h1, h2, st, prec, r);
+  if (rc != GBS_OK) return rc;
+  out[0] = r[0];
+  out[1] = r[1];
   return GBS_OK;
 }
 

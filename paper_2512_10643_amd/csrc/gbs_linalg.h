@@ -9,6 +9,12 @@ template <typename C>
 hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long lda, long sA, int opA, const C* B,
                  long ldb, long sB, int opB, C beta, C* Cm, long ldc, long sC, int batch);
 
+// The same product for complex FP32 data by split-BF16x3 products on the BF16
+// matrix cores (relative error of order 2^-16 per real product).
+hipError_t zgemm_bf16x3(hipStream_t st, int M, int N, int K, cplx32 alpha, const cplx32* A, long lda, long sA,
+                        int opA, const cplx32* B, long ldb, long sB, int opB, cplx32 beta, cplx32* Cm, long ldc,
+                        long sC, int batch);
+
 // Batched Hermitian eigensolver (FP64 Jacobi).  Matrix b: size dims[b] (or ld
 // when dims == NULL), leading dimension ld, batch stride sA.  Writes
 // eigenvalues (descending) to w[b*ld + k] and eigenvectors as columns of Vout.

@@ -203,6 +203,182 @@ template hipError_t zgemm<cplx32>(hipStream_t, int, int, int, cplx32, const cplx
                                   long, long, int, cplx32, cplx32*, long, long, int);
 
 // ---------------------------------------------------------------------------
+// Complex GEMM on FP32 data by split-BF16x3 products on the BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16).  Every FP32 operand x is split as
+// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi); a real product is
+// taken as hi_a hi_b + hi_a lo_b + lo_a hi_b, accumulated in FP32, which
+// leaves a relative error of order 2^-16 per product (the lo_a lo_b term and
+// the residuals r are dropped).  A complex multiply-add is four real products,
+// so twelve BF16 MFMAs per complex 16x16x32 step.  Same tiling as
+// zgemm_mfma_kernel: a 32x32 complex tile per workgroup, K split over the four
+// waves, partial tiles summed in a fixed order.  Operand layout of the BF16
+// MFMA: A[i = lane % 16][k = 8 (lane / 16) + e], B[k = 8 (lane / 16) + e][j =
+// lane % 16] for e = 0..7; accumulator v holds D[4 (lane / 16) + v][lane % 16].
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int kXK = 32;   // K block per stage (one BF16 MFMA deep)
+
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, cplx32 alpha,
+                                                           const cplx32* __restrict__ A, long lda, long sA, int opA,
+                                                           const cplx32* __restrict__ B, long ldb, long sB, int opB,
+                                                           cplx32 beta, cplx32* __restrict__ Cm, long ldc, long sC) {
+  __shared__ float2 lds[4 * 2 * kXK * kGT];
+  const int bz = blockIdx.z;
+  A += (long)bz * sA;
+  B += (long)bz * sB;
+  Cm += (long)bz * sC;
+  const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  float2* As = lds + w * 2 * kXK * kGT;
+  float2* Bs = As + kXK * kGT;
+  const int kq = ((K + 4 * kXK - 1) / (4 * kXK)) * kXK;
+  const int kb = w * kq, ke = min(K, kb + kq);
+  f32x4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      cim[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  // staging: 1024 complex of each operand per block, 16 per lane
+  float2 ra[16], rb[16];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = lane + 64 * r;
+      int ii, kk;
+      if (opA == 0) { ii = e / kXK; kk = e % kXK; } else { kk = e / kGT; ii = e % kGT; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (gi < M && gk < ke) {
+        const cplx32 z = opA == 0 ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi];
+        v = make_float2(z.re, opA == 2 ? -z.im : z.im);
+      }
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = lane + 64 * r;
+      int jj, kk;
+      if (opB == 0) { kk = e / kGT; jj = e % kGT; } else { jj = e / kXK; kk = e % kXK; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (gj < N && gk < ke) {
+        const cplx32 z = opB == 0 ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk];
+        v = make_float2(z.re, opB == 2 ? -z.im : z.im);
+      }
+      rb[r] = v;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = lane + 64 * r;
+      int ii, kk;
+      if (opA == 0) { ii = e / kXK; kk = e % kXK; } else { kk = e / kGT; ii = e % kGT; }
+      As[kk * kGT + ii] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = lane + 64 * r;
+      int jj, kk;
+      if (opB == 0) { kk = e / kGT; jj = e % kGT; } else { jj = e / kXK; kk = e % kXK; }
+      Bs[kk * kGT + jj] = rb[r];
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += kXK) {
+    stage();
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    if (k0 + kXK < ke) fetch(k0 + kXK);
+    // split operands: for quadrant t, A rows 16 t + lane % 16, B columns 16 t + lane % 16
+    bf16x8 arh[2], arl[2], aih[2], ail[2], naih[2], nail[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int kk = 8 * (lane >> 4) + e;
+        const float2 av = As[kk * kGT + 16 * t + (lane & 15)];
+        const float2 bv = Bs[kk * kGT + 16 * t + (lane & 15)];
+        __bf16 h, l;
+        split_bf16(av.x, h, l); arh[t][e] = h; arl[t][e] = l;
+        split_bf16(av.y, h, l); aih[t][e] = h; ail[t][e] = l; naih[t][e] = -h; nail[t][e] = -l;
+        split_bf16(bv.x, h, l); brh[t][e] = h; brl[t][e] = l;
+        split_bf16(bv.y, h, l); bih[t][e] = h; bil[t][e] = l;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        f32x4 r = cre[a][b], q = cim[a][b];
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], brh[b], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], brl[b], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl[a], brh[b], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih[a], bih[b], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih[a], bil[b], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nail[a], bih[b], r, 0, 0, 0);
+        q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], bih[b], q, 0, 0, 0);
+        q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh[a], bil[b], q, 0, 0, 0);
+        q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl[a], bih[b], q, 0, 0, 0);
+        q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih[a], brh[b], q, 0, 0, 0);
+        q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih[a], brl[b], q, 0, 0, 0);
+        q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail[a], brh[b], q, 0, 0, 0);
+        cre[a][b] = r;
+        cim[a][b] = q;
+      }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  float2* part = lds + w * kGT * kGT;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = 16 * a + 4 * (lane >> 4) + v, jj = 16 * b + (lane & 15);
+        part[ii * kGT + jj] = make_float2(cre[a][b][v], cim[a][b][v]);
+      }
+  __syncthreads();
+  for (int e = tid; e < kGT * kGT; e += 256) {
+    const int ii = e / kGT, jj = e % kGT;
+    const int gi = i0 + ii, gj = j0 + jj;
+    if (gi >= M || gj >= N) continue;
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float2 z = lds[q * kGT * kGT + e];
+      sr += z.x;
+      si += z.y;
+    }
+    cplx32 v = cmul(alpha, cmake<cplx32>(sr, si));
+    if (beta.re != 0.f || beta.im != 0.f) v = cadd(v, cmul(beta, Cm[(long)gi * ldc + gj]));
+    Cm[(long)gi * ldc + gj] = v;
+  }
+}
+
+hipError_t zgemm_bf16x3(hipStream_t st, int M, int N, int K, cplx32 alpha, const cplx32* A, long lda, long sA,
+                        int opA, const cplx32* B, long ldb, long sB, int opB, cplx32 beta, cplx32* Cm, long ldc,
+                        long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch);
+  hipLaunchKernelGGL(zgemm_bf16x3_kernel, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB,
+                     beta, Cm, ldc, sC);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Batched Hermitian Jacobi (FP64), one 1024-thread workgroup per matrix.
 // Matrix b has size n = dims[b] (<= ld), stored at A + b*sA with leading
 // dimension ld.  On exit: w[b*ld + k] eigenvalues in descending order,

@@ -56,10 +56,11 @@ class GaussianMPS:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
-    def overlap(self, other: "GaussianMPS", stream=None) -> complex:
-        """<self|other> by an FP64 transfer contraction on the GPU."""
+    def overlap(self, other: "GaussianMPS", stream=None, precision: str = "fp64") -> complex:
+        """<self|other> by a transfer contraction on the GPU in the given
+        arithmetic (fp64, fp32 or bf16x3)."""
         out = (ctypes.c_double * 2)()
-        check(lib().gbs_mps_overlap(self._h, other._h, out, _stream_handle(stream)))
+        check(lib().gbs_mps_overlap_prec(self._h, other._h, _lib.PRECISIONS[precision], out, _stream_handle(stream)))
         return complex(out[0], out[1])
 
     def fidelity(self, other: "GaussianMPS", stream=None) -> float:

@@ -306,3 +306,30 @@ def test_c3_sampling_tvd_1e6_shots(torch_cuda):
     _say(f"  max per-mode TVD = {worst:.2e} (max TVD/floor {worst_ratio:.2f}); "
          f"mean photons {mean:.4f} vs exact {g['mean_photons']:.4f}")
     h.free()
+
+
+def test_bf16x3_contractions_c2(torch_cuda):
+    """Split-BF16x3 bond contractions (site transforms of the truncation sweep
+    and the fidelity transfer) against the FP64 build: 1 - F <= 1e-6, and the
+    transfer overlap within the expected ~2^-16 relative error per product."""
+    _say("case: c2 bf16x3 build and transfer contractions vs fp64")
+    w = W.workload("c2")
+    h64 = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    hb = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="bf16x3")
+    h32 = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
+    fb = hb.fidelity(h64)
+    f32 = h32.fidelity(h64)
+    _say(f"  1-F: bf16x3 {1 - fb:.3e}, fp32 {1 - f32:.3e}")
+    assert 1 - fb <= 1e-6
+    assert 1 - f32 <= 1e-9
+    ref = h64.overlap(h32)
+    e32 = abs(h64.overlap(h32, precision="fp32") - ref)
+    eb = abs(h64.overlap(h32, precision="bf16x3") - ref)
+    _say(f"  transfer <fp64|fp32> error: fp32 {e32:.3e}, bf16x3 {eb:.3e}")
+    assert e32 <= 1e-5
+    assert eb <= 1e-3
+    # the BF16x3 build samples through the FP32 sampler: parity of every shot
+    s = hb.sample(4096, seed=5)
+    assert int((s.sum(1) % 2).abs().sum()) == 0
+    for h in (h64, hb, h32):
+        h.free()
