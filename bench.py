@@ -23,6 +23,23 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 
+def sampler_traffic(avg_shots):
+    """HBM bytes of one interior-site sampling launch from the committed
+    rocprofv3 counter summary, scaled to `avg_shots`; None when the sampler
+    source has changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2512_10643_amd", "csrc", "gbs_sampler.hip")
+    prof = os.path.join(ROOT, "profiles", "sample_mfma_kernel_c3_traffic.md")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch_262144_shots", "sampler_source_sha256"))
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["sampler_source_sha256"].strip():
+            return None
+        return float(fields["traffic_bytes_per_launch_262144_shots"]) * avg_shots / 262144.0
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def sampling_flops_per_shot(bonds, d):
     """Algorithmic flops of one shot: sum_m 8 d chi_{m-1} chi_m (complex MACs)."""
     return sum(8.0 * d * bonds[m - 1] * bonds[m] for m in range(1, len(bonds)))
@@ -157,6 +174,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="copy a buffer of this many MiB on the device before the steps (a plain copy kernel of "
+                         "known size, to calibrate hardware byte counters)")
     ap.add_argument("--contractions", metavar="WORKLOAD", default=None,
                     help="instead of the step: compare bond contractions (truncation sweep and fidelity "
                          "transfer) in fp64 / fp32 / bf16x3 on a workload (e.g. c5)")
@@ -176,6 +196,12 @@ def main():
         return
     w = workloads.workload(args.workload)
     dev = torch.device("cuda:0")
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
     gamma = torch.tensor(w.gamma, dtype=torch.float64, device=dev)
     out = torch.empty((args.shots, w.M), dtype=torch.int32, device=dev)
@@ -236,9 +262,36 @@ def main():
         "eps_max": inf["eps_max"],
         "max_bond": inf["max_bond"],
         "flops_per_sample": fl_shot,
-        "roofline": {"bound": "mfma", "kernel": "sampling sweep (all sites)", "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
+        "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (whole sampling sweep, all sites)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": sampler_traffic(args.shots / max(1, -(-args.shots // 262144)))
+                     if args.precision != "fp64" and w.chi == 256 else None,
+                     "traffic_per": "bytes of one interior-site launch (average shots per chunk)"},
     }
+    # FP64 reference of the same workload (outside the timed region): 1 - F of
+    # the timed build's precision against FP64, and FP64 build / sampling rates
+    if args.precision != "fp64":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h64 = gmps.build(gamma, w.d, w.chi, precision="fp64")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        hp = gmps.build(gamma, w.d, w.chi, precision=args.precision)
+        one_minus_f = 1.0 - hp.fidelity(h64)
+        n64 = min(args.shots, 100_000)
+        s64 = torch.empty((n64, w.M), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h64.sample(n64, args.seed, out=s64)
+        torch.cuda.synchronize()
+        ts64 = time.perf_counter() - t0
+        res["one_minus_fidelity_vs_fp64"] = one_minus_f
+        res["fp64_reference"] = {"sites_per_s": w.M / t64, "build_ms": 1000 * t64,
+                                 "samples_per_s_sampling_only": n64 / ts64, "sampled_shots": n64,
+                                 "sites_per_s_ratio": res["sites_per_s"] / (w.M / t64),
+                                 "samples_per_s_ratio": res["samples_per_s_sampling_only"] / (n64 / ts64)}
+        hp.free()
+        h64.free()
     if not args.no_serving:
         res["serving"] = serving_mix(args.serving_requests, args.slots)
     if not args.no_cpu_baseline:
