@@ -509,8 +509,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_ord, (size_t)n2max));
   ga.ld_glr = 2 * M;
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_glr, (size_t)n2max * 2 * M));
-  HIP_CHECK_RET(dalloc(tmp, &ga.rot_log, (size_t)GBS_GSVD_MAX_SWEEPS * n2max * (n2max / 2 + 1)));
-  HIP_CHECK_RET(dalloc(tmp, &ga.nsweep, 1));
+  HIP_CHECK_RET(dalloc(tmp, &ga.ws_tri, (size_t)2 * n2max * n2max + 4 * n2max));
   ga.ld_u = n2max / 2 + 1;
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_U, (size_t)ga.ld_u * ga.ld_u));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_V, (size_t)ga.ld_u * ga.ld_u));
@@ -1036,7 +1035,7 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   const int64_t n2 = std::min<int64_t>(m + 2, GBS_GSVD_N2_MAX);
   int64_t b = 0;
   // Gaussian SVD chain: residual blocks, stage workspaces, rotation log, Q^m
-  b += 2 * (n2 * n2 + n2 * 2 * m) * 8 + 10 * n2 * n2 * 8 + (int64_t)GBS_GSVD_MAX_SWEEPS * n2 * (n2 / 2 + 1) * 16;
+  b += 2 * (n2 * n2 + n2 * 2 * m) * 8 + 10 * n2 * n2 * 8 + (2 * n2 * n2 + 4 * n2) * 8;
   b += m * (n2 / 2 + 2) * (n2 / 2 + 2) * 16 * 2;
   // kept bases and maps
   b += (m + 1) * chi * (40 + 16 * GBS_K_MAX + 6 * (n2 / 2 + 1));

@@ -4,8 +4,6 @@
 
 #define GBS_GSVD_N2_MAX 600      // 2 * (n_e^{m-1} + 1) handled by one workgroup
 #define GBS_GSVD_LDS_N2 176      // packed symmetric working matrix kept in LDS up to this size
-#define GBS_GSVD_MAX_SWEEPS 40   // Jacobi sweep limit
-#define GBS_GSVD_VROWS 4         // eigenvector rows per workgroup in the replay pass
 
 struct GsvdArgs {
   int M;
@@ -27,8 +25,7 @@ struct GsvdArgs {
   // workspace
   double *ws_G, *ws_L, *ws_A, *ws_B, *ws_E, *ws_O, *ws_S, *ws_vec, *ws_W, *ws_pack, *ws_w, *ws_glr;
   int* ws_ord;
-  double2* rot_log;
-  int* nsweep;
+  double* ws_tri;        // inverse-iteration scratch: 4 N2 doubles per thread, N2 / 2 threads
   long ld_ws, ld_glr;
   cplx64 *ws_U, *ws_V, *ws_aug;
   long ld_u;

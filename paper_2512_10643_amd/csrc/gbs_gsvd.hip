@@ -45,6 +45,23 @@ __device__ double wg_sum(double x, double* red) {
   return r;
 }
 
+// Maximum of one value per thread, same protocol as wg_sum.
+__device__ double wg_max(double x, double* red) {
+  const int tid = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = x;
+  wg_sync();
+  double r = 0.0;
+  if (tid == 0) {
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) r = fmax(r, red[i]);
+    red[32] = r;
+  }
+  wg_sync();
+  r = red[32];
+  wg_sync();
+  return r;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -118,12 +135,17 @@ __global__ __launch_bounds__(1024) void chol_xx_kernel(const double* g, int M, d
 }
 
 // ---------------------------------------------------------------------------
-// Gaussian SVD chain, three launches per cut (all sizes read from device
-// state so the host enqueues every cut without synchronising):
-//   stage 1 (one workgroup): Gamma_LL, Cholesky, A = L^T Omega L, B = A^T A,
-//            Jacobi on B packed in LDS; every rotation (c, s) is logged;
-//   V-apply (several workgroups): eigenvectors of B by replaying the log on
-//            row blocks of the identity (rows are independent);
+// Gaussian SVD chain, two launches per cut (all sizes read from device state
+// so the host enqueues every cut without synchronising):
+//   stage 1 (one workgroup): Gamma_LL, Cholesky 2 Gamma_LL = L L^T, the
+//            antisymmetric A = L^T Omega L, and the real Schur pairs of A:
+//            Householder reduction A = Q T Q^T to skew-tridiagonal T; the
+//            singular values D of A are the positive eigenvalues of the
+//            symmetric tridiagonal G with T's off-diagonal and zero diagonal
+//            (Golub-Kahan form), found by Sturm bisection; inverse iteration on
+//            G gives z, and its even / odd entries (signs + + - - ...) give the
+//            pair x_e, x_o with T x_e = D x_o, T x_o = -D x_e; back-transformed
+//            by Q they are orthonormal eigenvectors of A^T A for D^2;
 //   stage 2 (one workgroup): symplectic pairs, S, U, V, (U^dag)^-1, Q^m and
 //            the next residual.
 namespace {
@@ -168,6 +190,75 @@ __device__ inline long pk(int i, int j) {  // packed lower triangle, any order
   return i >= j ? (long)i * (i + 1) / 2 + j : (long)j * (j + 1) / 2 + i;
 }
 
+// packed strict lower triangle of an antisymmetric matrix: a(i, j) for i > j
+__device__ inline long pk2(int i, int j) { return (long)i * (i - 1) / 2 + j; }
+__device__ inline double aget(const double* P, int i, int j) {
+  return i > j ? P[pk2(i, j)] : (i < j ? -P[pk2(j, i)] : 0.0);
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with zero
+// diagonal and off-diagonal t[0..n-2] (Sturm sequence of the LDL^T pivots).
+__device__ int sturm_below(const double* t, int n, double x) {
+  int cnt = 0;
+  double d = -x;
+  if (d < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    if (d == 0.0) d = 1e-300;
+    d = -x - t[i - 1] * t[i - 1] / d;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Solve (G - s I) y = b in place (y holds b), G as in sturm_below, by
+// Gaussian elimination with partial pivoting.  Interleaved storage: y[i] at
+// y[i * ys], element i of scratch array a (0..3) at w[(a * n + i) * wsd].  Zero
+// pivots are replaced by `tiny` (inverse iteration only needs a direction).
+__device__ void tri_shift_solve_il(const double* t, int n, double s, double* y, long ys, double* w, long wsd,
+                                   double tiny) {
+#define D_(i) w[((long)(i)) * wsd]
+#define DU_(i) w[((long)n + (i)) * wsd]
+#define DU2_(i) w[(2L * n + (i)) * wsd]
+#define DL_(i) w[(3L * n + (i)) * wsd]
+#define Y_(i) y[((long)(i)) * ys]
+  for (int i = 0; i < n; ++i) {
+    D_(i) = -s;
+    DU_(i) = i + 1 < n ? t[i] : 0.0;
+    DL_(i) = i + 1 < n ? t[i] : 0.0;
+    DU2_(i) = 0.0;
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    if (fabs(D_(i)) >= fabs(DL_(i))) {
+      if (D_(i) == 0.0) D_(i) = tiny;
+      const double f = DL_(i) / D_(i);
+      D_(i + 1) -= f * DU_(i);
+      Y_(i + 1) -= f * Y_(i);
+    } else {
+      const double f = D_(i) / DL_(i);
+      D_(i) = DL_(i);
+      const double tmp = D_(i + 1);
+      D_(i + 1) = DU_(i) - f * tmp;
+      DU_(i) = tmp;
+      if (i + 2 < n) {
+        DU2_(i) = DU_(i + 1);
+        DU_(i + 1) = -f * DU_(i + 1);
+      }
+      const double yi = Y_(i);
+      Y_(i) = Y_(i + 1);
+      Y_(i + 1) = yi - f * Y_(i + 1);
+    }
+  }
+  if (D_(n - 1) == 0.0) D_(n - 1) = tiny;
+  Y_(n - 1) /= D_(n - 1);
+  if (n > 1) Y_(n - 2) = (Y_(n - 2) - DU_(n - 2) * Y_(n - 1)) / D_(n - 2);
+  for (int i = n - 3; i >= 0; --i) Y_(i) = (Y_(i) - DU_(i) * Y_(i + 1) - DU2_(i) * Y_(i + 2)) / D_(i);
+#undef D_
+#undef DU_
+#undef DU2_
+#undef DL_
+#undef Y_
+}
+
 }  // namespace
 
 // Stage 1.
@@ -182,14 +273,14 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     return;
   }
   extern __shared__ double lds[];
-  __shared__ double rc[GBS_GSVD_N2_MAX / 2 + 1], rs[GBS_GSVD_N2_MAX / 2 + 1];
-  __shared__ int rp[GBS_GSVD_N2_MAX / 2 + 1], rq[GBS_GSVD_N2_MAX / 2 + 1];
-  __shared__ int flag, bad;
+  __shared__ double vL[GBS_GSVD_N2_MAX], pL[GBS_GSVD_N2_MAX], part[1024], red[40];
+  __shared__ double tL[GBS_GSVD_N2_MAX], tauL[GBS_GSVD_N2_MAX];
+  __shared__ double sig0[GBS_GSVD_N2_MAX / 2], sigR[GBS_GSVD_N2_MAX / 2];
+  __shared__ int first[GBS_GSVD_N2_MAX / 2];
+  __shared__ int bad;
   const long ld = a.ld_ws;
-  const long npk = (long)N2 * (N2 + 1) / 2;
   const bool in_lds = N2 <= GBS_GSVD_LDS_N2;
-  double* P = in_lds ? lds : a.ws_pack;        // packed symmetric working matrix
-  double* tiles = lds + (long)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2;
+  double* P = in_lds ? lds : a.ws_pack;        // packed working matrix (Cholesky, then A)
   double* G = a.ws_G;
   double* Lm = a.ws_L;
   double* W = a.ws_W;
@@ -253,153 +344,158 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     W[(long)k * ld + j] = k < nL ? Lm[(long)(k + nL) * ld + j] : -Lm[(long)(k - nL) * ld + j];
   }
   wg_sync();
-  // A = L^T W;  B = A^T A (packed into P).
-  wg_dgemm(N2, N2, N2, 1.0, Lm, ld, true, W, ld, false, 0.0, Am, ld, tiles);
+  // A = L^T W, antisymmetric; its strict lower triangle, packed, is reduced below.
+  wg_dgemm(N2, N2, N2, 1.0, Lm, ld, true, W, ld, false, 0.0, Am, ld, nullptr);
   wg_sync();
-  wg_dgemm(N2, N2, N2, 1.0, Am, ld, true, Am, ld, false, 0.0, a.ws_B, ld, tiles);
-  wg_sync();
-  for (long e = tid; e < npk; e += nt) {
-    int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-    while ((long)(i + 1) * (i + 2) / 2 <= e) ++i;
-    while ((long)i * (i + 1) / 2 > e) --i;
-    int j = (int)(e - (long)i * (i + 1) / 2);
-    P[e] = 0.5 * (a.ws_B[(long)i * ld + j] + a.ws_B[(long)j * ld + i]);
+  for (long e = tid; e < (long)N2 * N2; e += nt) {
+    const int i = (int)(e / N2), j = (int)(e % N2);
+    if (i > j) P[pk2(i, j)] = 0.5 * (Am[(long)i * ld + j] - Am[(long)j * ld + i]);
   }
   wg_sync();
-  // Jacobi on the packed matrix; rotations logged for the eigenvector pass.
-  const int npad = N2 + (N2 & 1), half = npad / 2;
-  const long nblk = (long)half * (half + 1) / 2;
-  double2* log = a.rot_log;
-  int sweeps = 0;
-  bool converged = false;
-  for (int sweep = 0; sweep < GBS_GSVD_MAX_SWEEPS && !converged; ++sweep) {
-    if (tid == 0) flag = 0;
-    wg_sync();
-    for (int s = 0; s < npad - 1; ++s) {
-      for (int i = tid; i < half; i += nt) {
-        int p, q;
-        rr_pair_s(npad, s, i, p, q);
-        double c = 1.0, sn = 0.0;
-        if (p < N2 && q < N2) {
-          double app = P[pk(p, p)], aqq = P[pk(q, q)], apq = P[pk(p, q)];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-            double th = (aqq - app) / (2.0 * apq);
-            double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            sn = t * c;
-            flag = 1;
-          }
-        }
-        rp[i] = p;
-        rq[i] = q;
-        rc[i] = c;
-        rs[i] = sn;
-        log[((long)sweep * (npad - 1) + s) * half + i] = make_double2(c, sn);
-      }
-      wg_sync();
-      for (long e = tid; e < nblk; e += nt) {
-        int PP = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-        while ((long)(PP + 1) * (PP + 2) / 2 <= e) ++PP;
-        while ((long)PP * (PP + 1) / 2 > e) --PP;
-        int QQ = (int)(e - (long)PP * (PP + 1) / 2);
-        int p1 = rp[PP], q1 = rq[PP], p2 = rp[QQ], q2 = rq[QQ];
-        if (PP == QQ) {
-          if (p1 >= N2 || q1 >= N2 || rs[PP] == 0.0) continue;
-          double t = rs[PP] / rc[PP];
-          double apq = P[pk(p1, q1)];
-          P[pk(p1, p1)] -= t * apq;
-          P[pk(q1, q1)] += t * apq;
-          P[pk(p1, q1)] = 0.0;
-          continue;
-        }
-        bool r0v = p1 < N2, r1v = q1 < N2, c0v = p2 < N2, c1v = q2 < N2;
-        double x00 = (r0v && c0v) ? P[pk(p1, p2)] : 0.0;
-        double x01 = (r0v && c1v) ? P[pk(p1, q2)] : 0.0;
-        double x10 = (r1v && c0v) ? P[pk(q1, p2)] : 0.0;
-        double x11 = (r1v && c1v) ? P[pk(q1, q2)] : 0.0;
-        double cq = rc[QQ], sq = rs[QQ];
-        if (sq != 0.0) {
-          double y00 = cq * x00 - sq * x01, y01 = sq * x00 + cq * x01;
-          double y10 = cq * x10 - sq * x11, y11 = sq * x10 + cq * x11;
-          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-        }
-        double cp = rc[PP], sp = rs[PP];
-        if (sp != 0.0) {
-          double y00 = cp * x00 - sp * x10, y01 = cp * x01 - sp * x11;
-          double y10 = sp * x00 + cp * x10, y11 = sp * x01 + cp * x11;
-          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-        }
-        if (r0v && c0v) P[pk(p1, p2)] = x00;
-        if (r0v && c1v) P[pk(p1, q2)] = x01;
-        if (r1v && c0v) P[pk(q1, p2)] = x10;
-        if (r1v && c1v) P[pk(q1, q2)] = x11;
-      }
-      wg_sync();
+  double* Vh = a.ws_B;            // reflector k in row k (length N2 - k - 1)
+  // Householder: column k of the trailing block -> beta e_1; A <- H A H keeps
+  // A antisymmetric: A_sub += v p^T - p v^T with p = tau A_sub v.
+  for (int k = 0; k + 2 < N2; ++k) {
+    const int r = N2 - k - 1;
+    double ss = 0.0;
+    for (int i = tid; i < r; i += nt) {
+      const double x = P[pk2(k + 1 + i, k)];
+      vL[i] = x;
+      ss += x * x;
     }
-    ++sweeps;
-    converged = (flag == 0);
+    ss = wg_sum(ss, red);
+    const double x0 = vL[0];
+    const double alpha = sqrt(ss);
+    const double beta = x0 > 0.0 ? -alpha : alpha;
+    const double vtv = 2.0 * (ss - x0 * beta);
+    const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    wg_sync();
+    if (tid == 0) {
+      vL[0] = x0 - beta;
+      tauL[k] = tau;
+      tL[k] = alpha > 0.0 ? beta : x0;
+    }
+    wg_sync();
+    for (int i = tid; i < r; i += nt) Vh[(long)k * ld + i] = vL[i];
+    // p = tau A_sub v: 32 threads per row, rows strided by nt / 32
+    for (int row = tid >> 5; row < r; row += nt >> 5) {
+      double acc = 0.0;
+      for (int j = tid & 31; j < r; j += 32) acc += aget(P, k + 1 + row, k + 1 + j) * vL[j];
+      for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
+      if ((tid & 31) == 0) pL[row] = tau * acc;
+    }
+    wg_sync();
+    for (int i = tid >> 5; i < r; i += nt >> 5) {
+      const double vi = vL[i], pi = pL[i];
+      double* Pi = P + pk2(k + 1 + i, k + 1);
+      for (int j = tid & 31; j < i; j += 32) Pi[j] += vi * pL[j] - pi * vL[j];
+    }
     wg_sync();
   }
-  if (!converged) {
-    if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_JACOBI);
-    return;
-  }
-  // eigenvalues and their descending order
-  for (int i = tid; i < N2; i += nt) a.ws_w[i] = P[pk(i, i)];
+  if (tid == 0) tL[N2 - 2] = P[pk2(N2 - 1, N2 - 2)];
   wg_sync();
-  for (int i = tid; i < N2; i += nt) {
-    double wi = a.ws_w[i];
-    int rank = 0;
-    for (int j = 0; j < N2; ++j) {
-      double wj = a.ws_w[j];
-      rank += (wj > wi) || (wj == wi && j < i);
+  // positive eigenvalues of G by Sturm bisection (one thread each)
+  double tm = 0.0;
+  for (int i = tid; i < N2 - 1; i += nt) tm = fmax(tm, fabs(tL[i]));
+  tm = wg_max(tm, red);
+  const double bound = 2.0 * tm + 1e-300;
+  const double tiny = 2.2e-16 * bound + 1e-300;
+  const int n = nL;
+  for (int q = tid; q < n; q += nt) {
+    double lo = 0.0, hi = bound;
+    for (int it = 0; it < 48; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (sturm_below(tL, N2, mid) <= N2 - 1 - q) lo = mid;
+      else hi = mid;
     }
-    a.ws_ord[rank] = i;
+    sig0[q] = 0.5 * (lo + hi);
   }
-  if (tid == 0) *a.nsweep = sweeps;
-}
-
-// Eigenvectors: rows [r0, r0 + ROWS) of V = J_1 J_2 ... (product of the logged
-// rotations); V starts as the identity.
-__global__ __launch_bounds__(256) void gsvd_vapply_kernel(GsvdArgs a, int m) {
-  constexpr int ROWS = GBS_GSVD_VROWS;
-  if (*a.err) return;
-  const int n_prev = a.ne[m - 1];
-  const int N2 = 2 * (n_prev + 1);
-  const int r0 = blockIdx.x * ROWS;
-  if (r0 >= N2) return;
-  const int nrow = min(ROWS, N2 - r0);
-  extern __shared__ double vs[];  // ROWS x N2
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < ROWS * N2; e += nt) {
-    int r = e / N2, c = e % N2;
-    vs[e] = (r0 + r == c) ? 1.0 : 0.0;
+  wg_sync();
+  // clusters of shifts closer than 1e-5 bound share one thread, which
+  // orthogonalises each member against the earlier ones inside the iteration
+  if (tid == 0) {
+    first[0] = 0;
+    for (int q = 1; q < n; ++q) first[q] = (sig0[q - 1] - sig0[q] < 1e-5 * bound) ? first[q - 1] : q;
   }
-  __syncthreads();
-  const int npad = N2 + (N2 & 1), half = npad / 2;
-  const int sweeps = *a.nsweep;
-  const double2* log = a.rot_log;
-  for (int sw = 0; sw < sweeps; ++sw) {
-    for (int s = 0; s < npad - 1; ++s) {
-      const double2* lg = log + ((long)sw * (npad - 1) + s) * half;
-      for (int e = tid; e < nrow * half; e += nt) {
-        int r = e / half, i = e % half;
-        double2 cs = lg[i];
-        if (cs.y == 0.0) continue;
-        int p, q;
-        rr_pair_s(npad, s, i, p, q);
-        if (p >= N2 || q >= N2) continue;
-        double vp = vs[r * N2 + p], vq = vs[r * N2 + q];
-        vs[r * N2 + p] = cs.x * vp - cs.y * vq;
-        vs[r * N2 + q] = cs.y * vp + cs.x * vq;
+  wg_sync();
+  // z_q as column q of Z (entry i at Z[i n + q]) and per-thread scratch with
+  // the same interleaving, so a wave's threads touch consecutive addresses
+  double* Z = a.ws_O;
+  double* scr = a.ws_tri;
+  for (int q = tid; q < n; q += nt) {
+    if (first[q] != q) continue;
+    int qe = q + 1;
+    while (qe < n && first[qe] == q) ++qe;
+    for (int u = q; u < qe; ++u) {
+      for (int i = 0; i < N2; ++i) Z[(long)i * n + u] = cos(0.7 * (u + 1) * i + 0.3);
+      for (int it = 0; it < 2; ++it) {
+        tri_shift_solve_il(tL, N2, sig0[u], Z + u, n, scr + q, n, tiny);
+        for (int v2 = q; v2 < u; ++v2) {
+          double c = 0.0;
+          for (int i = 0; i < N2; ++i) c += Z[(long)i * n + v2] * Z[(long)i * n + u];
+          for (int i = 0; i < N2; ++i) Z[(long)i * n + u] -= c * Z[(long)i * n + v2];
+        }
+        double nn = 0.0;
+        for (int i = 0; i < N2; ++i) nn += Z[(long)i * n + u] * Z[(long)i * n + u];
+        const double inv = 1.0 / sqrt(nn);
+        for (int i = 0; i < N2; ++i) Z[(long)i * n + u] *= inv;
       }
-      __syncthreads();
+      double rq = 0.0;  // Rayleigh quotient z^T G z
+      for (int i = 0; i + 1 < N2; ++i) rq += 2.0 * tL[i] * Z[(long)i * n + u] * Z[(long)i * n + u + n];
+      sigR[u] = fabs(rq);
     }
   }
-  const long ld = a.ld_ws;
-  for (int e = tid; e < nrow * N2; e += nt) {
-    int r = e / N2, c = e % N2;
-    a.ws_E[(long)(r0 + r) * ld + c] = vs[r * N2 + c];
+  wg_sync();
+  // U = Q X_e with X_e column q = sqrt2 (even entries of z_q, signs + + - - ..),
+  // kept in LDS (the packed A is no longer needed): column q at XU[q N2 + i].
+  // Reflectors are applied last to first, each by all threads: G threads per
+  // column form the dot product v^T x, then update their share of rows.
+  double* XU = in_lds && (long)n * N2 <= (long)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2 ? lds : a.ws_W;
+  for (long e = tid; e < (long)n * N2; e += nt) {
+    const int q = (int)(e / N2), i = (int)(e % N2);
+    const double sg = ((i >> 1) & 1) ? -1.41421356237309515 : 1.41421356237309515;
+    XU[e] = (i & 1) ? 0.0 : sg * Z[(long)i * n + q];
+  }
+  const int Gp = max(1, nt / n);
+  const int cq = tid / Gp, gq = tid % Gp;
+  for (int k = N2 - 3; k >= 0; --k) {
+    const int r = N2 - k - 1;
+    wg_sync();
+    for (int i = tid; i < r; i += nt) vL[i] = Vh[(long)k * ld + i];
+    wg_sync();
+    double acc = 0.0;
+    if (cq < n)
+      for (int i = gq; i < r; i += Gp) acc += vL[i] * XU[(long)cq * N2 + k + 1 + i];
+    part[tid] = acc;
+    wg_sync();
+    if (cq < n) {
+      double w = 0.0;
+      for (int g2 = 0; g2 < Gp; ++g2) w += part[cq * Gp + g2];
+      w *= tauL[k];
+      for (int i = gq; i < r; i += Gp) XU[(long)cq * N2 + k + 1 + i] -= w * vL[i];
+    }
+  }
+  wg_sync();
+  // E: column 2q = u_q, column 2q + 1 = A u_q / D_q (the partner in the plane)
+  double* Uc = a.ws_O;   // U (N2 x n); z is no longer needed
+  double* AU = a.ws_B;   // A U; the reflectors are no longer needed
+  for (long e = tid; e < (long)n * N2; e += nt) {
+    const int q = (int)(e / N2), i = (int)(e % N2);
+    a.ws_E[(long)i * ld + 2 * q] = XU[e];
+    Uc[(long)i * ld + q] = XU[e];
+  }
+  wg_sync();
+  wg_dgemm(N2, n, N2, 1.0, Am, ld, false, Uc, ld, false, 0.0, AU, ld, nullptr);
+  wg_sync();
+  for (long e = tid; e < (long)n * N2; e += nt) {
+    const int i = (int)(e / n), q = (int)(e % n);
+    a.ws_E[(long)i * ld + 2 * q + 1] = AU[(long)i * ld + q] / sigR[q];
+  }
+  // eigenvalues of A^T A (D^2, each twice), already in descending order
+  for (int c = tid; c < N2; c += nt) {
+    const double sgm = sigR[c >> 1];
+    a.ws_w[c] = sgm * sgm;
+    a.ws_ord[c] = c;
   }
 }
 
@@ -692,11 +788,9 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
 }
 
 hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max) {
-  const size_t lds1 = sizeof(double) * ((size_t)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2 + 2 * 32 * 33);
+  (void)n2max;
+  const size_t lds1 = sizeof(double) * ((size_t)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2);
   hipLaunchKernelGGL(gsvd_stage1_kernel, dim3(1), dim3(1024), lds1, st, a, m);
-  const int nblk = (n2max + GBS_GSVD_VROWS - 1) / GBS_GSVD_VROWS;
-  const size_t lds2 = sizeof(double) * (size_t)GBS_GSVD_VROWS * n2max;
-  hipLaunchKernelGGL(gsvd_vapply_kernel, dim3(nblk), dim3(256), lds2, st, a, m);
   const size_t lds3 = sizeof(double) * ((size_t)2 * 32 * 33 + GBS_GSVD_N2_MAX + 8);
   hipLaunchKernelGGL(gsvd_stage2_kernel, dim3(1), dim3(1024), lds3, st, a, m);
   return hipGetLastError();
