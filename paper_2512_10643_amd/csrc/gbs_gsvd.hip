@@ -216,47 +216,46 @@ __device__ int sturm_below(const double* t, int n, double x) {
 // pivots are replaced by `tiny` (inverse iteration only needs a direction).
 __device__ void tri_shift_solve_il(const double* t, int n, double s, double* y, long ys, double* w, long wsd,
                                    double tiny) {
-#define D_(i) w[((long)(i)) * wsd]
-#define DU_(i) w[((long)n + (i)) * wsd]
-#define DU2_(i) w[(2L * n + (i)) * wsd]
-#define DL_(i) w[(3L * n + (i)) * wsd]
-#define Y_(i) y[((long)(i)) * ys]
-  for (int i = 0; i < n; ++i) {
-    D_(i) = -s;
-    DU_(i) = i + 1 < n ? t[i] : 0.0;
-    DL_(i) = i + 1 < n ? t[i] : 0.0;
-    DU2_(i) = 0.0;
-  }
+  // forward elimination with the current row carried in registers; the final
+  // pivot rows (diag, super, second super) go to the scratch arrays
+  double* D = w;
+  double* DU = w + (long)n * wsd;
+  double* DU2 = w + 2L * n * wsd;
+  double cd = -s, cdu = n > 1 ? t[0] : 0.0, cy = y[0];
   for (int i = 0; i + 1 < n; ++i) {
-    if (fabs(D_(i)) >= fabs(DL_(i))) {
-      if (D_(i) == 0.0) D_(i) = tiny;
-      const double f = DL_(i) / D_(i);
-      D_(i + 1) -= f * DU_(i);
-      Y_(i + 1) -= f * Y_(i);
-    } else {
-      const double f = D_(i) / DL_(i);
-      D_(i) = DL_(i);
-      const double tmp = D_(i + 1);
-      D_(i + 1) = DU_(i) - f * tmp;
-      DU_(i) = tmp;
-      if (i + 2 < n) {
-        DU2_(i) = DU_(i + 1);
-        DU_(i + 1) = -f * DU_(i + 1);
-      }
-      const double yi = Y_(i);
-      Y_(i) = Y_(i + 1);
-      Y_(i + 1) = yi - f * Y_(i + 1);
+    const double tn = t[i], nd = -s, ndu = i + 2 < n ? t[i + 1] : 0.0, ny = y[(long)(i + 1) * ys];
+    if (fabs(cd) >= fabs(tn)) {
+      if (cd == 0.0) cd = tiny;
+      const double f = tn / cd;
+      D[(long)i * wsd] = cd;
+      DU[(long)i * wsd] = cdu;
+      DU2[(long)i * wsd] = 0.0;
+      y[(long)i * ys] = cy;
+      cd = nd - f * cdu;
+      cdu = ndu;
+      cy = ny - f * cy;
+    } else {  // the next row becomes the pivot row
+      const double f = cd / tn;
+      D[(long)i * wsd] = tn;
+      DU[(long)i * wsd] = nd;
+      DU2[(long)i * wsd] = ndu;
+      y[(long)i * ys] = ny;
+      const double ed = cdu - f * nd, edu = -f * ndu, ey = cy - f * ny;
+      cd = ed;
+      cdu = edu;
+      cy = ey;
     }
   }
-  if (D_(n - 1) == 0.0) D_(n - 1) = tiny;
-  Y_(n - 1) /= D_(n - 1);
-  if (n > 1) Y_(n - 2) = (Y_(n - 2) - DU_(n - 2) * Y_(n - 1)) / D_(n - 2);
-  for (int i = n - 3; i >= 0; --i) Y_(i) = (Y_(i) - DU_(i) * Y_(i + 1) - DU2_(i) * Y_(i + 2)) / D_(i);
-#undef D_
-#undef DU_
-#undef DU2_
-#undef DL_
-#undef Y_
+  if (cd == 0.0) cd = tiny;
+  // back substitution, the two later unknowns carried in registers
+  double x2 = 0.0, x1 = cy / cd;
+  y[(long)(n - 1) * ys] = x1;
+  for (int i = n - 2; i >= 0; --i) {
+    const double xi = (y[(long)i * ys] - DU[(long)i * wsd] * x1 - DU2[(long)i * wsd] * x2) / D[(long)i * wsd];
+    y[(long)i * ys] = xi;
+    x2 = x1;
+    x1 = xi;
+  }
 }
 
 }  // namespace
@@ -306,38 +305,99 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     if (j <= i) P[pk(i, j)] = 2.0 * val;
   }
   wg_sync();
-  // Cholesky (right looking, packed lower triangle).
-  for (int j = 0; j < N2; ++j) {
+  // A factor L with L L^T = 2 Gamma_LL.  The r block is the Williamson normal
+  // form left by the previous cut (diagonal), so in the order (x_r, p_r, x_a,
+  // p_a) the factor is [[sqrt(Dd), 0], [c^T Dd^-1/2, chol(h)]] with
+  // h = g - c^T Dd^-1 c (2 x 2); its rows are stored back in the xxpp order
+  // (any factor serves: the Williamson form only needs L L^T = 2 Gamma_LL).
+  // A general Cholesky is used when the r block is not diagonal to 1e-13.
+  const int nr = n_prev;
+  auto orow = [&](int i) { return i < nr ? i : (i < 2 * nr ? nL + (i - nr) : (i == 2 * nr ? nL - 1 : 2 * nL - 1)); };
+  double dmx = 0.0;
+  for (int i = tid; i < 2 * nr; i += nt) dmx = fmax(dmx, fabs(G[(long)orow(i) * ld + orow(i)]));
+  dmx = wg_max(dmx, red);
+  if (tid == 0) bad = 0;
+  wg_sync();
+  for (long e = tid; e < 4L * nr * nr; e += nt) {
+    const int i = (int)(e / (2 * nr)), j = (int)(e % (2 * nr));
+    if (i != j && fabs(G[(long)orow(i) * ld + orow(j)]) > 1e-13 * dmx) bad = 1;
+  }
+  wg_sync();
+  const bool structured = (bad == 0);
+  wg_sync();
+  if (structured) {
+    for (long e = tid; e < (long)N2 * N2; e += nt) Lm[(long)(e / N2) * ld + (e % N2)] = 0.0;
+    wg_sync();
+    const int xa = nL - 1, pa = 2 * nL - 1;
+    double h00 = 0.0, h01 = 0.0, h11 = 0.0;
+    for (int i = tid; i < 2 * nr; i += nt) {
+      const int o = orow(i);
+      const double dd = 2.0 * G[(long)o * ld + o];
+      const double c0 = 2.0 * G[(long)o * ld + xa], c1 = 2.0 * G[(long)o * ld + pa];
+      if (dd > 0.0) {
+        const double sd = sqrt(dd);
+        Lm[(long)o * ld + i] = sd;
+        Lm[(long)xa * ld + i] = c0 / sd;
+        Lm[(long)pa * ld + i] = c1 / sd;
+        h00 += c0 * c0 / dd;
+        h01 += c0 * c1 / dd;
+        h11 += c1 * c1 / dd;
+      } else {
+        bad = 2;
+      }
+    }
+    h00 = 2.0 * G[(long)xa * ld + xa] - wg_sum(h00, red);
+    h01 = 2.0 * G[(long)xa * ld + pa] - wg_sum(h01, red);
+    h11 = 2.0 * G[(long)pa * ld + pa] - wg_sum(h11, red);
     if (tid == 0) {
-      double dj = P[pk(j, j)];
-      bad = !(dj > 0.0);
-      P[pk(j, j)] = dj > 0.0 ? sqrt(dj) : 1.0;
+      const double s00 = h00 > 0.0 ? sqrt(h00) : 0.0;
+      const double s10 = s00 > 0.0 ? h01 / s00 : 0.0;
+      const double r11 = h11 - s10 * s10;
+      if (!(s00 > 0.0) || !(r11 > 0.0)) bad = 2;
+      Lm[(long)xa * ld + 2 * nr] = s00;
+      Lm[(long)pa * ld + 2 * nr] = s10;
+      Lm[(long)pa * ld + 2 * nr + 1] = r11 > 0.0 ? sqrt(r11) : 0.0;
     }
     wg_sync();
-    if (bad) {
+    if (bad == 2) {
       if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_NOT_PD);
       return;
     }
-    const double piv = P[pk(j, j)];
-    for (int i = j + 1 + tid; i < N2; i += nt) P[pk(i, j)] /= piv;
-    wg_sync();
-    const int rem = N2 - j - 1;
-    const long ntri = (long)rem * (rem + 1) / 2;
-    for (long e = tid; e < ntri; e += nt) {
-      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-      while ((long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      while ((long)ii * (ii + 1) / 2 > e) --ii;
-      int kk = (int)(e - (long)ii * (ii + 1) / 2);
-      int i = j + 1 + ii, k = j + 1 + kk;
-      P[pk(i, k)] -= P[pk(i, j)] * P[pk(k, j)];
+  } else {
+    // Cholesky (right looking, packed lower triangle).
+    for (int j = 0; j < N2; ++j) {
+      if (tid == 0) {
+        double dj = P[pk(j, j)];
+        bad = !(dj > 0.0);
+        P[pk(j, j)] = dj > 0.0 ? sqrt(dj) : 1.0;
+      }
+      wg_sync();
+      if (bad) {
+        if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_NOT_PD);
+        return;
+      }
+      const double piv = P[pk(j, j)];
+      for (int i = j + 1 + tid; i < N2; i += nt) P[pk(i, j)] /= piv;
+      wg_sync();
+      const int rem = N2 - j - 1;
+      const long ntri = (long)rem * (rem + 1) / 2;
+      for (long e = tid; e < ntri; e += nt) {
+        int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+        while ((long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
+        while ((long)ii * (ii + 1) / 2 > e) --ii;
+        int kk = (int)(e - (long)ii * (ii + 1) / 2);
+        int i = j + 1 + ii, k = j + 1 + kk;
+        P[pk(i, k)] -= P[pk(i, j)] * P[pk(k, j)];
+      }
+      wg_sync();
     }
-    wg_sync();
+    // L (full, row-major)
+    for (long e = tid; e < (long)N2 * N2; e += nt) {
+      int i = (int)(e / N2), j = (int)(e % N2);
+      Lm[(long)i * ld + j] = j <= i ? P[pk(i, j)] : 0.0;
+    }
   }
-  // L (full, row-major) and W = Omega L: W_k = L_{k+nL} (k < nL), -L_{k-nL} (k >= nL).
-  for (long e = tid; e < (long)N2 * N2; e += nt) {
-    int i = (int)(e / N2), j = (int)(e % N2);
-    Lm[(long)i * ld + j] = j <= i ? P[pk(i, j)] : 0.0;
-  }
+  // W = Omega L: W_k = L_{k+nL} (k < nL), -L_{k-nL} (k >= nL).
   wg_sync();
   for (long e = tid; e < (long)N2 * N2; e += nt) {
     int k = (int)(e / N2), j = (int)(e % N2);
@@ -401,14 +461,28 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   const double bound = 2.0 * tm + 1e-300;
   const double tiny = 2.2e-16 * bound + 1e-300;
   const int n = nL;
-  for (int q = tid; q < n; q += nt) {
-    double lo = 0.0, hi = bound;
-    for (int it = 0; it < 48; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (sturm_below(tL, N2, mid) <= N2 - 1 - q) lo = mid;
-      else hi = mid;
+  // 8-section: the 8 lanes of a group test 8 interior points of the interval
+  // at once (the Sturm count is monotone in x), so each round shrinks it 9x
+  {
+    const int grpi = tid >> 3, gl = tid & 7, ngrp = nt >> 3;
+    const int sh = (threadIdx.x & 63) & ~7;  // first lane of this group in the wave
+    for (int q0 = 0; q0 < n; q0 += ngrp) {
+      const int q = q0 + grpi;
+      const bool live = q < n;
+      double lo = 0.0, hi = bound;
+      for (int it = 0; it < 17; ++it) {
+        const double x = lo + (hi - lo) * (double)(gl + 1) / 9.0;
+        const bool below = live && sturm_below(tL, N2, x) <= N2 - 1 - q;
+        const unsigned long long bal = __ballot(below);
+        const int j = __popcll((bal >> sh) & 0xFFull);   // points at or below the target
+        const double xl = __shfl(x, sh + (j > 0 ? j - 1 : 0), 64);
+        const double xh = __shfl(x, sh + (j < 8 ? j : 7), 64);
+        const double nlo = j > 0 ? xl : lo, nhi = j < 8 ? xh : hi;
+        lo = nlo;
+        hi = nhi;
+      }
+      if (live && gl == 0) sig0[q] = 0.5 * (lo + hi);
     }
-    sig0[q] = 0.5 * (lo + hi);
   }
   wg_sync();
   // clusters of shifts closer than 1e-5 bound share one thread, which
