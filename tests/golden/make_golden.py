@@ -7,6 +7,11 @@ workload with, for the oracle's normalised MPS:
   * exact single-mode photon-number marginals P_m(p).
 
     python tests/golden/make_golden.py c3
+
+For workloads too large for the oracle's full build (C5, M=1024), the
+Gaussian SVD chain alone (n_e and Lambda per cut):
+
+    python tests/golden/make_golden.py gsvd:c5
 """
 import json
 import os
@@ -19,7 +24,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import numpy as np  # noqa: E402
 
 import workloads  # noqa: E402
-from oracle import build, mps  # noqa: E402
+from oracle import build, gaussian, mps  # noqa: E402
 
 
 def patterns(M, d, n, seed):
@@ -54,6 +59,20 @@ def main(name):
     print(f"{name}: oracle build {t1 - t0:.1f}s, total {time.time() - t0:.1f}s")
 
 
+def main_gsvd(name):
+    w = workloads.workload(name)
+    t0 = time.time()
+    r = gaussian.gsvd(w.gamma)
+    res = dict(workload=name, M=w.M, oracle_gsvd_s=time.time() - t0,
+               n_e=[len(c.Lam) for c in r.cuts], lam=[list(map(float, c.Lam)) for c in r.cuts])
+    with open(os.path.join(HERE, f"{name}_gsvd_oracle.json"), "w") as f:
+        json.dump(res, f)
+    print(f"{name}: oracle Gaussian SVD chain {time.time() - t0:.1f}s")
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:] or ["c3"]:
-        main(n)
+        if n.startswith("gsvd:"):
+            main_gsvd(n[5:])
+        else:
+            main(n)
