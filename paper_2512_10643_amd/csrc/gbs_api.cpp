@@ -318,12 +318,14 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
       cplx64* vsub;
       int* active;
       double* dmx;
+      int* vid;
       HIP_CHECK_RET(dalloc(tmp, &vsub, (size_t)jacobi_blocked_ws_elems((int)eld, nb)));
+      HIP_CHECK_RET(dalloc(tmp, &vid, (size_t)jacobi_blocked_ws_elems((int)eld, nb) / 1024 + 1));
       HIP_CHECK_RET(dalloc(tmp, &active, nb));
       HIP_CHECK_RET(dalloc(tmp, &dmx, nb));
       int sweeps = 0;
       HIP_CHECK_RET(jacobi_herm_blocked(st, E64 + off, EVt + off, W64 + eld, edim_dev + 1, (int)eld, eld, eld * eld, nb,
-                                        jerr, EV64 + off, vsub, active, dmx, 60, &sweeps));
+                                        jerr, EV64 + off, vsub, active, vid, dmx, 60, &sweeps));
       if (sweeps < 0) return fail(GBS_E_INTERNAL, deverr_msg(GBS_DEVERR_JACOBI_BOND));
       h->eig_sweeps = sweeps;
     }

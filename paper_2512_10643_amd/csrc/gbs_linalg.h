@@ -24,11 +24,12 @@ hipError_t jacobi_herm(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const
 
 // Same problem by blocked Jacobi (32 x 32 subproblems per round, see the
 // kernels): workspace Vs of jacobi_blocked_ws_elems(nmax, batch) complex,
-// `active` (batch ints) and `dm` (batch doubles).  Runs sweeps until a whole
+// `active` (batch ints), `vid` (jacobi_blocked_ws_elems / 1024 ints) and `dm`
+// (batch doubles).  Runs sweeps until a whole
 // sweep needs no rotation or max_sweeps is reached; synchronises `st` once per
 // sweep.  *sweeps_done receives the number of sweeps run, or -1 when the
 // last allowed sweep still rotated (not converged).
 long jacobi_blocked_ws_elems(int nmax, int batch);
 hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax,
                                long ld, long sA, int batch, int* err, cplx64* Vout, cplx64* Vs, int* active,
-                               double* dm, int max_sweeps, int* sweeps_done);
+                               int* vid, double* dm, int max_sweeps, int* sweeps_done);

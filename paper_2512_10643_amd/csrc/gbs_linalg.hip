@@ -631,7 +631,8 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const cplx64* __restrict__
 __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
                                                       long ld, long sA, int npb, int round,
                                                       const double* __restrict__ dm, double tol, int inner_sweeps,
-                                                      cplx64* __restrict__ Vs, int* __restrict__ active) {
+                                                      cplx64* __restrict__ Vs, int* __restrict__ active,
+                                                      int* __restrict__ vid) {
   const int pr = blockIdx.x, b = blockIdx.y, lane = threadIdx.x;
   const int n = dims ? dims[b] : (int)ld;
   const int npairs = npb / 2;
@@ -655,6 +656,22 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
   // entries below ~8 ulp of the largest diagonal entry are at the rounding
   // level of the tile products that update A between rounds
   const double floor_abs = fmax(1.8e-15 * dm[b], 1e-300);
+  // a subproblem that needs no rotation leaves V = I: flag it, so the update
+  // passes skip this pair
+  {
+    bool need = false;
+    for (int e = lane; e < kBP * kBP; e += 64) {
+      const int i = e / kBP, j = e % kBP;
+      if (j <= i || idx[i] < 0 || idx[j] < 0) continue;
+      const double ab = sqrt(cabs2(S[i][j]));
+      need = need || (ab > tol * sqrt(fabs(S[i][i].re * S[j][j].re)) && ab > floor_abs);
+    }
+    if (__ballot(need) == 0ull) {
+      if (lane == 0) vid[(long)b * npairs + pr] = 1;
+      return;
+    }
+    if (lane == 0) vid[(long)b * npairs + pr] = 0;
+  }
   bool converged = false;
   for (int sweep = 0; sweep < inner_sweeps && !converged; ++sweep) {
     if (lane == 0) anyrot = 0;
@@ -740,7 +757,8 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
 template <bool ROWS>
 __global__ __launch_bounds__(256) void bj_pass_kernel(cplx64* __restrict__ A, cplx64* __restrict__ Wv,
                                                       const int* __restrict__ dims, long ld, long sA, int npb,
-                                                      int round, const cplx64* __restrict__ Vs, int nch) {
+                                                      int round, const cplx64* __restrict__ Vs,
+                                                      const int* __restrict__ vid, int nch) {
   typedef mma_traits<cplx64> T;
   const int P = blockIdx.x, y = blockIdx.y, b = blockIdx.z;
   const int n = dims ? dims[b] : (int)ld;
@@ -751,6 +769,7 @@ __global__ __launch_bounds__(256) void bj_pass_kernel(cplx64* __restrict__ A, cp
   const bool onW = !ROWS && y >= nch;
   const int c0 = kBP * (onW ? y - nch : y);
   if (c0 >= n) return;
+  if (vid[(long)b * npairs + P]) return;  // V_P = I
   if (tid == 0) bj_pair_idx(npb, round, P, n, ip);
   __syncthreads();
   if (ip[0] < 0 && ip[kBJ] < 0) return;  // pair entirely beyond n (uniform)
@@ -807,7 +826,7 @@ long jacobi_blocked_ws_elems(int nmax, int batch) {
 
 hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* w, const int* dims, int nmax,
                                long ld, long sA, int batch, int* err, cplx64* Vout, cplx64* Vs, int* active,
-                               double* dm, int max_sweeps, int* sweeps_done) {
+                               int* vid, double* dm, int max_sweeps, int* sweeps_done) {
   if (batch <= 0 || nmax <= 0) return hipSuccess;
   const int nb = (nmax + kBJ - 1) / kBJ;
   const int npb = std::max(2, nb + (nb & 1));
@@ -822,12 +841,12 @@ hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* 
     if (e != hipSuccess) return e;
     for (int r = 0; r < npb - 1; ++r) {
       hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(64), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
-                         4, Vs, active);
+                         4, Vs, active, vid);
       const int nch = (nmax + kBP - 1) / kBP;
       hipLaunchKernelGGL(bj_pass_kernel<true>, dim3(npairs, nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld, sA,
-                         npb, r, Vs, nch);
+                         npb, r, Vs, vid, nch);
       hipLaunchKernelGGL(bj_pass_kernel<false>, dim3(npairs, 2 * nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld,
-                         sA, npb, r, Vs, nch);
+                         sA, npb, r, Vs, vid, nch);
     }
     e = hipMemcpyAsync(act.data(), active, batch * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
