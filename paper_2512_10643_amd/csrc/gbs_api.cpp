@@ -285,6 +285,10 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   HIP_CHECK_RET(dalloc(tmp, &Ec, (size_t)2 * eld * eld));
   HIP_CHECK_RET(dalloc(tmp, &Tb, (size_t)eld * d * eld));
   std::vector<int> edim(M + 1, 1);
+  // split-K workspace for the chain products (few output tiles, K = d chi)
+  const long gws_elems = 8 * eld * eld;
+  C* gws;
+  HIP_CHECK_RET(dalloc(tmp, &gws, (size_t)gws_elems));
   {
     C one = cone<C>();
     HIP_CHECK_RET(hipMemcpyAsync(Ec, &one, sizeof(C), hipMemcpyHostToDevice, st));
@@ -298,7 +302,7 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
                              (long)d * b, b, d));
       // E_{m-1} = Tb (a x d b) * A^m^H, stored with leading dimension eld
       HIP_CHECK_RET(zgemm<C>(st, a, a, d * b, cone<C>(), Tb, (long)d * b, 0, 0, A[m], (long)d * b, 0, 2, czero<C>(),
-                             Eout, eld, 0, 1));
+                             Eout, eld, 0, 1, gws, gws_elems));
       HIP_CHECK_RET(convert<cplx64, C>(st, E64 + (long)(m - 1) * eld * eld, Eout, (long)a * eld));
       edim[m - 1] = a;
       cur = 1 - cur;
@@ -429,7 +433,8 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
       // X = L_{m-1} B (a x d b), then L_m = B^H X over the (a, p) rows
       HIP_CHECK_RET(zgemm<C>(st, a, d * b, a, one, Lin, eld, 0, 0, B64, (long)d * b, 0, 0, czero<C>(), X64,
                              (long)d * b, 0, 1));
-      HIP_CHECK_RET(zgemm<C>(st, b, b, a * d, one, B64, b, 0, 2, X64, b, 0, 0, czero<C>(), Lout, eld, 0, 1));
+      HIP_CHECK_RET(zgemm<C>(st, b, b, a * d, one, B64, b, 0, 2, X64, b, 0, 0, czero<C>(), Lout, eld, 0, 1, gws,
+                             gws_elems));
       cur = 1 - cur;
     }
     nrm2_dev = (const double*)(Lb + (long)cur * eld * eld);  // real part of the 1 x 1 L_M
@@ -754,6 +759,9 @@ int overlap_impl(gbs_mps_s* h1, gbs_mps_s* h2, hipStream_t st, int prec, double*
   HIP_CHECK_RET(dalloc(tmp, &X, (size_t)rmax * d * rmax));
   HIP_CHECK_RET(dalloc(tmp, &A1, (size_t)rmax * d * rmax));
   HIP_CHECK_RET(dalloc(tmp, &A2, (size_t)rmax * d * rmax));
+  const long gws_elems = 8L * rmax * rmax;
+  C* gws;
+  HIP_CHECK_RET(dalloc(tmp, &gws, (size_t)gws_elems));
   auto site = [&](gbs_mps_s* h, int m, C* dst) -> hipError_t {
     long n = (long)h->bond[m - 1] * d * h->bond[m];
     if (h->esz == sizeof(cplx64)) return convert<C, cplx64>(st, dst, (cplx64*)h->tens + h->toff[m], n);
@@ -763,8 +771,9 @@ int overlap_impl(gbs_mps_s* h1, gbs_mps_s* h2, hipStream_t st, int prec, double*
                   long ldc) -> hipError_t {
     if (prec == GBS_BF16X3)
       return zgemm_bf16x3(st, Mr, Nc, K, cone<cplx32>(), (const cplx32*)A, lda, 0, opA, (const cplx32*)B, ldb, 0, 0,
-                          czero<cplx32>(), (cplx32*)Cm, ldc, 0, 1);
-    return zgemm<C>(st, Mr, Nc, K, cone<C>(), A, lda, 0, opA, B, ldb, 0, 0, czero<C>(), Cm, ldc, 0, 1);
+                          czero<cplx32>(), (cplx32*)Cm, ldc, 0, 1, (cplx32*)gws, gws_elems);
+    return zgemm<C>(st, Mr, Nc, K, cone<C>(), A, lda, 0, opA, B, ldb, 0, 0, czero<C>(), Cm, ldc, 0, 1, gws,
+                    gws_elems);
   };
   const C one = cone<C>();
   HIP_CHECK_RET(hipMemcpyAsync(E[0], &one, sizeof(C), hipMemcpyHostToDevice, st));

@@ -47,14 +47,16 @@ template <typename C>
 __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C alpha, const C* __restrict__ A,
                                                          long lda, long sA, int opA, const C* __restrict__ B,
                                                          long ldb, long sB, int opB, C beta, C* __restrict__ Cm,
-                                                         long ldc, long sC) {
+                                                         long ldc, long sC, int ksplit, C* __restrict__ part_out) {
   typedef mma_traits<C> T;
   typedef typename T::R R;
   typedef typename T::R4 R4;
   typedef typename T::V2 V2;
   // per wave: As[kGK][kGT] and Bs[kGK][kGT]; reused for the 4 partial tiles
   __shared__ V2 lds[4 * 2 * kGK * kGT];
-  const int bz = blockIdx.z;
+  // blockIdx.z = problem * ksplit + slice: a slice of K per workgroup when the
+  // output has too few tiles to fill the device (partials summed afterwards)
+  const int bz = blockIdx.z / ksplit, ks = blockIdx.z % ksplit;
   A += (long)bz * sA;
   B += (long)bz * sB;
   Cm += (long)bz * sC;
@@ -62,9 +64,11 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   V2* As = lds + w * 2 * kGK * kGT;
   V2* Bs = As + kGK * kGT;
-  // this wave's K range
-  const int kq = ((K + 4 * kGK - 1) / (4 * kGK)) * kGK;
-  const int kb = w * kq, ke = min(K, kb + kq);
+  // this wave's K range within the workgroup's slice
+  const int ksl = ((K + ksplit * kGK - 1) / (ksplit * kGK)) * kGK;
+  const int k_lo = ks * ksl, k_hi = min(K, k_lo + ksl);
+  const int kq = ((max(0, k_hi - k_lo) + 4 * kGK - 1) / (4 * kGK)) * kGK;
+  const int kb = k_lo + w * kq, ke = min(k_hi, kb + kq);
   R4 cre[2][2], cim[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -182,25 +186,60 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
       sr += z.x;
       si += z.y;
     }
+    if (ksplit > 1) {  // partial of slice ks, dense M x N per (slice, problem)
+      const int nbatch = gridDim.z / ksplit;
+      part_out[(((long)ks * nbatch + bz) * M + gi) * N + gj] = cmake<C>(sr, si);
+      continue;
+    }
     C v = cmul(alpha, cmake<C>(sr, si));
     if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, Cm[(long)gi * ldc + gj]));
     Cm[(long)gi * ldc + gj] = v;
   }
 }
 
+// Sum of the K-slice partials in slice order, then alpha / beta.
+template <typename C>
+__global__ void zgemm_reduce_kernel(int M, int N, int batch, int ksplit, C alpha, C beta, const C* __restrict__ part,
+                                    C* __restrict__ Cm, long ldc, long sC) {
+  typedef typename real_of<C>::type R;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long per = (long)M * N;
+  if (e >= per * batch) return;
+  const int bz = (int)(e / per);
+  const long r = e % per;
+  const int gi = (int)(r / N), gj = (int)(r % N);
+  C acc = cmake<C>((R)0, (R)0);
+  for (int ks = 0; ks < ksplit; ++ks) acc = cadd(acc, part[((long)ks * batch + bz) * per + r]);
+  C v = cmul(alpha, acc);
+  C* c = Cm + (long)bz * sC + (long)gi * ldc + gj;
+  if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, *c));
+  *c = v;
+}
+
 template <typename C>
 hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long lda, long sA, int opA, const C* B,
-                 long ldb, long sB, int opB, C beta, C* Cm, long ldc, long sC, int batch) {
+                 long ldb, long sB, int opB, C beta, C* Cm, long ldc, long sC, int batch, C* ws, long ws_elems) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch);
+  const long tiles = (long)((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT) * batch;
+  int ksplit = 1;
+  // a long K over few output tiles: slice K across workgroups (with a workspace)
+  while (ws && tiles * ksplit < 256 && K / (2 * ksplit) >= 4 * kGK * 4 &&
+         (long)(2 * ksplit) * batch * M * N <= ws_elems)
+    ksplit *= 2;
+  dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch * ksplit);
   hipLaunchKernelGGL(zgemm_mfma_kernel<C>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB,
-                     beta, Cm, ldc, sC);
+                     beta, Cm, ldc, sC, ksplit, ws);
+  if (ksplit > 1) {
+    const long n = (long)batch * M * N;
+    hipLaunchKernelGGL(zgemm_reduce_kernel<C>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, N, batch,
+                       ksplit, alpha, beta, (const C*)ws, Cm, ldc, sC);
+  }
   return hipGetLastError();
 }
 template hipError_t zgemm<cplx64>(hipStream_t, int, int, int, cplx64, const cplx64*, long, long, int, const cplx64*,
-                                  long, long, int, cplx64, cplx64*, long, long, int);
+                                  long, long, int, cplx64, cplx64*, long, long, int, cplx64*, long);
 template hipError_t zgemm<cplx32>(hipStream_t, int, int, int, cplx32, const cplx32*, long, long, int, const cplx32*,
-                                  long, long, int, cplx32, cplx32*, long, long, int);
+                                  long, long, int, cplx32, cplx32*, long, long, int, cplx32*, long);
 
 // ---------------------------------------------------------------------------
 // Complex GEMM on FP32 data by split-BF16x3 products on the BF16 matrix cores
@@ -229,9 +268,10 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
 __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, cplx32 alpha,
                                                            const cplx32* __restrict__ A, long lda, long sA, int opA,
                                                            const cplx32* __restrict__ B, long ldb, long sB, int opB,
-                                                           cplx32 beta, cplx32* __restrict__ Cm, long ldc, long sC) {
+                                                           cplx32 beta, cplx32* __restrict__ Cm, long ldc, long sC,
+                                                           int ksplit, cplx32* __restrict__ part_out) {
   __shared__ float2 lds[4 * 2 * kXK * kGT];
-  const int bz = blockIdx.z;
+  const int bz = blockIdx.z / ksplit, ks = blockIdx.z % ksplit;
   A += (long)bz * sA;
   B += (long)bz * sB;
   Cm += (long)bz * sC;
@@ -239,8 +279,10 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   float2* As = lds + w * 2 * kXK * kGT;
   float2* Bs = As + kXK * kGT;
-  const int kq = ((K + 4 * kXK - 1) / (4 * kXK)) * kXK;
-  const int kb = w * kq, ke = min(K, kb + kq);
+  const int ksl = ((K + ksplit * kXK - 1) / (ksplit * kXK)) * kXK;
+  const int k_lo = ks * ksl, k_hi = min(K, k_lo + ksl);
+  const int kq = ((max(0, k_hi - k_lo) + 4 * kXK - 1) / (4 * kXK)) * kXK;
+  const int kb = k_lo + w * kq, ke = min(k_hi, kb + kq);
   f32x4 cre[2][2], cim[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -362,6 +404,11 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
       sr += z.x;
       si += z.y;
     }
+    if (ksplit > 1) {
+      const int nbatch = gridDim.z / ksplit;
+      part_out[(((long)ks * nbatch + bz) * M + gi) * N + gj] = cmake<cplx32>(sr, si);
+      continue;
+    }
     cplx32 v = cmul(alpha, cmake<cplx32>(sr, si));
     if (beta.re != 0.f || beta.im != 0.f) v = cadd(v, cmul(beta, Cm[(long)gi * ldc + gj]));
     Cm[(long)gi * ldc + gj] = v;
@@ -370,11 +417,21 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
 
 hipError_t zgemm_bf16x3(hipStream_t st, int M, int N, int K, cplx32 alpha, const cplx32* A, long lda, long sA,
                         int opA, const cplx32* B, long ldb, long sB, int opB, cplx32 beta, cplx32* Cm, long ldc,
-                        long sC, int batch) {
+                        long sC, int batch, cplx32* ws, long ws_elems) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch);
+  const long tiles = (long)((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT) * batch;
+  int ksplit = 1;
+  while (ws && tiles * ksplit < 256 && K / (2 * ksplit) >= 4 * kXK * 2 &&
+         (long)(2 * ksplit) * batch * M * N <= ws_elems)
+    ksplit *= 2;
+  dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch * ksplit);
   hipLaunchKernelGGL(zgemm_bf16x3_kernel, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB,
-                     beta, Cm, ldc, sC);
+                     beta, Cm, ldc, sC, ksplit, ws);
+  if (ksplit > 1) {
+    const long n = (long)batch * M * N;
+    hipLaunchKernelGGL(zgemm_reduce_kernel<cplx32>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, N, batch,
+                       ksplit, alpha, beta, (const cplx32*)ws, Cm, ldc, sC);
+  }
   return hipGetLastError();
 }
 
