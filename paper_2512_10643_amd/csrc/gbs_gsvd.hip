@@ -458,6 +458,12 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   double tm = 0.0;
   for (int i = tid; i < N2 - 1; i += nt) tm = fmax(tm, fabs(tL[i]));
   tm = wg_max(tm, red);
+  // off-diagonal entries at the rounding level of the reduction split G into
+  // independent blocks: set them to zero, or a tiny coupling mixes the null
+  // vectors of blocks that share an eigenvalue (degenerate D) in the solves
+  for (int i = tid; i < N2 - 1; i += nt)
+    if (fabs(tL[i]) <= 2.2e-16 * N2 * tm) tL[i] = 0.0;
+  wg_sync();
   const double bound = 2.0 * tm + 1e-300;
   const double tiny = 2.2e-16 * bound + 1e-300;
   const int n = nL;
@@ -520,6 +526,47 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     }
   }
   wg_sync();
+  // Check Z^T Z = 1; if the solves left a vector mixed (close eigenvalues in
+  // different blocks), re-orthogonalise all of them in order (modified
+  // Gram-Schmidt against the accurate earlier vectors restores it).
+  {
+    double* Gz = a.ws_S;  // n x n
+    wg_dgemm(n, n, N2, 1.0, Z, n, true, Z, n, false, 0.0, Gz, ld, nullptr);
+    wg_sync();
+    double dev = 0.0;
+    for (long e = tid; e < (long)n * n; e += nt) {
+      const int i = (int)(e / n), j = (int)(e % n);
+      dev = fmax(dev, fabs(Gz[(long)i * ld + j] - (i == j ? 1.0 : 0.0)));
+    }
+    dev = wg_max(dev, red);
+    if (dev > 1e-10) {
+      for (int q = 0; q < n; ++q) {
+        for (int rr = tid; rr < q; rr += nt) {
+          double c = 0.0;
+          for (int i = 0; i < N2; ++i) c += Z[(long)i * n + rr] * Z[(long)i * n + q];
+          part[rr] = c;
+        }
+        wg_sync();
+        double nn = 0.0;
+        for (int i = tid; i < N2; i += nt) {
+          double z = Z[(long)i * n + q];
+          for (int rr = 0; rr < q; ++rr) z -= part[rr] * Z[(long)i * n + rr];
+          Z[(long)i * n + q] = z;
+          nn += z * z;
+        }
+        nn = wg_sum(nn, red);
+        const double inv = 1.0 / sqrt(nn);
+        for (int i = tid; i < N2; i += nt) Z[(long)i * n + q] *= inv;
+        wg_sync();
+        if (tid == 0) {
+          double rq = 0.0;
+          for (int i = 0; i + 1 < N2; ++i) rq += 2.0 * tL[i] * Z[(long)i * n + q] * Z[(long)(i + 1) * n + q];
+          sigR[q] = fabs(rq);
+        }
+        wg_sync();
+      }
+    }
+  }
   // U = Q X_e with X_e column q = sqrt2 (even entries of z_q, signs + + - - ..),
   // kept in LDS (the packed A is no longer needed): column q at XU[q N2 + i].
   // Reflectors are applied last to first, each by all threads: G threads per

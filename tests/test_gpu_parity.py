@@ -122,7 +122,8 @@ def test_c2_fp32_fidelity(torch_cuda):
 
 # ---------------------------------------------------------- edge cases
 
-@pytest.mark.parametrize("case", ["single_mode", "two_mode_tmsv", "product", "d1", "chi1", "ragged"])
+@pytest.mark.parametrize("case", ["single_mode", "two_mode_tmsv", "product", "d1", "chi1", "ragged",
+                                  "degenerate_frozen"])
 def test_edge_cases(torch_cuda, case):
     _say(f"case: edge {case}")
     if case == "single_mode":
@@ -137,9 +138,14 @@ def test_edge_cases(torch_cuda, case):
     elif case == "chi1":
         w = W.custom(5, 4, 1, (0.3, 0.7), "haar", 4)
         rr, u, d, chi = w.r, w.U, 4, 1
-    else:  # ragged: odd sizes spanning several tiles
+    elif case == "ragged":  # odd sizes spanning several tiles
         w = W.custom(11, 5, 37, (0.2, 0.9), ("brick", 5), 5)
         rr, u, d, chi = w.r, w.U, 5, 37
+    else:  # degenerate_frozen: a cut whose left block holds two exactly unentangled
+        # modes in separate blocks of the reduced tridiagonal form (request 468 of the
+        # serving mix: M=63, d=8, chi=32, brick-wall)
+        w = W.serving_requests(469)[468]["workload"]
+        rr, u, d, chi = w.r, w.U, w.d, w.chi
     g = W.gamma_of_circuit(rr, np.asarray(u, dtype=np.complex128))
     o = obuild.build_mps(g, d, chi)
     h = gpu_build(torch_cuda, g, d, chi, precision="fp64")
