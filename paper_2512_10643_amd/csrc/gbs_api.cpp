@@ -408,38 +408,52 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   for (int m = 1; m <= M; ++m) ptrs[m - 1] = out + h->toff[m];
   HIP_CHECK_RET(dalloc(h->keep, &h->site_ptrs, M));
   HIP_CHECK_RET(hipMemcpyAsync(h->site_ptrs, ptrs.data(), M * sizeof(void*), hipMemcpyHostToDevice, st));
-  cplx64* vbuf;
   double* nrm;
-  HIP_CHECK_RET(dalloc(tmp, &vbuf, 2 * GBS_CHI_MAX));
   HIP_CHECK_RET(dalloc(tmp, &nrm, 1));
-  // Reduced-precision tensors are right-canonical only to their rounding
-  // level, and those deviations add up along the chain; their squared norm is
-  // therefore taken from the full FP64 transfer chain
+  // Vacuum amplitude z = <0..0|psi> = B^1[0, 0, :] ... B^M[:, 0, 0] (FP64
+  // chain of vector-matrix products), for the global phase.  Reduced-precision
+  // tensors are right-canonical only to their rounding level, and those
+  // deviations add up along the chain; their squared norm is therefore taken
+  // from the full FP64 transfer chain
   //   L_m = sum_p B^m[p]^H L_{m-1} B^m[p],  L_0 = 1,  norm^2 = L_M.
   const double* nrm2_dev = nullptr;
-  if (!std::is_same<CT, cplx64>::value) {
-    C *Lb, *B64, *X64;
+  C *vac, *Lb = nullptr, *B64 = nullptr, *X64 = nullptr;
+  C one = cone<C>();
+  HIP_CHECK_RET(dalloc(tmp, &vac, (size_t)2 * eld));
+  HIP_CHECK_RET(hipMemcpyAsync(vac, &one, sizeof(C), hipMemcpyHostToDevice, st));
+  const bool reduced = !std::is_same<CT, cplx64>::value;
+  if (reduced) {
     HIP_CHECK_RET(dalloc(tmp, &Lb, (size_t)2 * eld * eld));
     HIP_CHECK_RET(dalloc(tmp, &B64, (size_t)eld * d * eld + d));
     HIP_CHECK_RET(dalloc(tmp, &X64, (size_t)eld * d * eld + d));
-    C one = cone<C>();
     HIP_CHECK_RET(hipMemcpyAsync(Lb, &one, sizeof(C), hipMemcpyHostToDevice, st));
-    int cur = 0;
-    for (int m = 1; m <= M; ++m) {
-      const int a = r[m - 1], b = r[m];
+  }
+  int cur = 0;
+  for (int m = 1; m <= M; ++m) {
+    const int a = r[m - 1], b = r[m];
+    const C* Bs;
+    if (reduced) {
+      HIP_CHECK_RET(convert<cplx64, CT>(st, B64, out + h->toff[m], (long)a * d * b));
+      Bs = B64;
+    } else {
+      Bs = (const C*)(out + h->toff[m]);
+    }
+    // z chain: v (1 x a) * B[:, 0, :] (a x b, row stride d b)
+    HIP_CHECK_RET(zgemm<C>(st, 1, b, a, one, vac + (long)cur * eld, a, 0, 0, Bs, (long)d * b, 0, 0, czero<C>(),
+                           vac + (long)(1 - cur) * eld, b, 0, 1));
+    if (reduced) {
       C* Lin = Lb + (long)cur * eld * eld;
       C* Lout = Lb + (long)(1 - cur) * eld * eld;
-      HIP_CHECK_RET(convert<cplx64, CT>(st, B64, out + h->toff[m], (long)a * d * b));
       // X = L_{m-1} B (a x d b), then L_m = B^H X over the (a, p) rows
       HIP_CHECK_RET(zgemm<C>(st, a, d * b, a, one, Lin, eld, 0, 0, B64, (long)d * b, 0, 0, czero<C>(), X64,
                              (long)d * b, 0, 1));
       HIP_CHECK_RET(zgemm<C>(st, b, b, a * d, one, B64, b, 0, 2, X64, b, 0, 0, czero<C>(), Lout, eld, 0, 1, gws,
                              gws_elems));
-      cur = 1 - cur;
     }
-    nrm2_dev = (const double*)(Lb + (long)cur * eld * eld);  // real part of the 1 x 1 L_M
+    cur = 1 - cur;
   }
-  HIP_CHECK_RET(normalize_mps<CT>(st, (CT**)h->site_ptrs, h->bond_dev, M, d, vbuf, nrm2_dev, nrm));
+  if (reduced) nrm2_dev = (const double*)(Lb + (long)cur * eld * eld);  // real part of the 1 x 1 L_M
+  HIP_CHECK_RET(normalize_mps<CT>(st, out + h->toff[1], d * r[1], vac + (long)cur * eld, nrm2_dev, nrm));
   HIP_CHECK_RET(hipMemcpyAsync(&h->norm_raw, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK_RET(hipStreamSynchronize(st));
   return GBS_OK;

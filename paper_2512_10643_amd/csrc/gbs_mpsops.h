@@ -10,12 +10,13 @@ hipError_t scaled_copy(hipStream_t st, CD* dst, long ld_dst, const cplx64* src, 
 // x[i][p][j] *= sqrt(wcol[j]) / sqrt(wrow[i])  (NULL -> 1)
 template <typename C>
 hipError_t gauge_scale(hipStream_t st, C* x, int rows, int d, int cols, const double* wrow, const double* wcol);
-// Scales site 1 so that the state has unit norm and a real positive vacuum
-// amplitude.  nrm2_in: the squared norm (device scalar), or NULL to take it
-// from site 1 alone (exact when sites 2..M are right-canonical).
+// Scales site 1 (n1 elements) so that the state has unit norm and a real
+// positive vacuum amplitude.  vac: <0..0|psi> before scaling (device);
+// nrm2_in: the squared norm (device scalar), or NULL to take it from site 1
+// alone (exact when sites 2..M are right-canonical).
 template <typename C>
-hipError_t normalize_mps(hipStream_t st, C** sites_dev, const int* bond_dev, int M, int d, cplx64* vbuf,
-                         const double* nrm2_in, double* out_norm);
+hipError_t normalize_mps(hipStream_t st, C* site1, int n1, const cplx64* vac, const double* nrm2_in,
+                         double* out_norm);
 template <typename C>
 hipError_t launch_amplitude(hipStream_t st, C* const* sites, const int* bond, int M, int d, const int32_t* pat,
                             int64_t B, double* out, int* bad, int maxbond);

@@ -82,19 +82,18 @@ hipError_t gauge_scale(hipStream_t st, C* x, int rows, int d, int cols, const do
 template hipError_t gauge_scale<cplx32>(hipStream_t, cplx32*, int, int, int, const double*, const double*);
 template hipError_t gauge_scale<cplx64>(hipStream_t, cplx64*, int, int, int, const double*, const double*);
 
-// Normalise to unit norm and make the vacuum amplitude real > 0.  One
-// workgroup; the MPS is right-canonical so the norm sits in site 1.
+// Normalise to unit norm and make the vacuum amplitude real > 0: site 1 is
+// multiplied by conj(z) / |z| / norm, with z = <0..0|psi> (vac, computed by
+// the caller) and norm^2 = *nrm2_in, or the squared norm of site 1 when
+// nrm2_in is NULL (exact when sites 2..M are right-canonical).  One workgroup.
 template <typename C>
-__global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* bond, int M, int d, cplx64* vbuf,
-                                                          const double* nrm2_in, double* out_norm) {
+__global__ __launch_bounds__(1024) void normalize_kernel(C* b1, int n1, const cplx64* vac, const double* nrm2_in,
+                                                          double* out_norm) {
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double red[64];
   __shared__ double s_re, s_im;
-  C* b1 = sites[0];
-  const int r1 = bond[1];
-  // squared norm of site 1 (1 x d x r1)
   double part = 0.0;
-  for (int e = tid; e < d * r1; e += nt) {
+  for (int e = tid; e < n1; e += nt) {
     C v = b1[e];
     part += (double)v.re * v.re + (double)v.im * v.im;
   }
@@ -102,39 +101,14 @@ __global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* b
   if ((tid & 63) == 0) red[tid >> 6] = part;
   __syncthreads();
   if (tid == 0) {
-    double s = 0.0;
-    for (int i = 0; i < (nt + 63) / 64; ++i) s += red[i];
-    red[40] = s;
-  }
-  __syncthreads();
-  const double nrm2 = nrm2_in ? *nrm2_in : red[40];
-  // vacuum chain: v = B1[0, :], v <- v B^m[:, 0, :]
-  cplx64* v = vbuf;
-  cplx64* w = vbuf + GBS_CHI_MAX;
-  for (int j = tid; j < r1; j += nt) v[j] = cmake<cplx64>((double)b1[j].re, (double)b1[j].im);
-  __syncthreads();
-  for (int m = 2; m <= M; ++m) {
-    const int rl = bond[m - 1], rr = bond[m];
-    const C* bm = sites[m - 1];
-    for (int j = tid; j < rr; j += nt) {
-      double ar = 0.0, ai = 0.0;
-      for (int i = 0; i < rl; ++i) {
-        C t = bm[(long)i * d * rr + j];  // p = 0
-        ar += v[i].re * t.re - v[i].im * t.im;
-        ai += v[i].re * t.im + v[i].im * t.re;
-      }
-      w[j] = cmake<cplx64>(ar, ai);
-    }
-    __syncthreads();
-    for (int j = tid; j < rr; j += nt) v[j] = w[j];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    double zr = v[0].re, zi = v[0].im;
-    double az = sqrt(zr * zr + zi * zi);
-    double inv = 1.0 / sqrt(nrm2);
+    double sacc = 0.0;
+    for (int i = 0; i < (nt + 63) / 64; ++i) sacc += red[i];
+    const double nrm2 = nrm2_in ? *nrm2_in : sacc;
+    const double zr = vac->re, zi = vac->im;
+    const double az = sqrt(zr * zr + zi * zi);
+    const double inv = 1.0 / sqrt(nrm2);
     if (az > 0.0) {
-      s_re = zr / az * inv;   // multiply by conj(z)/|z| / norm
+      s_re = zr / az * inv;
       s_im = -zi / az * inv;
     } else {
       s_re = inv;
@@ -143,7 +117,7 @@ __global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* b
     *out_norm = sqrt(nrm2);
   }
   __syncthreads();
-  for (int e = tid; e < d * r1; e += nt) {
+  for (int e = tid; e < n1; e += nt) {
     C x = b1[e];
     double xr = x.re, xi = x.im;
     b1[e] = cmake<C>((typename real_of<C>::type)(xr * s_re - xi * s_im), (typename real_of<C>::type)(xr * s_im + xi * s_re));
@@ -151,14 +125,13 @@ __global__ __launch_bounds__(1024) void normalize_kernel(C** sites, const int* b
 }
 
 template <typename C>
-hipError_t normalize_mps(hipStream_t st, C** sites_dev, const int* bond_dev, int M, int d, cplx64* vbuf,
-                         const double* nrm2_in, double* out_norm) {
-  hipLaunchKernelGGL((normalize_kernel<C>), dim3(1), dim3(1024), 0, st, sites_dev, bond_dev, M, d, vbuf, nrm2_in,
-                     out_norm);
+hipError_t normalize_mps(hipStream_t st, C* site1, int n1, const cplx64* vac, const double* nrm2_in,
+                         double* out_norm) {
+  hipLaunchKernelGGL((normalize_kernel<C>), dim3(1), dim3(1024), 0, st, site1, n1, vac, nrm2_in, out_norm);
   return hipGetLastError();
 }
-template hipError_t normalize_mps<cplx32>(hipStream_t, cplx32**, const int*, int, int, cplx64*, const double*, double*);
-template hipError_t normalize_mps<cplx64>(hipStream_t, cplx64**, const int*, int, int, cplx64*, const double*, double*);
+template hipError_t normalize_mps<cplx32>(hipStream_t, cplx32*, int, const cplx64*, const double*, double*);
+template hipError_t normalize_mps<cplx64>(hipStream_t, cplx64*, int, const cplx64*, const double*, double*);
 
 // ---------------------------------------------------------------------------
 // Amplitudes: one workgroup per pattern, FP64 accumulation.
