@@ -87,27 +87,35 @@ class GaussianMPS:
         return d
 
     def export(self, m: int, what: str) -> np.ndarray:
+        """gbs_mps_export: tensor / raw (kept[m-1] x d x kept[m]) / Q / basis /
+        lambda / svals of site or cut m, copied to host memory."""
         inf = self.info()
-        d = self.d
+        d, chi = self.d, inf["chi"]
+        bond, ne = inf["bond"], inf["ne"]
         kind = _lib.EXPORT[what]
-        if what in ("tensor", "raw", "Q"):
-            cap = 16 * (4097 * 4097 * max(1, d))
-            buf = np.empty(cap // 16, dtype=np.complex128)
-        else:
-            buf = np.empty(4097 * 4097 * 2, dtype=np.int32 if what == "basis" else np.float64)
+        if what == "tensor":
+            buf = np.empty(max(1, bond[m - 1] * d * bond[m]), dtype=np.complex128)
+        elif what == "raw":
+            buf = np.empty(max(1, chi * d * chi), dtype=np.complex128)
+        elif what == "Q":
+            k = ne[m - 1] + 1 + ne[m]
+            buf = np.empty(max(1, k * k), dtype=np.complex128)
+        elif what == "basis":
+            buf = np.empty(max(1, chi * max(1, ne[m])), dtype=np.int32)
+        else:  # lambda, svals
+            buf = np.empty(max(1, chi, ne[m]), dtype=np.float64)
         written = ctypes.c_int64(0)
         check(lib().gbs_mps_export(self._h, m, kind, ctypes.c_void_p(buf.ctypes.data), buf.nbytes,
                                    ctypes.byref(written)))
-        n = written.value // buf.itemsize
-        arr = buf[:n].copy()
-        bond, ne = inf["bond"], inf["ne"]
+        arr = buf[:written.value // buf.itemsize].copy()
         if what == "tensor":
             return arr.reshape(bond[m - 1], d, bond[m])
         if what == "Q":
             k = ne[m - 1] + 1 + ne[m]
             return arr.reshape(k, k)
         if what == "raw":
-            return arr.reshape(-1, d, arr.size // max(1, d) // max(1, arr.size // max(1, d)) or 1) if False else arr
+            kl = len(self.export(m - 1, "basis"))
+            return arr.reshape(kl, d, arr.size // (kl * d))
         if what == "basis":
             return arr.reshape(-1, ne[m]) if ne[m] else np.zeros((1, 0), dtype=np.int32)
         return arr
