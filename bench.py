@@ -41,8 +41,27 @@ def sampler_traffic(avg_shots):
 
 
 def sampling_flops_per_shot(bonds, d):
-    """Algorithmic flops of one shot: sum_m 8 d chi_{m-1} chi_m (complex MACs)."""
+    """Flops of one shot over whole bonds: sum_m 8 d chi_{m-1} chi_m (complex MACs)."""
     return sum(8.0 * d * bonds[m - 1] * bonds[m] for m in range(1, len(bonds)))
+
+
+def sector_flops_per_shot(sectors, d, samples, pad=1):
+    """Flops of one shot when each bond splits into photon-parity sectors:
+    a shot whose bond m-1 lies in sector pi multiplies n_pi(m-1) rows by the
+    n_{pi ^ (p & 1)}(m) columns of every outcome p.  The sector of bond m-1 is
+    the parity of the photons drawn at sites 1..m-1, taken from `samples`
+    (device tensor).  pad=16 counts the padded tiles the kernel executes."""
+    import torch
+    M = samples.shape[1]
+    pre = torch.cumsum(samples, dim=1, dtype=torch.int64) - samples  # photons before site m
+    f1 = (pre % 2).double().mean(0).cpu().numpy()                    # fraction in sector 1
+    padn = lambda n: -(-int(n) // pad) * pad
+    tot = 0.0
+    for m in range(1, M + 1):
+        for pi, f in ((0, 1.0 - f1[m - 1]), (1, f1[m - 1])):
+            cols = sum(padn(sectors[m][pi ^ (p & 1)]) for p in range(d))
+            tot += f * 8.0 * padn(sectors[m - 1][pi]) * cols
+    return tot
 
 
 def cpu_baseline(workload, budget_s=20.0):
@@ -219,8 +238,9 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         inf = h.info()
+        sec = h.export(0, "sectors") if inf["sampler_layout"] == 2 else None
         h.free()
-        return dict(build_s=t1 - t0, sample_s=t2 - t1, sample_ev_ms=e0.elapsed_time(e1), info=inf)
+        return dict(build_s=t1 - t0, sample_s=t2 - t1, sample_ev_ms=e0.elapsed_time(e1), info=inf, sectors=sec)
 
     for i in range(args.warmup):
         step(args.seed + 1000 + i)
@@ -234,7 +254,14 @@ def main():
     ms_per_step = 1000.0 * total / args.steps
     inf = recs[-1]["info"]
     bonds = inf["bond"]
-    fl_shot = sampling_flops_per_shot(bonds, w.d)
+    fl_dense = sampling_flops_per_shot(bonds, w.d)
+    sec = recs[-1]["sectors"]
+    if sec is not None:
+        fl_shot = sector_flops_per_shot(sec, w.d, out)
+        fl_exec = sector_flops_per_shot(sec, w.d, out, pad=16)
+    else:
+        fl_shot = fl_dense
+        fl_exec = sampling_flops_per_shot([-(-b // 16) * 16 for b in bonds], w.d)
     samp_ms = sum(r["sample_ev_ms"] for r in recs) / len(recs)
     build_s = sum(r["build_s"] for r in recs) / len(recs)
     achieved = fl_shot * args.shots / (samp_ms / 1000.0) / 1e12
@@ -261,7 +288,10 @@ def main():
         "samples_per_s_sampling_only": args.shots / (samp_ms / 1000.0),
         "eps_max": inf["eps_max"],
         "max_bond": inf["max_bond"],
+        "sampler_layout": {0: "none", 1: "dense", 2: "parity sectors"}[inf["sampler_layout"]],
         "flops_per_sample": fl_shot,
+        "flops_per_sample_whole_bonds": fl_dense,
+        "mfma_tflops_executed": fl_exec * args.shots / (samp_ms / 1000.0) / 1e12,
         "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (whole sampling sweep, all sites)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": sampler_traffic(args.shots / max(1, -(-args.shots // 262144)))

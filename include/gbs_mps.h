@@ -54,8 +54,12 @@ typedef enum {
  * treated as unentangled); trunc_rel: singular values below
  * trunc_rel * sigma_max are dropped by the truncation sweep (0 selects the
  * default, 1e-12 for FP64 and 1e-8 for FP32 builds); flags: GBS_KEEP_RAW keeps
- * the PCO tensors for gbs_mps_export. */
+ * the PCO tensors for gbs_mps_export; GBS_DENSE_SAMPLER makes the FP32
+ * sampler use whole bonds instead of photon-parity sectors (the sectors need
+ * the parity structure a zero-mean state has, and are checked on the built
+ * tensors; the dense layout is also taken when that check fails). */
 #define GBS_KEEP_RAW 1u
+#define GBS_DENSE_SAMPLER 2u
 typedef struct {
   int32_t d;
   int32_t chi;
@@ -116,6 +120,8 @@ typedef struct {
   int64_t pco_updates;     /* tensor elements produced by the PCO level gather */
   double t_gsvd_ms, t_kept_ms, t_pco_ms, t_svd_ms;  /* build phase times */
   int32_t eig_sweeps;      /* sweeps of the bond eigensolver in the truncation step */
+  int32_t sampler_layout;  /* FP32 sampling operand: 0 none (FP64 builds, or a bond the
+                              MFMA sampler cannot take), 1 dense, 2 photon-parity sectors */
 } gbs_mps_info_t;
 
 /* Fill `info`; optional host arrays (may be NULL):
@@ -134,11 +140,14 @@ int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, do
  *                       n = ne[m-1] + 1 + ne[m];
  *   GBS_EXPORT_BASIS  : kept basis of cut m (0..M), int32 kept[m] x ne[m];
  *   GBS_EXPORT_LAMBDA : Lambda_q of cut m (1..M-1), FP64, ne[m] values;
- *   GBS_EXPORT_SVALS  : singular values of bond m after truncation, FP64.
+ *   GBS_EXPORT_SVALS  : singular values of bond m after truncation, FP64;
+ *   GBS_EXPORT_SECTORS: sizes of the two photon-parity sectors of every bond,
+ *                       int32 (M+1) x 2 (m is ignored; zeros unless
+ *                       sampler_layout is 2).
  * `dst` is a host buffer of `cap` bytes; the number of bytes written is
  * returned through *written (host, may be NULL). */
 enum { GBS_EXPORT_TENSOR = 0, GBS_EXPORT_RAW = 1, GBS_EXPORT_Q = 2, GBS_EXPORT_BASIS = 3, GBS_EXPORT_LAMBDA = 4,
-       GBS_EXPORT_SVALS = 5 };
+       GBS_EXPORT_SVALS = 5, GBS_EXPORT_SECTORS = 6 };
 int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, int64_t* written);
 
 /* Release every device buffer of the handle. NULL is ignored. */

@@ -19,7 +19,8 @@ ERROR_NAMES = {0: "OK", -1: "INVAL", -2: "NOT_PD", -3: "NOT_PURE", -4: "NOMEM", 
                -7: "INTERNAL"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 GBS_KEEP_RAW = 1
-EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5}
+GBS_DENSE_SAMPLER = 2
+EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5, "sectors": 6}
 
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
 EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_overlap", "gbs_mps_overlap_prec",
@@ -46,7 +47,8 @@ class InfoT(ctypes.Structure):
                 ("max_bond", ctypes.c_int32), ("max_ne", ctypes.c_int32), ("eps_max", ctypes.c_double),
                 ("norm_raw", ctypes.c_double), ("bytes", ctypes.c_int64), ("pco_updates", ctypes.c_int64),
                 ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
-                ("t_svd_ms", ctypes.c_double), ("eig_sweeps", ctypes.c_int32)]
+                ("t_svd_ms", ctypes.c_double), ("eig_sweeps", ctypes.c_int32),
+                ("sampler_layout", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

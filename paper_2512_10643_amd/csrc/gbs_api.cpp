@@ -141,6 +141,10 @@ struct gbs_mps_s {
   long q_stride = 0, ld_q = 0;
   float* packed = nullptr;       // MFMA sampler operand layout (FP32 builds)
   std::vector<long> poff;        // per site offset into `packed` (floats)
+  std::vector<SamplerSite> ssite;  // per site sector sizes of the packed operand
+  bool psplit = false;           // bonds split into photon-parity sectors
+  std::vector<int32_t> secn;     // (M+1) x 2 sector sizes when psplit
+  long ldl2 = 0;                 // sampler row stride (floats)
   cplx64* raw = nullptr;         // PCO tensors (GBS_KEEP_RAW)
   std::vector<long> raw_off;
   short* occ = nullptr;
@@ -741,19 +745,78 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off)
                                  : canonicalize<cplx32>(h, st, tmp, T64, t64off);
   if (rc) return rc;
-  if (h->prec != GBS_FP64 && h->maxbond <= 256) {
-    // sampler operand layout
-    h->poff.assign(M + 1, 0);
-    long tot = 0;
-    for (int m = 1; m <= M; ++m) {
-      h->poff[m] = tot;
-      tot += (long)d * 2 * sampler_pad(h->bond[m - 1]) * 2 * sampler_pad(h->bond[m]);
+  if (h->prec != GBS_FP64 && h->maxbond <= 2 * kSamplerMaxSector) {
+    // Photon-parity sector of every bond index, read off the site tensors
+    // (a zero-mean Gaussian state has definite total photon parity, so the
+    // canonical tensors are block sparse); any tensor that breaks the
+    // structure sends the sampler to the dense layout.
+    const int mb = h->maxbond;
+    bool split = !(h->flags & GBS_DENSE_SAMPLER);
+    std::vector<int32_t> hm((size_t)(M + 1) * mb, 0);
+    if (split) {
+      int32_t* mask = nullptr;
+      HIP_CHECK_RET(tmp.alloc((void**)&mask, hm.size() * sizeof(int32_t)));
+      HIP_CHECK_RET(hipMemsetAsync(mask, 0, hm.size() * sizeof(int32_t), st));
+      for (int m = 1; m <= M; ++m)
+        HIP_CHECK_RET(launch_sector_mask(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
+                                         m == 1 ? nullptr : mask + (long)(m - 1) * mb, mask + (long)m * mb));
+      HIP_CHECK_RET(hipMemcpyAsync(hm.data(), mask, hm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_CHECK_RET(hipStreamSynchronize(st));
     }
-    HIP_CHECK_RET(dalloc(h->keep, &h->packed, (size_t)tot));
-    for (int m = 1; m <= M; ++m)
-      HIP_CHECK_RET(launch_pack(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
-                                h->packed + h->poff[m]));
-    HIP_CHECK_RET(hipStreamSynchronize(st));
+    std::vector<int32_t> maps((size_t)(M + 1) * mb, 0);
+    std::vector<int> n0(M + 1, 0), n1(M + 1, 0);
+    n0[0] = h->bond[0];
+    for (int i = 0; i < h->bond[0]; ++i) maps[i] = i;
+    for (int m = 1; m <= M && split; ++m) {
+      const int32_t* mk = hm.data() + (size_t)m * mb;
+      int32_t* mp = maps.data() + (size_t)m * mb;
+      for (int b = 0; b < h->bond[m]; ++b)
+        if (mk[b] == 3) split = false;
+      for (int b = 0; b < h->bond[m]; ++b)
+        if (mk[b] != 2) mp[n0[m]++] = b;  // sector 0, zero columns included
+      for (int b = 0; b < h->bond[m]; ++b)
+        if (mk[b] == 2) mp[n0[m] + n1[m]++] = b;
+      if (sampler_pad(std::max(n0[m], n1[m])) > kSamplerMaxSector) split = false;
+    }
+    if (split || mb <= kSamplerMaxSector) {
+      h->psplit = split;
+      if (split) {
+        h->secn.resize(2 * (size_t)(M + 1));
+        for (int m = 0; m <= M; ++m) {
+          h->secn[2 * m] = n0[m];
+          h->secn[2 * m + 1] = n1[m];
+        }
+      }
+      int32_t* dmaps = nullptr;
+      if (split) {
+        HIP_CHECK_RET(dalloc(h->keep, &dmaps, maps.size()));
+        HIP_CHECK_RET(hipMemcpyAsync(dmaps, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      }
+      h->ssite.assign(M + 1, SamplerSite{});
+      h->poff.assign(M + 1, 0);
+      int widest = 1;
+      long tot = 0;
+      for (int m = 1; m <= M; ++m) {
+        SamplerSite s;
+        if (split) {
+          s = SamplerSite{{n0[m - 1], n1[m - 1]}, {n0[m], n1[m]}};
+          widest = std::max(widest, std::max(std::max(n0[m - 1], n1[m - 1]), std::max(n0[m], n1[m])));
+        } else {
+          s = SamplerSite{{h->bond[m - 1], 0}, {h->bond[m], h->bond[m]}};
+          widest = std::max(widest, std::max(h->bond[m - 1], h->bond[m]));
+        }
+        h->ssite[m] = s;
+        h->poff[m] = tot;
+        tot += sampler_site_floats(s, d, nullptr);
+      }
+      h->ldl2 = 2L * sampler_pad(widest);
+      HIP_CHECK_RET(dalloc(h->keep, &h->packed, (size_t)tot));
+      for (int m = 1; m <= M; ++m)
+        HIP_CHECK_RET(launch_pack(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
+                                  h->ssite[m], split ? dmaps + (long)(m - 1) * mb : nullptr,
+                                  split ? dmaps + (long)m * mb : nullptr, h->packed + h->poff[m]));
+      HIP_CHECK_RET(hipStreamSynchronize(st));
+    }
   }
   h->t_svd = now_ms() - t3;
   return GBS_OK;
@@ -823,6 +886,7 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   if (opt->prec != GBS_FP64 && opt->prec != GBS_FP32 && opt->prec != GBS_BF16X3)
     return fail(GBS_E_INVAL, "unknown precision");
   if ((long)opt->chi * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi * d too large");
+  if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER)) return fail(GBS_E_INVAL, "unknown build flag");
   gbs_mps_s* h = new (std::nothrow) gbs_mps_s();
   if (!h) return fail(GBS_E_NOMEM, "host allocation failed");
   h->M = M;
@@ -894,28 +958,44 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   const int64_t chunk = std::min<int64_t>(shots, (int64_t)1 << 18);
   DevArena tmp(st);
   void* lbuf[2];
-  const size_t rowbytes = std::max((size_t)ldl * h->esz, (size_t)2 * sampler_pad(h->maxbond) * sizeof(float));
-  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * rowbytes));
   if (h->packed) {
-    // MFMA path: left vectors as interleaved floats, rows padded to 16 complex,
-    // plus one inverse row norm per shot
-    const long ldl2 = 2L * sampler_pad(h->maxbond);
-    float* fb[2] = {(float*)lbuf[0], (float*)lbuf[1]};
+    // MFMA path: left vectors as interleaved floats in sector-local indices,
+    // rows padded to 16 complex, plus one inverse row norm per shot
+    const long ldl2 = h->ldl2;
+    float* fb[2];
     float* sb[2];
-    for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc((void**)&sb[i], (size_t)chunk * sizeof(float)));
+    for (int i = 0; i < 2; ++i) {
+      HIP_CHECK_RET(tmp.alloc((void**)&fb[i], (size_t)chunk * ldl2 * sizeof(float)));
+      HIP_CHECK_RET(tmp.alloc((void**)&sb[i], (size_t)chunk * sizeof(float)));
+    }
+    int8_t* par = nullptr;
+    int32_t *perm = nullptr, *cnt = nullptr, *bcnt = nullptr;
+    if (h->psplit) {
+      HIP_CHECK_RET(tmp.alloc((void**)&par, (size_t)chunk));
+      HIP_CHECK_RET(tmp.alloc((void**)&perm, (size_t)(chunk + sampler_shots_per_block()) * sizeof(int32_t)));
+      HIP_CHECK_RET(tmp.alloc((void**)&cnt, 2 * sizeof(int32_t)));
+      HIP_CHECK_RET(tmp.alloc((void**)&bcnt, (size_t)sampler_partition_blocks(chunk) * sizeof(int32_t)));
+    }
     for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
       const int64_t n = std::min(chunk, shots - s0);
       HIP_CHECK_RET(launch_sampler_init(st, fb[0], ldl2, h->bond[0], n));
       int cur = 0;
       for (int m = 1; m <= M; ++m) {
-        HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], h->bond[m - 1], d, h->bond[m], fb[cur],
-                                         m == 1 ? nullptr : sb[cur], fb[1 - cur], sb[1 - cur], ldl2, s0, n, m, seed,
-                                         out, M));
+        // site 1: every shot starts in sector 0 of the one-dimensional bond
+        const bool part = h->psplit && m > 1;
+        const bool next = h->psplit && m < M;
+        HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], d, h->ssite[m], fb[cur],
+                                         m == 1 ? nullptr : sb[cur], fb[1 - cur], sb[1 - cur], ldl2,
+                                         part ? perm : nullptr, part ? cnt : nullptr, next ? par : nullptr, s0, n, m,
+                                         seed, out, M));
+        if (next) HIP_CHECK_RET(launch_sampler_partition(st, par, n, bcnt, perm, cnt));
         cur = 1 - cur;
       }
     }
     return GBS_OK;  // the temporaries are freed in stream order
   }
+  const size_t rowbytes = (size_t)ldl * h->esz;
+  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * rowbytes));
   for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
     const int64_t n = std::min(chunk, shots - s0);
     int cur = 0;
@@ -974,6 +1054,7 @@ int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, do
   info->t_pco_ms = h->t_pco;
   info->t_svd_ms = h->t_svd;
   info->eig_sweeps = h->eig_sweeps;
+  info->sampler_layout = h->packed ? (h->psplit ? 2 : 1) : 0;
   for (int m = 0; m <= h->M; ++m) {
     if (bond) bond[m] = h->bond[m];
     if (ne) ne[m] = h->ne[m];
@@ -1043,6 +1124,11 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
     if (m < 1 || m >= M) return fail(GBS_E_INVAL, "bond out of range");
     return put(h->svals[m].data(), h->svals[m].size() * sizeof(double));
   }
+  if (what == GBS_EXPORT_SECTORS) {
+    std::vector<int32_t> out(2 * (size_t)(M + 1), 0);
+    if (h->psplit) out = h->secn;
+    return put(out.data(), out.size() * sizeof(int32_t));
+  }
   return fail(GBS_E_INVAL, "unknown export kind");
 }
 
@@ -1072,11 +1158,12 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   b += 3 * (m + 1) * chi * chi * 16 + 3 * site * 16;
   b += (int64_t)jacobi_blocked_ws_elems((int)chi, (int)std::max<int64_t>(m - 1, 1)) * 16 + 16 * m;
   b += m * site * esz + (m + 1) * chi * chi * esz + 2 * site * esz;
-  if (opt->prec != GBS_FP64 && chi <= 256) b += m * 16 * site;  // sampler operand
-  // sampling buffers
-  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 0), 1 << 18);
   const int64_t pad = (chi + 15) / 16 * 16;
-  b += 2 * chunk * std::max<int64_t>(chi * esz, 8 * pad);
+  // sampler operand: sector blocks pad at most 16 rows and columns each
+  if (opt->prec != GBS_FP64 && chi <= 512) b += m * 16 * d * (pad + 16) * (pad + 16) + (m + 1) * chi * 8;
+  // sampling buffers: rows, scales, parities and partition
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 0), 1 << 18);
+  b += 2 * chunk * std::max<int64_t>(chi * esz, 8 * pad) + 16 * chunk + 4096;
   return b + b / 8 + (64LL << 20);
 }
 

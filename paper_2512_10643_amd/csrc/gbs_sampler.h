@@ -1,21 +1,66 @@
 // MFMA sampling sweep launch interface.
+//
+// The sweep works on photon-parity sectors.  A Gaussian state with zero mean
+// is an eigenstate of the total photon parity, so every bond index of its
+// canonical MPS can carry a parity (0 or 1) with B[a, p, b] = 0 unless
+// par(a) + p + par(b) is even.  A shot whose left vector lies in sector pi of
+// bond m-1 then only touches the rows of sector pi and, for outcome p, the
+// columns of sector pi ^ (p & 1) of bond m.  Left vectors are stored in
+// sector-local indices.  With one sector per bond (pi = 0 for every shot and
+// both column sets equal to the whole bond) the same code is the dense sweep.
 #pragma once
 #include "gbs_common.h"
 
 // K and N padded to multiples of 16 for the packed layout.
 int sampler_pad(int n);
-// Pack site tensor B (K x d x N, complex FP32) into the MFMA operand layout:
-// d * (2 pad(K)) * (2 pad(N)) floats.
-hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, float* P);
+// Largest padded sector width the sampling kernel takes.
+constexpr int kSamplerMaxSector = 256;
+
+// Sector sizes of one site: nL[pi] rows of left sector pi, nR[s] columns of
+// right sector s.  Dense layout: nL = {K, 0}, nR = {N, N}.
+struct SamplerSite {
+  int nL[2];
+  int nR[2];
+};
+// Floats of the packed operand of one site, and the offset of the block of
+// left sector pi within it (pbase may be NULL).
+long sampler_site_floats(const SamplerSite& s, int d, long pbase[2]);
+
+// Bond parities from the site tensors, one site per call, left to right.
+// mask_l (K ints) is the previous bond's result, mask_r (N ints, zeroed by the
+// caller) receives bit (par(a) + p) & 1 for every nonzero B[a, p, b], with
+// par(a) = 1 iff mask_l[a] == 2.  A column with mask 3 breaks the parity
+// structure; mask 0 marks a zero column.
+hipError_t launch_sector_mask(hipStream_t st, const cplx32* B, int K, int d, int N, const int32_t* mask_l,
+                              int32_t* mask_r);
+
+// Pack site tensor B (K x d x N, complex FP32) into the MFMA operand layout,
+// sector by sector.  mapL / mapR list the bond indices of sector 0 followed
+// by those of sector 1 (NULL: identity, for the dense layout).
+hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, const SamplerSite& s,
+                       const int32_t* mapL, const int32_t* mapR, float* P);
 // Shots per workgroup of the sampling kernel.
 int sampler_shots_per_block();
 // Left vectors of the first site (bond dimension k0, normally 1): row r of
 // `l` (stride ldl2 floats) becomes e_0 over 2 pad(k0) floats.
 hipError_t launch_sampler_init(hipStream_t st, float* l, long ldl2, int k0, int64_t n);
+
 // One conditional-sampling step at `site` for nshots shots (chunk-local rows
-// of lin/lout, row stride ldl2 floats, 2 pad(K) <= ldl2 and 2 pad(N) <= ldl2;
-// pad(N) <= 256).  Rows of lin are scaled by sin (NULL: 1); lout receives the
-// unnormalised selected rows and sout their inverse norms.
-hipError_t launch_sample_mfma(hipStream_t st, const float* P, int K, int d, int N, const float* lin,
-                              const float* sin, float* lout, float* sout, long ldl2, int64_t shot0, int64_t nshots,
-                              int site, uint64_t seed, int32_t* out, int M);
+// of lin/lout, row stride ldl2 floats).  Rows of lin are scaled by sin (NULL:
+// 1); lout receives the unnormalised selected rows and sout their inverse
+// norms.  perm == NULL: every shot is in sector 0 and workgroup b takes shots
+// [128 b, 128 b + 128).  Otherwise perm / cnt come from
+// launch_sampler_partition and the grid covers both sector groups.  par_out
+// (may be NULL) receives the parity of each shot's new bond index.
+hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerSite& s, const float* lin,
+                              const float* sin, float* lout, float* sout, long ldl2, const int32_t* perm,
+                              const int32_t* cnt, int8_t* par_out, int64_t shot0, int64_t nshots, int site,
+                              uint64_t seed, int32_t* out, int M);
+
+// Stable partition of shots by parity: perm[0, c0) lists the shots with
+// par == 0 in order, perm[E, E + c1) those with par == 1, E = c0 rounded up to
+// a multiple of 128; cnt = {c0, c1}.  perm holds nshots + 128 ints; bcnt is a
+// workspace of sampler_partition_blocks(nshots) ints.
+int64_t sampler_partition_blocks(int64_t nshots);
+hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t nshots, int32_t* bcnt,
+                                    int32_t* perm, int32_t* cnt);

@@ -88,7 +88,8 @@ class GaussianMPS:
 
     def export(self, m: int, what: str) -> np.ndarray:
         """gbs_mps_export: tensor / raw (kept[m-1] x d x kept[m]) / Q / basis /
-        lambda / svals of site or cut m, copied to host memory."""
+        lambda / svals of site or cut m, or the (M+1) x 2 parity-sector sizes
+        of the sampler ("sectors", m ignored), copied to host memory."""
         inf = self.info()
         d, chi = self.d, inf["chi"]
         bond, ne = inf["bond"], inf["ne"]
@@ -102,6 +103,8 @@ class GaussianMPS:
             buf = np.empty(max(1, k * k), dtype=np.complex128)
         elif what == "basis":
             buf = np.empty(max(1, chi * max(1, ne[m])), dtype=np.int32)
+        elif what == "sectors":
+            buf = np.empty(2 * (self.M + 1), dtype=np.int32)
         else:  # lambda, svals
             buf = np.empty(max(1, chi, ne[m]), dtype=np.float64)
         written = ctypes.c_int64(0)
@@ -118,13 +121,18 @@ class GaussianMPS:
             return arr.reshape(kl, d, arr.size // (kl * d))
         if what == "basis":
             return arr.reshape(-1, ne[m]) if ne[m] else np.zeros((1, 0), dtype=np.int32)
+        if what == "sectors":
+            return arr.reshape(self.M + 1, 2)
         return arr
 
 
 def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, precision: str = "fp64",
-          keep_raw: bool = False, trunc_rel: float = 0.0, stream=None) -> GaussianMPS:
+          keep_raw: bool = False, trunc_rel: float = 0.0, dense_sampler: bool = False,
+          stream=None) -> GaussianMPS:
     """Convert the pure Gaussian state with covariance `gamma` (2M x 2M FP64
-    CUDA tensor, xxpp, vacuum = I/2) into an MPS with cutoff d and bond chi."""
+    CUDA tensor, xxpp, vacuum = I/2) into an MPS with cutoff d and bond chi.
+    dense_sampler: FP32 sampling over whole bonds instead of photon-parity
+    sectors."""
     if not isinstance(gamma, torch.Tensor) or not gamma.is_cuda or gamma.dtype != torch.float64:
         raise ValueError("gamma must be a CUDA float64 tensor")
     if gamma.dim() != 2 or gamma.shape[0] != gamma.shape[1] or gamma.shape[0] % 2:
@@ -132,7 +140,8 @@ def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, pre
     gamma = gamma.contiguous()
     M = gamma.shape[0] // 2
     opts = BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS[precision],
-                     flags=_lib.GBS_KEEP_RAW if keep_raw else 0, trunc_rel=trunc_rel)
+                     flags=(_lib.GBS_KEEP_RAW if keep_raw else 0) | (_lib.GBS_DENSE_SAMPLER if dense_sampler else 0),
+                     trunc_rel=trunc_rel)
     h = ctypes.c_void_p()
     check(lib().gbs_mps_build(ctypes.c_void_p(gamma.data_ptr()), M, ctypes.byref(opts), _stream_handle(stream),
                               ctypes.byref(h)))

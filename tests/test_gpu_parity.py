@@ -242,6 +242,53 @@ def test_sampling_fp32_mfma_c2(torch_cuda):
     h.free()
 
 
+@pytest.mark.parametrize("name,shots", [("c2", 100_000 + 77), ("c3", 65_536 + 77)])
+def test_sampler_parity_sectors_match_dense(torch_cuda, name, shots):
+    """The photon-parity sector sampler against the dense layout over the same
+    FP32 tensors.  Both draw with the same uniforms per (shot, site, outcome),
+    so their samples differ only where the rounding of |T_p|^2 moves a
+    threshold; the sector one must also keep every shot's total photon number
+    even."""
+    _say(f"case: {name} sector vs dense sampler, {shots} shots")
+    w = W.workload(name)
+    hs = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
+    hd = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32", dense_sampler=True)
+    assert hs.info()["sampler_layout"] == 2
+    assert hd.info()["sampler_layout"] == 1
+    sec = hs.export(0, "sectors")
+    bonds = hs.info()["bond"]
+    assert np.array_equal(sec.sum(1), bonds)
+    assert not hd.export(0, "sectors").any()
+    if name == "c2":
+        # parities read off the exported tensors on the host: the first
+        # nonzero entry of each column fixes its sector, every other entry
+        # must agree, and the sector sizes must be the exported ones
+        par = np.zeros(1, dtype=int)
+        for m in range(1, w.M + 1):
+            B = hs.export(m, "tensor")
+            nz = B != 0
+            cls = (par[:, None] + np.arange(w.d)[None, :]) % 2
+            pr = np.zeros(B.shape[2], dtype=int)
+            for b in range(B.shape[2]):
+                c = np.unique(cls[nz[:, :, b]])
+                assert len(c) <= 1, (m, b)
+                pr[b] = c[0] if len(c) else 0
+            assert [int((pr == 0).sum()), int((pr == 1).sum())] == list(sec[m]), m
+            par = pr
+    a = hs.sample(shots, seed=9).cpu().numpy()
+    b = hd.sample(shots, seed=9).cpu().numpy()
+    assert np.all((a >= 0) & (a < w.d))
+    assert np.all(a.sum(1) % 2 == 0)
+    same = float(np.mean(np.all(a == b, axis=1)))
+    _say(f"  shots identical in both layouts: {same:.5f}")
+    assert same >= 0.99
+    # the tail of a ragged chunk and a second call agree with the first
+    a2 = hs.sample(333, seed=9).cpu().numpy()
+    assert np.array_equal(a2, a[:333])
+    hs.free()
+    hd.free()
+
+
 # ---------------------------------------------------------- full size (C3)
 
 def _golden(name):
