@@ -142,6 +142,8 @@ struct gbs_mps_s {
   float* packed = nullptr;       // MFMA sampler operand layout (FP32 builds)
   std::vector<long> poff;        // per site offset into `packed` (floats)
   std::vector<SamplerSite> ssite;  // per site sector sizes of the packed operand
+  std::vector<SamplerGeom> sgeo;   // per site launch geometry (host copy)
+  SamplerGeom* sgeo_dev = nullptr; // the same on the device, M + 1 entries
   bool psplit = false;           // bonds split into photon-parity sectors
   std::vector<int32_t> secn;     // (M+1) x 2 sector sizes when psplit
   long ldl2 = 0;                 // sampler row stride (floats)
@@ -745,7 +747,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off)
                                  : canonicalize<cplx32>(h, st, tmp, T64, t64off);
   if (rc) return rc;
-  if (h->prec != GBS_FP64 && h->maxbond <= 2 * kSamplerMaxSector) {
+  if (h->prec != GBS_FP64 && h->maxbond <= 2 * kSamplerMaxSector && d <= kSamplerMaxOutcomes) {
     // Photon-parity sector of every bond index, read off the site tensors
     // (a zero-mean Gaussian state has definite total photon parity, so the
     // canonical tensors are block sparse); any tensor that breaks the
@@ -789,10 +791,11 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
       }
       int32_t* dmaps = nullptr;
       if (split) {
-        HIP_CHECK_RET(dalloc(h->keep, &dmaps, maps.size()));
+        HIP_CHECK_RET(dalloc(tmp, &dmaps, maps.size()));
         HIP_CHECK_RET(hipMemcpyAsync(dmaps, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
       }
       h->ssite.assign(M + 1, SamplerSite{});
+      h->sgeo.assign(M + 1, SamplerGeom{});
       h->poff.assign(M + 1, 0);
       int widest = 1;
       long tot = 0;
@@ -807,13 +810,19 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
         }
         h->ssite[m] = s;
         h->poff[m] = tot;
-        tot += sampler_site_floats(s, d, nullptr);
+        const long f = sampler_geometry(s, d, &h->sgeo[m]);
+        if (f < 0) return fail(GBS_E_INTERNAL, "sampler geometry");  // sizes were checked above
+        tot += f;
       }
       h->ldl2 = 2L * sampler_pad(widest);
+      HIP_CHECK_RET(dalloc(h->keep, &h->sgeo_dev, (size_t)(M + 1)));
+      HIP_CHECK_RET(hipMemcpyAsync(h->sgeo_dev, h->sgeo.data(), (M + 1) * sizeof(SamplerGeom),
+                                   hipMemcpyHostToDevice, st));
       HIP_CHECK_RET(dalloc(h->keep, &h->packed, (size_t)tot));
       for (int m = 1; m <= M; ++m)
         HIP_CHECK_RET(launch_pack(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
-                                  h->ssite[m], split ? dmaps + (long)(m - 1) * mb : nullptr,
+                                  h->ssite[m], h->sgeo[m], h->sgeo_dev + m,
+                                  split ? dmaps + (long)(m - 1) * mb : nullptr,
                                   split ? dmaps + (long)m * mb : nullptr, h->packed + h->poff[m]));
       HIP_CHECK_RET(hipStreamSynchronize(st));
     }
@@ -984,7 +993,7 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
         // site 1: every shot starts in sector 0 of the one-dimensional bond
         const bool part = h->psplit && m > 1;
         const bool next = h->psplit && m < M;
-        HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], d, h->ssite[m], fb[cur],
+        HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], d, h->sgeo[m], h->sgeo_dev + m, fb[cur],
                                          m == 1 ? nullptr : sb[cur], fb[1 - cur], sb[1 - cur], ldl2,
                                          part ? perm : nullptr, part ? cnt : nullptr, next ? par : nullptr, s0, n, m,
                                          seed, out, M));

@@ -8,13 +8,20 @@
 // columns of sector pi ^ (p & 1) of bond m.  Left vectors are stored in
 // sector-local indices.  With one sector per bond (pi = 0 for every shot and
 // both column sets equal to the whole bond) the same code is the dense sweep.
+//
+// Outcomes are visited in the order 0, 2, 4, ..., 1, 3, 5, ... and grouped
+// into passes: consecutive outcomes whose column tiles together fit the
+// kernel's accumulator budget share one sweep over the K rows.
 #pragma once
 #include "gbs_common.h"
 
 // K and N padded to multiples of 16 for the packed layout.
 int sampler_pad(int n);
-// Largest padded sector width the sampling kernel takes.
+// Largest padded sector width and number of outcomes the kernel takes.
 constexpr int kSamplerMaxSector = 256;
+constexpr int kSamplerMaxOutcomes = 32;
+// Accumulator budget: 16-column tiles of one pass.
+constexpr int kSamplerMaxTiles = 32;
 
 // Sector sizes of one site: nL[pi] rows of left sector pi, nR[s] columns of
 // right sector s.  Dense layout: nL = {K, 0}, nR = {N, N}.
@@ -22,9 +29,25 @@ struct SamplerSite {
   int nL[2];
   int nR[2];
 };
-// Floats of the packed operand of one site, and the offset of the block of
-// left sector pi within it (pbase may be NULL).
-long sampler_site_floats(const SamplerSite& s, int d, long pbase[2]);
+
+// Launch geometry of one site (host and device copies).  For left sector pi:
+// nchunk[pi] K-chunks of 32 real rows; right sector s is nt[s] tiles wide;
+// pass q covers visiting positions [j0[pi][q], j0[pi][q + 1]) with
+// tiles[pi][q] tiles per chunk, its chunks starting at float base[pi][q] of
+// the packed operand.  NT: accumulator tiles of the kernel instance.
+struct SamplerGeom {
+  int nchunk[2];
+  int nt[2];
+  int npass[2];
+  int NT;
+  int j0[2][kSamplerMaxOutcomes + 1];
+  int tiles[2][kSamplerMaxOutcomes];
+  long base[2][kSamplerMaxOutcomes];
+};
+// Fill g for site s with d outcomes; returns the floats of the packed
+// operand, or -1 when the site does not fit the kernel (d or a sector too
+// large).
+long sampler_geometry(const SamplerSite& s, int d, SamplerGeom* g);
 
 // Bond parities from the site tensors, one site per call, left to right.
 // mask_l (K ints) is the previous bond's result, mask_r (N ints, zeroed by the
@@ -35,10 +58,12 @@ hipError_t launch_sector_mask(hipStream_t st, const cplx32* B, int K, int d, int
                               int32_t* mask_r);
 
 // Pack site tensor B (K x d x N, complex FP32) into the MFMA operand layout,
-// sector by sector.  mapL / mapR list the bond indices of sector 0 followed
-// by those of sector 1 (NULL: identity, for the dense layout).
+// sector by sector and pass by pass.  mapL / mapR list the bond indices of
+// sector 0 followed by those of sector 1 (NULL: identity, for the dense
+// layout).  gd: device copy of g.
 hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, const SamplerSite& s,
-                       const int32_t* mapL, const int32_t* mapR, float* P);
+                       const SamplerGeom& g, const SamplerGeom* gd, const int32_t* mapL, const int32_t* mapR,
+                       float* P);
 // Shots per workgroup of the sampling kernel.
 int sampler_shots_per_block();
 // Left vectors of the first site (bond dimension k0, normally 1): row r of
@@ -52,10 +77,10 @@ hipError_t launch_sampler_init(hipStream_t st, float* l, long ldl2, int k0, int6
 // [128 b, 128 b + 128).  Otherwise perm / cnt come from
 // launch_sampler_partition and the grid covers both sector groups.  par_out
 // (may be NULL) receives the parity of each shot's new bond index.
-hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerSite& s, const float* lin,
-                              const float* sin, float* lout, float* sout, long ldl2, const int32_t* perm,
-                              const int32_t* cnt, int8_t* par_out, int64_t shot0, int64_t nshots, int site,
-                              uint64_t seed, int32_t* out, int M);
+hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerGeom& g, const SamplerGeom* gd,
+                              const float* lin, const float* sin, float* lout, float* sout, long ldl2,
+                              const int32_t* perm, const int32_t* cnt, int8_t* par_out, int64_t shot0,
+                              int64_t nshots, int site, uint64_t seed, int32_t* out, int M);
 
 // Stable partition of shots by parity: perm[0, c0) lists the shots with
 // par == 0 in order, perm[E, E + c1) those with par == 1, E = c0 rounded up to

@@ -13,18 +13,23 @@
 // are those of sector pi and outcome p only needs the columns of sector
 // pi ^ (p & 1); the blocks B[pi, p, pi ^ (p & 1)] are the only nonzero ones.
 //
+// Outcomes are visited in the order 0, 2, 4, ..., 1, 3, 5, ... and grouped
+// into passes whose column tiles together fit the accumulators, so narrow
+// sectors share one sweep over K.
+//
 // Workgroup: 8 waves x 16 shots, two waves per SIMD.  Each wave keeps the
-// T_p row block of its 16 shots in MFMA accumulators (v_mfma_f32_16x16x4f32
-// tiles), reduces the squared norms across lanes and draws by weighted
-// reservoir selection (p replaces the running choice when
-// u (W_{p-1} + w_p) < w_p, one Philox uniform per p >= 1 keyed by
-// (seed, shot, site)); a replacing T_p row is stored at once to the output
-// row of its shot, so no second register set holds the selection.  Rows are
-// left unnormalised: the conditional probabilities do not depend on the scale
-// of L, and the next site multiplies its A operand by the stored 1/|T_p|.
-// B' arrives in LDS in K-chunks of 32 real rows, double buffered by the LDS
-// DMA path, in the lane order the B operand needs, four k-steps per 16-byte
-// LDS read.
+// row block of its 16 shots for all outcomes of a pass in MFMA accumulators
+// (v_mfma_f32_16x16x4f32 tiles), reduces the squared norms across lanes and
+// draws by weighted reservoir selection: the outcome at visiting position
+// j >= 1 replaces the running choice when u_j (W_{j-1} + w_j) < w_j, with u_j
+// from Philox keyed by (seed, shot, site, j).  A replacing row is stored at
+// once to the output row of its shot, so no second register set holds the
+// selection.  Rows are left unnormalised: the conditional probabilities do
+// not depend on the scale of L, and the next site multiplies its A operand by
+// the stored 1/|T_p|.  B' arrives in LDS in K-chunks of 32 real rows, double
+// buffered by the LDS DMA path into two separate LDS arrays (so reads of one
+// need not wait for the DMA into the other), in the lane order the B operand
+// needs, four k-steps per 16-byte LDS read.
 #include "gbs_sampler.h"
 
 #include <algorithm>
@@ -37,54 +42,42 @@ namespace {
 constexpr int kWaves = 8;              // waves per workgroup
 constexpr int kShotsPerWg = 16 * kWaves;
 
-// Per-launch geometry: for left sector pi, nchunk[pi] K-chunks of 32 real
-// rows; right sector s is nt[s] 16-column tiles wide; pbase[pi] is the first
-// float of sector pi's block in the packed operand.
-struct SampleGeom {
-  int nchunk[2];
-  int nt[2];
-  long pbase[2];
-};
-
-// Floats before chunk (p, c) inside a sector block: the outcomes p run in
-// order, even p with nte tiles and odd p with nto tiles per chunk.
-__host__ __device__ inline long chunk_offset(int nchunk, int nte, int nto, int p, int c) {
-  const int ntp = (p & 1) ? nto : nte;
-  return 512L * ((long)nchunk * (((p + 1) >> 1) * nte + (p >> 1) * nto) + (long)c * ntp);
+// Outcome visited at position j: the even outcomes first, then the odd ones.
+__host__ __device__ inline int outcome_at(int j, int d) {
+  const int ne = (d + 1) >> 1;
+  return j < ne ? 2 * j : 2 * (j - ne) + 1;
 }
 
-SampleGeom make_geom(const SamplerSite& s, int d) {
-  SampleGeom g;
-  for (int i = 0; i < 2; ++i) {
-    g.nchunk[i] = sampler_pad(s.nL[i]) / 16;
-    g.nt[i] = sampler_pad(s.nR[i]) / 8;
-  }
-  sampler_site_floats(s, d, g.pbase);
-  return g;
-}
-
-// Packed layout of B' for one site, per left sector pi and outcome p, one
-// 1 KiB block per (c, t, h):
-//   P[pi][p][c][t][h][lane][j] = B'_{pi,p}[32 c + 8 (lane/16) + 4 h + j][16 t + lane%16]
-// where B'_{pi,p} is the real embedding of B restricted to the rows of left
-// sector pi and the columns of right sector pi ^ (p & 1), in sector-local
-// order.  c: chunk of 32 real K rows, t: 16-column tile, h: half of the
+// Packed layout of B' for one site, per left sector pi and pass q, one 1 KiB
+// block per (c, t, h):
+//   P[pi][q][c][t][h][lane][j] = B'_{pi,q}[32 c + 8 (lane/16) + 4 h + j][16 t + lane%16]
+// where B'_{pi,q} is the real embedding of B restricted to the rows of left
+// sector pi (sector-local order) and, side by side, the columns of right
+// sector pi ^ (p & 1) of every outcome p of the pass, each padded to whole
+// tiles.  c: chunk of 32 real K rows, t: 16-column tile, h: half of the
 // chunk's 8 k-steps, j: k-step within the half (4 per 16-byte read).
-__global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerSite s, SampleGeom g,
-                            const int32_t* __restrict__ mapL, const int32_t* __restrict__ mapR,
-                            float* __restrict__ P) {
-  const int pi = blockIdx.y / d, p = blockIdx.y % d;
-  if (s.nL[pi] == 0) return;
-  const int sig = pi ^ (p & 1);
-  const int ntp = g.nt[sig];
-  const long per_chunk = 512L * ntp;
+__global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerSite s,
+                            const SamplerGeom* __restrict__ g, const int32_t* __restrict__ mapL,
+                            const int32_t* __restrict__ mapR, float* __restrict__ P) {
+  const int pi = blockIdx.y / kSamplerMaxOutcomes, q = blockIdx.y % kSamplerMaxOutcomes;
+  if (s.nL[pi] == 0 || q >= g->npass[pi]) return;
+  const int T = g->tiles[pi][q];
+  const long per_chunk = 512L * T;
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= per_chunk * g.nchunk[pi]) return;
+  if (e >= per_chunk * g->nchunk[pi]) return;
   const int c = (int)(e / per_chunk);
   const int r = (int)(e % per_chunk);
-  const int j = r & 3, lane = (r >> 2) & 63, h = (r >> 8) & 1, t = r >> 9;
+  const int j = r & 3, lane = (r >> 2) & 63, h = (r >> 8) & 1;
+  int t = r >> 9;
+  // the outcome owning tile t
+  int jo = g->j0[pi][q], p = outcome_at(jo, d), sig = pi ^ (p & 1);
+  while (t >= g->nt[sig]) {
+    t -= g->nt[sig];
+    p = outcome_at(++jo, d);
+    sig = pi ^ (p & 1);
+  }
   const int kr = 32 * c + 8 * (lane >> 4) + 4 * h + j;  // real row of B'
-  const int nr = 16 * t + (lane & 15);                  // real column of B'
+  const int nr = 16 * t + (lane & 15);                  // real column within outcome p
   const int k = kr >> 1, a = kr & 1, jj = nr >> 1, bcol = nr & 1;
   float v = 0.f;
   if (k < s.nL[pi] && jj < s.nR[sig]) {
@@ -93,7 +86,7 @@ __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerS
     const cplx32 z = B[((long)al * d + p) * N + be];
     v = (a == 0) ? (bcol == 0 ? z.re : z.im) : (bcol == 0 ? -z.im : z.re);
   }
-  P[g.pbase[pi] + chunk_offset(g.nchunk[pi], g.nt[pi], g.nt[pi ^ 1], p, 0) + e] = v;
+  P[g->base[pi][q] + e] = v;
 }
 
 // One thread per column b and a slice of the (a, p) rows; see launch_sector_mask.
@@ -117,11 +110,14 @@ __global__ __launch_bounds__(256) void sector_mask_kernel(const cplx32* __restri
 
 template <int NT>
 __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
-    const float* __restrict__ P, SampleGeom geo, int d, const float* __restrict__ lin,
+    const float* __restrict__ P, const SamplerGeom* __restrict__ geo, int d, const float* __restrict__ lin,
     const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
     int64_t shot0, int64_t nshots, int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
-  __shared__ __attribute__((aligned(16))) float Bs[2][512 * NT];
+  // two separate LDS buffers (not one 2-D array), so the compiler can tell
+  // the buffer being read from the one the DMA is filling
+  __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
+  __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int grp = lane >> 4;   // k sub-block for A, row block for outputs
   const int col = lane & 15;
@@ -140,9 +136,9 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     }
     if (slot0 >= send) return;  // whole workgroup, before any barrier
   }
-  const int nchunk = geo.nchunk[pi];
-  const int nte = geo.nt[pi], nto = geo.nt[pi ^ 1];
-  const float* Pb = P + geo.pbase[pi];
+  const int nchunk = geo->nchunk[pi];
+  const int npass = geo->npass[pi];
+  const int nte = geo->nt[pi], nto = geo->nt[pi ^ 1];
   const int64_t wslot = slot0 + w * 16;  // first slot of this wave
   // A operand rows: lane row = col, k = 32c + 8 grp + i
   const bool avalid = wslot + col < send;
@@ -150,10 +146,10 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   const float* arow_ptr = lin + arow * ldl2 + 8 * grp;
   const float ascale = (sin && avalid) ? sin[arow] : 1.f;
   floatx4 acc[NT];
-  float wsum[4], wsel[4], uu[4][4];
+  float wsum[4], wsel[4];
   int psel[4];
   bool rowok[4];
-  int64_t oshot[4];  // chunk-local shot of output row 4 grp + v
+  int oshot[4];  // chunk-local shot of output row 4 grp + v
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     wsum[v] = 0.f;
@@ -161,123 +157,163 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     psel[v] = 0;
     const int64_t sl = wslot + 4 * grp + v;
     rowok[v] = sl < send;
-    oshot[v] = rowok[v] ? (perm ? (int64_t)perm[sl] : sl) : 0;
+    oshot[v] = rowok[v] ? (perm ? perm[sl] : (int)sl) : 0;
   }
-  auto load_a = [&](int c, float* a) {
-    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+  // A rows arrive raw and are scaled only when they become the current
+  // operand, so nothing waits on the loads before the end of the chunk
+  auto load_a = [&](int c, float4* r) {
+    r[0] = r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (avalid) {
       const float4* ap = (const float4*)(arow_ptr + 32 * c);
-      a0 = ap[0];
-      a1 = ap[1];
+      r[0] = ap[0];
+      r[1] = ap[1];
     }
-    a[0] = a0.x * ascale; a[1] = a0.y * ascale; a[2] = a0.z * ascale; a[3] = a0.w * ascale;
-    a[4] = a1.x * ascale; a[5] = a1.y * ascale; a[6] = a1.z * ascale; a[7] = a1.w * ascale;
+  };
+  auto scale_a = [&](const float4* r, float* a) {
+    a[0] = r[0].x * ascale; a[1] = r[0].y * ascale; a[2] = r[0].z * ascale; a[3] = r[0].w * ascale;
+    a[4] = r[1].x * ascale; a[5] = r[1].y * ascale; a[6] = r[1].z * ascale; a[7] = r[1].w * ascale;
   };
   // global -> LDS by the DMA path: lane l carries 16 bytes to block base + 16 l.
-  // Chunks run as one sequence over (p, c), so the first chunk of p + 1 is in
-  // flight while p's draw is made.
-  auto issue = [&](int g, int buf) {
-    const int p = g / nchunk, c = g - p * nchunk;
-    const int ntp = (p & 1) ? nto : nte;
-    const float* src = Pb + chunk_offset(nchunk, nte, nto, p, c);
-    for (int blk = w; blk < 2 * ntp; blk += kWaves)  // uniform per wave
+  // Chunks run as one sequence over (pass, c), so the first chunk of the next
+  // pass is in flight while this pass's draws are made.
+  auto issue = [&](int g, float* dst) {
+    const int q = g / nchunk, c = g - q * nchunk;
+    const int T = geo->tiles[pi][q];
+    const float* src = P + geo->base[pi][q] + 512L * c * T;
+    for (int blk = w; blk < 2 * T; blk += kWaves)  // uniform per wave
       __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
-                                       (void __attribute__((address_space(3)))*)(&Bs[buf][blk * 256]), 16, 0, 0);
+                                       (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
   };
-  const int total = d * nchunk;
-  float a[8], an[8];
+  const int total = npass * nchunk;
+  float a[8];
+  float4 an[2];
   if (total > 0) {
-    issue(0, 0);
-    load_a(0, a);
+    issue(0, Bs0);
+    load_a(0, an);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  for (int p = 0; p < d; ++p) {
-    const int ntp = (p & 1) ? nto : nte;
+  scale_a(an, a);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int c = 0; c < nchunk; ++c) {
-      const int g = p * nchunk + c;
-      const int buf = g & 1;
-      if (g + 1 < total) {
-        issue(g + 1, buf ^ 1);
-        load_a(c + 1 < nchunk ? c + 1 : 0, an);
-      }
-      const float4* bsrc = (const float4*)Bs[buf];
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // chunk g of the sequence over (pass, c): MFMAs on one buffer while chunk
+  // g + 1 streams into the other (u fixes which buffer at compile time); the
+  // draws follow the last chunk of each pass.  An empty left sector (no
+  // chunks) leaves every shot at outcome 0 with weight zero, as a draw over
+  // all-zero weights would.
+  for (int g0 = 0; g0 < total; g0 += 2) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+    for (int u = 0; u < 2; ++u) {
+      const int g = g0 + u;
+      if (g >= total) break;
+      const int q = g / nchunk, c = g - q * nchunk;
+      const int T = geo->tiles[pi][q];
+      {
+        if (g + 1 < total) {
+          issue(g + 1, u ? Bs0 : Bs1);
+          load_a(c + 1 < nchunk ? c + 1 : 0, an);
+        }
+        const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
 #pragma unroll
-        for (int t0 = 0; t0 < NT; t0 += 2) {
-          if (t0 < ntp) {
-            const float4 b0 = bsrc[((t0 + 0) * 2 + h) * 64 + lane];
-            const float4 b1 = bsrc[((t0 + 1) * 2 + h) * 64 + lane];
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 0], b0.x, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 0], b1.x, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 1], b0.y, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 1], b1.y, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 2], b0.z, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 2], b1.z, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b0.w, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b1.w, acc[t0 + 1], 0, 0, 0);
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int t0 = 0; t0 < NT; t0 += 2) {
+            if (t0 < T) {
+              const float4 b0 = bsrc[((t0 + 0) * 2 + h) * 64 + lane];
+              const float4 b1 = bsrc[((t0 + 1) * 2 + h) * 64 + lane];
+              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 0], b0.x, acc[t0], 0, 0, 0);
+              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 0], b1.x, acc[t0 + 1], 0, 0, 0);
+              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 1], b0.y, acc[t0], 0, 0, 0);
+              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 1], b1.y, acc[t0 + 1], 0, 0, 0);
+              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 2], b0.z, acc[t0], 0, 0, 0);
+              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 2], b1.z, acc[t0 + 1], 0, 0, 0);
+              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b0.w, acc[t0], 0, 0, 0);
+              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b1.w, acc[t0 + 1], 0, 0, 0);
+            }
           }
         }
+        // every wave's share of chunk g + 1 (and its A rows) has landed
+        // before any wave reads it
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (g + 1 < total) scale_a(an, a);
       }
-      // the next chunk (B' in LDS, A in registers) was issued a whole chunk ago
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (g + 1 < total) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = an[i];
-      }
-    }
-    // squared norms of the 4 rows this lane holds (rows 4*grp + v); tiles at
-    // and beyond ntp stay zero
-    float part[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float s = 0.f;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) s += acc[t][v] * acc[t][v];
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 4, 64);
-      s += __shfl_xor(s, 8, 64);
-      part[v] = s;
-    }
-    if (p >= 1 && ((p - 1) & 3) == 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t gs = shot0 + oshot[v];
-        philox4 ctr;
-        ctr.v[0] = (uint32_t)gs;
-        ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
-        ctr.v[2] = (uint32_t)site;
-        ctr.v[3] = (uint32_t)((p - 1) >> 2);
-        philox4 rr = philox4x32_10(ctr, k0, k1);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) uu[v][j] = u01_24(rr.v[j]);
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float wp = part[v];
-      bool take;
-      if (p == 0) {
-        take = true;
-      } else {
-        const float u = uu[v][(p - 1) & 3];
-        take = u * (wsum[v] + wp) < wp;
-      }
-      wsum[v] += wp;
-      if (take) {
-        psel[v] = p;
-        wsel[v] = wp;
-        if (rowok[v]) {
-          float* orow = lout + oshot[v] * ldl2;
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (t < ntp) orow[16 * t + col] = acc[t][v];
+      if (c == nchunk - 1) {
+        // draws for the outcomes of this pass, in visiting order; outcome p owns
+        // the accumulator tiles whose bits are set in `own`
+        int lo = 0;
+        for (int j = geo->j0[pi][q]; j < geo->j0[pi][q + 1]; ++j) {
+          const int p = outcome_at(j, d);
+          const int hi = lo + ((p & 1) ? nto : nte);
+          const uint32_t own = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) &
+                               ~(lo >= 32 ? 0xffffffffu : ((1u << lo) - 1u));
+          // squared norms of the 4 rows this lane holds (rows 4*grp + v)
+          float part[4] = {0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float f = ((own >> t) & 1u) ? 1.f : 0.f;
+    #pragma unroll
+            for (int v = 0; v < 4; ++v) part[v] = fmaf(f * acc[t][v], acc[t][v], part[v]);
+          }
+    #pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float s = part[v];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            part[v] = s;
+          }
+          // one uniform per (shot, site, visiting position): lane col draws it
+          // for row (col & 3) of its group, the rows' lanes fetch it by shuffle
+          float ur = 0.f;
+          if (j >= 1) {
+            const int vr = col & 3;
+            const int64_t gs =
+                shot0 + (vr == 0 ? oshot[0] : vr == 1 ? oshot[1] : vr == 2 ? oshot[2] : oshot[3]);
+            philox4 ctr;
+            ctr.v[0] = (uint32_t)gs;
+            ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
+            ctr.v[2] = (uint32_t)site;
+            ctr.v[3] = (uint32_t)j;
+            ur = u01_24(philox4x32_10(ctr, k0, k1).v[0]);
+          }
+          bool take[4];
+    #pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float wp = part[v];
+            if (j == 0) {
+              take[v] = true;
+            } else {
+              const float u = __shfl(ur, (lane & 48) | v, 64);
+              take[v] = u * (wsum[v] + wp) < wp;
+            }
+            wsum[v] += wp;
+            if (take[v]) {
+              psel[v] = p;
+              wsel[v] = wp;
+            }
+            take[v] = take[v] && rowok[v];
+          }
+          // a replacing outcome's row goes straight to its shot's output row
+          if (take[0] || take[1] || take[2] || take[3]) {
+            float* orow[4];
+    #pragma unroll
+            for (int v = 0; v < 4; ++v) orow[v] = lout + (int64_t)oshot[v] * ldl2 + col - 16 * lo;
+    #pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              if ((own >> t) & 1u) {
+    #pragma unroll
+                for (int v = 0; v < 4; ++v)
+                  if (take[v]) orow[v][16 * t] = acc[t][v];
+              }
+            }
+          }
+          lo = hi;
         }
+        // the next pass accumulates from zero
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
     }
   }
@@ -395,15 +431,51 @@ int sampler_pad(int n) { return (n + 15) / 16 * 16; }
 
 int sampler_shots_per_block() { return kShotsPerWg; }
 
-long sampler_site_floats(const SamplerSite& s, int d, long pbase[2]) {
+long sampler_geometry(const SamplerSite& s, int d, SamplerGeom* g) {
+  if (d < 1 || d > kSamplerMaxOutcomes) return -1;
+  SamplerGeom G{};
+  for (int i = 0; i < 2; ++i) {
+    if (sampler_pad(s.nL[i]) > kSamplerMaxSector || sampler_pad(s.nR[i]) > kSamplerMaxSector) return -1;
+    G.nchunk[i] = sampler_pad(s.nL[i]) / 16;
+    G.nt[i] = sampler_pad(s.nR[i]) / 8;
+  }
+  // accumulator tiles: the widest single outcome, raised towards the budget
+  // so that narrow outcomes share passes
+  int widest = 2, sum_max = 0;
+  for (int pi = 0; pi < 2; ++pi) {
+    if (s.nL[pi] <= 0) continue;
+    int sum = 0;
+    for (int p = 0; p < d; ++p) {
+      const int t = G.nt[pi ^ (p & 1)];
+      widest = std::max(widest, t);
+      sum += t;
+    }
+    sum_max = std::max(sum_max, sum);
+  }
+  G.NT = std::max(widest, std::min(kSamplerMaxTiles, sum_max));
+  G.NT += G.NT & 1;
   long tot = 0;
   for (int pi = 0; pi < 2; ++pi) {
-    if (pbase) pbase[pi] = tot;
+    G.npass[pi] = 0;
+    G.j0[pi][0] = 0;
     if (s.nL[pi] <= 0) continue;
-    const long nchunk = sampler_pad(s.nL[pi]) / 16;
-    const long nte = sampler_pad(s.nR[pi]) / 8, nto = sampler_pad(s.nR[pi ^ 1]) / 8;
-    tot += 512L * nchunk * (((d + 1) / 2) * nte + (d / 2) * nto);
+    int j = 0;
+    while (j < d) {
+      const int q = G.npass[pi]++;
+      int T = 0;
+      while (j < d) {
+        const int t = G.nt[pi ^ (outcome_at(j, d) & 1)];
+        if (T > 0 && T + t > G.NT) break;
+        T += t;
+        ++j;
+      }
+      G.tiles[pi][q] = T;
+      G.base[pi][q] = tot;
+      G.j0[pi][q + 1] = j;
+      tot += 512L * G.nchunk[pi] * T;
+    }
   }
+  if (g) *g = G;
   return tot;
 }
 
@@ -418,39 +490,40 @@ hipError_t launch_sector_mask(hipStream_t st, const cplx32* B, int K, int d, int
 }
 
 hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, const SamplerSite& s,
-                       const int32_t* mapL, const int32_t* mapR, float* P) {
+                       const SamplerGeom& g, const SamplerGeom* gd, const int32_t* mapL, const int32_t* mapR,
+                       float* P) {
   if (s.nL[0] + s.nL[1] > K || (mapR && s.nR[0] + s.nR[1] > N) || (!mapR && (s.nR[0] > N || s.nR[1] > N)))
     return hipErrorInvalidValue;
-  const SampleGeom g = make_geom(s, d);
   long mx = 0;
   for (int pi = 0; pi < 2; ++pi)
-    for (int q = 0; q < 2; ++q) mx = std::max(mx, 512L * g.nchunk[pi] * g.nt[q]);
+    for (int q = 0; q < g.npass[pi]; ++q) mx = std::max(mx, 512L * g.nchunk[pi] * g.tiles[pi][q]);
   if (mx == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((mx + 255) / 256), (unsigned)(2 * d)), dim3(256), 0, st, B, d, N,
-                     s, g, mapL, mapR, P);
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((mx + 255) / 256), (unsigned)(2 * kSamplerMaxOutcomes)), dim3(256),
+                     0, st, B, d, N, s, gd, mapL, mapR, P);
   return hipGetLastError();
 }
 
-hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerSite& s, const float* lin,
-                              const float* sin, float* lout, float* sout, long ldl2, const int32_t* perm,
-                              const int32_t* cnt, int8_t* par_out, int64_t shot0, int64_t nshots, int site,
-                              uint64_t seed, int32_t* out, int M) {
+hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerGeom& g, const SamplerGeom* gd,
+                              const float* lin, const float* sin, float* lout, float* sout, long ldl2,
+                              const int32_t* perm, const int32_t* cnt, int8_t* par_out, int64_t shot0,
+                              int64_t nshots, int site, uint64_t seed, int32_t* out, int M) {
   if (nshots <= 0) return hipSuccess;
   if ((perm == nullptr) != (cnt == nullptr)) return hipErrorInvalidValue;
-  if (!perm && s.nL[1] != 0) return hipErrorInvalidValue;
-  const SampleGeom g = make_geom(s, d);
+  if (!perm && g.npass[1] != 0) return hipErrorInvalidValue;
   for (int i = 0; i < 2; ++i)
     if (32L * g.nchunk[i] > ldl2 || 16L * g.nt[i] > ldl2) return hipErrorInvalidValue;
-  const int NT = std::max(g.nt[0], g.nt[1]);
+  for (int pi = 0; pi < 2; ++pi)
+    for (int q = 0; q < g.npass[pi]; ++q)
+      if (g.tiles[pi][q] > g.NT) return hipErrorInvalidValue;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   // with a partition, sector 1 starts on a fresh workgroup: one more block
   dim3 grid((unsigned)((nshots + kShotsPerWg - 1) / kShotsPerWg + (perm ? 1 : 0)));
 #define GBS_SAMPLE_CASE(NTV)                                                                                      \
   case NTV:                                                                                                       \
-    hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, g, d, lin, sin, lout, sout, \
-                       ldl2, perm, cnt, par_out, shot0, nshots, site, k0, k1, out, M);                           \
+    hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, gd, d, lin, sin, lout, sout, \
+                       ldl2, perm, cnt, par_out, shot0, nshots, site, k0, k1, out, M);                            \
     break;
-  switch (NT) {
+  switch (g.NT) {
     GBS_SAMPLE_CASE(2)
     GBS_SAMPLE_CASE(4)
     GBS_SAMPLE_CASE(6)
