@@ -214,22 +214,45 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
           load_a(c + 1 < nchunk ? c + 1 : 0, an);
         }
         const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
+        // Tile pairs in order.  The four B fragments of pair k + 1 (both
+        // k-halves) are read while pair k's MFMAs issue, into the other of
+        // two register sets; pair k waits only for reads issued a whole pair
+        // earlier.  A read past the pass's last pair stays inside the buffer
+        // and is not used.
+        float4 F[2][4];
+        F[0][0] = bsrc[(0 * 2 + 0) * 64 + lane];
+        F[0][1] = bsrc[(1 * 2 + 0) * 64 + lane];
+        F[0][2] = bsrc[(0 * 2 + 1) * 64 + lane];
+        F[0][3] = bsrc[(1 * 2 + 1) * 64 + lane];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-          for (int t0 = 0; t0 < NT; t0 += 2) {
-            if (t0 < T) {
-              const float4 b0 = bsrc[((t0 + 0) * 2 + h) * 64 + lane];
-              const float4 b1 = bsrc[((t0 + 1) * 2 + h) * 64 + lane];
-              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 0], b0.x, acc[t0], 0, 0, 0);
-              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 0], b1.x, acc[t0 + 1], 0, 0, 0);
-              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 1], b0.y, acc[t0], 0, 0, 0);
-              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 1], b1.y, acc[t0 + 1], 0, 0, 0);
-              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 2], b0.z, acc[t0], 0, 0, 0);
-              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 2], b1.z, acc[t0 + 1], 0, 0, 0);
-              acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b0.w, acc[t0], 0, 0, 0);
-              acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + 3], b1.w, acc[t0 + 1], 0, 0, 0);
+        for (int t0 = 0; t0 < NT; t0 += 2) {
+          if (t0 < T) {
+            const int cs = (t0 >> 1) & 1, ns = cs ^ 1;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this pair's fragments are in
+            if (t0 + 2 < NT) {
+              F[ns][0] = bsrc[((t0 + 2) * 2 + 0) * 64 + lane];
+              F[ns][1] = bsrc[((t0 + 3) * 2 + 0) * 64 + lane];
+              F[ns][2] = bsrc[((t0 + 2) * 2 + 1) * 64 + lane];
+              F[ns][3] = bsrc[((t0 + 3) * 2 + 1) * 64 + lane];
             }
+            __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], F[cs][0].x, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], F[cs][1].x, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], F[cs][0].y, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], F[cs][1].y, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], F[cs][0].z, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], F[cs][1].z, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], F[cs][0].w, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], F[cs][1].w, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4], F[cs][2].x, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4], F[cs][3].x, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[5], F[cs][2].y, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[5], F[cs][3].y, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[6], F[cs][2].z, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[6], F[cs][3].z, acc[t0 + 1], 0, 0, 0);
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[7], F[cs][2].w, acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[7], F[cs][3].w, acc[t0 + 1], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
         // every wave's share of chunk g + 1 (and its A rows) has landed
@@ -453,7 +476,7 @@ long sampler_geometry(const SamplerSite& s, int d, SamplerGeom* g) {
     sum_max = std::max(sum_max, sum);
   }
   G.NT = std::max(widest, std::min(kSamplerMaxTiles, sum_max));
-  G.NT += G.NT & 1;
+  G.NT = (G.NT + 7) / 8 * 8;  // kernel instances: 8, 16, 24, 32 tiles
   long tot = 0;
   for (int pi = 0; pi < 2; ++pi) {
     G.npass[pi] = 0;
@@ -524,21 +547,9 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const Sampl
                        ldl2, perm, cnt, par_out, shot0, nshots, site, k0, k1, out, M);                            \
     break;
   switch (g.NT) {
-    GBS_SAMPLE_CASE(2)
-    GBS_SAMPLE_CASE(4)
-    GBS_SAMPLE_CASE(6)
     GBS_SAMPLE_CASE(8)
-    GBS_SAMPLE_CASE(10)
-    GBS_SAMPLE_CASE(12)
-    GBS_SAMPLE_CASE(14)
     GBS_SAMPLE_CASE(16)
-    GBS_SAMPLE_CASE(18)
-    GBS_SAMPLE_CASE(20)
-    GBS_SAMPLE_CASE(22)
     GBS_SAMPLE_CASE(24)
-    GBS_SAMPLE_CASE(26)
-    GBS_SAMPLE_CASE(28)
-    GBS_SAMPLE_CASE(30)
     GBS_SAMPLE_CASE(32)
     default:
       return hipErrorInvalidValue;
