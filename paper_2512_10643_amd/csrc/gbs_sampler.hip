@@ -108,6 +108,11 @@ __global__ __launch_bounds__(256) void sector_mask_kernel(const cplx32* __restri
   if (m) atomicOr(&mask_r[b], m);
 }
 
+// One MFMA step with the B' fragment as the A operand and the left vectors as
+// the B operand: the accumulator tile is T^T, so lane (grp, col) holds
+// columns 16 t + 4 grp + v (v = 0..3) of shot col.
+#define GBS_MF(T_, AV, BV) acc[T_] = __builtin_amdgcn_mfma_f32_16x16x4f32(BV, AV, acc[T_], 0, 0, 0)
+
 template <int NT>
 __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, int d, const float* __restrict__ lin,
@@ -119,8 +124,8 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
   __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int grp = lane >> 4;   // k sub-block for A, row block for outputs
-  const int col = lane & 15;
+  const int grp = lane >> 4;   // k sub-block of the left vector; column quad of the output
+  const int col = lane & 15;   // shot within the wave
   // sector of this workgroup and the end of its slot range
   int pi = 0;
   const int64_t slot0 = (int64_t)blockIdx.x * kShotsPerWg;
@@ -139,31 +144,20 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   const int nchunk = geo->nchunk[pi];
   const int npass = geo->npass[pi];
   const int nte = geo->nt[pi], nto = geo->nt[pi ^ 1];
-  const int64_t wslot = slot0 + w * 16;  // first slot of this wave
-  // A operand rows: lane row = col, k = 32c + 8 grp + i
-  const bool avalid = wslot + col < send;
-  const int64_t arow = avalid ? (perm ? (int64_t)perm[wslot + col] : wslot + col) : 0;
-  const float* arow_ptr = lin + arow * ldl2 + 8 * grp;
-  const float ascale = (sin && avalid) ? sin[arow] : 1.f;
+  // this lane's shot: left-vector row for the MFMA operand and output row
+  const int64_t slot = slot0 + w * 16 + col;
+  const bool valid = slot < send;
+  const int64_t shot = valid ? (perm ? (int64_t)perm[slot] : slot) : 0;
+  const float* arow_ptr = lin + shot * ldl2 + 8 * grp;
+  const float ascale = (sin && valid) ? sin[shot] : 1.f;
   floatx4 acc[NT];
-  float wsum[4], wsel[4];
-  int psel[4];
-  bool rowok[4];
-  int oshot[4];  // chunk-local shot of output row 4 grp + v
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    wsum[v] = 0.f;
-    wsel[v] = 0.f;
-    psel[v] = 0;
-    const int64_t sl = wslot + 4 * grp + v;
-    rowok[v] = sl < send;
-    oshot[v] = rowok[v] ? (perm ? perm[sl] : (int)sl) : 0;
-  }
+  float wsum = 0.f, wsel = 0.f, ur = 0.f;
+  int psel = 0;
   // A rows arrive raw and are scaled only when they become the current
   // operand, so nothing waits on the loads before the end of the chunk
   auto load_a = [&](int c, float4* r) {
     r[0] = r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (avalid) {
+    if (valid) {
       const float4* ap = (const float4*)(arow_ptr + 32 * c);
       r[0] = ap[0];
       r[1] = ap[1];
@@ -208,128 +202,113 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
       if (g >= total) break;
       const int q = g / nchunk, c = g - q * nchunk;
       const int T = geo->tiles[pi][q];
-      {
-        if (g + 1 < total) {
-          issue(g + 1, u ? Bs0 : Bs1);
-          load_a(c + 1 < nchunk ? c + 1 : 0, an);
-        }
-        const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
-        // Tile pairs in order.  The four B fragments of pair k + 1 (both
-        // k-halves) are read while pair k's MFMAs issue, into the other of
-        // two register sets; pair k waits only for reads issued a whole pair
-        // earlier.  A read past the pass's last pair stays inside the buffer
-        // and is not used.
-        float4 F[2][4];
-        F[0][0] = bsrc[(0 * 2 + 0) * 64 + lane];
-        F[0][1] = bsrc[(1 * 2 + 0) * 64 + lane];
-        F[0][2] = bsrc[(0 * 2 + 1) * 64 + lane];
-        F[0][3] = bsrc[(1 * 2 + 1) * 64 + lane];
-#pragma unroll
-        for (int t0 = 0; t0 < NT; t0 += 2) {
-          if (t0 < T) {
-            const int cs = (t0 >> 1) & 1, ns = cs ^ 1;
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this pair's fragments are in
-            if (t0 + 2 < NT) {
-              F[ns][0] = bsrc[((t0 + 2) * 2 + 0) * 64 + lane];
-              F[ns][1] = bsrc[((t0 + 3) * 2 + 0) * 64 + lane];
-              F[ns][2] = bsrc[((t0 + 2) * 2 + 1) * 64 + lane];
-              F[ns][3] = bsrc[((t0 + 3) * 2 + 1) * 64 + lane];
-            }
-            __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], F[cs][0].x, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], F[cs][1].x, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], F[cs][0].y, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], F[cs][1].y, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], F[cs][0].z, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], F[cs][1].z, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], F[cs][0].w, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], F[cs][1].w, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4], F[cs][2].x, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4], F[cs][3].x, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[5], F[cs][2].y, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[5], F[cs][3].y, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[6], F[cs][2].z, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[6], F[cs][3].z, acc[t0 + 1], 0, 0, 0);
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[7], F[cs][2].w, acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[7], F[cs][3].w, acc[t0 + 1], 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        }
-        // every wave's share of chunk g + 1 (and its A rows) has landed
-        // before any wave reads it
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (g + 1 < total) scale_a(an, a);
+      if (g + 1 < total) {
+        issue(g + 1, u ? Bs0 : Bs1);
+        load_a(c + 1 < nchunk ? c + 1 : 0, an);
       }
+      const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
+      // Tile pairs in order.  The four B' fragments of pair k + 1 (both
+      // k-halves) are read while pair k's MFMAs issue, into the other of two
+      // register sets; pair k waits only for reads issued a whole pair
+      // earlier.  A read past the pass's last pair stays inside the buffer
+      // and is not used.
+      float4 F[2][4];
+      F[0][0] = bsrc[(0 * 2 + 0) * 64 + lane];
+      F[0][1] = bsrc[(1 * 2 + 0) * 64 + lane];
+      F[0][2] = bsrc[(0 * 2 + 1) * 64 + lane];
+      F[0][3] = bsrc[(1 * 2 + 1) * 64 + lane];
+#pragma unroll
+      for (int t0 = 0; t0 < NT; t0 += 2) {
+        if (t0 < T) {
+          const int cs = (t0 >> 1) & 1, ns = cs ^ 1;
+          __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this pair's fragments are in
+          if (t0 + 2 < NT) {
+            F[ns][0] = bsrc[((t0 + 2) * 2 + 0) * 64 + lane];
+            F[ns][1] = bsrc[((t0 + 3) * 2 + 0) * 64 + lane];
+            F[ns][2] = bsrc[((t0 + 2) * 2 + 1) * 64 + lane];
+            F[ns][3] = bsrc[((t0 + 3) * 2 + 1) * 64 + lane];
+          }
+          __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
+          GBS_MF(t0, a[0], F[cs][0].x);
+          GBS_MF(t0 + 1, a[0], F[cs][1].x);
+          GBS_MF(t0, a[1], F[cs][0].y);
+          GBS_MF(t0 + 1, a[1], F[cs][1].y);
+          GBS_MF(t0, a[2], F[cs][0].z);
+          GBS_MF(t0 + 1, a[2], F[cs][1].z);
+          GBS_MF(t0, a[3], F[cs][0].w);
+          GBS_MF(t0 + 1, a[3], F[cs][1].w);
+          GBS_MF(t0, a[4], F[cs][2].x);
+          GBS_MF(t0 + 1, a[4], F[cs][3].x);
+          GBS_MF(t0, a[5], F[cs][2].y);
+          GBS_MF(t0 + 1, a[5], F[cs][3].y);
+          GBS_MF(t0, a[6], F[cs][2].z);
+          GBS_MF(t0 + 1, a[6], F[cs][3].z);
+          GBS_MF(t0, a[7], F[cs][2].w);
+          GBS_MF(t0 + 1, a[7], F[cs][3].w);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      // every wave's share of chunk g + 1 (and its A rows) has landed before
+      // any wave reads it
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (g + 1 < total) scale_a(an, a);
       if (c == nchunk - 1) {
-        // draws for the outcomes of this pass, in visiting order; outcome p owns
-        // the accumulator tiles whose bits are set in `own`
+        // draws for the outcomes of this pass, in visiting order; outcome p
+        // owns the accumulator tiles whose bits are set in `own`
+        const int j0 = geo->j0[pi][q], j1 = geo->j0[pi][q + 1];
         int lo = 0;
-        for (int j = geo->j0[pi][q]; j < geo->j0[pi][q + 1]; ++j) {
+        for (int j = j0; j < j1; ++j) {
           const int p = outcome_at(j, d);
           const int hi = lo + ((p & 1) ? nto : nte);
           const uint32_t own = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) &
                                ~(lo >= 32 ? 0xffffffffu : ((1u << lo) - 1u));
-          // squared norms of the 4 rows this lane holds (rows 4*grp + v)
-          float part[4] = {0.f, 0.f, 0.f, 0.f};
-    #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const float f = ((own >> t) & 1u) ? 1.f : 0.f;
-    #pragma unroll
-            for (int v = 0; v < 4; ++v) part[v] = fmaf(f * acc[t][v], acc[t][v], part[v]);
-          }
-    #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            float s = part[v];
-            s += __shfl_xor(s, 1, 64);
-            s += __shfl_xor(s, 2, 64);
-            s += __shfl_xor(s, 4, 64);
-            s += __shfl_xor(s, 8, 64);
-            part[v] = s;
-          }
-          // one uniform per (shot, site, visiting position): lane col draws it
-          // for row (col & 3) of its group, the rows' lanes fetch it by shuffle
-          float ur = 0.f;
-          if (j >= 1) {
-            const int vr = col & 3;
-            const int64_t gs =
-                shot0 + (vr == 0 ? oshot[0] : vr == 1 ? oshot[1] : vr == 2 ? oshot[2] : oshot[3]);
-            philox4 ctr;
-            ctr.v[0] = (uint32_t)gs;
-            ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
-            ctr.v[2] = (uint32_t)site;
-            ctr.v[3] = (uint32_t)j;
-            ur = u01_24(philox4x32_10(ctr, k0, k1).v[0]);
-          }
-          bool take[4];
-    #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float wp = part[v];
-            if (j == 0) {
-              take[v] = true;
-            } else {
-              const float u = __shfl(ur, (lane & 48) | v, 64);
-              take[v] = u * (wsum[v] + wp) < wp;
-            }
-            wsum[v] += wp;
-            if (take[v]) {
-              psel[v] = p;
-              wsel[v] = wp;
-            }
-            take[v] = take[v] && rowok[v];
-          }
-          // a replacing outcome's row goes straight to its shot's output row
-          if (take[0] || take[1] || take[2] || take[3]) {
-            float* orow[4];
-    #pragma unroll
-            for (int v = 0; v < 4; ++v) orow[v] = lout + (int64_t)oshot[v] * ldl2 + col - 16 * lo;
-    #pragma unroll
+          // squared norm of this lane's shot: its 4 columns per tile, then the
+          // four column quads
+          float part = 0.f;
+          if (j1 - j0 == 1) {
+            // the pass's only outcome owns every nonzero tile
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) part = fmaf(acc[t][v], acc[t][v], part);
+          } else {
+#pragma unroll
             for (int t = 0; t < NT; ++t) {
-              if ((own >> t) & 1u) {
-    #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                  if (take[v]) orow[v][16 * t] = acc[t][v];
-              }
+              const float f = ((own >> t) & 1u) ? 1.f : 0.f;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) part = fmaf(f * acc[t][v], acc[t][v], part);
+            }
+          }
+          part += __shfl_xor(part, 16, 64);
+          part += __shfl_xor(part, 32, 64);
+          // uniforms: one Philox block per shot and four visiting positions,
+          // output grp drawn by lane (grp, col), fetched by the shot's lanes
+          bool take = true;
+          if (j >= 1) {
+            if (((j - 1) & 3) == 0) {
+              const int64_t gs = shot0 + shot;
+              philox4 ctr;
+              ctr.v[0] = (uint32_t)gs;
+              ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
+              ctr.v[2] = (uint32_t)site;
+              ctr.v[3] = (uint32_t)((j - 1) >> 2);
+              const philox4 rr = philox4x32_10(ctr, k0, k1);
+              ur = u01_24(grp == 0 ? rr.v[0] : grp == 1 ? rr.v[1] : grp == 2 ? rr.v[2] : rr.v[3]);
+            }
+            const float uj = __shfl(ur, (((j - 1) & 3) << 4) | col, 64);
+            take = uj * (wsum + part) < part;
+          }
+          wsum += part;
+          if (take) {
+            psel = p;
+            wsel = part;
+            // a replacing outcome's row goes straight to its shot's output row
+            if (valid) {
+              float* orow = lout + shot * ldl2 + 4 * grp - 16 * lo;
+#pragma unroll
+              for (int t = 0; t < NT; ++t)
+                if ((own >> t) & 1u) *(float4*)(orow + 16 * t) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
             }
           }
           lo = hi;
@@ -340,18 +319,14 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
       }
     }
   }
-  // row scales, samples and the parity of the new bond index
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    if (!rowok[v]) continue;
-    const int64_t ls = oshot[v];
-    if (col == 0) {
-      sout[ls] = wsel[v] > 0.f ? 1.f / sqrtf(wsel[v]) : 0.f;
-      out[(shot0 + ls) * (int64_t)M + (site - 1)] = psel[v];
-      if (par_out) par_out[ls] = (int8_t)((pi + psel[v]) & 1);
-    }
+  // row scale, sample and the parity of the new bond index
+  if (valid && grp == 0) {
+    sout[shot] = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
+    out[(shot0 + shot) * (int64_t)M + (site - 1)] = psel;
+    if (par_out) par_out[shot] = (int8_t)((pi + psel) & 1);
   }
 }
+#undef GBS_MF
 
 // Sum over the 256 threads of a block (every thread gets the total).
 __device__ inline int block_sum256(int v, int* sh) {
