@@ -154,14 +154,13 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   float wsum = 0.f, wsel = 0.f, ur = 0.f;
   int psel = 0;
   // A rows arrive raw and are scaled only when they become the current
-  // operand, so nothing waits on the loads before the end of the chunk
+  // operand, so nothing waits on the loads before the end of the chunk.  A
+  // lane past the end of the slot range reads row 0 (in bounds); it feeds
+  // only its own output column, which is never stored.
   auto load_a = [&](int c, float4* r) {
-    r[0] = r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid) {
-      const float4* ap = (const float4*)(arow_ptr + 32 * c);
-      r[0] = ap[0];
-      r[1] = ap[1];
-    }
+    const float4* ap = (const float4*)(arow_ptr + 32 * c);
+    r[0] = ap[0];
+    r[1] = ap[1];
   };
   auto scale_a = [&](const float4* r, float* a) {
     a[0] = r[0].x * ascale; a[1] = r[0].y * ascale; a[2] = r[0].z * ascale; a[3] = r[0].w * ascale;
@@ -170,20 +169,35 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   // global -> LDS by the DMA path: lane l carries 16 bytes to block base + 16 l.
   // Chunks run as one sequence over (pass, c), so the first chunk of the next
   // pass is in flight while this pass's draws are made.
-  auto issue = [&](int g, float* dst) {
-    const int q = g / nchunk, c = g - q * nchunk;
-    const int T = geo->tiles[pi][q];
-    const float* src = P + geo->base[pi][q] + 512L * c * T;
+  auto issue = [&](const float* src, int T, float* dst) {
     for (int blk = w; blk < 2 * T; blk += kWaves)  // uniform per wave
       __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
                                        (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
   };
   const int total = npass * nchunk;
+  // the chunk being multiplied (pass q, chunk c, T tiles) and the one being
+  // fetched (nq, nc, nT from nsrc), stepped without divisions; pass
+  // parameters are read from the geometry only when a pass starts
+  int q = 0, c = 0, T = total > 0 ? geo->tiles[pi][0] : 0;
+  int nq = 0, nc = 0, nT = T;
+  const float* nsrc = P + (total > 0 ? geo->base[pi][0] : 0);
+  auto advance_next = [&]() {
+    if (++nc == nchunk) {
+      nc = 0;
+      if (++nq < npass) {
+        nT = geo->tiles[pi][nq];
+        nsrc = P + geo->base[pi][nq];
+      }
+    } else {
+      nsrc += 512L * nT;
+    }
+  };
   float a[8];
   float4 an[2];
   if (total > 0) {
-    issue(0, Bs0);
+    issue(nsrc, nT, Bs0);
     load_a(0, an);
+    advance_next();
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -200,12 +214,8 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     for (int u = 0; u < 2; ++u) {
       const int g = g0 + u;
       if (g >= total) break;
-      const int q = g / nchunk, c = g - q * nchunk;
-      const int T = geo->tiles[pi][q];
-      if (g + 1 < total) {
-        issue(g + 1, u ? Bs0 : Bs1);
-        load_a(c + 1 < nchunk ? c + 1 : 0, an);
-      }
+      if (g + 1 < total) issue(nsrc, nT, u ? Bs0 : Bs1);
+      if (g + 1 < total) load_a(nc, an);
       const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
       // Tile pairs in order.  The four B' fragments of pair k + 1 (both
       // k-halves) are read while pair k's MFMAs issue, into the other of two
@@ -248,10 +258,10 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      // every wave's share of chunk g + 1 (and its A rows) has landed before
-      // any wave reads it
+      // every wave's share of chunk g + 1 (and its A rows) has landed, and
+      // its LDS reads of chunk g are done, before any wave goes on
       __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
+      __builtin_amdgcn_s_barrier();
       if (g + 1 < total) scale_a(an, a);
       if (c == nchunk - 1) {
         // draws for the outcomes of this pass, in visiting order; outcome p
@@ -317,6 +327,10 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
+      q = nq;
+      c = nc;
+      T = nT;
+      if (g + 1 < total) advance_next();
     }
   }
   // row scale, sample and the parity of the new bond index
