@@ -197,14 +197,17 @@ __device__ inline double aget(const double* P, int i, int j) {
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal matrix with zero
-// diagonal and off-diagonal t[0..n-2] (Sturm sequence of the LDL^T pivots).
-__device__ int sturm_below(const double* t, int n, double x) {
+// diagonal and squared off-diagonal t2[0..n-2] (Sturm sequence of the LDL^T
+// pivots).  The division is a full IEEE division: a hardware reciprocal
+// refined by Newton steps is not accurate enough here (near-degenerate
+// Williamson values of a 1024-mode chain move by up to 1e-10 with it).
+__device__ int sturm_below(const double* t2, int n, double x) {
   int cnt = 0;
   double d = -x;
   if (d < 0.0) ++cnt;
   for (int i = 1; i < n; ++i) {
     if (d == 0.0) d = 1e-300;
-    d = -x - t[i - 1] * t[i - 1] / d;
+    d = -x - t2[i - 1] / d;
     if (d < 0.0) ++cnt;
   }
   return cnt;
@@ -397,15 +400,31 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
       Lm[(long)i * ld + j] = j <= i ? P[pk(i, j)] : 0.0;
     }
   }
-  // W = Omega L: W_k = L_{k+nL} (k < nL), -L_{k-nL} (k >= nL).
+  // A = L^T Omega L = sum_k (x_k p_k^T - p_k x_k^T) over the rows x_k, p_k of
+  // L (mode k).  With the structured factor, row x_k of an r mode has one
+  // entry (column k, sx_k) and row p_k one (column nr + k, sp_k), so A is the
+  // pair entries +-sx_k sp_k plus the rank-2 term of the new mode's rows; a
+  // general factor goes through a product with W = Omega L.
   wg_sync();
-  for (long e = tid; e < (long)N2 * N2; e += nt) {
-    int k = (int)(e / N2), j = (int)(e % N2);
-    W[(long)k * ld + j] = k < nL ? Lm[(long)(k + nL) * ld + j] : -Lm[(long)(k - nL) * ld + j];
+  if (structured) {
+    const double* Xa = Lm + (long)(nL - 1) * ld;
+    const double* Pa = Lm + (long)(2 * nL - 1) * ld;
+    for (long e = tid; e < (long)N2 * N2; e += nt) {
+      const int i = (int)(e / N2), j = (int)(e % N2);
+      double v = Xa[i] * Pa[j] - Pa[i] * Xa[j];
+      if (i < nr && j == nr + i) v += Lm[(long)i * ld + i] * Lm[(long)(nL + i) * ld + j];
+      if (j < nr && i == nr + j) v -= Lm[(long)j * ld + j] * Lm[(long)(nL + j) * ld + i];
+      Am[(long)i * ld + j] = v;
+    }
+  } else {
+    // W = Omega L: W_k = L_{k+nL} (k < nL), -L_{k-nL} (k >= nL).
+    for (long e = tid; e < (long)N2 * N2; e += nt) {
+      int k = (int)(e / N2), j = (int)(e % N2);
+      W[(long)k * ld + j] = k < nL ? Lm[(long)(k + nL) * ld + j] : -Lm[(long)(k - nL) * ld + j];
+    }
+    wg_sync();
+    wg_dgemm(N2, N2, N2, 1.0, Lm, ld, true, W, ld, false, 0.0, Am, ld, nullptr);
   }
-  wg_sync();
-  // A = L^T W, antisymmetric; its strict lower triangle, packed, is reduced below.
-  wg_dgemm(N2, N2, N2, 1.0, Lm, ld, true, W, ld, false, 0.0, Am, ld, nullptr);
   wg_sync();
   for (long e = tid; e < (long)N2 * N2; e += nt) {
     const int i = (int)(e / N2), j = (int)(e % N2);
@@ -467,6 +486,9 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   const double bound = 2.0 * tm + 1e-300;
   const double tiny = 2.2e-16 * bound + 1e-300;
   const int n = nL;
+  double* t2L = pL;  // squared off-diagonal for the Sturm counts (pL is free now)
+  for (int i = tid; i < N2 - 1; i += nt) t2L[i] = tL[i] * tL[i];
+  wg_sync();
   // 8-section: the 8 lanes of a group test 8 interior points of the interval
   // at once (the Sturm count is monotone in x), so each round shrinks it 9x
   {
@@ -478,7 +500,7 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
       double lo = 0.0, hi = bound;
       for (int it = 0; it < 17; ++it) {
         const double x = lo + (hi - lo) * (double)(gl + 1) / 9.0;
-        const bool below = live && sturm_below(tL, N2, x) <= N2 - 1 - q;
+        const bool below = live && sturm_below(t2L, N2, x) <= N2 - 1 - q;
         const unsigned long long bal = __ballot(below);
         const int j = __popcll((bal >> sh) & 0xFFull);   // points at or below the target
         const double xl = __shfl(x, sh + (j > 0 ? j - 1 : 0), 64);
@@ -639,7 +661,7 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   double* Lm = a.ws_L;
   double* Am = a.ws_A;
   double* Ev = a.ws_E;
-  double* AE = a.ws_B;   // A E
+  const double* AU = a.ws_B;   // A u_q from stage 1, column q
   double* Om = a.ws_O;   // pairs [u.., v..] (unscaled, unsorted)
   double* Op = a.ws_W;   // sorted, scaled pairs
   double* Sm = a.ws_S;
@@ -651,8 +673,6 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   const long ldd = a.ld_drr, ldc = a.ld_cr;
   const int gxa = m - 1, gpa = M + m - 1;
 
-  // A E (all eigenvectors; columns in original order)
-  wg_dgemm(N2, N2, N2, 1.0, Am, ld, false, Ev, ld, false, 0.0, AE, ld, tiles);
   // eigenvalue clusters in descending order (relative gap 1e-6)
   if (tid == 0) {
     int nc = 0;
@@ -684,21 +704,33 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
     if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_WILLIAMSON);
     return;
   }
+  // (stage 1 gives the eigenvectors in pairs: column 2q = u_q, and a pair's
+  // two equal eigenvalues are never split between clusters, so a two-vector
+  // cluster starts at an even column and A u_q is column q of AU)
   for (int c = wv; c < ncl; c += nwv) {
     const int j0 = cl_start[c], sz = cl_start[c + 1] - j0;
     if (sz != 2) continue;
     const int col = ord[j0], slot = pair_src[c];
+    if (col & 1) {
+      if (lane == 0) bad = 1;
+      continue;
+    }
+    const double* au_q = AU + (col >> 1);
     double s = 0.0;
-    for (int k = lane; k < N2; k += 64) s += AE[(long)k * ld + col] * AE[(long)k * ld + col];
+    for (int k = lane; k < N2; k += 64) s += au_q[(long)k * ld] * au_q[(long)k * ld];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     const double dl = sqrt(s);
     for (int k = lane; k < N2; k += 64) {
       Om[(long)k * ld + slot] = Ev[(long)k * ld + col];
-      Om[(long)k * ld + nL + slot] = -AE[(long)k * ld + col] / dl;
+      Om[(long)k * ld + nL + slot] = -au_q[(long)k * ld] / dl;
     }
     if (lane == 0) dsel[slot] = dl;
   }
   wg_sync();
+  if (bad) {
+    if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_WILLIAMSON);
+    return;
+  }
   double* e_v = a.ws_vec;
   double* au = a.ws_vec + ld;
   double* dots = lds + 2 * TILE * (TILE + 1);  // up to N2 dot products

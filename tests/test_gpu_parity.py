@@ -395,25 +395,33 @@ def test_c5_gaussian_chain_against_oracle(torch_cuda):
     to 1e-11.  (Lambda itself is compared through Lambda^2: for modes just
     above the frozen-mode threshold, D - 1 ~ 1e-10, the ~1e-12 absolute
     precision of D in FP64 leaves Lambda ~ 1e-5 with relative errors ~1e-3 on
-    either side, while the weight it carries is ~1e-10.)"""
+    either side, while the weight it carries is ~1e-10.)  A mode whose D lies
+    within that precision of the threshold D* (Sec. II.A) may be counted on
+    either side: such a mode, present in one list only, must have
+    |D - D*| <= 1e-12."""
     _say("case: c5 full size (M=1024, d=4, chi=512) Gaussian chain vs oracle")
     g = _golden("c5_gsvd")
     w = W.workload("c5")
     h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
     inf = h.info()
-    assert inf["ne"][1:w.M] == g["n_e"]
-    worst, where = 0.0, None
+    th, band = 1e-10, 1e-12           # D* - 1 of the build (default dstar) and D's precision
+    dm1 = lambda lam: 2.0 * lam ** 2 / (1.0 - lam ** 2)   # D - 1 from Lambda
+    worst, where, ambiguous = 0.0, None, 0
     for m in range(1, w.M):
-        lam = h.export(m, "lambda")
-        ref = np.array(g["lam"][m - 1])
-        assert lam.shape == ref.shape, m
-        if ref.size:
-            err2 = np.abs(lam ** 2 - ref ** 2)
-            k = int(np.argmax(err2))
-            if err2[k] > worst:
-                worst, where = float(err2[k]), (m, k, float(ref[k]))
+        lam = np.sort(h.export(m, "lambda"))[::-1]
+        ref = np.sort(np.array(g["lam"][m - 1]))[::-1]
+        assert len(lam) == inf["ne"][m], m
+        k = min(len(lam), len(ref))
+        extra = lam[k:] if len(lam) > k else ref[k:]
+        assert np.all(np.abs(dm1(extra) - th) <= band), (m, len(lam), len(ref), dm1(extra))
+        ambiguous += len(extra)
+        if k:
+            err2 = np.abs(lam[:k] ** 2 - ref[:k] ** 2)
+            i = int(np.argmax(err2))
+            if err2[i] > worst:
+                worst, where = float(err2[i]), (m, i, float(ref[i]))
     _say(f"  max |Lambda^2_gpu - Lambda^2_oracle| over all cuts = {worst:.3e} at (cut, index, Lambda) {where}; "
-         f"max bond {inf['max_bond']}")
+         f"modes within 1e-12 of D* counted on one side only: {ambiguous}; max bond {inf['max_bond']}")
     assert worst <= 1e-11
     assert 1 <= inf["max_bond"] <= w.chi
     s = h.sample(2000, seed=11)
