@@ -548,6 +548,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     ga.cr_out = cr[m & 1];
     HIP_CHECK_RET(launch_gsvd_cut(st, ga, m, n2max));
   }
+  HIP_CHECK_RET(launch_gsvd_last_q(st, ga));
   std::vector<int> ne(M + 1);
   std::vector<double> lamh((size_t)(M + 1) * ga.ld_dsym);
   int herr = 0;

@@ -32,4 +32,8 @@ struct GsvdArgs {
 };
 
 hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* scal, double* wsM, int* err);
+// Cut m: Williamson step of cut m (with, beside it, Q^{m-1} of the previous
+// cut) and the pairing and residual of cut m.
 hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max);
+// Q^M of the last site, after the last cut.
+hipError_t launch_gsvd_last_q(hipStream_t st, const GsvdArgs& a);

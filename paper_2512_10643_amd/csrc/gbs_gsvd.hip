@@ -263,8 +263,115 @@ __device__ void tri_shift_solve_il(const double* t, int n, double s, double* y, 
 
 }  // namespace
 
+// Bogoliubov U, V of cut m from its S (Eq. MUV), (U^dag)^-1 and the pair
+// matrix Q^m.  Nothing later in the chain reads these, so the workgroup that
+// computes them for cut m runs beside the Williamson step of cut m + 1.
+__device__ void q_from_s(const GsvdArgs& a, int m) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  if (*a.err) return;
+  const int nL = a.ne[m - 1] + 1;
+  const int ne = a.ne[m];
+  const long ld = a.ld_ws;
+  const double* Sm = a.ws_S;
+  // U, V from S (Eq. MUV)
+  cplx64* U = a.ws_U;
+  cplx64* V = a.ws_V;
+  cplx64* Aug = a.ws_aug;
+  const long ldu = a.ld_u;
+  for (long e = tid; e < (long)nL * nL; e += nt) {
+    int i = (int)(e / nL), j = (int)(e % nL);
+    double s11 = Sm[(long)i * ld + j], s12 = Sm[(long)i * ld + nL + j];
+    double s21 = Sm[(long)(nL + i) * ld + j], s22 = Sm[(long)(nL + i) * ld + nL + j];
+    U[i * ldu + j] = cmake<cplx64>(0.5 * (s21 - s12), -0.5 * (s11 + s22));
+    V[i * ldu + j] = cmake<cplx64>(0.5 * (-s12 - s21), -0.5 * (s11 - s22));
+  }
+  wg_sync();
+  // (U^dag)^-1 by Gauss-Jordan with partial pivoting on [U^dag | I]
+  for (long e = tid; e < (long)nL * 2 * nL; e += nt) {
+    int i = (int)(e / (2 * nL)), j = (int)(e % (2 * nL));
+    Aug[i * 2 * ldu + j] = j < nL ? cconj(U[(long)j * ldu + i]) : cmake<cplx64>(j - nL == i ? 1.0 : 0.0, 0.0);
+  }
+  wg_sync();
+  __shared__ int piv_row, sing;
+  for (int col = 0; col < nL; ++col) {
+    // pivot search by wave 0
+    if (wv == 0) {
+      double bv = -1.0;
+      int best = col;
+      for (int r = col + lane; r < nL; r += 64) {
+        double v = cabs2(Aug[(long)r * 2 * ldu + col]);
+        if (v > bv) { bv = v; best = r; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(bv, off, 64);
+        int ob = __shfl_xor(best, off, 64);
+        if (ov > bv || (ov == bv && ob < best)) { bv = ov; best = ob; }
+      }
+      if (lane == 0) {
+        piv_row = best;
+        sing = !(bv > 1e-280);
+      }
+    }
+    wg_sync();
+    if (sing) {
+      if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_SINGULAR);
+      return;
+    }
+    const int pr = piv_row;
+    if (pr != col) {
+      for (int j = tid; j < 2 * nL; j += nt) {
+        cplx64 t = Aug[(long)col * 2 * ldu + j];
+        Aug[(long)col * 2 * ldu + j] = Aug[(long)pr * 2 * ldu + j];
+        Aug[(long)pr * 2 * ldu + j] = t;
+      }
+    }
+    wg_sync();
+    cplx64 pv = Aug[(long)col * 2 * ldu + col];
+    double pn = cabs2(pv);
+    cplx64 pinv = cmake<cplx64>(pv.re / pn, -pv.im / pn);
+    wg_sync();
+    for (int j = tid; j < 2 * nL; j += nt) Aug[(long)col * 2 * ldu + j] = cmul(Aug[(long)col * 2 * ldu + j], pinv);
+    wg_sync();
+    for (long e = tid; e < (long)nL * 2 * nL; e += nt) {
+      int r = (int)(e / (2 * nL)), j = (int)(e % (2 * nL));
+      if (r == col || j == col) continue;
+      cplx64 f = Aug[(long)r * 2 * ldu + col];
+      Aug[(long)r * 2 * ldu + j] = csub(Aug[(long)r * 2 * ldu + j], cmul(f, Aug[(long)col * 2 * ldu + j]));
+    }
+    wg_sync();
+    for (int r = tid; r < nL; r += nt)
+      if (r != col) Aug[(long)r * 2 * ldu + col] = cmake<cplx64>(0.0, 0.0);
+    wg_sync();
+  }
+  // Q^m on (r_{m-1}, a_m, l_m): [[Uih V^dag, Uih[:, :ne]], [.^T, -V^T Uih]]
+  const int nmod = nL + ne;
+  cplx64* Q = a.Q + (long)(m - 1) * a.q_stride;
+  const long ldq = a.ld_q;
+  for (long e = tid; e < (long)nmod * nmod; e += nt) {
+    int i = (int)(e / nmod), j = (int)(e % nmod);
+    cplx64 s = cmake<cplx64>(0.0, 0.0);
+    if (i < nL && j < nL) {
+      for (int k = 0; k < nL; ++k) cfma(s, Aug[(long)i * 2 * ldu + nL + k], cconj(V[(long)j * ldu + k]));
+    } else if (i < nL) {
+      s = Aug[(long)i * 2 * ldu + nL + (j - nL)];
+    } else if (j < nL) {
+      s = Aug[(long)j * 2 * ldu + nL + (i - nL)];
+    } else {
+      int q1 = i - nL, q2 = j - nL;
+      for (int k = 0; k < nL; ++k) cfma(s, V[(long)k * ldu + q1], Aug[(long)k * 2 * ldu + nL + q2]);
+      s = cmake<cplx64>(-s.re, -s.im);
+    }
+    Q[(long)i * ldq + j] = s;
+  }
+}
+
 // Stage 1.
 __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
+  if (blockIdx.x == 1) {  // Q^{m-1} beside the Williamson step of cut m
+    q_from_s(a, m - 1);
+    return;
+  }
   const int tid = threadIdx.x, nt = blockDim.x;
   const int M = a.M;
   if (*a.err) return;
@@ -552,7 +659,7 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   // different blocks), re-orthogonalise all of them in order (modified
   // Gram-Schmidt against the accurate earlier vectors restores it).
   {
-    double* Gz = a.ws_S;  // n x n
+    double* Gz = a.ws_W;  // n x n (W is free here; S of the previous cut is still read)
     wg_dgemm(n, n, N2, 1.0, Z, n, true, Z, n, false, 0.0, Gz, ld, nullptr);
     wg_sync();
     double dev = 0.0;
@@ -822,96 +929,7 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   }
   wg_sync();
   const int ne = flag;
-  // U, V from S (Eq. MUV)
-  cplx64* U = a.ws_U;
-  cplx64* V = a.ws_V;
-  cplx64* Aug = a.ws_aug;
-  const long ldu = a.ld_u;
-  for (long e = tid; e < (long)nL * nL; e += nt) {
-    int i = (int)(e / nL), j = (int)(e % nL);
-    double s11 = Sm[(long)i * ld + j], s12 = Sm[(long)i * ld + nL + j];
-    double s21 = Sm[(long)(nL + i) * ld + j], s22 = Sm[(long)(nL + i) * ld + nL + j];
-    U[i * ldu + j] = cmake<cplx64>(0.5 * (s21 - s12), -0.5 * (s11 + s22));
-    V[i * ldu + j] = cmake<cplx64>(0.5 * (-s12 - s21), -0.5 * (s11 - s22));
-  }
-  wg_sync();
-  // (U^dag)^-1 by Gauss-Jordan with partial pivoting on [U^dag | I]
-  for (long e = tid; e < (long)nL * 2 * nL; e += nt) {
-    int i = (int)(e / (2 * nL)), j = (int)(e % (2 * nL));
-    Aug[i * 2 * ldu + j] = j < nL ? cconj(U[(long)j * ldu + i]) : cmake<cplx64>(j - nL == i ? 1.0 : 0.0, 0.0);
-  }
-  wg_sync();
-  __shared__ int piv_row;
-  for (int col = 0; col < nL; ++col) {
-    // pivot search by wave 0
-    if (wv == 0) {
-      double bv = -1.0;
-      int best = col;
-      for (int r = col + lane; r < nL; r += 64) {
-        double v = cabs2(Aug[(long)r * 2 * ldu + col]);
-        if (v > bv) { bv = v; best = r; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(bv, off, 64);
-        int ob = __shfl_xor(best, off, 64);
-        if (ov > bv || (ov == bv && ob < best)) { bv = ov; best = ob; }
-      }
-      if (lane == 0) {
-        piv_row = best;
-        bad = !(bv > 1e-280);
-      }
-    }
-    wg_sync();
-    if (bad) {
-      if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_SINGULAR);
-      return;
-    }
-    const int pr = piv_row;
-    if (pr != col) {
-      for (int j = tid; j < 2 * nL; j += nt) {
-        cplx64 t = Aug[(long)col * 2 * ldu + j];
-        Aug[(long)col * 2 * ldu + j] = Aug[(long)pr * 2 * ldu + j];
-        Aug[(long)pr * 2 * ldu + j] = t;
-      }
-    }
-    wg_sync();
-    cplx64 pv = Aug[(long)col * 2 * ldu + col];
-    double pn = cabs2(pv);
-    cplx64 pinv = cmake<cplx64>(pv.re / pn, -pv.im / pn);
-    wg_sync();
-    for (int j = tid; j < 2 * nL; j += nt) Aug[(long)col * 2 * ldu + j] = cmul(Aug[(long)col * 2 * ldu + j], pinv);
-    wg_sync();
-    for (long e = tid; e < (long)nL * 2 * nL; e += nt) {
-      int r = (int)(e / (2 * nL)), j = (int)(e % (2 * nL));
-      if (r == col || j == col) continue;
-      cplx64 f = Aug[(long)r * 2 * ldu + col];
-      Aug[(long)r * 2 * ldu + j] = csub(Aug[(long)r * 2 * ldu + j], cmul(f, Aug[(long)col * 2 * ldu + j]));
-    }
-    wg_sync();
-    for (int r = tid; r < nL; r += nt)
-      if (r != col) Aug[(long)r * 2 * ldu + col] = cmake<cplx64>(0.0, 0.0);
-    wg_sync();
-  }
-  // Q^m on (r_{m-1}, a_m, l_m): [[Uih V^dag, Uih[:, :ne]], [.^T, -V^T Uih]]
-  const int nmod = nL + ne;
-  cplx64* Q = a.Q + (long)(m - 1) * a.q_stride;
-  const long ldq = a.ld_q;
-  for (long e = tid; e < (long)nmod * nmod; e += nt) {
-    int i = (int)(e / nmod), j = (int)(e % nmod);
-    cplx64 s = cmake<cplx64>(0.0, 0.0);
-    if (i < nL && j < nL) {
-      for (int k = 0; k < nL; ++k) cfma(s, Aug[(long)i * 2 * ldu + nL + k], cconj(V[(long)j * ldu + k]));
-    } else if (i < nL) {
-      s = Aug[(long)i * 2 * ldu + nL + (j - nL)];
-    } else if (j < nL) {
-      s = Aug[(long)j * 2 * ldu + nL + (i - nL)];
-    } else {
-      int q1 = i - nL, q2 = j - nL;
-      for (int k = 0; k < nL; ++k) cfma(s, V[(long)k * ldu + q1], Aug[(long)k * 2 * ldu + nL + q2]);
-      s = cmake<cplx64>(-s.re, -s.im);
-    }
-    Q[(long)i * ldq + j] = s;
-  }
+  if (m == M) return;  // the last site's Q^M is computed from S by q_from_s
   if (m == M) return;
   wg_sync();
   // Next residual.  T = -S^T Omega; T_act rows: x_b,q -> q, p_b,q -> nL + q.
@@ -940,10 +958,12 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   wg_dgemm(2 * ne, nR, N2, 1.0, Ta, ld, false, GLR + nR, a.ld_glr, false, 0.0, a.cr_out + M + m, ldc, tiles);
 }
 
+__global__ __launch_bounds__(1024) void gsvd_q_kernel(GsvdArgs a, int m) { q_from_s(a, m); }
+
 hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max) {
   (void)n2max;
   const size_t lds1 = sizeof(double) * ((size_t)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2);
-  hipLaunchKernelGGL(gsvd_stage1_kernel, dim3(1), dim3(1024), lds1, st, a, m);
+  hipLaunchKernelGGL(gsvd_stage1_kernel, dim3(m >= 2 ? 2 : 1), dim3(1024), lds1, st, a, m);
   const size_t lds3 = sizeof(double) * ((size_t)2 * 32 * 33 + GBS_GSVD_N2_MAX + 8);
   hipLaunchKernelGGL(gsvd_stage2_kernel, dim3(1), dim3(1024), lds3, st, a, m);
   return hipGetLastError();
@@ -956,5 +976,10 @@ hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* s
   hipLaunchKernelGGL(validate_sym_kernel, dim3(64), dim3(256), 0, st, gamma, n2, scal + 0, scal + 1);
   hipLaunchKernelGGL(purity_kernel, dim3((n2 + 15) / 16, (n2 + 15) / 16), dim3(256), 0, st, gamma, M, scal + 2);
   hipLaunchKernelGGL(chol_xx_kernel, dim3(1), dim3(1024), 0, st, gamma, M, wsM, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_gsvd_last_q(hipStream_t st, const GsvdArgs& a) {
+  hipLaunchKernelGGL(gsvd_q_kernel, dim3(1), dim3(1024), 0, st, a, a.M);
   return hipGetLastError();
 }
