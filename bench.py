@@ -45,22 +45,23 @@ def sampling_flops_per_shot(bonds, d):
     return sum(8.0 * d * bonds[m - 1] * bonds[m] for m in range(1, len(bonds)))
 
 
-def sector_flops_per_shot(sectors, d, samples, pad=1):
+def sector_flops_per_shot(sectors, d, samples, padr=1, padc=1):
     """Flops of one shot when each bond splits into photon-parity sectors:
     a shot whose bond m-1 lies in sector pi multiplies n_pi(m-1) rows by the
     n_{pi ^ (p & 1)}(m) columns of every outcome p.  The sector of bond m-1 is
     the parity of the photons drawn at sites 1..m-1, taken from `samples`
-    (device tensor).  pad=16 counts the padded tiles the kernel executes."""
+    (device tensor).  padr=8, padc=16 count the padded rows and tiles the
+    kernel executes."""
     import torch
     M = samples.shape[1]
     pre = torch.cumsum(samples, dim=1, dtype=torch.int64) - samples  # photons before site m
     f1 = (pre % 2).double().mean(0).cpu().numpy()                    # fraction in sector 1
-    padn = lambda n: -(-int(n) // pad) * pad
+    padn = lambda n, q: -(-int(n) // q) * q
     tot = 0.0
     for m in range(1, M + 1):
         for pi, f in ((0, 1.0 - f1[m - 1]), (1, f1[m - 1])):
-            cols = sum(padn(sectors[m][pi ^ (p & 1)]) for p in range(d))
-            tot += f * 8.0 * padn(sectors[m - 1][pi]) * cols
+            cols = sum(padn(sectors[m][pi ^ (p & 1)], padc) for p in range(d))
+            tot += f * 8.0 * padn(sectors[m - 1][pi], padr) * cols
     return tot
 
 
@@ -258,7 +259,7 @@ def main():
     sec = recs[-1]["sectors"]
     if sec is not None:
         fl_shot = sector_flops_per_shot(sec, w.d, out)
-        fl_exec = sector_flops_per_shot(sec, w.d, out, pad=16)
+        fl_exec = sector_flops_per_shot(sec, w.d, out, padr=8, padc=16)
     else:
         fl_shot = fl_dense
         fl_exec = sampling_flops_per_shot([-(-b // 16) * 16 for b in bonds], w.d)

@@ -31,12 +31,15 @@ struct SamplerSite {
 };
 
 // Launch geometry of one site (host and device copies).  For left sector pi:
-// nchunk[pi] K-chunks of 32 real rows; right sector s is nt[s] tiles wide;
+// nchunk[pi] K-chunks of 32 real rows, the last of each pass holding only
+// its first 16 when half[pi] (rows are padded to 8 complex entries); right
+// sector s is nt[s] tiles wide;
 // pass q covers visiting positions [j0[pi][q], j0[pi][q + 1]) with
 // tiles[pi][q] tiles per chunk, its chunks starting at float base[pi][q] of
 // the packed operand.  NT: accumulator tiles of the kernel instance.
 struct SamplerGeom {
   int nchunk[2];
+  int half[2];
   int nt[2];
   int npass[2];
   int NT;

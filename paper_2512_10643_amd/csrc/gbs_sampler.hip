@@ -50,12 +50,13 @@ __host__ __device__ inline int outcome_at(int j, int d) {
 
 // Packed layout of B' for one site, per left sector pi and pass q, one 1 KiB
 // block per (c, t, h):
-//   P[pi][q][c][t][h][lane][j] = B'_{pi,q}[32 c + 8 (lane/16) + 4 h + j][16 t + lane%16]
+//   P[pi][q][c][t][h][lane][j] = B'_{pi,q}[32 c + 16 h + 4 (lane/16) + j][16 t + lane%16]
 // where B'_{pi,q} is the real embedding of B restricted to the rows of left
 // sector pi (sector-local order) and, side by side, the columns of right
 // sector pi ^ (p & 1) of every outcome p of the pass, each padded to whole
 // tiles.  c: chunk of 32 real K rows, t: 16-column tile, h: half of the
-// chunk's 8 k-steps, j: k-step within the half (4 per 16-byte read).
+// chunk (16 rows, 4 k-steps), j: k-step within the half (4 per 16-byte
+// read).  A half last chunk stores only its h = 0 blocks.
 __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerSite s,
                             const SamplerGeom* __restrict__ g, const int32_t* __restrict__ mapL,
                             const int32_t* __restrict__ mapR, float* __restrict__ P) {
@@ -63,12 +64,22 @@ __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerS
   if (s.nL[pi] == 0 || q >= g->npass[pi]) return;
   const int T = g->tiles[pi][q];
   const long per_chunk = 512L * T;
+  const int nfull = g->nchunk[pi] - g->half[pi];
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= per_chunk * g->nchunk[pi]) return;
-  const int c = (int)(e / per_chunk);
-  const int r = (int)(e % per_chunk);
-  const int j = r & 3, lane = (r >> 2) & 63, h = (r >> 8) & 1;
-  int t = r >> 9;
+  if (e >= per_chunk * nfull + (g->half[pi] ? 256L * T : 0)) return;
+  int c, r, h, t;
+  if (e < per_chunk * nfull) {
+    c = (int)(e / per_chunk);
+    r = (int)(e % per_chunk);
+    h = (r >> 8) & 1;
+    t = r >> 9;
+  } else {  // half chunk: blocks (t, h = 0) only
+    c = nfull;
+    r = (int)(e - per_chunk * nfull);
+    h = 0;
+    t = r >> 8;
+  }
+  const int j = r & 3, lane = (r >> 2) & 63;
   // the outcome owning tile t
   int jo = g->j0[pi][q], p = outcome_at(jo, d), sig = pi ^ (p & 1);
   while (t >= g->nt[sig]) {
@@ -76,7 +87,7 @@ __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerS
     p = outcome_at(++jo, d);
     sig = pi ^ (p & 1);
   }
-  const int kr = 32 * c + 8 * (lane >> 4) + 4 * h + j;  // real row of B'
+  const int kr = 32 * c + 16 * h + 4 * (lane >> 4) + j;  // real row of B'
   const int nr = 16 * t + (lane & 15);                  // real column within outcome p
   const int k = kr >> 1, a = kr & 1, jj = nr >> 1, bcol = nr & 1;
   float v = 0.f;
@@ -142,13 +153,14 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     if (slot0 >= send) return;  // whole workgroup, before any barrier
   }
   const int nchunk = geo->nchunk[pi];
+  const bool halfk = geo->half[pi] != 0;  // last chunk of each pass is half
   const int npass = geo->npass[pi];
   const int nte = geo->nt[pi], nto = geo->nt[pi ^ 1];
   // this lane's shot: left-vector row for the MFMA operand and output row
   const int64_t slot = slot0 + w * 16 + col;
   const bool valid = slot < send;
   const int64_t shot = valid ? (perm ? (int64_t)perm[slot] : slot) : 0;
-  const float* arow_ptr = lin + shot * ldl2 + 8 * grp;
+  const float* arow_ptr = lin + shot * ldl2 + 4 * grp;
   const float ascale = (sin && valid) ? sin[shot] : 1.f;
   floatx4 acc[NT];
   float wsum = 0.f, wsel = 0.f, ur = 0.f;
@@ -158,9 +170,8 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   // lane past the end of the slot range reads row 0 (in bounds); it feeds
   // only its own output column, which is never stored.
   auto load_a = [&](int c, float4* r) {
-    const float4* ap = (const float4*)(arow_ptr + 32 * c);
-    r[0] = ap[0];
-    r[1] = ap[1];
+    r[0] = *(const float4*)(arow_ptr + 32 * c);       // k-half 0: rows 32c + 4 grp + (0..3)
+    r[1] = *(const float4*)(arow_ptr + 32 * c + 16);  // k-half 1: 16 rows further
   };
   auto scale_a = [&](const float4* r, float* a) {
     a[0] = r[0].x * ascale; a[1] = r[0].y * ascale; a[2] = r[0].z * ascale; a[3] = r[0].w * ascale;
@@ -169,10 +180,16 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   // global -> LDS by the DMA path: lane l carries 16 bytes to block base + 16 l.
   // Chunks run as one sequence over (pass, c), so the first chunk of the next
   // pass is in flight while this pass's draws are made.
-  auto issue = [&](const float* src, int T, float* dst) {
-    for (int blk = w; blk < 2 * T; blk += kWaves)  // uniform per wave
-      __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
-                                       (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
+  auto issue = [&](const float* src, int T, float* dst, bool halfc) {
+    if (halfc) {  // blocks (t, h = 0) of a half chunk land where a full chunk has them
+      for (int blk = w; blk < T; blk += kWaves)
+        __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
+                                         (void __attribute__((address_space(3)))*)(dst + 2 * blk * 256), 16, 0, 0);
+    } else {
+      for (int blk = w; blk < 2 * T; blk += kWaves)  // uniform per wave
+        __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
+                                         (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
+    }
   };
   const int total = npass * nchunk;
   // the chunk being multiplied (pass q, chunk c, T tiles) and the one being
@@ -195,7 +212,7 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   float a[8];
   float4 an[2];
   if (total > 0) {
-    issue(nsrc, nT, Bs0);
+    issue(nsrc, nT, Bs0, halfk && nchunk == 1);
     load_a(0, an);
     advance_next();
   }
@@ -214,9 +231,10 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     for (int u = 0; u < 2; ++u) {
       const int g = g0 + u;
       if (g >= total) break;
-      if (g + 1 < total) issue(nsrc, nT, u ? Bs0 : Bs1);
+      if (g + 1 < total) issue(nsrc, nT, u ? Bs0 : Bs1, halfk && nc == nchunk - 1);
       if (g + 1 < total) load_a(nc, an);
       const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
+      const bool hc = halfk && c == nchunk - 1;  // this chunk holds k-half 0 only
       // Tile pairs in order.  The four B' fragments of pair k + 1 (both
       // k-halves) are read while pair k's MFMAs issue, into the other of two
       // register sets; pair k waits only for reads issued a whole pair
@@ -247,14 +265,16 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
           GBS_MF(t0 + 1, a[2], F[cs][1].z);
           GBS_MF(t0, a[3], F[cs][0].w);
           GBS_MF(t0 + 1, a[3], F[cs][1].w);
-          GBS_MF(t0, a[4], F[cs][2].x);
-          GBS_MF(t0 + 1, a[4], F[cs][3].x);
-          GBS_MF(t0, a[5], F[cs][2].y);
-          GBS_MF(t0 + 1, a[5], F[cs][3].y);
-          GBS_MF(t0, a[6], F[cs][2].z);
-          GBS_MF(t0 + 1, a[6], F[cs][3].z);
-          GBS_MF(t0, a[7], F[cs][2].w);
-          GBS_MF(t0 + 1, a[7], F[cs][3].w);
+          if (!hc) {  // k-half 1 (absent from a half chunk)
+            GBS_MF(t0, a[4], F[cs][2].x);
+            GBS_MF(t0 + 1, a[4], F[cs][3].x);
+            GBS_MF(t0, a[5], F[cs][2].y);
+            GBS_MF(t0 + 1, a[5], F[cs][3].y);
+            GBS_MF(t0, a[6], F[cs][2].z);
+            GBS_MF(t0 + 1, a[6], F[cs][3].z);
+            GBS_MF(t0, a[7], F[cs][2].w);
+            GBS_MF(t0 + 1, a[7], F[cs][3].w);
+          }
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -448,7 +468,9 @@ long sampler_geometry(const SamplerSite& s, int d, SamplerGeom* g) {
   SamplerGeom G{};
   for (int i = 0; i < 2; ++i) {
     if (sampler_pad(s.nL[i]) > kSamplerMaxSector || sampler_pad(s.nR[i]) > kSamplerMaxSector) return -1;
-    G.nchunk[i] = sampler_pad(s.nL[i]) / 16;
+    const int nkh = (s.nL[i] + 7) / 8;  // K in halves of 16 real rows (8 complex)
+    G.nchunk[i] = (nkh + 1) / 2;
+    G.half[i] = nkh & 1;
     G.nt[i] = sampler_pad(s.nR[i]) / 8;
   }
   // accumulator tiles: the widest single outcome, raised towards the budget
@@ -484,7 +506,7 @@ long sampler_geometry(const SamplerSite& s, int d, SamplerGeom* g) {
       G.tiles[pi][q] = T;
       G.base[pi][q] = tot;
       G.j0[pi][q + 1] = j;
-      tot += 512L * G.nchunk[pi] * T;
+      tot += (512L * (G.nchunk[pi] - G.half[pi]) + 256L * G.half[pi]) * T;
     }
   }
   if (g) *g = G;
@@ -508,7 +530,7 @@ hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, con
     return hipErrorInvalidValue;
   long mx = 0;
   for (int pi = 0; pi < 2; ++pi)
-    for (int q = 0; q < g.npass[pi]; ++q) mx = std::max(mx, 512L * g.nchunk[pi] * g.tiles[pi][q]);
+    for (int q = 0; q < g.npass[pi]; ++q) mx = std::max(mx, 512L * g.nchunk[pi] * g.tiles[pi][q]);  // bound
   if (mx == 0) return hipSuccess;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((mx + 255) / 256), (unsigned)(2 * kSamplerMaxOutcomes)), dim3(256),
                      0, st, B, d, N, s, gd, mapL, mapR, P);
