@@ -685,12 +685,12 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const cplx64* __restrict__
   }
 }
 
-__global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
+__global__ __launch_bounds__(256) void bj_solve_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
                                                       long ld, long sA, int npb, int round,
                                                       const double* __restrict__ dm, double tol, int inner_sweeps,
                                                       cplx64* __restrict__ Vs, int* __restrict__ active,
                                                       int* __restrict__ vid) {
-  const int pr = blockIdx.x, b = blockIdx.y, lane = threadIdx.x;
+  const int pr = blockIdx.x, b = blockIdx.y, lane = threadIdx.x, nth = blockDim.x;
   const int n = dims ? dims[b] : (int)ld;
   const int npairs = npb / 2;
   __shared__ cplx64 S[kBP][kBP + 1], V[kBP][kBP + 1];
@@ -698,11 +698,11 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
   __shared__ int rp[kBP / 2], rq[kBP / 2];
   __shared__ double rc[kBP / 2], rs[kBP / 2];
   __shared__ cplx64 rz[kBP / 2];
-  __shared__ int anyrot;
+  __shared__ int anyrot, needs;
   if (lane == 0) bj_pair_idx(npb, round, pr, n, idx);
   __syncthreads();
   const cplx64* a = A + (long)b * sA;
-  for (int e = lane; e < kBP * kBP; e += 64) {
+  for (int e = lane; e < kBP * kBP; e += nth) {
     const int i = e / kBP, j = e % kBP, gi = idx[i], gj = idx[j];
     S[i][j] = (gi >= 0 && gj >= 0) ? a[(long)gi * ld + gj] : cmake<cplx64>(0.0, 0.0);
     V[i][j] = cmake<cplx64>(i == j ? 1.0 : 0.0, 0.0);
@@ -717,13 +717,17 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
   // passes skip this pair
   {
     bool need = false;
-    for (int e = lane; e < kBP * kBP; e += 64) {
+    for (int e = lane; e < kBP * kBP; e += nth) {
       const int i = e / kBP, j = e % kBP;
       if (j <= i || idx[i] < 0 || idx[j] < 0) continue;
       const double ab = sqrt(cabs2(S[i][j]));
       need = need || (ab > tol * sqrt(fabs(S[i][i].re * S[j][j].re)) && ab > floor_abs);
     }
-    if (__ballot(need) == 0ull) {
+    if (lane == 0) needs = 0;
+    __syncthreads();
+    if (need) needs = 1;
+    __syncthreads();
+    if (!needs) {
       if (lane == 0) vid[(long)b * npairs + pr] = 1;
       return;
     }
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
       }
       __syncthreads();
       // rows: S <- J^H S   (y_p = c x_p - s e^{i phi} x_q, y_q = s x_p + c e^{i phi} x_q)
-      for (int e = lane; e < (kBP / 2) * kBP; e += 64) {
+      for (int e = lane; e < (kBP / 2) * kBP; e += nth) {
         const int pi = e / kBP, j = e % kBP;
         const double sn = rs[pi];
         if (sn == 0.0) continue;
@@ -773,7 +777,7 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
       }
       __syncthreads();
       // columns: S <- S J and V <- V J   (y_p = c x_p - s e^{-i phi} x_q, y_q = s x_p + c e^{-i phi} x_q)
-      for (int e = lane; e < 2 * (kBP / 2) * kBP; e += 64) {
+      for (int e = lane; e < 2 * (kBP / 2) * kBP; e += nth) {
         const int mat = e / ((kBP / 2) * kBP), rem = e % ((kBP / 2) * kBP);
         const int pi = rem / kBP, i = rem % kBP;
         const double sn = rs[pi];
@@ -802,7 +806,7 @@ __global__ __launch_bounds__(64) void bj_solve_kernel(const cplx64* __restrict__
   }
   // an unconverged subproblem is fine: later rounds keep rotating its indices
   cplx64* vo = Vs + ((long)b * npairs + pr) * kBP * kBP;
-  for (int e = lane; e < kBP * kBP; e += 64) vo[e] = V[e / kBP][e % kBP];
+  for (int e = lane; e < kBP * kBP; e += nth) vo[e] = V[e / kBP][e % kBP];
 }
 
 // One half of the round's update, on FP64 matrix cores.  ROWS: the rows of
@@ -897,7 +901,7 @@ hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* 
     hipError_t e = hipMemsetAsync(active, 0, batch * sizeof(int), st);
     if (e != hipSuccess) return e;
     for (int r = 0; r < npb - 1; ++r) {
-      hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(64), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
+      hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(256), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
                          4, Vs, active, vid);
       const int nch = (nmax + kBP - 1) / kBP;
       hipLaunchKernelGGL(bj_pass_kernel<true>, dim3(npairs, nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld, sA,
