@@ -286,6 +286,10 @@ def main():
         "sites_per_s": w.M / build_s,
         "build_ms": 1000 * build_s,
         "build_phase_ms": {k: inf[k] for k in ("t_gsvd_ms", "t_kept_ms", "t_pco_ms", "t_svd_ms")},
+        # PCO tensors by the level gather: every element is produced once from
+        # the previous photon level (no dense padding, so executed = algorithmic)
+        "pco": {"elements": inf["pco_updates"], "ms": inf["t_pco_ms"],
+                "elements_per_s": inf["pco_updates"] / max(inf["t_pco_ms"], 1e-9) * 1e3},
         "samples_per_s_sampling_only": args.shots / (samp_ms / 1000.0),
         "eps_max": inf["eps_max"],
         "max_bond": inf["max_bond"],
