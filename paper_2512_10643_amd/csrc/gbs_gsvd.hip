@@ -543,25 +543,30 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   // A antisymmetric: A_sub += v p^T - p v^T with p = tau A_sub v.
   for (int k = 0; k + 2 < N2; ++k) {
     const int r = N2 - k - 1;
-    double ss = 0.0;
-    for (int i = tid; i < r; i += nt) {
-      const double x = P[pk2(k + 1 + i, k)];
-      vL[i] = x;
-      ss += x * x;
+    // the reflector of column k by the first wave alone (its r entries are
+    // reduced by shuffles), published with one barrier
+    if (tid < 64) {
+      double ss = 0.0, xf = 0.0;
+      for (int i = tid; i < r; i += 64) {
+        const double x = P[pk2(k + 1 + i, k)];
+        if (i == 0) xf = x;
+        vL[i] = x;
+        ss += x * x;
+      }
+      for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+      const double x0 = __shfl(xf, 0, 64);
+      const double alpha = sqrt(ss);
+      const double beta = x0 > 0.0 ? -alpha : alpha;
+      const double vtv = 2.0 * (ss - x0 * beta);
+      const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      if (tid == 0) {
+        vL[0] = x0 - beta;
+        tauL[k] = tau;
+        tL[k] = alpha > 0.0 ? beta : x0;
+      }
     }
-    ss = wg_sum(ss, red);
-    const double x0 = vL[0];
-    const double alpha = sqrt(ss);
-    const double beta = x0 > 0.0 ? -alpha : alpha;
-    const double vtv = 2.0 * (ss - x0 * beta);
-    const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
     wg_sync();
-    if (tid == 0) {
-      vL[0] = x0 - beta;
-      tauL[k] = tau;
-      tL[k] = alpha > 0.0 ? beta : x0;
-    }
-    wg_sync();
+    const double tau = tauL[k];
     for (int i = tid; i < r; i += nt) Vh[(long)k * ld + i] = vL[i];
     // p = tau A_sub v: 32 threads per row, rows strided by nt / 32
     for (int row = tid >> 5; row < r; row += nt >> 5) {

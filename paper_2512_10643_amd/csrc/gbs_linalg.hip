@@ -685,7 +685,7 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const cplx64* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void bj_solve_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
+__global__ __launch_bounds__(512) void bj_solve_kernel(const cplx64* __restrict__ A, const int* __restrict__ dims,
                                                       long ld, long sA, int npb, int round,
                                                       const double* __restrict__ dm, double tol, int inner_sweeps,
                                                       cplx64* __restrict__ Vs, int* __restrict__ active,
@@ -901,7 +901,7 @@ hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* 
     hipError_t e = hipMemsetAsync(active, 0, batch * sizeof(int), st);
     if (e != hipSuccess) return e;
     for (int r = 0; r < npb - 1; ++r) {
-      hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(256), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
+      hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(512), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
                          4, Vs, active, vid);
       const int nch = (nmax + kBP - 1) / kBP;
       hipLaunchKernelGGL(bj_pass_kernel<true>, dim3(npairs, nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld, sA,
