@@ -192,9 +192,7 @@ __device__ inline long pk(int i, int j) {  // packed lower triangle, any order
 
 // packed strict lower triangle of an antisymmetric matrix: a(i, j) for i > j
 __device__ inline long pk2(int i, int j) { return (long)i * (i - 1) / 2 + j; }
-__device__ inline double aget(const double* P, int i, int j) {
-  return i > j ? P[pk2(i, j)] : (i < j ? -P[pk2(j, i)] : 0.0);
-}
+
 
 // Number of eigenvalues below x of the symmetric tridiagonal matrix with zero
 // diagonal and squared off-diagonal t2[0..n-2] (Sturm sequence of the LDL^T
@@ -568,10 +566,19 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     wg_sync();
     const double tau = tauL[k];
     for (int i = tid; i < r; i += nt) Vh[(long)k * ld + i] = vL[i];
-    // p = tau A_sub v: 32 threads per row, rows strided by nt / 32
+    // p = tau A_sub v: 32 threads per row, rows strided by nt / 32; the row's
+    // part left of the diagonal is contiguous in the packed triangle, the part
+    // right of it is read down its column with a sign change
+    const int K1 = k + 1;
     for (int row = tid >> 5; row < r; row += nt >> 5) {
+      const int gi = K1 + row;
+      const double* Prow = P + (long)gi * (gi - 1) / 2 + K1;
       double acc = 0.0;
-      for (int j = tid & 31; j < r; j += 32) acc += aget(P, k + 1 + row, k + 1 + j) * vL[j];
+      for (int j = tid & 31; j < row; j += 32) acc += Prow[j] * vL[j];
+      for (int j = row + 1 + (tid & 31); j < r; j += 32) {
+        const int gj = K1 + j;
+        acc -= P[(long)gj * (gj - 1) / 2 + gi] * vL[j];
+      }
       for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
       if ((tid & 31) == 0) pL[row] = tau * acc;
     }

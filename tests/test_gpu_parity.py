@@ -398,7 +398,9 @@ def test_c5_gaussian_chain_against_oracle(torch_cuda):
     either side, while the weight it carries is ~1e-10.)  A mode whose D lies
     within that precision of the threshold D* (Sec. II.A) may be counted on
     either side: such a mode, present in one list only, must have
-    |D - D*| <= 1e-12."""
+    |D - D*| <= 1e-12.  Freezing or keeping it changes the state by its
+    weight Lambda^2 ~ (D* - 1) / 2, so after such a cut the Lambda^2 of later
+    cuts are compared to 2e-10 instead of 1e-11."""
     _say("case: c5 full size (M=1024, d=4, chi=512) Gaussian chain vs oracle")
     g = _golden("c5_gsvd")
     w = W.workload("c5")
@@ -407,6 +409,7 @@ def test_c5_gaussian_chain_against_oracle(torch_cuda):
     th, band = 1e-10, 1e-12           # D* - 1 of the build (default dstar) and D's precision
     dm1 = lambda lam: 2.0 * lam ** 2 / (1.0 - lam ** 2)   # D - 1 from Lambda
     worst, where, ambiguous = 0.0, None, 0
+    worst_after, where_after = 0.0, None   # cuts after an ambiguous freezing decision
     for m in range(1, w.M):
         lam = np.sort(h.export(m, "lambda"))[::-1]
         ref = np.sort(np.array(g["lam"][m - 1]))[::-1]
@@ -414,15 +417,19 @@ def test_c5_gaussian_chain_against_oracle(torch_cuda):
         k = min(len(lam), len(ref))
         extra = lam[k:] if len(lam) > k else ref[k:]
         assert np.all(np.abs(dm1(extra) - th) <= band), (m, len(lam), len(ref), dm1(extra))
-        ambiguous += len(extra)
         if k:
             err2 = np.abs(lam[:k] ** 2 - ref[:k] ** 2)
             i = int(np.argmax(err2))
-            if err2[i] > worst:
+            if ambiguous == 0 and err2[i] > worst:
                 worst, where = float(err2[i]), (m, i, float(ref[i]))
-    _say(f"  max |Lambda^2_gpu - Lambda^2_oracle| over all cuts = {worst:.3e} at (cut, index, Lambda) {where}; "
-         f"modes within 1e-12 of D* counted on one side only: {ambiguous}; max bond {inf['max_bond']}")
+            if ambiguous > 0 and err2[i] > worst_after:
+                worst_after, where_after = float(err2[i]), (m, i, float(ref[i]))
+        ambiguous += len(extra)
+    _say(f"  max |Lambda^2_gpu - Lambda^2_oracle| = {worst:.3e} at (cut, index, Lambda) {where}; "
+         f"modes within 1e-12 of D* counted on one side only: {ambiguous}; after the first of them "
+         f"{worst_after:.3e} at {where_after}; max bond {inf['max_bond']}")
     assert worst <= 1e-11
+    assert worst_after <= 2e-10
     assert 1 <= inf["max_bond"] <= w.chi
     s = h.sample(2000, seed=11)
     assert int((s.sum(1) % 2).abs().sum()) == 0
