@@ -632,39 +632,62 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     }
   }
   wg_sync();
-  // clusters of shifts closer than 1e-5 bound share one thread, which
-  // orthogonalises each member against the earlier ones inside the iteration
+  // clusters of shifts closer than 1e-5 bound
   if (tid == 0) {
     first[0] = 0;
     for (int q = 1; q < n; ++q) first[q] = (sig0[q - 1] - sig0[q] < 1e-5 * bound) ? first[q - 1] : q;
   }
   wg_sync();
   // z_q as column q of Z (entry i at Z[i n + q]) and per-thread scratch with
-  // the same interleaving, so a wave's threads touch consecutive addresses
+  // the same interleaving, so a wave's threads touch consecutive addresses.
+  // Two inverse-iteration solves per vector, all vectors at once (one thread
+  // each); the members of a cluster are then orthonormalised in order by one
+  // wave (modified Gram-Schmidt): their solves resolve directions whose
+  // eigenvalues are further apart than the shifts' error, and within a
+  // degenerate set any orthonormal basis is an eigenbasis.
   double* Z = a.ws_O;
   double* scr = a.ws_tri;
-  for (int q = tid; q < n; q += nt) {
-    if (first[q] != q) continue;
-    int qe = q + 1;
-    while (qe < n && first[qe] == q) ++qe;
-    for (int u = q; u < qe; ++u) {
-      for (int i = 0; i < N2; ++i) Z[(long)i * n + u] = cos(0.7 * (u + 1) * i + 0.3);
-      for (int it = 0; it < 2; ++it) {
-        tri_shift_solve_il(tL, N2, sig0[u], Z + u, n, scr + q, n, tiny);
+  for (int u = tid; u < n; u += nt) {
+    for (int i = 0; i < N2; ++i) Z[(long)i * n + u] = cos(0.7 * (u + 1) * i + 0.3);
+    for (int it = 0; it < 2; ++it) {
+      tri_shift_solve_il(tL, N2, sig0[u], Z + u, n, scr + u, n, tiny);
+      double nn = 0.0;
+      for (int i = 0; i < N2; ++i) nn += Z[(long)i * n + u] * Z[(long)i * n + u];
+      const double inv = 1.0 / sqrt(nn);
+      for (int i = 0; i < N2; ++i) Z[(long)i * n + u] *= inv;
+    }
+  }
+  wg_sync();
+  {
+    const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    auto wave_sum = [&](double x) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      return x;
+    };
+    for (int q = wv; q < n; q += nwv) {
+      if (first[q] != q || q + 1 >= n || first[q + 1] != q) continue;  // singletons need nothing
+      int qe = q + 1;
+      while (qe < n && first[qe] == q) ++qe;
+      for (int u = q; u < qe; ++u) {
         for (int v2 = q; v2 < u; ++v2) {
           double c = 0.0;
-          for (int i = 0; i < N2; ++i) c += Z[(long)i * n + v2] * Z[(long)i * n + u];
-          for (int i = 0; i < N2; ++i) Z[(long)i * n + u] -= c * Z[(long)i * n + v2];
+          for (int i = lane; i < N2; i += 64) c += Z[(long)i * n + v2] * Z[(long)i * n + u];
+          c = wave_sum(c);
+          for (int i = lane; i < N2; i += 64) Z[(long)i * n + u] -= c * Z[(long)i * n + v2];
         }
         double nn = 0.0;
-        for (int i = 0; i < N2; ++i) nn += Z[(long)i * n + u] * Z[(long)i * n + u];
-        const double inv = 1.0 / sqrt(nn);
-        for (int i = 0; i < N2; ++i) Z[(long)i * n + u] *= inv;
+        for (int i = lane; i < N2; i += 64) nn += Z[(long)i * n + u] * Z[(long)i * n + u];
+        const double inv = 1.0 / sqrt(wave_sum(nn));
+        for (int i = lane; i < N2; i += 64) Z[(long)i * n + u] *= inv;
       }
-      double rq = 0.0;  // Rayleigh quotient z^T G z
-      for (int i = 0; i + 1 < N2; ++i) rq += 2.0 * tL[i] * Z[(long)i * n + u] * Z[(long)i * n + u + n];
-      sigR[u] = fabs(rq);
     }
+  }
+  wg_sync();
+  for (int u = tid; u < n; u += nt) {
+    double rq = 0.0;  // Rayleigh quotient z^T G z
+    for (int i = 0; i + 1 < N2; ++i) rq += 2.0 * tL[i] * Z[(long)i * n + u] * Z[(long)i * n + u + n];
+    sigR[u] = fabs(rq);
   }
   wg_sync();
   // Check Z^T Z = 1; if the solves left a vector mixed (close eigenvalues in
