@@ -156,6 +156,13 @@ struct gbs_mps_s {
 
 namespace {
 
+// Shots per sampling sweep.  The MFMA sweep takes up to 2^20 rows per
+// ping-pong buffer (2 GB each at a 256-wide bond), so that a 10^6-shot call is
+// one launch per site and the last, partly filled round of workgroups is a
+// small part of it; the generic sweep keeps 2^18 (rows there are up to 16 KB).
+constexpr int64_t kSampleChunk = (int64_t)1 << 20;
+constexpr int64_t kSampleChunkGeneric = (int64_t)1 << 18;
+
 template <typename C>
 C cone() {
   return cmake<C>(1, 0);
@@ -965,7 +972,7 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   HIP_CHECK_RET(ensure_pool(st));
   const int M = h->M, d = h->d;
   const long ldl = h->maxbond;
-  const int64_t chunk = std::min<int64_t>(shots, (int64_t)1 << 18);
+  const int64_t chunk = std::min<int64_t>(shots, h->packed ? kSampleChunk : kSampleChunkGeneric);
   DevArena tmp(st);
   void* lbuf[2];
   if (h->packed) {
@@ -1172,7 +1179,8 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   // sampler operand: sector blocks pad at most 16 rows and columns each
   if (opt->prec != GBS_FP64 && chi <= 512) b += m * 16 * d * (pad + 16) * (pad + 16) + (m + 1) * chi * 8;
   // sampling buffers: rows, scales, parities and partition
-  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 0), 1 << 18);
+  const bool mfma = opt->prec != GBS_FP64 && chi <= 512 && d <= 32;
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 0), mfma ? kSampleChunk : kSampleChunkGeneric);
   b += 2 * chunk * std::max<int64_t>(chi * esz, 8 * pad) + 16 * chunk + 4096;
   return b + b / 8 + (64LL << 20);
 }
