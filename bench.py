@@ -23,6 +23,10 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 
+# Shots per launch of the MFMA sampling sweep (the library's sweep size).
+SAMPLE_CHUNK = 1 << 20
+
+
 def sampler_traffic(avg_shots):
     """HBM bytes of one interior-site sampling launch from the committed
     rocprofv3 counter summary, scaled to `avg_shots`; None when the sampler
@@ -30,12 +34,13 @@ def sampler_traffic(avg_shots):
     import hashlib
     src = os.path.join(ROOT, "paper_2512_10643_amd", "csrc", "gbs_sampler.hip")
     prof = os.path.join(ROOT, "profiles", "sample_mfma_kernel_c3_traffic.md")
+    keys = ("traffic_bytes_per_launch", "shots_per_launch", "sampler_source_sha256")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
-                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch_262144_shots", "sampler_source_sha256"))
+                      and line.split(": ", 1)[0] in keys)
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["sampler_source_sha256"].strip():
             return None
-        return float(fields["traffic_bytes_per_launch_262144_shots"]) * avg_shots / 262144.0
+        return float(fields["traffic_bytes_per_launch"]) * avg_shots / float(fields["shots_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -299,7 +304,7 @@ def main():
         "mfma_tflops_executed": fl_exec * args.shots / (samp_ms / 1000.0) / 1e12,
         "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (whole sampling sweep, all sites)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": sampler_traffic(args.shots / max(1, -(-args.shots // 262144)))
+                     "traffic": sampler_traffic(args.shots / max(1, -(-args.shots // SAMPLE_CHUNK)))
                      if args.precision != "fp64" and w.chi == 256 else None,
                      "traffic_per": "bytes of one interior-site launch (average shots per chunk)"},
     }
