@@ -50,24 +50,32 @@ def sampling_flops_per_shot(bonds, d):
     return sum(8.0 * d * bonds[m - 1] * bonds[m] for m in range(1, len(bonds)))
 
 
-def sector_flops_per_shot(sectors, d, samples, padr=1, padc=1):
-    """Flops of one shot when each bond splits into photon-parity sectors:
-    a shot whose bond m-1 lies in sector pi multiplies n_pi(m-1) rows by the
-    n_{pi ^ (p & 1)}(m) columns of every outcome p.  The sector of bond m-1 is
-    the parity of the photons drawn at sites 1..m-1, taken from `samples`
-    (device tensor).  padr=8, padc=16 count the padded rows and tiles the
-    kernel executes."""
+def evaluated_flops_per_shot(bonds, sectors, samples, padr=1, padc=1):
+    """Flops of one shot under inverse-CDF sampling with early stopping: at
+    site m a shot whose bond m-1 lies in sector pi and which draws p has formed
+    T_j for j = 0..p, each n_pi(m-1) x n_{pi ^ (j & 1)}(m) complex multiply-
+    adds (8 real flops).  pi is the parity of the photons drawn at sites
+    1..m-1, read from `samples` (device tensor).  sectors: (M+1) x 2 sector
+    sizes, or None for the whole-bond layout (one sector, every outcome
+    multiplies the whole bond).  padr=8, padc=16 count the padded rows and
+    columns the kernel executes."""
     import torch
-    M = samples.shape[1]
-    pre = torch.cumsum(samples, dim=1, dtype=torch.int64) - samples  # photons before site m
-    f1 = (pre % 2).double().mean(0).cpu().numpy()                    # fraction in sector 1
+    s = samples.to(torch.int64)
+    S, M = s.shape
+    pre = (torch.cumsum(s, dim=1) - s) % 2  # parity before site m
     padn = lambda n, q: -(-int(n) // q) * q
     tot = 0.0
     for m in range(1, M + 1):
-        for pi, f in ((0, 1.0 - f1[m - 1]), (1, f1[m - 1])):
-            cols = sum(padn(sectors[m][pi ^ (p & 1)], padc) for p in range(d))
-            tot += f * 8.0 * padn(sectors[m - 1][pi], padr) * cols
-    return tot
+        p = s[:, m - 1]
+        if sectors is None:
+            tot += 8.0 * padn(bonds[m - 1], padr) * padn(bonds[m], padc) * float((p + 1).sum().item())
+            continue
+        pi = pre[:, m - 1]
+        nl = torch.tensor([padn(sectors[m - 1][0], padr), padn(sectors[m - 1][1], padr)], device=s.device)[pi]
+        nr = torch.tensor([padn(sectors[m][0], padc), padn(sectors[m][1], padc)], device=s.device)
+        cols = (p // 2 + 1) * nr[pi] + ((p + 1) // 2) * nr[1 - pi]
+        tot += 8.0 * float((nl * cols).sum().item())
+    return tot / S
 
 
 def cpu_baseline(workload, budget_s=20.0):
@@ -262,12 +270,11 @@ def main():
     bonds = inf["bond"]
     fl_dense = sampling_flops_per_shot(bonds, w.d)
     sec = recs[-1]["sectors"]
-    if sec is not None:
-        fl_shot = sector_flops_per_shot(sec, w.d, out)
-        fl_exec = sector_flops_per_shot(sec, w.d, out, padr=8, padc=16)
+    if args.precision != "fp64":
+        fl_shot = evaluated_flops_per_shot(bonds, sec, out)
+        fl_exec = evaluated_flops_per_shot(bonds, sec, out, padr=8, padc=16)
     else:
-        fl_shot = fl_dense
-        fl_exec = sampling_flops_per_shot([-(-b // 16) * 16 for b in bonds], w.d)
+        fl_shot = fl_exec = evaluated_flops_per_shot(bonds, None, out)
     samp_ms = sum(r["sample_ev_ms"] for r in recs) / len(recs)
     build_s = sum(r["build_s"] for r in recs) / len(recs)
     achieved = fl_shot * args.shots / (samp_ms / 1000.0) / 1e12

@@ -985,14 +985,22 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
       HIP_CHECK_RET(tmp.alloc((void**)&fb[i], (size_t)chunk * ldl2 * sizeof(float)));
       HIP_CHECK_RET(tmp.alloc((void**)&sb[i], (size_t)chunk * sizeof(float)));
     }
-    int8_t* par = nullptr;
-    int32_t *perm = nullptr, *cnt = nullptr, *bcnt = nullptr;
+    // parities and their partition (sector layout); key, running sums and
+    // the partition of the shots left undecided by a site's first pass
+    int8_t *par = nullptr, *key;
+    float* cum;
+    int32_t *perm = nullptr, *cnt = nullptr, *perm2, *cnt2, *bcnt;
+    const size_t permb = (size_t)(chunk + sampler_shots_per_block()) * sizeof(int32_t);
     if (h->psplit) {
       HIP_CHECK_RET(tmp.alloc((void**)&par, (size_t)chunk));
-      HIP_CHECK_RET(tmp.alloc((void**)&perm, (size_t)(chunk + sampler_shots_per_block()) * sizeof(int32_t)));
+      HIP_CHECK_RET(tmp.alloc((void**)&perm, permb));
       HIP_CHECK_RET(tmp.alloc((void**)&cnt, 2 * sizeof(int32_t)));
-      HIP_CHECK_RET(tmp.alloc((void**)&bcnt, (size_t)sampler_partition_blocks(chunk) * sizeof(int32_t)));
     }
+    HIP_CHECK_RET(tmp.alloc((void**)&key, (size_t)chunk));
+    HIP_CHECK_RET(tmp.alloc((void**)&cum, (size_t)chunk * sizeof(float)));
+    HIP_CHECK_RET(tmp.alloc((void**)&perm2, permb));
+    HIP_CHECK_RET(tmp.alloc((void**)&cnt2, 2 * sizeof(int32_t)));
+    HIP_CHECK_RET(tmp.alloc((void**)&bcnt, (size_t)sampler_partition_ws(chunk) * sizeof(int32_t)));
     for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
       const int64_t n = std::min(chunk, shots - s0);
       HIP_CHECK_RET(launch_sampler_init(st, fb[0], ldl2, h->bond[0], n));
@@ -1001,10 +1009,21 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
         // site 1: every shot starts in sector 0 of the one-dimensional bond
         const bool part = h->psplit && m > 1;
         const bool next = h->psplit && m < M;
-        HIP_CHECK_RET(launch_sample_mfma(st, h->packed + h->poff[m], d, h->sgeo[m], h->sgeo_dev + m, fb[cur],
-                                         m == 1 ? nullptr : sb[cur], fb[1 - cur], sb[1 - cur], ldl2,
-                                         part ? perm : nullptr, part ? cnt : nullptr, next ? par : nullptr, s0, n, m,
-                                         seed, out, M));
+        const SamplerGeom& G = h->sgeo[m];
+        const bool more = G.npass[0] > 1 || G.npass[1] > 1;
+        const float* P = h->packed + h->poff[m];
+        const float* sin = m == 1 ? nullptr : sb[cur];
+        // first pass (outcome 0) for every shot
+        HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, fb[cur], sin, fb[1 - cur], sb[1 - cur], ldl2,
+                                         part ? perm : nullptr, part ? cnt : nullptr, next ? par : nullptr,
+                                         more ? cum : nullptr, more ? key : nullptr, 0, 1, s0, n, m, seed, out, M));
+        if (more) {
+          // the other passes for the shots the first one left undecided
+          HIP_CHECK_RET(launch_sampler_partition(st, key, n, bcnt, perm2, cnt2));
+          HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, fb[cur], sin, fb[1 - cur], sb[1 - cur], ldl2,
+                                           perm2, cnt2, next ? par : nullptr, cum, nullptr, 1, kSamplerMaxOutcomes,
+                                           s0, n, m, seed, out, M));
+        }
         if (next) HIP_CHECK_RET(launch_sampler_partition(st, par, n, bcnt, perm, cnt));
         cur = 1 - cur;
       }
@@ -1178,10 +1197,10 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   const int64_t pad = (chi + 15) / 16 * 16;
   // sampler operand: sector blocks pad at most 16 rows and columns each
   if (opt->prec != GBS_FP64 && chi <= 512) b += m * 16 * d * (pad + 16) * (pad + 16) + (m + 1) * chi * 8;
-  // sampling buffers: rows, scales, parities and partition
+  // sampling buffers: rows, scales, parities, running sums and partitions
   const bool mfma = opt->prec != GBS_FP64 && chi <= 512 && d <= 32;
   const int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 0), mfma ? kSampleChunk : kSampleChunkGeneric);
-  b += 2 * chunk * std::max<int64_t>(chi * esz, 8 * pad) + 16 * chunk + 4096;
+  b += 2 * chunk * std::max<int64_t>(chi * esz, 8 * pad) + 32 * chunk + 4096;
   return b + b / 8 + (64LL << 20);
 }
 

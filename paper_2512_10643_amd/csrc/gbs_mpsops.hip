@@ -204,10 +204,14 @@ template hipError_t launch_amplitude<cplx64>(hipStream_t, cplx64* const*, const 
 // ---------------------------------------------------------------------------
 // Sampling, one site per launch.  A workgroup owns SHOTS shots; their left
 // vectors L (bond[m-1] each) come from `lin`, the next ones go to `lout`.
-// For each p, T_p = L B[:, p, :] is formed in registers (each thread owns a
-// set of columns j for every shot), its squared norm reduced across the
-// workgroup, and a weighted reservoir decision (one uniform per p >= 1,
-// Philox keyed by the seed, counter (shot, site)) keeps the selected T.
+// For p = 0, 1, ..., T_p = L B[:, p, :] is formed in registers (each thread
+// owns a set of columns j for every shot) and its squared norm reduced across
+// the workgroup.  L has unit norm and B is right-canonical, so these
+// conditional probabilities sum to 1: each shot takes the first p whose
+// running sum passes its uniform u (Philox keyed by the seed, counter
+// (shot, site)), and the workgroup stops once all its shots are decided.  A
+// shot whose u lies above the rounded total keeps the last p of positive
+// weight (p = 0 if none).
 template <typename C, int SHOTS, int JPT>
 __global__ __launch_bounds__(256) void sample_site_kernel(const C* __restrict__ Bm, int rl, int d, int rr,
                                                           const C* __restrict__ lin, C* __restrict__ lout, long ldl,
@@ -219,11 +223,20 @@ __global__ __launch_bounds__(256) void sample_site_kernel(const C* __restrict__ 
   __shared__ C Ls[SHOTS][64];
   __shared__ R red[SHOTS][4];
   __shared__ R wsum[SHOTS], wsel[SHOTS];
-  __shared__ int psel[SHOTS], take[SHOTS];
+  __shared__ float ush[SHOTS];
+  __shared__ int psel[SHOTS], take[SHOTS], left;
   C acc[SHOTS][JPT], sel[SHOTS][JPT];
   for (int s = tid; s < SHOTS; s += 256) {
     wsum[s] = (R)0;
     psel[s] = 0;
+    const int64_t gs = sbase + s;
+    philox4 c;
+    c.v[0] = (uint32_t)(shot0 + gs);
+    c.v[1] = (uint32_t)((uint64_t)(shot0 + gs) >> 32);
+    c.v[2] = (uint32_t)site;
+    c.v[3] = 0u;
+    // a shot past the end is decided from the start
+    ush[s] = gs < nshots ? u01_24(philox4x32_10(c, k0, k1).v[0]) : -1.f;
   }
   for (int p = 0; p < d; ++p) {
 #pragma unroll
@@ -264,24 +277,18 @@ __global__ __launch_bounds__(256) void sample_site_kernel(const C* __restrict__ 
       if ((tid & 63) == 0) red[s][tid >> 6] = part;
     }
     __syncthreads();
+    if (tid == 0) left = 0;
     for (int s = tid; s < SHOTS; s += 256) {
-      R wp = red[s][0] + red[s][1] + red[s][2] + red[s][3];
-      int64_t gs = sbase + s;
+      const R wp = red[s][0] + red[s][1] + red[s][2] + red[s][3];
       int tk = 0;
-      if (p == 0) {
-        tk = 1;
-      } else if (gs < nshots) {
-        philox4 c;
-        c.v[0] = (uint32_t)(shot0 + gs);
-        c.v[1] = (uint32_t)((uint64_t)(shot0 + gs) >> 32);
-        c.v[2] = (uint32_t)site;
-        c.v[3] = (uint32_t)((p - 1) >> 2);
-        philox4 r = philox4x32_10(c, k0, k1);
-        float u = u01_24(r.v[(p - 1) & 3]);
-        R wtot = wsum[s] + wp;
-        tk = (R)u * wtot < wp;
+      if (ush[s] >= 0.f) {
+        wsum[s] += wp;
+        const bool dec = (R)ush[s] < wsum[s];
+        // taken, or the provisional choice: the last p of positive weight
+        tk = dec || wp > (R)0 || p == 0;
+        if (dec) ush[s] = -1.f;
+        else left = 1;
       }
-      wsum[s] += wp;
       take[s] = tk;
       if (tk) {
         psel[s] = p;
@@ -296,6 +303,7 @@ __global__ __launch_bounds__(256) void sample_site_kernel(const C* __restrict__ 
         for (int u = 0; u < JPT; ++u) sel[s][u] = acc[s][u];
       }
     }
+    if (!left) break;  // every shot of the workgroup is decided
   }
   __syncthreads();
 #pragma unroll

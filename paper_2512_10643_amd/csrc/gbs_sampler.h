@@ -9,9 +9,11 @@
 // sector-local indices.  With one sector per bond (pi = 0 for every shot and
 // both column sets equal to the whole bond) the same code is the dense sweep.
 //
-// Outcomes are visited in the order 0, 2, 4, ..., 1, 3, 5, ... and grouped
-// into passes: consecutive outcomes whose column tiles together fit the
-// kernel's accumulator budget share one sweep over the K rows.
+// Outcomes are visited in the order 0, 1, 2, ... and grouped into passes:
+// outcome 0 alone, then runs of consecutive outcomes whose column tiles
+// together fit the kernel's accumulator budget, each pass one sweep over the
+// K rows.  A shot stops at the first outcome whose cumulative probability
+// passes its uniform, so most shots need only the first pass.
 #pragma once
 #include "gbs_common.h"
 
@@ -73,22 +75,29 @@ int sampler_shots_per_block();
 // `l` (stride ldl2 floats) becomes e_0 over 2 pad(k0) floats.
 hipError_t launch_sampler_init(hipStream_t st, float* l, long ldl2, int k0, int64_t n);
 
-// One conditional-sampling step at `site` for nshots shots (chunk-local rows
-// of lin/lout, row stride ldl2 floats).  Rows of lin are scaled by sin (NULL:
-// 1); lout receives the unnormalised selected rows and sout their inverse
-// norms.  perm == NULL: every shot is in sector 0 and workgroup b takes shots
-// [128 b, 128 b + 128).  Otherwise perm / cnt come from
-// launch_sampler_partition and the grid covers both sector groups.  par_out
-// (may be NULL) receives the parity of each shot's new bond index.
-hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerGeom& g, const SamplerGeom* gd,
+// Passes [qbeg, qend) of one conditional-sampling step at `site` for nshots
+// shots (chunk-local rows of lin/lout, row stride ldl2 floats).  Rows of lin
+// are scaled by sin (NULL: 1); lout receives the unnormalised row of each
+// shot's outcome and sout its inverse norm.  perm == NULL: every shot is in
+// sector 0 and workgroup b takes shots [128 b, 128 b + 128).  Otherwise
+// perm / cnt come from launch_sampler_partition and the grid covers both
+// sector groups.  par_out (may be NULL) receives the parity of each shot's
+// new bond index.  A launch with qbeg = 0 starts every shot's cumulative
+// probability at 0; if it stops before a sector's last pass, it writes key
+// (2: decided, else the shot's left sector) and the running sum cum of each
+// undecided shot, and a second launch with qbeg = 1 takes the undecided
+// shots from the partition of key and continues from cum.
+hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom& g, const SamplerGeom* gd,
                               const float* lin, const float* sin, float* lout, float* sout, long ldl2,
-                              const int32_t* perm, const int32_t* cnt, int8_t* par_out, int64_t shot0,
-                              int64_t nshots, int site, uint64_t seed, int32_t* out, int M);
+                              const int32_t* perm, const int32_t* cnt, int8_t* par_out, float* cum, int8_t* key,
+                              int qbeg, int qend, int64_t shot0, int64_t nshots, int site, uint64_t seed, int32_t* out,
+                              int M);
 
-// Stable partition of shots by parity: perm[0, c0) lists the shots with
-// par == 0 in order, perm[E, E + c1) those with par == 1, E = c0 rounded up to
-// a multiple of 128; cnt = {c0, c1}.  perm holds nshots + 128 ints; bcnt is a
-// workspace of sampler_partition_blocks(nshots) ints.
-int64_t sampler_partition_blocks(int64_t nshots);
+// Stable partition of shots by a key in {0, 1, other}: perm[0, c0) lists the
+// shots with key 0 in order, perm[E, E + c1) those with key 1, E = c0 rounded
+// up to a multiple of 128; other keys are left out; cnt = {c0, c1}.  perm
+// holds nshots + 128 ints; bcnt is a workspace of sampler_partition_ws(nshots)
+// ints.
+int64_t sampler_partition_ws(int64_t nshots);
 hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t nshots, int32_t* bcnt,
                                     int32_t* perm, int32_t* cnt);

@@ -13,19 +13,24 @@
 // are those of sector pi and outcome p only needs the columns of sector
 // pi ^ (p & 1); the blocks B[pi, p, pi ^ (p & 1)] are the only nonzero ones.
 //
-// Outcomes are visited in the order 0, 2, 4, ..., 1, 3, 5, ... and grouped
-// into passes whose column tiles together fit the accumulators, so narrow
-// sectors share one sweep over K.
+// Draw by inverse CDF with early stopping.  The site tensors are right-
+// canonical (sum_p B_p B_p^dag = 1) and each left vector enters with unit
+// norm, so the conditional probabilities |T_p|^2 of one shot sum to 1 before
+// any of them is known.  With one uniform u per (shot, site) (Philox keyed by
+// the seed, counter (shot, site)), outcomes are visited in the order
+// 0, 1, 2, ... and the first p whose running sum exceeds u is taken; the
+// outcomes after it are never formed.  Outcome 0 is its own first pass, and
+// a site runs in two launches: the first pass for every shot, then, for the
+// shots still undecided (listed by a partition), the remaining passes, where
+// a workgroup stops as soon as all of its shots are decided.  A shot whose u
+// lies above the rounded total keeps the last outcome of positive
+// probability (outcome 0 if none): each pass stores the row of its taken
+// outcome, or of its last positive one as a provisional choice.
 //
 // Workgroup: 8 waves x 16 shots, two waves per SIMD.  Each wave keeps the
 // row block of its 16 shots for all outcomes of a pass in MFMA accumulators
-// (v_mfma_f32_16x16x4f32 tiles), reduces the squared norms across lanes and
-// draws by weighted reservoir selection: the outcome at visiting position
-// j >= 1 replaces the running choice when u_j (W_{j-1} + w_j) < w_j, with u_j
-// from Philox keyed by (seed, shot, site, j).  A replacing row is stored at
-// once to the output row of its shot, so no second register set holds the
-// selection.  Rows are left unnormalised: the conditional probabilities do
-// not depend on the scale of L, and the next site multiplies its A operand by
+// (v_mfma_f32_16x16x4f32 tiles) and reduces the squared norms across lanes.
+// Rows are stored unnormalised; the next site multiplies its A operand by
 // the stored 1/|T_p|.  B' arrives in LDS in K-chunks of 32 real rows, double
 // buffered by the LDS DMA path into two separate LDS arrays (so reads of one
 // need not wait for the DMA into the other), in the lane order the B operand
@@ -41,12 +46,6 @@ namespace {
 
 constexpr int kWaves = 8;              // waves per workgroup
 constexpr int kShotsPerWg = 16 * kWaves;
-
-// Outcome visited at position j: the even outcomes first, then the odd ones.
-__host__ __device__ inline int outcome_at(int j, int d) {
-  const int ne = (d + 1) >> 1;
-  return j < ne ? 2 * j : 2 * (j - ne) + 1;
-}
 
 // Packed layout of B' for one site, per left sector pi and pass q, one 1 KiB
 // block per (c, t, h):
@@ -81,10 +80,10 @@ __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerS
   }
   const int j = r & 3, lane = (r >> 2) & 63;
   // the outcome owning tile t
-  int jo = g->j0[pi][q], p = outcome_at(jo, d), sig = pi ^ (p & 1);
+  int p = g->j0[pi][q], sig = pi ^ (p & 1);
   while (t >= g->nt[sig]) {
     t -= g->nt[sig];
-    p = outcome_at(++jo, d);
+    ++p;
     sig = pi ^ (p & 1);
   }
   const int kr = 32 * c + 16 * h + 4 * (lane >> 4) + j;  // real row of B'
@@ -124,16 +123,22 @@ __global__ __launch_bounds__(256) void sector_mask_kernel(const cplx32* __restri
 // columns 16 t + 4 grp + v (v = 0..3) of shot col.
 #define GBS_MF(T_, AV, BV) acc[T_] = __builtin_amdgcn_mfma_f32_16x16x4f32(BV, AV, acc[T_], 0, 0, 0)
 
-template <int NT>
+// kFirst: the launch of a site's first pass alone (qbeg = 0, qend = 1);
+// otherwise any other pass range, such as the remaining passes for the
+// shots the first launch left undecided.
+template <int NT, bool kFirst>
 __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
-    const float* __restrict__ P, const SamplerGeom* __restrict__ geo, int d, const float* __restrict__ lin,
+    const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
     const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
-    int64_t shot0, int64_t nshots, int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
+    float* __restrict__ cum, int8_t* __restrict__ key, int qbeg_, int qend_, int64_t shot0, int64_t nshots,
+    int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
+  const int qbeg = kFirst ? 0 : qbeg_, qend = kFirst ? 1 : qend_;
   // two separate LDS buffers (not one 2-D array), so the compiler can tell
   // the buffer being read from the one the DMA is filling
   __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
   __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
+  __shared__ int wdone[kWaves];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int grp = lane >> 4;   // k sub-block of the left vector; column quad of the output
   const int col = lane & 15;   // shot within the wave
@@ -152,19 +157,44 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     }
     if (slot0 >= send) return;  // whole workgroup, before any barrier
   }
-  const int nchunk = geo->nchunk[pi];
-  const bool halfk = geo->half[pi] != 0;  // last chunk of each pass is half
-  const int npass = geo->npass[pi];
-  const int nte = geo->nt[pi], nto = geo->nt[pi ^ 1];
   // this lane's shot: left-vector row for the MFMA operand and output row
   const int64_t slot = slot0 + w * 16 + col;
   const bool valid = slot < send;
   const int64_t shot = valid ? (perm ? (int64_t)perm[slot] : slot) : 0;
+  const int npass = geo->npass[pi];
+  const int qlast = min(qend, npass);
+  if (qbeg >= qlast) {
+    // no rows in this left sector: outcome 0 with weight zero (a shot cannot
+    // reach an empty sector with positive probability)
+    if (valid && grp == 0 && qbeg == 0) {
+      sout[shot] = 0.f;
+      out[(shot0 + shot) * (int64_t)M + (site - 1)] = 0;
+      if (par_out) par_out[shot] = (int8_t)pi;
+      if (key) key[shot] = 2;
+    }
+    return;  // uniform over the workgroup
+  }
+  const int nchunk = geo->nchunk[pi];
+  const bool halfk = geo->half[pi] != 0;  // last chunk of each pass is half
+  const int nte = geo->nt[pi], nto = geo->nt[pi ^ 1];
   const float* arow_ptr = lin + shot * ldl2 + 4 * grp;
   const float ascale = (sin && valid) ? sin[shot] : 1.f;
-  floatx4 acc[NT];
-  float wsum = 0.f, wsel = 0.f, ur = 0.f;
+  // the shot's uniform (every lane of the shot draws the same one) and the
+  // running sum of its conditional probabilities
+  float ur, csum = (qbeg > 0 && valid) ? cum[shot] : 0.f;
+  {
+    const int64_t gs = shot0 + shot;
+    philox4 ctr;
+    ctr.v[0] = (uint32_t)gs;
+    ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
+    ctr.v[2] = (uint32_t)site;
+    ctr.v[3] = 0u;
+    ur = u01_24(philox4x32_10(ctr, k0, k1).v[0]);
+  }
+  bool done = false, wrote = false;
   int psel = 0;
+  float wsel = 0.f;
+  floatx4 acc[NT];
   // A rows arrive raw and are scaled only when they become the current
   // operand, so nothing waits on the loads before the end of the chunk.  A
   // lane past the end of the slot range reads row 0 (in bounds); it feeds
@@ -191,17 +221,17 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
                                          (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
     }
   };
-  const int total = npass * nchunk;
+  const int total = (qlast - qbeg) * nchunk;
   // the chunk being multiplied (pass q, chunk c, T tiles) and the one being
   // fetched (nq, nc, nT from nsrc), stepped without divisions; pass
   // parameters are read from the geometry only when a pass starts
-  int q = 0, c = 0, T = total > 0 ? geo->tiles[pi][0] : 0;
-  int nq = 0, nc = 0, nT = T;
-  const float* nsrc = P + (total > 0 ? geo->base[pi][0] : 0);
+  int q = qbeg, c = 0, T = geo->tiles[pi][qbeg];
+  int nq = qbeg, nc = 0, nT = T;
+  const float* nsrc = P + geo->base[pi][qbeg];
   auto advance_next = [&]() {
     if (++nc == nchunk) {
       nc = 0;
-      if (++nq < npass) {
+      if (++nq < qlast) {
         nT = geo->tiles[pi][nq];
         nsrc = P + geo->base[pi][nq];
       }
@@ -211,11 +241,9 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   };
   float a[8];
   float4 an[2];
-  if (total > 0) {
-    issue(nsrc, nT, Bs0, halfk && nchunk == 1);
-    load_a(0, an);
-    advance_next();
-  }
+  issue(nsrc, nT, Bs0, halfk && nchunk == 1);
+  load_a(0, an);
+  advance_next();
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   scale_a(an, a);
@@ -223,10 +251,9 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   // chunk g of the sequence over (pass, c): MFMAs on one buffer while chunk
   // g + 1 streams into the other (u fixes which buffer at compile time); the
-  // draws follow the last chunk of each pass.  An empty left sector (no
-  // chunks) leaves every shot at outcome 0 with weight zero, as a draw over
-  // all-zero weights would.
-  for (int g0 = 0; g0 < total; g0 += 2) {
+  // draws follow the last chunk of each pass
+  bool stop = false;
+  for (int g0 = 0; g0 < total && !stop; g0 += 2) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int g = g0 + u;
@@ -284,15 +311,13 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
       __builtin_amdgcn_s_barrier();
       if (g + 1 < total) scale_a(an, a);
       if (c == nchunk - 1) {
-        // draws for the outcomes of this pass, in visiting order; outcome p
-        // owns the accumulator tiles whose bits are set in `own`
+        // draws for the outcomes of this pass, in order; outcome p owns the
+        // accumulator tiles [lo, hi)
         const int j0 = geo->j0[pi][q], j1 = geo->j0[pi][q + 1];
-        int lo = 0;
-        for (int j = j0; j < j1; ++j) {
-          const int p = outcome_at(j, d);
+        int lo = 0, slo = 0, shi = 0;
+        bool pick = false;
+        for (int p = j0; p < j1; ++p) {
           const int hi = lo + ((p & 1) ? nto : nte);
-          const uint32_t own = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) &
-                               ~(lo >= 32 ? 0xffffffffu : ((1u << lo) - 1u));
           // squared norm of this lane's shot: its 4 columns per tile, then the
           // four column quads
           float part = 0.f;
@@ -303,6 +328,8 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
 #pragma unroll
               for (int v = 0; v < 4; ++v) part = fmaf(acc[t][v], acc[t][v], part);
           } else {
+            const uint32_t own = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) &
+                                 ~(lo >= 32 ? 0xffffffffu : ((1u << lo) - 1u));
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
               const float f = ((own >> t) & 1u) ? 1.f : 0.f;
@@ -312,40 +339,50 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
           }
           part += __shfl_xor(part, 16, 64);
           part += __shfl_xor(part, 32, 64);
-          // uniforms: one Philox block per shot and four visiting positions,
-          // output grp drawn by lane (grp, col), fetched by the shot's lanes
-          bool take = true;
-          if (j >= 1) {
-            if (((j - 1) & 3) == 0) {
-              const int64_t gs = shot0 + shot;
-              philox4 ctr;
-              ctr.v[0] = (uint32_t)gs;
-              ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
-              ctr.v[2] = (uint32_t)site;
-              ctr.v[3] = (uint32_t)((j - 1) >> 2);
-              const philox4 rr = philox4x32_10(ctr, k0, k1);
-              ur = u01_24(grp == 0 ? rr.v[0] : grp == 1 ? rr.v[1] : grp == 2 ? rr.v[2] : rr.v[3]);
-            }
-            const float uj = __shfl(ur, (((j - 1) & 3) << 4) | col, 64);
-            take = uj * (wsum + part) < part;
-          }
-          wsum += part;
-          if (take) {
-            psel = p;
-            wsel = part;
-            // a replacing outcome's row goes straight to its shot's output row
-            if (valid) {
-              float* orow = lout + shot * ldl2 + 4 * grp - 16 * lo;
-#pragma unroll
-              for (int t = 0; t < NT; ++t)
-                if ((own >> t) & 1u) *(float4*)(orow + 16 * t) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+          if (!done) {
+            csum += part;
+            // taken when the running sum passes u; otherwise the last outcome
+            // of positive weight (outcome 0 in any case) is the provisional one
+            done = ur < csum;
+            if (done || part > 0.f || p == 0) {
+              pick = true;
+              psel = p;
+              wsel = part;
+              slo = lo;
+              shi = hi;
             }
           }
           lo = hi;
         }
+        if (pick) {
+          wrote = true;
+          if (valid) {
+            const uint32_t own = (shi >= 32 ? 0xffffffffu : ((1u << shi) - 1u)) &
+                                 ~(slo >= 32 ? 0xffffffffu : ((1u << slo) - 1u));
+            float* orow = lout + shot * ldl2 + 4 * grp - 16 * slo;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              if ((own >> t) & 1u) *(float4*)(orow + 16 * t) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+          }
+        }
         // the next pass accumulates from zero
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (!kFirst && q + 1 < qlast) {
+          // the workgroup stops once every one of its shots is decided; the
+          // chunk already in flight is waited for first
+          const int wall = __all(done || !valid);
+          if (lane == 0) wdone[w] = wall;
+          __syncthreads();
+          int all = 1;
+#pragma unroll
+          for (int i = 0; i < kWaves; ++i) all &= wdone[i];
+          if (all) {
+            __builtin_amdgcn_s_waitcnt(0);
+            stop = true;
+            break;
+          }
+        }
       }
       q = nq;
       c = nc;
@@ -353,11 +390,17 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
       if (g + 1 < total) advance_next();
     }
   }
-  // row scale, sample and the parity of the new bond index
   if (valid && grp == 0) {
-    sout[shot] = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
-    out[(shot0 + shot) * (int64_t)M + (site - 1)] = psel;
-    if (par_out) par_out[shot] = (int8_t)((pi + psel) & 1);
+    // row scale, sample and the parity of the new bond index of the outcome
+    // stored here; an undecided shot hands its running sum to the next launch
+    if (wrote) {
+      sout[shot] = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
+      out[(shot0 + shot) * (int64_t)M + (site - 1)] = psel;
+      if (par_out) par_out[shot] = (int8_t)((pi + psel) & 1);
+    }
+    const bool fin = done || qlast >= npass;
+    if (key) key[shot] = fin ? 2 : (int8_t)pi;
+    if (!fin) cum[shot] = csum;
   }
 }
 #undef GBS_MF
@@ -378,12 +421,19 @@ __global__ __launch_bounds__(256) void part_count_kernel(const int8_t* __restric
                                                          int32_t* __restrict__ bcnt) {
   __shared__ int sh[4];
   const int64_t base = (int64_t)blockIdx.x * kPartElems + 4 * threadIdx.x;
-  int c = 0;
+  int c0 = 0, c1 = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (base + j < n && par[base + j] == 0) ++c;
-  c = block_sum256(c, sh);
-  if (threadIdx.x == 0) bcnt[blockIdx.x] = c;
+  for (int j = 0; j < 4; ++j) {
+    const int v = base + j < n ? (int)par[base + j] : -1;
+    c0 += v == 0;
+    c1 += v == 1;
+  }
+  c0 = block_sum256(c0, sh);
+  c1 = block_sum256(c1, sh);
+  if (threadIdx.x == 0) {
+    bcnt[2 * blockIdx.x] = c0;
+    bcnt[2 * blockIdx.x + 1] = c1;
+  }
 }
 
 __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restrict__ par, int64_t n,
@@ -392,14 +442,20 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restr
   __shared__ int sh[4];
   __shared__ int wtot[4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int before = 0, tot = 0;
+  int before = 0, before1 = 0, tot = 0, tot1 = 0;
   for (int i = tid; i < nblk; i += 256) {
-    const int v = bcnt[i];
+    const int v = bcnt[2 * i], v1 = bcnt[2 * i + 1];
     tot += v;
-    if (i < (int)blockIdx.x) before += v;
+    tot1 += v1;
+    if (i < (int)blockIdx.x) {
+      before += v;
+      before1 += v1;
+    }
   }
   before = block_sum256(before, sh);
+  before1 = block_sum256(before1, sh);
   tot = block_sum256(tot, sh);
+  tot1 = block_sum256(tot1, sh);
   const int64_t c0 = tot;
   const int64_t e = (c0 + kShotsPerWg - 1) / kShotsPerWg * kShotsPerWg;
   const int64_t blk0 = (int64_t)blockIdx.x * kPartElems;
@@ -426,7 +482,7 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restr
   for (int i = 0; i < w; ++i) wpre += wtot[i];
   const int ex = x - v + wpre;
   int64_t re = before + (ex & 0xffff);
-  int64_t ro = e + (blk0 - before) + (ex >> 16);
+  int64_t ro = e + before1 + (ex >> 16);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (q[j] == 0) perm[re++] = (int32_t)(base + j);
@@ -434,7 +490,7 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restr
   }
   if (blockIdx.x == 0 && tid == 0) {
     cnt[0] = (int32_t)c0;
-    cnt[1] = (int32_t)(n - c0);
+    cnt[1] = (int32_t)tot1;
   }
 }
 
@@ -498,10 +554,11 @@ long sampler_geometry(const SamplerSite& s, int d, SamplerGeom* g) {
       const int q = G.npass[pi]++;
       int T = 0;
       while (j < d) {
-        const int t = G.nt[pi ^ (outcome_at(j, d) & 1)];
+        const int t = G.nt[pi ^ (j & 1)];
         if (T > 0 && T + t > G.NT) break;
         T += t;
         ++j;
+        if (j == 1 && T > 0) break;  // outcome 0 alone: the first launch decides most shots with it
       }
       G.tiles[pi][q] = T;
       G.base[pi][q] = tot;
@@ -537,27 +594,42 @@ hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, con
   return hipGetLastError();
 }
 
-hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const SamplerGeom& g, const SamplerGeom* gd,
+hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom& g, const SamplerGeom* gd,
                               const float* lin, const float* sin, float* lout, float* sout, long ldl2,
-                              const int32_t* perm, const int32_t* cnt, int8_t* par_out, int64_t shot0,
-                              int64_t nshots, int site, uint64_t seed, int32_t* out, int M) {
+                              const int32_t* perm, const int32_t* cnt, int8_t* par_out, float* cum, int8_t* key,
+                              int qbeg, int qend, int64_t shot0, int64_t nshots, int site, uint64_t seed, int32_t* out,
+                              int M) {
   if (nshots <= 0) return hipSuccess;
   if ((perm == nullptr) != (cnt == nullptr)) return hipErrorInvalidValue;
   if (!perm && g.npass[1] != 0) return hipErrorInvalidValue;
+  if (qbeg < 0 || qend <= qbeg) return hipErrorInvalidValue;
+  // a launch that leaves shots undecided hands them on through cum and key;
+  // a later launch reads cum and gets its shots from a partition of key
+  const bool leaves = qend < g.npass[0] || qend < g.npass[1];
+  if ((leaves && (!cum || !key)) || (qbeg > 0 && (!cum || !perm))) return hipErrorInvalidValue;
   for (int i = 0; i < 2; ++i)
     if (32L * g.nchunk[i] > ldl2 || 16L * g.nt[i] > ldl2) return hipErrorInvalidValue;
+  // accumulator tiles of the kernel instance: the widest pass of the range
+  int mx = 8;
   for (int pi = 0; pi < 2; ++pi)
-    for (int q = 0; q < g.npass[pi]; ++q)
+    for (int q = 0; q < g.npass[pi]; ++q) {
       if (g.tiles[pi][q] > g.NT) return hipErrorInvalidValue;
+      if (q >= qbeg && q < qend) mx = std::max(mx, g.tiles[pi][q]);
+    }
+  const int nt = (mx + 7) / 8 * 8;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   // with a partition, sector 1 starts on a fresh workgroup: one more block
   dim3 grid((unsigned)((nshots + kShotsPerWg - 1) / kShotsPerWg + (perm ? 1 : 0)));
-#define GBS_SAMPLE_CASE(NTV)                                                                                      \
-  case NTV:                                                                                                       \
-    hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, gd, d, lin, sin, lout, sout, \
-                       ldl2, perm, cnt, par_out, shot0, nshots, site, k0, k1, out, M);                            \
+#define GBS_SAMPLE_CASE(NTV)                                                                                       \
+  case NTV:                                                                                                        \
+    if (qbeg == 0 && qend == 1)                                                                                    \
+      hipLaunchKernelGGL((sample_mfma_kernel<NTV, true>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout,  \
+                         sout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M); \
+    else                                                                                                           \
+      hipLaunchKernelGGL((sample_mfma_kernel<NTV, false>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout, \
+                         sout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M); \
     break;
-  switch (g.NT) {
+  switch (nt) {
     GBS_SAMPLE_CASE(8)
     GBS_SAMPLE_CASE(16)
     GBS_SAMPLE_CASE(24)
@@ -569,13 +641,13 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, int d, const Sampl
   return hipGetLastError();
 }
 
-int64_t sampler_partition_blocks(int64_t nshots) { return (nshots + kPartElems - 1) / kPartElems; }
+int64_t sampler_partition_ws(int64_t nshots) { return 2 * ((nshots + kPartElems - 1) / kPartElems); }
 
 hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t nshots, int32_t* bcnt,
                                     int32_t* perm, int32_t* cnt) {
   if (nshots <= 0) return hipSuccess;
   if (nshots > INT32_MAX - 256) return hipErrorInvalidValue;
-  const int nblk = (int)sampler_partition_blocks(nshots);
+  const int nblk = (int)((nshots + kPartElems - 1) / kPartElems);
   hipLaunchKernelGGL(part_count_kernel, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt);
   hipLaunchKernelGGL(part_scatter_kernel, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt, nblk, perm,
                      cnt);
