@@ -78,6 +78,25 @@ def evaluated_flops_per_shot(bonds, sectors, samples, padr=1, padc=1):
     return tot / S
 
 
+def first_pass_flops_per_shot(sectors, samples, padr=1, padc=1):
+    """Flops of the first pass alone (outcome 0 for every shot): a shot in
+    left sector pi at site m forms T_0, n_pi(m-1) x n_pi(m) complex
+    multiply-adds.  Also returns the fraction of shot-sites in sector 0."""
+    import torch
+    s = samples.to(torch.int64)
+    S, M = s.shape
+    pre = (torch.cumsum(s, dim=1) - s) % 2
+    padn = lambda n, q: -(-int(n) // q) * q
+    tot, f0 = 0.0, 0.0
+    for m in range(1, M + 1):
+        n1 = float(pre[:, m - 1].sum().item())
+        n0 = S - n1
+        f0 += n0
+        tot += 8.0 * (n0 * padn(sectors[m - 1][0], padr) * padn(sectors[m][0], padc)
+                      + n1 * padn(sectors[m - 1][1], padr) * padn(sectors[m][1], padc))
+    return tot / S, f0 / (S * M)
+
+
 def cpu_baseline(workload, budget_s=20.0):
     """Time the CPU oracle on a bounded sample of the same workload and scale
     it to samples/s of the whole step (build + shots)."""
@@ -275,6 +294,11 @@ def main():
         fl_exec = evaluated_flops_per_shot(bonds, sec, out, padr=8, padc=16)
     else:
         fl_shot = fl_exec = evaluated_flops_per_shot(bonds, None, out)
+    fp_info = None
+    if sec is not None:
+        fa, f0 = first_pass_flops_per_shot(sec, out)
+        fe, _ = first_pass_flops_per_shot(sec, out, padr=8, padc=16)
+        fp_info = {"flops_per_sample": fa, "flops_per_sample_executed": fe, "sector0_fraction": f0}
     samp_ms = sum(r["sample_ev_ms"] for r in recs) / len(recs)
     build_s = sum(r["build_s"] for r in recs) / len(recs)
     achieved = fl_shot * args.shots / (samp_ms / 1000.0) / 1e12
@@ -308,6 +332,7 @@ def main():
         "sampler_layout": {0: "none", 1: "dense", 2: "parity sectors"}[inf["sampler_layout"]],
         "flops_per_sample": fl_shot,
         "flops_per_sample_whole_bonds": fl_dense,
+        "first_pass": fp_info,
         "mfma_tflops_executed": fl_exec * args.shots / (samp_ms / 1000.0) / 1e12,
         "roofline": {"bound": "mfma", "kernel": "sample_mfma_kernel (whole sampling sweep, all sites)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,

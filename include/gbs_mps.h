@@ -91,8 +91,14 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
 
 /* Draw `shots` photon-number samples by sequential conditional sampling on
  * the right-canonical MPS (the "standard MPS sampling" the paper defers to,
- * Sec. I).  Random numbers: Philox-4x32-10 keyed by `seed`, counter (shot,
- * site), so results do not depend on batching.
+ * Sec. I).  At site m shot s draws one uniform u from Philox-4x32-10 keyed by
+ * `seed` (low word, high word), counter (s low word, s high word, m, 0),
+ * first output word, top 24 bits / 2^24; it takes the first photon number p
+ * = 0, 1, ... whose cumulative conditional probability exceeds u.  The left
+ * vector enters each site with unit norm and the tensors are right-
+ * canonical, so the cumulative sum reaches 1 up to rounding; a u above the
+ * rounded total takes the last p of positive probability.  Results do not
+ * depend on batching.
  *   out : device, shots x M int32.  Asynchronous on `stream`. */
 int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
 

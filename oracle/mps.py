@@ -9,13 +9,17 @@ Readings: the paper leaves the normalisation free; the
 MPS is rescaled to unit norm and its global phase chosen so that the vacuum
 amplitude is real and positive.  Fidelity is |<psi1|psi2>|^2/(|psi1|^2|psi2|^2).
 Sampling is sequential conditional sampling, P(p_m | p_<m) from the left
-vector and the exact right environment.  SVD truncation: left-to-right QR,
+vector and the exact right environment, either with NumPy's generator or with
+counter-based uniforms (Philox-4x32-10 keyed by the seed, counter (shot, site))
+by inverse CDF over p = 0, 1, ..., the rule the GPU sampler follows.  SVD truncation: left-to-right QR,
 then right-to-left SVD keeping at most chi values above tol * sigma_max.
 
 Parity: pinned in tests by brute-force sums over all patterns (norm), by
 single-mode and two-mode squeezed-vacuum closed forms, by exact Gaussian
 photon numbers, by hafnian amplitudes and by sampler statistics against exact
-marginals.
+marginals; the counter-based sampler also by its generator's published
+known-answer vectors, a one-site state whose boundaries are known in closed
+form, and independence of the shot range.
 """
 from __future__ import annotations
 
@@ -141,6 +145,40 @@ def sample(tensors, shots: int, rng: np.random.Generator) -> np.ndarray:
             out[s, m - 1] = p
             v = w[p] / np.sqrt(pr[p])
     return out
+
+
+def sample_counter(tensors, shots: int, seed: int, shot0: int = 0):
+    """Sequential conditional sampling with counter-based uniforms: at site m
+    shot s draws u = site_uniforms(shot0 + s, m, seed) and takes the first p
+    with u < F_p, F_p = sum_{j <= p} P(j | p_<m) (inverse CDF over p = 0, 1,
+    ...).  The conditional probabilities come from the left vector and the
+    exact right environment, normalised by their sum.  All shots advance one
+    site at a time (the same arithmetic per shot as a loop over shots).
+
+    Returns (samples, margin): margin[s, m - 1] = min over p < d - 1 of
+    |u - F_p|, the distance of the draw from the nearest decision boundary."""
+    from .philox import site_uniforms
+    R = right_environments(tensors)
+    M = len(tensors)
+    d = tensors[0].shape[1]
+    out = np.zeros((shots, M), dtype=np.int32)
+    margin = np.zeros((shots, M))
+    v = np.ones((shots, 1), dtype=np.complex128)
+    ids = shot0 + np.arange(shots, dtype=np.int64)
+    for m in range(1, M + 1):
+        a = tensors[m - 1]
+        w = [v @ a[:, p, :] for p in range(d)]
+        pr = np.stack([np.real(np.sum((x @ R[m]) * x.conj(), axis=1)) for x in w], axis=1)
+        pr = np.clip(pr, 0.0, None)
+        cdf = np.cumsum(pr / pr.sum(axis=1, keepdims=True), axis=1)
+        u = site_uniforms(ids, m, seed)
+        p = np.minimum(np.sum(cdf <= u[:, None], axis=1), d - 1)
+        out[:, m - 1] = p
+        margin[:, m - 1] = np.min(np.abs(cdf[:, :-1] - u[:, None]), axis=1) if d > 1 else np.inf
+        rows = np.arange(shots)
+        wp = np.stack(w, axis=1)[rows, p]
+        v = wp / np.sqrt(pr[rows, p])[:, None]
+    return out, margin
 
 
 def overlap(t1, t2) -> complex:

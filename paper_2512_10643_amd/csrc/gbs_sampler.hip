@@ -39,6 +39,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -123,17 +125,128 @@ __global__ __launch_bounds__(256) void sector_mask_kernel(const cplx32* __restri
 // columns 16 t + 4 grp + v (v = 0..3) of shot col.
 #define GBS_MF(T_, AV, BV) acc[T_] = __builtin_amdgcn_mfma_f32_16x16x4f32(BV, AV, acc[T_], 0, 0, 0)
 
-// kFirst: the launch of a site's first pass alone (qbeg = 0, qend = 1);
-// otherwise any other pass range, such as the remaining passes for the
-// shots the first launch left undecided.
-template <int NT, bool kFirst>
+// MFMAs of one K-chunk: tiles [0, T) of the accumulators from the B' chunk
+// in LDS at bsrc and this lane's eight scaled A values; hc: the chunk holds
+// k-half 0 only.
+template <int NT>
+__device__ __forceinline__ void chunk_mfma(floatx4 (&acc)[NT], const float4* __restrict__ bsrc, const float (&a)[8],
+                                           int T, bool hc, int lane) {
+        // Tile pairs in order.  The four B' fragments of pair k + 1 (both
+        // k-halves) are read while pair k's MFMAs issue, into the other of two
+        // register sets; pair k waits only for reads issued a whole pair
+        // earlier.  A read past the pass's last pair stays inside the buffer
+        // and is not used.
+        float4 F[2][4];
+        F[0][0] = bsrc[(0 * 2 + 0) * 64 + lane];
+        F[0][1] = bsrc[(1 * 2 + 0) * 64 + lane];
+        F[0][2] = bsrc[(0 * 2 + 1) * 64 + lane];
+        F[0][3] = bsrc[(1 * 2 + 1) * 64 + lane];
+  #pragma unroll
+        for (int t0 = 0; t0 < NT; t0 += 2) {
+          if (t0 < T) {
+            const int cs = (t0 >> 1) & 1, ns = cs ^ 1;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this pair's fragments are in
+            if (t0 + 2 < NT) {
+              F[ns][0] = bsrc[((t0 + 2) * 2 + 0) * 64 + lane];
+              F[ns][1] = bsrc[((t0 + 3) * 2 + 0) * 64 + lane];
+              F[ns][2] = bsrc[((t0 + 2) * 2 + 1) * 64 + lane];
+              F[ns][3] = bsrc[((t0 + 3) * 2 + 1) * 64 + lane];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
+            GBS_MF(t0, a[0], F[cs][0].x);
+            GBS_MF(t0 + 1, a[0], F[cs][1].x);
+            GBS_MF(t0, a[1], F[cs][0].y);
+            GBS_MF(t0 + 1, a[1], F[cs][1].y);
+            GBS_MF(t0, a[2], F[cs][0].z);
+            GBS_MF(t0 + 1, a[2], F[cs][1].z);
+            GBS_MF(t0, a[3], F[cs][0].w);
+            GBS_MF(t0 + 1, a[3], F[cs][1].w);
+            if (!hc) {  // k-half 1 (absent from a half chunk)
+              GBS_MF(t0, a[4], F[cs][2].x);
+              GBS_MF(t0 + 1, a[4], F[cs][3].x);
+              GBS_MF(t0, a[5], F[cs][2].y);
+              GBS_MF(t0 + 1, a[5], F[cs][3].y);
+              GBS_MF(t0, a[6], F[cs][2].z);
+              GBS_MF(t0 + 1, a[6], F[cs][3].z);
+              GBS_MF(t0, a[7], F[cs][2].w);
+              GBS_MF(t0 + 1, a[7], F[cs][3].w);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+}
+
+// Draws after the last chunk of a pass over outcomes [j0, j1): squared norms
+// of this lane's shot per outcome (outcome p owns the accumulator tiles
+// [lo, hi), nte / nto tiles for even / odd p), inverse CDF against ur with
+// the running sum csum, and the store of the taken or provisional row to
+// orow (this lane's column quad of its shot's output row).
+template <int NT>
+__device__ __forceinline__ void pass_draws(const floatx4 (&acc)[NT], int j0, int j1, int nte, int nto, float ur,
+                                           float& csum, bool& done, bool& wrote, int& psel, float& wsel, bool valid,
+                                           float* orow0) {
+  int lo = 0, slo = 0, shi = 0;
+  bool pick = false;
+  for (int p = j0; p < j1; ++p) {
+    const int hi = lo + ((p & 1) ? nto : nte);
+    // squared norm of this lane's shot: its 4 columns per tile, then the
+    // four column quads
+    float part = 0.f;
+    if (j1 - j0 == 1) {
+      // the pass's only outcome owns every nonzero tile
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part = fmaf(acc[t][v], acc[t][v], part);
+    } else {
+      const uint32_t own = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) &
+                           ~(lo >= 32 ? 0xffffffffu : ((1u << lo) - 1u));
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float f = ((own >> t) & 1u) ? 1.f : 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part = fmaf(f * acc[t][v], acc[t][v], part);
+      }
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (!done) {
+      csum += part;
+      // taken when the running sum passes u; otherwise the last outcome of
+      // positive weight (outcome 0 in any case) is the provisional one
+      done = ur < csum;
+      if (done || part > 0.f || p == 0) {
+        pick = true;
+        psel = p;
+        wsel = part;
+        slo = lo;
+        shi = hi;
+      }
+    }
+    lo = hi;
+  }
+  if (pick) {
+    wrote = true;
+    if (valid) {
+      const uint32_t own = (shi >= 32 ? 0xffffffffu : ((1u << shi) - 1u)) &
+                           ~(slo >= 32 ? 0xffffffffu : ((1u << slo) - 1u));
+      float* orow = orow0 - 16 * slo;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        if ((own >> t) & 1u) *(float4*)(orow + 16 * t) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+    }
+  }
+}
+
+// Passes [qbeg, qend) of one site, one workgroup per 128 slots (used for the
+// remaining passes of the shots a site's first launch left undecided).
+template <int NT>
 __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
     const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
-    float* __restrict__ cum, int8_t* __restrict__ key, int qbeg_, int qend_, int64_t shot0, int64_t nshots,
+    float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend, int64_t shot0, int64_t nshots,
     int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
-  const int qbeg = kFirst ? 0 : qbeg_, qend = kFirst ? 1 : qend_;
   // two separate LDS buffers (not one 2-D array), so the compiler can tell
   // the buffer being read from the one the DMA is filling
   __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
@@ -262,113 +375,19 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
       if (g + 1 < total) load_a(nc, an);
       const float4* bsrc = (const float4*)(u ? Bs1 : Bs0);
       const bool hc = halfk && c == nchunk - 1;  // this chunk holds k-half 0 only
-      // Tile pairs in order.  The four B' fragments of pair k + 1 (both
-      // k-halves) are read while pair k's MFMAs issue, into the other of two
-      // register sets; pair k waits only for reads issued a whole pair
-      // earlier.  A read past the pass's last pair stays inside the buffer
-      // and is not used.
-      float4 F[2][4];
-      F[0][0] = bsrc[(0 * 2 + 0) * 64 + lane];
-      F[0][1] = bsrc[(1 * 2 + 0) * 64 + lane];
-      F[0][2] = bsrc[(0 * 2 + 1) * 64 + lane];
-      F[0][3] = bsrc[(1 * 2 + 1) * 64 + lane];
-#pragma unroll
-      for (int t0 = 0; t0 < NT; t0 += 2) {
-        if (t0 < T) {
-          const int cs = (t0 >> 1) & 1, ns = cs ^ 1;
-          __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this pair's fragments are in
-          if (t0 + 2 < NT) {
-            F[ns][0] = bsrc[((t0 + 2) * 2 + 0) * 64 + lane];
-            F[ns][1] = bsrc[((t0 + 3) * 2 + 0) * 64 + lane];
-            F[ns][2] = bsrc[((t0 + 2) * 2 + 1) * 64 + lane];
-            F[ns][3] = bsrc[((t0 + 3) * 2 + 1) * 64 + lane];
-          }
-          __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
-          GBS_MF(t0, a[0], F[cs][0].x);
-          GBS_MF(t0 + 1, a[0], F[cs][1].x);
-          GBS_MF(t0, a[1], F[cs][0].y);
-          GBS_MF(t0 + 1, a[1], F[cs][1].y);
-          GBS_MF(t0, a[2], F[cs][0].z);
-          GBS_MF(t0 + 1, a[2], F[cs][1].z);
-          GBS_MF(t0, a[3], F[cs][0].w);
-          GBS_MF(t0 + 1, a[3], F[cs][1].w);
-          if (!hc) {  // k-half 1 (absent from a half chunk)
-            GBS_MF(t0, a[4], F[cs][2].x);
-            GBS_MF(t0 + 1, a[4], F[cs][3].x);
-            GBS_MF(t0, a[5], F[cs][2].y);
-            GBS_MF(t0 + 1, a[5], F[cs][3].y);
-            GBS_MF(t0, a[6], F[cs][2].z);
-            GBS_MF(t0 + 1, a[6], F[cs][3].z);
-            GBS_MF(t0, a[7], F[cs][2].w);
-            GBS_MF(t0 + 1, a[7], F[cs][3].w);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
+      chunk_mfma<NT>(acc, bsrc, a, T, hc, lane);
       // every wave's share of chunk g + 1 (and its A rows) has landed, and
       // its LDS reads of chunk g are done, before any wave goes on
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_s_barrier();
       if (g + 1 < total) scale_a(an, a);
       if (c == nchunk - 1) {
-        // draws for the outcomes of this pass, in order; outcome p owns the
-        // accumulator tiles [lo, hi)
-        const int j0 = geo->j0[pi][q], j1 = geo->j0[pi][q + 1];
-        int lo = 0, slo = 0, shi = 0;
-        bool pick = false;
-        for (int p = j0; p < j1; ++p) {
-          const int hi = lo + ((p & 1) ? nto : nte);
-          // squared norm of this lane's shot: its 4 columns per tile, then the
-          // four column quads
-          float part = 0.f;
-          if (j1 - j0 == 1) {
-            // the pass's only outcome owns every nonzero tile
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) part = fmaf(acc[t][v], acc[t][v], part);
-          } else {
-            const uint32_t own = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) &
-                                 ~(lo >= 32 ? 0xffffffffu : ((1u << lo) - 1u));
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              const float f = ((own >> t) & 1u) ? 1.f : 0.f;
-#pragma unroll
-              for (int v = 0; v < 4; ++v) part = fmaf(f * acc[t][v], acc[t][v], part);
-            }
-          }
-          part += __shfl_xor(part, 16, 64);
-          part += __shfl_xor(part, 32, 64);
-          if (!done) {
-            csum += part;
-            // taken when the running sum passes u; otherwise the last outcome
-            // of positive weight (outcome 0 in any case) is the provisional one
-            done = ur < csum;
-            if (done || part > 0.f || p == 0) {
-              pick = true;
-              psel = p;
-              wsel = part;
-              slo = lo;
-              shi = hi;
-            }
-          }
-          lo = hi;
-        }
-        if (pick) {
-          wrote = true;
-          if (valid) {
-            const uint32_t own = (shi >= 32 ? 0xffffffffu : ((1u << shi) - 1u)) &
-                                 ~(slo >= 32 ? 0xffffffffu : ((1u << slo) - 1u));
-            float* orow = lout + shot * ldl2 + 4 * grp - 16 * slo;
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              if ((own >> t) & 1u) *(float4*)(orow + 16 * t) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
-          }
-        }
+        pass_draws<NT>(acc, geo->j0[pi][q], geo->j0[pi][q + 1], nte, nto, ur, csum, done, wrote, psel, wsel, valid,
+                       lout + shot * ldl2 + 4 * grp);
         // the next pass accumulates from zero
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (!kFirst && q + 1 < qlast) {
+        if (q + 1 < qlast) {
           // the workgroup stops once every one of its shots is decided; the
           // chunk already in flight is waited for first
           const int wall = __all(done || !valid);
@@ -401,6 +420,176 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     const bool fin = done || qlast >= npass;
     if (key) key[shot] = fin ? 2 : (int8_t)pi;
     if (!fin) cum[shot] = csum;
+  }
+}
+
+// The first pass of a site (outcome 0, plus any outcomes sharing its pass)
+// for every shot, as a persistent launch: each workgroup loops over blocks
+// of 128 slots (sector-0 blocks, then sector-1 blocks from slot E) with a
+// stride of the grid size, and the chunk sequence runs on across blocks, so
+// the next block's first B' chunk and A rows are fetched during the current
+// block's last chunk and its row stores drain under the next block's MFMAs.
+template <int NT>
+__global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
+    const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
+    const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
+    float* __restrict__ cum, int8_t* __restrict__ key, int64_t shot0, int64_t nshots, int site, uint32_t k0,
+    uint32_t k1, int32_t* __restrict__ out, int M) {
+  __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
+  __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int grp = lane >> 4, col = lane & 15;
+  int64_t c0 = nshots, c1 = 0;
+  if (perm) {
+    c0 = cnt[0];
+    c1 = cnt[1];
+  }
+  const int64_t nb0 = (c0 + kShotsPerWg - 1) / kShotsPerWg;
+  const int64_t nblk = nb0 + (c1 + kShotsPerWg - 1) / kShotsPerWg;
+  const int64_t e = nb0 * kShotsPerWg;
+  const int64_t stride = gridDim.x;
+  // one block as seen by this lane
+  struct Blk {
+    int pi, nchunk, T;
+    bool halfk, valid;
+    long base;
+    int64_t shot;
+    float ascale;
+  };
+  auto setup = [&](int64_t bb) {
+    Blk s;
+    const bool one = bb >= nb0;
+    s.pi = one ? 1 : 0;
+    const int64_t slot = (one ? e + (bb - nb0) * kShotsPerWg : bb * kShotsPerWg) + w * 16 + col;
+    s.valid = slot < (one ? e + c1 : c0);
+    s.shot = s.valid ? (perm ? (int64_t)perm[slot] : slot) : 0;
+    s.nchunk = geo->nchunk[s.pi];
+    s.halfk = geo->half[s.pi] != 0;
+    s.T = geo->tiles[s.pi][0];
+    s.base = geo->base[s.pi][0];
+    s.ascale = (sin && s.valid) ? sin[s.shot] : 1.f;
+    return s;
+  };
+  // the first block at or after bb whose sector has rows; the shots of a
+  // block in an empty sector get outcome 0 with weight zero (a shot cannot
+  // reach an empty sector with positive probability)
+  auto next_block = [&](int64_t bb) {
+    for (; bb < nblk; bb += stride) {
+      const int pb = bb >= nb0 ? 1 : 0;
+      if (geo->npass[pb] > 0) break;
+      const Blk s = setup(bb);
+      if (s.valid && grp == 0) {
+        sout[s.shot] = 0.f;
+        out[(shot0 + s.shot) * (int64_t)M + (site - 1)] = 0;
+        if (par_out) par_out[s.shot] = (int8_t)pb;
+        if (key) key[s.shot] = 2;
+      }
+    }
+    return bb;
+  };
+  auto load_a = [&](const Blk& s, int c, float4* r) {
+    const float* row = lin + s.shot * ldl2 + 4 * grp + 32 * c;
+    r[0] = *(const float4*)(row);       // k-half 0: rows 32c + 4 grp + (0..3)
+    r[1] = *(const float4*)(row + 16);  // k-half 1: 16 rows further
+  };
+  auto scale_a = [&](const float4* r, float sc, float* a) {
+    a[0] = r[0].x * sc; a[1] = r[0].y * sc; a[2] = r[0].z * sc; a[3] = r[0].w * sc;
+    a[4] = r[1].x * sc; a[5] = r[1].y * sc; a[6] = r[1].z * sc; a[7] = r[1].w * sc;
+  };
+  auto issue = [&](const Blk& s, int c, float* dst) {
+    const float* src = P + s.base + 512L * s.T * c;
+    if (s.halfk && c == s.nchunk - 1) {  // blocks (t, h = 0) of a half chunk
+      for (int blk = w; blk < s.T; blk += kWaves)
+        __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
+                                         (void __attribute__((address_space(3)))*)(dst + 2 * blk * 256), 16, 0, 0);
+    } else {
+      for (int blk = w; blk < 2 * s.T; blk += kWaves)
+        __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
+                                         (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
+    }
+  };
+  int64_t b = next_block((int64_t)blockIdx.x);
+  if (b >= nblk) return;  // uniform over the workgroup
+  Blk cur = setup(b);
+  int64_t bn = next_block(b + stride);
+  bool has_next = bn < nblk;
+  Blk nxt = has_next ? setup(bn) : cur;
+  floatx4 acc[NT];
+  float a[8];
+  float4 an[2];
+  issue(cur, 0, Bs0);
+  load_a(cur, 0, an);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  scale_a(an, cur.ascale, a);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int c = 0;  // chunk of the current block in the buffer being multiplied
+  bool last = false;
+  while (!last) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      // fetch the chunk that follows: the current block's next one, or the
+      // next block's first
+      const bool fnext = c + 1 >= cur.nchunk;
+      const bool fetch = !fnext || has_next;
+      if (fetch) {
+        if (fnext) {
+          issue(nxt, 0, u ? Bs0 : Bs1);
+          load_a(nxt, 0, an);
+        } else {
+          issue(cur, c + 1, u ? Bs0 : Bs1);
+          load_a(cur, c + 1, an);
+        }
+      }
+      chunk_mfma<NT>(acc, (const float4*)(u ? Bs1 : Bs0), a, cur.T, cur.halfk && c == cur.nchunk - 1, lane);
+      // every wave's share of the fetched chunk (and its A rows) has landed,
+      // and its LDS reads of this chunk are done, before any wave goes on
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_s_barrier();
+      if (fetch) scale_a(an, fnext ? nxt.ascale : cur.ascale, a);
+      if (!fnext) {
+        ++c;
+        continue;
+      }
+      // last chunk of the block: draw and store
+      float ur;
+      {
+        const int64_t gs = shot0 + cur.shot;
+        philox4 ctr;
+        ctr.v[0] = (uint32_t)gs;
+        ctr.v[1] = (uint32_t)((uint64_t)gs >> 32);
+        ctr.v[2] = (uint32_t)site;
+        ctr.v[3] = 0u;
+        ur = u01_24(philox4x32_10(ctr, k0, k1).v[0]);
+      }
+      float csum = 0.f, wsel = 0.f;
+      bool done = false, wrote = false;
+      int psel = 0;
+      pass_draws<NT>(acc, geo->j0[cur.pi][0], geo->j0[cur.pi][1], geo->nt[cur.pi], geo->nt[cur.pi ^ 1], ur, csum,
+                     done, wrote, psel, wsel, cur.valid, lout + cur.shot * ldl2 + 4 * grp);
+      if (cur.valid && grp == 0) {
+        // outcome 0 is in the first pass, so every shot has a row stored
+        sout[cur.shot] = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
+        out[(shot0 + cur.shot) * (int64_t)M + (site - 1)] = psel;
+        if (par_out) par_out[cur.shot] = (int8_t)((cur.pi + psel) & 1);
+        const bool fin = done || geo->npass[cur.pi] <= 1;
+        if (key) key[cur.shot] = fin ? 2 : (int8_t)cur.pi;
+        if (!fin) cum[cur.shot] = csum;
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (!has_next) {
+        last = true;
+        break;
+      }
+      cur = nxt;
+      c = 0;
+      bn = next_block(bn + stride);
+      has_next = bn < nblk;
+      if (has_next) nxt = setup(bn);
+    }
   }
 }
 #undef GBS_MF
@@ -594,6 +783,24 @@ hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, con
   return hipGetLastError();
 }
 
+// Workgroups of a persistent launch: as many as the device runs at once
+// (resident workgroups per CU times the CU count), counted once per kernel.
+static int64_t persistent_grid(const void* kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int64_t> known;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = known.find({dev, kernel});
+  if (it != known.end()) return it->second;
+  int ncu = 0, per = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 64 * kWaves, 0) != hipSuccess || per < 1) per = 1;
+  const int64_t g = (int64_t)ncu * per;
+  known[{dev, kernel}] = g;
+  return g;
+}
+
 hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom& g, const SamplerGeom* gd,
                               const float* lin, const float* sin, float* lout, float* sout, long ldl2,
                               const int32_t* perm, const int32_t* cnt, int8_t* par_out, float* cum, int8_t* key,
@@ -620,14 +827,16 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom&
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   // with a partition, sector 1 starts on a fresh workgroup: one more block
   dim3 grid((unsigned)((nshots + kShotsPerWg - 1) / kShotsPerWg + (perm ? 1 : 0)));
-#define GBS_SAMPLE_CASE(NTV)                                                                                       \
-  case NTV:                                                                                                        \
-    if (qbeg == 0 && qend == 1)                                                                                    \
-      hipLaunchKernelGGL((sample_mfma_kernel<NTV, true>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout,  \
-                         sout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M); \
-    else                                                                                                           \
-      hipLaunchKernelGGL((sample_mfma_kernel<NTV, false>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout, \
-                         sout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M); \
+#define GBS_SAMPLE_CASE(NTV)                                                                                      \
+  case NTV:                                                                                                       \
+    if (qbeg == 0 && qend == 1) {                                                                                 \
+      const dim3 pg((unsigned)std::min<int64_t>(grid.x, persistent_grid((const void*)sample_first_kernel<NTV>))); \
+      hipLaunchKernelGGL((sample_first_kernel<NTV>), pg, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout, sout,   \
+                         ldl2, perm, cnt, par_out, cum, key, shot0, nshots, site, k0, k1, out, M);                \
+    } else {                                                                                                      \
+      hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout, sout,  \
+                         ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M);    \
+    }                                                                                                             \
     break;
   switch (nt) {
     GBS_SAMPLE_CASE(8)

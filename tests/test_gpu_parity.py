@@ -242,10 +242,37 @@ def test_sampling_fp32_mfma_c2(torch_cuda):
     h.free()
 
 
+@pytest.mark.parametrize("name,precision,shots", [("c1", "fp64", 3_000), ("c1", "fp32", 3_000),
+                                                   ("c2", "fp64", 4_000 + 77), ("c2", "fp32", 4_000 + 77)])
+def test_sampler_matches_counter_oracle_shot_by_shot(torch_cuda, name, precision, shots):
+    """Shot-by-shot parity of the GPU sampler (FP32: MFMA sweep, FP64: vector
+    sweep) with the oracle's counter-based sampler on the oracle's own tensors:
+    the same uniform per (shot, site) and the same inverse-CDF rule.  A shot
+    may differ only from a site where the oracle's draw lies within `tol` of a
+    decision boundary (the two sides' probabilities differ by rounding: FP32
+    tensors and sums, or FP64); every other shot must be identical."""
+    _say(f"case: {name} {precision} sampler vs counter-based oracle, {shots} shots")
+    w = W.workload(name)
+    o = obuild.build_mps(w.gamma, w.d, w.chi)
+    ref, margin = omps.sample_counter(o.tensors, shots, seed=21)
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision=precision)
+    got = h.sample(shots, seed=21).cpu().numpy()
+    h.free()
+    tol = 1e-4 if precision == "fp32" else 1e-9
+    diff = got != ref
+    bad = np.flatnonzero(diff.any(axis=1))
+    for s in bad:
+        m0 = int(np.flatnonzero(diff[s])[0])
+        assert margin[s, m0] < tol, (int(s), m0, float(margin[s, m0]), got[s, m0], ref[s, m0])
+    same = 1.0 - len(bad) / shots
+    _say(f"  identical shots: {same:.5f} ({len(bad)} differ, each from a near-tie)")
+    assert same >= 0.99
+
+
 @pytest.mark.parametrize("name,shots", [("c2", 100_000 + 77), ("c3", 65_536 + 77)])
 def test_sampler_parity_sectors_match_dense(torch_cuda, name, shots):
     """The photon-parity sector sampler against the dense layout over the same
-    FP32 tensors.  Both draw with the same uniforms per (shot, site, outcome),
+    FP32 tensors.  Both draw with the same uniform per (shot, site),
     so their samples differ only where the rounding of |T_p|^2 moves a
     threshold; the sector one must also keep every shot's total photon number
     even."""

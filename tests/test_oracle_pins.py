@@ -345,6 +345,58 @@ def test_sampler_statistics():
         assert 0.5 * np.abs(emp - pm[m]).sum() < 4 * floor + 1e-3
 
 
+def test_philox_known_answer_vectors():
+    """Philox-4x32-10 against the known-answer vectors published with the
+    generator (Salmon et al., SC'11; the Random123 distribution): zero
+    counter and key, all-ones counter and key, and the digits of pi."""
+    from oracle.philox import philox4x32_10
+    kat = [((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+           ((0xffffffff,) * 4, (0xffffffff, 0xffffffff), (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+           ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+            (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1))]
+    for ctr, key, want in kat:
+        got = philox4x32_10(np.array(ctr), key)
+        assert [int(x) for x in got] == list(want)
+
+
+def test_counter_sampler_one_site_boundaries():
+    """A one-site state sum_p sqrt(q_p)|p>: the conditional distribution is q,
+    so every shot's outcome p must satisfy Q_{p-1} <= u < Q_p with Q the
+    cumulative sums of q and u the shot's uniform."""
+    from oracle.philox import site_uniforms
+    q = np.array([0.45, 0.0, 0.3, 0.15, 0.1])
+    a = np.sqrt(q).astype(np.complex128).reshape(1, 5, 1)
+    shots = 5000
+    s, margin = P.sample_counter([a], shots, seed=123)
+    u = site_uniforms(np.arange(shots), 1, 123)
+    Q = np.concatenate([[0.0], np.cumsum(q)])
+    assert np.all((Q[s[:, 0]] <= u) & (u < Q[s[:, 0] + 1]))
+    assert not np.any(s[:, 0] == 1)                   # zero-probability outcome never drawn
+    emp = np.bincount(s[:, 0], minlength=5) / shots
+    assert 0.5 * np.abs(emp - q).sum() < 4 * 0.5 * np.sum(np.sqrt(2 * q / (np.pi * shots))) + 1e-3
+    assert np.all(margin[:, 0] == np.min(np.abs(np.cumsum(q)[:-1][None, :] - u[:, None]), axis=1))
+
+
+def test_counter_sampler_statistics_and_shot_ranges():
+    """Counter-based sampler: marginals within the noise floor of the exact
+    ones, even total photon number, and a shot range reproduces the same
+    shots of a longer run (the uniforms depend on (shot, site) only)."""
+    w = W.custom(6, 4, 16, (0.3, 0.8), "haar", 12)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    shots = 4000
+    s, _ = P.sample_counter(o.tensors, shots, seed=7)
+    assert np.all(s.sum(1) % 2 == 0)
+    pm = P.site_marginals(o.tensors)
+    for m in range(w.M):
+        emp = np.bincount(s[:, m], minlength=w.d) / shots
+        floor = 0.5 * np.sum(np.sqrt(2 * pm[m] / (np.pi * shots)))
+        assert 0.5 * np.abs(emp - pm[m]).sum() < 4 * floor + 1e-3
+    part, _ = P.sample_counter(o.tensors, 300, seed=7, shot0=1234)
+    assert np.array_equal(part, s[1234:1534])
+    other, _ = P.sample_counter(o.tensors, 300, seed=8)
+    assert not np.array_equal(other, s[:300])
+
+
 def test_fidelity_overlap_and_svd_truncation():
     w = W.workload("c1")
     o = build.build_mps(w.gamma, w.d, w.chi)
