@@ -4,7 +4,9 @@ Calls only oracle/ and workloads/ (no GPU code).  Output: one JSON file per
 workload with, for the oracle's normalised MPS:
   * eps and n_e per cut, Lambda spectra per cut,
   * amplitudes <n|psi> for seeded low-photon patterns (even totals) + vacuum,
-  * exact single-mode photon-number marginals P_m(p).
+  * exact single-mode photon-number marginals P_m(p),
+  * shots of the counter-based sampler (seed 31) with every site whose draw
+    lies within 1e-3 of a decision boundary (shot, site, distance).
 
     python tests/golden/make_golden.py c3
 
@@ -50,7 +52,11 @@ def main(name):
     pats = patterns(w.M, w.d, 96, 2024)
     amps = mps.amplitudes(o.tensors, pats)
     marg = mps.site_marginals(o.tensors)
+    shots, seed = 600, 31
+    smp, margin = mps.sample_counter(o.tensors, shots, seed)
+    ties = [[int(s), int(m) + 1, float(margin[s, m])] for s, m in zip(*np.nonzero(margin < 1e-3))]
     res = dict(workload=name, M=w.M, d=w.d, chi=w.chi, oracle_build_s=t1 - t0,
+               counter_samples=dict(seed=seed, shots=shots, samples=smp.tolist(), near_ties=ties),
                n_e=o.n_e, eps=o.eps, lam=[list(map(float, l)) for l in o.Lam],
                patterns=pats, amp_re=[float(a.real) for a in amps], amp_im=[float(a.imag) for a in amps],
                marginals=marg.tolist(), mean_photons=float(np.sum(marg @ np.arange(w.d))))

@@ -363,6 +363,30 @@ def test_c3_full_size_against_oracle_reference(torch_cuda, precision):
     h.free()
 
 
+def test_c3_sampler_matches_counter_oracle_shot_by_shot(torch_cuda):
+    """M=144, d=8, chi=256, FP32 build in the configuration bench.py times:
+    600 shots of the MFMA sampler against the oracle's counter-based sampler
+    (values written by tests/golden/make_golden.py).  A shot may differ only
+    from a site listed among the oracle's near-ties (draw within 1e-4 of a
+    decision boundary); every other shot must be identical."""
+    _say("case: c3 fp32 sampler vs counter-based oracle, 600 shots")
+    g = _golden("c3")["counter_samples"]
+    ref = np.array(g["samples"], dtype=np.int32)
+    ties = {(s, m): dist for s, m, dist in g["near_ties"]}
+    w = W.workload("c3")
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
+    got = h.sample(g["shots"], seed=g["seed"]).cpu().numpy()
+    h.free()
+    diff = got != ref
+    bad = np.flatnonzero(diff.any(axis=1))
+    for s in bad:
+        m0 = int(np.flatnonzero(diff[s])[0])
+        assert ties.get((int(s), m0 + 1), 1.0) < 1e-4, (int(s), m0 + 1, got[s, m0], ref[s, m0])
+    same = 1.0 - len(bad) / len(ref)
+    _say(f"  identical shots: {same:.5f} ({len(bad)} differ, each from a near-tie)")
+    assert same >= 0.99
+
+
 def test_c3_sampling_tvd_1e6_shots(torch_cuda):
     """10^6 FP32-MFMA samples at C3: per-mode marginal TVD against the oracle's
     exact marginals <= 1e-3 (and within 5x the statistical floor)."""
