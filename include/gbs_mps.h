@@ -102,6 +102,24 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
  *   out : device, shots x M int32.  Asynchronous on `stream`. */
 int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
 
+/* GPU time of the launches of one sampling call (HIP events on its stream). */
+typedef struct {
+  int32_t first_launches;  /* first-pass launches: outcome 0 for every shot, one per site */
+  int32_t rest_launches;   /* launches for the shots a first pass left undecided */
+  double first_ms;         /* summed time of the first-pass launches */
+  double rest_ms;          /* summed time of the other launches */
+  double total_ms;         /* the whole call, first launch to last */
+} gbs_sample_timing_t;
+
+/* gbs_mps_sample with HIP events recorded on `stream` around each launch of
+ * the MFMA sampling sweep (FP32 and BF16x3 handles), for measurement: same
+ * samples, plus the launch counts and times in `t` (host).  Synchronises
+ * `stream` before returning.  Handles sampled by the vector sweep (FP64)
+ * report zero launches and only total_ms.  Errors as gbs_mps_sample; a NULL
+ * `t` is GBS_E_INVAL. */
+int gbs_mps_sample_timed(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream,
+                         gbs_sample_timing_t* t);
+
 /* Overlap <psi1|psi2> of two MPS over the same M and d, by an FP64 transfer
  * contraction on the GPU (E <- sum_p A1[p]^dag E A2[p]).  The wavefunction
  * fidelity used to compare builds (Sec. III.A) is

@@ -23,7 +23,7 @@ GBS_DENSE_SAMPLER = 2
 EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5, "sectors": 6}
 
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
-EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_overlap", "gbs_mps_overlap_prec",
+EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
                     "gbs_mps_info",
                     "gbs_mps_export", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
                     "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
@@ -40,6 +40,11 @@ class GbsError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("chi", ctypes.c_int32), ("dstar", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32), ("trunc_rel", ctypes.c_double)]
+
+
+class SampleTimingT(ctypes.Structure):
+    _fields_ = [("first_launches", ctypes.c_int32), ("rest_launches", ctypes.c_int32), ("first_ms", ctypes.c_double),
+                ("rest_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
 class InfoT(ctypes.Structure):
@@ -87,6 +92,8 @@ def lib():
         L.gbs_mps_amplitude.restype = ctypes.c_int
         L.gbs_mps_sample.argtypes = [vp, i64, u64, dp, vp]
         L.gbs_mps_sample.restype = ctypes.c_int
+        L.gbs_mps_sample_timed.argtypes = [vp, i64, u64, dp, vp, ctypes.POINTER(SampleTimingT)]
+        L.gbs_mps_sample_timed.restype = ctypes.c_int
         L.gbs_mps_overlap.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         L.gbs_mps_overlap.restype = ctypes.c_int
         L.gbs_mps_overlap_prec.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp]

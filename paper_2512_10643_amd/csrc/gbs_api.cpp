@@ -962,7 +962,80 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
   return GBS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// HIP events around the sampling launches of one call (measurement only).
+struct SampleClock {
+  std::vector<hipEvent_t> first, rest;  // start / end pairs
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipStream_t st;
+  explicit SampleClock(hipStream_t s) : st(s) {}
+  ~SampleClock() {
+    for (auto e : first) hipEventDestroy(e);
+    for (auto e : rest) hipEventDestroy(e);
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+  }
+  hipError_t mark(std::vector<hipEvent_t>& v) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    v.push_back(e);
+    return hipEventRecord(e, st);
+  }
+  hipError_t edge(hipEvent_t* e) {
+    hipError_t r = hipEventCreate(e);
+    if (r != hipSuccess) return r;
+    return hipEventRecord(*e, st);
+  }
+};
+
+double pair_ms(const std::vector<hipEvent_t>& v) {
+  double s = 0;
+  for (size_t i = 0; i + 1 < v.size(); i += 2) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) s += ms;
+  }
+  return s;
+}
+
+int sample_impl(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream, SampleClock* clk);
+
+}  // namespace
+
+extern "C" {
+
 int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream) {
+  return sample_impl(h, shots, seed, out, stream, nullptr);
+}
+
+int gbs_mps_sample_timed(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream,
+                         gbs_sample_timing_t* t) {
+  if (!t) return fail(GBS_E_INVAL, "NULL timing output");
+  *t = gbs_sample_timing_t{};
+  SampleClock clk((hipStream_t)stream);
+  HIP_CHECK_RET(clk.edge(&clk.t0));
+  int rc = sample_impl(h, shots, seed, out, stream, &clk);
+  if (rc != GBS_OK) return rc;
+  HIP_CHECK_RET(clk.edge(&clk.t1));
+  HIP_CHECK_RET(hipStreamSynchronize((hipStream_t)stream));
+  float ms = 0;
+  HIP_CHECK_RET(hipEventElapsedTime(&ms, clk.t0, clk.t1));
+  t->total_ms = ms;
+  t->first_launches = (int32_t)(clk.first.size() / 2);
+  t->rest_launches = (int32_t)(clk.rest.size() / 2);
+  t->first_ms = pair_ms(clk.first);
+  t->rest_ms = pair_ms(clk.rest);
+  return GBS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int sample_impl(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream, SampleClock* clk) {
   if (!h) return fail(GBS_E_INVAL, "NULL handle");
   if (shots < 0) return fail(GBS_E_INVAL, "shots < 0");
   if (shots == 0) return GBS_OK;
@@ -1014,15 +1087,19 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
         const float* P = h->packed + h->poff[m];
         const float* sin = m == 1 ? nullptr : sb[cur];
         // first pass (outcome 0) for every shot
+        if (clk) HIP_CHECK_RET(clk->mark(clk->first));
         HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, fb[cur], sin, fb[1 - cur], sb[1 - cur], ldl2,
                                          part ? perm : nullptr, part ? cnt : nullptr, next ? par : nullptr,
                                          more ? cum : nullptr, more ? key : nullptr, 0, 1, s0, n, m, seed, out, M));
+        if (clk) HIP_CHECK_RET(clk->mark(clk->first));
         if (more) {
           // the other passes for the shots the first one left undecided
           HIP_CHECK_RET(launch_sampler_partition(st, key, n, bcnt, perm2, cnt2));
+          if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
           HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, fb[cur], sin, fb[1 - cur], sb[1 - cur], ldl2,
                                            perm2, cnt2, next ? par : nullptr, cum, nullptr, 1, kSamplerMaxOutcomes,
                                            s0, n, m, seed, out, M));
+          if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
         }
         if (next) HIP_CHECK_RET(launch_sampler_partition(st, par, n, bcnt, perm, cnt));
         cur = 1 - cur;
@@ -1055,6 +1132,10 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
   }
   return GBS_OK;  // the temporaries are freed in stream order
 }
+
+}  // namespace
+
+extern "C" {
 
 int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream) {
   return gbs_mps_overlap_prec(h1, h2, GBS_FP64, out, stream);

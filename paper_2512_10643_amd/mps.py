@@ -56,6 +56,17 @@ class GaussianMPS:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
+    def sample_timed(self, shots: int, seed: int, out: torch.Tensor | None = None, stream=None):
+        """sample() with HIP events around each sampling launch; returns
+        (samples, dict of launch counts and GPU milliseconds).  Synchronises
+        the stream."""
+        if out is None:
+            out = torch.empty((shots, self.M), dtype=torch.int32, device="cuda")
+        t = _lib.SampleTimingT()
+        check(lib().gbs_mps_sample_timed(self._h, int(shots), ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream), ctypes.byref(t)))
+        return out, {k: getattr(t, k) for k, _ in _lib.SampleTimingT._fields_}
+
     def overlap(self, other: "GaussianMPS", stream=None, precision: str = "fp64") -> complex:
         """<self|other> by a transfer contraction on the GPU in the given
         arithmetic (fp64, fp32 or bf16x3)."""

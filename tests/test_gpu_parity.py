@@ -316,6 +316,25 @@ def test_sampler_parity_sectors_match_dense(torch_cuda, name, shots):
     hd.free()
 
 
+def test_sample_timed_matches_sample(torch_cuda):
+    """The timed sampling entry point draws the same samples and reports one
+    first-pass launch per site, with positive times that fit in the call."""
+    _say("case: c2 fp32 sample_timed vs sample, 20077 shots")
+    w = W.workload("c2")
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp32")
+    a = h.sample(20_077, seed=3).cpu().numpy()
+    b, t = h.sample_timed(20_077, seed=3)
+    assert np.array_equal(a, b.cpu().numpy())
+    assert t["first_launches"] == w.M
+    assert 0 <= t["rest_launches"] <= w.M
+    assert 0 < t["first_ms"] and 0 <= t["rest_ms"] and t["first_ms"] + t["rest_ms"] <= t["total_ms"] * 1.001
+    h.free()
+    h64 = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    c, t64 = h64.sample_timed(1000, seed=3)
+    assert t64["first_launches"] == 0 and t64["total_ms"] > 0
+    h64.free()
+
+
 # ---------------------------------------------------------- full size (C3)
 
 def _golden(name):
