@@ -154,6 +154,22 @@ def test_edge_cases(torch_cuda, case):
     err = np.max(np.abs(gpu_amps(torch_cuda, h, pats) - omps.amplitudes(o.tensors, pats)))
     _say(f"  max |delta| = {err:.3e}")
     assert err <= 1e-10
+    # samples of the FP64 (vector sweep) and FP32 (MFMA sweep) builds against
+    # the counter-based oracle, shot by shot (differences only from near-ties)
+    shots = 2_000 + 37
+    ref, margin = omps.sample_counter(o.tensors, shots, seed=17)
+    h32 = gpu_build(torch_cuda, g, d, chi, precision="fp32")
+    for hh, tol in ((h, 1e-9), (h32, 1e-4)):
+        got = hh.sample(shots, seed=17).cpu().numpy()
+        assert np.all((got >= 0) & (got < d)) and np.all(got.sum(1) % 2 == 0)
+        diff = got != ref
+        bad = np.flatnonzero(diff.any(axis=1))
+        for sh in bad:
+            m0 = int(np.flatnonzero(diff[sh])[0])
+            assert margin[sh, m0] < tol, (int(sh), m0, float(margin[sh, m0]))
+        _say(f"  samples ({hh.info()['sampler_layout']}): {len(bad)} of {shots} shots differ, each from a near-tie")
+        assert len(bad) <= 0.01 * shots
+    h32.free()
     h.free()
 
 
