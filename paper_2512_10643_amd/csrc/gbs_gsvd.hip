@@ -741,23 +741,58 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     const double sg = ((i >> 1) & 1) ? -1.41421356237309515 : 1.41421356237309515;
     XU[e] = (i & 1) ? 0.0 : sg * Z[(long)i * n + q];
   }
-  const int Gp = max(1, nt / n);
-  const int cq = tid / Gp, gq = tid % Gp;
-  for (int k = N2 - 3; k >= 0; --k) {
-    const int r = N2 - k - 1;
-    wg_sync();
-    for (int i = tid; i < r; i += nt) vL[i] = Vh[(long)k * ld + i];
-    wg_sync();
-    double acc = 0.0;
-    if (cq < n)
-      for (int i = gq; i < r; i += Gp) acc += vL[i] * XU[(long)cq * N2 + k + 1 + i];
-    part[tid] = acc;
-    wg_sync();
-    if (cq < n) {
-      double w = 0.0;
-      for (int g2 = 0; g2 < Gp; ++g2) w += part[cq * Gp + g2];
-      w *= tauL[k];
-      for (int i = gq; i < r; i += Gp) XU[(long)cq * N2 + k + 1 + i] -= w * vL[i];
+  // With XU in LDS and room beside it, a column belongs to an aligned group
+  // of Gp lanes of one wave and each lane to a fixed set of rows (i = g mod
+  // Gp), so a reflector needs no barrier: the dot product is reduced by
+  // shuffles within the group and every lane updates only its own rows.  The
+  // reflectors are staged into LDS a few at a time (two barriers per group).
+  const long lds_cap = (long)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2;
+  const int nst = XU == lds ? (int)min(8L, (lds_cap - (long)n * N2) / N2) : 0;
+  if (nst >= 2 && n <= nt) {
+    int Gp = 64;
+    while (Gp > 1 && Gp * n > nt) Gp >>= 1;
+    const int cq = tid / Gp, gq = tid % Gp;
+    double* VS = lds + (long)n * N2;  // staged reflectors, slot s at VS[s N2 + j]
+    double* xc = XU + (long)cq * N2;
+    for (int kb = N2 - 3; kb >= 0; kb -= nst) {
+      const int kl = max(0, kb - nst + 1);
+      wg_sync();
+      for (int e = tid; e < (kb - kl + 1) * N2; e += nt) {
+        const int sl = e / N2, j = e % N2, k = kb - sl;
+        VS[e] = j < N2 - k - 1 ? Vh[(long)k * ld + j] : 0.0;
+      }
+      wg_sync();
+      if (cq < n) {
+        for (int k = kb; k >= kl; --k) {
+          const double* v = VS + (long)(kb - k) * N2 - (k + 1);  // v[i]: entry of row i
+          const int i0 = k + 1 <= gq ? gq : gq + (k + 1 - gq + Gp - 1) / Gp * Gp;
+          double acc = 0.0;
+          for (int i = i0; i < N2; i += Gp) acc += v[i] * xc[i];
+          for (int off = Gp >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+          const double w = acc * tauL[k];
+          for (int i = i0; i < N2; i += Gp) xc[i] -= w * v[i];
+        }
+      }
+    }
+  } else {
+    const int Gp = max(1, nt / n);
+    const int cq = tid / Gp, gq = tid % Gp;
+    for (int k = N2 - 3; k >= 0; --k) {
+      const int r = N2 - k - 1;
+      wg_sync();
+      for (int i = tid; i < r; i += nt) vL[i] = Vh[(long)k * ld + i];
+      wg_sync();
+      double acc = 0.0;
+      if (cq < n)
+        for (int i = gq; i < r; i += Gp) acc += vL[i] * XU[(long)cq * N2 + k + 1 + i];
+      part[tid] = acc;
+      wg_sync();
+      if (cq < n) {
+        double w = 0.0;
+        for (int g2 = 0; g2 < Gp; ++g2) w += part[cq * Gp + g2];
+        w *= tauL[k];
+        for (int i = gq; i < r; i += Gp) XU[(long)cq * N2 + k + 1 + i] -= w * vL[i];
+      }
     }
   }
   wg_sync();
