@@ -36,7 +36,7 @@ struct SamplerSite {
 // nchunk[pi] K-chunks of 32 real rows, the last of each pass holding only
 // its first 16 when half[pi] (rows are padded to 8 complex entries); right
 // sector s is nt[s] tiles wide;
-// pass q covers visiting positions [j0[pi][q], j0[pi][q + 1]) with
+// pass q covers outcomes [j0[pi][q], j0[pi][q + 1]) with
 // tiles[pi][q] tiles per chunk, its chunks starting at float base[pi][q] of
 // the packed operand.  NT: accumulator tiles of the kernel instance.
 struct SamplerGeom {
