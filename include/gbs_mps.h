@@ -82,6 +82,20 @@ typedef struct {
  * Synchronises `stream` internally (buffer sizes depend on the spectra). */
 int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out);
 
+/* The tensor of one site alone, at bond dimension chi <= 4096: the shape of
+ * the paper's own benchmark, a central tensor at large D (Sec. III.A).  Runs
+ * the Gaussian SVD chain, the kept bases of cuts site-1 and site, and the
+ * PCO build of that tensor (Eq. Am_definition, Sec. II.C.2), in FP64, with no
+ * truncation sweep or normalisation.  The handle holds the raw tensor
+ * (gbs_mps_export GBS_EXPORT_RAW at `site`, kept[site-1] x d x kept[site]),
+ * the Gaussian data of every cut and the kept bases of the two cuts;
+ * amplitude, sample and overlap calls on it fail with GBS_E_INVAL.
+ *   gamma, M, opt, stream, out : as gbs_mps_build (opt->prec and
+ *   opt->trunc_rel are not used; the chi * d limit of full builds does not
+ *   apply, d <= 64);  site : 1..M (GBS_E_INVAL otherwise). */
+int gbs_mps_build_site(const double* gamma, int32_t M, const gbs_build_opts* opt, int32_t site, void* stream,
+                       gbs_mps* out);
+
 /* Amplitudes <n|psi> of the normalised MPS for B occupation patterns.
  *   patterns : device, B x M int32, 0 <= n < d.
  *   out      : device, B x 2 FP64 (re, im).

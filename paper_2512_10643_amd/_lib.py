@@ -23,7 +23,7 @@ GBS_DENSE_SAMPLER = 2
 EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5, "sectors": 6}
 
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
-EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
+EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_build_site", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
                     "gbs_mps_info",
                     "gbs_mps_export", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
                     "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
@@ -88,6 +88,8 @@ def lib():
         vp, i32, i64, u64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
         L.gbs_mps_build.argtypes = [dp, i32, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
         L.gbs_mps_build.restype = ctypes.c_int
+        L.gbs_mps_build_site.argtypes = [dp, i32, ctypes.POINTER(BuildOpts), i32, vp, ctypes.POINTER(vp)]
+        L.gbs_mps_build_site.restype = ctypes.c_int
         L.gbs_mps_amplitude.argtypes = [vp, dp, i64, dp, vp]
         L.gbs_mps_amplitude.restype = ctypes.c_int
         L.gbs_mps_sample.argtypes = [vp, i64, u64, dp, vp]

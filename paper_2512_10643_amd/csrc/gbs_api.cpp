@@ -129,6 +129,7 @@ struct gbs_mps_s {
   int64_t pco_updates = 0;
   double t_gsvd = 0, t_kept = 0, t_pco = 0, t_svd = 0;
   int eig_sweeps = 0;            // sweeps of the bond eigensolver
+  int single_site = 0;           // > 0: the handle holds that site's PCO tensor only
   // canonical tensors
   void* tens = nullptr;          // contiguous, element size esz
   size_t esz = 16;
@@ -472,7 +473,7 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   return GBS_OK;
 }
 
-int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t st, gbs_mps_s* h) {
+int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t st, gbs_mps_s* h, int only_site) {
   const int d = opt->d, chi = opt->chi;
   HIP_CHECK_RET(ensure_pool(st));
   DevArena tmp(st);
@@ -582,8 +583,10 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   std::vector<CutDesc> cuts(M + 1);
   long off_state = 0, off_occ = 0;
   for (int m = 0; m <= M; ++m) {
+    // a single-site build needs the kept bases of the two cuts of its site
+    const bool need = only_site == 0 || m == only_site - 1 || m == only_site;
     cuts[m].ne = ne[m];
-    cuts[m].chi = ne[m] > 0 ? chi : 1;
+    cuts[m].chi = ne[m] > 0 && need ? chi : 1;
     cuts[m].off_state = off_state;
     cuts[m].off_occ = off_occ;
     off_state += cuts[m].chi;
@@ -629,7 +632,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   // truncation error per cut: eps_m = 1 - (1/Z) sum_kept exp(-E)
   h->eps.assign(M + 1, 0.0);
   for (int m = 1; m < M; ++m) {
-    if (ne[m] == 0) continue;
+    if (ne[m] == 0 || (only_site && m != only_site - 1 && m != only_site)) continue;
     double logz = 0;
     for (double l : h->lam[m]) logz += -std::log1p(-l * l);
     double acc = 0;
@@ -681,6 +684,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   // blocks per level
   std::vector<std::vector<LevelBlock>> lv;
   for (int m = 1; m <= M; ++m) {
+    if (only_site && m != only_site) continue;
     for (size_t ia = 0; ia < grp_n[m - 1].size(); ++ia)
       for (size_t ib = 0; ib < grp_n[m].size(); ++ib)
         for (int p = 0; p < d; ++p) {
@@ -715,7 +719,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   }
   lv_first[lv.size()] = allb.size();
   cplx64* T64;
-  HIP_CHECK_RET(dalloc(h->flags & GBS_KEEP_RAW ? h->keep : tmp, &T64, (size_t)std::max(ttot, 1L)));
+  HIP_CHECK_RET(dalloc((h->flags & GBS_KEEP_RAW) || only_site ? h->keep : tmp, &T64, (size_t)std::max(ttot, 1L)));
   HIP_CHECK_RET(hipMemsetAsync(T64, 0, sizeof(cplx64) * ttot, st));
   PcoArgs pa{};
   SiteDesc* sites_dev;
@@ -744,13 +748,20 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     updates += lv_nelem[k];
   }
   h->pco_updates = updates;
-  if (h->flags & GBS_KEEP_RAW) {
+  if ((h->flags & GBS_KEEP_RAW) || only_site) {
     h->raw = T64;
     h->raw_off = t64off;
   }
   HIP_CHECK_RET(hipStreamSynchronize(st));
   double t3 = now_ms();
   h->t_pco = t3 - t2;
+  if (only_site) {
+    // the raw PCO tensor of one site: no truncation sweep or normalisation
+    h->single_site = only_site;
+    h->bond = kept;
+    h->maxbond = *std::max_element(kept.begin(), kept.end());
+    return GBS_OK;
+  }
   // ---- truncation sweep and canonical form
   int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off)
                                  : canonicalize<cplx32>(h, st, tmp, T64, t64off);
@@ -892,7 +903,7 @@ int overlap_impl(gbs_mps_s* h1, gbs_mps_s* h2, hipStream_t st, int prec, double*
 __attribute__((visibility("hidden"))) int gbs_fail(int code, const std::string& msg) { return fail(code, msg); }
 
 __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t stream, bool ordered_keep,
-                     gbs_mps* out) {
+                     gbs_mps* out, int only_site) {
   if (!out) return fail(GBS_E_INVAL, "out_handle is NULL");
   *out = nullptr;
   if (!gamma || !opt) return fail(GBS_E_INVAL, "NULL gamma or options");
@@ -902,7 +913,9 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   if (!(opt->dstar > 1.0)) return fail(GBS_E_INVAL, "dstar must be > 1");
   if (opt->prec != GBS_FP64 && opt->prec != GBS_FP32 && opt->prec != GBS_BF16X3)
     return fail(GBS_E_INVAL, "unknown precision");
-  if ((long)opt->chi * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi * d too large");
+  if (only_site < 0 || only_site > M) return fail(GBS_E_INVAL, "site out of range");
+  if (!only_site && (long)opt->chi * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi * d too large");
+  if (opt->d > 64) return fail(GBS_E_INVAL, "d must be <= 64");
   if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER)) return fail(GBS_E_INVAL, "unknown build flag");
   gbs_mps_s* h = new (std::nothrow) gbs_mps_s();
   if (!h) return fail(GBS_E_NOMEM, "host allocation failed");
@@ -919,7 +932,7 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   }
   int rc;
   try {
-    rc = build_impl(gamma, M, opt, stream, h);
+    rc = build_impl(gamma, M, opt, stream, h, only_site);
   } catch (...) {
     rc = fail(GBS_E_INTERNAL, "unexpected host exception");
   }
@@ -935,12 +948,20 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
 extern "C" {
 
 int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out) {
-  return gbs_build_handle(gamma, M, opt, (hipStream_t)stream, false, out);
+  return gbs_build_handle(gamma, M, opt, (hipStream_t)stream, false, out, 0);
+}
+
+int gbs_mps_build_site(const double* gamma, int32_t M, const gbs_build_opts* opt, int32_t site, void* stream,
+                       gbs_mps* out) {
+  if (out) *out = nullptr;
+  if (site < 1 || site > M) return fail(GBS_E_INVAL, "site out of range");
+  return gbs_build_handle(gamma, M, opt, (hipStream_t)stream, false, out, site);
 }
 
 
 int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out, void* stream) {
   if (!h) return fail(GBS_E_INVAL, "NULL handle");
+  if (h->single_site) return fail(GBS_E_INVAL, "the handle holds one site's tensor only");
   if (B < 0) return fail(GBS_E_INVAL, "B < 0");
   if (B == 0) return GBS_OK;
   if (!patterns || !out) return fail(GBS_E_INVAL, "NULL pointer");
@@ -1037,6 +1058,7 @@ namespace {
 
 int sample_impl(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream, SampleClock* clk) {
   if (!h) return fail(GBS_E_INVAL, "NULL handle");
+  if (h->single_site) return fail(GBS_E_INVAL, "the handle holds one site's tensor only");
   if (shots < 0) return fail(GBS_E_INVAL, "shots < 0");
   if (shots == 0) return GBS_OK;
   if (!out) return fail(GBS_E_INVAL, "NULL output");
@@ -1143,6 +1165,7 @@ int gbs_mps_overlap(gbs_mps h1, gbs_mps h2, double* out, void* stream) {
 
 int gbs_mps_overlap_prec(gbs_mps h1, gbs_mps h2, int32_t prec, double* out, void* stream) {
   if (!h1 || !h2 || !out) return fail(GBS_E_INVAL, "NULL argument");
+  if (h1->single_site || h2->single_site) return fail(GBS_E_INVAL, "a handle holds one site's tensor only");
   if (h1->M != h2->M || h1->d != h2->d) return fail(GBS_E_INVAL, "overlap needs equal M and d");
   if (prec != GBS_FP64 && prec != GBS_FP32 && prec != GBS_BF16X3) return fail(GBS_E_INVAL, "unknown precision");
   hipStream_t st = (hipStream_t)stream;
@@ -1191,6 +1214,10 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
     if (written) *written = (int64_t)n;
     return GBS_OK;
   };
+  if (h->single_site && (what == GBS_EXPORT_TENSOR || what == GBS_EXPORT_SVALS || what == GBS_EXPORT_SECTORS))
+    return fail(GBS_E_INVAL, "the handle holds one site's PCO tensor only");
+  if (h->single_site && what == GBS_EXPORT_RAW && m != h->single_site)
+    return fail(GBS_E_INVAL, "the handle holds the tensor of another site");
   if (what == GBS_EXPORT_TENSOR) {
     if (m < 1 || m > M) return fail(GBS_E_INVAL, "site out of range");
     long n = (long)h->bond[m - 1] * d * h->bond[m];

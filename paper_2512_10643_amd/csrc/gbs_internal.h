@@ -10,7 +10,7 @@
 // buffers are stream-ordered allocations on `stream` and are released in
 // order on it by gbs_mps_free (the stream must outlive the handle).
 int gbs_build_handle(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t stream, bool ordered_keep,
-                     gbs_mps* out);
+                     gbs_mps* out, int only_site);
 
 // Record `msg` as this thread's gbs_last_error() text and return `code`.
 int gbs_fail(int code, const std::string& msg);

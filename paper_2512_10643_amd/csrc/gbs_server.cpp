@@ -100,7 +100,7 @@ void gbs_server_s::worker(int slot) {
     }
     q->t_start = wall_ms();
     gbs_mps h = nullptr;
-    int rc = gbs_build_handle(q->r.gamma, q->r.M, &q->r.opt, st, true, &h);
+    int rc = gbs_build_handle(q->r.gamma, q->r.M, &q->r.opt, st, true, &h, 0);
     q->t_built = wall_ms();
     if (rc == GBS_OK && q->r.shots > 0) rc = gbs_mps_sample(h, q->r.shots, q->r.seed, q->r.out, st);
     if (rc == GBS_OK && hipStreamSynchronize(st) != hipSuccess) {

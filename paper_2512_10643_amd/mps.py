@@ -24,6 +24,7 @@ class GaussianMPS:
         self._h = handle
         self.M = M
         self.d = d
+        self.site = None  # set for a single-site build (build_site)
 
     # -- lifetime
     def free(self) -> None:
@@ -108,7 +109,8 @@ class GaussianMPS:
         if what == "tensor":
             buf = np.empty(max(1, bond[m - 1] * d * bond[m]), dtype=np.complex128)
         elif what == "raw":
-            buf = np.empty(max(1, chi * d * chi), dtype=np.complex128)
+            n = bond[m - 1] * d * bond[m] if self.site else chi * d * chi
+            buf = np.empty(max(1, n), dtype=np.complex128)
         elif what == "Q":
             k = ne[m - 1] + 1 + ne[m]
             buf = np.empty(max(1, k * k), dtype=np.complex128)
@@ -135,6 +137,26 @@ class GaussianMPS:
         if what == "sectors":
             return arr.reshape(self.M + 1, 2)
         return arr
+
+
+def build_site(gamma: torch.Tensor, d: int, chi: int, site: int, dstar: float = 1.0 + 1e-10,
+               stream=None) -> GaussianMPS:
+    """The raw PCO tensor of one site (1-based) at bond dimension chi, in
+    FP64, without the rest of the MPS: export(site, "raw") gives it as
+    kept[site-1] x d x kept[site]; info() gives the phase times."""
+    if not isinstance(gamma, torch.Tensor) or not gamma.is_cuda or gamma.dtype != torch.float64:
+        raise ValueError("gamma must be a CUDA float64 tensor")
+    if gamma.dim() != 2 or gamma.shape[0] != gamma.shape[1] or gamma.shape[0] % 2:
+        raise GbsError(_lib.GBS_E_INVAL, "gamma must be 2M x 2M")
+    gamma = gamma.contiguous()
+    M = gamma.shape[0] // 2
+    opts = BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS["fp64"], flags=0, trunc_rel=0.0)
+    h = ctypes.c_void_p()
+    check(lib().gbs_mps_build_site(ctypes.c_void_p(gamma.data_ptr()), M, ctypes.byref(opts), int(site),
+                                   _stream_handle(stream), ctypes.byref(h)))
+    g = GaussianMPS(h, M, d)
+    g.site = int(site)
+    return g
 
 
 def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, precision: str = "fp64",

@@ -351,6 +351,81 @@ def test_sample_timed_matches_sample(torch_cuda):
     h64.free()
 
 
+# ------------------------------------------------- one site at large D (C3)
+
+def _oracle_site_inputs(w, m, chi):
+    """The oracle's own Q^m and kept bases of cuts m-1 and m (Gaussian SVD
+    chain and best-first enumeration, no GPU data)."""
+    from oracle import gaussian as og, kept as ok
+    gs = og.gsvd(w.gamma)
+    bl = ok.kept_basis(gs.cuts[m - 2].Lam, chi)[0] if m >= 2 else [()]
+    br = ok.kept_basis(gs.cuts[m - 1].Lam, chi)[0] if m <= w.M - 1 else [()]
+    return gs.Q[m - 1], bl, br
+
+
+def test_single_site_tensor_matches_oracle(torch_cuda):
+    """The central tensor of C3 alone (site 72, D=300, d=8): kept bases equal
+    the oracle's and every element of the raw PCO tensor matches the oracle's
+    sequential PCO build (up to a phase per virtual mode: magnitudes), to the
+    FP64 amplitude bar of 1e-10."""
+    _say("case: c3 central tensor alone, site 72, D=300, d=8")
+    from oracle import pco as opco
+    from paper_2512_10643_amd import mps as gmps
+    w, m, D, d = W.workload("c3"), 72, 300, 8
+    q, bl, br = _oracle_site_inputs(w, m, D)
+    ref = opco.build_tensor(q, bl, br, d)
+    g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
+    h = gmps.build_site(g, d, D, m)
+    assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
+    assert [tuple(r) for r in h.export(m, "basis")] == list(br)
+    raw = h.export(m, "raw")
+    assert raw.shape == ref.shape
+    err = np.max(np.abs(np.abs(raw) - np.abs(ref)))
+    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {np.max(np.abs(ref)):.3e})")
+    # the FP64 amplitude bar: both sides' Q^m come from 71 cuts of their own
+    # Gaussian SVD chains, which agree to ~1e-11 at the central cut
+    assert err <= 1e-10 * max(1.0, np.max(np.abs(ref)))
+    from paper_2512_10643_amd import GbsError
+    with pytest.raises(GbsError):
+        h.sample(10, seed=1)
+    h.free()
+
+
+def test_single_site_large_d_elements_are_hafnians(torch_cuda):
+    """The central tensor of C3 at D=4096, d=4 (the largest bond the build
+    takes): kept bases equal the oracle's enumeration, sampled elements equal
+    haf(Q_[n]) / sqrt(n!) of the oracle's own Q^m (magnitudes), and elements
+    of odd total photon number vanish."""
+    _say("case: c3 central tensor alone, site 72, D=4096, d=4")
+    from oracle import hafnian as oh
+    from paper_2512_10643_amd import mps as gmps
+    w, m, D, d = W.workload("c3"), 72, 4096, 4
+    q, bl, br = _oracle_site_inputs(w, m, D)
+    g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
+    h = gmps.build_site(g, d, D, m)
+    inf = h.info()
+    _say(f"  kept {inf['bond'][m - 1]} x {d} x {inf['bond'][m]}; gsvd {inf['t_gsvd_ms']:.1f} ms, "
+         f"kept {inf['t_kept_ms']:.1f} ms, pco {inf['t_pco_ms']:.1f} ms, {inf['pco_updates']} elements")
+    assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
+    assert [tuple(r) for r in h.export(m, "basis")] == list(br)
+    raw = h.export(m, "raw")
+    h.free()
+    rng = np.random.default_rng(5)
+    worst, checked, zeros = 0.0, 0, 0
+    while checked < 60:
+        i, p, j = int(rng.integers(len(bl))), int(rng.integers(d)), int(rng.integers(len(br)))
+        n = tuple(bl[i]) + (p,) + tuple(br[j])
+        if sum(n) % 2:
+            zeros += 1
+            assert raw[i, p, j] == 0
+            continue
+        ref = oh.fock_amplitude(q, n)
+        worst = max(worst, abs(abs(raw[i, p, j]) - abs(ref)))
+        checked += 1
+    _say(f"  {checked} sampled elements: max ||A| - |haf / sqrt(n!)|| = {worst:.3e}; {zeros} odd ones are 0")
+    assert worst <= 1e-10
+
+
 # ---------------------------------------------------------- full size (C3)
 
 def _golden(name):
