@@ -213,6 +213,50 @@ def contractions(name):
     return out
 
 
+def central_tensor(dims=(300, 1000, 2000, 4096), cutoffs=(4, 6, 8, 10), oracle=True):
+    """The paper's own benchmark shape: the central tensor of a 144-mode pure
+    state with five squeezed modes among vacua through a Haar interferometer,
+    built alone (gbs_mps_build_site, FP64) at bond dimension D and cutoff d.
+    Reports the phase times of the second of two builds, the tensor elements
+    the PCO level gather produced and their rate; with oracle=True, the CPU
+    oracle's time for the same tensor at D=1000, d=10."""
+    import torch
+    import workloads
+    from paper_2512_10643_amd import mps as gmps
+    w = workloads.few_squeezed()
+    site = w.M // 2
+    g = torch.tensor(w.gamma, dtype=torch.float64, device="cuda")
+    out = {"metric": "central tensor alone (FP64): build time and PCO elements/s",
+           "workload": f"M={w.M}, 5 squeezed modes r~U[0.6,1.0] among vacua, Haar interferometer; site {site}",
+           "mean_photons": w.mean_photons, "runs": []}
+    for D in dims:
+        for d in cutoffs:
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = gmps.build_site(g, d, D, site)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                inf = h.info()
+                h.free()
+            out["runs"].append({"D": D, "d": d, "kept": [inf["bond"][site - 1], inf["bond"][site]],
+                                "n_e": [inf["ne"][site - 1], inf["ne"][site]], "total_ms": 1000 * dt,
+                                "gsvd_ms": inf["t_gsvd_ms"], "kept_ms": inf["t_kept_ms"], "pco_ms": inf["t_pco_ms"],
+                                "elements": inf["pco_updates"],
+                                "elements_per_s": inf["pco_updates"] / max(inf["t_pco_ms"], 1e-9) * 1e3})
+            print(f"central tensor D={D} d={d}: {1000 * dt:.1f} ms", file=sys.stderr, flush=True)
+    if oracle:
+        from oracle import gaussian as og, kept as ok, pco as opco
+        D, d = 1000, 10  # about 15 s of CPU work
+        t0 = time.perf_counter()
+        gs = og.gsvd(w.gamma)
+        bl = ok.kept_basis(gs.cuts[site - 2].Lam, D)[0]
+        br = ok.kept_basis(gs.cuts[site - 1].Lam, D)[0]
+        opco.build_tensor(gs.Q[site - 1], bl, br, d)
+        out["cpu_oracle"] = {"D": D, "d": d, "seconds": time.perf_counter() - t0, "kind": "oracle"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +273,9 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="copy a buffer of this many MiB on the device before the steps (a plain copy kernel of "
                          "known size, to calibrate hardware byte counters)")
+    ap.add_argument("--central", action="store_true",
+                    help="instead of the step: the central tensor alone at D up to 4096 and d up to 10 on a "
+                         "144-mode state with five squeezed modes (the paper's benchmark shape)")
     ap.add_argument("--contractions", metavar="WORKLOAD", default=None,
                     help="instead of the step: compare bond contractions (truncation sweep and fidelity "
                          "transfer) in fp64 / fp32 / bf16x3 on a workload (e.g. c5)")
@@ -245,6 +292,9 @@ def main():
 
     if args.contractions:
         print(json.dumps(contractions(args.contractions)))
+        return
+    if args.central:
+        print(json.dumps(central_tensor()))
         return
     w = workloads.workload(args.workload)
     dev = torch.device("cuda:0")

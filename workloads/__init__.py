@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "haar_unitary", "beamsplitter_network", "symplectic_of_unitary",
     "gamma_of_circuit", "pair_matrix_of_circuit", "GaussianWorkload",
-    "workload", "serving_requests", "CONFIGS",
+    "workload", "serving_requests", "few_squeezed", "CONFIGS",
 ]
 
 
@@ -128,6 +128,19 @@ def workload(name: str, **override) -> GaussianWorkload:
 
 def custom(M: int, d: int, chi: int, r_range, circuit, seed: int, name="custom") -> GaussianWorkload:
     return _make(name, M, d, chi, tuple(r_range), circuit, seed)
+
+
+def few_squeezed(M: int = 144, n_sq: int = 5, r=(0.6, 1.0), seed: int = 6, d: int = 4,
+                 chi: int = 300) -> GaussianWorkload:
+    """A pure state shaped like the paper's central-tensor benchmark: n_sq
+    squeezed vacua among M modes (the rest vacuum) through a Haar-random
+    M x M interferometer, so that at most n_sq mode pairs are entangled
+    across any cut (an effective squeezed-mode number of n_sq)."""
+    rng = np.random.default_rng(seed)
+    rr = np.zeros(M)
+    rr[:n_sq] = rng.uniform(r[0], r[1], n_sq)
+    u = haar_unitary(M, rng)
+    return GaussianWorkload("few_squeezed", M, d, chi, rr, u)
 
 
 def serving_requests(n: int = 512, seed: int = 3, rate: float | None = None):
