@@ -213,7 +213,7 @@ def contractions(name):
     return out
 
 
-def central_tensor(dims=(300, 1000, 2000, 4096), cutoffs=(4, 6, 8, 10), oracle=True):
+def central_tensor(dims=(300, 1000, 2000, 4096, 10000), cutoffs=(4, 6, 8, 10), oracle=True):
     """The paper's own benchmark shape: the central tensor of a 144-mode pure
     state with five squeezed modes among vacua through a Haar interferometer,
     built alone (gbs_mps_build_site, FP64) at bond dimension D and cutoff d.
@@ -274,7 +274,7 @@ def main():
                     help="copy a buffer of this many MiB on the device before the steps (a plain copy kernel of "
                          "known size, to calibrate hardware byte counters)")
     ap.add_argument("--central", action="store_true",
-                    help="instead of the step: the central tensor alone at D up to 4096 and d up to 10 on a "
+                    help="instead of the step: the central tensor alone at D up to 10^4 and d up to 10 on a "
                          "144-mode state with five squeezed modes (the paper's benchmark shape)")
     ap.add_argument("--contractions", metavar="WORKLOAD", default=None,
                     help="instead of the step: compare bond contractions (truncation sweep and fidelity "

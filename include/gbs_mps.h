@@ -82,7 +82,7 @@ typedef struct {
  * Synchronises `stream` internally (buffer sizes depend on the spectra). */
 int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out);
 
-/* The tensor of one site alone, at bond dimension chi <= 4096: the shape of
+/* The tensor of one site alone, at bond dimension chi <= 16384: the shape of
  * the paper's own benchmark, a central tensor at large D (Sec. III.A).  Runs
  * the Gaussian SVD chain, the kept bases of cuts site-1 and site, and the
  * PCO build of that tensor (Eq. Am_definition, Sec. II.C.2), in FP64, with no
@@ -92,7 +92,10 @@ int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, voi
  * amplitude, sample and overlap calls on it fail with GBS_E_INVAL.
  *   gamma, M, opt, stream, out : as gbs_mps_build (opt->prec and
  *   opt->trunc_rel are not used; the chi * d limit of full builds does not
- *   apply, d <= 64);  site : 1..M (GBS_E_INVAL otherwise). */
+ *   apply, d <= 64; a kept state may occupy at most 12 distinct modes,
+ *   GBS_E_INVAL otherwise);  site : 1..M (GBS_E_INVAL otherwise).
+ * The tensor takes kept[site-1] * d * kept[site] * 16 bytes of device
+ * memory (16 GB at chi = 10^4, d = 10). */
 int gbs_mps_build_site(const double* gamma, int32_t M, const gbs_build_opts* opt, int32_t site, void* stream,
                        gbs_mps* out);
 

@@ -610,6 +610,11 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(dalloc(tmp, &ka.olist, (size_t)off_state * GBS_K_MAX));
   HIP_CHECK_RET(dalloc(tmp, &ka.chi_out, M + 1));
   ka.err = err;
+  if (kept_workspace_bytes(chi) > kKeptLdsMax) {
+    // large chi: the enumeration's heap and sort buffer go to global memory
+    ka.gws_stride = (long)kept_workspace_bytes(chi);
+    HIP_CHECK_RET(tmp.alloc((void**)&ka.gws, (size_t)(M + 1) * ka.gws_stride));
+  }
   h->occ = ka.occ;
   // vacuum cuts report one state
   {
@@ -909,7 +914,8 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   if (!gamma || !opt) return fail(GBS_E_INVAL, "NULL gamma or options");
   if (M < 1) return fail(GBS_E_INVAL, "M must be >= 1");
   if (opt->d < 1) return fail(GBS_E_INVAL, "d must be >= 1");
-  if (opt->chi < 1 || opt->chi > GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi must be in [1, 4096]");
+  if (opt->chi < 1 || opt->chi > (only_site ? GBS_CHI_MAX_SITE : GBS_CHI_MAX))
+    return fail(GBS_E_INVAL, only_site ? "chi must be in [1, 16384]" : "chi must be in [1, 4096]");
   if (!(opt->dstar > 1.0)) return fail(GBS_E_INVAL, "dstar must be > 1");
   if (opt->prec != GBS_FP64 && opt->prec != GBS_FP32 && opt->prec != GBS_BF16X3)
     return fail(GBS_E_INVAL, "unknown precision");

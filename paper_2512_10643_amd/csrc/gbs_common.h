@@ -5,6 +5,7 @@
 
 #define GBS_K_MAX 12          // max distinct occupied modes per kept state (2^k <= chi <= 4096)
 #define GBS_CHI_MAX 4096
+#define GBS_CHI_MAX_SITE 16384  // single-site builds (no truncation sweep)
 
 // Device-side error codes written into the handle's error word.
 enum {

@@ -21,6 +21,13 @@ struct KeptArgs {
   int4* olist;           // chi x GBS_K_MAX per cut: (mode, count, low index, 0)
   int* chi_out;          // kept count per cut
   int* err;
+  char* gws;             // NULL: heap and sort buffer in LDS; else cut m's at gws + m * gws_stride
+  long gws_stride;
 };
+
+// Bytes of the heap / sort workspace of one cut with `chi` states, and the
+// largest that the kernel keeps in LDS.
+size_t kept_workspace_bytes(int chi);
+constexpr size_t kKeptLdsMax = 144 * 1024;
 
 hipError_t launch_kept(hipStream_t st, const KeptArgs& a, int ncuts, int chi);

@@ -73,6 +73,9 @@ __global__ __launch_bounds__(256) void kept_kernel(KeptArgs a) {
   const int ne = cd.ne, chi = cd.chi;
   const int tid = threadIdx.x, nt = blockDim.x;
   extern __shared__ char smem[];
+  // heap and sort buffer: LDS, or this cut's slice of a global workspace
+  // when they do not fit (large chi)
+  char* wbase = a.gws ? a.gws + (long)m * a.gws_stride : smem;
   double* E = a.E + cd.off_state;
   int* parent = a.parent + cd.off_state;
   int* pmode = a.pmode + cd.off_state;
@@ -93,8 +96,8 @@ __global__ __launch_bounds__(256) void kept_kernel(KeptArgs a) {
     }
     return;
   }
-  // ---- best-first enumeration (thread 0); heap in LDS
-  HeapNode* heap = (HeapNode*)smem;
+  // ---- best-first enumeration (thread 0)
+  HeapNode* heap = (HeapNode*)wbase;
   if (tid == 0) {
     int hn = 0;
     E[0] = 0.0; parent[0] = -1; pmode[0] = -1; ntot[0] = 0;
@@ -139,10 +142,10 @@ __global__ __launch_bounds__(256) void kept_kernel(KeptArgs a) {
     if (k > GBS_K_MAX) gbs_set_error(a.err, GBS_DEVERR_KMAX);
   }
   __syncthreads();
-  // ---- sort (hash, index) pairs in LDS (bitonic, padded to a power of two)
+  // ---- sort (hash, index) pairs (bitonic, padded to a power of two)
   int np2 = 1;
   while (np2 < nk) np2 <<= 1;
-  unsigned long long* sh = (unsigned long long*)smem;
+  unsigned long long* sh = (unsigned long long*)wbase;
   int* si = (int*)(sh + np2);
   for (int i = tid; i < np2; i += nt) {
     sh[i] = i < nk ? H[i] : ~0ull;
@@ -204,13 +207,19 @@ __global__ __launch_bounds__(256) void kept_kernel(KeptArgs a) {
   }
 }
 
-hipError_t launch_kept(hipStream_t st, const KeptArgs& a, int ncuts, int chi) {
-  if (ncuts <= 0) return hipSuccess;
+size_t kept_workspace_bytes(int chi) {
   int np2 = 1;
   while (np2 < chi) np2 <<= 1;
-  size_t heap_bytes = (size_t)(2 * chi + 4) * sizeof(HeapNode);
-  size_t sort_bytes = (size_t)np2 * (sizeof(unsigned long long) + sizeof(int));
-  size_t lds = heap_bytes > sort_bytes ? heap_bytes : sort_bytes;
-  hipLaunchKernelGGL(kept_kernel, dim3(ncuts), dim3(256), lds, st, a);
+  const size_t heap_bytes = (size_t)(2 * chi + 4) * sizeof(HeapNode);
+  const size_t sort_bytes = (size_t)np2 * (sizeof(unsigned long long) + sizeof(int));
+  const size_t b = heap_bytes > sort_bytes ? heap_bytes : sort_bytes;
+  return (b + 255) / 256 * 256;
+}
+
+hipError_t launch_kept(hipStream_t st, const KeptArgs& a, int ncuts, int chi) {
+  if (ncuts <= 0) return hipSuccess;
+  const size_t ws = kept_workspace_bytes(chi);
+  if (a.gws ? (long)ws > a.gws_stride : ws > kKeptLdsMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kept_kernel, dim3(ncuts), dim3(256), a.gws ? 0 : ws, st, a);
   return hipGetLastError();
 }

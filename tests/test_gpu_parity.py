@@ -426,6 +426,31 @@ def test_single_site_large_d_elements_are_hafnians(torch_cuda):
     assert worst <= 1e-10
 
 
+def test_single_site_beyond_lds_heap(torch_cuda):
+    """D=10^4 (the paper's largest bond), where the kept-basis enumeration
+    keeps its heap and sort buffer in global memory: the kept bases of both
+    cuts equal the oracle's enumeration and the PCO gather produces every
+    element of even total photon number (five squeezed modes among 144)."""
+    _say("case: few-squeezed central tensor alone, site 72, D=10000, d=4")
+    from oracle import gaussian as og, kept as ok
+    from paper_2512_10643_amd import mps as gmps
+    w, m, D, d = W.few_squeezed(), 72, 10_000, 4
+    gs = og.gsvd(w.gamma)
+    bl, br = ok.kept_basis(gs.cuts[m - 2].Lam, D)[0], ok.kept_basis(gs.cuts[m - 1].Lam, D)[0]
+    g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
+    h = gmps.build_site(g, d, D, m)
+    inf = h.info()
+    _say(f"  kept {inf['bond'][m - 1]} x {d} x {inf['bond'][m]}; kept {inf['t_kept_ms']:.1f} ms, "
+         f"pco {inf['t_pco_ms']:.1f} ms, {inf['pco_updates']} elements")
+    assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
+    assert [tuple(r) for r in h.export(m, "basis")] == list(br)
+    par_l = np.array([sum(x) % 2 for x in bl])
+    par_r = np.array([sum(x) % 2 for x in br])
+    even = sum(int(np.sum((par_l[:, None] + p + par_r[None, :]) % 2 == 0)) for p in range(d))
+    assert inf["pco_updates"] == even - 1  # every even element but the vacuum one
+    h.free()
+
+
 # ---------------------------------------------------------- full size (C3)
 
 def _golden(name):
