@@ -57,7 +57,11 @@ typedef enum {
  * the PCO tensors for gbs_mps_export; GBS_DENSE_SAMPLER makes the FP32
  * sampler use whole bonds instead of photon-parity sectors (the sectors need
  * the parity structure a zero-mean state has, and are checked on the built
- * tensors; the dense layout is also taken when that check fails). */
+ * tensors; the dense layout is also taken when that check fails).
+ * eps_target > 0 picks the bond dimension per cut (Sec. II.C.2, D(eps)):
+ * each cut keeps the fewest lowest-energy states whose discarded weight
+ * eps_m = 1 - (1/Z) sum_kept exp(-E) is at most eps_target, and at most chi
+ * of them; the truncation sweep then acts on those bonds as usual. */
 #define GBS_KEEP_RAW 1u
 #define GBS_DENSE_SAMPLER 2u
 typedef struct {
@@ -67,6 +71,7 @@ typedef struct {
   int32_t prec;      /* gbs_precision */
   uint32_t flags;
   double trunc_rel;
+  double eps_target;  /* > 0: D(eps) per cut, see below; 0: chi states at every cut */
 } gbs_build_opts;
 
 /* Build the MPS of the pure state with covariance `gamma`.

@@ -610,6 +610,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(dalloc(tmp, &ka.olist, (size_t)off_state * GBS_K_MAX));
   HIP_CHECK_RET(dalloc(tmp, &ka.chi_out, M + 1));
   ka.err = err;
+  ka.eps_target = opt->eps_target;
   if (kept_workspace_bytes(chi) > kKeptLdsMax) {
     // large chi: the enumeration's heap and sort buffer go to global memory
     ka.gws_stride = (long)kept_workspace_bytes(chi);
@@ -917,6 +918,7 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   if (opt->chi < 1 || opt->chi > (only_site ? GBS_CHI_MAX_SITE : GBS_CHI_MAX))
     return fail(GBS_E_INVAL, only_site ? "chi must be in [1, 16384]" : "chi must be in [1, 4096]");
   if (!(opt->dstar > 1.0)) return fail(GBS_E_INVAL, "dstar must be > 1");
+  if (!(opt->eps_target >= 0.0 && opt->eps_target < 1.0)) return fail(GBS_E_INVAL, "eps_target must be in [0, 1)");
   if (opt->prec != GBS_FP64 && opt->prec != GBS_FP32 && opt->prec != GBS_BF16X3)
     return fail(GBS_E_INVAL, "unknown precision");
   if (only_site < 0 || only_site > M) return fail(GBS_E_INVAL, "site out of range");

@@ -23,6 +23,7 @@ struct KeptArgs {
   int* err;
   char* gws;             // NULL: heap and sort buffer in LDS; else cut m's at gws + m * gws_stride
   long gws_stride;
+  double eps_target;     // > 0: stop once the discarded weight is at most this (D(eps))
 };
 
 // Bytes of the heap / sort workspace of one cut with `chi` states, and the

@@ -104,10 +104,16 @@ __global__ __launch_bounds__(256) void kept_kernel(KeptArgs a) {
     // mode energies e_q = -2 log Lambda_q (Lambda descending => e ascending)
     HeapNode first = {-2.0 * log(lam[0]), 0, 0};
     heap_push(heap, hn, first, occ, ne);
+    // D(eps): the kept weight (1/Z) sum exp(-E), log Z = -sum_q log(1 - Lambda_q^2)
+    const double tgt = a.eps_target;
+    double logz = 0.0;
+    for (int q = 0; q < ne; ++q) logz -= log1p(-lam[q] * lam[q]);
+    double kw = exp(-logz);  // the vacuum state, E = 0
     int count = 1;
-    while (count < chi && hn > 0) {
+    while (count < chi && hn > 0 && !(tgt > 0.0 && 1.0 - kw <= tgt)) {
       HeapNode t = heap_pop(heap, hn, occ, ne);
       const int b = count++;
+      kw += exp(-t.E - logz);
       E[b] = t.E; parent[b] = t.parent; pmode[b] = t.q; ntot[b] = ntot[t.parent] + 1;
       // materialise the occupation row now (needed for later tie-breaks)
       for (int j = 0; j < ne; ++j) occ[(long)b * ne + j] = occ[(long)t.parent * ne + j];

@@ -351,6 +351,38 @@ def test_sample_timed_matches_sample(torch_cuda):
     h64.free()
 
 
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_bond_dimension_from_target_error(torch_cuda, eps):
+    """D(eps) per cut (eps_target): every cut keeps as many states as the
+    oracle's bond_dimension_for (capped at chi), its discarded weight is at
+    most eps where the cap is not reached, and the state stays within the
+    summed discarded weights of the fixed-chi build."""
+    _say(f"case: c2 fp64 build with eps_target={eps:g}, chi cap 64")
+    from oracle import gaussian as og, kept as ok
+    w = W.workload("c2")
+    gs = og.gsvd(w.gamma)
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64", eps_target=eps)
+    inf = h.info()
+    sizes = []
+    for m in range(1, w.M):
+        want = min(ok.bond_dimension_for(gs.cuts[m - 1].Lam, eps, d_max=4 * w.chi), w.chi)
+        got = len(h.export(m, "basis"))
+        sizes.append(got)
+        assert got == want, (m, got, want)
+        if got < w.chi:
+            assert inf["eps"][m] <= eps * (1 + 1e-9), (m, inf["eps"][m])
+    _say(f"  kept sizes per cut: min {min(sizes)}, max {max(sizes)}, mean {np.mean(sizes):.1f}")
+    # the cuts at the cap keep the same states as the fixed-chi build; the
+    # others discard at most eps each beyond it
+    href = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    f = h.fidelity(href)
+    budget = sum(inf["eps"][m] for m in range(1, w.M) if sizes[m - 1] < w.chi)
+    _say(f"  1 - F vs the chi=64 build = {1 - f:.3e} (eps summed over the cuts below the cap {budget:.3e})")
+    assert 1 - f <= 2 * budget + 1e-12
+    h.free()
+    href.free()
+
+
 # ------------------------------------------------- one site at large D (C3)
 
 def _oracle_site_inputs(w, m, chi):
