@@ -645,9 +645,10 @@ __global__ __launch_bounds__(256) void jacobi_herm_sort_kernel(const int* __rest
 // Blocked two-sided Jacobi for batches of Hermitian matrices (FP64).
 //
 // Indices are grouped in blocks of 16; a round pairs the blocks round robin
-// (as the scalar method pairs indices) and for every pair solves the 32 x 32
-// Hermitian subproblem on its rows and columns to full convergence (one wave
-// per subproblem, in LDS), giving a unitary V_P.  The round then applies
+// (as the scalar method pairs indices) and for every pair applies one cyclic
+// sweep of rotations to the 32 x 32 Hermitian subproblem on its rows and
+// columns (one workgroup per subproblem, in LDS), giving a unitary V_P; the
+// outer sweeps continue until no subproblem needs a rotation.  The round then applies
 // A <- V^H A V and W <- W V with V block diagonal over the pairs, as 32 x 32
 // tile products spread over many workgroups.  A sweep visits every block pair
 // once, so the matrix is read and written once per round instead of once per
@@ -902,7 +903,7 @@ hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* 
     if (e != hipSuccess) return e;
     for (int r = 0; r < npb - 1; ++r) {
       hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(512), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
-                         4, Vs, active, vid);
+                         1, Vs, active, vid);
       const int nch = (nmax + kBP - 1) / kBP;
       hipLaunchKernelGGL(bj_pass_kernel<true>, dim3(npairs, nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld, sA,
                          npb, r, Vs, vid, nch);
