@@ -248,7 +248,11 @@ typedef struct {
 /* Create a server on the current device.  slots in [1, 64]; budget_bytes:
  * device memory the admitted requests may hold together (a request larger
  * than the budget is rejected at submit with GBS_E_NOMEM); max_queue: queued
- * requests beyond which submit returns GBS_E_BUSY.  out: host. */
+ * requests beyond which submit returns GBS_E_BUSY.  out: host.  Each slot
+ * works on its own HIP stream; slots run concurrently on the device only up
+ * to the process's hardware queue count (the GPU_MAX_HW_QUEUES environment
+ * variable, read when HIP starts), so a process serving many slots should
+ * set it to at least the slot count. */
 int gbs_server_create(int32_t slots, int64_t budget_bytes, int32_t max_queue, gbs_server* out);
 /* Queue a request (host struct, copied).  *id (host) receives its id. */
 int gbs_server_submit(gbs_server s, const gbs_request* req, int64_t* id);
