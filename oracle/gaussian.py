@@ -172,7 +172,7 @@ def entropy(lam: np.ndarray) -> float:
     return float(np.sum(-np.log1p(-l2) - l2 / (1 - l2) * np.log(l2)))
 
 
-def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10) -> GSVDResult:
+def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10, first: int = 1, last: int | None = None) -> GSVDResult:
     """Iterative GSVD (Sec. II.B.2): first mode, bulk modes, last mode.
 
     At step m the residual state lives on (r_{m-1}, a_m, ..., a_N).  The left
@@ -181,13 +181,24 @@ def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10) -> GSVDResult:
     pair matrix Q_L restricted to (r_{m-1}, a_m, l_m); the next residual has
     the active b_L modes relabelled r_m.  The last site takes the pure
     residual's own pair matrix (U^dag)^-1 V^dag.
+
+    first > 1 starts the chain at cut `first` straight from Gamma: the modes
+    a_1..a_{first-1} play the part of r_{first-1}, uncompressed, so the L
+    block of that cut is Gamma's own block on a_1..a_first (the Gaussian SVD of
+    a bipartition needs only the covariance of the state, Sec. II.B, which is
+    what lets each tensor be built on its own, Sec. III.A).  Steps run for
+    m = first..last (last defaults to N); Q[0] is then the pair matrix of the
+    block (a_1..a_first, l_first) and Q[i] that of site first + i.
     """
     g = np.asarray(gamma, dtype=np.float64)
     N = g.shape[0] // 2
+    last = N if last is None else last
+    if not 1 <= first <= last <= N:
+        raise ValueError("need 1 <= first <= last <= N")
     res = g.copy()           # residual covariance on (r_prev, a_m..a_N), xxpp
-    n_prev = 0
+    n_prev = first - 1       # a_1..a_{first-1} stand in for r_{first-1}
     Qs, cuts, n_in, n_out = [], [], [], []
-    for m in range(1, N + 1):
+    for m in range(first, last + 1):
         n_tot = n_prev + (N - m + 1)
         n_l = n_prev + 1
         idx_l = np.r_[0:n_l, n_tot:n_tot + n_l]

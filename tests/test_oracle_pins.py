@@ -417,3 +417,85 @@ def test_fidelity_overlap_and_svd_truncation():
         mat = a.reshape(a.shape[0], -1)
         assert np.max(np.abs(mat @ mat.conj().T - np.eye(a.shape[0]))) < 1e-12
     assert tt[0].shape[2] <= w.d                       # edge rank cut to d
+
+
+def _symplectic_spectrum(g):
+    """Symplectic eigenvalues of a covariance (vacuum = I/2), descending, as
+    the moduli of the eigenvalues of 2 i Omega Gamma (each appears twice)."""
+    n = g.shape[0] // 2
+    ev = np.sort(np.abs(np.linalg.eigvals(2j * G.omega(n) @ g)))[::-1]
+    return ev[::2]
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_restarted_gsvd_spectra_match_reduced_states(name):
+    """P4c: the Gaussian SVD started at cut s-1 straight from Gamma (the
+    per-site build of Sec. III.A) gives, at cuts s-1 and s, the symplectic
+    spectra of the reduced states on a_1..a_{s-1} and a_1..a_s (the spectrum
+    of a cut is that of either side's reduced state, Sec. II.B)."""
+    w = W.workload(name)
+    g = w.gamma
+    for s in range(2, w.M + 1):
+        gs = G.gsvd(g, first=s - 1, last=s)
+        assert gs.n_in[0] == s - 2
+        for k, cut in zip((s - 1, s), gs.cuts):
+            idx = np.r_[0:k, w.M:w.M + k]
+            d = _symplectic_spectrum(g[np.ix_(idx, idx)])
+            ne = cut.n_e
+            assert np.allclose(cut.D[:ne], d[:ne], rtol=1e-9, atol=1e-9), (s, k)
+            assert np.all(d[ne:] < 1 + 1e-8), (s, k)
+        if s == w.M:
+            assert len(gs.cuts) == 1 and gs.n_out[-1] == 0
+
+
+@pytest.mark.parametrize("name,chi", [("c1", 16), ("c2", 24)])
+def test_restarted_site_tensor_equals_chain_tensor_up_to_mode_phases(name, chi):
+    """P4d: the tensor of site s from the restarted Gaussian SVD equals the
+    sequential chain's tensor up to a phase per virtual mode: the two bond
+    bases of a cut are the same Bogoliubov modes (non-degenerate spectra)
+    with their own phases, and a phase e^{i theta} on a mode multiplies an
+    element by e^{i theta n} for its occupation n.  So |A| agrees element by
+    element and the phase ratio is linear in the bond occupations."""
+    w = W.workload(name)
+    d = w.d
+    ch = G.gsvd(w.gamma)
+    for s in range(2, w.M + 1):
+        rs = G.gsvd(w.gamma, first=s - 1, last=s)
+        bl = K.kept_basis(ch.cuts[s - 2].Lam, chi)[0]
+        br = K.kept_basis(ch.cuts[s - 1].Lam, chi)[0] if s < w.M else [()]
+        assert K.kept_basis(rs.cuts[0].Lam, chi)[0] == bl
+        a_ch = pco.build_tensor(ch.Q[s - 1], bl, br, d)
+        a_rs = pco.build_tensor(rs.Q[1], bl, br, d)
+        scale = np.max(np.abs(a_ch))
+        # the chain projects modes with 1 < D_q < D* onto vacuum at every
+        # earlier cut and the restart does not: elements differ by the order
+        # of the weight projected away (each such mode has Lambda^2 < 5e-11)
+        dropped = sum(c.frozen_weight for c in ch.cuts[:s - 1])
+        assert np.max(np.abs(np.abs(a_rs) - np.abs(a_ch))) < (1e-12 + 5 * dropped) * scale, s
+        # phases: fit one per left and right mode from single occupations
+        nl, nr = len(bl[0]), len(br[0])
+        theta, phi = {}, {}
+        big = np.abs(a_ch) > 1e-6 * scale
+        ratio = np.where(big, a_rs / np.where(big, a_ch, 1), 0)
+        for i, sa in enumerate(bl):
+            for j, sb in enumerate(br):
+                for p in range(d):
+                    if not big[i, p, j]:
+                        continue
+                    if sum(sa) == 1 and sum(sb) == 0 and sa.index(1) not in theta:
+                        theta[sa.index(1)] = np.angle(ratio[i, p, j])
+                    if sum(sb) == 1 and sum(sa) == 0 and sb.index(1) not in phi:
+                        phi[sb.index(1)] = np.angle(ratio[i, p, j])
+        checked = 0
+        for i, sa in enumerate(bl):
+            for j, sb in enumerate(br):
+                occ_l = [q for q in range(nl) if sa[q]]
+                occ_r = [q for q in range(nr) if sb[q]]
+                if any(q not in theta for q in occ_l) or any(q not in phi for q in occ_r):
+                    continue
+                ang = sum(sa[q] * theta[q] for q in occ_l) + sum(sb[q] * phi[q] for q in occ_r)
+                for p in range(d):
+                    if big[i, p, j]:
+                        assert abs(ratio[i, p, j] - np.exp(1j * ang)) < 1e-7, (s, sa, p, sb)
+                        checked += 1
+        assert checked > 0
