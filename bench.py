@@ -258,10 +258,10 @@ def central_tensor(dims=(300, 1000, 2000, 4096, 10000), cutoffs=(4, 6, 8, 10), o
         from oracle import gaussian as og, kept as ok, pco as opco
         D, d = 1000, 10  # about 15 s of CPU work
         t0 = time.perf_counter()
-        gs = og.gsvd(w.gamma)
-        bl = ok.kept_basis(gs.cuts[site - 2].Lam, D)[0]
-        br = ok.kept_basis(gs.cuts[site - 1].Lam, D)[0]
-        opco.build_tensor(gs.Q[site - 1], bl, br, d)
+        gs = og.gsvd(w.gamma, first=site - 1, last=site)   # the same two cuts as the device build
+        bl = ok.kept_basis(gs.cuts[0].Lam, D)[0]
+        br = ok.kept_basis(gs.cuts[1].Lam, D)[0]
+        opco.build_tensor(gs.Q[1], bl, br, d)
         out["cpu_oracle"] = {"D": D, "d": d, "seconds": time.perf_counter() - t0, "kind": "oracle"}
     return out
 

@@ -504,7 +504,12 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   }
   // ---- Gaussian SVD chain
   double t0 = now_ms();
-  const int n2max = std::min(GBS_GSVD_N2_MAX, M + 2);
+  // A single-site build starts the chain at cut k = s - 1 straight from Gamma
+  // (a_1..a_{k-1} stand in for r_{k-1}, Sec. III.A): two steps instead of
+  // s.  Its first L block is 2 k wide, so k is capped at what one workgroup
+  // takes; beyond that the chain runs from the cap to s.
+  const int restart = only_site >= 3 ? std::min(only_site - 1, GBS_GSVD_N2_MAX / 2) : 0;
+  const int n2max = std::min(GBS_GSVD_N2_MAX, std::max(M + 2, 2 * restart));
   GsvdArgs ga{};
   ga.M = M;
   ga.dstar = opt->dstar;
@@ -549,14 +554,24 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_U, (size_t)ga.ld_u * ga.ld_u));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_V, (size_t)ga.ld_u * ga.ld_u));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_aug, (size_t)ga.ld_u * 2 * ga.ld_u));
-  for (int m = 1; m <= M; ++m) {
+  ga.q_first = only_site;  // a single-site build forms Q^s alone
+  if (restart) {
+    ga.drr_in = drr[(restart + 1) & 1];
+    ga.cr_in = cr[(restart + 1) & 1];
+    HIP_CHECK_RET(launch_gsvd_restart(st, ga, restart));
+  }
+  const int m_first = restart ? restart : 1, m_last = only_site ? only_site : M;
+  for (int m = m_first; m <= m_last; ++m) {
     ga.drr_in = drr[(m + 1) & 1];
     ga.drr_out = drr[m & 1];
     ga.cr_in = cr[(m + 1) & 1];
     ga.cr_out = cr[m & 1];
     HIP_CHECK_RET(launch_gsvd_cut(st, ga, m, n2max));
   }
-  HIP_CHECK_RET(launch_gsvd_last_q(st, ga));
+  if (only_site && only_site < M)
+    HIP_CHECK_RET(launch_gsvd_q(st, ga, only_site));
+  else
+    HIP_CHECK_RET(launch_gsvd_last_q(st, ga));
   std::vector<int> ne(M + 1);
   std::vector<double> lamh((size_t)(M + 1) * ga.ld_dsym);
   int herr = 0;
@@ -565,6 +580,9 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK_RET(hipStreamSynchronize(st));
   if (herr) return fail(herr == GBS_DEVERR_NOT_PD ? GBS_E_NOT_PD : GBS_E_INTERNAL, deverr_msg(herr));
+  if (only_site)  // only the two cuts of the site were formed
+    for (int m = 0; m <= M; ++m)
+      if (m != only_site - 1 && m != only_site) ne[m] = 0;
   h->ne = ne;
   h->lam.assign(M + 1, {});
   h->entropy.assign(M + 1, 0.0);

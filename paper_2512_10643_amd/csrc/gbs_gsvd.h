@@ -29,6 +29,7 @@ struct GsvdArgs {
   long ld_ws, ld_glr;
   cplx64 *ws_U, *ws_V, *ws_aug;
   long ld_u;
+  int q_first;           // Q^j is formed beside cut j + 1 only for j >= q_first
 };
 
 hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* scal, double* wsM, int* err);
@@ -37,3 +38,10 @@ hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* s
 hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max);
 // Q^M of the last site, after the last cut.
 hipError_t launch_gsvd_last_q(hipStream_t st, const GsvdArgs& a);
+// Q^m of site m alone, after cut m (its S is the last one formed).
+hipError_t launch_gsvd_q(hipStream_t st, const GsvdArgs& a, int m);
+// Start the chain at cut k straight from Gamma: the modes a_1..a_{k-1} stand
+// in for r_{k-1}, so drr_in and cr_in receive Gamma's rows of their
+// quadratures and ne[k-1] = k - 1.  Needs 2 k <= n2max (the leading dimension
+// and row count of drr_in, the row count of cr_in).
+hipError_t launch_gsvd_restart(hipStream_t st, const GsvdArgs& a, int k);

@@ -12,6 +12,8 @@
 // b-mode quadrature map T = -S^T Omega restricted to the active modes.
 #include "gbs_gsvd.h"
 
+#include <algorithm>
+
 namespace {
 
 __device__ inline void wg_sync() { __syncthreads(); }
@@ -367,7 +369,7 @@ __device__ void q_from_s(const GsvdArgs& a, int m) {
 // Stage 1.
 __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   if (blockIdx.x == 1) {  // Q^{m-1} beside the Williamson step of cut m
-    q_from_s(a, m - 1);
+    if (m - 1 >= a.q_first) q_from_s(a, m - 1);
     return;
   }
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -607,7 +609,47 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   const int n = nL;
   double* t2L = pL;  // squared off-diagonal for the Sturm counts (pL is free now)
   for (int i = tid; i < N2 - 1; i += nt) t2L[i] = tL[i] * tL[i];
+  // Unreduced blocks of the split G.  Each even block of G (zero diagonal)
+  // holds half of its eigenvalues above zero; eigenvalue q of the whole is
+  // taken as eigenvalue k of its own block, and its vector is solved on that
+  // block alone.  Equal eigenvalues of different blocks (modes in vacuum,
+  // D = 1) then get vectors of disjoint support, which no solve over the
+  // whole matrix can separate.  If a block is odd (a zero eigenvalue, which
+  // a definite Gamma excludes) the whole matrix is taken as one block.
+  int* bst = reinterpret_cast<int*>(part);  // block starts (part is free until the checks below)
+  int* bpre = bst + 1024;                   // eigenvalues above zero before each block
+  __shared__ int nblk;
+  if (tid == 0) {
+    int nb = 0, cnt = 0;
+    bool even = true;
+    bst[0] = 0;
+    for (int i = 0; i < N2 - 1; ++i)
+      if (tL[i] == 0.0) bst[++nb] = i + 1;
+    bst[++nb] = N2;
+    for (int b = 0; b < nb; ++b) {
+      const int sz = bst[b + 1] - bst[b];
+      bpre[b] = cnt;
+      even = even && !(sz & 1);
+      cnt += sz / 2;
+    }
+    bpre[nb] = cnt;
+    if (!even || cnt != n) {
+      nb = 1;
+      bst[1] = N2;
+      bpre[0] = 0;
+      bpre[1] = n;
+    }
+    nblk = nb;
+  }
   wg_sync();
+  auto block_of = [&](int q) {  // the block holding eigenvalue q (bpre[b] <= q < bpre[b + 1])
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (bpre[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
   // 8-section: the 8 lanes of a group test 8 interior points of the interval
   // at once (the Sturm count is monotone in x), so each round shrinks it 9x
   {
@@ -616,10 +658,12 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     for (int q0 = 0; q0 < n; q0 += ngrp) {
       const int q = q0 + grpi;
       const bool live = q < n;
+      const int b = live ? block_of(q) : 0;
+      const int b0 = bst[b], nbk = bst[b + 1] - b0, k = live ? q - bpre[b] : 0;
       double lo = 0.0, hi = bound;
       for (int it = 0; it < 17; ++it) {
         const double x = lo + (hi - lo) * (double)(gl + 1) / 9.0;
-        const bool below = live && sturm_below(t2L, N2, x) <= N2 - 1 - q;
+        const bool below = live && sturm_below(t2L + b0, nbk, x) <= nbk - 1 - k;
         const unsigned long long bal = __ballot(below);
         const int j = __popcll((bal >> sh) & 0xFFull);   // points at or below the target
         const double xl = __shfl(x, sh + (j > 0 ? j - 1 : 0), 64);
@@ -632,32 +676,54 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
     }
   }
   wg_sync();
+  // z_q as column q of Z (entry i at Z[i n + q]) and per-thread scratch with
+  // the same interleaving, so a wave's threads touch consecutive addresses.
+  // Two inverse-iteration solves per vector on its own block, all vectors at
+  // once (one thread each); rows outside the block are zero.
+  double* Z = a.ws_O;
+  double* scr = a.ws_tri;
+  for (int u = tid; u < n; u += nt) {
+    const int b = block_of(u), b0 = bst[b], nbk = bst[b + 1] - b0;
+    for (int i = 0; i < N2; ++i) Z[(long)i * n + u] = (i >= b0 && i < b0 + nbk) ? cos(0.7 * (u + 1) * i + 0.3) : 0.0;
+    for (int it = 0; it < 2; ++it) {
+      tri_shift_solve_il(tL + b0, nbk, sig0[u], Z + (long)b0 * n + u, n, scr + u, n, tiny);
+      double nn = 0.0;
+      for (int i = b0; i < b0 + nbk; ++i) nn += Z[(long)i * n + u] * Z[(long)i * n + u];
+      const double inv = 1.0 / sqrt(nn);
+      for (int i = b0; i < b0 + nbk; ++i) Z[(long)i * n + u] *= inv;
+    }
+  }
+  wg_sync();
+  // all eigenvalues in descending order (stable), vectors with them
+  {
+    double* Zs = a.ws_W;  // free here
+    for (int u = tid; u < n; u += nt) {
+      int r = 0;
+      for (int v = 0; v < n; ++v) r += (sig0[v] > sig0[u]) || (sig0[v] == sig0[u] && v < u);
+      first[u] = r;
+    }
+    wg_sync();
+    for (long e = tid; e < (long)N2 * n; e += nt) {
+      const int i = (int)(e / n), u = (int)(e % n);
+      Zs[(long)i * n + first[u]] = Z[e];
+    }
+    for (int u = tid; u < n; u += nt) sigR[first[u]] = sig0[u];
+    wg_sync();
+    for (long e = tid; e < (long)N2 * n; e += nt) Z[e] = Zs[e];
+    for (int u = tid; u < n; u += nt) sig0[u] = sigR[u];
+    wg_sync();
+  }
   // clusters of shifts closer than 1e-5 bound
   if (tid == 0) {
     first[0] = 0;
     for (int q = 1; q < n; ++q) first[q] = (sig0[q - 1] - sig0[q] < 1e-5 * bound) ? first[q - 1] : q;
   }
   wg_sync();
-  // z_q as column q of Z (entry i at Z[i n + q]) and per-thread scratch with
-  // the same interleaving, so a wave's threads touch consecutive addresses.
-  // Two inverse-iteration solves per vector, all vectors at once (one thread
-  // each); the members of a cluster are then orthonormalised in order by one
-  // wave (modified Gram-Schmidt): their solves resolve directions whose
+  // The members of a cluster are orthonormalised in order by one wave
+  // (modified Gram-Schmidt): their solves resolve directions whose
   // eigenvalues are further apart than the shifts' error, and within a
-  // degenerate set any orthonormal basis is an eigenbasis.
-  double* Z = a.ws_O;
-  double* scr = a.ws_tri;
-  for (int u = tid; u < n; u += nt) {
-    for (int i = 0; i < N2; ++i) Z[(long)i * n + u] = cos(0.7 * (u + 1) * i + 0.3);
-    for (int it = 0; it < 2; ++it) {
-      tri_shift_solve_il(tL, N2, sig0[u], Z + u, n, scr + u, n, tiny);
-      double nn = 0.0;
-      for (int i = 0; i < N2; ++i) nn += Z[(long)i * n + u] * Z[(long)i * n + u];
-      const double inv = 1.0 / sqrt(nn);
-      for (int i = 0; i < N2; ++i) Z[(long)i * n + u] *= inv;
-    }
-  }
-  wg_sync();
+  // degenerate set any orthonormal basis is an eigenbasis (members from
+  // different blocks are orthogonal already).
   {
     const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
     auto wave_sum = [&](double x) {
@@ -911,10 +977,25 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   double* e_v = a.ws_vec;
   double* au = a.ws_vec + ld;
   double* dots = lds + 2 * TILE * (TILE + 1);  // up to N2 dot products
+  // A cut whose pair matrix is not formed (the first cut of a single-site
+  // build) needs only its active pairs: the next residual takes the active
+  // columns of S alone, so a cluster of vacuum modes (D below D*) keeps zero
+  // columns there instead of a Gram-Schmidt pairing of the whole cluster.
+  const bool pair_vacuum = m >= a.q_first;
   for (int c = 0; c < ncl; ++c) {
     const int j0 = cl_start[c], sz = cl_start[c + 1] - j0;
     if (sz == 2) continue;
     const int slot0 = pair_src[c], want = sz / 2;
+    if (!pair_vacuum && w[ord[j0]] < a.dstar * a.dstar) {
+      for (long e = tid; e < (long)N2 * want; e += nt) {
+        const int k = (int)(e / want), q = (int)(e % want);
+        Om[(long)k * ld + slot0 + q] = 0.0;
+        Om[(long)k * ld + nL + slot0 + q] = 0.0;
+      }
+      for (int q = tid; q < want; q += nt) dsel[slot0 + q] = 1.0;
+      wg_sync();
+      continue;
+    }
     int found = 0;
     for (int jj = 0; jj < sz && found < want; ++jj) {
       const int col = ord[j0 + jj];
@@ -1000,7 +1081,6 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   wg_sync();
   const int ne = flag;
   if (m == M) return;  // the last site's Q^M is computed from S by q_from_s
-  if (m == M) return;
   wg_sync();
   // Next residual.  T = -S^T Omega; T_act rows: x_b,q -> q, p_b,q -> nL + q.
   double* Ta = a.ws_A;   // reuse: T_act (2ne x N2)
@@ -1051,5 +1131,42 @@ hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* s
 
 hipError_t launch_gsvd_last_q(hipStream_t st, const GsvdArgs& a) {
   hipLaunchKernelGGL(gsvd_q_kernel, dim3(1), dim3(1024), 0, st, a, a.M);
+  return hipGetLastError();
+}
+
+hipError_t launch_gsvd_q(hipStream_t st, const GsvdArgs& a, int m) {
+  hipLaunchKernelGGL(gsvd_q_kernel, dim3(1), dim3(1024), 0, st, a, m);
+  return hipGetLastError();
+}
+
+// Rows of Gamma for the quadratures (x_1..x_{k-1}, p_1..p_{k-1}): the r-r
+// block (columns in the same order) into drr_in and whole rows into cr_in.
+__global__ void gsvd_restart_kernel(const double* g, int M, int k, double* drr, long ldd, double* cr, long ldc,
+                                    int* ne) {
+  const int nr = k - 1, n2r = 2 * nr, n2g = 2 * M;
+  const long tot_c = (long)n2r * n2g, tot = tot_c + (long)n2r * n2r;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    if (e < tot_c) {
+      const int i = (int)(e / n2g), c = (int)(e % n2g);
+      const int gi = i < nr ? i : M + (i - nr);
+      cr[(long)i * ldc + c] = g[(long)gi * n2g + c];
+    } else {
+      const long f = e - tot_c;
+      const int i = (int)(f / n2r), j = (int)(f % n2r);
+      const int gi = i < nr ? i : M + (i - nr), gj = j < nr ? j : M + (j - nr);
+      drr[(long)i * ldd + j] = g[(long)gi * n2g + gj];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ne[k - 1] = nr;
+}
+
+hipError_t launch_gsvd_restart(hipStream_t st, const GsvdArgs& a, int k) {
+  if (k < 1 || k > a.M || 2L * k > a.ld_drr) return hipErrorInvalidValue;
+  const long tot = (long)(2 * (k - 1)) * (2 * a.M + 2 * (k - 1));
+  const int blocks = (int)std::max<long>(1, std::min<long>(1024, (tot + 255) / 256));
+  // drr_in / cr_in are read-only inputs of the cut kernels; the restart
+  // writes the buffers that the next cut will read through them
+  hipLaunchKernelGGL(gsvd_restart_kernel, dim3(blocks), dim3(256), 0, st, a.gamma, a.M, k,
+                     const_cast<double*>(a.drr_in), a.ld_drr, const_cast<double*>(a.cr_in), a.ld_cr, a.ne);
   return hipGetLastError();
 }

@@ -387,40 +387,73 @@ def test_bond_dimension_from_target_error(torch_cuda, eps):
 
 def _oracle_site_inputs(w, m, chi):
     """The oracle's own Q^m and kept bases of cuts m-1 and m (Gaussian SVD
-    chain and best-first enumeration, no GPU data)."""
+    started at cut m-1 straight from Gamma, as a single-site build does, and
+    best-first enumeration; no GPU data)."""
     from oracle import gaussian as og, kept as ok
-    gs = og.gsvd(w.gamma)
-    bl = ok.kept_basis(gs.cuts[m - 2].Lam, chi)[0] if m >= 2 else [()]
-    br = ok.kept_basis(gs.cuts[m - 1].Lam, chi)[0] if m <= w.M - 1 else [()]
-    return gs.Q[m - 1], bl, br
+    first = max(1, m - 1)
+    gs = og.gsvd(w.gamma, first=first, last=m)
+    bl = ok.kept_basis(gs.cuts[m - 1 - first].Lam, chi)[0] if m >= 2 else [()]
+    br = ok.kept_basis(gs.cuts[m - first].Lam, chi)[0] if m <= w.M - 1 else [()]
+    return gs.Q[m - first], bl, br
+
+
+def _check_single_site(torch_cuda, w, m, D, d):
+    from oracle import pco as opco
+    from paper_2512_10643_amd import mps as gmps
+    q, bl, br = _oracle_site_inputs(w, m, D)
+    ref = opco.build_tensor(q, bl, br, d)
+    g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
+    h = gmps.build_site(g, d, D, m)
+    try:
+        assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
+        assert [tuple(r) for r in h.export(m, "basis")] == list(br)
+        raw = h.export(m, "raw")
+        t = h.info()["t_gsvd_ms"]
+    finally:
+        h.free()
+    assert raw.shape == ref.shape
+    return np.max(np.abs(np.abs(raw) - np.abs(ref))), np.max(np.abs(ref)), t
 
 
 def test_single_site_tensor_matches_oracle(torch_cuda):
     """The central tensor of C3 alone (site 72, D=300, d=8): kept bases equal
     the oracle's and every element of the raw PCO tensor matches the oracle's
-    sequential PCO build (up to a phase per virtual mode: magnitudes), to the
-    FP64 amplitude bar of 1e-10."""
+    PCO build (up to a phase per virtual mode: magnitudes), to the FP64
+    amplitude bar of 1e-10."""
     _say("case: c3 central tensor alone, site 72, D=300, d=8")
-    from oracle import pco as opco
-    from paper_2512_10643_amd import mps as gmps
+    from paper_2512_10643_amd import mps as gmps, GbsError
     w, m, D, d = W.workload("c3"), 72, 300, 8
-    q, bl, br = _oracle_site_inputs(w, m, D)
-    ref = opco.build_tensor(q, bl, br, d)
+    err, amax, t = _check_single_site(torch_cuda, w, m, D, d)
+    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
+    assert err <= 1e-10 * max(1.0, amax)
     g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
     h = gmps.build_site(g, d, D, m)
-    assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
-    assert [tuple(r) for r in h.export(m, "basis")] == list(br)
-    raw = h.export(m, "raw")
-    assert raw.shape == ref.shape
-    err = np.max(np.abs(np.abs(raw) - np.abs(ref)))
-    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {np.max(np.abs(ref)):.3e})")
-    # the FP64 amplitude bar: both sides' Q^m come from 71 cuts of their own
-    # Gaussian SVD chains, which agree to ~1e-11 at the central cut
-    assert err <= 1e-10 * max(1.0, np.max(np.abs(ref)))
-    from paper_2512_10643_amd import GbsError
     with pytest.raises(GbsError):
         h.sample(10, seed=1)
     h.free()
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 9, 16, 24, 31, 32])
+def test_single_site_every_position_c2(torch_cuda, m):
+    """Single-site builds of C2 (brick-wall, M=32) at the ends and inside:
+    the Gaussian SVD starts at cut m-1 from Gamma, whose left block then holds
+    many modes in vacuum (one large cluster of equal symplectic eigenvalues)."""
+    _say(f"case: c2 single site {m}, D=24, d=6")
+    w = W.workload("c2")
+    err, amax, t = _check_single_site(torch_cuda, w, m, 24, 6)
+    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
+    assert err <= 1e-10 * max(1.0, amax)
+
+
+@pytest.mark.parametrize("m", [120, 144])
+def test_single_site_wide_first_block(torch_cuda, m):
+    """C3 sites past the middle: the first Gaussian SVD block is 2(m-1) wide
+    (238 and 286), past the size whose working matrix stays in LDS."""
+    _say(f"case: c3 single site {m}, D=64, d=4")
+    w = W.workload("c3")
+    err, amax, t = _check_single_site(torch_cuda, w, m, 64, 4)
+    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
+    assert err <= 1e-10 * max(1.0, amax)
 
 
 def test_single_site_large_d_elements_are_hafnians(torch_cuda):
@@ -467,8 +500,8 @@ def test_single_site_beyond_lds_heap(torch_cuda):
     from oracle import gaussian as og, kept as ok
     from paper_2512_10643_amd import mps as gmps
     w, m, D, d = W.few_squeezed(), 72, 10_000, 4
-    gs = og.gsvd(w.gamma)
-    bl, br = ok.kept_basis(gs.cuts[m - 2].Lam, D)[0], ok.kept_basis(gs.cuts[m - 1].Lam, D)[0]
+    gs = og.gsvd(w.gamma, first=m - 1, last=m)
+    bl, br = ok.kept_basis(gs.cuts[0].Lam, D)[0], ok.kept_basis(gs.cuts[1].Lam, D)[0]
     g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
     h = gmps.build_site(g, d, D, m)
     inf = h.info()
