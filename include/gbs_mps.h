@@ -89,11 +89,16 @@ int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, voi
 
 /* The tensor of one site alone, at bond dimension chi <= 16384: the shape of
  * the paper's own benchmark, a central tensor at large D (Sec. III.A).  Runs
- * the Gaussian SVD chain, the kept bases of cuts site-1 and site, and the
- * PCO build of that tensor (Eq. Am_definition, Sec. II.C.2), in FP64, with no
- * truncation sweep or normalisation.  The handle holds the raw tensor
- * (gbs_mps_export GBS_EXPORT_RAW at `site`, kept[site-1] x d x kept[site]),
- * the Gaussian data of every cut and the kept bases of the two cuts;
+ * the Gaussian SVD of cuts site-1 and site alone: the chain starts at cut
+ * site-1 straight from Gamma's block on modes 1..site-1, which stand in for
+ * the bond modes of the cut before (from cut 300 when site > 301, the
+ * widest block one workgroup takes), so each tensor is built on its own.
+ * Then the kept bases of the two cuts and the PCO build of that tensor (Eq.
+ * Am_definition, Sec. II.C.2), in FP64, with no truncation sweep or
+ * normalisation.  The tensor's bond bases are those of this build: they
+ * equal a full build's up to a phase per bond mode.  The handle holds the
+ * raw tensor (gbs_mps_export GBS_EXPORT_RAW at `site`, kept[site-1] x d x
+ * kept[site]), the Gaussian data and kept bases of the two cuts;
  * amplitude, sample and overlap calls on it fail with GBS_E_INVAL.
  *   gamma, M, opt, stream, out : as gbs_mps_build (opt->prec and
  *   opt->trunc_rel are not used; the chi * d limit of full builds does not
