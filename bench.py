@@ -254,6 +254,26 @@ def central_tensor(dims=(300, 1000, 2000, 4096, 10000), cutoffs=(4, 6, 8, 10), o
                                 "elements": inf["pco_updates"],
                                 "elements_per_s": inf["pco_updates"] / max(inf["t_pco_ms"], 1e-9) * 1e3})
             print(f"central tensor D={D} d={d}: {1000 * dt:.1f} ms", file=sys.stderr, flush=True)
+    # every tensor on its own: single-site builds along the chain, on this
+    # state and on C3's (144 squeezed modes through a Haar interferometer)
+    c3 = workloads.workload("c3")
+    g3 = torch.tensor(c3.gamma, dtype=torch.float64, device="cuda")
+    out["sites"] = []
+    for name, gg, D, d in (("few squeezed", g, 1000, 4), ("c3", g3, 256, 8)):
+        for s in (1, 2, 36, 72, 108, 143, 144):
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = gmps.build_site(gg, d, D, s)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                inf = h.info()
+                h.free()
+            out["sites"].append({"state": name, "site": s, "D": D, "d": d, "total_ms": 1000 * dt,
+                                 "gsvd_ms": inf["t_gsvd_ms"], "kept_ms": inf["t_kept_ms"], "pco_ms": inf["t_pco_ms"],
+                                 "kept": [inf["bond"][s - 1], inf["bond"][s]]})
+            print(f"{name} site {s} D={D} d={d}: {1000 * dt:.1f} ms (gsvd {inf['t_gsvd_ms']:.1f} ms)",
+                  file=sys.stderr, flush=True)
     if oracle:
         from oracle import gaussian as og, kept as ok, pco as opco
         D, d = 1000, 10  # about 15 s of CPU work
