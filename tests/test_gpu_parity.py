@@ -390,11 +390,20 @@ def _oracle_site_inputs(w, m, chi):
     started at cut m-1 straight from Gamma, as a single-site build does, and
     best-first enumeration; no GPU data)."""
     from oracle import gaussian as og, kept as ok
-    first = max(1, m - 1)
+    first = max(1, min(m - 1, 300))  # the widest first block the library takes is 600 (cut 300)
     gs = og.gsvd(w.gamma, first=first, last=m)
     bl = ok.kept_basis(gs.cuts[m - 1 - first].Lam, chi)[0] if m >= 2 else [()]
     br = ok.kept_basis(gs.cuts[m - first].Lam, chi)[0] if m <= w.M - 1 else [()]
     return gs.Q[m - first], bl, br
+
+
+def _min_lambda(w, m):
+    """Smallest Lambda_q of the two cuts of site m, by the oracle."""
+    from oracle import gaussian as og
+    first = max(1, min(m - 1, 300))
+    gs = og.gsvd(w.gamma, first=first, last=m)
+    lams = [c.Lam for c in gs.cuts[max(0, m - 1 - first):] if c.n_e]
+    return min(float(np.min(x)) for x in lams) if lams else 1.0
 
 
 def _check_single_site(torch_cuda, w, m, D, d):
@@ -443,6 +452,22 @@ def test_single_site_every_position_c2(torch_cuda, m):
     err, amax, t = _check_single_site(torch_cuda, w, m, 24, 6)
     _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
     assert err <= 1e-10 * max(1.0, amax)
+
+
+def test_single_site_past_the_widest_first_block(torch_cuda):
+    """C5 (M=1024, brick-wall) site 400: the first block is capped at cut 300
+    (600 wide, the most one workgroup takes) and the chain runs from there."""
+    _say("case: c5 single site 400, D=64, d=4")
+    w = W.workload("c5")
+    err, amax, t = _check_single_site(torch_cuda, w, 400, 64, 4)
+    # Both cuts hold modes just above the frozen threshold (D - 1 ~ 1e-9,
+    # Lambda ~ 2e-5).  D carries ~1e-12 of absolute FP64 precision after a
+    # 600-wide Williamson step and 100 chain steps, so such a Lambda is known
+    # to ~1e-12 / (4 Lambda) (from Lambda^2 = (D - 1) / (D + 1)), and elements
+    # linear in it carry that error.
+    tol = 1e-10 + 1e-12 / (4.0 * _min_lambda(w, 400))
+    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}, bound {tol:.2e}); gsvd {t:.2f} ms")
+    assert err <= tol * max(1.0, amax)
 
 
 @pytest.mark.parametrize("m", [120, 144])
