@@ -233,6 +233,15 @@ def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10, first: int = 1, last: in
     return GSVDResult(Q=Qs, cuts=cuts, n_in=n_in, n_out=n_out)
 
 
+def reverse_modes(gamma: np.ndarray) -> np.ndarray:
+    """Covariance of the same state with the modes numbered M..1 (xxpp kept):
+    cut m of the reversed state is cut M - m of the original."""
+    g = np.asarray(gamma, dtype=np.float64)
+    n = g.shape[0] // 2
+    idx = np.r_[n - 1:-1:-1, 2 * n - 1:n - 1:-1]
+    return g[np.ix_(idx, idx)]
+
+
 def mean_photons(gamma: np.ndarray) -> np.ndarray:
     """<n_j> = (Gamma_xjxj + Gamma_pjpj - 1)/2 for vacuum = I/2."""
     g = np.asarray(gamma)

@@ -499,3 +499,70 @@ def test_restarted_site_tensor_equals_chain_tensor_up_to_mode_phases(name, chi):
                         assert abs(ratio[i, p, j] - np.exp(1j * ang)) < 1e-7, (s, sa, p, sb)
                         checked += 1
         assert checked > 0
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_reversed_modes_mirror_the_cuts(name):
+    """P4e: numbering the modes backwards is an involution, and cut m of the
+    reversed state has the spectrum of cut M - m (the Schmidt spectrum of a
+    bipartition does not depend on the order of the modes, Sec. II.B)."""
+    w = W.workload(name)
+    gr = G.reverse_modes(w.gamma)
+    assert np.array_equal(G.reverse_modes(gr), w.gamma)
+    a, b = G.gsvd(w.gamma), G.gsvd(gr)
+    for m in range(1, w.M):
+        x, y = a.cuts[m - 1], b.cuts[w.M - m - 1]
+        assert x.n_e == y.n_e, m
+        # Schmidt weights Lambda^2 to 1e-10: the two chains project different
+        # near-vacuum modes (Lambda^2 < 5e-11 each, D < D*) onto vacuum
+        assert np.max(np.abs(x.Lam ** 2 - y.Lam ** 2)) < 1e-10, m
+
+
+@pytest.mark.parametrize("name,chi", [("c1", 16), ("c2", 24)])
+def test_mirrored_site_tensor_is_a_diagonal_gauge_of_the_chain_tensor(name, chi):
+    """P4f: the tensor of site s built on the reversed state (site M+1-s there)
+    and transposed is the chain's tensor of site s in another gauge: the two
+    label each bond by Fock states of the two partner Bogoliubov modes of the
+    same Schmidt pair, so A_rev[beta, p, alpha] = A[alpha, p, beta] u_alpha v_beta
+    with u, v products of one factor per bond mode and photon (weights and
+    phases).  Checked: the ratio factorises as prod_q x_q^{alpha_q} y_q^{beta_q}
+    with the factors fitted from single occupations."""
+    w = W.workload(name)
+    d, M = w.d, w.M
+    ch = G.gsvd(w.gamma)
+    gr = G.reverse_modes(w.gamma)
+    for s in range(2, M):
+        sr = M + 1 - s
+        first = max(1, sr - 1)
+        rs = G.gsvd(gr, first=first, last=sr)
+        bl = K.kept_basis(ch.cuts[s - 2].Lam, chi)[0]
+        br = K.kept_basis(ch.cuts[s - 1].Lam, chi)[0]
+        assert K.kept_basis(rs.cuts[sr - 1 - first].Lam, chi)[0] == br
+        a_ch = pco.build_tensor(ch.Q[s - 1], bl, br, d)
+        a_rv = pco.build_tensor(rs.Q[sr - first], br, bl, d).transpose(2, 1, 0)
+        big = np.abs(a_ch) > 1e-8 * np.max(np.abs(a_ch))
+        ratio = np.where(big, a_rv / np.where(big, a_ch, 1), 0)
+        assert ratio[0, 0, 0] == pytest.approx(1.0)          # both vacuum elements are 1
+        x, y = {}, {}
+        for i, sa in enumerate(bl):
+            for j, sb in enumerate(br):
+                p = next((p for p in range(d) if big[i, p, j]), None)
+                if p is None:
+                    continue
+                if sum(sa) == 1 and sum(sb) == 0:
+                    x.setdefault(sa.index(1), ratio[i, p, j])
+                if sum(sb) == 1 and sum(sa) == 0:
+                    y.setdefault(sb.index(1), ratio[i, p, j])
+        checked = 0
+        for i, sa in enumerate(bl):
+            for j, sb in enumerate(br):
+                ql = [q for q in range(len(sa)) if sa[q]]
+                qr = [q for q in range(len(sb)) if sb[q]]
+                if any(q not in x for q in ql) or any(q not in y for q in qr):
+                    continue
+                f = np.prod([x[q] ** sa[q] for q in ql]) * np.prod([y[q] ** sb[q] for q in qr])
+                for p in range(d):
+                    if big[i, p, j]:
+                        assert abs(ratio[i, p, j] / f - 1) < 1e-6, (s, sa, p, sb)
+                        checked += 1
+        assert checked > 0, s
