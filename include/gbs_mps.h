@@ -93,10 +93,15 @@ int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, voi
  * site-1 straight from Gamma's block on modes 1..site-1, which stand in for
  * the bond modes of the cut before (from cut 300 when site > 301, the
  * widest block one workgroup takes), so each tensor is built on its own.
+ * Past the middle (M - site < site - 1) the site is built as site
+ * M + 1 - site of the mode-reversed state and its bonds are transposed, so
+ * the first block is never wider than the middle one.
  * Then the kept bases of the two cuts and the PCO build of that tensor (Eq.
  * Am_definition, Sec. II.C.2), in FP64, with no truncation sweep or
  * normalisation.  The tensor's bond bases are those of this build: they
- * equal a full build's up to a phase per bond mode.  The handle holds the
+ * equal a full build's up to a factor per bond mode and photon (a phase, and
+ * for mirrored sites also the Schmidt weight, which then sits on the other
+ * bond).  The handle holds the
  * raw tensor (gbs_mps_export GBS_EXPORT_RAW at `site`, kept[site-1] x d x
  * kept[site]), the Gaussian data and kept bases of the two cuts;
  * amplitude, sample and overlap calls on it fail with GBS_E_INVAL.

@@ -87,6 +87,14 @@ struct DevArena {
     }
     return e;
   }
+  void release(void* p) {  // one buffer of this arena
+    for (size_t i = 0; i < ptrs.size(); ++i)
+      if (ptrs[i] == p) {
+        (void)(ordered ? hipFreeAsync(p, st) : hipFree(p));
+        ptrs.erase(ptrs.begin() + (long)i);
+        return;
+      }
+  }
   void release_all() {
     for (void* p : ptrs) (void)(ordered ? hipFreeAsync(p, st) : hipFree(p));
     ptrs.clear();
@@ -926,6 +934,46 @@ int overlap_impl(gbs_mps_s* h1, gbs_mps_s* h2, hipStream_t st, int prec, double*
 
 __attribute__((visibility("hidden"))) int gbs_fail(int code, const std::string& msg) { return fail(code, msg); }
 
+namespace {
+
+// A single-site build of site s past the middle ran on the mode-reversed
+// state as site M + 1 - s: number its cuts back (cut m there is cut M - m
+// here), transpose its tensor's two bonds, and put its pair matrix in the
+// mode order (left bond, a_s, right bond) of site s.
+int mirror_single_site(gbs_mps_s* h, hipStream_t st) {
+  const int M = h->M, d = h->d, sr = h->single_site, s = M + 1 - sr;
+  std::reverse(h->ne.begin(), h->ne.end());
+  std::reverse(h->kept.begin(), h->kept.end());
+  std::reverse(h->bond.begin(), h->bond.end());
+  std::reverse(h->eps.begin(), h->eps.end());
+  std::reverse(h->entropy.begin(), h->entropy.end());
+  std::reverse(h->lam.begin(), h->lam.end());
+  std::reverse(h->occ_off.begin(), h->occ_off.end());
+  // tensor: kept[s] x d x kept[s-1] in the reversed numbering's bond order
+  const long A = h->kept[s], B = h->kept[s - 1];
+  cplx64* t;
+  HIP_CHECK_RET(dalloc(h->keep, &t, (size_t)std::max(A * d * B, 1L)));
+  HIP_CHECK_RET(launch_transpose_bonds(st, h->raw + h->raw_off[sr], A, d, B, t));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  h->keep.release(h->raw);
+  h->raw = t;
+  h->raw_off.assign(M + 1, 0);
+  // pair matrix: modes (r', a, l') = (cut s modes, a_s, cut s-1 modes)
+  const int nr = h->ne[s], nl = h->ne[s - 1], n = nl + 1 + nr;
+  std::vector<cplx64> qa((size_t)h->q_stride), qb((size_t)h->q_stride);
+  HIP_CHECK_RET(hipMemcpy(qa.data(), h->Q + (long)(sr - 1) * h->q_stride, h->q_stride * sizeof(cplx64),
+                          hipMemcpyDeviceToHost));
+  auto src = [&](int i) { return i < nl ? nr + 1 + i : (i == nl ? nr : i - nl - 1); };  // new index -> old
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) qb[(size_t)i * h->ld_q + j] = qa[(size_t)src(i) * h->ld_q + src(j)];
+  HIP_CHECK_RET(hipMemcpy(h->Q + (long)(s - 1) * h->q_stride, qb.data(), h->q_stride * sizeof(cplx64),
+                          hipMemcpyHostToDevice));
+  h->single_site = s;
+  return GBS_OK;
+}
+
+}  // namespace
+
 __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t stream, bool ordered_keep,
                      gbs_mps* out, int only_site) {
   if (!out) return fail(GBS_E_INVAL, "out_handle is NULL");
@@ -956,9 +1004,26 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
     h->keep.st = stream;
     h->keep.ordered = true;
   }
+  // Past the middle a single site is built on the mode-reversed state, where
+  // it lies before the middle: its first Gaussian SVD block, 2(s-1) wide in
+  // the given order, is then at most M wide.
+  const bool mirror = only_site > 0 && M - only_site < only_site - 1;
   int rc;
   try {
-    rc = build_impl(gamma, M, opt, stream, h, only_site);
+    DevArena rev(stream);
+    const double* g = gamma;
+    if (mirror) {
+      double* gr;
+      rc = rev.alloc((void**)&gr, sizeof(double) * 4 * (size_t)M * M) == hipSuccess &&
+                   launch_reverse_modes(stream, gamma, M, gr) == hipSuccess
+               ? GBS_OK
+               : fail(GBS_E_NOMEM, "reversed covariance");
+      g = gr;
+    } else {
+      rc = GBS_OK;
+    }
+    if (rc == GBS_OK) rc = build_impl(g, M, opt, stream, h, mirror ? M + 1 - only_site : only_site);
+    if (rc == GBS_OK && mirror) rc = mirror_single_site(h, stream);
   } catch (...) {
     rc = fail(GBS_E_INTERNAL, "unexpected host exception");
   }

@@ -45,3 +45,7 @@ hipError_t launch_gsvd_q(hipStream_t st, const GsvdArgs& a, int m);
 // quadratures and ne[k-1] = k - 1.  Needs 2 k <= n2max (the leading dimension
 // and row count of drr_in, the row count of cr_in).
 hipError_t launch_gsvd_restart(hipStream_t st, const GsvdArgs& a, int k);
+// out = Gamma with the modes numbered M..1 (xxpp order kept), 2M x 2M.
+hipError_t launch_reverse_modes(hipStream_t st, const double* gamma, int M, double* out);
+// out[b][p][a] = in[a][p][b] for an A x d x B complex FP64 tensor.
+hipError_t launch_transpose_bonds(hipStream_t st, const cplx64* in, long A, int d, long B, cplx64* out);

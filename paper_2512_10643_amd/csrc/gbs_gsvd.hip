@@ -1170,3 +1170,43 @@ hipError_t launch_gsvd_restart(hipStream_t st, const GsvdArgs& a, int k) {
                      const_cast<double*>(a.drr_in), a.ld_drr, const_cast<double*>(a.cr_in), a.ld_cr, a.ne);
   return hipGetLastError();
 }
+
+__global__ void reverse_modes_kernel(const double* g, int M, double* out) {
+  const long n2 = 2L * M;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n2 * n2; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / n2, j = e % n2;
+    const long si = i < M ? M - 1 - i : 3L * M - 1 - i, sj = j < M ? M - 1 - j : 3L * M - 1 - j;
+    out[e] = g[si * n2 + sj];
+  }
+}
+
+hipError_t launch_reverse_modes(hipStream_t st, const double* gamma, int M, double* out) {
+  const long tot = 4L * M * M;
+  const int blocks = (int)std::max<long>(1, std::min<long>(4096, (tot + 255) / 256));
+  hipLaunchKernelGGL(reverse_modes_kernel, dim3(blocks), dim3(256), 0, st, gamma, M, out);
+  return hipGetLastError();
+}
+
+// 32 x 32 tiles of one physical index p through LDS, so that both the reads
+// (along b) and the writes (along a) are contiguous.
+__global__ __launch_bounds__(256) void transpose_bonds_kernel(const cplx64* in, long A, int d, long B, cplx64* out) {
+  __shared__ cplx64 tile[32][33];
+  const int p = blockIdx.z;
+  const long a0 = (long)blockIdx.y * 32, b0 = (long)blockIdx.x * 32;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const long a = a0 + r, b = b0 + threadIdx.x;
+    if (a < A && b < B) tile[r][threadIdx.x] = in[(a * d + p) * B + b];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const long b = b0 + r, a = a0 + threadIdx.x;
+    if (a < A && b < B) out[(b * d + p) * A + a] = tile[threadIdx.x][r];
+  }
+}
+
+hipError_t launch_transpose_bonds(hipStream_t st, const cplx64* in, long A, int d, long B, cplx64* out) {
+  if (A < 1 || B < 1 || d < 1 || (B + 31) / 32 > 0x7fffffffL || (A + 31) / 32 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_bonds_kernel, dim3((unsigned)((B + 31) / 32), (unsigned)((A + 31) / 32), d), dim3(32, 8),
+                     0, st, in, A, d, B, out);
+  return hipGetLastError();
+}

@@ -6,6 +6,8 @@ Tolerances: FP64 path, max |delta amplitude| <= 1e-10; FP32 path,
 import itertools
 import sys
 
+import types
+
 import numpy as np
 import pytest
 
@@ -407,10 +409,18 @@ def _min_lambda(w, m):
 
 
 def _check_single_site(torch_cuda, w, m, D, d):
-    from oracle import pco as opco
+    """A single-site build against the oracle's build of the same site by the
+    same route: past the middle (M - m < m - 1), site M + 1 - m of the
+    mode-reversed state with the tensor's bonds transposed."""
+    from oracle import gaussian as og, pco as opco
     from paper_2512_10643_amd import mps as gmps
-    q, bl, br = _oracle_site_inputs(w, m, D)
-    ref = opco.build_tensor(q, bl, br, d)
+    if w.M - m < m - 1:
+        wr = types.SimpleNamespace(gamma=og.reverse_modes(w.gamma), M=w.M)
+        q, br, bl = _oracle_site_inputs(wr, w.M + 1 - m, D)
+        ref = opco.build_tensor(q, br, bl, d).transpose(2, 1, 0)
+    else:
+        q, bl, br = _oracle_site_inputs(w, m, D)
+        ref = opco.build_tensor(q, bl, br, d)
     g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
     h = gmps.build_site(g, d, D, m)
     try:
@@ -470,10 +480,11 @@ def test_single_site_past_the_widest_first_block(torch_cuda):
     assert err <= tol * max(1.0, amax)
 
 
-@pytest.mark.parametrize("m", [120, 144])
-def test_single_site_wide_first_block(torch_cuda, m):
-    """C3 sites past the middle: the first Gaussian SVD block is 2(m-1) wide
-    (238 and 286), past the size whose working matrix stays in LDS."""
+@pytest.mark.parametrize("m", [73, 120, 144])
+def test_single_site_past_the_middle(torch_cuda, m):
+    """C3 sites past the middle, built as sites 72, 25 and 1 of the
+    mode-reversed state (first Gaussian SVD block at most 144 wide), with the
+    tensor's bonds transposed and the cuts numbered back."""
     _say(f"case: c3 single site {m}, D=64, d=4")
     w = W.workload("c3")
     err, amax, t = _check_single_site(torch_cuda, w, m, 64, 4)
