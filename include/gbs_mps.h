@@ -61,7 +61,13 @@ typedef enum {
  * eps_target > 0 picks the bond dimension per cut (Sec. II.C.2, D(eps)):
  * each cut keeps the fewest lowest-energy states whose discarded weight
  * eps_m = 1 - (1/Z) sum_kept exp(-E) is at most eps_target, and at most chi
- * of them; the truncation sweep then acts on those bonds as usual. */
+ * of them; the truncation sweep then acts on those bonds as usual.
+ * chi_build > chi (full builds): the kept bases and PCO tensors are built at
+ * chi_build states per cut (D_build; eps_target then caps at chi_build) and
+ * the truncation sweep recompresses every bond to at most chi singular
+ * directions, a global truncation in place of the local analytic one
+ * (Sec. II.C.1); 0 or <= chi: D_build = chi.  chi_build <= 4096 and
+ * chi_build * d <= 8192; single-site builds do not use it. */
 #define GBS_KEEP_RAW 1u
 #define GBS_DENSE_SAMPLER 2u
 typedef struct {
@@ -72,6 +78,7 @@ typedef struct {
   uint32_t flags;
   double trunc_rel;
   double eps_target;  /* > 0: D(eps) per cut, see below; 0: chi states at every cut */
+  int32_t chi_build;  /* > chi: kept states per cut before the recompression to chi */
 } gbs_build_opts;
 
 /* Build the MPS of the pure state with covariance `gamma`.

@@ -40,7 +40,7 @@ class GbsError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("chi", ctypes.c_int32), ("dstar", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32), ("trunc_rel", ctypes.c_double),
-                ("eps_target", ctypes.c_double)]
+                ("eps_target", ctypes.c_double), ("chi_build", ctypes.c_int32)]
 
 
 class SampleTimingT(ctypes.Structure):

@@ -482,7 +482,8 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
 }
 
 int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t st, gbs_mps_s* h, int only_site) {
-  const int d = opt->d, chi = opt->chi;
+  // kept states per cut (D_build); the truncation sweep caps bonds at h->chi
+  const int d = opt->d, chi = only_site ? opt->chi : std::max(opt->chi, opt->chi_build);
   HIP_CHECK_RET(ensure_pool(st));
   DevArena tmp(st);
   int* err;
@@ -989,6 +990,8 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
     return fail(GBS_E_INVAL, "unknown precision");
   if (only_site < 0 || only_site > M) return fail(GBS_E_INVAL, "site out of range");
   if (!only_site && (long)opt->chi * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi * d too large");
+  if (opt->chi_build < 0 || opt->chi_build > GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi_build must be in [0, 4096]");
+  if (!only_site && (long)opt->chi_build * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi_build * d too large");
   if (opt->d > 64) return fail(GBS_E_INVAL, "d must be <= 64");
   if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER)) return fail(GBS_E_INVAL, "unknown build flag");
   gbs_mps_s* h = new (std::nothrow) gbs_mps_s();
@@ -1376,7 +1379,8 @@ void gbs_mps_free(gbs_mps h) {
 // `shots`) holds at its peak: every buffer is sized from M, d and chi alone.
 int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   if (!opt || M < 1 || opt->d < 1 || opt->chi < 1) return -1;
-  const int64_t d = opt->d, chi = std::min<int64_t>(opt->chi, GBS_CHI_MAX), m = M;
+  if (opt->chi_build < 0) return -1;
+  const int64_t d = opt->d, chi = std::min<int64_t>(std::max(opt->chi, opt->chi_build), GBS_CHI_MAX), m = M;
   const int64_t esz = opt->prec == GBS_FP64 ? 16 : 8;
   const int64_t n2 = std::min<int64_t>(m + 2, GBS_GSVD_N2_MAX);
   int64_t b = 0;

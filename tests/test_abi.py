@@ -41,7 +41,8 @@ def test_invalid_arguments_rejected_on_host():
     fake = ctypes.c_void_p(1)  # never dereferenced: validation fails first
     assert L.gbs_mps_build(fake, 0, ctypes.byref(opts), None, ctypes.byref(h)) == _lib.GBS_E_INVAL
     assert h.value is None
-    for bad in (dict(d=0), dict(chi=0), dict(chi=5000), dict(dstar=1.0), dict(prec=9)):
+    for bad in (dict(d=0), dict(chi=0), dict(chi=5000), dict(dstar=1.0), dict(prec=9), dict(chi_build=-1),
+                dict(chi_build=5000), dict(chi_build=4096)):  # the last: chi_build * d = 16384 > 8192
         o = _lib.BuildOpts(**{**dict(d=4, chi=16, dstar=1.0 + 1e-10, prec=0, flags=0, trunc_rel=0.0), **bad})
         assert L.gbs_mps_build(fake, 4, ctypes.byref(o), None, ctypes.byref(h)) == _lib.GBS_E_INVAL
     assert L.gbs_mps_build(None, 4, ctypes.byref(opts), None, ctypes.byref(h)) == _lib.GBS_E_INVAL
@@ -67,6 +68,11 @@ def test_server_and_footprint_host_checks():
     o.chi = 64
     f3 = L.gbs_mps_footprint(144, ctypes.byref(o), 0)
     assert 0 < f3 < f1 < f2
+    o.chi_build = 256     # built at 256 states per cut, recompressed to 64
+    assert L.gbs_mps_footprint(144, ctypes.byref(o), 0) == f1
+    o.chi_build = -1
+    assert L.gbs_mps_footprint(144, ctypes.byref(o), 0) == -1
+    o.chi_build = 0
     # the C3 build holds its PCO tensors (144 x 8 x 256^2 complex FP64) at least
     assert f1 > 144 * 8 * 256 * 256 * 16
     o.d = 0
