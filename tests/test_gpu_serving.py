@@ -1,6 +1,8 @@
 """Request server (gbs_server_* in the C ABI) on the GPU: a request's samples
 are identical alone and in a concurrent mix, failures stay with their own
 request, and admission limits are enforced."""
+import time
+
 import numpy as np
 import pytest
 
@@ -89,7 +91,16 @@ def test_admission_limits(torch_cuda):
             srv.submit(g, w.d, 4 * w.chi, 1000, 1)  # larger than the whole budget
         assert e.value.code == GBS_E_NOMEM
         a = srv.submit(g, w.d, w.chi, 1000, 1)
-        b = srv.submit(g, w.d, w.chi, 1000, 2)
+        # until a worker takes `a` off the queue the queue (max 1) is full,
+        # and BUSY is the answer; then `b` is queued
+        b, t0 = None, time.time()
+        while b is None:
+            try:
+                b = srv.submit(g, w.d, w.chi, 1000, 2)
+            except GbsError as ex:
+                assert ex.code == GBS_E_BUSY
+                assert time.time() - t0 < 30
+                time.sleep(0.001)
         busy = None
         try:
             c = srv.submit(g, w.d, w.chi, 1000, 3)
