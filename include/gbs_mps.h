@@ -110,7 +110,9 @@ int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, voi
  * for mirrored sites also the Schmidt weight, which then sits on the other
  * bond).  The handle holds the
  * raw tensor (gbs_mps_export GBS_EXPORT_RAW at `site`, kept[site-1] x d x
- * kept[site]), the Gaussian data and kept bases of the two cuts;
+ * kept[site]), its pair matrix (GBS_EXPORT_Q at `site`, modes in the order
+ * left bond, a_site, right bond), the Gaussian data and kept bases of the
+ * two cuts; exports of other sites fail with GBS_E_INVAL;
  * amplitude, sample and overlap calls on it fail with GBS_E_INVAL.
  *   gamma, M, opt, stream, out : as gbs_mps_build (opt->prec and
  *   opt->trunc_rel are not used; the chi * d limit of full builds does not

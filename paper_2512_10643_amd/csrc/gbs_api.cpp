@@ -1017,10 +1017,12 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
     const double* g = gamma;
     if (mirror) {
       double* gr;
-      rc = rev.alloc((void**)&gr, sizeof(double) * 4 * (size_t)M * M) == hipSuccess &&
-                   launch_reverse_modes(stream, gamma, M, gr) == hipSuccess
-               ? GBS_OK
-               : fail(GBS_E_NOMEM, "reversed covariance");
+      if (rev.alloc((void**)&gr, sizeof(double) * 4 * (size_t)M * M) != hipSuccess)
+        rc = fail(GBS_E_NOMEM, "device allocation of the reversed covariance failed");
+      else if (launch_reverse_modes(stream, gamma, M, gr) != hipSuccess)
+        rc = fail(GBS_E_INTERNAL, "launch of the mode reversal failed");
+      else
+        rc = GBS_OK;
       g = gr;
     } else {
       rc = GBS_OK;
@@ -1310,7 +1312,7 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
   };
   if (h->single_site && (what == GBS_EXPORT_TENSOR || what == GBS_EXPORT_SVALS || what == GBS_EXPORT_SECTORS))
     return fail(GBS_E_INVAL, "the handle holds one site's PCO tensor only");
-  if (h->single_site && what == GBS_EXPORT_RAW && m != h->single_site)
+  if (h->single_site && (what == GBS_EXPORT_RAW || what == GBS_EXPORT_Q) && m != h->single_site)
     return fail(GBS_E_INVAL, "the handle holds the tensor of another site");
   if (what == GBS_EXPORT_TENSOR) {
     if (m < 1 || m > M) return fail(GBS_E_INVAL, "site out of range");

@@ -448,6 +448,10 @@ def _check_single_site(torch_cuda, w, m, D, d):
         wr = types.SimpleNamespace(gamma=og.reverse_modes(w.gamma), M=w.M)
         q, br, bl = _oracle_site_inputs(wr, w.M + 1 - m, D)
         ref = opco.build_tensor(q, br, bl, d).transpose(2, 1, 0)
+        # pair matrix in the order (left bond, a_m, right bond) of site m
+        nr, nl = len(br[0]), len(bl[0])
+        order = list(range(nr + 1, nr + 1 + nl)) + [nr] + list(range(nr))
+        q = q[np.ix_(order, order)]
     else:
         q, bl, br = _oracle_site_inputs(w, m, D)
         ref = opco.build_tensor(q, bl, br, d)
@@ -457,10 +461,18 @@ def _check_single_site(torch_cuda, w, m, D, d):
         assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
         assert [tuple(r) for r in h.export(m, "basis")] == list(br)
         raw = h.export(m, "raw")
+        qg = h.export(m, "Q")
         t = h.info()["t_gsvd_ms"]
     finally:
         h.free()
     assert raw.shape == ref.shape
+    # the pair matrix comes in the order (left bond, a_m, right bond): its
+    # size, and the physical mode's own entry (free of the bond gauge, and
+    # well conditioned, unlike entries of bond modes with Lambda near the
+    # frozen threshold, which the kept tensor elements above do not feel)
+    assert qg.shape == q.shape
+    na = len(bl[0])
+    assert abs(abs(qg[na, na]) - abs(q[na, na])) <= 1e-10
     return np.max(np.abs(np.abs(raw) - np.abs(ref))), np.max(np.abs(ref)), t
 
 
