@@ -143,6 +143,23 @@ int gbs_mps_amplitude(gbs_mps h, const int32_t* patterns, int64_t B, double* out
  *   out : device, shots x M int32.  Asynchronous on `stream`. */
 int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
 
+/* gbs_mps_sample for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, samples and errors as gbs_mps_sample (bit-identical
+ * output), but the sweep's buffers (left vectors, norms, parities, running
+ * sums, shot partitions) come from one static device array of
+ * GBS_SAMPLE_NOALLOC_SCRATCH_BYTES that each GPU holds for the life of the
+ * process, so the call makes no hipMalloc, hipFree or allocating library
+ * call.  The shots go through in sweeps of the largest multiple of 128 shots
+ * whose buffers fit the array (about 80 000 at a 256-wide bond, whole 10^6
+ * sweeps never); a handle whose 128-shot sweep does not fit is rejected with
+ * GBS_E_NOMEM.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on the same GPU (other streams or host threads) race and must be
+ * serialised by the caller.  The array keeps the last call's contents; each
+ * call writes every buffer before reading it.  Asynchronous on `stream`. */
+#define GBS_SAMPLE_NOALLOC_SCRATCH_BYTES (256ll << 20)
+int gbs_mps_sample_noalloc(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream);
+
 /* GPU time of the launches of one sampling call (HIP events on its stream). */
 typedef struct {
   int32_t first_launches;  /* first-pass launches: outcome 0 for every shot, one per site */

@@ -20,10 +20,13 @@ ERROR_NAMES = {0: "OK", -1: "INVAL", -2: "NOT_PD", -3: "NOT_PURE", -4: "NOMEM", 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 GBS_KEEP_RAW = 1
 GBS_DENSE_SAMPLER = 2
+# Size of the static device array gbs_mps_sample_noalloc samples on (the
+# header's GBS_SAMPLE_NOALLOC_SCRATCH_BYTES).
+GBS_SAMPLE_NOALLOC_SCRATCH_BYTES = 256 << 20
 EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5, "sectors": 6}
 
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
-EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_build_site", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
+EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_build_site", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_noalloc", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
                     "gbs_mps_info",
                     "gbs_mps_export", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
                     "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
@@ -95,6 +98,8 @@ def lib():
         L.gbs_mps_amplitude.restype = ctypes.c_int
         L.gbs_mps_sample.argtypes = [vp, i64, u64, dp, vp]
         L.gbs_mps_sample.restype = ctypes.c_int
+        L.gbs_mps_sample_noalloc.argtypes = [vp, i64, u64, dp, vp]
+        L.gbs_mps_sample_noalloc.restype = ctypes.c_int
         L.gbs_mps_sample_timed.argtypes = [vp, i64, u64, dp, vp, ctypes.POINTER(SampleTimingT)]
         L.gbs_mps_sample_timed.restype = ctypes.c_int
         L.gbs_mps_overlap.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]

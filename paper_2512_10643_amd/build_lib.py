@@ -22,6 +22,7 @@ SOURCES = [
     "gbs_pco.hip",
     "gbs_mpsops.hip",
     "gbs_sampler.hip",
+    "gbs_noalloc.hip",
     "gbs_api.cpp",
     "gbs_server.cpp",
 ]

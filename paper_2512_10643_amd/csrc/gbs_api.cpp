@@ -1152,49 +1152,89 @@ int gbs_mps_sample_timed(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, 
 
 namespace {
 
-int sample_impl(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream, SampleClock* clk) {
+// Device buffers of one sampling call, sized for `chunk` shots per sweep.
+struct SampleBufs {
+  float* fb[2] = {nullptr, nullptr};  // MFMA sweep: left vectors (ping-pong)
+  float* sb[2] = {nullptr, nullptr};  // their inverse norms
+  int8_t *par = nullptr, *key = nullptr;
+  float* cum = nullptr;
+  int32_t *perm = nullptr, *cnt = nullptr, *perm2 = nullptr, *cnt2 = nullptr, *bcnt = nullptr;
+  void* lbuf[2] = {nullptr, nullptr};  // vector sweep: left vectors (ping-pong)
+};
+
+// Source of those buffers: stream-ordered allocations from an arena, or
+// consecutive 256-byte aligned pieces of a region the caller provides.  With
+// neither (base == nullptr and no arena) it only counts the bytes.
+struct SampleAlloc {
+  DevArena* ar = nullptr;
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  hipError_t get(void** p, size_t n) {
+    n = (std::max<size_t>(n, 16) + 255) & ~(size_t)255;
+    if (ar) return ar->alloc(p, n);
+    if (base && used + n > cap) return hipErrorOutOfMemory;
+    *p = base ? base + used : nullptr;
+    used += n;
+    return hipSuccess;
+  }
+};
+
+hipError_t sample_buffers(const gbs_mps_s* h, int64_t chunk, SampleAlloc& a, SampleBufs& b) {
+  if (h->packed) {
+    // MFMA path: left vectors as interleaved floats in sector-local indices,
+    // rows padded to 16 complex, plus one inverse row norm per shot; parities
+    // and their partition (sector layout); key, running sums and the
+    // partition of the shots left undecided by a site's first pass
+    for (int i = 0; i < 2; ++i) {
+      hipError_t e = a.get((void**)&b.fb[i], (size_t)chunk * h->ldl2 * sizeof(float));
+      if (e == hipSuccess) e = a.get((void**)&b.sb[i], (size_t)chunk * sizeof(float));
+      if (e != hipSuccess) return e;
+    }
+    const size_t permb = (size_t)(chunk + sampler_shots_per_block()) * sizeof(int32_t);
+    hipError_t e = hipSuccess;
+    if (h->psplit) {
+      e = a.get((void**)&b.par, (size_t)chunk);
+      if (e == hipSuccess) e = a.get((void**)&b.perm, permb);
+      if (e == hipSuccess) e = a.get((void**)&b.cnt, 2 * sizeof(int32_t));
+    }
+    if (e == hipSuccess) e = a.get((void**)&b.key, (size_t)chunk);
+    if (e == hipSuccess) e = a.get((void**)&b.cum, (size_t)chunk * sizeof(float));
+    if (e == hipSuccess) e = a.get((void**)&b.perm2, permb);
+    if (e == hipSuccess) e = a.get((void**)&b.cnt2, 2 * sizeof(int32_t));
+    if (e == hipSuccess) e = a.get((void**)&b.bcnt, (size_t)sampler_partition_ws(chunk) * sizeof(int32_t));
+    return e;
+  }
+  const size_t rowbytes = (size_t)h->maxbond * h->esz;
+  for (int i = 0; i < 2; ++i) {
+    hipError_t e = a.get(&b.lbuf[i], (size_t)chunk * rowbytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Largest shot count per sweep for this handle: 2^20 on the MFMA path (one
+// launch per site for 10^6 shots), 2^18 on the vector path (rows up to 16 KB).
+int64_t sample_chunk_max(const gbs_mps_s* h) { return h->packed ? kSampleChunk : kSampleChunkGeneric; }
+
+int sample_checks(gbs_mps h, int64_t shots, int32_t* out) {
   if (!h) return fail(GBS_E_INVAL, "NULL handle");
   if (h->single_site) return fail(GBS_E_INVAL, "the handle holds one site's tensor only");
   if (shots < 0) return fail(GBS_E_INVAL, "shots < 0");
-  if (shots == 0) return GBS_OK;
-  if (!out) return fail(GBS_E_INVAL, "NULL output");
+  if (shots > 0 && !out) return fail(GBS_E_INVAL, "NULL output");
   if (h->maxbond > 1024) return fail(GBS_E_INVAL, "sampler supports bond dimension <= 1024");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_CHECK_RET(ensure_pool(st));
+  return GBS_OK;
+}
+
+// The sweep itself, `chunk` shots at a time, on buffers `b`.
+int sample_sweep(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, hipStream_t st, SampleClock* clk,
+                 int64_t chunk, const SampleBufs& b) {
   const int M = h->M, d = h->d;
   const long ldl = h->maxbond;
-  const int64_t chunk = std::min<int64_t>(shots, h->packed ? kSampleChunk : kSampleChunkGeneric);
-  DevArena tmp(st);
-  void* lbuf[2];
   if (h->packed) {
-    // MFMA path: left vectors as interleaved floats in sector-local indices,
-    // rows padded to 16 complex, plus one inverse row norm per shot
     const long ldl2 = h->ldl2;
-    float* fb[2];
-    float* sb[2];
-    for (int i = 0; i < 2; ++i) {
-      HIP_CHECK_RET(tmp.alloc((void**)&fb[i], (size_t)chunk * ldl2 * sizeof(float)));
-      HIP_CHECK_RET(tmp.alloc((void**)&sb[i], (size_t)chunk * sizeof(float)));
-    }
-    // parities and their partition (sector layout); key, running sums and
-    // the partition of the shots left undecided by a site's first pass
-    int8_t *par = nullptr, *key;
-    float* cum;
-    int32_t *perm = nullptr, *cnt = nullptr, *perm2, *cnt2, *bcnt;
-    const size_t permb = (size_t)(chunk + sampler_shots_per_block()) * sizeof(int32_t);
-    if (h->psplit) {
-      HIP_CHECK_RET(tmp.alloc((void**)&par, (size_t)chunk));
-      HIP_CHECK_RET(tmp.alloc((void**)&perm, permb));
-      HIP_CHECK_RET(tmp.alloc((void**)&cnt, 2 * sizeof(int32_t)));
-    }
-    HIP_CHECK_RET(tmp.alloc((void**)&key, (size_t)chunk));
-    HIP_CHECK_RET(tmp.alloc((void**)&cum, (size_t)chunk * sizeof(float)));
-    HIP_CHECK_RET(tmp.alloc((void**)&perm2, permb));
-    HIP_CHECK_RET(tmp.alloc((void**)&cnt2, 2 * sizeof(int32_t)));
-    HIP_CHECK_RET(tmp.alloc((void**)&bcnt, (size_t)sampler_partition_ws(chunk) * sizeof(int32_t)));
     for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
       const int64_t n = std::min(chunk, shots - s0);
-      HIP_CHECK_RET(launch_sampler_init(st, fb[0], ldl2, h->bond[0], n));
+      HIP_CHECK_RET(launch_sampler_init(st, b.fb[0], ldl2, h->bond[0], n));
       int cur = 0;
       for (int m = 1; m <= M; ++m) {
         // site 1: every shot starts in sector 0 of the one-dimensional bond
@@ -1203,55 +1243,111 @@ int sample_impl(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* str
         const SamplerGeom& G = h->sgeo[m];
         const bool more = G.npass[0] > 1 || G.npass[1] > 1;
         const float* P = h->packed + h->poff[m];
-        const float* sin = m == 1 ? nullptr : sb[cur];
+        const float* sin = m == 1 ? nullptr : b.sb[cur];
         // first pass (outcome 0) for every shot
         if (clk) HIP_CHECK_RET(clk->mark(clk->first));
-        HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, fb[cur], sin, fb[1 - cur], sb[1 - cur], ldl2,
-                                         part ? perm : nullptr, part ? cnt : nullptr, next ? par : nullptr,
-                                         more ? cum : nullptr, more ? key : nullptr, 0, 1, s0, n, m, seed, out, M));
+        HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], sin, b.fb[1 - cur], b.sb[1 - cur], ldl2,
+                                         part ? b.perm : nullptr, part ? b.cnt : nullptr, next ? b.par : nullptr,
+                                         more ? b.cum : nullptr, more ? b.key : nullptr, 0, 1, s0, n, m, seed, out, M));
         if (clk) HIP_CHECK_RET(clk->mark(clk->first));
         if (more) {
           // the other passes for the shots the first one left undecided
-          HIP_CHECK_RET(launch_sampler_partition(st, key, n, bcnt, perm2, cnt2));
+          HIP_CHECK_RET(launch_sampler_partition(st, b.key, n, b.bcnt, b.perm2, b.cnt2));
           if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
-          HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, fb[cur], sin, fb[1 - cur], sb[1 - cur], ldl2,
-                                           perm2, cnt2, next ? par : nullptr, cum, nullptr, 1, kSamplerMaxOutcomes,
-                                           s0, n, m, seed, out, M));
+          HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], sin, b.fb[1 - cur], b.sb[1 - cur],
+                                           ldl2, b.perm2, b.cnt2, next ? b.par : nullptr, b.cum, nullptr, 1,
+                                           kSamplerMaxOutcomes, s0, n, m, seed, out, M));
           if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
         }
-        if (next) HIP_CHECK_RET(launch_sampler_partition(st, par, n, bcnt, perm, cnt));
+        if (next) HIP_CHECK_RET(launch_sampler_partition(st, b.par, n, b.bcnt, b.perm, b.cnt));
         cur = 1 - cur;
       }
     }
-    return GBS_OK;  // the temporaries are freed in stream order
+    return GBS_OK;
   }
-  const size_t rowbytes = (size_t)ldl * h->esz;
-  for (int i = 0; i < 2; ++i) HIP_CHECK_RET(tmp.alloc(&lbuf[i], (size_t)chunk * rowbytes));
   for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
     const int64_t n = std::min(chunk, shots - s0);
     int cur = 0;
     if (h->esz == sizeof(cplx64)) {
-      HIP_CHECK_RET(launch_fill_first<cplx64>(st, (cplx64*)lbuf[0], ldl, n));
+      HIP_CHECK_RET(launch_fill_first<cplx64>(st, (cplx64*)b.lbuf[0], ldl, n));
       for (int m = 1; m <= M; ++m) {
         const cplx64* Bm = (const cplx64*)h->tens + h->toff[m];
-        HIP_CHECK_RET(launch_sample_site<cplx64>(st, Bm, h->bond[m - 1], d, h->bond[m], (const cplx64*)lbuf[cur],
-                                                 (cplx64*)lbuf[1 - cur], ldl, s0, n, m, seed, out, M));
+        HIP_CHECK_RET(launch_sample_site<cplx64>(st, Bm, h->bond[m - 1], d, h->bond[m], (const cplx64*)b.lbuf[cur],
+                                                 (cplx64*)b.lbuf[1 - cur], ldl, s0, n, m, seed, out, M));
         cur = 1 - cur;
       }
     } else {
-      HIP_CHECK_RET(launch_fill_first<cplx32>(st, (cplx32*)lbuf[0], ldl, n));
+      HIP_CHECK_RET(launch_fill_first<cplx32>(st, (cplx32*)b.lbuf[0], ldl, n));
       for (int m = 1; m <= M; ++m) {
         const cplx32* Bm = (const cplx32*)h->tens + h->toff[m];
-        HIP_CHECK_RET(launch_sample_site<cplx32>(st, Bm, h->bond[m - 1], d, h->bond[m], (const cplx32*)lbuf[cur],
-                                                 (cplx32*)lbuf[1 - cur], ldl, s0, n, m, seed, out, M));
+        HIP_CHECK_RET(launch_sample_site<cplx32>(st, Bm, h->bond[m - 1], d, h->bond[m], (const cplx32*)b.lbuf[cur],
+                                                 (cplx32*)b.lbuf[1 - cur], ldl, s0, n, m, seed, out, M));
         cur = 1 - cur;
       }
     }
   }
-  return GBS_OK;  // the temporaries are freed in stream order
+  return GBS_OK;
+}
+
+int sample_impl(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* stream, SampleClock* clk) {
+  if (int rc = sample_checks(h, shots, out)) return rc;
+  if (shots == 0) return GBS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_CHECK_RET(ensure_pool(st));
+  const int64_t chunk = std::min<int64_t>(shots, sample_chunk_max(h));
+  DevArena tmp(st);
+  SampleAlloc a;
+  a.ar = &tmp;
+  SampleBufs b;
+  HIP_CHECK_RET(sample_buffers(h, chunk, a, b));
+  return sample_sweep(h, shots, seed, out, st, clk, chunk, b);  // temporaries are freed in stream order
 }
 
 }  // namespace
+
+// Sampling on a caller-provided device region of `cap` bytes instead of
+// stream-ordered allocations: the shots go through in sweeps of the largest
+// multiple of 128 shots whose buffers fit the region (at most the usual
+// sweep size).  Allocates nothing.
+__attribute__((visibility("hidden"))) int gbs_sample_in_region(gbs_mps h, int64_t shots, uint64_t seed,
+                                                               int32_t* out, hipStream_t st, void* region,
+                                                               size_t cap) {
+  if (int rc = sample_checks(h, shots, out)) return rc;
+  if (shots == 0) return GBS_OK;
+  if (!region) return fail(GBS_E_INVAL, "NULL workspace region");
+  const int64_t blk = sampler_shots_per_block();
+  auto bytes = [&](int64_t c) {
+    SampleAlloc a;  // counting only
+    SampleBufs b;
+    (void)sample_buffers(h, c, a, b);
+    return a.used;
+  };
+  const int64_t want = std::min<int64_t>(shots, sample_chunk_max(h));
+  int64_t chunk = 0;
+  if (bytes(want) <= cap) {
+    chunk = want;
+  } else {
+    int64_t lo = 0, hi = want / blk;  // largest multiple of blk that fits
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (bytes(mid * blk) <= cap) lo = mid;
+      else hi = mid - 1;
+    }
+    chunk = lo * blk;
+  }
+  if (chunk <= 0) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes holds fewer than %lld shots of this handle (%zu bytes needed)",
+             cap, (long long)std::min<int64_t>(blk, shots), bytes(std::min<int64_t>(blk, shots)));
+    return fail(GBS_E_NOMEM, buf);
+  }
+  SampleAlloc a;
+  a.base = (char*)region;
+  a.cap = cap;
+  SampleBufs b;
+  HIP_CHECK_RET(sample_buffers(h, chunk, a, b));
+  return sample_sweep(h, shots, seed, out, st, nullptr, chunk, b);
+}
 
 extern "C" {
 

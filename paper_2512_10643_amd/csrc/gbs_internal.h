@@ -14,3 +14,8 @@ int gbs_build_handle(const double* gamma, int M, const gbs_build_opts* opt, hipS
 
 // Record `msg` as this thread's gbs_last_error() text and return `code`.
 int gbs_fail(int code, const std::string& msg);
+
+// Sampling (as gbs_mps_sample) on buffers carved from a device region of
+// `cap` bytes the caller provides; allocates nothing.
+int gbs_sample_in_region(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, hipStream_t st, void* region,
+                         size_t cap);

@@ -57,6 +57,16 @@ class GaussianMPS:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
+    def sample_noalloc(self, shots: int, seed: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """sample() through gbs_mps_sample_noalloc: the same samples, drawn on
+        the library's static device scratch array (no device allocation in
+        the call; `out` must be given)."""
+        if out.dtype != torch.int32 or not out.is_cuda or tuple(out.shape) != (shots, self.M):
+            raise ValueError("out must be a CUDA int32 tensor of shape (shots, M)")
+        check(lib().gbs_mps_sample_noalloc(self._h, int(shots), ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
     def sample_timed(self, shots: int, seed: int, out: torch.Tensor | None = None, stream=None):
         """sample() with HIP events around each sampling launch; returns
         (samples, dict of launch counts and GPU milliseconds).  Synchronises

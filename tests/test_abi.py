@@ -32,6 +32,12 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) == set(_lib.EXPORTED_SYMBOLS)
 
 
+def test_noalloc_scratch_size_matches_header():
+    from paper_2512_10643_amd import _lib
+    m = re.search(r"#define GBS_SAMPLE_NOALLOC_SCRATCH_BYTES \((\d+)ll << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.GBS_SAMPLE_NOALLOC_SCRATCH_BYTES
+
+
 def test_invalid_arguments_rejected_on_host():
     """Argument validation happens before any device work."""
     from paper_2512_10643_amd import _lib
@@ -49,6 +55,7 @@ def test_invalid_arguments_rejected_on_host():
     assert b"NULL" in L.gbs_last_error()
     assert L.gbs_mps_amplitude(None, None, 1, None, None) == _lib.GBS_E_INVAL
     assert L.gbs_mps_sample(None, 1, 0, None, None) == _lib.GBS_E_INVAL
+    assert L.gbs_mps_sample_noalloc(None, 1, 0, None, None) == _lib.GBS_E_INVAL
     L.gbs_mps_free(None)
 
 
