@@ -106,9 +106,10 @@ int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, voi
  * Then the kept bases of the two cuts and the PCO build of that tensor (Eq.
  * Am_definition, Sec. II.C.2), in FP64, with no truncation sweep or
  * normalisation.  The tensor's bond bases are those of this build: they
- * equal a full build's up to a factor per bond mode and photon (a phase, and
- * for mirrored sites also the Schmidt weight, which then sits on the other
- * bond).  The handle holds the
+ * equal a full build's up to a phase per bond mode and photon (for a site
+ * past the middle the Schmidt weights Lambda_q, which the reversed chain
+ * puts on the other bond, are moved back: element (alpha, p, beta) times
+ * prod Lambda_{site-1}^alpha / prod Lambda_site^beta).  The handle holds the
  * raw tensor (gbs_mps_export GBS_EXPORT_RAW at `site`, kept[site-1] x d x
  * kept[site]), its pair matrix (GBS_EXPORT_Q at `site`, modes in the order
  * left bond, a_site, right bond), the Gaussian data and kept bases of the
@@ -231,6 +232,13 @@ int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, do
 enum { GBS_EXPORT_TENSOR = 0, GBS_EXPORT_RAW = 1, GBS_EXPORT_Q = 2, GBS_EXPORT_BASIS = 3, GBS_EXPORT_LAMBDA = 4,
        GBS_EXPORT_SVALS = 5, GBS_EXPORT_SECTORS = 6 };
 int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, int64_t* written);
+
+/* Selected elements of the tensor of site m (tests of tensors too large to
+ * export whole, e.g. a 16 GB single-site tensor).  what: GBS_EXPORT_TENSOR
+ * (canonical tensor, bond[m-1] x d x bond[m]) or GBS_EXPORT_RAW (PCO tensor,
+ * kept[m-1] x d x kept[m]).  idx: host, n x 3 int64 (alpha, p, beta);
+ * out: host, n x 2 FP64 (re, im).  GBS_E_INVAL for an index out of range. */
+int gbs_mps_export_elements(gbs_mps h, int32_t m, int32_t what, const int64_t* idx, int64_t n, double* out);
 
 /* Release every device buffer of the handle. NULL is ignored. */
 void gbs_mps_free(gbs_mps h);

@@ -62,3 +62,52 @@ def build_mps(gamma, d: int, chi: int, dstar: float = 1.0 + 1e-10,
     return OracleMPS(tensors=tens, raw=raw, Q=gs.Q, bases=bases, energies=energies,
                      Lam=[c.Lam for c in gs.cuts], n_e=[c.n_e for c in gs.cuts],
                      eps=eps, entropy=ent, norm_raw=float(nrm))
+
+
+def site_tensor(gamma, d: int, D: int, s: int, dstar: float = 1.0 + 1e-10, first_cap: int = 300):
+    """The PCO tensor of site s (1-based) built on its own (Sec. III.A: each
+    tensor can be generated independently), FP64, unnormalised.
+
+    The Gaussian SVD starts at cut s-1 straight from Gamma (modes a_1..a_{s-2}
+    stand in, uncompressed, for the bond modes of cut s-2; ``gsvd(first=)``),
+    at most at cut ``first_cap``, and one chain step gives cut s.  Past the
+    middle (M - s < s - 1) the same is done for site M+1-s of the
+    mode-reversed state, the tensor's bonds are transposed back, and the
+    Schmidt weights are moved to the bond the forward chain gives them: the
+    forward chain absorbs Lambda_q into the state right of each cut (Eq.
+    SVD3's footnote), the reversed one into the state left of it, so element
+    (alpha, p, beta) is multiplied by prod_q Lambda_{s-1,q}^alpha_q /
+    prod_q Lambda_{s,q}^beta_q = exp(-E_alpha/2 + E_beta/2) with the
+    entanglement energies of the two bond states.  Either way the result
+    equals the full chain's tensor up to a phase per bond mode.
+
+    Returns (A, Q, basis_left, basis_right); Q is the pair matrix with modes
+    ordered (left bond, a_s, right bond).
+    """
+    g = np.asarray(gamma, dtype=np.float64)
+    M = g.shape[0] // 2
+
+    def forward(gg, site):
+        first = max(1, min(site - 1, first_cap))
+        gs = gaussian.gsvd(gg, dstar, first=first, last=site)
+        if site >= 2:
+            bl, el = kept.kept_basis(gs.cuts[site - 1 - first].Lam, D)
+        else:
+            bl, el = [()], np.zeros(1)
+        if site <= M - 1:
+            br, er = kept.kept_basis(gs.cuts[site - first].Lam, D)
+        else:
+            br, er = [()], np.zeros(1)
+        q = gs.Q[site - first]
+        return pco.build_tensor(q, bl, br, d), q, bl, br, el, er
+
+    if M - s >= s - 1:
+        a, q, bl, br, _, _ = forward(g, s)
+        return a, q, bl, br
+    sr = M + 1 - s
+    a, q, bs, bt, es, et = forward(gaussian.reverse_modes(g), sr)
+    # reversed site sr: left bond = cut s here, right bond = cut s-1 here
+    a = a.transpose(2, 1, 0) * np.exp(-0.5 * et)[:, None, None] * np.exp(0.5 * es)[None, None, :]
+    nr, nl = len(bs[0]), len(bt[0])
+    order = list(range(nr + 1, nr + 1 + nl)) + [nr] + list(range(nr))
+    return a, q[np.ix_(order, order)], bt, bs

@@ -233,6 +233,116 @@ def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10, first: int = 1, last: in
     return GSVDResult(Q=Qs, cuts=cuts, n_in=n_in, n_out=n_out)
 
 
+@dataclasses.dataclass
+class TwoSidedCut:
+    """Diagnostics of one cut of the two-sided construction."""
+    D_L: np.ndarray          # Williamson spectrum of the left block, descending
+    D_R: np.ndarray          # Williamson spectrum of the right block, descending
+    offdiag: float           # largest entry of M_L^-1 2 Gamma_LR M_R^-T outside the pair blocks
+    gauge_orth: float        # largest |B_q G_q - diag(P_q, -P_q)| over the pairs after the gauge rotation
+    relation: float          # max |Gamma_LR - M_L [[P,0],[0,-P]] M_R'^T / 2| after gauge fixing
+
+
+def gauge_fixed_right(m_l: np.ndarray, d_l: np.ndarray, m_r: np.ndarray, d_r: np.ndarray, g_lr: np.ndarray):
+    """Fix the per-mode gauge of the right block's symplectic M_R with the
+    off-diagonal block (Sec. II.A, the Gamma_LR relation after Eq. symDiag):
+    find M_R' = M_R G, G a rotation of each mode's (x, p) pair, such that
+    Gamma_LR = M_L [[P, 0], [0, -P]] M_R'^T / 2 with P_qq = sqrt(D_q^2 - 1).
+
+    Returns (M_R', largest entry outside the pair blocks, largest pair
+    residual after the rotation, largest residual of the whole relation).
+    Pairs with P_q below 1e-12 (no entanglement to fix a gauge with) keep
+    M_R's own choice.
+    """
+    nl, nr = len(d_l), len(d_r)
+    k = 2.0 * np.linalg.solve(m_l, g_lr) @ np.linalg.inv(m_r).T      # 2 nl x 2 nr
+    g = np.eye(2 * nr)
+    off = np.abs(k.copy())
+    orth = 0.0
+    for q in range(min(nl, nr)):
+        rows, cols = [q, nl + q], [q, nr + q]
+        off[np.ix_(rows, cols)] = 0.0
+        p = np.sqrt(max(d_l[q] ** 2 - 1.0, 0.0))
+        if p < 1e-12:
+            continue
+        blk = k[np.ix_(rows, cols)]
+        x = np.linalg.solve(blk, np.diag([p, -p]))
+        # the gauge of a mode pair is a rotation of its (x, p): take the
+        # rotation nearest to x, so M_R' stays exactly symplectic (x itself
+        # carries the rounding of blk divided by P_q)
+        th = np.arctan2(x[1, 0] - x[0, 1], x[0, 0] + x[1, 1])
+        gq = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        orth = max(orth, float(np.max(np.abs(blk @ gq - np.diag([p, -p])))))
+        g[np.ix_(cols, cols)] = gq
+    m_r2 = m_r @ g
+    pmat = np.zeros((nl, nr))
+    for q in range(min(nl, nr)):
+        pmat[q, q] = np.sqrt(max(d_l[q] ** 2 - 1.0, 0.0))
+    z = np.zeros_like(pmat)
+    rel = float(np.max(np.abs(g_lr - 0.5 * m_l @ np.block([[pmat, z], [z, -pmat]]) @ m_r2.T)))
+    return m_r2, float(np.max(off)), orth, rel
+
+
+def gsvd_two_sided(gamma: np.ndarray, dstar: float = 1.0 + 1e-10):
+    """The Gaussian SVD chain taken literally from Sec. II.A-B: at each cut
+    both blocks of the current residual are brought to Williamson form, the
+    right block's gauge is fixed with the off-diagonal block, and the next
+    residual is built from the pieces of the Schmidt form: each active left
+    b-mode, relabelled r_q, forms a two-mode squeezed pair with the right
+    b-mode b_{R,q} (D_q, P_q = sqrt(D_q^2 - 1); phi_R of Eq. SVD3), and the
+    right b-modes are mapped back to the physical right modes by M_R'.
+    Q^m comes from the left block as in the one-sided chain.
+
+    A second route to what ``gsvd`` computes from the left blocks alone; the
+    two must agree on spectra and on every Q^m up to a phase per virtual mode.
+    Returns (GSVDResult, list of TwoSidedCut).
+    """
+    g = np.asarray(gamma, dtype=np.float64)
+    N = g.shape[0] // 2
+    res = g.copy()
+    n_prev = 0
+    Qs, cuts, n_in, n_out, diag = [], [], [], [], []
+    for m in range(1, N + 1):
+        n_tot = n_prev + (N - m + 1)
+        n_l = n_prev + 1
+        idx_l = np.r_[0:n_l, n_tot:n_tot + n_l]
+        d_l, m_l = williamson(res[np.ix_(idx_l, idx_l)])
+        u, v = bogoliubov_from_symplectic(m_l)
+        if m == N:
+            Qs.append(paired_q(u, v))
+            n_in.append(n_prev)
+            n_out.append(0)
+            break
+        n_r = N - m
+        idx_r = np.r_[n_l:n_tot, n_tot + n_l:2 * n_tot]
+        d_r, m_r = williamson(res[np.ix_(idx_r, idx_r)])
+        m_r2, off, orth, rel = gauge_fixed_right(m_l, d_l, m_r, d_r, res[np.ix_(idx_l, idx_r)])
+        diag.append(TwoSidedCut(D_L=d_l, D_R=d_r, offdiag=off, gauge_orth=orth, relation=rel))
+        n_e = int(min(np.count_nonzero(d_l >= dstar), n_r))
+        cuts.append(Cut(D=d_l, n_e=n_e, Lam=schmidt_lambda(d_l[:n_e]),
+                        frozen_weight=float(np.sum(schmidt_lambda(d_l[n_e:]) ** 2))))
+        Qs.append(paired_q_left(u, v, n_e))
+        n_in.append(n_prev)
+        n_out.append(n_e)
+        # phi_R in (r, b_R) quadratures, then b_R -> a_R by M_R'
+        pt = np.zeros((n_e, n_r))
+        for q in range(n_e):
+            pt[q, q] = np.sqrt(d_l[q] ** 2 - 1.0)
+        dd = np.diag(d_l[:n_e])
+        dr = np.diag(d_r)
+        cov_b = 0.5 * np.block([[dd, pt, np.zeros((n_e, n_e)), np.zeros((n_e, n_r))],
+                                [pt.T, dr, np.zeros((n_r, n_e)), np.zeros((n_r, n_r))],
+                                [np.zeros((n_e, n_e)), np.zeros((n_e, n_r)), dd, -pt],
+                                [np.zeros((n_r, n_e)), np.zeros((n_r, n_r)), -pt.T, dr]])
+        t = np.eye(2 * (n_e + n_r))
+        ridx = np.r_[n_e:n_e + n_r, 2 * n_e + n_r:2 * (n_e + n_r)]
+        t[np.ix_(ridx, ridx)] = m_r2
+        res = t @ cov_b @ t.T
+        res = 0.5 * (res + res.T)
+        n_prev = n_e
+    return GSVDResult(Q=Qs, cuts=cuts, n_in=n_in, n_out=n_out), diag
+
+
 def reverse_modes(gamma: np.ndarray) -> np.ndarray:
     """Covariance of the same state with the modes numbered M..1 (xxpp kept):
     cut m of the reversed state is cut M - m of the original."""

@@ -98,27 +98,32 @@ def site_marginals(tensors) -> np.ndarray:
     return out
 
 
-def total_photon_distribution(tensors) -> np.ndarray:
-    """Exact distribution of N = sum_m n_m, length (d-1) M + 1, by a transfer
-    sweep that carries one environment per value of N."""
+def total_photon_distribution(tensors, nmax: int | None = None) -> np.ndarray:
+    """Exact distribution of N = sum_m n_m, by a transfer sweep that carries
+    one environment per value of N.  Without nmax: length (d-1) M + 1,
+    normalised to sum 1.  With nmax: P(N) for N <= nmax only (environments of
+    larger N are never formed), divided by the squared norm, so that
+    1 - sum is the probability of N > nmax."""
     M = len(tensors)
     d = tensors[0].shape[1]
-    nmax = (d - 1) * M
+    top = (d - 1) * M if nmax is None else min(nmax, (d - 1) * M)
     env = {0: np.ones((1, 1), dtype=np.complex128)}
     for a in tensors:
         new = {}
         for n, e in env.items():
             for p in range(d):
+                if n + p > top:
+                    break
                 t = a[:, p, :].conj().T @ e @ a[:, p, :]
                 if n + p in new:
                     new[n + p] = new[n + p] + t
                 else:
                     new[n + p] = t
         env = new
-    out = np.zeros(nmax + 1)
+    out = np.zeros(top + 1)
     for n, e in env.items():
         out[n] = np.real(e[0, 0])
-    return out / out.sum()
+    return out / (out.sum() if nmax is None else norm2(tensors))
 
 
 def mean_photons(tensors) -> np.ndarray:

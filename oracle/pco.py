@@ -8,8 +8,8 @@ kept subspace is closed under creation operators, Eq. pass_projector).
 
 Implementation of the paper's algorithms, in its order and notation:
 
-* Algorithm 1: vector set {v_in, v_out, v_ord} of one virtual mode, built in
-  reverse beta order.
+* Algorithm 1: vector set {v_in, v_out, v_ord} of one virtual mode: the pairs
+  of kept states that differ by kappa photons in that mode.
 * Algorithm 3: composition of two vector sets (used by intra-type PCOs).
 * Algorithm 2: cross-type PCO  exp[g r_q^dag l_q'^dag].
 * Algorithm 4: intra-type PCO  exp[g l_q^dag l_q'^dag], q != q' (and the
@@ -21,9 +21,10 @@ Implementation of the paper's algorithms, in its order and notation:
 
 Differences from the printed listings, all readings of the paper:
 * Each PCO is applied out of place (the update reads the coefficients as they
-  were before this PCO).  The printed algorithms update in place and rely on
-  the reverse ordering of Algorithm 1 so that sources are read before they
-  are overwritten; the result is the same.
+  were before this PCO).  The printed algorithms update in place, which needs
+  the vector sets in a particular order so that sources are read before they
+  are overwritten; out of place, neither the order of the vector sets nor the
+  in-place bookkeeping is needed, and the result is the same.
 * The header garbles of Algs. 4 and 5 are read from their update formulas.
 * Factorials are combined in logarithms (virtual occupations can reach a few
   hundred at bonds with one entangled mode); the value is the same.
@@ -47,18 +48,21 @@ def _lgf(n):
 
 
 def vector_set(basis, q):
-    """Algorithm 1: for beta = D-1 down to 0, for kappa = 1..n_{beta,q}:
-    append (alpha, beta, kappa) where |v_alpha> has n_q - kappa photons in q."""
+    """Vector set of virtual mode q (App. B, Alg. 1): every triple
+    (alpha, beta, kappa) with |v_beta> proportional to (l_q^dag)^kappa |v_alpha>,
+    kappa >= 1, both states kept.  The kept set is closed under removing
+    photons, so for each kept beta and each kappa <= n_{beta,q} the state with
+    kappa fewer photons in mode q is kept; its index comes from a lookup of
+    the occupation tuple.  Listed by kappa, then beta (the PCOs here are
+    applied out of place, so no order is needed)."""
     index = {s: i for i, s in enumerate(basis)}
+    occ = np.asarray([s[q] for s in basis], dtype=np.int64)
     vin, vout, vord = [], [], []
-    for beta in range(len(basis) - 1, -1, -1):
-        s = basis[beta]
-        nq = s[q]
-        for kappa in range(1, nq + 1):
-            t = s[:q] + (nq - kappa,) + s[q + 1:]
-            alpha = index[t]                     # "Find index alpha"
-            vin.append(alpha)
-            vout.append(beta)
+    for kappa in range(1, int(occ.max(initial=0)) + 1):
+        for beta in np.nonzero(occ >= kappa)[0]:
+            s = basis[beta]
+            vin.append(index[s[:q] + (s[q] - kappa,) + s[q + 1:]])
+            vout.append(int(beta))
             vord.append(kappa)
     return (np.asarray(vin, dtype=np.int64), np.asarray(vout, dtype=np.int64),
             np.asarray(vord, dtype=np.int64))

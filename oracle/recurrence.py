@@ -17,11 +17,12 @@ import math
 import numpy as np
 
 
-def tensor_by_recurrence(Q, basis_left, basis_right, d):
+def element(Q, n, memo=None) -> complex:
+    """<n| exp(d^dag Q d^dag / 2)|0> for the occupation tuple n over the
+    modes of Q, by the recurrence above (memo: a dict shared between calls
+    on the same Q)."""
     Q = np.asarray(Q, dtype=np.complex128)
-    nl = len(basis_left[0])
-    nr = len(basis_right[0])
-    memo = {}
+    memo = {} if memo is None else memo
 
     def psi(n):
         if n in memo:
@@ -44,9 +45,14 @@ def tensor_by_recurrence(Q, basis_left, basis_right, d):
         memo[n] = val
         return val
 
+    return psi(tuple(int(k) for k in n))
+
+
+def tensor_by_recurrence(Q, basis_left, basis_right, d):
+    memo = {}
     out = np.zeros((len(basis_left), d, len(basis_right)), dtype=np.complex128)
     for a, sa in enumerate(basis_left):
         for p in range(d):
             for b, sb in enumerate(basis_right):
-                out[a, p, b] = psi(tuple(sa) + (p,) + tuple(sb))
+                out[a, p, b] = element(Q, tuple(sa) + (p,) + tuple(sb), memo)
     return out

@@ -28,7 +28,7 @@ EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5, "s
 # Symbols declared in include/gbs_mps.h (checked by the CPU tests).
 EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_build_site", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_noalloc", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
                     "gbs_mps_info",
-                    "gbs_mps_export", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
+                    "gbs_mps_export", "gbs_mps_export_elements", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
                     "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
                     "gbs_server_stats", "gbs_server_reset_stats", "gbs_server_destroy")
 
@@ -110,6 +110,8 @@ def lib():
         L.gbs_mps_info.restype = ctypes.c_int
         L.gbs_mps_export.argtypes = [vp, i32, i32, dp, i64, ctypes.POINTER(i64)]
         L.gbs_mps_export.restype = ctypes.c_int
+        L.gbs_mps_export_elements.argtypes = [vp, i32, i32, dp, i64, dp]
+        L.gbs_mps_export_elements.restype = ctypes.c_int
         L.gbs_mps_free.argtypes = [vp]
         L.gbs_mps_free.restype = None
         L.gbs_last_error.argtypes = []

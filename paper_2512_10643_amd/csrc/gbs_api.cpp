@@ -939,7 +939,8 @@ namespace {
 
 // A single-site build of site s past the middle ran on the mode-reversed
 // state as site M + 1 - s: number its cuts back (cut m there is cut M - m
-// here), transpose its tensor's two bonds, and put its pair matrix in the
+// here), transpose its tensor's two bonds, move the Schmidt weights back to
+// the bond the forward chain puts them on, and put its pair matrix in the
 // mode order (left bond, a_s, right bond) of site s.
 int mirror_single_site(gbs_mps_s* h, hipStream_t st) {
   const int M = h->M, d = h->d, sr = h->single_site, s = M + 1 - sr;
@@ -955,6 +956,35 @@ int mirror_single_site(gbs_mps_s* h, hipStream_t st) {
   cplx64* t;
   HIP_CHECK_RET(dalloc(h->keep, &t, (size_t)std::max(A * d * B, 1L)));
   HIP_CHECK_RET(launch_transpose_bonds(st, h->raw + h->raw_off[sr], A, d, B, t));
+  // The reversed chain absorbs each Schmidt weight Lambda_q into the state
+  // left of its cut, the forward chain into the state right of it (Eq.
+  // SVD3): move them back, element (alpha, p, beta) times
+  // prod Lambda_{s-1}^alpha / prod Lambda_s^beta = exp(-E_alpha/2 + E_beta/2)
+  // with the entanglement energies of the two bond states.
+  auto energies = [&](int cut, std::vector<double>& E) -> int {
+    const int n = h->kept[cut], ne = h->ne[cut];
+    E.assign((size_t)n, 0.0);
+    if (ne == 0) return GBS_OK;
+    std::vector<short> oc((size_t)n * ne);
+    HIP_CHECK_RET(hipMemcpy(oc.data(), h->occ + h->occ_off[cut], oc.size() * sizeof(short), hipMemcpyDeviceToHost));
+    std::vector<double> e(ne);
+    for (int q = 0; q < ne; ++q) e[q] = -2.0 * std::log(h->lam[cut][q]);
+    for (int b = 0; b < n; ++b)
+      for (int q = 0; q < ne; ++q) E[b] += oc[(size_t)b * ne + q] * e[q];
+    return GBS_OK;
+  };
+  std::vector<double> wl, wr;
+  if (int rc = energies(s - 1, wl)) return rc;
+  if (int rc = energies(s, wr)) return rc;
+  for (double& x : wl) x = std::exp(x);  // gauge_scale divides row i by sqrt(wl[i]) and
+  for (double& x : wr) x = std::exp(x);  // multiplies column j by sqrt(wr[j])
+  DevArena wtmp(st);
+  double *wl_d, *wr_d;
+  HIP_CHECK_RET(dalloc(wtmp, &wl_d, wl.size()));
+  HIP_CHECK_RET(dalloc(wtmp, &wr_d, wr.size()));
+  HIP_CHECK_RET(hipMemcpyAsync(wl_d, wl.data(), wl.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(wr_d, wr.data(), wr.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(gauge_scale<cplx64>(st, t, (int)B, d, (int)A, wl_d, wr_d));
   HIP_CHECK_RET(hipStreamSynchronize(st));
   h->keep.release(h->raw);
   h->raw = t;
@@ -1466,6 +1496,38 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
     return put(out.data(), out.size() * sizeof(int32_t));
   }
   return fail(GBS_E_INVAL, "unknown export kind");
+}
+
+int gbs_mps_export_elements(gbs_mps h, int32_t m, int32_t what, const int64_t* idx, int64_t n, double* out) {
+  if (!h || (n > 0 && (!idx || !out))) return fail(GBS_E_INVAL, "NULL argument");
+  if (n < 0) return fail(GBS_E_INVAL, "n < 0");
+  if (what != GBS_EXPORT_TENSOR && what != GBS_EXPORT_RAW) return fail(GBS_E_INVAL, "elements of TENSOR or RAW only");
+  if (m < 1 || m > h->M) return fail(GBS_E_INVAL, "site out of range");
+  if (what == GBS_EXPORT_TENSOR && h->single_site) return fail(GBS_E_INVAL, "the handle holds one site's PCO tensor only");
+  if (what == GBS_EXPORT_RAW && !h->raw) return fail(GBS_E_INVAL, "raw tensors not kept (build with GBS_KEEP_RAW)");
+  if (what == GBS_EXPORT_RAW && h->single_site && m != h->single_site)
+    return fail(GBS_E_INVAL, "the handle holds the tensor of another site");
+  const int d = h->d;
+  const long a = what == GBS_EXPORT_RAW ? h->kept[m - 1] : h->bond[m - 1];
+  const long b = what == GBS_EXPORT_RAW ? h->kept[m] : h->bond[m];
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t i = idx[3 * k], p = idx[3 * k + 1], j = idx[3 * k + 2];
+    if (i < 0 || i >= a || p < 0 || p >= d || j < 0 || j >= b) return fail(GBS_E_INVAL, "element index out of range");
+    const long e = (i * d + p) * b + j;
+    if (what == GBS_EXPORT_RAW || h->esz == sizeof(cplx64)) {
+      const cplx64* src = what == GBS_EXPORT_RAW ? h->raw + h->raw_off[m] : (const cplx64*)h->tens + h->toff[m];
+      cplx64 v;
+      HIP_CHECK_RET(hipMemcpy(&v, src + e, sizeof v, hipMemcpyDeviceToHost));
+      out[2 * k] = v.re;
+      out[2 * k + 1] = v.im;
+    } else {
+      cplx32 v;
+      HIP_CHECK_RET(hipMemcpy(&v, (const cplx32*)h->tens + h->toff[m] + e, sizeof v, hipMemcpyDeviceToHost));
+      out[2 * k] = v.re;
+      out[2 * k + 1] = v.im;
+    }
+  }
+  return GBS_OK;
 }
 
 void gbs_mps_free(gbs_mps h) {

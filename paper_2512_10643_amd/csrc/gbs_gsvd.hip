@@ -1,15 +1,22 @@
 // Input validation and the iterative Gaussian SVD (Sec. II.A-B, App. A), FP64.
 //
 // Cuts run in order on the stream because each consumes the residual the
-// previous one produced.  Williamson form of the left block L = (r_{m-1}, a_m):
-//   2 Gamma_LL = L L^T (Cholesky), A = L^T Omega L (antisymmetric),
-//   B = A^T A (symmetric, eigenvalues D_q^2 twice) by Jacobi rotations,
-//   symplectic pairs (u, v = -A u / D) from the sorted eigenvectors (within
-//   a cluster of equal eigenvalues by Gram-Schmidt), and
-//   S = L [u.., v..] diag(D, D)^(-1/2).
-// Bogoliubov matrices follow from Eq. MUV, the paired form of the local
-// state from the regularised Q_L of App. A, and the next residual from the
-// b-mode quadrature map T = -S^T Omega restricted to the active modes.
+// previous one produced.  Williamson form of the left block L = (r_{m-1}, a_m)
+// (stage 1, one workgroup):
+//   2 Gamma_LL = L L^T in closed form (the r modes are already in normal
+//   form: sqrt(D) on their pairs, a 2x2 Cholesky for the new mode),
+//   A = L^T Omega L formed entry by entry (pair entries +-D_k plus the new
+//   mode's rank-2 term), reduced to skew-tridiagonal form by Householder
+//   reflections; its singular values D are the positive eigenvalues of the
+//   zero-diagonal symmetric tridiagonal matrix with the same off-diagonal,
+//   found by Sturm-count bisection on each unreduced block; eigenvectors by
+//   inverse iteration, orthonormalised within clusters of close eigenvalues;
+//   their even and odd entries are the real Schur pairs (u, v), back-
+//   transformed by the reflectors, and S = L [u.., v..] diag(D, D)^(-1/2).
+// Stage 2 (a second workgroup, beside the next cut's stage 1): Bogoliubov
+// matrices from Eq. MUV, the paired form of the local state from the
+// regularised Q_L of App. A, and the next residual from the b-mode
+// quadrature map T = -S^T Omega restricted to the active modes.
 #include "gbs_gsvd.h"
 
 #include <algorithm>
@@ -17,18 +24,6 @@
 namespace {
 
 __device__ inline void wg_sync() { __syncthreads(); }
-
-// Round-robin pair for parallel Jacobi.
-__device__ inline void rr_pair_s(int npad, int s, int i, int& p, int& q) {
-  int m = npad - 1;
-  if (i == 0) {
-    p = 0;
-    q = 1 + (s % m);
-  } else {
-    p = 1 + ((s + i) % m);
-    q = 1 + (((s - i) % m + m) % m);
-  }
-}
 
 // Parallel reduction of one value per thread into red[0] (block of 1024).
 __device__ double wg_sum(double x, double* red) {

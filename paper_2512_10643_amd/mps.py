@@ -108,6 +108,16 @@ class GaussianMPS:
         d["entropy"] = list(ent)
         return d
 
+    def export_elements(self, m: int, what: str, idx) -> np.ndarray:
+        """gbs_mps_export_elements: complex values of the elements
+        (alpha, p, beta) listed in idx (n x 3) of the "tensor" or "raw"
+        tensor of site m."""
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 3))
+        out = np.empty((idx.shape[0], 2), dtype=np.float64)
+        check(lib().gbs_mps_export_elements(self._h, int(m), _lib.EXPORT[what], ctypes.c_void_p(idx.ctypes.data),
+                                            idx.shape[0], ctypes.c_void_p(out.ctypes.data)))
+        return out[:, 0] + 1j * out[:, 1]
+
     def export(self, m: int, what: str) -> np.ndarray:
         """gbs_mps_export: tensor / raw (kept[m-1] x d x kept[m]) / Q / basis /
         lambda / svals of site or cut m, or the (M+1) x 2 parity-sector sizes

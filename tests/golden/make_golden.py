@@ -5,6 +5,7 @@ workload with, for the oracle's normalised MPS:
   * eps and n_e per cut, Lambda spectra per cut,
   * amplitudes <n|psi> for seeded low-photon patterns (even totals) + vacuum,
   * exact single-mode photon-number marginals P_m(p),
+  * the exact distribution of the total photon number N for N <= 48,
   * shots of the counter-based sampler (seed 31) with every site whose draw
     lies within 1e-3 of a decision boundary (shot, site, distance).
 
@@ -52,6 +53,7 @@ def main(name):
     pats = patterns(w.M, w.d, 96, 2024)
     amps = mps.amplitudes(o.tensors, pats)
     marg = mps.site_marginals(o.tensors)
+    ptot = mps.total_photon_distribution(o.tensors, nmax=48)
     shots, seed = 600, 31
     smp, margin = mps.sample_counter(o.tensors, shots, seed)
     ties = [[int(s), int(m) + 1, float(margin[s, m])] for s, m in zip(*np.nonzero(margin < 1e-3))]
@@ -59,7 +61,8 @@ def main(name):
                counter_samples=dict(seed=seed, shots=shots, samples=smp.tolist(), near_ties=ties),
                n_e=o.n_e, eps=o.eps, lam=[list(map(float, l)) for l in o.Lam],
                patterns=pats, amp_re=[float(a.real) for a in amps], amp_im=[float(a.imag) for a in amps],
-               marginals=marg.tolist(), mean_photons=float(np.sum(marg @ np.arange(w.d))))
+               marginals=marg.tolist(), mean_photons=float(np.sum(marg @ np.arange(w.d))),
+               total_photons=ptot.tolist())
     with open(os.path.join(HERE, f"{name}_oracle.json"), "w") as f:
         json.dump(res, f)
     print(f"{name}: oracle build {t1 - t0:.1f}s, total {time.time() - t0:.1f}s")

@@ -419,8 +419,8 @@ def test_bond_dimension_from_target_error(torch_cuda, eps):
 
 def _oracle_site_inputs(w, m, chi):
     """The oracle's own Q^m and kept bases of cuts m-1 and m (Gaussian SVD
-    started at cut m-1 straight from Gamma, as a single-site build does, and
-    best-first enumeration; no GPU data)."""
+    started at cut m-1 straight from Gamma, as a single-site build does, for
+    a site before the middle; best-first enumeration; no GPU data)."""
     from oracle import gaussian as og, kept as ok
     first = max(1, min(m - 1, 300))  # the widest first block the library takes is 600 (cut 300)
     gs = og.gsvd(w.gamma, first=first, last=m)
@@ -438,23 +438,17 @@ def _min_lambda(w, m):
     return min(float(np.min(x)) for x in lams) if lams else 1.0
 
 
-def _check_single_site(torch_cuda, w, m, D, d):
-    """A single-site build against the oracle's build of the same site by the
-    same route: past the middle (M - m < m - 1), site M + 1 - m of the
-    mode-reversed state with the tensor's bonds transposed."""
-    from oracle import gaussian as og, pco as opco
+def _check_single_site(torch_cuda, w, m, D, d, tol=1e-10):
+    """A single-site build against the oracle's build of the same site alone
+    (oracle.build.site_tensor: the same route, restart at cut m-1, mirrored
+    past the middle with the Schmidt weights moved back).  The two Williamson
+    solvers choose their own phase for each Bogoliubov mode, so the element
+    ratio must factorise into one unit-modulus factor per bond mode raised to
+    its occupation (fitted from singly occupied bond states); magnitudes must
+    agree element by element to `tol` (relative to max |A|)."""
+    import mode_phases
     from paper_2512_10643_amd import mps as gmps
-    if w.M - m < m - 1:
-        wr = types.SimpleNamespace(gamma=og.reverse_modes(w.gamma), M=w.M)
-        q, br, bl = _oracle_site_inputs(wr, w.M + 1 - m, D)
-        ref = opco.build_tensor(q, br, bl, d).transpose(2, 1, 0)
-        # pair matrix in the order (left bond, a_m, right bond) of site m
-        nr, nl = len(br[0]), len(bl[0])
-        order = list(range(nr + 1, nr + 1 + nl)) + [nr] + list(range(nr))
-        q = q[np.ix_(order, order)]
-    else:
-        q, bl, br = _oracle_site_inputs(w, m, D)
-        ref = opco.build_tensor(q, bl, br, d)
+    ref, q, bl, br = obuild.site_tensor(w.gamma, d, D, m)
     g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
     h = gmps.build_site(g, d, D, m)
     try:
@@ -473,7 +467,18 @@ def _check_single_site(torch_cuda, w, m, D, d):
     assert qg.shape == q.shape
     na = len(bl[0])
     assert abs(abs(qg[na, na]) - abs(q[na, na])) <= 1e-10
-    return np.max(np.abs(np.abs(raw) - np.abs(ref))), np.max(np.abs(ref)), t
+    amax = float(np.max(np.abs(ref)))
+    err = float(np.max(np.abs(np.abs(raw) - np.abs(ref))))
+    # phases: elements above 1e-3 of the largest carry a relative error of at
+    # most tol * 1e3 from the magnitude bound
+    f = mode_phases.bond_mode_factors(ref, raw, bl, br, rel=1e-3)
+    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); bond-mode factors: "
+         f"{f['checked']} elements, max |ratio - factor| = {f['err']:.2e}, max ||factor| - 1| = {f['modulus']:.2e}; "
+         f"gsvd {t:.2f} ms")
+    assert err <= tol * max(1.0, amax)
+    assert f["checked"] > 0
+    assert f["err"] <= 1e3 * tol * 10 and f["modulus"] <= 1e3 * tol * 10
+    return raw, ref, bl, br
 
 
 def test_single_site_tensor_matches_oracle(torch_cuda):
@@ -484,9 +489,7 @@ def test_single_site_tensor_matches_oracle(torch_cuda):
     _say("case: c3 central tensor alone, site 72, D=300, d=8")
     from paper_2512_10643_amd import mps as gmps, GbsError
     w, m, D, d = W.workload("c3"), 72, 300, 8
-    err, amax, t = _check_single_site(torch_cuda, w, m, D, d)
-    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
-    assert err <= 1e-10 * max(1.0, amax)
+    _check_single_site(torch_cuda, w, m, D, d)
     g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
     h = gmps.build_site(g, d, D, m)
     with pytest.raises(GbsError):
@@ -501,9 +504,7 @@ def test_single_site_every_position_c2(torch_cuda, m):
     many modes in vacuum (one large cluster of equal symplectic eigenvalues)."""
     _say(f"case: c2 single site {m}, D=24, d=6")
     w = W.workload("c2")
-    err, amax, t = _check_single_site(torch_cuda, w, m, 24, 6)
-    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
-    assert err <= 1e-10 * max(1.0, amax)
+    _check_single_site(torch_cuda, w, m, 24, 6)
 
 
 def test_single_site_past_the_widest_first_block(torch_cuda):
@@ -511,27 +512,38 @@ def test_single_site_past_the_widest_first_block(torch_cuda):
     (600 wide, the most one workgroup takes) and the chain runs from there."""
     _say("case: c5 single site 400, D=64, d=4")
     w = W.workload("c5")
-    err, amax, t = _check_single_site(torch_cuda, w, 400, 64, 4)
     # Both cuts hold modes just above the frozen threshold (D - 1 ~ 1e-9,
     # Lambda ~ 2e-5).  D carries ~1e-12 of absolute FP64 precision after a
     # 600-wide Williamson step and 100 chain steps, so such a Lambda is known
     # to ~1e-12 / (4 Lambda) (from Lambda^2 = (D - 1) / (D + 1)), and elements
     # linear in it carry that error.
     tol = 1e-10 + 1e-12 / (4.0 * _min_lambda(w, 400))
-    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}, bound {tol:.2e}); gsvd {t:.2f} ms")
-    assert err <= tol * max(1.0, amax)
+    _say(f"  magnitude bound {tol:.2e}")
+    _check_single_site(torch_cuda, w, 400, 64, 4, tol=tol)
 
 
 @pytest.mark.parametrize("m", [73, 120, 144])
 def test_single_site_past_the_middle(torch_cuda, m):
     """C3 sites past the middle, built as sites 72, 25 and 1 of the
     mode-reversed state (first Gaussian SVD block at most 144 wide), with the
-    tensor's bonds transposed and the cuts numbered back."""
+    tensor's bonds transposed, the cuts numbered back and the Schmidt weights
+    moved back to the right of each cut.  Against the oracle's mirrored build
+    (complex, up to bond-mode phases) and against the oracle's forward build
+    of the same site (restart at cut m-1 on the state as given, whose first
+    block is 2(m-1) wide): equal magnitudes, so tensors built on either side
+    of the middle fit together (Sec. III.A)."""
     _say(f"case: c3 single site {m}, D=64, d=4")
+    from oracle import gaussian as og, kept as ok, pco as opco
     w = W.workload("c3")
-    err, amax, t = _check_single_site(torch_cuda, w, m, 64, 4)
-    _say(f"  max ||A_gpu| - |A_oracle|| = {err:.3e} (max |A| = {amax:.3e}); gsvd {t:.2f} ms")
-    assert err <= 1e-10 * max(1.0, amax)
+    raw, ref, bl, br = _check_single_site(torch_cuda, w, m, 64, 4)
+    gs = og.gsvd(w.gamma, first=m - 1, last=m)
+    fbl = ok.kept_basis(gs.cuts[0].Lam, 64)[0]
+    fbr = ok.kept_basis(gs.cuts[1].Lam, 64)[0] if m < w.M else [()]
+    assert fbl == list(bl) and fbr == list(br)
+    fwd = opco.build_tensor(gs.Q[1], fbl, fbr, 4)
+    err = float(np.max(np.abs(np.abs(raw) - np.abs(fwd))))
+    _say(f"  against the forward build: max ||A_gpu| - |A_fwd|| = {err:.3e}")
+    assert err <= 1e-10 * max(1.0, float(np.max(np.abs(fwd))))
 
 
 def test_single_site_large_d_elements_are_hafnians(torch_cuda):
@@ -569,32 +581,59 @@ def test_single_site_large_d_elements_are_hafnians(torch_cuda):
     assert worst <= 1e-10
 
 
-def test_single_site_beyond_lds_heap(torch_cuda):
+@pytest.mark.parametrize("d", [4, 10])
+def test_single_site_beyond_lds_heap(torch_cuda, d):
     """D=10^4 (the paper's largest bond), where the kept-basis enumeration
-    keeps its heap and sort buffer in global memory: the kept bases of both
-    cuts equal the oracle's enumeration and the PCO gather produces every
-    element of even total photon number (five squeezed modes among 144)."""
-    _say("case: few-squeezed central tensor alone, site 72, D=10000, d=4")
-    from oracle import gaussian as og, kept as ok
+    keeps its heap and sort buffer in global memory, at d = 4 and d = 10: the
+    kept bases of both cuts equal the oracle's enumeration, the PCO gather
+    produces every element of even total photon number (five squeezed modes
+    among 144), and sampled element values equal the oracle's per-element
+    recurrence on its own Q^m (magnitudes: the bond modes carry each side's
+    own phases); odd elements are exactly zero."""
+    _say(f"case: few-squeezed central tensor alone, site 72, D=10000, d={d}")
+    from oracle import recurrence as orec
     from paper_2512_10643_amd import mps as gmps
-    w, m, D, d = W.few_squeezed(), 72, 10_000, 4
-    gs = og.gsvd(w.gamma, first=m - 1, last=m)
-    bl, br = ok.kept_basis(gs.cuts[0].Lam, D)[0], ok.kept_basis(gs.cuts[1].Lam, D)[0]
+    w, m, D = W.few_squeezed(), 72, 10_000
+    q, bl, br = _oracle_site_inputs(w, m, D)
     g = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
     h = gmps.build_site(g, d, D, m)
-    inf = h.info()
-    _say(f"  kept {inf['bond'][m - 1]} x {d} x {inf['bond'][m]}; kept {inf['t_kept_ms']:.1f} ms, "
-         f"pco {inf['t_pco_ms']:.1f} ms, {inf['pco_updates']} elements")
-    assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
-    assert [tuple(r) for r in h.export(m, "basis")] == list(br)
-    par_l = np.array([sum(x) % 2 for x in bl])
-    par_r = np.array([sum(x) % 2 for x in br])
-    even = sum(int(np.sum((par_l[:, None] + p + par_r[None, :]) % 2 == 0)) for p in range(d))
-    assert inf["pco_updates"] == even - 1  # every even element but the vacuum one
-    h.free()
+    try:
+        inf = h.info()
+        _say(f"  kept {inf['bond'][m - 1]} x {d} x {inf['bond'][m]}; kept {inf['t_kept_ms']:.1f} ms, "
+             f"pco {inf['t_pco_ms']:.1f} ms, {inf['pco_updates']} elements")
+        assert [tuple(r) for r in h.export(m - 1, "basis")] == list(bl)
+        assert [tuple(r) for r in h.export(m, "basis")] == list(br)
+        par_l = np.array([sum(x) % 2 for x in bl])
+        par_r = np.array([sum(x) % 2 for x in br])
+        even = sum(int(np.sum((par_l[:, None] + p + par_r[None, :]) % 2 == 0)) for p in range(d))
+        assert inf["pco_updates"] == even - 1  # every even element but the vacuum one
+        rng = np.random.default_rng(11 + d)
+        idx = np.stack([rng.integers(len(bl), size=200), rng.integers(d, size=200), rng.integers(len(br), size=200)], 1)
+        got = h.export_elements(m, "raw", idx)
+    finally:
+        h.free()
+    memo, worst, amax, n_even = {}, 0.0, 0.0, 0
+    for (i, p, j), v in zip(idx, got):
+        n = tuple(bl[i]) + (int(p),) + tuple(br[j])
+        if sum(n) % 2:
+            assert v == 0
+            continue
+        ref = orec.element(q, n, memo)
+        worst = max(worst, abs(abs(v) - abs(ref)))
+        amax = max(amax, abs(ref))
+        n_even += 1
+    _say(f"  {n_even} sampled even elements: max ||A| - |A_rec|| = {worst:.3e} (max |A| {amax:.3e})")
+    assert n_even >= 50 and worst <= 1e-10 * max(1.0, amax)
 
 
 # ---------------------------------------------------------- full size (C3)
+
+def _state_distance(h1, h2):
+    """||psi1 - psi2|| from FP64 transfer overlaps: by Cauchy-Schwarz no
+    amplitude of the two states differs by more."""
+    d2 = h1.overlap(h1).real + h2.overlap(h2).real - 2 * h1.overlap(h2).real
+    return float(np.sqrt(max(d2, 0.0)))
+
 
 def _golden(name):
     import json
@@ -627,13 +666,18 @@ def test_c3_full_size_against_oracle_reference(torch_cuda, precision):
     if precision == "fp64":
         assert err <= 1e-10
     else:
-        assert rel <= 1e-3
         # fidelity of the FP32 build against the FP64 build (which matches the
         # oracle's amplitudes to <= 1e-10 above)
         h64 = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
         f = h.fidelity(h64)
         _say(f"  1 - F(fp32 build, fp64 build) = {1 - f:.3e}")
         assert 1 - f <= 1e-6
+        # every amplitude error is at most the norm of the difference of the
+        # two states (both unit norm, vacuum amplitude real > 0), plus the
+        # FP64 build's own distance to the oracle
+        dist = _state_distance(h, h64)
+        _say(f"  max |amp_fp32 - amp_oracle| = {err:.3e} <= ||psi_fp32 - psi_fp64|| + 1e-10 = {dist + 1e-10:.3e}")
+        assert err <= dist + 1e-10
         # both states carry unit norm (the FP32 one up to the rounding of site 1)
         assert abs(h64.overlap(h64) - 1) <= 1e-10
         assert abs(h.overlap(h) - 1) <= 1e-6
@@ -667,7 +711,9 @@ def test_c3_sampler_matches_counter_oracle_shot_by_shot(torch_cuda):
 
 def test_c3_sampling_tvd_1e6_shots(torch_cuda):
     """10^6 FP32-MFMA samples at C3: per-mode marginal TVD against the oracle's
-    exact marginals <= 1e-3 (and within 5x the statistical floor)."""
+    exact marginals <= 1e-3 (and within 5x the statistical floor), and the
+    total photon number's histogram against the oracle's exact distribution
+    by a chi-squared test (p > 1e-3)."""
     _say("case: c3 sampling, 1e6 shots, fp32")
     g = _golden("c3")
     w = W.workload("c3")
@@ -688,6 +734,24 @@ def test_c3_sampling_tvd_1e6_shots(torch_cuda):
     _say(f"  max per-mode TVD = {worst:.2e} (max TVD/floor {worst_ratio:.2f}); "
          f"mean photons {mean:.4f} vs exact {g['mean_photons']:.4f}")
     h.free()
+    # total photon number: chi-squared goodness of fit against the oracle's
+    # exact distribution (even N only; bins with an expected count below 5,
+    # and N beyond the stored range, merged into one tail bin)
+    from scipy.stats import chi2
+    ptot = np.array(g["total_photons"])
+    cnt = np.bincount(s.sum(1), minlength=len(ptot))
+    obs, exp_ = [], []
+    for n in range(0, len(ptot), 2):
+        if shots * ptot[n] >= 5:
+            obs.append(int(cnt[n]))
+            exp_.append(shots * ptot[n])
+    obs.append(shots - sum(obs))
+    exp_.append(shots - sum(exp_))
+    obs, exp_ = np.array(obs, dtype=float), np.array(exp_)
+    stat = float(np.sum((obs - exp_) ** 2 / exp_))
+    pval = float(chi2.sf(stat, len(obs) - 1))
+    _say(f"  total photons: chi2 = {stat:.2f} on {len(obs) - 1} dof, p = {pval:.3f}")
+    assert exp_[-1] >= 5 and pval > 1e-3
 
 
 def test_bf16x3_contractions_c2(torch_cuda):
@@ -763,3 +827,42 @@ def test_c5_gaussian_chain_against_oracle(torch_cuda):
     s = h.sample(2000, seed=11)
     assert int((s.sum(1) % 2).abs().sum()) == 0
     h.free()
+
+
+def test_c5_reduced_precision_builds_against_fp64(torch_cuda):
+    """C5 (M=1024, d=4, chi=512, 32 brick-wall layers) built in FP32 and in
+    split-BF16x3 against the FP64 build of the same state on the GPU (the FP64
+    path matches the oracle to 1e-10 at C1-C3, and its Gaussian chain matches
+    the oracle's stored C5 values, test above): 1 - F <= 1e-6 for both; every
+    amplitude of seeded patterns within ||psi - psi_64|| of the FP64 one (no
+    amplitude can differ by more); and each reduced-precision transfer
+    <psi_64|psi_32> within
+    16 M 2^-24 of the FP64 transfer (FP32 accumulation over M sites, a few
+    roundings of 2^-24 per site)."""
+    _say("case: c5 fp32 and bf16x3 builds and transfers vs fp64 (M=1024, d=4, chi=512)")
+    w = W.workload("c5")
+    h64 = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    pats = low_patterns(w.M, w.d, 6)[:257]
+    ref = gpu_amps(torch_cuda, h64, pats)
+    out = {}
+    for prec in ("fp32", "bf16x3"):
+        h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision=prec)
+        f = h.fidelity(h64)
+        amp = gpu_amps(torch_cuda, h, pats)
+        err = float(np.max(np.abs(amp - ref)))
+        rel = float(np.max(np.abs(amp - ref) / np.abs(ref)))
+        dist = _state_distance(h, h64)
+        out[prec] = (1 - f, err, h)
+        _say(f"  {prec}: 1 - F = {1 - f:.3e}; {len(pats)} amplitudes: max |delta| {err:.3e} (relative {rel:.2e}), "
+             f"||psi - psi_64|| = {dist:.3e}; max bond {h.info()['max_bond']}")
+        assert 1 - f <= 1e-6
+        assert err <= dist + 1e-12
+    ov = h64.overlap(out["fp32"][2])
+    bound = 16 * w.M * 2.0 ** -24
+    for prec in ("fp32", "bf16x3"):
+        e = abs(h64.overlap(out["fp32"][2], precision=prec) - ov)
+        _say(f"  transfer <fp64|fp32> in {prec}: |error| = {e:.3e} (bound {bound:.2e})")
+        assert e <= bound
+    for _, _, h in out.values():
+        h.free()
+    h64.free()

@@ -39,13 +39,32 @@ def _pin_suite():
     lam = np.array([0.6, 0.5, 0.2])
     st, _ = K.kept_basis(lam, 20)
     e = -2 * np.log(lam)
-    allst = sorted(itertools.product(range(10), repeat=3), key=lambda s: (float(np.dot(s, e)), s))
+    # ties in energy ordered by descending occupation tuple (the kept-basis tie reading)
+    allst = sorted(itertools.product(range(10), repeat=3), key=lambda s: (float(np.dot(s, e)), tuple(-k for k in s)))
     ok &= st == [tuple(s) for s in allst[:20]]
+    lam = np.array([0.5, 0.5, 0.25])        # many ties in energy
+    st, _ = K.kept_basis(lam, 12)
+    e = -2 * np.log(lam)
+    allst = sorted(itertools.product(range(8), repeat=3), key=lambda s: (float(np.dot(s, e)), tuple(-k for k in s)))
+    ok &= st == [tuple(s) for s in allst[:12]]
     # norm over all patterns
     w2 = W.custom(4, 3, 8, (0.3, 0.9), "haar", 11)
     o2 = build.build_mps(w2.gamma, w2.d, w2.chi)
     allp = list(itertools.product(range(w2.d), repeat=w2.M))
     ok &= abs(np.sum(np.abs(P.amplitudes(o2.tensors, allp)) ** 2) - 1) < 1e-12
+    # fidelity of two products of squeezed vacua: prod 1/cosh(r1 - r2)
+    r1, r2 = (0.3, 0.6), (0.5, 0.2)
+    t1 = build.build_mps(W.gamma_of_circuit(np.array(r1), np.eye(2, dtype=complex)), 40, 1).tensors
+    t2 = build.build_mps(W.gamma_of_circuit(np.array(r2), np.eye(2, dtype=complex)), 40, 1).tensors
+    ok &= abs(P.fidelity(t1, t2) - np.prod(1 / np.cosh(np.subtract(r1, r2)))) < 1e-10
+    # one truncated bond loses exactly the dropped Schmidt weight
+    rng = np.random.default_rng(5)
+    t = P.normalize([rng.standard_normal((1, 4, 4)) + 1j * rng.standard_normal((1, 4, 4)),
+                     rng.standard_normal((4, 4, 1)) + 1j * rng.standard_normal((4, 4, 1))])
+    psi = np.array([[P.amplitude(t, (a, b)) for b in range(4)] for a in range(4)])
+    sv = np.linalg.svd(psi, compute_uv=False)
+    tt, _ = P.svd_truncate(t, 2)
+    ok &= abs((1 - P.fidelity(t, tt)) - np.sum(sv[2:] ** 2)) < 1e-10
     return bool(ok)
 
 
@@ -109,10 +128,25 @@ def _mut_kept_energy_sign(lam, D):
     return _orig["kept_basis"](1.0 / np.sqrt(np.asarray(lam)), D) if len(lam) else _orig["kept_basis"](lam, D)
 
 
+def _mut_kept_ties_ascending(lam, D):
+    st, en = _orig["kept_basis"](lam, D + 64)
+    order = sorted(range(len(st)), key=lambda i: (round(float(en[i]), 12), st[i]))[:D]
+    return [st[i] for i in order], np.asarray([en[i] for i in order])
+
+
 def _mut_normalize_no_phase(tensors):
     out = [a.copy() for a in tensors]
     out[0] = out[0] / np.sqrt(P.norm2(out)) * 1j
     return out
+
+
+def _mut_fidelity_sqrt(t1, t2):
+    o = P.overlap(t1, t2)
+    return float(abs(o) / np.sqrt(np.real(P.overlap(t1, t1)) * np.real(P.overlap(t2, t2))))
+
+
+def _mut_truncate_ignores_chi(tensors, chi, tol=1e-14):
+    return _orig["svd_truncate"](tensors, 1 << 30, tol)
 
 
 _orig = {
@@ -124,6 +158,7 @@ _orig = {
     "dup_pco_right": pco.dup_pco_right,
     "cross_pco": pco.cross_pco,
     "kept_basis": K.kept_basis,
+    "svd_truncate": P.svd_truncate,
 }
 
 MUTANTS = [
@@ -137,7 +172,10 @@ MUTANTS = [
     (pco, "cross_pco", _mut_cross_conj),
     (pco, "phys_dup_pco", _mut_phys_dup_dropped),
     (K, "kept_basis", _mut_kept_energy_sign),
+    (K, "kept_basis", _mut_kept_ties_ascending),
     (P, "normalize", _mut_normalize_no_phase),
+    (P, "fidelity", _mut_fidelity_sqrt),
+    (P, "svd_truncate", _mut_truncate_ignores_chi),
 ]
 
 

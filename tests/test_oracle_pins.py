@@ -318,6 +318,20 @@ def test_mean_photon_number_approaches_gaussian_value():
     assert got == pytest.approx(w.mean_photons, rel=2e-3)
 
 
+def test_total_photon_distribution_against_brute_force():
+    w = W.custom(4, 3, 8, (0.3, 0.9), "haar", 11)
+    o = build.build_mps(w.gamma, w.d, w.chi)
+    pats = list(itertools.product(range(w.d), repeat=w.M))
+    prob = np.abs(P.amplitudes(o.tensors, pats)) ** 2
+    want = np.zeros((w.d - 1) * w.M + 1)
+    for p, x in zip(pats, prob):
+        want[sum(p)] += x
+    assert np.allclose(P.total_photon_distribution(o.tensors), want / want.sum(), atol=1e-14)
+    capped = P.total_photon_distribution(o.tensors, nmax=4)   # the oracle's MPS has unit norm
+    assert capped.shape == (5,) and np.allclose(capped, want[:5], atol=1e-14)
+    assert np.all(want[1::2] < 1e-28)                          # parity: odd totals vanish
+
+
 def test_exact_marginals_against_brute_force():
     w = W.custom(5, 3, 8, (0.3, 0.9), "haar", 11)
     o = build.build_mps(w.gamma, w.d, w.chi)
@@ -519,50 +533,143 @@ def test_reversed_modes_mirror_the_cuts(name):
 
 
 @pytest.mark.parametrize("name,chi", [("c1", 16), ("c2", 24)])
-def test_mirrored_site_tensor_is_a_diagonal_gauge_of_the_chain_tensor(name, chi):
-    """P4f: the tensor of site s built on the reversed state (site M+1-s there)
-    and transposed is the chain's tensor of site s in another gauge: the two
-    label each bond by Fock states of the two partner Bogoliubov modes of the
-    same Schmidt pair, so A_rev[beta, p, alpha] = A[alpha, p, beta] u_alpha v_beta
-    with u, v products of one factor per bond mode and photon (weights and
-    phases).  Checked: the ratio factorises as prod_q x_q^{alpha_q} y_q^{beta_q}
-    with the factors fitted from single occupations."""
+def test_site_tensor_built_alone_is_the_chain_tensor_up_to_mode_phases(name, chi):
+    """P4f: the tensor of every site built on its own (restart at cut s-1;
+    past the middle, site M+1-s of the reversed state, transposed, with the
+    Schmidt weights moved back to the bond right of each cut) equals the
+    chain's tensor up to a phase per bond mode: the ratio factorises into one
+    unit-modulus factor per bond mode, raised to its occupation, and |A|
+    agrees element by element within the weight the chain drops below D*."""
+    import mode_phases
     w = W.workload(name)
     d, M = w.d, w.M
     ch = G.gsvd(w.gamma)
-    gr = G.reverse_modes(w.gamma)
-    for s in range(2, M):
-        sr = M + 1 - s
-        first = max(1, sr - 1)
-        rs = G.gsvd(gr, first=first, last=sr)
-        bl = K.kept_basis(ch.cuts[s - 2].Lam, chi)[0]
-        br = K.kept_basis(ch.cuts[s - 1].Lam, chi)[0]
-        assert K.kept_basis(rs.cuts[sr - 1 - first].Lam, chi)[0] == br
-        a_ch = pco.build_tensor(ch.Q[s - 1], bl, br, d)
-        a_rv = pco.build_tensor(rs.Q[sr - first], br, bl, d).transpose(2, 1, 0)
-        big = np.abs(a_ch) > 1e-8 * np.max(np.abs(a_ch))
-        ratio = np.where(big, a_rv / np.where(big, a_ch, 1), 0)
-        assert ratio[0, 0, 0] == pytest.approx(1.0)          # both vacuum elements are 1
-        x, y = {}, {}
-        for i, sa in enumerate(bl):
-            for j, sb in enumerate(br):
-                p = next((p for p in range(d) if big[i, p, j]), None)
-                if p is None:
-                    continue
-                if sum(sa) == 1 and sum(sb) == 0:
-                    x.setdefault(sa.index(1), ratio[i, p, j])
-                if sum(sb) == 1 and sum(sa) == 0:
-                    y.setdefault(sb.index(1), ratio[i, p, j])
-        checked = 0
-        for i, sa in enumerate(bl):
-            for j, sb in enumerate(br):
-                ql = [q for q in range(len(sa)) if sa[q]]
-                qr = [q for q in range(len(sb)) if sb[q]]
-                if any(q not in x for q in ql) or any(q not in y for q in qr):
-                    continue
-                f = np.prod([x[q] ** sa[q] for q in ql]) * np.prod([y[q] ** sb[q] for q in qr])
-                for p in range(d):
-                    if big[i, p, j]:
-                        assert abs(ratio[i, p, j] / f - 1) < 1e-6, (s, sa, p, sb)
-                        checked += 1
-        assert checked > 0, s
+    mirrored = 0
+    for s in range(1, M + 1):
+        a, q, bl, br = build.site_tensor(w.gamma, d, chi, s)
+        cbl = K.kept_basis(ch.cuts[s - 2].Lam, chi)[0] if s >= 2 else [()]
+        cbr = K.kept_basis(ch.cuts[s - 1].Lam, chi)[0] if s < M else [()]
+        assert bl == cbl and br == cbr, s
+        a_ch = pco.build_tensor(ch.Q[s - 1], cbl, cbr, d)
+        scale = np.max(np.abs(a_ch))
+        dropped = sum(c.frozen_weight for c in ch.cuts)
+        assert np.max(np.abs(np.abs(a) - np.abs(a_ch))) < (1e-12 + 5 * dropped) * scale, s
+        f = mode_phases.bond_mode_factors(a_ch, a, cbl, cbr)
+        assert f["err"] < 1e-7 and f["modulus"] < 1e-7 and f["checked"] > 0, (s, f["err"], f["modulus"])
+        mirrored += M - s < s - 1
+    assert mirrored > 0
+
+
+# --------------------------------------- two-sided Gaussian SVD (Sec. II.A)
+
+def _q_up_to_mode_phases(qa, qb, ia):
+    """max |qb - diag(ph) qa diag(ph)| with the phases read off the physical
+    row ia (the physical mode carries no gauge), and max ||ph| - 1|."""
+    ph = np.ones(qa.shape[0], dtype=np.complex128)
+    for i in range(qa.shape[0]):
+        if i != ia and abs(qa[ia, i]) > 1e-12:
+            ph[i] = qb[ia, i] / qa[ia, i]
+    return float(np.max(np.abs(qb - np.outer(ph, ph) * qa))), float(np.max(np.abs(np.abs(ph) - 1)))
+
+
+@pytest.mark.parametrize("case", ["c1", "haar10", "haar12", "haar16"])
+def test_two_sided_literal_gsvd_agrees_with_one_sided(case):
+    """O2: the chain taken literally from Sec. II.A-B (Williamson of both
+    blocks at every cut, the right block's gauge fixed by Gamma_LR, the next
+    residual assembled from the Schmidt pairs of Eq. SVD3) against the
+    one-sided chain (left block only, residual T Gamma T^T):
+      - each D_q appears on both sides (D_R = D_L padded with ones);
+      - after a per-mode rotation, Gamma_LR = M_L [[P, 0], [0, -P]] M_R^T / 2
+        with P = sqrt(D^2 - 1), and no coupling outside the pairs;
+      - the same n_e and spectra, and every Q^m equal up to a phase per
+        virtual mode.
+    States with only strongly entangled pairs: a pair with D - 1 near zero
+    fixes its gauge from a coupling of size sqrt(D - 1), which rounding
+    swamps (the one-sided chain never needs that gauge)."""
+    w = W.workload("c1") if case == "c1" else W.custom(int(case[4:]), 4, 16, (0.4, 0.9), "haar", 30 + int(case[4:]))
+    one = G.gsvd(w.gamma)
+    two, diag = G.gsvd_two_sided(w.gamma)
+    assert [c.n_e for c in one.cuts] == [c.n_e for c in two.cuts]
+    for c1, c2, dg in zip(one.cuts, two.cuts, diag):
+        assert np.max(np.abs(c1.D - c2.D)) < 1e-12
+        k = min(len(dg.D_L), len(dg.D_R))
+        assert np.max(np.abs(dg.D_L[:k] - dg.D_R[:k])) < 1e-11
+        assert np.all(np.abs(dg.D_R[k:] - 1.0) < 1e-11) and np.all(np.abs(dg.D_L[k:] - 1.0) < 1e-11)
+        assert dg.offdiag < 1e-11 and dg.gauge_orth < 1e-11 and dg.relation < 1e-11
+    for m, (qa, qb) in enumerate(zip(one.Q, two.Q)):
+        err, mod = _q_up_to_mode_phases(qa, qb, one.n_in[m])
+        assert err < 1e-11 and mod < 1e-11, (m, err, mod)
+
+
+# ------------------------------------------------- fidelity, truncation
+
+def _squeezed_product(rs, d):
+    """Oracle MPS of a product of single-mode squeezed vacua (no
+    interferometer): bond dimension 1 at every cut."""
+    g = W.gamma_of_circuit(np.asarray(rs, dtype=float), np.eye(len(rs), dtype=np.complex128))
+    return build.build_mps(g, d, 1).tensors
+
+
+def test_fidelity_of_squeezed_products_closed_form():
+    """|<0|S(r1)^dag S(r2)|0>|^2 = 1/cosh(r1 - r2) for squeezers along the
+    same axis, so two products of squeezed vacua have
+    F = prod_j 1/cosh(r1_j - r2_j).  d = 48 leaves a truncated tail below
+    1e-12 at these squeezings."""
+    r1, r2 = (0.3, 0.5, 0.6), (0.45, 0.2, 0.6)
+    t1, t2 = _squeezed_product(r1, 48), _squeezed_product(r2, 48)
+    want = float(np.prod([1.0 / np.cosh(a - b) for a, b in zip(r1, r2)]))
+    assert P.fidelity(t1, t2) == pytest.approx(want, rel=1e-10)
+    assert P.fidelity(t2, t1) == pytest.approx(want, rel=1e-10)
+    # overlap of the normalised product states: prod 1/sqrt(cosh), real positive
+    assert P.overlap(t1, t2) == pytest.approx(np.sqrt(want), rel=1e-10)
+
+
+def _random_mps(bonds, d, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((bonds[m], d, bonds[m + 1])) + 1j * rng.standard_normal((bonds[m], d, bonds[m + 1]))
+            for m in range(len(bonds) - 1)]
+
+
+def test_overlap_and_fidelity_by_brute_force():
+    """<psi1|psi2> = sum_n conj(psi1(n)) psi2(n) over all d^M patterns of two
+    different random MPS (amplitudes by plain matrix products)."""
+    d = 3
+    t1 = _random_mps([1, 2, 3, 2, 1], d, 1)
+    t2 = _random_mps([1, 3, 2, 3, 1], d, 2)
+    pats = list(itertools.product(range(d), repeat=4))
+    a1, a2 = P.amplitudes(t1, pats), P.amplitudes(t2, pats)
+    ov = np.sum(np.conj(a1) * a2)
+    assert P.overlap(t1, t2) == pytest.approx(ov, rel=1e-12)
+    f = abs(ov) ** 2 / (np.sum(np.abs(a1) ** 2) * np.sum(np.abs(a2) ** 2))
+    assert P.fidelity(t1, t2) == pytest.approx(f, rel=1e-12)
+    assert P.norm2(t1) == pytest.approx(np.sum(np.abs(a1) ** 2), rel=1e-12)
+
+
+def test_svd_truncate_drops_the_discarded_weight():
+    """Truncating one bond of a unit-norm state to chi < rank keeps its chi
+    largest Schmidt coefficients (singular values of the amplitude matrix
+    split at that bond, from brute-force amplitudes) and loses exactly the
+    dropped weight: 1 - F = sum of the dropped sigma^2.  With several
+    truncated bonds the loss is at most the sum of the dropped weights, and
+    the last bond the sweep cuts (its first) sees the exact Schmidt values."""
+    d = 4
+    pats2 = list(itertools.product(range(d), repeat=2))
+    t = P.normalize(_random_mps([1, 4, 1], d, 3))
+    psi = P.amplitudes(t, pats2).reshape(d, d)
+    s = np.linalg.svd(psi, compute_uv=False)
+    for chi in (1, 2, 3):
+        tt, sv = P.svd_truncate(t, chi)
+        assert tt[0].shape[2] == chi
+        assert np.allclose(sv[0], s[:chi], rtol=1e-12, atol=1e-14)
+        assert 1.0 - P.fidelity(t, tt) == pytest.approx(float(np.sum(s[chi:] ** 2)), rel=1e-9, abs=1e-15)
+    # three sites, both bonds cut
+    pats3 = list(itertools.product(range(d), repeat=3))
+    t3 = P.normalize(_random_mps([1, 4, 4, 1], d, 4))
+    psi3 = P.amplitudes(t3, pats3)
+    s2 = np.linalg.svd(psi3.reshape(d * d, d), compute_uv=False)   # bond 2: (n1 n2) | n3
+    s1 = np.linalg.svd(psi3.reshape(d, d * d), compute_uv=False)   # bond 1: n1 | (n2 n3)
+    tt, sv = P.svd_truncate(t3, 2)
+    assert np.allclose(sv[1], s2[:2], rtol=1e-12)
+    loss = 1.0 - P.fidelity(t3, tt)
+    assert 0.0 < loss <= np.sum(s2[2:] ** 2) + np.sum(s1[2:] ** 2) + 1e-12
+    assert loss >= max(np.sum(s2[2:] ** 2), np.sum(s1[2:] ** 2)) - 1e-12
