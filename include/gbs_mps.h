@@ -249,6 +249,47 @@ void gbs_mps_free(gbs_mps h);
  * Used for admission control by the server below. */
 int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots);
 
+/* ---- Mixed -> pure filtration (Sec. III, Eq. decompose; App. C) ---------
+ * A measured covariance Gamma_th describes a mixed state; the conversion
+ * needs a pure one.  Gamma_th = Gamma_p + W with Gamma_p = S S^T / 2 pure
+ * (S symplectic) and W >= 0 classical noise; the wanted split has the
+ * fewest squeezed photons.  Following App. C: start at S = 1 and descend the
+ * loss L(S) = -lambda_min(Gamma_th - S S^T / 2) (Eq. loss) along the
+ * Riemannian gradient on Sp(2N) (the unit-norm element of the Lie algebra
+ * that maximises the directional derivative, for the Frobenius norm), with
+ * the exponential map as retraction, until L <= eps.  The step is the Newton
+ * step of the loss along the gradient, capped at alpha_max (the paper leaves
+ * the step size open).  FP64 throughout. */
+#define GBS_FILTER_MODES_MAX 288
+typedef struct {
+  double eps;        /* stop when L <= eps; 0 selects 1e-12 */
+  double alpha_max;  /* largest step along the unit gradient; 0 selects 0.5 */
+  int32_t max_iter;  /* step budget; 0 selects 100000 */
+} gbs_filter_opts;
+
+typedef struct {
+  int32_t iterations;  /* retraction steps taken */
+  int32_t converged;   /* 1 when L <= eps was reached within max_iter */
+  double loss;         /* L at the returned S */
+  double n_eff;        /* mean photon number of Gamma_p, tr(Gamma_p)/2 - N/2 (vacuum = 1/2) */
+  double ms;           /* wall time of the call */
+} gbs_filter_info_t;
+
+/* Pure part of a mixed Gaussian state.
+ *   gamma_th : device, 2N x 2N FP64, xxpp, vacuum = identity/2, symmetric
+ *              (GBS_E_NOT_PD otherwise); read only.
+ *   N        : modes, 1..GBS_FILTER_MODES_MAX.
+ *   opt      : host.
+ *   gamma_p  : device, 2N x 2N FP64 output, S S^T / 2 (a valid input of
+ *              gbs_mps_build).
+ *   S_out    : device, 2N x 2N FP64 output (may be NULL): the symplectic S.
+ *   info     : host output.
+ * Synchronises `stream` (the host checks the loss between batches of
+ * steps).  A state that does not reach L <= eps within max_iter returns
+ * GBS_OK with info->converged = 0 and the last S. */
+int gbs_filter_pure(const double* gamma_th, int32_t N, const gbs_filter_opts* opt, double* gamma_p, double* S_out,
+                    gbs_filter_info_t* info, void* stream);
+
 /* ---- Serving: many build + sample requests on one GPU ------------------
  * The consumer the paper names for its MPS is sampling (Sec. I); a server
  * takes requests "convert this state, then draw `shots` samples" from many

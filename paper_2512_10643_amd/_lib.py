@@ -29,6 +29,7 @@ EXPORT = {"tensor": 0, "raw": 1, "Q": 2, "basis": 3, "lambda": 4, "svals": 5, "s
 EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_build_site", "gbs_mps_amplitude", "gbs_mps_sample", "gbs_mps_sample_noalloc", "gbs_mps_sample_timed", "gbs_mps_overlap", "gbs_mps_overlap_prec",
                     "gbs_mps_info",
                     "gbs_mps_export", "gbs_mps_export_elements", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
+                    "gbs_filter_pure",
                     "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
                     "gbs_server_stats", "gbs_server_reset_stats", "gbs_server_destroy")
 
@@ -58,6 +59,15 @@ class InfoT(ctypes.Structure):
                 ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
                 ("t_svd_ms", ctypes.c_double), ("eig_sweeps", ctypes.c_int32),
                 ("sampler_layout", ctypes.c_int32)]
+
+
+class FilterOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("alpha_max", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
+class FilterInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("loss", ctypes.c_double),
+                ("n_eff", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -118,6 +128,8 @@ def lib():
         L.gbs_last_error.restype = ctypes.c_char_p
         L.gbs_mps_footprint.argtypes = [i32, ctypes.POINTER(BuildOpts), i64]
         L.gbs_mps_footprint.restype = ctypes.c_int64
+        L.gbs_filter_pure.argtypes = [dp, i32, ctypes.POINTER(FilterOpts), dp, dp, ctypes.POINTER(FilterInfo), vp]
+        L.gbs_filter_pure.restype = ctypes.c_int
         L.gbs_server_create.argtypes = [i32, i64, i32, ctypes.POINTER(vp)]
         L.gbs_server_create.restype = ctypes.c_int
         L.gbs_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]

@@ -23,6 +23,7 @@ SOURCES = [
     "gbs_mpsops.hip",
     "gbs_sampler.hip",
     "gbs_noalloc.hip",
+    "gbs_filter.hip",
     "gbs_api.cpp",
     "gbs_server.cpp",
 ]

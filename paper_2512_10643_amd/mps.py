@@ -202,3 +202,25 @@ def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, pre
     check(lib().gbs_mps_build(ctypes.c_void_p(gamma.data_ptr()), M, ctypes.byref(opts), _stream_handle(stream),
                               ctypes.byref(h)))
     return GaussianMPS(h, M, d)
+
+
+def filter_pure(gamma_th: torch.Tensor, eps: float = 0.0, alpha_max: float = 0.0, max_iter: int = 0,
+                want_S: bool = False, stream=None):
+    """gbs_filter_pure: pure part Gamma_p = S S^T / 2 of the mixed covariance
+    gamma_th (2N x 2N FP64 CUDA tensor) by the descent of App. C.  Returns
+    (gamma_p, S or None, info dict with iterations, converged, loss, n_eff, ms);
+    0 selects the library's defaults (eps 1e-12, alpha_max 0.5, 100000 steps)."""
+    if not isinstance(gamma_th, torch.Tensor) or not gamma_th.is_cuda or gamma_th.dtype != torch.float64:
+        raise ValueError("gamma_th must be a CUDA float64 tensor")
+    if gamma_th.dim() != 2 or gamma_th.shape[0] != gamma_th.shape[1] or gamma_th.shape[0] % 2:
+        raise GbsError(_lib.GBS_E_INVAL, "gamma_th must be 2N x 2N")
+    gamma_th = gamma_th.contiguous()
+    n = gamma_th.shape[0]
+    gp = torch.empty_like(gamma_th)
+    S = torch.empty_like(gamma_th) if want_S else None
+    info = _lib.FilterInfo()
+    opts = _lib.FilterOpts(eps=eps, alpha_max=alpha_max, max_iter=max_iter)
+    check(lib().gbs_filter_pure(ctypes.c_void_p(gamma_th.data_ptr()), n // 2, ctypes.byref(opts),
+                                ctypes.c_void_p(gp.data_ptr()), ctypes.c_void_p(S.data_ptr()) if want_S else None,
+                                ctypes.byref(info), _stream_handle(stream)))
+    return gp, S, {f: getattr(info, f) for f, _ in _lib.FilterInfo._fields_}

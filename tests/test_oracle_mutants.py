@@ -189,3 +189,71 @@ def test_mutant_is_caught(monkeypatch, mod, name, fn):
     except Exception:
         caught = True
     assert caught
+
+
+# ---------------------------------------------------- mixed -> pure filtration
+
+from oracle import filtration as F  # noqa: E402
+
+
+def _filtration_suite():
+    """True when the filtration oracle passes its closed forms and invariants."""
+    x = W.lossy(M=6, seed=2)
+    res = F.filter_pure(x["gamma"], max_iter=3000)
+    b = x["eta"] * np.exp(-2 * x["r"]) + 1 - x["eta"] + 2 * x["n_th"]
+    rp = np.maximum(0.0, -0.5 * np.log(b))
+    ok = res.loss <= 1e-12
+    ok &= np.max(np.abs(res.gamma_p - W.gamma_of_circuit(rp, x["U"]))) < 1e-10
+    ok &= abs(res.n_eff - np.sum(np.sinh(rp) ** 2)) < 1e-10
+    om = G.omega(6)
+    ok &= np.max(np.abs(res.S @ om @ res.S.T - om)) < 1e-10
+    return bool(ok)
+
+
+def test_unmutated_filtration_passes_its_suite():
+    assert _filtration_suite()
+
+
+def _mut_gradient_unprojected(s, v0):
+    w = s.T @ v0
+    e = np.outer(w, w)
+    return e / np.linalg.norm(e), float(np.linalg.norm(e))
+
+
+def _mut_gradient_wrong_sign(s, v0):
+    g, nrm = _orig_f["gradient"](s, v0)
+    return -g, nrm
+
+
+def _mut_gradient_x_only(s, v0):
+    g, nrm = _orig_f["gradient"](s, v0)
+    n = s.shape[0] // 2
+    g = g.copy()
+    g[n:, :] = 0.0
+    return g, nrm
+
+
+def _mut_neff_unit_vacuum(gamma_th, **kw):
+    res = _orig_f["filter_pure"](gamma_th, **kw)
+    res.n_eff = 0.5 * float(np.trace(res.gamma_p - np.eye(res.gamma_p.shape[0])))
+    return res
+
+
+_orig_f = {"gradient": F.gradient, "filter_pure": F.filter_pure}
+
+F_MUTANTS = [
+    ("gradient", _mut_gradient_unprojected),
+    ("gradient", _mut_gradient_wrong_sign),
+    ("gradient", _mut_gradient_x_only),
+    ("filter_pure", _mut_neff_unit_vacuum),
+]
+
+
+@pytest.mark.parametrize("name,fn", F_MUTANTS, ids=[m[1].__name__ for m in F_MUTANTS])
+def test_filtration_mutant_is_caught(monkeypatch, name, fn):
+    monkeypatch.setattr(F, name, fn)
+    try:
+        caught = not _filtration_suite()
+    except Exception:
+        caught = True
+    assert caught

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "haar_unitary", "beamsplitter_network", "symplectic_of_unitary",
     "gamma_of_circuit", "pair_matrix_of_circuit", "GaussianWorkload",
-    "workload", "serving_requests", "few_squeezed", "CONFIGS",
+    "workload", "serving_requests", "few_squeezed", "CONFIGS", "lossy_gamma", "lossy",
 ]
 
 
@@ -164,3 +164,41 @@ def serving_requests(n: int = 512, seed: int = 3, rate: float | None = None):
         w = _make(f"req{i}", M, d, chi, (0.1, 0.8), ("brick", depth), 1000 + i)
         reqs.append(dict(id=i, workload=w, arrival=t, shots=10_000, seed=1000 + i))
     return reqs
+
+
+def lossy_gamma(r, u, eta, n_th=0.0, extra=None) -> np.ndarray:
+    """Covariance (xxpp, vacuum = I/2) of a mixed state shaped like a lossy
+    boson-sampling source: squeezer j (strength r_j) loses a fraction
+    1 - eta_j of its light and picks up n_th_j thermal photons before the
+    passive interferometer U.  Mode j's covariance before U is
+    diag(eta e^{2r} + 1 - eta + 2 n_th, eta e^{-2r} + 1 - eta + 2 n_th) / 2.
+    `extra` (2M x 2M, positive semidefinite) adds noise after U."""
+    r = np.asarray(r, dtype=np.float64)
+    M = r.shape[0]
+    eta = np.broadcast_to(np.asarray(eta, dtype=np.float64), (M,))
+    n_th = np.broadcast_to(np.asarray(n_th, dtype=np.float64), (M,))
+    a = eta * np.exp(2 * r) + 1 - eta + 2 * n_th
+    b = eta * np.exp(-2 * r) + 1 - eta + 2 * n_th
+    su = symplectic_of_unitary(u)
+    g = 0.5 * su @ np.diag(np.concatenate([a, b])) @ su.T
+    if extra is not None:
+        g = g + np.asarray(extra, dtype=np.float64)
+    return 0.5 * (g + g.T)
+
+
+def lossy(M: int = 16, r=(0.3, 1.0), eta=(0.5, 0.9), n_th=0.02, circuit="haar", seed: int = 7,
+          noise: float = 0.0):
+    """Seeded lossy input: r ~ U[r], eta ~ U[eta] per source, thermal
+    photons n_th per source, a Haar (or ("brick", depth)) interferometer;
+    noise > 0 adds noise * R R^T / (2M) after it, R a 2M x 2M standard
+    normal matrix (correlated noise, which breaks the product form).
+    Returns dict(gamma, r, eta, n_th, U)."""
+    rng = np.random.default_rng(seed)
+    rr = rng.uniform(r[0], r[1], M)
+    ee = rng.uniform(eta[0], eta[1], M)
+    u = haar_unitary(M, rng) if circuit == "haar" else beamsplitter_network(M, circuit[1], rng)
+    extra = None
+    if noise > 0:
+        x = rng.standard_normal((2 * M, 2 * M))
+        extra = noise * x @ x.T / (2 * M)
+    return dict(gamma=lossy_gamma(rr, u, ee, n_th, extra), r=rr, eta=ee, n_th=n_th, U=u)
