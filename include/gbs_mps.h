@@ -290,26 +290,40 @@ typedef struct {
 int gbs_filter_pure(const double* gamma_th, int32_t N, const gbs_filter_opts* opt, double* gamma_p, double* S_out,
                     gbs_filter_info_t* info, void* stream);
 
-/* ---- Serving: many build + sample requests on one GPU ------------------
- * The consumer the paper names for its MPS is sampling (Sec. I); a server
- * takes requests "convert this state, then draw `shots` samples" from many
- * callers.  Requests queue in FIFO order.  `slots` worker threads, each with
- * its own HIP stream, start the head of the queue as soon as one is free and
- * the head's footprint (gbs_mps_footprint) fits `budget_bytes` beside the
- * requests in service, so requests enter and leave service continuously and
- * the kernels of up to `slots` requests run on the GPU at the same time.
- * A request's samples are identical whether it runs alone or in a mix: the
- * build is deterministic and the random numbers are keyed by (seed, shot,
- * site). */
+/* ---- Serving: build and sample requests on one GPU ----------------------
+ * The consumer the paper names for its MPS is sampling (Sec. I).  A server
+ * takes three kinds of request from many callers:
+ *   GBS_REQ_BUILD_SAMPLE : convert a state, draw `shots` samples, free the MPS;
+ *   GBS_REQ_BUILD        : convert a state and keep its MPS resident on the
+ *                          device (drawing `shots` samples too when > 0); the
+ *                          request's id names the resident MPS;
+ *   GBS_REQ_SAMPLE       : draw `shots` samples from a resident MPS (`handle`).
+ * Builds queue in FIFO order.  `slots` worker threads, each with its own HIP
+ * stream, start the head of the build queue as soon as one is free and the
+ * head's footprint (gbs_mps_footprint) fits `budget_bytes` beside everything
+ * admitted, resident MPS included.  Samples are drawn by one batched sweep
+ * (its own thread and stream): every request in it advances one site per
+ * step, all requests in the same launches, each through its own descriptor
+ * (site tensors, current site, buffers, seed, output); requests join at any
+ * step as memory allows and leave after their last site.  MPS without the
+ * FP32 sampler operand (FP64 builds) and requests above 2^20 shots are
+ * sampled on their own.  A request's samples are identical whether it runs
+ * alone or in a mix: the build is deterministic and the random numbers are
+ * keyed by (seed, shot, site), so every shot's arithmetic depends only on its
+ * own MPS, seed and shot number. */
 typedef struct gbs_server_s* gbs_server;
 
+enum { GBS_REQ_BUILD_SAMPLE = 0, GBS_REQ_BUILD = 1, GBS_REQ_SAMPLE = 2 };
+
 typedef struct {
-  const double* gamma; /* device, 2M x 2M FP64 as for gbs_mps_build; caller keeps it valid until the request is done */
+  const double* gamma; /* builds: device, 2M x 2M FP64 as for gbs_mps_build; caller keeps it valid until done */
   int32_t M;
   gbs_build_opts opt;
-  int64_t shots;       /* >= 0 */
+  int64_t shots;       /* >= 0 (>= 1 for GBS_REQ_SAMPLE) */
   uint64_t seed;
   int32_t* out;        /* device, shots x M int32; written when the request is done */
+  int32_t kind;        /* GBS_REQ_* */
+  int64_t handle;      /* GBS_REQ_SAMPLE: id of the GBS_REQ_BUILD request whose MPS to sample */
 } gbs_request;
 
 typedef struct {
@@ -317,9 +331,10 @@ typedef struct {
   int32_t max_bond;
   double eps_max;
   double queue_ms;     /* submit -> start of service */
-  double build_ms;     /* gbs_mps_build */
+  double build_ms;     /* gbs_mps_build (0 for sample requests) */
   double sample_ms;    /* sampling, up to samples ready on the device */
   double latency_ms;   /* submit -> samples ready */
+  int64_t handle;      /* GBS_REQ_BUILD: id of the resident MPS (the request's id); else 0 */
 } gbs_result;
 
 typedef struct {
@@ -328,19 +343,29 @@ typedef struct {
   double wall_s;                          /* first submit -> last completion */
   double throughput_rps;                  /* completed / wall_s */
   int64_t peak_bytes;                     /* largest admitted footprint sum */
+  int64_t resident;                       /* MPS held resident now */
+  int64_t sweep_steps;                    /* steps of the batched sampling sweep */
+  double mean_batch;                      /* requests per sweep step, mean */
+  int64_t max_batch;                      /* requests per sweep step, largest */
 } gbs_server_stats_t;
 
 /* Create a server on the current device.  slots in [1, 64]; budget_bytes:
- * device memory the admitted requests may hold together (a request larger
- * than the budget is rejected at submit with GBS_E_NOMEM); max_queue: queued
- * requests beyond which submit returns GBS_E_BUSY.  out: host.  Each slot
- * works on its own HIP stream; slots run concurrently on the device only up
- * to the process's hardware queue count (the GPU_MAX_HW_QUEUES environment
- * variable, read when HIP starts), so a process serving many slots should
- * set it to at least the slot count. */
+ * device memory the admitted requests and resident MPS may hold together (a
+ * build larger than the budget is rejected at submit with GBS_E_NOMEM);
+ * max_queue: queued builds (or queued samples) beyond which submit returns
+ * GBS_E_BUSY.  out: host.  Each build slot works on its own HIP stream;
+ * slots run concurrently on the device only up to the process's hardware
+ * queue count (the GPU_MAX_HW_QUEUES environment variable, read when HIP
+ * starts), so a process serving many slots should set it to at least the
+ * slot count plus one. */
 int gbs_server_create(int32_t slots, int64_t budget_bytes, int32_t max_queue, gbs_server* out);
-/* Queue a request (host struct, copied).  *id (host) receives its id. */
+/* Queue a request (host struct, copied).  *id (host) receives its id.
+ * GBS_E_INVAL for an unknown kind, a sample request naming no resident MPS
+ * (or one being released), or missing pointers. */
 int gbs_server_submit(gbs_server s, const gbs_request* req, int64_t* id);
+/* Release a resident MPS: freed once the sample requests admitted or
+ * queued on it are done; later sample requests naming it are rejected. */
+int gbs_server_release(gbs_server s, int64_t handle);
 /* *done (host) = 1 once the request's samples are ready. */
 int gbs_server_poll(gbs_server s, int64_t id, int32_t* done);
 /* Block until the request is done, fill *res (host, may be NULL), forget the
@@ -349,7 +374,8 @@ int gbs_server_wait(gbs_server s, int64_t id, gbs_result* res);
 /* Latency and throughput over the requests completed since the last reset. */
 int gbs_server_stats(gbs_server s, gbs_server_stats_t* out);
 int gbs_server_reset_stats(gbs_server s);
-/* Finish every queued request, then stop the workers and free the server. */
+/* Finish every queued request, then stop the workers, free every resident
+ * MPS and the server. */
 void gbs_server_destroy(gbs_server s);
 
 /* Thread-local message for the last failing call on this thread. */

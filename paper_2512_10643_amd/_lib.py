@@ -30,7 +30,8 @@ EXPORTED_SYMBOLS = ("gbs_mps_build", "gbs_mps_build_site", "gbs_mps_amplitude", 
                     "gbs_mps_info",
                     "gbs_mps_export", "gbs_mps_export_elements", "gbs_mps_free", "gbs_last_error", "gbs_mps_footprint",
                     "gbs_filter_pure",
-                    "gbs_server_create", "gbs_server_submit", "gbs_server_poll", "gbs_server_wait",
+                    "gbs_server_create", "gbs_server_submit", "gbs_server_release", "gbs_server_poll",
+                    "gbs_server_wait",
                     "gbs_server_stats", "gbs_server_reset_stats", "gbs_server_destroy")
 
 
@@ -70,22 +71,27 @@ class FilterInfo(ctypes.Structure):
                 ("n_eff", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
+GBS_REQ_BUILD_SAMPLE, GBS_REQ_BUILD, GBS_REQ_SAMPLE = 0, 1, 2
+
+
 class Request(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_void_p), ("M", ctypes.c_int32), ("opt", BuildOpts), ("shots", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p), ("kind", ctypes.c_int32),
+                ("handle", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("max_bond", ctypes.c_int32), ("eps_max", ctypes.c_double),
                 ("queue_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
-                ("latency_ms", ctypes.c_double)]
+                ("latency_ms", ctypes.c_double), ("handle", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("throughput_rps", ctypes.c_double),
-                ("peak_bytes", ctypes.c_int64)]
+                ("peak_bytes", ctypes.c_int64), ("resident", ctypes.c_int64), ("sweep_steps", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double), ("max_batch", ctypes.c_int64)]
 
 
 _lib = None
@@ -134,6 +140,8 @@ def lib():
         L.gbs_server_create.restype = ctypes.c_int
         L.gbs_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]
         L.gbs_server_submit.restype = ctypes.c_int
+        L.gbs_server_release.argtypes = [vp, i64]
+        L.gbs_server_release.restype = ctypes.c_int
         L.gbs_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32)]
         L.gbs_server_poll.restype = ctypes.c_int
         L.gbs_server_wait.argtypes = [vp, i64, ctypes.POINTER(Result)]

@@ -150,6 +150,7 @@ struct gbs_mps_s {
   long q_stride = 0, ld_q = 0;
   float* packed = nullptr;       // MFMA sampler operand layout (FP32 builds)
   std::vector<long> poff;        // per site offset into `packed` (floats)
+  long* poff_dev = nullptr;      // the same on the device, M + 1 entries
   std::vector<SamplerSite> ssite;  // per site sector sizes of the packed operand
   std::vector<SamplerGeom> sgeo;   // per site launch geometry (host copy)
   SamplerGeom* sgeo_dev = nullptr; // the same on the device, M + 1 entries
@@ -871,6 +872,8 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
       HIP_CHECK_RET(hipMemcpyAsync(h->sgeo_dev, h->sgeo.data(), (M + 1) * sizeof(SamplerGeom),
                                    hipMemcpyHostToDevice, st));
       HIP_CHECK_RET(dalloc(h->keep, &h->packed, (size_t)tot));
+      HIP_CHECK_RET(dalloc(h->keep, &h->poff_dev, (size_t)(M + 1)));
+      HIP_CHECK_RET(hipMemcpyAsync(h->poff_dev, h->poff.data(), (M + 1) * sizeof(long), hipMemcpyHostToDevice, st));
       for (int m = 1; m <= M; ++m)
         HIP_CHECK_RET(launch_pack(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
                                   h->ssite[m], h->sgeo[m], h->sgeo_dev + m,
@@ -1378,6 +1381,58 @@ __attribute__((visibility("hidden"))) int gbs_sample_in_region(gbs_mps h, int64_
   HIP_CHECK_RET(sample_buffers(h, chunk, a, b));
   return sample_sweep(h, shots, seed, out, st, nullptr, chunk, b);
 }
+
+// ---- batched sampling of several handles (used by the server)
+
+__attribute__((visibility("hidden"))) bool gbs_batch_supported(gbs_mps h, int64_t shots) {
+  return h && !h->single_site && h->packed && h->poff_dev && shots > 0 && shots <= kSampleChunk;
+}
+
+__attribute__((visibility("hidden"))) int64_t gbs_batch_bytes(gbs_mps h, int64_t shots) {
+  SampleAlloc a;  // counting only
+  SampleBufs b;
+  (void)sample_buffers(h, shots, a, b);
+  return (int64_t)a.used;
+}
+
+__attribute__((visibility("hidden"))) int gbs_batch_prepare(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out,
+                                                            hipStream_t st, void* region, size_t cap,
+                                                            SampleBatchDesc* d) {
+  if (!gbs_batch_supported(h, shots) || !out) return fail(GBS_E_INVAL, "request not sampled by the batched sweep");
+  SampleAlloc a;
+  a.base = (char*)region;
+  a.cap = cap;
+  SampleBufs b;
+  HIP_CHECK_RET(sample_buffers(h, shots, a, b));
+  HIP_CHECK_RET(launch_sampler_init(st, b.fb[0], h->ldl2, h->bond[0], shots));
+  *d = SampleBatchDesc{};
+  d->packed = h->packed;
+  d->poff = h->poff_dev;
+  d->geo = h->sgeo_dev;
+  for (int i = 0; i < 2; ++i) {
+    d->fb[i] = b.fb[i];
+    d->sb[i] = b.sb[i];
+  }
+  d->par = b.par;
+  d->perm = b.perm;
+  d->cnt = b.cnt;
+  d->bcnt = b.bcnt;
+  d->out = out;
+  d->ldl2 = h->ldl2;
+  d->nshots = shots;
+  d->k0 = (uint32_t)seed;
+  d->k1 = (uint32_t)(seed >> 32);
+  d->M = h->M;
+  d->site = 1;
+  d->psplit = h->psplit ? 1 : 0;
+  return GBS_OK;
+}
+
+__attribute__((visibility("hidden"))) int gbs_batch_site_nt(gbs_mps h, int site) {
+  return sampler_batch_nt(h->sgeo[site]);
+}
+
+__attribute__((visibility("hidden"))) int64_t gbs_mps_device_bytes(gbs_mps h) { return h ? h->keep.bytes : 0; }
 
 extern "C" {
 

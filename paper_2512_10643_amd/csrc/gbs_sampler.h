@@ -101,3 +101,37 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom&
 int64_t sampler_partition_ws(int64_t nshots);
 hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t nshots, int32_t* bcnt,
                                     int32_t* perm, int32_t* cnt);
+
+// One request of a batched sampling sweep at its current site (device copy
+// read by the batched kernels).  The request's shots are numbered from 0
+// (Philox counter and output row), its left-vector rows ping-pong between
+// fb[0] / fb[1] (site m reads fb[(m - 1) & 1]) with their inverse norms in
+// sb, and par / perm / cnt / bcnt are its parity partition buffers (sized as
+// for a single-request sweep of nshots).
+struct SampleBatchDesc {
+  const float* packed;      // packed operand of the handle
+  const long* poff;         // device, M + 1 offsets into packed (floats), by site
+  const SamplerGeom* geo;   // device, M + 1 site geometries
+  float* fb[2];
+  float* sb[2];
+  int8_t* par;
+  int32_t* perm;
+  int32_t* cnt;
+  int32_t* bcnt;
+  int32_t* out;             // nshots x M int32
+  long ldl2;
+  int64_t nshots;
+  uint32_t k0, k1;          // seed (low, high word)
+  int M;
+  int site;                 // current site, 1..M
+  int psplit;               // photon-parity sectors
+  int pad;
+};
+// Accumulator tiles (8, 16, 24 or 32) a site's passes need.
+int sampler_batch_nt(const SamplerGeom& g);
+// One site step of nreq requests (desc: device array); max_blocks: the
+// largest ceil(nshots / 128) + 1 among them; nt: the largest
+// sampler_batch_nt of their current sites.
+hipError_t launch_sample_batch(hipStream_t st, const SampleBatchDesc* desc, int nreq, int64_t max_blocks, int nt);
+// The parity partitions of the same step (requests at their last site skip).
+hipError_t launch_partition_batch(hipStream_t st, const SampleBatchDesc* desc, int nreq, int64_t max_shots);

@@ -238,26 +238,26 @@ __device__ __forceinline__ void pass_draws(const floatx4 (&acc)[NT], int j0, int
   }
 }
 
-// Passes [qbeg, qend) of one site, one workgroup per 128 slots (used for the
-// remaining passes of the shots a site's first launch left undecided).
+// Passes [qbeg, qend) of one site for the 128 slots of workgroup `blk` (used
+// for the remaining passes of the shots a site's first launch left
+// undecided, and, over all passes, by the batched sweep).  Bs0, Bs1: the
+// kernel's two LDS operand buffers (512 NT floats each, two separate arrays
+// so the compiler can tell the buffer being read from the one the DMA is
+// filling); wdone: kWaves ints of LDS.
 template <int NT>
-__global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
+__device__ __forceinline__ void sample_passes(
+    float* __restrict__ Bs0, float* __restrict__ Bs1, int* __restrict__ wdone, int64_t blk,
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
     const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
     float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend, int64_t shot0, int64_t nshots,
     int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
-  // two separate LDS buffers (not one 2-D array), so the compiler can tell
-  // the buffer being read from the one the DMA is filling
-  __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
-  __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
-  __shared__ int wdone[kWaves];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int grp = lane >> 4;   // k sub-block of the left vector; column quad of the output
   const int col = lane & 15;   // shot within the wave
   // sector of this workgroup and the end of its slot range
   int pi = 0;
-  const int64_t slot0 = (int64_t)blockIdx.x * kShotsPerWg;
+  const int64_t slot0 = blk * kShotsPerWg;
   int64_t send = nshots;
   if (perm) {
     const int64_t c0 = cnt[0], c1 = cnt[1];
@@ -421,6 +421,42 @@ __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     if (key) key[shot] = fin ? 2 : (int8_t)pi;
     if (!fin) cum[shot] = csum;
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
+    const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
+    const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
+    float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend, int64_t shot0, int64_t nshots,
+    int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
+  __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
+  __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
+  __shared__ int wdone[kWaves];
+  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, P, geo, lin, sin, lout, sout, ldl2, perm, cnt, par_out, cum, key,
+                    qbeg, qend, shot0, nshots, site, k0, k1, out, M);
+}
+
+// Batched sweep: one site step of several sampling requests in one launch.
+// Workgroup (x, y) takes slot block x of request y at that request's own
+// current site (requests join and leave the batch at any step), all passes
+// of the site with early stopping.  The arithmetic of every shot is that of
+// the single-request sweep.
+template <int NT>
+__global__ __launch_bounds__(64 * kWaves) void sample_batch_kernel(const SampleBatchDesc* __restrict__ desc) {
+  __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
+  __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
+  __shared__ int wdone[kWaves];
+  const SampleBatchDesc& D = desc[blockIdx.y];
+  const int m = D.site;
+  const bool part = D.psplit && m > 1, next = D.psplit && m < D.M;
+  const int64_t blocks = (D.nshots + kShotsPerWg - 1) / kShotsPerWg + (part ? 1 : 0);
+  if ((int64_t)blockIdx.x >= blocks) return;  // whole workgroup
+  const int cur = (m - 1) & 1;
+  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, D.packed + D.poff[m], D.geo + m, D.fb[cur],
+                    m == 1 ? nullptr : D.sb[cur], D.fb[1 - cur], D.sb[1 - cur], D.ldl2, part ? D.perm : nullptr,
+                    part ? D.cnt : nullptr, next ? D.par : nullptr, nullptr, nullptr, 0, kSamplerMaxOutcomes, 0,
+                    D.nshots, m, D.k0, D.k1, D.out, D.M);
 }
 
 // The first pass of a site (outcome 0, plus any outcomes sharing its pass)
@@ -606,10 +642,9 @@ __device__ inline int block_sum256(int v, int* sh) {
 
 constexpr int kPartElems = 1024;  // parities per partition block (256 threads x 4)
 
-__global__ __launch_bounds__(256) void part_count_kernel(const int8_t* __restrict__ par, int64_t n,
-                                                         int32_t* __restrict__ bcnt) {
-  __shared__ int sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kPartElems + 4 * threadIdx.x;
+__device__ __forceinline__ void part_count(const int8_t* __restrict__ par, int64_t n, int32_t* __restrict__ bcnt,
+                                           int64_t blk, int* sh) {
+  const int64_t base = blk * kPartElems + 4 * threadIdx.x;
   int c0 = 0, c1 = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -620,23 +655,21 @@ __global__ __launch_bounds__(256) void part_count_kernel(const int8_t* __restric
   c0 = block_sum256(c0, sh);
   c1 = block_sum256(c1, sh);
   if (threadIdx.x == 0) {
-    bcnt[2 * blockIdx.x] = c0;
-    bcnt[2 * blockIdx.x + 1] = c1;
+    bcnt[2 * blk] = c0;
+    bcnt[2 * blk + 1] = c1;
   }
 }
 
-__global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restrict__ par, int64_t n,
-                                                           const int32_t* __restrict__ bcnt, int nblk,
-                                                           int32_t* __restrict__ perm, int32_t* __restrict__ cnt) {
-  __shared__ int sh[4];
-  __shared__ int wtot[4];
+__device__ __forceinline__ void part_scatter(const int8_t* __restrict__ par, int64_t n,
+                                             const int32_t* __restrict__ bcnt, int nblk, int32_t* __restrict__ perm,
+                                             int32_t* __restrict__ cnt, int blk, int* sh, int* wtot) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int before = 0, before1 = 0, tot = 0, tot1 = 0;
   for (int i = tid; i < nblk; i += 256) {
     const int v = bcnt[2 * i], v1 = bcnt[2 * i + 1];
     tot += v;
     tot1 += v1;
-    if (i < (int)blockIdx.x) {
+    if (i < blk) {
       before += v;
       before1 += v1;
     }
@@ -647,7 +680,7 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restr
   tot1 = block_sum256(tot1, sh);
   const int64_t c0 = tot;
   const int64_t e = (c0 + kShotsPerWg - 1) / kShotsPerWg * kShotsPerWg;
-  const int64_t blk0 = (int64_t)blockIdx.x * kPartElems;
+  const int64_t blk0 = (int64_t)blk * kPartElems;
   const int64_t base = blk0 + 4 * tid;
   int q[4];
   int ne = 0, no = 0;
@@ -677,10 +710,43 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restr
     if (q[j] == 0) perm[re++] = (int32_t)(base + j);
     else if (q[j] == 1) perm[ro++] = (int32_t)(base + j);
   }
-  if (blockIdx.x == 0 && tid == 0) {
+  if (blk == 0 && tid == 0) {
     cnt[0] = (int32_t)c0;
     cnt[1] = (int32_t)tot1;
   }
+}
+
+__global__ __launch_bounds__(256) void part_count_kernel(const int8_t* __restrict__ par, int64_t n,
+                                                         int32_t* __restrict__ bcnt) {
+  __shared__ int sh[4];
+  part_count(par, n, bcnt, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restrict__ par, int64_t n,
+                                                           const int32_t* __restrict__ bcnt, int nblk,
+                                                           int32_t* __restrict__ perm, int32_t* __restrict__ cnt) {
+  __shared__ int sh[4];
+  __shared__ int wtot[4];
+  part_scatter(par, n, bcnt, nblk, perm, cnt, blockIdx.x, sh, wtot);
+}
+
+// Partition by the parities of request y's outcomes at its current site,
+// for the next site (requests at their last site, or without sectors, skip).
+__global__ __launch_bounds__(256) void part_count_batch_kernel(const SampleBatchDesc* __restrict__ desc) {
+  __shared__ int sh[4];
+  const SampleBatchDesc& D = desc[blockIdx.y];
+  const int64_t nblk = (D.nshots + kPartElems - 1) / kPartElems;
+  if (!D.psplit || D.site >= D.M || (int64_t)blockIdx.x >= nblk) return;
+  part_count(D.par, D.nshots, D.bcnt, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(256) void part_scatter_batch_kernel(const SampleBatchDesc* __restrict__ desc) {
+  __shared__ int sh[4];
+  __shared__ int wtot[4];
+  const SampleBatchDesc& D = desc[blockIdx.y];
+  const int64_t nblk = (D.nshots + kPartElems - 1) / kPartElems;
+  if (!D.psplit || D.site >= D.M || (int64_t)blockIdx.x >= nblk) return;
+  part_scatter(D.par, D.nshots, D.bcnt, (int)nblk, D.perm, D.cnt, blockIdx.x, sh, wtot);
 }
 
 // First left vectors: L = e_0 (the site-1 left bond has dimension 1), as
@@ -860,5 +926,35 @@ hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t n
   hipLaunchKernelGGL(part_count_kernel, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt);
   hipLaunchKernelGGL(part_scatter_kernel, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt, nblk, perm,
                      cnt);
+  return hipGetLastError();
+}
+
+int sampler_batch_nt(const SamplerGeom& g) {
+  int mx = 8;
+  for (int pi = 0; pi < 2; ++pi)
+    for (int q = 0; q < g.npass[pi]; ++q) mx = std::max(mx, g.tiles[pi][q]);
+  return (mx + 7) / 8 * 8;
+}
+
+hipError_t launch_sample_batch(hipStream_t st, const SampleBatchDesc* desc, int nreq, int64_t max_blocks, int nt) {
+  if (nreq <= 0 || max_blocks <= 0) return hipSuccess;
+  if (nreq > 65535 || max_blocks > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)max_blocks, (unsigned)nreq);
+  switch (nt) {
+    case 8: hipLaunchKernelGGL((sample_batch_kernel<8>), grid, dim3(64 * kWaves), 0, st, desc); break;
+    case 16: hipLaunchKernelGGL((sample_batch_kernel<16>), grid, dim3(64 * kWaves), 0, st, desc); break;
+    case 24: hipLaunchKernelGGL((sample_batch_kernel<24>), grid, dim3(64 * kWaves), 0, st, desc); break;
+    case 32: hipLaunchKernelGGL((sample_batch_kernel<32>), grid, dim3(64 * kWaves), 0, st, desc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_partition_batch(hipStream_t st, const SampleBatchDesc* desc, int nreq, int64_t max_shots) {
+  if (nreq <= 0 || max_shots <= 0) return hipSuccess;
+  if (nreq > 65535 || max_shots > INT32_MAX - 256) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((max_shots + kPartElems - 1) / kPartElems), (unsigned)nreq);
+  hipLaunchKernelGGL(part_count_batch_kernel, grid, dim3(256), 0, st, desc);
+  hipLaunchKernelGGL(part_scatter_batch_kernel, grid, dim3(256), 0, st, desc);
   return hipGetLastError();
 }

@@ -1,17 +1,23 @@
 // Request serving on one GPU behind the C ABI (gbs_server_* in gbs_mps.h).
 //
-// A request is one pure Gaussian state to convert (Sec. II) plus a number of
-// photon-number samples to draw from its MPS.  Requests wait in a FIFO queue.
-// `slots` worker threads, each owning one HIP stream, take the head of the
-// queue as soon as they are free and the head's device-memory footprint fits
-// the budget beside the requests already in service.  Admission is therefore
-// continuous: a request does not wait for a batch to form or drain, and the
-// kernels of up to `slots` requests (a latency-bound Gaussian SVD chain of one
-// request next to the sampling GEMMs of another) share the GPU at once.
-// Every temporary is a stream-ordered allocation on the worker's stream, so
-// one request's frees never wait on another's kernels.  A request's results
-// do not depend on what else is in service: the build is deterministic and
-// the sampler's random numbers are keyed by (seed, shot, site).
+// Requests convert pure Gaussian states (Sec. II) and draw photon-number
+// samples from their MPS (the consumer of Sec. I).  Three kinds:
+//   build + sample : build, draw the shots, free the MPS;
+//   build          : build and keep the MPS resident (optionally drawing shots),
+//                    the request's id naming the resident MPS;
+//   sample         : draw shots from a resident MPS.
+// Builds wait in a FIFO queue; `slots` worker threads, each with its own HIP
+// stream, take its head as soon as they are free and the head's footprint
+// fits the memory budget beside everything admitted (resident MPS included).
+// Sampling has its own engine: one thread and one stream run a batched
+// sweep in which every active request advances one site per step, all of
+// them in the same launches (a descriptor per request: its site tensors,
+// current site, buffers, seed and output).  Requests join the sweep at any
+// step, as memory allows, and leave it after their last site, so sampling
+// is batched continuously across requests while builds run beside it.  A
+// request's samples are identical whether it runs alone or in a mix: the
+// build is deterministic and every shot's arithmetic depends only on its own
+// MPS, seed and shot number.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,22 +37,35 @@
 
 namespace {
 
+constexpr int kMaxActive = 256;  // requests in the batched sweep at once
+
 int sfail(int code, const std::string& msg) { return gbs_fail(code, msg); }
 
 double wall_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+struct Resident {
+  gbs_mps h = nullptr;
+  int64_t bytes = 0;
+  int refs = 0;          // sample requests admitted or queued on it
+  bool release = false;  // free once refs reaches 0
+};
+
 struct Req {
-  gbs_request r;
+  gbs_request r{};
   int64_t id = 0;
-  int64_t fp = 0;
+  int64_t fp = 0;        // bytes reserved while building
+  int64_t sbytes = 0;    // bytes of its sampling buffers while in the sweep
   double t_submit = 0, t_start = 0, t_built = 0, t_done = 0;
   int status = GBS_OK;
   int max_bond = 0;
   double eps_max = 0;
   bool done = false;
   std::string err;
+  gbs_mps h = nullptr;       // MPS to sample
+  bool free_after = false;   // build + sample: free h after the shots
+  int64_t resident = 0;      // id of the resident MPS it samples (0: none)
 };
 
 double percentile(std::vector<double> v, double q) {
@@ -57,6 +76,12 @@ double percentile(std::vector<double> v, double q) {
   return v[std::min(k, v.size()) - 1];
 }
 
+struct Job {  // one request in the batched sweep
+  Req* q;
+  SampleBatchDesc d;
+  void* region;
+};
+
 }  // namespace
 
 struct gbs_server_s {
@@ -65,20 +90,60 @@ struct gbs_server_s {
   int slots = 0;
   int max_queue = 0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<Req*> queue;
+  std::condition_variable cv_work, cv_done, cv_sample;
+  std::deque<Req*> queue;          // builds
+  std::deque<Req*> squeue;         // samples waiting for the sweep
   std::unordered_map<int64_t, Req*> recs;
+  std::unordered_map<int64_t, Resident> residents;
   int64_t in_use = 0, peak = 0, next_id = 1;
   int running = 0;
   bool stop = false;
   std::vector<std::thread> workers;
+  std::thread engine;
   std::vector<hipStream_t> streams;
+  hipStream_t sstream = nullptr;   // the sampling engine's stream
+  SampleBatchDesc* desc_dev = nullptr;
+  SampleBatchDesc* desc_host = nullptr;  // pinned
   std::vector<double> lat;
   int64_t submitted = 0, completed = 0, failed = 0;
+  int64_t steps = 0, step_requests = 0, max_batch = 0;
   double t_first = -1.0, t_last = 0.0;
 
   void worker(int slot);
+  void sampler();
+  void finish(Req* q, int rc);       // with mu held
+  void unref(Req* q);                // with mu held: drop the request's hold on its MPS
 };
+
+// With mu held: record the outcome and wake waiters.
+void gbs_server_s::finish(Req* q, int rc) {
+  q->t_done = wall_ms();
+  q->status = rc;
+  q->done = true;
+  if (rc == GBS_OK) {
+    ++completed;
+    lat.push_back(q->t_done - q->t_submit);
+  } else {
+    ++failed;
+  }
+  t_last = std::max(t_last, q->t_done);
+}
+
+void gbs_server_s::unref(Req* q) {
+  if (q->free_after && q->h) {
+    in_use -= gbs_mps_device_bytes(q->h);
+    gbs_mps_free(q->h);
+    q->h = nullptr;
+  }
+  if (q->resident) {
+    auto it = residents.find(q->resident);
+    if (it != residents.end() && --it->second.refs == 0 && it->second.release) {
+      in_use -= it->second.bytes;
+      gbs_mps_free(it->second.h);
+      residents.erase(it);
+    }
+  }
+}
 
 void gbs_server_s::worker(int slot) {
   (void)hipSetDevice(device);
@@ -102,35 +167,170 @@ void gbs_server_s::worker(int slot) {
     gbs_mps h = nullptr;
     int rc = gbs_build_handle(q->r.gamma, q->r.M, &q->r.opt, st, true, &h, 0);
     q->t_built = wall_ms();
-    if (rc == GBS_OK && q->r.shots > 0) rc = gbs_mps_sample(h, q->r.shots, q->r.seed, q->r.out, st);
-    if (rc == GBS_OK && hipStreamSynchronize(st) != hipSuccess) {
-      (void)hipGetLastError();
-      rc = sfail(GBS_E_DEVICE, "HIP error while sampling");
-    }
-    q->t_done = wall_ms();
-    if (rc != GBS_OK) q->err = gbs_last_error();
+    std::string err = rc != GBS_OK ? gbs_last_error() : std::string();
     if (h) {
       gbs_mps_info_t inf;
       if (gbs_mps_info(h, &inf, nullptr, nullptr, nullptr, nullptr) == GBS_OK) {
         q->max_bond = inf.max_bond;
         q->eps_max = inf.eps_max;
       }
-      gbs_mps_free(h);  // stream-ordered release on `st`
+    }
+    // FP64 handles have no MFMA sampler operand: their shots are drawn here
+    const bool direct = h && q->r.shots > 0 && !gbs_batch_supported(h, q->r.shots);
+    if (rc == GBS_OK && direct) {
+      rc = gbs_mps_sample(h, q->r.shots, q->r.seed, q->r.out, st);
+      if (rc == GBS_OK && hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = sfail(GBS_E_DEVICE, "HIP error while sampling");
+      }
+      if (rc != GBS_OK) err = gbs_last_error();
     }
     {
       std::lock_guard<std::mutex> lk(mu);
-      in_use -= q->fp;
       --running;
-      q->status = rc;
-      q->done = true;
-      if (rc == GBS_OK) {
-        ++completed;
-        lat.push_back(q->t_done - q->t_submit);
+      in_use -= q->fp;  // the build's reservation; the MPS now holds its own bytes
+      q->err = err;
+      if (rc != GBS_OK) {
+        if (h) gbs_mps_free(h);
+        finish(q, rc);
       } else {
-        ++failed;
+        const int64_t hb = gbs_mps_device_bytes(h);
+        in_use += hb;
+        peak = std::max(peak, in_use);
+        const bool keep = q->r.kind == GBS_REQ_BUILD;
+        if (keep) residents[q->id] = Resident{h, hb, 0, false};
+        if (q->r.shots > 0 && !direct) {
+          q->h = h;
+          q->free_after = !keep;
+          if (keep) {
+            q->resident = q->id;
+            residents[q->id].refs++;
+          }
+          squeue.push_back(q);  // the sweep completes the request
+        } else {
+          if (!keep) {
+            in_use -= hb;
+            gbs_mps_free(h);
+          }
+          finish(q, GBS_OK);
+        }
       }
-      t_last = std::max(t_last, q->t_done);
     }
+    cv_done.notify_all();
+    cv_work.notify_all();
+    cv_sample.notify_all();
+  }
+}
+
+void gbs_server_s::sampler() {
+  (void)hipSetDevice(device);
+  hipStream_t st = sstream;
+  std::vector<Job> active;
+  for (;;) {
+    std::vector<Req*> admit;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_sample.wait(lk, [&] { return stop || !squeue.empty() || !active.empty(); });
+      if (stop && squeue.empty() && active.empty() && queue.empty() && running == 0) return;
+      // admit from the head while memory allows (always one when idle)
+      while (!squeue.empty() && (int)(active.size() + admit.size()) < kMaxActive) {
+        Req* q = squeue.front();
+        const bool batch = gbs_batch_supported(q->h, q->r.shots);
+        const int64_t b = batch ? gbs_batch_bytes(q->h, q->r.shots) : 0;
+        if (!(active.empty() && admit.empty()) && in_use + b > budget) break;
+        squeue.pop_front();
+        q->sbytes = b;
+        in_use += b;
+        peak = std::max(peak, in_use);
+        if (q->t_start == 0) q->t_start = wall_ms();
+        admit.push_back(q);
+      }
+    }
+    if (admit.empty() && active.empty()) {
+      std::unique_lock<std::mutex> lk(mu);
+      // woken with nothing to do (e.g. stop with builds still running)
+      cv_sample.wait_for(lk, std::chrono::milliseconds(5));
+      continue;
+    }
+    for (Req* q : admit) {
+      int rc = GBS_OK;
+      Job j{q, SampleBatchDesc{}, nullptr};
+      if (gbs_batch_supported(q->h, q->r.shots)) {
+        if (hipMallocAsync(&j.region, (size_t)q->sbytes, st) != hipSuccess) {
+          (void)hipGetLastError();
+          j.region = nullptr;
+          rc = sfail(GBS_E_NOMEM, "device allocation of the sampling buffers failed");
+        } else {
+          rc = gbs_batch_prepare(q->h, q->r.shots, q->r.seed, q->r.out, st, j.region, (size_t)q->sbytes, &j.d);
+        }
+      } else {  // an FP64 resident MPS: the vector sweep, on its own
+        rc = gbs_mps_sample(q->h, q->r.shots, q->r.seed, q->r.out, st);
+        if (rc == GBS_OK && hipStreamSynchronize(st) != hipSuccess) {
+          (void)hipGetLastError();
+          rc = sfail(GBS_E_DEVICE, "HIP error while sampling");
+        }
+        if (rc == GBS_OK) {
+          std::lock_guard<std::mutex> lk(mu);
+          unref(q);
+          finish(q, GBS_OK);
+          cv_done.notify_all();
+          cv_work.notify_all();
+          continue;
+        }
+      }
+      if (rc != GBS_OK) {
+        const std::string err = gbs_last_error();
+        if (j.region) (void)hipFreeAsync(j.region, st);
+        std::lock_guard<std::mutex> lk(mu);
+        in_use -= q->sbytes;
+        q->err = err;
+        unref(q);
+        finish(q, rc);
+        cv_done.notify_all();
+        cv_work.notify_all();
+        continue;
+      }
+      active.push_back(j);
+    }
+    if (active.empty()) continue;
+    // one site step of every active request
+    int nt = 8;
+    int64_t max_blocks = 0, max_shots = 0;
+    const int64_t spb = sampler_shots_per_block();
+    for (size_t i = 0; i < active.size(); ++i) {
+      Job& j = active[i];
+      desc_host[i] = j.d;
+      nt = std::max(nt, gbs_batch_site_nt(j.q->h, j.d.site));
+      max_blocks = std::max(max_blocks, (j.d.nshots + spb - 1) / spb + 1);
+      max_shots = std::max(max_shots, j.d.nshots);
+    }
+    const int nreq = (int)active.size();
+    hipError_t e = hipMemcpyAsync(desc_dev, desc_host, nreq * sizeof(SampleBatchDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_sample_batch(st, desc_dev, nreq, max_blocks, nt);
+    if (e == hipSuccess) e = launch_partition_batch(st, desc_dev, nreq, max_shots);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) (void)hipGetLastError();
+    std::vector<Job> next;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      ++steps;
+      step_requests += nreq;
+      max_batch = std::max<int64_t>(max_batch, nreq);
+      for (Job& j : active) {
+        const bool last = j.d.site >= j.d.M;
+        if (e == hipSuccess && !last) {
+          j.d.site += 1;
+          next.push_back(j);
+          continue;
+        }
+        (void)hipFreeAsync(j.region, st);
+        in_use -= j.q->sbytes;
+        if (e != hipSuccess) j.q->err = std::string("HIP error '") + hipGetErrorString(e) + "' in the batched sweep";
+        unref(j.q);
+        finish(j.q, e == hipSuccess ? GBS_OK : GBS_E_DEVICE);
+      }
+    }
+    active.swap(next);
     cv_done.notify_all();
     cv_work.notify_all();
   }
@@ -149,31 +349,47 @@ int gbs_server_create(int32_t slots, int64_t budget_bytes, int32_t max_queue, gb
   s->budget = budget_bytes;
   s->slots = slots;
   s->max_queue = max_queue;
-  if (hipGetDevice(&s->device) != hipSuccess) {
+  auto undo = [&](const char* msg) {
+    for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+    if (s->sstream) (void)hipStreamDestroy(s->sstream);
+    if (s->desc_dev) (void)hipFree(s->desc_dev);
+    if (s->desc_host) (void)hipHostFree(s->desc_host);
+    (void)hipGetLastError();
     delete s;
-    return sfail(GBS_E_DEVICE, "hipGetDevice failed");
-  }
+    return sfail(GBS_E_DEVICE, msg);
+  };
+  if (hipGetDevice(&s->device) != hipSuccess) return undo("hipGetDevice failed");
   for (int i = 0; i < slots; ++i) {
     hipStream_t st;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
-      delete s;
-      return sfail(GBS_E_DEVICE, "hipStreamCreateWithFlags failed");
-    }
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return undo("hipStreamCreateWithFlags failed");
     s->streams.push_back(st);
   }
+  if (hipStreamCreateWithFlags(&s->sstream, hipStreamNonBlocking) != hipSuccess)
+    return undo("hipStreamCreateWithFlags failed");
+  if (hipMalloc((void**)&s->desc_dev, kMaxActive * sizeof(SampleBatchDesc)) != hipSuccess)
+    return undo("device allocation of the sweep descriptors failed");
+  if (hipHostMalloc((void**)&s->desc_host, kMaxActive * sizeof(SampleBatchDesc), hipHostMallocDefault) != hipSuccess)
+    return undo("pinned host allocation of the sweep descriptors failed");
   for (int i = 0; i < slots; ++i) s->workers.emplace_back(&gbs_server_s::worker, s, i);
+  s->engine = std::thread(&gbs_server_s::sampler, s);
   *out = s;
   return GBS_OK;
 }
 
 int gbs_server_submit(gbs_server s, const gbs_request* req, int64_t* id) {
   if (!s || !req || !id) return sfail(GBS_E_INVAL, "NULL argument");
-  if (!req->gamma || req->M < 1 || req->shots < 0 || (req->shots > 0 && !req->out))
-    return sfail(GBS_E_INVAL, "invalid request (gamma, M, shots or out)");
-  const int64_t fp = gbs_mps_footprint(req->M, &req->opt, req->shots);
-  if (fp < 0) return sfail(GBS_E_INVAL, "invalid build options");
-  if (fp > s->budget) return sfail(GBS_E_NOMEM, "request footprint exceeds the server's memory budget");
+  if (req->kind < GBS_REQ_BUILD_SAMPLE || req->kind > GBS_REQ_SAMPLE) return sfail(GBS_E_INVAL, "unknown request kind");
+  if (req->shots < 0 || (req->shots > 0 && !req->out)) return sfail(GBS_E_INVAL, "invalid request (shots or out)");
+  int64_t fp = 0;
+  if (req->kind != GBS_REQ_SAMPLE) {
+    if (!req->gamma || req->M < 1) return sfail(GBS_E_INVAL, "invalid request (gamma or M)");
+    fp = gbs_mps_footprint(req->M, &req->opt, req->shots);
+    if (fp < 0) return sfail(GBS_E_INVAL, "invalid build options");
+    if (fp > s->budget) return sfail(GBS_E_NOMEM, "request footprint exceeds the server's memory budget");
+    fp = gbs_mps_footprint(req->M, &req->opt, 0);  // the build's own reservation
+  } else if (req->shots < 1) {
+    return sfail(GBS_E_INVAL, "a sample request needs shots >= 1");
+  }
   Req* q = new (std::nothrow) Req();
   if (!q) return sfail(GBS_E_NOMEM, "host allocation failed");
   q->r = *req;
@@ -184,19 +400,57 @@ int gbs_server_submit(gbs_server s, const gbs_request* req, int64_t* id) {
       delete q;
       return sfail(GBS_E_INVAL, "server is shutting down");
     }
-    if ((int)s->queue.size() >= s->max_queue) {
-      delete q;
-      return sfail(GBS_E_BUSY, "request queue is full");
+    if (req->kind == GBS_REQ_SAMPLE) {
+      auto it = s->residents.find(req->handle);
+      if (it == s->residents.end() || it->second.release) {
+        delete q;
+        return sfail(GBS_E_INVAL, "no resident MPS with this id");
+      }
+      if ((int)s->squeue.size() >= s->max_queue) {
+        delete q;
+        return sfail(GBS_E_BUSY, "request queue is full");
+      }
+      it->second.refs++;
+      q->h = it->second.h;
+      q->resident = req->handle;
+      q->id = s->next_id++;
+      q->t_submit = wall_ms();
+      if (s->t_first < 0) s->t_first = q->t_submit;
+      s->recs[q->id] = q;
+      s->squeue.push_back(q);
+      ++s->submitted;
+      *id = q->id;
+    } else {
+      if ((int)s->queue.size() >= s->max_queue) {
+        delete q;
+        return sfail(GBS_E_BUSY, "request queue is full");
+      }
+      q->id = s->next_id++;
+      q->t_submit = wall_ms();
+      if (s->t_first < 0) s->t_first = q->t_submit;
+      s->recs[q->id] = q;
+      s->queue.push_back(q);
+      ++s->submitted;
+      *id = q->id;
     }
-    q->id = s->next_id++;
-    q->t_submit = wall_ms();
-    if (s->t_first < 0) s->t_first = q->t_submit;
-    s->recs[q->id] = q;
-    s->queue.push_back(q);
-    ++s->submitted;
-    *id = q->id;
   }
   s->cv_work.notify_one();
+  s->cv_sample.notify_one();
+  return GBS_OK;
+}
+
+int gbs_server_release(gbs_server s, int64_t handle) {
+  if (!s) return sfail(GBS_E_INVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->residents.find(handle);
+  if (it == s->residents.end() || it->second.release) return sfail(GBS_E_INVAL, "no resident MPS with this id");
+  it->second.release = true;
+  if (it->second.refs == 0) {
+    s->in_use -= it->second.bytes;
+    gbs_mps_free(it->second.h);
+    s->residents.erase(it);
+  }
+  s->cv_work.notify_all();
   return GBS_OK;
 }
 
@@ -225,10 +479,13 @@ int gbs_server_wait(gbs_server s, int64_t id, gbs_result* res) {
     res->status = q->status;
     res->max_bond = q->max_bond;
     res->eps_max = q->eps_max;
-    res->queue_ms = q->t_start - q->t_submit;
-    res->build_ms = q->t_built - q->t_start;
-    res->sample_ms = q->t_done - q->t_built;
+    const double t_start = q->t_start > 0 ? q->t_start : q->t_done;
+    const double t_built = q->t_built > 0 ? q->t_built : t_start;
+    res->queue_ms = t_start - q->t_submit;
+    res->build_ms = t_built - t_start;
+    res->sample_ms = q->t_done - t_built;
     res->latency_ms = q->t_done - q->t_submit;
+    res->handle = q->r.kind == GBS_REQ_BUILD && rc == GBS_OK ? q->id : 0;
   }
   std::string err = q->err;
   delete q;
@@ -253,6 +510,10 @@ int gbs_server_stats(gbs_server s, gbs_server_stats_t* out) {
   out->wall_s = s->t_first >= 0 ? std::max(0.0, (s->t_last - s->t_first) / 1000.0) : 0.0;
   out->throughput_rps = out->wall_s > 0 ? (double)s->completed / out->wall_s : 0.0;
   out->peak_bytes = s->peak;
+  out->resident = (int64_t)s->residents.size();
+  out->sweep_steps = s->steps;
+  out->mean_batch = s->steps > 0 ? (double)s->step_requests / (double)s->steps : 0.0;
+  out->max_batch = s->max_batch;
   return GBS_OK;
 }
 
@@ -261,6 +522,7 @@ int gbs_server_reset_stats(gbs_server s) {
   std::lock_guard<std::mutex> lk(s->mu);
   s->lat.clear();
   s->submitted = s->completed = s->failed = 0;
+  s->steps = s->step_requests = s->max_batch = 0;
   s->t_first = -1.0;
   s->t_last = 0.0;
   s->peak = s->in_use;
@@ -275,7 +537,18 @@ void gbs_server_destroy(gbs_server s) {
   }
   s->cv_work.notify_all();
   for (std::thread& t : s->workers) t.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);  // builds are done: wake the sweep to drain
+  }
+  s->cv_sample.notify_all();
+  s->engine.join();
+  for (auto& kv : s->residents) gbs_mps_free(kv.second.h);
+  (void)hipStreamSynchronize(s->sstream);
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  (void)hipStreamDestroy(s->sstream);
+  (void)hipFree(s->desc_dev);
+  (void)hipHostFree(s->desc_host);
   for (auto& kv : s->recs) delete kv.second;
   delete s;
 }

@@ -19,7 +19,7 @@ from ._lib import BuildOpts, Request, Result, ServerStats, check, lib
 class Ticket:
     id: int
     out: torch.Tensor
-    gamma: torch.Tensor
+    gamma: torch.Tensor | None
 
 
 class Server:
@@ -36,7 +36,10 @@ class Server:
         self.budget_bytes = budget_bytes
 
     def submit(self, gamma: torch.Tensor, d: int, chi: int, shots: int, seed: int, precision: str = "fp32",
-               dstar: float = 1.0 + 1e-10, trunc_rel: float = 0.0, out: torch.Tensor | None = None) -> Ticket:
+               dstar: float = 1.0 + 1e-10, trunc_rel: float = 0.0, out: torch.Tensor | None = None,
+               keep: bool = False) -> Ticket:
+        """Build (and keep the MPS resident when `keep`), then draw `shots`
+        samples.  A kept MPS is named by the ticket's id (sample(), release())."""
         if not isinstance(gamma, torch.Tensor) or not gamma.is_cuda or gamma.dtype != torch.float64:
             raise ValueError("gamma must be a CUDA float64 tensor")
         gamma = gamma.contiguous()
@@ -48,10 +51,27 @@ class Server:
         req = Request(gamma=gamma.data_ptr(), M=M,
                       opt=BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS[precision], flags=0,
                                     trunc_rel=trunc_rel),
-                      shots=shots, seed=seed & (2 ** 64 - 1), out=out.data_ptr() if shots > 0 else None)
+                      shots=shots, seed=seed & (2 ** 64 - 1), out=out.data_ptr() if shots > 0 else None,
+                      kind=_lib.GBS_REQ_BUILD if keep else _lib.GBS_REQ_BUILD_SAMPLE, handle=0)
         rid = ctypes.c_int64()
         check(lib().gbs_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
         return Ticket(rid.value, out, gamma)
+
+    def sample(self, handle: int, M: int, shots: int, seed: int, out: torch.Tensor | None = None,
+               device="cuda") -> Ticket:
+        """Draw `shots` samples from the resident MPS named `handle` (the id
+        of the keep=True submit that built it); M: its mode count."""
+        if out is None:
+            out = torch.empty((shots, M), dtype=torch.int32, device=device)
+        req = Request(gamma=None, M=M, opt=BuildOpts(), shots=shots, seed=seed & (2 ** 64 - 1),
+                      out=out.data_ptr(), kind=_lib.GBS_REQ_SAMPLE, handle=int(handle))
+        rid = ctypes.c_int64()
+        check(lib().gbs_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        return Ticket(rid.value, out, None)
+
+    def release(self, handle: int) -> None:
+        """Free a resident MPS once the samples admitted or queued on it are done."""
+        check(lib().gbs_server_release(self._h, int(handle)))
 
     def poll(self, t: Ticket) -> bool:
         done = ctypes.c_int32()

@@ -32,28 +32,90 @@ def _alone(torch, gamma, w, shots, seed, precision):
     return s
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_alone_equals_mix(torch_cuda, precision):
+@pytest.mark.parametrize("precision,n,shots", [("fp32", 64, 10_000), ("fp64", 10, 2000)])
+def test_alone_equals_mix(torch_cuda, precision, n, shots):
+    """n requests of the serving mix submitted at once (FP32: their samples
+    drawn by the batched sweep, many requests per launch) against the same
+    requests built and sampled alone through gbs_mps_build / gbs_mps_sample,
+    and, for a few, against a server holding only that request: identical
+    samples, integer for integer."""
     torch = torch_cuda
     from paper_2512_10643_amd import serving as S
-    reqs = W.serving_requests(10)
-    _say(f"case: serving alone-vs-mix, 10 requests, {precision}")
+    reqs = W.serving_requests(n)
+    _say(f"case: serving alone-vs-mix, {n} requests x {shots} shots, {precision}")
     gam = [torch.tensor(r["workload"].gamma, device="cuda") for r in reqs]
-    alone = [_alone(torch, g, r["workload"], 2000, r["seed"], precision) for r, g in zip(reqs, gam)]
+    alone = [_alone(torch, g, r["workload"], shots, r["seed"], precision) for r, g in zip(reqs, gam)]
     with S.Server(slots=4) as srv:
-        tickets = [srv.submit(g, r["workload"].d, r["workload"].chi, 2000, r["seed"], precision=precision)
+        tickets = [srv.submit(g, r["workload"].d, r["workload"].chi, shots, r["seed"], precision=precision)
                    for r, g in zip(reqs, gam)]
         res = [srv.wait(t) for t in tickets]
         st = srv.stats()
-    assert st["completed"] == 10 and st["failed"] == 0
+    _say(f"  p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms; sweep steps {st['sweep_steps']}, "
+         f"requests per step mean {st['mean_batch']:.1f} max {st['max_batch']}")
+    assert st["completed"] == n and st["failed"] == 0
     for a, t, r in zip(alone, tickets, res):
         assert r["status"] == 0
         assert torch.equal(a, t.out)
         assert r["latency_ms"] >= r["build_ms"] + r["sample_ms"] - 1e-6
     assert st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    if precision == "fp32":
+        assert st["max_batch"] > 1  # the sweep carried several requests at once
+        for i in (0, 1, n - 1):     # a server holding one request alone
+            r, g = reqs[i], gam[i]
+            with S.Server(slots=1) as srv:
+                t = srv.submit(g, r["workload"].d, r["workload"].chi, shots, r["seed"], precision=precision)
+                srv.wait(t)
+            assert torch.equal(t.out, tickets[i].out)
     # parity of every sample (pair creation only)
     for t in tickets:
         assert int((t.out.sum(1) % 2).abs().sum()) == 0
+
+
+def test_resident_mps_and_sample_requests(torch_cuda):
+    """Build requests that keep their MPS resident, then sample-only requests
+    against them (several seeds and shot counts, interleaved with
+    build + sample requests), then release: every sample equals
+    gbs_mps_sample on a directly built MPS with the same seed; a released
+    MPS takes no more requests and its memory returns to the budget."""
+    torch = torch_cuda
+    from paper_2512_10643_amd import serving as S
+    from paper_2512_10643_amd._lib import GbsError, GBS_E_INVAL
+    from paper_2512_10643_amd import mps as gmps
+    reqs = W.serving_requests(6)
+    _say("case: serving with resident MPS and sample-only requests")
+    gam = [torch.tensor(r["workload"].gamma, device="cuda") for r in reqs]
+    with S.Server(slots=3) as srv:
+        keep = [srv.submit(gam[i], reqs[i]["workload"].d, reqs[i]["workload"].chi, 0, 0, keep=True)
+                for i in range(3)]
+        handles = [srv.wait(t)["handle"] for t in keep]
+        assert handles == [t.id for t in keep]
+        assert srv.stats()["resident"] == 3
+        jobs = []
+        for k in range(4):
+            for i in range(3):
+                M = reqs[i]["workload"].M
+                jobs.append((i, 500 + 3001 * k, 77 + 10 * k + i,
+                             srv.sample(handles[i], M, 500 + 3001 * k, 77 + 10 * k + i)))
+            j = 3 + (k % 3)
+            w = reqs[j]["workload"]
+            jobs.append((j, 4000, 5 + k, srv.submit(gam[j], w.d, w.chi, 4000, 5 + k)))
+        outs = [(i, shots, seed, srv.wait(t), t) for i, shots, seed, t in jobs]
+        bytes_before = srv.stats()["peak_bytes"]
+        for hnd in handles:
+            srv.release(hnd)
+        with pytest.raises(GbsError) as e:
+            srv.sample(handles[0], reqs[0]["workload"].M, 10, 1)
+        assert e.value.code == GBS_E_INVAL
+        assert srv.stats()["resident"] == 0
+    for i, shots, seed, r, t in outs:
+        assert r["status"] == 0
+        w = reqs[i]["workload"]
+        h = gmps.build(gam[i], w.d, w.chi, precision="fp32")
+        ref = h.sample(shots, seed)
+        torch.cuda.synchronize()
+        h.free()
+        assert torch.equal(ref, t.out), (i, shots, seed)
+    assert bytes_before > 0
 
 
 def test_failure_stays_with_its_request(torch_cuda):
