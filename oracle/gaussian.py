@@ -233,6 +233,98 @@ def gsvd(gamma: np.ndarray, dstar: float = 1.0 + 1e-10, first: int = 1, last: in
     return GSVDResult(Q=Qs, cuts=cuts, n_in=n_in, n_out=n_out)
 
 
+def gsvd_independent(gamma: np.ndarray, dstar: float = 1.0 + 1e-10) -> GSVDResult:
+    """Every site's Gaussian data computed on its own (Sec. III.A: each tensor
+    can be generated independently), with bond modes shared between
+    neighbours.
+
+    Site m: the chain started at cut m-1 straight from Gamma (the modes
+    a_1..a_{m-1} in place of r_{m-2}; ``gsvd(first=)``), then one chain step
+    to cut m, which gives Q^m.  Cut m is thus met twice: as the right bond of
+    site m (its chain step) and as the left bond of site m+1 (its start from
+    Gamma).  The two give the same Bogoliubov modes b_q of cut m up to a
+    rotation of each mode's (x, p) pair, i.e. a phase e^{i theta_q} per mode
+    (non-degenerate D; degenerate pairs are not separated by this).  Writing
+    the b-mode quadratures of both as functions of the quadratures of
+    a_1..a_m (through the b-mode map of Eq. bmode, T = M^-1 as used for the
+    residual), the 2x2 block of step-rows times the inverse of restart-rows
+    for mode q is that rotation, theta_q its angle.  Multiplying the rows and
+    columns of l_q in Q^m by e^{i theta_q} relabels site m's right bond in the
+    modes of site m+1's left bond, so the local tensors fit together as the
+    chain's do (up to a gauge on each bond).
+
+    Returns a GSVDResult like ``gsvd``: Q^m aligned, the cuts as the chain
+    steps give them."""
+    g = np.asarray(gamma, dtype=np.float64)
+    N = g.shape[0] // 2
+    step_t, start_t, Qs, cuts, n_in, n_out = {}, {}, [], [], [], []
+    for m in range(1, N + 1):
+        n0, t0 = 0, None
+        if m >= 2:  # cut m-1 from Gamma: its b-mode map on a_1..a_{m-1}
+            k = m - 1
+            idx = np.r_[0:k, N:N + k]
+            d0, s0 = williamson(g[np.ix_(idx, idx)])
+            n0 = int(min(np.count_nonzero(d0 >= dstar), N - k))
+            t0 = bmode_quadrature_map(*bogoliubov_from_symplectic(s0))
+            start_t[k] = (t0, n0)
+        r = gsvd(g, dstar, first=max(1, m - 1), last=m)
+        Qs.append(r.Q[-1].copy())
+        n_in.append(r.n_in[-1])
+        n_out.append(r.n_out[-1])
+        if m < N:
+            cuts.append(r.cuts[-1])
+            # the chain step's b-mode map on (r_{m-1}, a_m), from the same L block
+            res_l = _left_block_of_step(g, dstar, m)
+            d1, s1 = williamson(res_l)
+            step_t[m] = (bmode_quadrature_map(*bogoliubov_from_symplectic(s1)), n0)
+    for m in range(1, N):
+        t1, n0 = step_t[m]
+        tr, n = start_t[m]
+        nl = n0 + 1
+        f = np.zeros((2 * nl, 2 * m))  # quadrature rows of (r_{m-1}, a_m) on a_1..a_m
+        if m >= 2:
+            t0, _ = start_t[m - 1]
+            k = m - 1
+            for q in range(n0):
+                f[q, np.r_[0:k, m:m + k]] = t0[q]
+                f[nl + q, np.r_[0:k, m:m + k]] = t0[k + q]
+        f[n0, m - 1] = 1.0
+        f[2 * nl - 1, 2 * m - 1] = 1.0
+        x = t1 @ f @ np.linalg.inv(tr)
+        ph = np.ones(n, dtype=np.complex128)
+        for q in range(n):
+            b = x[np.ix_([q, nl + q], [q, m + q])]
+            ph[q] = np.exp(1j * np.arctan2(b[1, 0] - b[0, 1], b[0, 0] + b[1, 1]))
+        Q = Qs[m - 1]
+        Q[nl:nl + n, :] *= ph[:, None]
+        Q[:, nl:nl + n] *= ph[None, :]
+    return GSVDResult(Q=Qs, cuts=cuts, n_in=n_in, n_out=n_out)
+
+
+def _left_block_of_step(g, dstar, m):
+    """Covariance of the left block (r_{m-1}, a_m) that the chain started at
+    cut m-1 from Gamma brings to Williamson form at cut m."""
+    N = g.shape[0] // 2
+    if m == 1:
+        return g[np.ix_([0, N], [0, N])]
+    k = m - 1
+    idx = np.r_[0:k, N:N + k]
+    d0, s0 = williamson(g[np.ix_(idx, idx)])
+    n_e = int(min(np.count_nonzero(d0 >= dstar), N - k))
+    t = bmode_quadrature_map(*bogoliubov_from_symplectic(s0))
+    n_r = N - k
+    f = np.zeros((2 * (n_e + n_r), 2 * N))
+    f[np.ix_(np.arange(n_e), idx)] = t[:n_e, :]
+    f[np.ix_(n_e + n_r + np.arange(n_e), idx)] = t[k:k + n_e, :]
+    f[n_e + np.arange(n_r), k + np.arange(n_r)] = 1.0
+    f[2 * n_e + n_r + np.arange(n_r), N + k + np.arange(n_r)] = 1.0
+    res = f @ g @ f.T
+    res = 0.5 * (res + res.T)
+    n_tot = n_e + n_r
+    il = np.r_[0:n_e + 1, n_tot:n_tot + n_e + 1]
+    return res[np.ix_(il, il)]
+
+
 @dataclasses.dataclass
 class TwoSidedCut:
     """Diagnostics of one cut of the two-sided construction."""
