@@ -67,9 +67,21 @@ typedef enum {
  * the truncation sweep recompresses every bond to at most chi singular
  * directions, a global truncation in place of the local analytic one
  * (Sec. II.C.1); 0 or <= chi: D_build = chi.  chi_build <= 4096 and
- * chi_build * d <= 8192; single-site builds do not use it. */
+ * chi_build * d <= 8192; single-site builds do not use it.
+ * Gaussian SVD: when every site's first block fits one workgroup
+ * (2 (M - 1) <= 600), each site's Gaussian data is computed on its own, all
+ * sites at once (Sec. III.A): site m starts at cut m - 1 straight from Gamma
+ * and takes one chain step to cut m; the two neighbours of a cut then agree
+ * on its Bogoliubov modes up to a phase per mode, which is read off their
+ * b-mode maps and put into Q^m.  A build with a bond mode weaker than
+ * Lambda = 1e-3 (D - 1 < 2e-6, whose phase the two sides cannot align to
+ * FP64 accuracy) reruns as the chain, as does one whose two sides of a cut
+ * count different modes.  GBS_CHAIN_GSVD forces the sequential chain (cut
+ * after cut, Sec. II.B), which larger M always take; gsvd_mode in
+ * gbs_mps_info_t tells which ran. */
 #define GBS_KEEP_RAW 1u
 #define GBS_DENSE_SAMPLER 2u
+#define GBS_CHAIN_GSVD 4u
 typedef struct {
   int32_t d;
   int32_t chi;
@@ -205,6 +217,8 @@ typedef struct {
   int32_t eig_sweeps;      /* sweeps of the bond eigensolver in the truncation step */
   int32_t sampler_layout;  /* FP32 sampling operand: 0 none (FP64 builds, or a bond the
                               MFMA sampler cannot take), 1 dense, 2 photon-parity sectors */
+  int32_t gsvd_mode;       /* 0: sequential Gaussian SVD chain; 1: every site's Gaussian data on its
+                              own, bond modes aligned between neighbours (Sec. III.A) */
 } gbs_mps_info_t;
 
 /* Fill `info`; optional host arrays (may be NULL):

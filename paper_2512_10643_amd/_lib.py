@@ -20,6 +20,7 @@ ERROR_NAMES = {0: "OK", -1: "INVAL", -2: "NOT_PD", -3: "NOT_PURE", -4: "NOMEM", 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 GBS_KEEP_RAW = 1
 GBS_DENSE_SAMPLER = 2
+GBS_CHAIN_GSVD = 4
 # Size of the static device array gbs_mps_sample_noalloc samples on (the
 # header's GBS_SAMPLE_NOALLOC_SCRATCH_BYTES).
 GBS_SAMPLE_NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -59,7 +60,7 @@ class InfoT(ctypes.Structure):
                 ("norm_raw", ctypes.c_double), ("bytes", ctypes.c_int64), ("pco_updates", ctypes.c_int64),
                 ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
                 ("t_svd_ms", ctypes.c_double), ("eig_sweeps", ctypes.c_int32),
-                ("sampler_layout", ctypes.c_int32)]
+                ("sampler_layout", ctypes.c_int32), ("gsvd_mode", ctypes.c_int32)]
 
 
 class FilterOpts(ctypes.Structure):

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -138,6 +139,7 @@ struct gbs_mps_s {
   double t_gsvd = 0, t_kept = 0, t_pco = 0, t_svd = 0;
   int eig_sweeps = 0;            // sweeps of the bond eigensolver
   int single_site = 0;           // > 0: the handle holds that site's PCO tensor only
+  int gsvd_independent = 0;      // 1: each site's Gaussian SVD ran on its own (bond modes aligned)
   // canonical tensors
   void* tens = nullptr;          // contiguous, element size esz
   size_t esz = 16;
@@ -482,6 +484,154 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   return GBS_OK;
 }
 
+// Every site's Gaussian data on its own, all sites in one batch (Sec. III.A):
+// site m starts the chain at cut m - 1 straight from Gamma and takes one step
+// to cut m, forming Q^m; then the bond modes of every cut are aligned between
+// its two neighbours (a phase per mode, put into Q^m), so the tensors fit
+// together as the sequential chain's do.  Fills h->Q (leading dimension
+// h->ld_q), ne (host, M + 1), and the Lambda of every cut on the device
+// (*lam, row stride ld_lam) and on the host (lamh).  Returns GBS_DEVERR_ALIGN
+// through *dev_err when the two sides of a cut count different entangled
+// pairs (a D within rounding of D*), and the caller then runs the chain.
+int gsvd_independent(gbs_mps_s* h, const double* gamma, int M, double dstar, hipStream_t st, DevArena& tmp, int* err,
+                     std::vector<int>& ne, std::vector<double>& lamh, double** lam, long ld_lam, int* dev_err) {
+  // one pool of doubles and one of ints, carved per site: site m's blocks are
+  // at most 2m wide (cut m - 1 from Gamma: 2(m - 1); its step: 2(n_e + 1)).
+  // carve(m, base, ...) lays site m's buffers out from `base` (NULL: count).
+  std::vector<GsvdArgs> a0(M), a1(M);
+  std::vector<int> c0(M), c1(M);
+  std::vector<double*> keep(M);
+  std::vector<long> keep_ld(M);
+  auto carve = [&](int m, double* base, int* ip) -> long {
+    const long n2 = 2L * m, lu = m + 1;
+    long used = 0;
+    auto take = [&](long n) {
+      double* r = base ? base + used : nullptr;
+      used += (n + 31) / 32 * 32;
+      return r;
+    };
+    GsvdArgs g{};
+    g.M = M;
+    g.dstar = dstar;
+    g.gamma = gamma;
+    g.err = err;
+    g.ne = ip;
+    g.ws_ord = ip ? ip + (M + 1) : nullptr;
+    g.ld_dsym = lu;
+    g.dsym = take((long)(M + 1) * lu);
+    g.lam = take((long)(M + 1) * lu);
+    g.ld_drr = n2;
+    g.ld_cr = 2L * M;
+    double* drr0 = take(n2 * n2);
+    double* drr1 = take(n2 * n2);
+    double* cr0 = take(n2 * 2L * M);
+    double* cr1 = take(n2 * 2L * M);
+    g.Q = h->Q;
+    g.q_stride = h->q_stride;
+    g.ld_q = h->ld_q;
+    g.ld_ws = n2;
+    g.ws_G = take(n2 * n2);
+    g.ws_L = take(n2 * n2);
+    g.ws_A = take(n2 * n2);
+    g.ws_B = take(n2 * n2);
+    g.ws_E = take(n2 * n2);
+    g.ws_O = take(n2 * n2);
+    g.ws_S = take(n2 * n2);
+    g.ws_W = take(n2 * n2);
+    double* kp = take(n2 * n2);
+    g.ws_vec = take(3 * n2);
+    g.ws_pack = take(n2 * (n2 + 1) / 2);
+    g.ws_w = take(n2);
+    g.ld_glr = 2L * M;
+    g.ws_glr = take(n2 * 2L * M);
+    g.ws_tri = take(2 * n2 * n2 + 4 * n2);
+    g.ld_u = lu;
+    g.ws_U = (cplx64*)take(2 * lu * lu);
+    g.ws_V = (cplx64*)take(2 * lu * lu);
+    g.ws_aug = (cplx64*)take(2 * lu * 2 * lu);
+    g.q_first = m;
+    if (base) {
+      keep[m - 1] = kp;
+      keep_ld[m - 1] = n2;
+      a0[m - 1] = g;
+      a0[m - 1].drr_in = drr0;
+      a0[m - 1].cr_in = cr0;
+      a0[m - 1].drr_out = drr1;
+      a0[m - 1].cr_out = cr1;
+      a1[m - 1] = g;
+      a1[m - 1].drr_in = drr1;
+      a1[m - 1].cr_in = cr1;
+      a1[m - 1].drr_out = drr0;
+      a1[m - 1].cr_out = cr0;
+      c0[m - 1] = m - 1;
+      c1[m - 1] = m;
+    }
+    return used;
+  };
+  std::vector<long> dof(M + 1), iof(M + 1);
+  long dtot = 0, itot = 0;
+  for (int m = 1; m <= M; ++m) {
+    dof[m] = dtot;
+    dtot += carve(m, nullptr, nullptr);
+    iof[m] = itot;
+    itot += (M + 1) + 2L * m + 64;  // ne, ord
+  }
+  double* dpool;
+  int* ipool;
+  HIP_CHECK_RET(dalloc(tmp, &dpool, (size_t)dtot));
+  HIP_CHECK_RET(dalloc(tmp, &ipool, (size_t)itot));
+  HIP_CHECK_RET(hipMemsetAsync(ipool, 0, (size_t)itot * sizeof(int), st));
+  for (int m = 1; m <= M; ++m) carve(m, dpool + dof[m], ipool + iof[m]);
+  std::vector<GsvdAlign> al(M - 1);
+  for (int m = 1; m < M; ++m) {
+    GsvdAlign& x = al[m - 1];
+    x.t0 = m >= 2 ? keep[m - 1] : nullptr;
+    x.ldt0 = keep_ld[m - 1];
+    x.ne_e = a0[m - 1].ne;
+    x.t1 = a0[m - 1].ws_A;
+    x.ldt1 = a0[m - 1].ld_ws;
+    x.tr = keep[m];
+    x.ldtr = keep_ld[m];
+    x.ne_r = a0[m].ne;
+    x.Q = h->Q + (long)(m - 1) * h->q_stride;
+    x.ld_q = h->ld_q;
+    x.m = m;
+  }
+  GsvdArgs *a0d, *a1d;
+  int *c0d, *c1d;
+  double** keepd;
+  long* keepld;
+  GsvdAlign* ald;
+  HIP_CHECK_RET(dalloc(tmp, &a0d, M));
+  HIP_CHECK_RET(dalloc(tmp, &a1d, M));
+  HIP_CHECK_RET(dalloc(tmp, &c0d, M));
+  HIP_CHECK_RET(dalloc(tmp, &c1d, M));
+  HIP_CHECK_RET(dalloc(tmp, &keepd, M));
+  HIP_CHECK_RET(dalloc(tmp, &keepld, M));
+  HIP_CHECK_RET(dalloc(tmp, &ald, std::max(M - 1, 1)));
+  HIP_CHECK_RET(hipMemcpyAsync(a0d, a0.data(), M * sizeof(GsvdArgs), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(a1d, a1.data(), M * sizeof(GsvdArgs), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(c0d, c0.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(c1d, c1.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(keepd, keep.data(), M * sizeof(double*), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(hipMemcpyAsync(keepld, keep_ld.data(), M * sizeof(long), hipMemcpyHostToDevice, st));
+  if (M > 1) HIP_CHECK_RET(hipMemcpyAsync(ald, al.data(), (M - 1) * sizeof(GsvdAlign), hipMemcpyHostToDevice, st));
+  HIP_CHECK_RET(launch_gsvd_independent(st, a0d, a1d, c0d, c1d, M, keepd, keepld, ald, M - 1, err));
+  int* ne_d;
+  HIP_CHECK_RET(dalloc(tmp, &ne_d, M + 1));
+  HIP_CHECK_RET(dalloc(tmp, lam, (size_t)(M + 1) * ld_lam));
+  HIP_CHECK_RET(hipMemsetAsync(ne_d, 0, (M + 1) * sizeof(int), st));
+  HIP_CHECK_RET(hipMemsetAsync(*lam, 0, (M + 1) * ld_lam * sizeof(double), st));
+  HIP_CHECK_RET(launch_gsvd_gather_cuts(st, a1d, M, ne_d, *lam, ld_lam));
+  ne.assign(M + 1, 0);
+  lamh.assign((size_t)(M + 1) * ld_lam, 0.0);
+  HIP_CHECK_RET(hipMemcpyAsync(ne.data(), ne_d, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(lamh.data(), *lam, lamh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipMemcpyAsync(dev_err, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipStreamSynchronize(st));
+  return GBS_OK;
+}
+
 int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_t st, gbs_mps_s* h, int only_site) {
   // kept states per cut (D_build); the truncation sweep caps bonds at h->chi
   const int d = opt->d, chi = only_site ? opt->chi : std::max(opt->chi, opt->chi_build);
@@ -565,30 +715,62 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_V, (size_t)ga.ld_u * ga.ld_u));
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_aug, (size_t)ga.ld_u * 2 * ga.ld_u));
   ga.q_first = only_site;  // a single-site build forms Q^s alone
-  if (restart) {
+  std::vector<int> ne(M + 1);
+  std::vector<double> lamh((size_t)(M + 1) * ga.ld_dsym);
+  int herr = 0;
+  // Full builds whose every first block fits one workgroup (2 (M - 1) wide
+  // for the last site) build each site's Gaussian data on its own; otherwise,
+  // or on request, the sequential chain runs.
+  bool chain = only_site || M < 3 || 2 * (M - 1) > GBS_GSVD_N2_MAX || (opt->flags & GBS_CHAIN_GSVD);
+  if (!chain) {
+    double* lam_ind = nullptr;
+    if (int rc = gsvd_independent(h, gamma, M, opt->dstar, st, tmp, err, ne, lamh, &lam_ind, ga.ld_dsym, &herr))
+      return rc;
+    // The two sides of a cut fix a bond mode's (x, p) rotation separately.  A
+    // mode with D close to 1 sits next to the vacuum cluster of its block
+    // (D = 1 exactly), so each side's mode carries an admixture of vacuum
+    // modes of order eps / (D - 1) that a per-mode phase cannot align; its
+    // weight in the state is Lambda ~ sqrt((D - 1) / 2), so amplitudes move
+    // by about eps n / Lambda.  Below Lambda = 1e-3 (D - 1 < 2e-6) that
+    // exceeds the FP64 accuracy the chain keeps (1e-10 at 2 M = 600), and
+    // the chain runs instead.
+    bool weak = false;
+    if (!herr)
+      for (int m = 1; m < M && !weak; ++m)
+        for (int q = 0; q < ne[m]; ++q)
+          if (lamh[(size_t)m * ga.ld_dsym + q] < GBS_GSVD_INDEP_LAMBDA_MIN) weak = true;
+    if (herr == GBS_DEVERR_ALIGN || weak) {  // a cut counted differently on its two sides, or a weak mode
+      HIP_CHECK_RET(hipMemsetAsync(err, 0, sizeof(int), st));
+      herr = 0;
+      chain = true;
+    } else {
+      ga.lam = lam_ind;
+      h->gsvd_independent = 1;
+    }
+  }
+  if (chain && restart) {
     ga.drr_in = drr[(restart + 1) & 1];
     ga.cr_in = cr[(restart + 1) & 1];
     HIP_CHECK_RET(launch_gsvd_restart(st, ga, restart));
   }
-  const int m_first = restart ? restart : 1, m_last = only_site ? only_site : M;
-  for (int m = m_first; m <= m_last; ++m) {
-    ga.drr_in = drr[(m + 1) & 1];
-    ga.drr_out = drr[m & 1];
-    ga.cr_in = cr[(m + 1) & 1];
-    ga.cr_out = cr[m & 1];
-    HIP_CHECK_RET(launch_gsvd_cut(st, ga, m, n2max));
+  if (chain) {
+    const int m_first = restart ? restart : 1, m_last = only_site ? only_site : M;
+    for (int m = m_first; m <= m_last; ++m) {
+      ga.drr_in = drr[(m + 1) & 1];
+      ga.drr_out = drr[m & 1];
+      ga.cr_in = cr[(m + 1) & 1];
+      ga.cr_out = cr[m & 1];
+      HIP_CHECK_RET(launch_gsvd_cut(st, ga, m, n2max));
+    }
+    if (only_site && only_site < M)
+      HIP_CHECK_RET(launch_gsvd_q(st, ga, only_site));
+    else
+      HIP_CHECK_RET(launch_gsvd_last_q(st, ga));
+    HIP_CHECK_RET(hipMemcpyAsync(ne.data(), ga.ne, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK_RET(hipMemcpyAsync(lamh.data(), ga.lam, lamh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK_RET(hipStreamSynchronize(st));
   }
-  if (only_site && only_site < M)
-    HIP_CHECK_RET(launch_gsvd_q(st, ga, only_site));
-  else
-    HIP_CHECK_RET(launch_gsvd_last_q(st, ga));
-  std::vector<int> ne(M + 1);
-  std::vector<double> lamh((size_t)(M + 1) * ga.ld_dsym);
-  int herr = 0;
-  HIP_CHECK_RET(hipMemcpyAsync(ne.data(), ga.ne, (M + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK_RET(hipMemcpyAsync(lamh.data(), ga.lam, lamh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK_RET(hipStreamSynchronize(st));
   if (herr) return fail(herr == GBS_DEVERR_NOT_PD ? GBS_E_NOT_PD : GBS_E_INTERNAL, deverr_msg(herr));
   if (only_site)  // only the two cuts of the site were formed
     for (int m = 0; m <= M; ++m)
@@ -1026,7 +1208,7 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   if (opt->chi_build < 0 || opt->chi_build > GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi_build must be in [0, 4096]");
   if (!only_site && (long)opt->chi_build * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi_build * d too large");
   if (opt->d > 64) return fail(GBS_E_INVAL, "d must be <= 64");
-  if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER)) return fail(GBS_E_INVAL, "unknown build flag");
+  if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER | GBS_CHAIN_GSVD)) return fail(GBS_E_INVAL, "unknown build flag");
   gbs_mps_s* h = new (std::nothrow) gbs_mps_s();
   if (!h) return fail(GBS_E_NOMEM, "host allocation failed");
   h->M = M;
@@ -1472,6 +1654,7 @@ int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, do
   info->t_svd_ms = h->t_svd;
   info->eig_sweeps = h->eig_sweeps;
   info->sampler_layout = h->packed ? (h->psplit ? 2 : 1) : 0;
+  info->gsvd_mode = h->gsvd_independent;
   for (int m = 0; m <= h->M; ++m) {
     if (bond) bond[m] = h->bond[m];
     if (ne) ne[m] = h->ne[m];

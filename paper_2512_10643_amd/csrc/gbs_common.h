@@ -18,6 +18,7 @@ enum {
   GBS_DEVERR_KMAX = 6,         // too many occupied modes in a kept state
   GBS_DEVERR_JACOBI = 7,       // Jacobi of a Williamson form did not converge
   GBS_DEVERR_JACOBI_BOND = 8,  // Hermitian Jacobi of a bond environment did not converge
+  GBS_DEVERR_ALIGN = 9,        // the two sides of a cut counted different entangled pairs
 };
 
 struct cplx64 { double re, im; };

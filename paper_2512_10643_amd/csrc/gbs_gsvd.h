@@ -4,6 +4,7 @@
 
 #define GBS_GSVD_N2_MAX 600      // 2 * (n_e^{m-1} + 1) handled by one workgroup
 #define GBS_GSVD_LDS_N2 176      // packed symmetric working matrix kept in LDS up to this size
+#define GBS_GSVD_INDEP_LAMBDA_MIN 1e-3  // weakest bond mode (Lambda) a full build aligns site by site
 
 struct GsvdArgs {
   int M;
@@ -32,6 +33,23 @@ struct GsvdArgs {
   int q_first;           // Q^j is formed beside cut j + 1 only for j >= q_first
 };
 
+// Alignment of the bond modes of cut m between site m (its chain step) and
+// site m + 1 (its start from Gamma at cut m).
+struct GsvdAlign {
+  const double* t0;   // site m's start map at cut m-1: active rows (x then p), 2 (m-1) columns; NULL when m = 1
+  long ldt0;
+  const int* ne_e;    // site m's ne (ne_e[m-1]: r_{m-1} modes, ne_e[m]: l_m modes)
+  const double* t1;   // site m's step map at cut m: active rows, 2 (ne_e[m-1] + 1) columns
+  long ldt1;
+  const double* tr;   // site m+1's start map at cut m: active rows, 2 m columns
+  long ldtr;
+  const int* ne_r;    // site m+1's ne (ne_r[m] must equal ne_e[m])
+  cplx64* Q;          // Q^m, row stride ld_q
+  long ld_q;
+  int m;
+  int pad;
+};
+
 hipError_t launch_validate(hipStream_t st, const double* gamma, int M, double* scal, double* wsM, int* err);
 // Cut m: Williamson step of cut m (with, beside it, Q^{m-1} of the previous
 // cut) and the pairing and residual of cut m.
@@ -45,6 +63,20 @@ hipError_t launch_gsvd_q(hipStream_t st, const GsvdArgs& a, int m);
 // quadratures and ne[k-1] = k - 1.  Needs 2 k <= n2max (the leading dimension
 // and row count of drr_in, the row count of cr_in).
 hipError_t launch_gsvd_restart(hipStream_t st, const GsvdArgs& a, int k);
+// Every site's Gaussian data on its own: element e (site m) runs cut
+// cut0[e] = m - 1 from Gamma (args0; 0 for site 1) and then cut1[e] = m
+// (args1: the same workspaces, residual buffers swapped), forming Q^m (for
+// the last site, the residual's own pair matrix).  keep_dst[e] / keep_ld[e]
+// receive the b-mode map rows of the first cut.  Then the bond modes of
+// every cut are aligned (al, nalign cuts).
+hipError_t launch_gsvd_independent(hipStream_t st, const GsvdArgs* args0, const GsvdArgs* args1, const int* cut0,
+                                   const int* cut1, int nel, double* const* keep_dst, const long* keep_ld,
+                                   const GsvdAlign* al, int nalign, int* err);
+// Entangled pairs and Lambda of every cut m = 1..M-1 from site m's second
+// cut (args: the second-cut arguments of the sites) into ne_out[m] and row
+// m of lam_out (leading dimension ld_out).
+hipError_t launch_gsvd_gather_cuts(hipStream_t st, const GsvdArgs* args, int M, int* ne_out, double* lam_out,
+                                   long ld_out);
 // out = Gamma with the modes numbered M..1 (xxpp order kept), 2M x 2M.
 hipError_t launch_reverse_modes(hipStream_t st, const double* gamma, int M, double* out);
 // out[b][p][a] = in[a][p][b] for an A x d x B complex FP64 tensor.

@@ -21,9 +21,22 @@
 
 #include <algorithm>
 
+
 namespace {
 
 __device__ inline void wg_sync() { __syncthreads(); }
+
+// A count or flag that steers the whole workgroup, read as wave-uniform.  The
+// batched kernels read their argument blocks from device memory, so a load
+// through a pointer held there is a generic (flat) load, which the compiler
+// must take as per-lane; the loops it bounds then become exec-masked loops.
+// At the exit of one of them the register allocator placed copies of live
+// values ahead of the exec restore, where they write no lane; that broke the
+// Williamson step of the batched cut (a later orthogonality test compared
+// i == j against a stale -n in every lane but the first).  Reading these
+// values with readfirstlane keeps such loops scalar, as in the kernels that
+// take their arguments by value.
+__device__ inline int uniform_load(const int* p) { return __builtin_amdgcn_readfirstlane(*p); }
 
 // Parallel reduction of one value per thread into red[0] (block of 1024).
 __device__ double wg_sum(double x, double* red) {
@@ -264,9 +277,9 @@ __device__ void tri_shift_solve_il(const double* t, int n, double s, double* y, 
 __device__ void q_from_s(const GsvdArgs& a, int m) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6;
-  if (*a.err) return;
-  const int nL = a.ne[m - 1] + 1;
-  const int ne = a.ne[m];
+  if (uniform_load(a.err)) return;
+  const int nL = uniform_load(a.ne + (m - 1)) + 1;
+  const int ne = uniform_load(a.ne + m);
   const long ld = a.ld_ws;
   const double* Sm = a.ws_S;
   // U, V from S (Eq. MUV)
@@ -362,15 +375,11 @@ __device__ void q_from_s(const GsvdArgs& a, int m) {
 }
 
 // Stage 1.
-__global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
-  if (blockIdx.x == 1) {  // Q^{m-1} beside the Williamson step of cut m
-    if (m - 1 >= a.q_first) q_from_s(a, m - 1);
-    return;
-  }
+__device__ void stage1_body(const GsvdArgs& a, int m) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int M = a.M;
-  if (*a.err) return;
-  const int n_prev = a.ne[m - 1];
+  if (uniform_load(a.err)) return;
+  const int n_prev = uniform_load(a.ne + (m - 1));
   const int nL = n_prev + 1, N2 = 2 * nL;
   if (N2 > GBS_GSVD_N2_MAX) {
     if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_KMAX);
@@ -880,13 +889,21 @@ __global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
   }
 }
 
+__global__ __launch_bounds__(1024) void gsvd_stage1_kernel(GsvdArgs a, int m) {
+  if (blockIdx.x == 1) {  // Q^{m-1} beside the Williamson step of cut m
+    if (m - 1 >= a.q_first) q_from_s(a, m - 1);
+    return;
+  }
+  stage1_body(a, m);
+}
+
 // Stage 2.
-__global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
+__device__ void stage2_body(const GsvdArgs& a, int m) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
   const int M = a.M;
-  if (*a.err) return;
-  const int n_prev = a.ne[m - 1];
+  if (uniform_load(a.err)) return;
+  const int n_prev = uniform_load(a.ne + (m - 1));
   const int nL = n_prev + 1, N2 = 2 * nL, nR = M - m;
   const long ld = a.ld_ws;
   extern __shared__ double lds[];
@@ -1103,7 +1120,150 @@ __global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) {
   wg_dgemm(2 * ne, nR, N2, 1.0, Ta, ld, false, GLR + nR, a.ld_glr, false, 0.0, a.cr_out + M + m, ldc, tiles);
 }
 
+__global__ __launch_bounds__(1024) void gsvd_stage2_kernel(GsvdArgs a, int m) { stage2_body(a, m); }
+
 __global__ __launch_bounds__(1024) void gsvd_q_kernel(GsvdArgs a, int m) { q_from_s(a, m); }
+
+// ---- every site on its own: element y of a batch runs its own cut cuts[y]
+// (0: nothing) with its own arguments and workspaces.
+__global__ __launch_bounds__(1024) void gsvd_stage1_batch_kernel(const GsvdArgs* __restrict__ args,
+                                                                 const int* __restrict__ cuts) {
+  const int m = cuts[blockIdx.y];
+  if (m <= 0) return;
+  const GsvdArgs a = args[blockIdx.y];
+  stage1_body(a, m);
+}
+
+__global__ __launch_bounds__(1024) void gsvd_stage2_batch_kernel(const GsvdArgs* __restrict__ args,
+                                                                 const int* __restrict__ cuts) {
+  const int m = cuts[blockIdx.y];
+  if (m <= 0) return;
+  const GsvdArgs a = args[blockIdx.y];
+  stage2_body(a, m);
+}
+
+__global__ __launch_bounds__(1024) void gsvd_q_batch_kernel(const GsvdArgs* __restrict__ args,
+                                                            const int* __restrict__ cuts) {
+  const int m = cuts[blockIdx.y];
+  if (m <= 0) return;
+  const GsvdArgs a = args[blockIdx.y];
+  q_from_s(a, m);
+}
+
+// Start from Gamma at cut k = cuts[y] (>= 2): Gamma's rows of a_1..a_{k-1}
+// into the element's drr_in / cr_in (as gsvd_restart_kernel).
+__global__ void gsvd_restart_batch_kernel(const GsvdArgs* __restrict__ args, const int* __restrict__ cuts) {
+  const int k = cuts[blockIdx.y];
+  if (k < 2) return;
+  const GsvdArgs& a = args[blockIdx.y];
+  const int M = a.M, nr = k - 1, n2r = 2 * nr, n2g = 2 * M;
+  double* drr = const_cast<double*>(a.drr_in);
+  double* cr = const_cast<double*>(a.cr_in);
+  const double* g = a.gamma;
+  const long tot_c = (long)n2r * n2g, tot = tot_c + (long)n2r * n2r;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    if (e < tot_c) {
+      const int i = (int)(e / n2g), c = (int)(e % n2g);
+      const int gi = i < nr ? i : M + (i - nr);
+      cr[(long)i * a.ld_cr + c] = g[(long)gi * n2g + c];
+    } else {
+      const long f = e - tot_c;
+      const int i = (int)(f / n2r), j = (int)(f % n2r);
+      const int gi = i < nr ? i : M + (i - nr), gj = j < nr ? j : M + (j - nr);
+      drr[(long)i * a.ld_drr + j] = g[(long)gi * n2g + gj];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ne[k - 1] = nr;
+}
+
+// Keep the b-mode map rows of the element's first cut (active rows, left in
+// ws_A by stage 2) before the second cut overwrites the workspace.
+__global__ void gsvd_keep_map_batch_kernel(const GsvdArgs* __restrict__ args, const int* __restrict__ cuts,
+                                           double* const* __restrict__ dst, const long* __restrict__ ld_dst) {
+  const int k = cuts[blockIdx.y];
+  if (k <= 0) return;
+  const GsvdArgs& a = args[blockIdx.y];
+  if (uniform_load(a.err)) return;
+  const int ne = uniform_load(a.ne + k), n2 = 2 * (uniform_load(a.ne + (k - 1)) + 1);
+  double* out = dst[blockIdx.y];
+  const long ldo = ld_dst[blockIdx.y];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < 2L * ne * n2; e += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n2), c = (int)(e % n2);
+    out[(long)r * ldo + c] = a.ws_A[(long)r * a.ld_ws + c];
+  }
+}
+
+// Align the bond modes of cut m between site m (its chain step) and site
+// m+1 (its start from Gamma), and put the phases into Q^m: for each active
+// mode q, the rows of the step's b-mode map written on the quadratures of
+// a_1..a_m (through the start map of cut m-1, which defines r_{m-1}) times
+// the inverse of the start map of cut m is a rotation of the mode's (x, p)
+// pair by theta_q; l_q's row and column of Q^m take e^{i theta_q}.
+__global__ __launch_bounds__(256) void gsvd_align_kernel(const GsvdAlign* __restrict__ al, int* err) {
+  const GsvdAlign A = al[blockIdx.x];
+  const int m = A.m, k = m - 1;
+  const int n0 = uniform_load(A.ne_e + (m - 1)), n = uniform_load(A.ne_e + m), nl = n0 + 1;
+  // (no early exit on *err: another block may set it while this one runs,
+  // and every wave of the block must reach the barrier below)
+  if (uniform_load(A.ne_r + m) != n) {
+    if (threadIdx.x == 0) gbs_set_error(err, GBS_DEVERR_ALIGN);
+    return;
+  }
+  if (n > GBS_GSVD_N2_MAX / 2) {
+    if (threadIdx.x == 0) gbs_set_error(err, GBS_DEVERR_KMAX);
+    return;
+  }
+  __shared__ double th_s[GBS_GSVD_N2_MAX / 2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  cplx64* Q = A.Q;
+  // F row i (quadratures of r_{m-1} and a_m) on a_1..a_m, column j in [0, 2m)
+  auto frow = [&](int i, int j) -> double {
+    const int jx = j < m ? j : j - m;   // mode of column j
+    const bool jp = j >= m;
+    if (i == n0) return (!jp && jx == m - 1) ? 1.0 : 0.0;           // x of a_m
+    if (i == 2 * nl - 1) return (jp && jx == m - 1) ? 1.0 : 0.0;    // p of a_m
+    if (jx == m - 1) return 0.0;
+    const int r = i < n0 ? i : n0 + (i - nl);                       // row of the start map
+    return A.t0[(long)r * A.ldt0 + (jp ? k + jx : jx)];
+  };
+  for (int q = wv; q < n; q += nwv) {
+    // omega(v_x, tr_p), omega(v_x, tr_x), omega(v_p, tr_p), omega(v_p, tr_x)
+    double o[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = lane; j < m; j += 64) {
+      // v[j] and v[m + j] for v = step rows x_q and p_q times F
+      double vx0 = 0.0, vx1 = 0.0, vp0 = 0.0, vp1 = 0.0;
+      for (int i = 0; i < 2 * nl; ++i) {
+        const double f0 = frow(i, j), f1 = frow(i, m + j);
+        const double tx = A.t1[(long)q * A.ldt1 + i], tp = A.t1[(long)(n + q) * A.ldt1 + i];
+        vx0 += tx * f0;
+        vx1 += tx * f1;
+        vp0 += tp * f0;
+        vp1 += tp * f1;
+      }
+      const double rx0 = A.tr[(long)q * A.ldtr + j], rx1 = A.tr[(long)q * A.ldtr + m + j];
+      const double rp0 = A.tr[(long)(n + q) * A.ldtr + j], rp1 = A.tr[(long)(n + q) * A.ldtr + m + j];
+      o[0] += vx0 * rp1 - vx1 * rp0;
+      o[1] += vx0 * rx1 - vx1 * rx0;
+      o[2] += vp0 * rp1 - vp1 * rp0;
+      o[3] += vp0 * rx1 - vp1 * rx0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      for (int off = 32; off > 0; off >>= 1) o[t] += __shfl_xor(o[t], off, 64);
+    // R = [[o0, -o1], [o2, -o3]]
+    if (lane == 0) th_s[q] = atan2(o[2] + o[1], o[0] - o[3]);
+  }
+  __syncthreads();
+  // Q_ij *= e^{i (theta_i + theta_j)}, theta = 0 off the l modes: every entry
+  // is scaled once, by one thread (row and column l_q in place would have two
+  // waves update the entry of two l modes at the same time)
+  const int nmod = nl + n;
+  for (long e = threadIdx.x; e < (long)nmod * nmod; e += blockDim.x) {
+    const int i = (int)(e / nmod), j = (int)(e % nmod);
+    const double th = (i >= nl ? th_s[i - nl] : 0.0) + (j >= nl ? th_s[j - nl] : 0.0);
+    if (th != 0.0) Q[(long)i * A.ld_q + j] = cmul(Q[(long)i * A.ld_q + j], cmake<cplx64>(cos(th), sin(th)));
+  }
+}
 
 hipError_t launch_gsvd_cut(hipStream_t st, const GsvdArgs& a, int m, int n2max) {
   (void)n2max;
@@ -1203,5 +1363,43 @@ hipError_t launch_transpose_bonds(hipStream_t st, const cplx64* in, long A, int 
   if (A < 1 || B < 1 || d < 1 || (B + 31) / 32 > 0x7fffffffL || (A + 31) / 32 > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL(transpose_bonds_kernel, dim3((unsigned)((B + 31) / 32), (unsigned)((A + 31) / 32), d), dim3(32, 8),
                      0, st, in, A, d, B, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gsvd_independent(hipStream_t st, const GsvdArgs* args0, const GsvdArgs* args1, const int* cut0,
+                                   const int* cut1, int nel, double* const* keep_dst, const long* keep_ld,
+                                   const GsvdAlign* al, int nalign, int* err) {
+  if (nel <= 0) return hipSuccess;
+  const size_t lds1 = sizeof(double) * ((size_t)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2);
+  const size_t lds3 = sizeof(double) * ((size_t)2 * 32 * 33 + GBS_GSVD_N2_MAX + 8);
+  const dim3 one(1, (unsigned)nel), many(64, (unsigned)nel);
+  // first cut of every element: from Gamma at cut m - 1 (or the first cut)
+  hipLaunchKernelGGL(gsvd_restart_batch_kernel, many, dim3(256), 0, st, args0, cut0);
+  hipLaunchKernelGGL(gsvd_stage1_batch_kernel, one, dim3(1024), lds1, st, args0, cut0);
+  hipLaunchKernelGGL(gsvd_stage2_batch_kernel, one, dim3(1024), lds3, st, args0, cut0);
+  hipLaunchKernelGGL(gsvd_keep_map_batch_kernel, many, dim3(256), 0, st, args0, cut0, keep_dst, keep_ld);
+  // second cut: the step that gives each site's right bond and Q^m
+  hipLaunchKernelGGL(gsvd_stage1_batch_kernel, one, dim3(1024), lds1, st, args1, cut1);
+  hipLaunchKernelGGL(gsvd_stage2_batch_kernel, one, dim3(1024), lds3, st, args1, cut1);
+  hipLaunchKernelGGL(gsvd_q_batch_kernel, one, dim3(1024), 0, st, args1, cut1);
+  if (nalign > 0) hipLaunchKernelGGL(gsvd_align_kernel, dim3((unsigned)nalign), dim3(256), 0, st, al, err);
+  return hipGetLastError();
+}
+
+__global__ void gsvd_gather_cuts_kernel(const GsvdArgs* __restrict__ args, int M, int* __restrict__ ne_out,
+                                        double* __restrict__ lam_out, long ld_out) {
+  const int m = blockIdx.x + 1;  // cut m, from site m's second cut
+  if (m >= M) return;
+  const GsvdArgs& a = args[m - 1];
+  const int ne = uniform_load(a.ne + m);
+  if (threadIdx.x == 0) ne_out[m] = ne;
+  for (int q = threadIdx.x; q < ne && q < ld_out; q += blockDim.x) lam_out[(long)m * ld_out + q] = a.lam[(long)m * a.ld_dsym + q];
+}
+
+hipError_t launch_gsvd_gather_cuts(hipStream_t st, const GsvdArgs* args, int M, int* ne_out, double* lam_out,
+                                   long ld_out) {
+  if (M < 2) return hipSuccess;
+  hipLaunchKernelGGL(gsvd_gather_cuts_kernel, dim3((unsigned)(M - 1)), dim3(64), 0, st, args, M, ne_out, lam_out,
+                     ld_out);
   return hipGetLastError();
 }

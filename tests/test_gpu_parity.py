@@ -867,3 +867,64 @@ def test_c5_reduced_precision_builds_against_fp64(torch_cuda):
     for _, _, h in out.values():
         h.free()
     h64.free()
+
+
+@pytest.mark.parametrize("name,precision", [("c1", "fp64"), ("haar24", "fp64"), ("c3", "fp64"), ("c3", "fp32")])
+def test_independent_site_gsvd_equals_chain(torch_cuda, name, precision):
+    """Full builds whose Gaussian SVD runs every site on its own (all sites in
+    one batch, bond modes aligned between neighbours) against the sequential
+    chain on the same GPU and against the oracle's chain build: spectra, n_e,
+    kept bases and amplitudes (FP64: 1e-10; FP32: 1 - F <= 1e-9 between the
+    two GPU builds)."""
+    _say(f"case: {name} {precision}, independent sites vs chain")
+    w = W.workload(name) if name != "haar24" else W.custom(24, 4, 32, (0.3, 0.9), "haar", 5)
+    hi = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision=precision)
+    hc = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision=precision, chain_gsvd=True)
+    ii, ic = hi.info(), hc.info()
+    assert ii["gsvd_mode"] == 1 and ic["gsvd_mode"] == 0
+    assert ii["ne"] == ic["ne"]
+    for m in range(1, w.M):
+        assert np.allclose(hi.export(m, "lambda"), hc.export(m, "lambda"), rtol=1e-9, atol=1e-12), m
+        # singular values come from eigenvalues of FP64 Gram matrices, which
+        # resolve s only to about sqrt(eps) s_0 (1.5e-8 s_0): values below
+        # that are rounding noise, and the truncation's cutoff (s / s_0 <=
+        # 1e-12) may keep such a value on one route and drop it on the other
+        si, sc = hi.export(m, "svals"), hc.export(m, "svals")
+        k = min(si.size, sc.size)
+        assert np.allclose(si[:k], sc[:k], rtol=1e-8, atol=1e-7 * sc[0]), m
+        extra = np.concatenate([si[k:], sc[k:]])
+        assert extra.size == 0 or np.max(extra) <= 1e-7 * sc[0], (m, extra)
+    pats = low_patterns(w.M, w.d, 4)[:2000]
+    ai, ac = gpu_amps(torch_cuda, hi, pats), gpu_amps(torch_cuda, hc, pats)
+    f = hi.fidelity(hc)
+    _say(f"  gsvd {ii['t_gsvd_ms']:.1f} ms (chain {ic['t_gsvd_ms']:.1f} ms); max |amp_ind - amp_chain| = "
+         f"{np.max(np.abs(ai - ac)):.2e}; 1 - F = {1 - f:.2e}")
+    if precision == "fp64":
+        assert np.max(np.abs(ai - ac)) <= 1e-10
+        if name != "c3":
+            o = obuild.build_mps(w.gamma, w.d, w.chi)
+            assert np.max(np.abs(ai - omps.amplitudes(o.tensors, pats))) <= 1e-10
+    assert 1 - f <= 1e-9
+    hi.free()
+    hc.free()
+
+
+@pytest.mark.parametrize("name", ["c2", "degenerate_frozen"])
+def test_weak_bond_modes_run_the_chain(torch_cuda, name):
+    """A bond mode with D close to 1 (Lambda < 1e-3) cannot be aligned
+    between two separately computed sites to FP64 accuracy (its vacuum
+    admixture is of order eps / (D - 1)); such full builds run the chain.
+    C2 (brick-wall) and the serving request with exactly unentangled modes
+    both have modes at D - 1 ~ 1e-10; their builds report the chain and
+    match the oracle to 1e-10."""
+    _say(f"case: {name}, weak bond modes -> chain")
+    w = W.workload(name) if name == "c2" else W.serving_requests(469)[468]["workload"]
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    inf = h.info()
+    lam_min = min(float(np.min(h.export(m, "lambda"))) for m in range(1, w.M) if inf["ne"][m])
+    _say(f"  smallest Lambda {lam_min:.2e}, gsvd mode {inf['gsvd_mode']}")
+    assert lam_min < 1e-3 and inf["gsvd_mode"] == 0
+    o = obuild.build_mps(w.gamma, w.d, w.chi)
+    pats = low_patterns(w.M, w.d, 6)[:1500]
+    assert np.max(np.abs(gpu_amps(torch_cuda, h, pats) - omps.amplitudes(o.tensors, pats))) <= 1e-10
+    h.free()
