@@ -103,7 +103,9 @@ typedef struct {
  * chain (Sec. II.B.2), the kept-basis selection (Sec. II.C.1), the PCO
  * tensor construction (Sec. II.C.2) and the truncation sweep, and leaves a
  * right-canonical, unit-norm MPS whose vacuum amplitude is real > 0.
- * Synchronises `stream` internally (buffer sizes depend on the spectra). */
+ * Synchronises `stream` internally (buffer sizes depend on the spectra).
+ * A cut with more than 299 entangled mode pairs (2 (n_e + 1) > 600, the
+ * widest Williamson step one workgroup takes) fails with GBS_E_INVAL. */
 int gbs_mps_build(const double* gamma, int32_t M, const gbs_build_opts* opt, void* stream, gbs_mps* out);
 
 /* The tensor of one site alone, at bond dimension chi <= 16384: the shape of

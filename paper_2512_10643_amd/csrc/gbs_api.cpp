@@ -147,9 +147,14 @@ struct gbs_mps_s {
   void** site_ptrs = nullptr;    // device array of per-site pointers
   int* bond_dev = nullptr;
   int maxbond = 1;
-  // diagnostics
+  // pair matrices: while building, Q^m in slot m - 1 - q_slot0 of a strided
+  // buffer of the build's scratch arena (Q, q_stride, ld_q); afterwards
+  // compact, Q^m (n_m x n_m) at Qc + qc_off[m], or qc_off[m] < 0 if not formed
   cplx64* Q = nullptr;
   long q_stride = 0, ld_q = 0;
+  int q_slot0 = 0;
+  cplx64* Qc = nullptr;
+  std::vector<long> qc_off;
   float* packed = nullptr;       // MFMA sampler operand layout (FP32 builds)
   std::vector<long> poff;        // per site offset into `packed` (floats)
   long* poff_dev = nullptr;      // the same on the device, M + 1 entries
@@ -689,10 +694,12 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   }
   h->ld_q = n2max;  // n_modes <= nL + ne <= n2max
   h->q_stride = (long)h->ld_q * h->ld_q;
-  HIP_CHECK_RET(dalloc(h->keep, &h->Q, (size_t)M * h->q_stride));
+  h->q_slot0 = only_site ? only_site - 1 : 0;  // a single-site build forms Q^s alone
+  HIP_CHECK_RET(dalloc(tmp, &h->Q, (size_t)(only_site ? 1 : M) * h->q_stride));
   ga.Q = h->Q;
   ga.q_stride = h->q_stride;
   ga.ld_q = h->ld_q;
+  ga.q_slot0 = h->q_slot0;
   ga.ld_ws = n2max;
   const size_t wsz = (size_t)n2max * n2max;
   HIP_CHECK_RET(dalloc(tmp, &ga.ws_G, wsz));
@@ -771,7 +778,9 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     HIP_CHECK_RET(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK_RET(hipStreamSynchronize(st));
   }
-  if (herr) return fail(herr == GBS_DEVERR_NOT_PD ? GBS_E_NOT_PD : GBS_E_INTERNAL, deverr_msg(herr));
+  if (herr)
+    return fail(herr == GBS_DEVERR_NOT_PD ? GBS_E_NOT_PD : herr == GBS_DEVERR_KMAX ? GBS_E_INVAL : GBS_E_INTERNAL,
+                deverr_msg(herr));
   if (only_site)  // only the two cuts of the site were formed
     for (int m = 0; m <= M; ++m)
       if (m != only_site - 1 && m != only_site) ne[m] = 0;
@@ -892,7 +901,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     s.off_state_r = cuts[m].off_state;
     s.off_occ_l = cuts[m - 1].off_occ;
     s.off_occ_r = cuts[m].off_occ;
-    s.off_q = (long)(m - 1) * h->q_stride;
+    s.off_q = (only_site && m != only_site) ? 0 : (long)(m - 1 - h->q_slot0) * h->q_stride;
     s.off_t = ttot;
     t64off[m] = ttot;
     ttot += (long)s.chiL * d * s.chiR;
@@ -968,7 +977,35 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     h->raw = T64;
     h->raw_off = t64off;
   }
+  {
+    // the pair matrices move to compact storage that lives with the handle
+    std::vector<int> qs, qn;
+    std::vector<long> qo;
+    long qtot = 0;
+    h->qc_off.assign(M + 1, -1);
+    for (int m = 1; m <= M; ++m) {
+      if (only_site && m != only_site) continue;
+      const int n = ne[m - 1] + 1 + ne[m];
+      qs.push_back(m);
+      qn.push_back(n);
+      qo.push_back(qtot);
+      h->qc_off[m] = qtot;
+      qtot += (long)n * n;
+    }
+    int *qs_d, *qn_d;
+    long* qo_d;
+    HIP_CHECK_RET(dalloc(h->keep, &h->Qc, (size_t)std::max(qtot, 1L)));
+    HIP_CHECK_RET(dalloc(tmp, &qs_d, qs.size()));
+    HIP_CHECK_RET(dalloc(tmp, &qn_d, qn.size()));
+    HIP_CHECK_RET(dalloc(tmp, &qo_d, qo.size()));
+    HIP_CHECK_RET(hipMemcpyAsync(qs_d, qs.data(), qs.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_CHECK_RET(hipMemcpyAsync(qn_d, qn.data(), qn.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_CHECK_RET(hipMemcpyAsync(qo_d, qo.data(), qo.size() * sizeof(long), hipMemcpyHostToDevice, st));
+    HIP_CHECK_RET(launch_q_compact(st, h->Q, h->q_stride, h->ld_q, h->q_slot0, qs_d, qn_d, qo_d, (int)qs.size(),
+                                   h->Qc));
+  }
   HIP_CHECK_RET(hipStreamSynchronize(st));
+  h->Q = nullptr;  // the strided buffer goes with the build's scratch arena
   double t3 = now_ms();
   h->t_pco = t3 - t2;
   if (only_site) {
@@ -1174,16 +1211,19 @@ int mirror_single_site(gbs_mps_s* h, hipStream_t st) {
   h->keep.release(h->raw);
   h->raw = t;
   h->raw_off.assign(M + 1, 0);
-  // pair matrix: modes (r', a, l') = (cut s modes, a_s, cut s-1 modes)
+  // pair matrix: modes (r', a, l') = (cut s modes, a_s, cut s-1 modes), in
+  // place of the mirrored site's (same size)
   const int nr = h->ne[s], nl = h->ne[s - 1], n = nl + 1 + nr;
-  std::vector<cplx64> qa((size_t)h->q_stride), qb((size_t)h->q_stride);
-  HIP_CHECK_RET(hipMemcpy(qa.data(), h->Q + (long)(sr - 1) * h->q_stride, h->q_stride * sizeof(cplx64),
-                          hipMemcpyDeviceToHost));
+  const long qoff = h->qc_off[sr];
+  if (qoff < 0) return fail(GBS_E_INTERNAL, "mirrored pair matrix missing");
+  std::vector<cplx64> qa((size_t)n * n), qb((size_t)n * n);
+  HIP_CHECK_RET(hipMemcpy(qa.data(), h->Qc + qoff, qa.size() * sizeof(cplx64), hipMemcpyDeviceToHost));
   auto src = [&](int i) { return i < nl ? nr + 1 + i : (i == nl ? nr : i - nl - 1); };  // new index -> old
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) qb[(size_t)i * h->ld_q + j] = qa[(size_t)src(i) * h->ld_q + src(j)];
-  HIP_CHECK_RET(hipMemcpy(h->Q + (long)(s - 1) * h->q_stride, qb.data(), h->q_stride * sizeof(cplx64),
-                          hipMemcpyHostToDevice));
+    for (int j = 0; j < n; ++j) qb[(size_t)i * n + j] = qa[(size_t)src(i) * n + src(j)];
+  HIP_CHECK_RET(hipMemcpy(h->Qc + qoff, qb.data(), qb.size() * sizeof(cplx64), hipMemcpyHostToDevice));
+  h->qc_off.assign(M + 1, -1);
+  h->qc_off[s] = qoff;
   h->single_site = s;
   return GBS_OK;
 }
@@ -1701,12 +1741,10 @@ int gbs_mps_export(gbs_mps h, int32_t m, int32_t what, void* dst, int64_t cap, i
   }
   if (what == GBS_EXPORT_Q) {
     if (m < 1 || m > M) return fail(GBS_E_INVAL, "site out of range");
+    if (h->qc_off.empty() || h->qc_off[m] < 0) return fail(GBS_E_INVAL, "pair matrix of this site not formed");
     int n = h->ne[m - 1] + 1 + h->ne[m];
-    std::vector<cplx64> full((size_t)h->q_stride), out((size_t)n * n);
-    HIP_CHECK_RET(hipMemcpy(full.data(), h->Q + (long)(m - 1) * h->q_stride, h->q_stride * sizeof(cplx64),
-                            hipMemcpyDeviceToHost));
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) out[(size_t)i * n + j] = full[(size_t)i * h->ld_q + j];
+    std::vector<cplx64> out((size_t)n * n);
+    HIP_CHECK_RET(hipMemcpy(out.data(), h->Qc + h->qc_off[m], out.size() * sizeof(cplx64), hipMemcpyDeviceToHost));
     return put(out.data(), out.size() * sizeof(cplx64));
   }
   if (what == GBS_EXPORT_BASIS) {
@@ -1782,9 +1820,19 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   const int64_t esz = opt->prec == GBS_FP64 ? 16 : 8;
   const int64_t n2 = std::min<int64_t>(m + 2, GBS_GSVD_N2_MAX);
   int64_t b = 0;
-  // Gaussian SVD chain: residual blocks, stage workspaces, rotation log, Q^m
+  // Gaussian SVD chain: residual blocks, stage workspaces, the strided Q^m
+  // of the build (n2^2 each), and the compact copy kept with the handle
   b += 2 * (n2 * n2 + n2 * 2 * m) * 8 + 10 * n2 * n2 * 8 + (2 * n2 * n2 + 4 * n2) * 8;
-  b += m * (n2 / 2 + 2) * (n2 / 2 + 2) * 16 * 2;
+  b += m * n2 * n2 * 16 + m * (n2 / 2 + 2) * (n2 / 2 + 2) * 16 * 4;
+  // every site on its own (2 (M - 1) <= 600): per-site pools of doubles
+  if (m >= 3 && 2 * (m - 1) <= GBS_GSVD_N2_MAX) {
+    int64_t pool = 0;
+    for (int64_t k = 1; k <= m; ++k) {
+      const int64_t w = 2 * k, lu = k + 1;
+      pool += 2 * (m + 1) * lu + 13 * w * w + 3 * w * 2 * m + 8 * w + w * (w + 1) / 2 + 8 * lu * lu + 23 * 32;
+    }
+    b += pool * 8;
+  }
   // kept bases and maps
   b += (m + 1) * chi * (40 + 16 * GBS_K_MAX + 6 * (n2 / 2 + 1));
   // PCO tensors (FP64) and the truncation sweep

@@ -31,6 +31,7 @@ struct GsvdArgs {
   cplx64 *ws_U, *ws_V, *ws_aug;
   long ld_u;
   int q_first;           // Q^j is formed beside cut j + 1 only for j >= q_first
+  int q_slot0;           // Q^j is stored in slot j - 1 - q_slot0 of Q (stride q_stride)
 };
 
 // Alignment of the bond modes of cut m between site m (its chain step) and
@@ -75,6 +76,11 @@ hipError_t launch_gsvd_independent(hipStream_t st, const GsvdArgs* args0, const 
 // Entangled pairs and Lambda of every cut m = 1..M-1 from site m's second
 // cut (args: the second-cut arguments of the sites) into ne_out[m] and row
 // m of lam_out (leading dimension ld_out).
+// Copy Q^m (n_m x n_m at leading dimension ld_q in slot m - 1 - slot0 of a
+// strided buffer) to dst + dst_off[i] (leading dimension n_m), for the
+// sites site[0..nsites).
+hipError_t launch_q_compact(hipStream_t st, const cplx64* src, long q_stride, long ld_q, int slot0, const int* site,
+                            const int* n, const long* dst_off, int nsites, cplx64* dst);
 hipError_t launch_gsvd_gather_cuts(hipStream_t st, const GsvdArgs* args, int M, int* ne_out, double* lam_out,
                                    long ld_out);
 // out = Gamma with the modes numbered M..1 (xxpp order kept), 2M x 2M.

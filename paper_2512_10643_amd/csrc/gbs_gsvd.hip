@@ -354,7 +354,7 @@ __device__ void q_from_s(const GsvdArgs& a, int m) {
   }
   // Q^m on (r_{m-1}, a_m, l_m): [[Uih V^dag, Uih[:, :ne]], [.^T, -V^T Uih]]
   const int nmod = nL + ne;
-  cplx64* Q = a.Q + (long)(m - 1) * a.q_stride;
+  cplx64* Q = a.Q + (long)(m - 1 - a.q_slot0) * a.q_stride;
   const long ldq = a.ld_q;
   for (long e = tid; e < (long)nmod * nmod; e += nt) {
     int i = (int)(e / nmod), j = (int)(e % nmod);
@@ -1383,6 +1383,24 @@ hipError_t launch_gsvd_independent(hipStream_t st, const GsvdArgs* args0, const 
   hipLaunchKernelGGL(gsvd_stage2_batch_kernel, one, dim3(1024), lds3, st, args1, cut1);
   hipLaunchKernelGGL(gsvd_q_batch_kernel, one, dim3(1024), 0, st, args1, cut1);
   if (nalign > 0) hipLaunchKernelGGL(gsvd_align_kernel, dim3((unsigned)nalign), dim3(256), 0, st, al, err);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void q_compact_kernel(const cplx64* __restrict__ src, long q_stride, long ld_q,
+                                                        int slot0, const int* __restrict__ site,
+                                                        const int* __restrict__ nn, const long* __restrict__ dst_off,
+                                                        cplx64* __restrict__ dst) {
+  const int m = site[blockIdx.x], n = nn[blockIdx.x];
+  const cplx64* q = src + (long)(m - 1 - slot0) * q_stride;
+  cplx64* o = dst + dst_off[blockIdx.x];
+  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) o[e] = q[(e / n) * ld_q + e % n];
+}
+
+hipError_t launch_q_compact(hipStream_t st, const cplx64* src, long q_stride, long ld_q, int slot0, const int* site,
+                            const int* n, const long* dst_off, int nsites, cplx64* dst) {
+  if (nsites <= 0) return hipSuccess;
+  hipLaunchKernelGGL(q_compact_kernel, dim3((unsigned)nsites), dim3(256), 0, st, src, q_stride, ld_q, slot0, site, n,
+                     dst_off, dst);
   return hipGetLastError();
 }
 

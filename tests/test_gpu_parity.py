@@ -265,6 +265,24 @@ def test_error_paths(torch_cuda):
     h.free()
 
 
+def test_more_entangled_pairs_than_one_workgroup_takes(torch_cuda):
+    """A cut with more than 299 entangled mode pairs (602 Haar-mixed squeezers:
+    the middle cut has 301) exceeds what one workgroup's Williamson step
+    takes (2 (n_e + 1) <= 600); the build fails cleanly with INVAL and the
+    library stays usable."""
+    from paper_2512_10643_amd import GbsError
+    _say("case: M=602 Haar, n_e = 301 at the middle cut -> INVAL")
+    w = W.custom(602, 2, 4, (0.3, 0.6), "haar", 8)
+    with pytest.raises(GbsError) as e:
+        gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    _say(f"  {e.value.name}: {e.value}")
+    assert e.value.name == "INVAL" and "size limit" in str(e.value)
+    w1 = W.workload("c1")
+    h = gpu_build(torch_cuda, w1.gamma, w1.d, w1.chi, precision="fp64")
+    assert h.info()["ne"][w1.M // 2] == 4
+    h.free()
+
+
 def test_sampling_fp32_mfma_c2(torch_cuda):
     """FP32 build -> MFMA sampler: per-mode marginals vs the oracle's exact ones,
     seed determinism and independence from batching."""
