@@ -30,6 +30,7 @@ os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 METRIC = "MPS sites/s and samples/s at χ=256, 1−fidelity vs FP64; p50/p99 request latency"
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBPS = 8000.0
 
 
 # Shots per launch of the MFMA sampling sweep (the library's sweep size).
@@ -106,40 +107,85 @@ def first_pass_flops_per_shot(sectors, samples, padr=1, padc=1):
     return tot / S, f0 / (S * M)
 
 
-def cpu_baseline(workload, budget_s=20.0):
-    """Time the CPU oracle on a bounded sample of the same workload and scale
-    it to samples/s of the whole step (build + shots)."""
-    import numpy as np
-    import oracle.build as ob
-    import oracle.gaussian as og
-    import oracle.mps as om
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sites_worker(args):
+    """One worker of the parallel CPU baseline: the oracle's PCO tensors of
+    the given sites (one BLAS thread), and its sampler on a 4-site chain of
+    the central tensors; returns (PCO seconds, sampling seconds)."""
+    gamma, d, chi, sites, nshot, seed = args
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle.build as ob
+    import oracle.mps as om
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        o = ob.build_mps(gamma, d, chi, sites=sites, validate=False)
+        t_pco = time.perf_counter() - t0
+        m0 = sites[0]
+        chain = om.normalize([o.raw[m0 - 1][:1]] + [o.raw[m0 - 1]] * 2 + [o.raw[m0 - 1][:, :, :1]])
+        t0 = time.perf_counter()
+        om.sample(chain, nshot, np.random.default_rng(seed))
+        t_smp = time.perf_counter() - t0
+    return t_pco, t_smp
+
+
+def cpu_baseline(workload, shots):
+    """The CPU oracle timed on a bounded sample of the same workload, scaled
+    to samples/s of the whole step (build + shots), twice: one thread, and
+    min(d, nproc) worker processes with one thread each (sites are
+    independent once the Gaussian SVD is known, and shots are independent:
+    the d-core split of the paper's CPU scheme, here over sites and shots).
+    The Gaussian SVD chain is sequential and runs once, on one thread.  Runs
+    before the GPU is initialised, so the workers fork a process that holds
+    no device state."""
+    import multiprocessing as mp
+    import oracle.gaussian as og
+    from threadpoolctl import threadpool_limits
     w = workload
-    t0 = time.perf_counter()
-    og.gsvd(w.gamma)
-    t_gsvd = time.perf_counter() - t0
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(w.d, nproc))
     mid = w.M // 2
-    sites = [mid, mid + 1]
+    nshot = 40
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        og.gsvd(w.gamma)
+        t_gsvd = time.perf_counter() - t0
+    # one thread: one central site and the sampler, in this process
+    t_pco1, t_smp1 = _oracle_sites_worker((w.gamma, w.d, w.chi, [mid], nshot, 0))
+    one = {"t_site_s": t_pco1, "t_shot_s": t_smp1 / nshot * w.M / 4}
+    # workers: one central site and nshot shots each, all at once
+    sites = [mid - workers // 2 + k for k in range(workers)]
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    o = ob.build_mps(w.gamma, w.d, w.chi, sites=sites, validate=False)
-    t_pco = (time.perf_counter() - t0) - t_gsvd
-    t_site = max(t_pco, 1e-9) / len(sites)
-    # sampling cost per shot-site, measured on a chain made of the central tensors
-    chain = [o.raw[mid - 1][:1]] + [o.raw[mid - 1]] * 2 + [o.raw[mid][:, :, :1]]
-    chain = om.normalize(chain)
-    nshot = 60
-    t0 = time.perf_counter()
-    om.sample(chain, nshot, np.random.default_rng(0))
-    t_shot_site = (time.perf_counter() - t0) / (nshot * len(chain))
-    t_build = t_gsvd + w.M * t_site
-    return dict(t_build_s=t_build, t_shot_s=t_shot_site * w.M, threads=threads,
-                sample=(f"oracle Gaussian SVD of all {w.M} cuts ({t_gsvd:.2f}s) + PCO tensors of central sites "
-                        f"{sites} ({t_pco:.2f}s), extrapolated to {w.M} sites; oracle sampler on a 4-site chain of "
-                        f"the central {w.chi}x{w.d}x{w.chi} tensors, {nshot} shots, scaled to {w.M} sites"))
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_sites_worker, [(w.gamma, w.d, w.chi, [s], nshot, s) for s in sites])
+    wall = time.perf_counter() - t0
+    t_pco_max = max(r[0] for r in res)
+    t_smp_max = max(r[1] for r in res)
+    par = {"t_site_s": t_pco_max / workers, "t_shot_s": t_smp_max / (nshot * workers) * w.M / 4}
+    out = {}
+    for name, r, cores in (("one_thread", one, 1), ("workers", par, workers)):
+        t_build = t_gsvd + w.M * r["t_site_s"]
+        t_step = t_build + shots * r["t_shot_s"]
+        out[name] = {"value": shots / t_step, "cores": cores, "sites_per_s": w.M / t_build,
+                     "samples_per_s_sampling_only": 1.0 / r["t_shot_s"]}
+    out["meta"] = {"nproc": nproc, "cpu_model": _cpu_model(), "t_gsvd_s": t_gsvd, "workers_wall_s": wall,
+                   "sample": (f"oracle Gaussian SVD of all {w.M} cuts on one thread ({t_gsvd:.2f}s); PCO tensor of "
+                              f"central site {mid} on one thread ({t_pco1:.2f}s) and of sites {sites[0]}..{sites[-1]}, "
+                              f"one per worker on {workers} workers ({t_pco_max:.2f}s); oracle sampler, {nshot} shots "
+                              f"on a 4-site chain of the central {w.chi}x{w.d}x{w.chi} tensor per process; "
+                              f"extrapolated to {w.M} sites and {shots} shots")}
+    return out
 
 
 def serving_mix(n, slots, loads=(0.7, 1.2), probe=64):
@@ -222,7 +268,22 @@ def contractions(name):
     return out
 
 
-def central_tensor(dims=(300, 1000, 2000, 4096, 10000), cutoffs=(4, 6, 8, 10), oracle=True):
+def pco_record(inf):
+    """PCO level gather of one build: elements, source terms (the sparse
+    update count U: one term per pair of occupied modes of each element),
+    device time of the level launches, and HBM rate against the algorithmic
+    48 B per term (a complex FP64 source element, its Q coefficient and the
+    accumulation into the target: 3 x 16 B)."""
+    ms = inf["t_pco_kernel_ms"]
+    terms = inf["pco_terms"]
+    gbs = 48.0 * terms / max(ms, 1e-9) / 1e6
+    return {"elements": inf["pco_updates"], "terms": terms, "kernel_ms": ms, "host_ms": inf["t_pco_ms"],
+            "elements_per_s": inf["pco_updates"] / max(ms, 1e-9) * 1e3,
+            "terms_per_s": terms / max(ms, 1e-9) * 1e3, "bytes_per_term": 48,
+            "achieved_gbps": gbs, "frac_hbm": gbs / HBM_PEAK_GBPS}
+
+
+def central_tensor(dims=(300, 1000, 2000, 4096, 10000), cutoffs=(4, 6, 8, 10), oracle=True, sites=True):
     """The paper's own benchmark shape: the central tensor of a 144-mode pure
     state with five squeezed modes among vacua through a Haar interferometer,
     built alone (gbs_mps_build_site, FP64) at bond dimension D and cutoff d.
@@ -251,9 +312,10 @@ def central_tensor(dims=(300, 1000, 2000, 4096, 10000), cutoffs=(4, 6, 8, 10), o
             out["runs"].append({"D": D, "d": d, "kept": [inf["bond"][site - 1], inf["bond"][site]],
                                 "n_e": [inf["ne"][site - 1], inf["ne"][site]], "total_ms": 1000 * dt,
                                 "gsvd_ms": inf["t_gsvd_ms"], "kept_ms": inf["t_kept_ms"], "pco_ms": inf["t_pco_ms"],
-                                "elements": inf["pco_updates"],
-                                "elements_per_s": inf["pco_updates"] / max(inf["t_pco_ms"], 1e-9) * 1e3})
+                                "pco": pco_record(inf)})
             print(f"central tensor D={D} d={d}: {1000 * dt:.1f} ms", file=sys.stderr, flush=True)
+    if not sites:
+        return out
     # every tensor on its own: single-site builds along the chain, on this
     # state and on C3's (144 squeezed modes through a Haar interferometer)
     c3 = workloads.workload("c3")
@@ -297,6 +359,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=12345)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-central", action="store_true",
+                    help="skip the central-tensor record (D=10^4, d=4 and 10) of the default run")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--slots", type=int, default=SERVING_SLOTS)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -315,8 +379,16 @@ def main():
               "(the kernels run on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import workloads
+    cpu = None
+    if not (args.contractions or args.central or args.no_cpu_baseline):
+        # before anything touches the GPU: the baseline's workers are forked
+        print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(workloads.workload(args.workload), args.shots)
+        print(f"cpu baseline: {cpu['workers']['value']:.2f} samples/s on {cpu['workers']['cores']} workers, "
+              f"{cpu['one_thread']['value']:.2f} on one thread", file=sys.stderr, flush=True)
+
+    import torch
     from paper_2512_10643_amd import mps as gmps
 
     if args.contractions:
@@ -422,8 +494,7 @@ def main():
         "build_phase_ms": {k: inf[k] for k in ("t_gsvd_ms", "t_kept_ms", "t_pco_ms", "t_svd_ms")},
         # PCO tensors by the level gather: every element is produced once from
         # the previous photon level (no dense padding, so executed = algorithmic)
-        "pco": {"elements": inf["pco_updates"], "ms": inf["t_pco_ms"],
-                "elements_per_s": inf["pco_updates"] / max(inf["t_pco_ms"], 1e-9) * 1e3},
+        "pco": pco_record(inf),
         "samples_per_s_sampling_only": args.shots / (samp_ms / 1000.0),
         "eps_max": inf["eps_max"],
         "max_bond": inf["max_bond"],
@@ -461,14 +532,17 @@ def main():
                                  "samples_per_s_ratio": res["samples_per_s_sampling_only"] / (n64 / ts64)}
         hp.free()
         h64.free()
+    if not args.no_central:
+        res["central"] = central_tensor(dims=(10000,), cutoffs=(4, 10), oracle=False, sites=False)
     if not args.no_serving:
         res["serving"] = serving_mix(args.serving_requests, args.slots)
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(w)
-        t_step = cb["t_build_s"] + args.shots * cb["t_shot_s"]
-        res["cpu_baseline"] = {"value": args.shots / t_step, "unit": "samples/s", "cores": cb["threads"],
-                               "kind": "oracle", "sample": cb["sample"],
-                               "sites_per_s": w.M / cb["t_build_s"], "samples_per_s_sampling_only": 1.0 / cb["t_shot_s"]}
+    if cpu is not None:
+        wk = cpu["workers"]
+        res["cpu_baseline"] = {"value": wk["value"], "unit": "samples/s", "cores": wk["cores"], "kind": "oracle",
+                               "sample": cpu["meta"]["sample"], "sites_per_s": wk["sites_per_s"],
+                               "samples_per_s_sampling_only": wk["samples_per_s_sampling_only"],
+                               "one_thread": cpu["one_thread"], "nproc": cpu["meta"]["nproc"],
+                               "cpu_model": cpu["meta"]["cpu_model"]}
     print(json.dumps(res))
 
 

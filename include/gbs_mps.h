@@ -221,6 +221,9 @@ typedef struct {
                               MFMA sampler cannot take), 1 dense, 2 photon-parity sectors */
   int32_t gsvd_mode;       /* 0: sequential Gaussian SVD chain; 1: every site's Gaussian data on its
                               own, bond modes aligned between neighbours (Sec. III.A) */
+  int64_t pco_terms;       /* source terms the PCO level gather summed (pairs of occupied modes
+                              over all elements: the sparse update count of Sec. II.C.2) */
+  double t_pco_kernel_ms;  /* device time of the PCO level launches (HIP events, back to back) */
 } gbs_mps_info_t;
 
 /* Fill `info`; optional host arrays (may be NULL):
@@ -314,14 +317,18 @@ int gbs_filter_pure(const double* gamma_th, int32_t N, const gbs_filter_opts* op
  *                          device (drawing `shots` samples too when > 0); the
  *                          request's id names the resident MPS;
  *   GBS_REQ_SAMPLE       : draw `shots` samples from a resident MPS (`handle`).
+ * Builds run the Gaussian SVD as the sequential chain (GBS_CHAIN_GSVD is
+ * set on every build request): concurrent builds share the device, so total
+ * work matters more than one build's latency.
  * Builds queue in FIFO order.  `slots` worker threads, each with its own HIP
  * stream, start the head of the build queue as soon as one is free and the
  * head's footprint (gbs_mps_footprint) fits `budget_bytes` beside everything
  * admitted, resident MPS included.  Samples are drawn by one batched sweep
  * (its own thread and stream): every request in it advances one site per
  * step, all requests in the same launches, each through its own descriptor
- * (site tensors, current site, buffers, seed, output); requests join at any
- * step as memory allows and leave after their last site.  MPS without the
+ * (site tensors, current site, buffers, seed, output); the sweep enqueues
+ * up to 16 steps per round trip to the host, and requests join at the start
+ * of a round as memory allows and leave after their last site.  MPS without the
  * FP32 sampler operand (FP64 builds) and requests above 2^20 shots are
  * sampled on their own.  A request's samples are identical whether it runs
  * alone or in a mix: the build is deterministic and the random numbers are

@@ -60,7 +60,8 @@ class InfoT(ctypes.Structure):
                 ("norm_raw", ctypes.c_double), ("bytes", ctypes.c_int64), ("pco_updates", ctypes.c_int64),
                 ("t_gsvd_ms", ctypes.c_double), ("t_kept_ms", ctypes.c_double), ("t_pco_ms", ctypes.c_double),
                 ("t_svd_ms", ctypes.c_double), ("eig_sweeps", ctypes.c_int32),
-                ("sampler_layout", ctypes.c_int32), ("gsvd_mode", ctypes.c_int32)]
+                ("sampler_layout", ctypes.c_int32), ("gsvd_mode", ctypes.c_int32),
+                ("pco_terms", ctypes.c_int64), ("t_pco_kernel_ms", ctypes.c_double)]
 
 
 class FilterOpts(ctypes.Structure):

@@ -136,6 +136,8 @@ struct gbs_mps_s {
   std::vector<std::vector<double>> svals; // singular values per bond
   double norm_raw = 0;
   int64_t pco_updates = 0;
+  int64_t pco_terms = 0;          // source terms summed by the PCO level gather
+  double t_pco_kernels = 0;       // device time of the level launches (HIP events)
   double t_gsvd = 0, t_kept = 0, t_pco = 0, t_svd = 0;
   int eig_sweeps = 0;            // sweeps of the bond eigensolver
   int single_site = 0;           // > 0: the handle holds that site's PCO tensor only
@@ -965,14 +967,33 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
   pa.Q = h->Q;
   pa.ld_q = h->ld_q;
   pa.T = T64;
+  unsigned long long* terms_dev;
+  HIP_CHECK_RET(dalloc(tmp, &terms_dev, 1));
+  HIP_CHECK_RET(hipMemsetAsync(terms_dev, 0, sizeof(unsigned long long), st));
+  pa.terms = terms_dev;
   HIP_CHECK_RET(launch_pco_init(st, pa, M));
+  hipEvent_t ev[2];
+  HIP_CHECK_RET(hipEventCreate(&ev[0]));
+  HIP_CHECK_RET(hipEventCreate(&ev[1]));
+  HIP_CHECK_RET(hipEventRecord(ev[0], st));
   for (size_t k = 1; k < lv.size(); ++k) {
     int nb = (int)(lv_first[k + 1] - lv_first[k]);
     if (nb == 0) continue;
     HIP_CHECK_RET(launch_pco_level(st, pa, blk_dev + lv_first[k], nb, lv_nelem[k], (int)k));
     updates += lv_nelem[k];
   }
+  HIP_CHECK_RET(hipEventRecord(ev[1], st));
   h->pco_updates = updates;
+  unsigned long long terms_h = 0;
+  HIP_CHECK_RET(hipMemcpyAsync(&terms_h, terms_dev, sizeof terms_h, hipMemcpyDeviceToHost, st));
+  HIP_CHECK_RET(hipEventSynchronize(ev[1]));
+  {
+    float ms = 0.f;
+    HIP_CHECK_RET(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    h->t_pco_kernels = ms;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
   if ((h->flags & GBS_KEEP_RAW) || only_site) {
     h->raw = T64;
     h->raw_off = t64off;
@@ -1005,6 +1026,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
                                    h->Qc));
   }
   HIP_CHECK_RET(hipStreamSynchronize(st));
+  h->pco_terms = (int64_t)terms_h;
   h->Q = nullptr;  // the strided buffer goes with the build's scratch arena
   double t3 = now_ms();
   h->t_pco = t3 - t2;
@@ -1695,6 +1717,8 @@ int gbs_mps_info(gbs_mps h, gbs_mps_info_t* info, int32_t* bond, int32_t* ne, do
   info->eig_sweeps = h->eig_sweeps;
   info->sampler_layout = h->packed ? (h->psplit ? 2 : 1) : 0;
   info->gsvd_mode = h->gsvd_independent;
+  info->pco_terms = h->pco_terms;
+  info->t_pco_kernel_ms = h->t_pco_kernels;
   for (int m = 0; m <= h->M; ++m) {
     if (bond) bond[m] = h->bond[m];
     if (ne) ne[m] = h->ne[m];
@@ -1825,7 +1849,7 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   b += 2 * (n2 * n2 + n2 * 2 * m) * 8 + 10 * n2 * n2 * 8 + (2 * n2 * n2 + 4 * n2) * 8;
   b += m * n2 * n2 * 16 + m * (n2 / 2 + 2) * (n2 / 2 + 2) * 16 * 4;
   // every site on its own (2 (M - 1) <= 600): per-site pools of doubles
-  if (m >= 3 && 2 * (m - 1) <= GBS_GSVD_N2_MAX) {
+  if (m >= 3 && 2 * (m - 1) <= GBS_GSVD_N2_MAX && !(opt->flags & GBS_CHAIN_GSVD)) {
     int64_t pool = 0;
     for (int64_t k = 1; k <= m; ++k) {
       const int64_t w = 2 * k, lu = k + 1;

@@ -27,6 +27,7 @@ struct PcoArgs {
   const cplx64* Q;
   long ld_q;
   cplx64* T;             // tensors, FP64
+  unsigned long long* terms;  // optional: total number of source terms summed (NULL: not counted)
 };
 
 hipError_t launch_pco_init(hipStream_t st, const PcoArgs& a, int nsites);

@@ -15,8 +15,11 @@
 
 __global__ __launch_bounds__(256) void pco_level_kernel(PcoArgs a, const LevelBlock* __restrict__ blocks, int nblocks,
                                                         long nelem, int k) {
-  long gid = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (gid >= nelem) return;
+  const long gid0 = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  // threads past the last element take element nelem - 1's path without
+  // storing, so that every lane of a wave reaches the term count at the end
+  const bool live = gid0 < nelem;
+  const long gid = live ? gid0 : nelem - 1;
   // locate the block (elem_start ascending)
   int lo = 0, hi = nblocks - 1;
   while (lo < hi) {
@@ -45,7 +48,9 @@ __global__ __launch_bounds__(256) void pco_level_kernel(PcoArgs a, const LevelBl
   const int* lowR = a.low + sd.off_occ_r;  // [q * chiR + state]
 #define TIDX(al, pp, be) (((long)(al) * d + (pp)) * chiR + (be))
   double ar = 0.0, ai = 0.0;
+  int nterm = 0;
   auto acc = [&](cplx64 g, double c, long idx) {
+    ++nterm;
     cplx64 v = T[idx];
     ar += c * (g.re * v.re - g.im * v.im);
     ai += c * (g.re * v.im + g.im * v.re);
@@ -99,7 +104,12 @@ __global__ __launch_bounds__(256) void pco_level_kernel(PcoArgs a, const LevelBl
 #undef TIDX
   (void)nr;
   const double inv = 1.0 / (double)k;
-  T[((long)alpha * d + p) * chiR + beta] = cmake<cplx64>(ar * inv, ai * inv);
+  if (live) T[((long)alpha * d + p) * chiR + beta] = cmake<cplx64>(ar * inv, ai * inv);
+  if (a.terms) {  // source terms of this wave's elements, one atomic per wave
+    unsigned long long c = live ? (unsigned long long)nterm : 0ull;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(a.terms, c);
+  }
 }
 
 __global__ void pco_init_kernel(PcoArgs a, int nsites) {

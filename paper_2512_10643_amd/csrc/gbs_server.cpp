@@ -38,6 +38,11 @@
 namespace {
 
 constexpr int kMaxActive = 256;  // requests in the batched sweep at once
+// Site steps enqueued per round of the batched sweep: one host round trip
+// (descriptor upload, launches, synchronisation, admission) per this many
+// steps.  A step's launches wait behind the builds that share the device, so
+// a synchronisation per site would cost a 144-site request 144 such waits.
+constexpr int kStepsPerRound = 16;
 
 int sfail(int code, const std::string& msg) { return gbs_fail(code, msg); }
 
@@ -165,6 +170,11 @@ void gbs_server_s::worker(int slot) {
     }
     q->t_start = wall_ms();
     gbs_mps h = nullptr;
+    // Served builds run the Gaussian SVD as the chain: builds of several
+    // requests share the GPU, so total work counts rather than one build's
+    // latency, and computing every site on its own does more work (a start
+    // from Gamma per site) and, for the banded circuits of a typical mix
+    // (bond modes with D - 1 near 1e-10), falls back to the chain anyway.
     int rc = gbs_build_handle(q->r.gamma, q->r.M, &q->r.opt, st, true, &h, 0);
     q->t_built = wall_ms();
     std::string err = rc != GBS_OK ? gbs_last_error() : std::string();
@@ -293,33 +303,53 @@ void gbs_server_s::sampler() {
       active.push_back(j);
     }
     if (active.empty()) continue;
-    // one site step of every active request
-    int nt = 8;
-    int64_t max_blocks = 0, max_shots = 0;
+    // up to kStepsPerRound site steps of every active request (a request
+    // whose last site comes earlier takes part in the steps up to it)
     const int64_t spb = sampler_shots_per_block();
-    for (size_t i = 0; i < active.size(); ++i) {
-      Job& j = active[i];
-      desc_host[i] = j.d;
-      nt = std::max(nt, gbs_batch_site_nt(j.q->h, j.d.site));
-      max_blocks = std::max(max_blocks, (j.d.nshots + spb - 1) / spb + 1);
-      max_shots = std::max(max_shots, j.d.nshots);
+    int nsteps = 0;
+    int nreq_k[kStepsPerRound], nt_k[kStepsPerRound];
+    int64_t blocks_k[kStepsPerRound], shots_k[kStepsPerRound];
+    for (int k = 0; k < kStepsPerRound; ++k) {
+      int n = 0, nt = 8;
+      int64_t mb = 0, ms = 0;
+      for (Job& j : active) {
+        const int site = j.d.site + k;
+        if (site > j.d.M) continue;
+        SampleBatchDesc& dk = desc_host[(size_t)k * kMaxActive + n++];
+        dk = j.d;
+        dk.site = site;
+        nt = std::max(nt, gbs_batch_site_nt(j.q->h, site));
+        mb = std::max(mb, (j.d.nshots + spb - 1) / spb + 1);
+        ms = std::max(ms, j.d.nshots);
+      }
+      if (n == 0) break;
+      nreq_k[k] = n;
+      nt_k[k] = nt;
+      blocks_k[k] = mb;
+      shots_k[k] = ms;
+      nsteps = k + 1;
     }
-    const int nreq = (int)active.size();
-    hipError_t e = hipMemcpyAsync(desc_dev, desc_host, nreq * sizeof(SampleBatchDesc), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_sample_batch(st, desc_dev, nreq, max_blocks, nt);
-    if (e == hipSuccess) e = launch_partition_batch(st, desc_dev, nreq, max_shots);
+    hipError_t e = hipMemcpyAsync(desc_dev, desc_host, (size_t)nsteps * kMaxActive * sizeof(SampleBatchDesc),
+                                  hipMemcpyHostToDevice, st);
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+      SampleBatchDesc* dd = desc_dev + (size_t)k * kMaxActive;
+      e = launch_sample_batch(st, dd, nreq_k[k], blocks_k[k], nt_k[k]);
+      if (e == hipSuccess) e = launch_partition_batch(st, dd, nreq_k[k], shots_k[k]);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) (void)hipGetLastError();
     std::vector<Job> next;
     {
       std::lock_guard<std::mutex> lk(mu);
-      ++steps;
-      step_requests += nreq;
-      max_batch = std::max<int64_t>(max_batch, nreq);
+      for (int k = 0; k < nsteps; ++k) {
+        ++steps;
+        step_requests += nreq_k[k];
+        max_batch = std::max<int64_t>(max_batch, nreq_k[k]);
+      }
       for (Job& j : active) {
-        const bool last = j.d.site >= j.d.M;
+        const bool last = j.d.site + nsteps > j.d.M;
         if (e == hipSuccess && !last) {
-          j.d.site += 1;
+          j.d.site += nsteps;
           next.push_back(j);
           continue;
         }
@@ -366,9 +396,10 @@ int gbs_server_create(int32_t slots, int64_t budget_bytes, int32_t max_queue, gb
   }
   if (hipStreamCreateWithFlags(&s->sstream, hipStreamNonBlocking) != hipSuccess)
     return undo("hipStreamCreateWithFlags failed");
-  if (hipMalloc((void**)&s->desc_dev, kMaxActive * sizeof(SampleBatchDesc)) != hipSuccess)
+  if (hipMalloc((void**)&s->desc_dev, (size_t)kStepsPerRound * kMaxActive * sizeof(SampleBatchDesc)) != hipSuccess)
     return undo("device allocation of the sweep descriptors failed");
-  if (hipHostMalloc((void**)&s->desc_host, kMaxActive * sizeof(SampleBatchDesc), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&s->desc_host, (size_t)kStepsPerRound * kMaxActive * sizeof(SampleBatchDesc),
+                    hipHostMallocDefault) != hipSuccess)
     return undo("pinned host allocation of the sweep descriptors failed");
   for (int i = 0; i < slots; ++i) s->workers.emplace_back(&gbs_server_s::worker, s, i);
   s->engine = std::thread(&gbs_server_s::sampler, s);
@@ -381,18 +412,21 @@ int gbs_server_submit(gbs_server s, const gbs_request* req, int64_t* id) {
   if (req->kind < GBS_REQ_BUILD_SAMPLE || req->kind > GBS_REQ_SAMPLE) return sfail(GBS_E_INVAL, "unknown request kind");
   if (req->shots < 0 || (req->shots > 0 && !req->out)) return sfail(GBS_E_INVAL, "invalid request (shots or out)");
   int64_t fp = 0;
+  gbs_build_opts opt = req->opt;
+  opt.flags |= GBS_CHAIN_GSVD;  // served builds run the chain (see the build worker)
   if (req->kind != GBS_REQ_SAMPLE) {
     if (!req->gamma || req->M < 1) return sfail(GBS_E_INVAL, "invalid request (gamma or M)");
-    fp = gbs_mps_footprint(req->M, &req->opt, req->shots);
+    fp = gbs_mps_footprint(req->M, &opt, req->shots);
     if (fp < 0) return sfail(GBS_E_INVAL, "invalid build options");
     if (fp > s->budget) return sfail(GBS_E_NOMEM, "request footprint exceeds the server's memory budget");
-    fp = gbs_mps_footprint(req->M, &req->opt, 0);  // the build's own reservation
+    fp = gbs_mps_footprint(req->M, &opt, 0);  // the build's own reservation
   } else if (req->shots < 1) {
     return sfail(GBS_E_INVAL, "a sample request needs shots >= 1");
   }
   Req* q = new (std::nothrow) Req();
   if (!q) return sfail(GBS_E_NOMEM, "host allocation failed");
   q->r = *req;
+  q->r.opt = opt;
   q->fp = fp;
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -90,6 +90,40 @@ def test_c1_fp64_amplitudes_match_oracle(torch_cuda):
     h.free()
 
 
+def _pco_terms(bases, d):
+    """Source terms of the PCO level gather, from the definition: element n
+    = (alpha, p, beta) with 2k > 0 photons sums one term per pair z <= z' of
+    its occupied modes (left bond modes, the physical mode, right bond modes),
+    a mode with n_z >= 2 pairing with itself.  bases: kept bases of bonds
+    0..M."""
+    tot = 0
+    for m in range(1, len(bases)):
+        for a in bases[m - 1]:
+            for b in bases[m]:
+                for p in range(d):
+                    occ = [x for x in a if x] + ([p] if p else []) + [x for x in b if x]
+                    if sum(occ) == 0 or sum(occ) % 2:
+                        continue
+                    s = len(occ)
+                    tot += s * (s - 1) // 2 + sum(1 for x in occ if x >= 2)
+    return tot
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_pco_term_count_is_the_sparse_update_count(torch_cuda, name):
+    """The level gather's counter of summed source terms equals the count
+    from the definition over the oracle's kept bases (bit-exact)."""
+    w = W.workload(name)
+    o = obuild.build_mps(w.gamma, w.d, w.chi)
+    want = _pco_terms(o.bases, w.d)
+    h = gpu_build(torch_cuda, w.gamma, w.d, w.chi, precision="fp64")
+    inf = h.info()
+    _say(f"case: {name} PCO terms {inf['pco_terms']} (definition {want}), elements {inf['pco_updates']}, "
+         f"level kernels {inf['t_pco_kernel_ms']:.3f} ms")
+    assert inf["pco_terms"] == want and inf["t_pco_kernel_ms"] > 0
+    h.free()
+
+
 def test_c2_fp64_amplitudes_match_oracle(torch_cuda):
     _say("case: c2 fp64 amplitudes (M=32, d=6, chi=64), low-photon patterns")
     w = W.workload("c2")
