@@ -82,6 +82,12 @@ typedef enum {
 #define GBS_KEEP_RAW 1u
 #define GBS_DENSE_SAMPLER 2u
 #define GBS_CHAIN_GSVD 4u
+/* GBS_KEPT_HEAP: enumerate every kept basis with the sequential best-first
+ * heap.  Bases of D >= 1024 states are otherwise enumerated in parallel
+ * (threshold search on the entanglement energy, then a sort by the same
+ * key), which gives the heap's basis and order exactly; the flag is there
+ * to compare the two. */
+#define GBS_KEPT_HEAP 8u
 typedef struct {
   int32_t d;
   int32_t chi;

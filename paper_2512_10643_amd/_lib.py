@@ -21,6 +21,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 GBS_KEEP_RAW = 1
 GBS_DENSE_SAMPLER = 2
 GBS_CHAIN_GSVD = 4
+GBS_KEPT_HEAP = 8
 # Size of the static device array gbs_mps_sample_noalloc samples on (the
 # header's GBS_SAMPLE_NOALLOC_SCRATCH_BYTES).
 GBS_SAMPLE_NOALLOC_SCRATCH_BYTES = 256 << 20

@@ -810,6 +810,7 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     cuts[m].chi = ne[m] > 0 && need ? chi : 1;
     cuts[m].off_state = off_state;
     cuts[m].off_occ = off_occ;
+    cuts[m].eslot = -1;
     off_state += cuts[m].chi;
     off_occ += (long)cuts[m].chi * ne[m];
   }
@@ -837,12 +838,31 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     ka.gws_stride = (long)kept_workspace_bytes(chi);
     HIP_CHECK_RET(tmp.alloc((void**)&ka.gws, (size_t)(M + 1) * ka.gws_stride));
   }
+  // large bases: the parallel enumeration, one workspace slot per such cut
+  {
+    int nslot = 0, ne_max = 0;
+    for (int m = 0; m <= M; ++m)
+      if (cuts[m].ne > 0 && cuts[m].chi >= kKeptParallelMin && cuts[m].ne <= kKeptEnumNeMax &&
+          !(opt->flags & GBS_KEPT_HEAP)) {
+        cuts[m].eslot = nslot++;
+        ne_max = std::max(ne_max, cuts[m].ne);
+      }
+    if (nslot > 0) {
+      ka.ews_ne = ne_max;
+      ka.ews_stride = (long)kept_enum_bytes(chi, ne_max);
+      HIP_CHECK_RET(tmp.alloc((void**)&ka.ews, (size_t)nslot * ka.ews_stride));
+      HIP_CHECK_RET(dalloc(tmp, &ka.enum_done, M + 1));
+      HIP_CHECK_RET(hipMemsetAsync(ka.enum_done, 0, (M + 1) * sizeof(int), st));
+      HIP_CHECK_RET(hipMemcpyAsync(cuts_dev, cuts.data(), (M + 1) * sizeof(CutDesc), hipMemcpyHostToDevice, st));
+    }
+  }
   h->occ = ka.occ;
   // vacuum cuts report one state
   {
     std::vector<int> ones(M + 1, 1);
     HIP_CHECK_RET(hipMemcpyAsync(ka.chi_out, ones.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   }
+  HIP_CHECK_RET(launch_kept_enum(st, ka, M + 1));
   HIP_CHECK_RET(launch_kept(st, ka, M + 1, chi));
   std::vector<int> kept(M + 1), ntot(off_state);
   std::vector<double> Eh(off_state);
@@ -1270,7 +1290,8 @@ __attribute__((visibility("hidden"))) int gbs_build_handle(const double* gamma, 
   if (opt->chi_build < 0 || opt->chi_build > GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi_build must be in [0, 4096]");
   if (!only_site && (long)opt->chi_build * opt->d > 2 * GBS_CHI_MAX) return fail(GBS_E_INVAL, "chi_build * d too large");
   if (opt->d > 64) return fail(GBS_E_INVAL, "d must be <= 64");
-  if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER | GBS_CHAIN_GSVD)) return fail(GBS_E_INVAL, "unknown build flag");
+  if (opt->flags & ~(GBS_KEEP_RAW | GBS_DENSE_SAMPLER | GBS_CHAIN_GSVD | GBS_KEPT_HEAP))
+    return fail(GBS_E_INVAL, "unknown build flag");
   gbs_mps_s* h = new (std::nothrow) gbs_mps_s();
   if (!h) return fail(GBS_E_NOMEM, "host allocation failed");
   h->M = M;
@@ -1859,6 +1880,8 @@ int64_t gbs_mps_footprint(int32_t M, const gbs_build_opts* opt, int64_t shots) {
   }
   // kept bases and maps
   b += (m + 1) * chi * (40 + 16 * GBS_K_MAX + 6 * (n2 / 2 + 1));
+  if (chi >= kKeptParallelMin && !(opt->flags & GBS_KEPT_HEAP))
+    b += (m + 1) * (int64_t)kept_enum_bytes((int)chi, (int)std::min<int64_t>(n2 / 2, kKeptEnumNeMax));
   // PCO tensors (FP64) and the truncation sweep
   const int64_t site = d * chi * chi;
   const int64_t chld = chi * d + 1;

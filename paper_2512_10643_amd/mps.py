@@ -160,17 +160,20 @@ class GaussianMPS:
 
 
 def build_site(gamma: torch.Tensor, d: int, chi: int, site: int, dstar: float = 1.0 + 1e-10,
-               stream=None) -> GaussianMPS:
+               eps_target: float = 0.0, kept_heap: bool = False, stream=None) -> GaussianMPS:
     """The raw PCO tensor of one site (1-based) at bond dimension chi, in
     FP64, without the rest of the MPS: export(site, "raw") gives it as
-    kept[site-1] x d x kept[site]; info() gives the phase times."""
+    kept[site-1] x d x kept[site]; info() gives the phase times.
+    eps_target > 0: the bond dimension of each cut is D(eps), capped at chi.
+    kept_heap: enumerate the kept bases with the sequential heap."""
     if not isinstance(gamma, torch.Tensor) or not gamma.is_cuda or gamma.dtype != torch.float64:
         raise ValueError("gamma must be a CUDA float64 tensor")
     if gamma.dim() != 2 or gamma.shape[0] != gamma.shape[1] or gamma.shape[0] % 2:
         raise GbsError(_lib.GBS_E_INVAL, "gamma must be 2M x 2M")
     gamma = gamma.contiguous()
     M = gamma.shape[0] // 2
-    opts = BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS["fp64"], flags=0, trunc_rel=0.0)
+    opts = BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS["fp64"],
+                     flags=_lib.GBS_KEPT_HEAP if kept_heap else 0, trunc_rel=0.0, eps_target=eps_target)
     h = ctypes.c_void_p()
     check(lib().gbs_mps_build_site(ctypes.c_void_p(gamma.data_ptr()), M, ctypes.byref(opts), int(site),
                                    _stream_handle(stream), ctypes.byref(h)))

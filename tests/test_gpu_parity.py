@@ -633,6 +633,59 @@ def test_single_site_large_d_elements_are_hafnians(torch_cuda):
     assert worst <= 1e-10
 
 
+def _tmsv_pairs_gamma(npair, r):
+    """npair two-mode squeezed vacua of equal strength on modes (i, i + npair):
+    every cut in the middle holds npair entangled pairs of one Lambda, so
+    states of equal total photon number have exactly equal energies."""
+    M = 2 * npair
+    u = np.zeros((M, M))
+    rr = np.zeros(M)
+    for i in range(npair):
+        u[i, i] = u[i + npair, i] = 1 / np.sqrt(2)
+        u[i, i + npair], u[i + npair, i + npair] = -1 / np.sqrt(2), 1 / np.sqrt(2)
+        rr[i], rr[i + npair] = r, -r
+    return W.gamma_of_circuit(rr, u.astype(np.complex128))
+
+
+@pytest.mark.parametrize("case", ["few_squeezed_1e4", "ties_2000", "eps_4096"])
+def test_parallel_kept_enumeration_equals_the_heap(torch_cuda, case):
+    """Bases of D >= 1024 states are enumerated in parallel (energy threshold
+    by counting, then a sort by the key); the sequential heap is the
+    reference order.  Both give the same basis, state by state, and the same
+    kept count: at D=10^4 (five squeezed modes), with exact energy ties
+    (four equal two-mode squeezed pairs: every state of one total photon
+    number has the same energy, bit for bit, so the tuple order decides),
+    and with D(eps) (eps = 1e-6: about 2480 states) capped at 4096."""
+    from paper_2512_10643_amd import mps as gmps
+    if case == "few_squeezed_1e4":
+        g, d, D, site, eps = W.few_squeezed().gamma, 4, 10_000, 72, 0.0
+    elif case == "ties_2000":
+        g, d, D, site, eps = _tmsv_pairs_gamma(4, 0.6), 4, 2000, 5, 0.0
+    else:
+        g, d, D, site, eps = W.few_squeezed().gamma, 4, 4096, 72, 1e-6  # D(eps) near 2480
+    gt = torch_cuda.tensor(g, dtype=torch_cuda.float64, device="cuda")
+    hp = gmps.build_site(gt, d, D, site, eps_target=eps)
+    hh = gmps.build_site(gt, d, D, site, eps_target=eps, kept_heap=True)
+    try:
+        ip, ih = hp.info(), hh.info()
+        _say(f"case: {case}: kept {ip['bond'][site - 1]}, {ip['bond'][site]}; parallel {ip['t_kept_ms']:.1f} ms, "
+             f"heap {ih['t_kept_ms']:.1f} ms")
+        assert ip["bond"] == ih["bond"] and ip["ne"] == ih["ne"]
+        for m in (site - 1, site):
+            bp, bh = hp.export(m, "basis"), hh.export(m, "basis")
+            assert np.array_equal(bp, bh), m
+        if case == "ties_2000":
+            assert ip["ne"][site - 1] == 4 and ip["bond"][site - 1] == D
+        if case == "eps_4096":
+            assert ip["bond"][site - 1] < D
+        raw_p = hp.export_elements(site, "raw", [[0, 0, 0], [1, 1, 0], [0, 2, 0]])
+        raw_h = hh.export_elements(site, "raw", [[0, 0, 0], [1, 1, 0], [0, 2, 0]])
+        assert np.array_equal(raw_p, raw_h)
+    finally:
+        hp.free()
+        hh.free()
+
+
 @pytest.mark.parametrize("d", [4, 10])
 def test_single_site_beyond_lds_heap(torch_cuda, d):
     """D=10^4 (the paper's largest bond), where the kept-basis enumeration
