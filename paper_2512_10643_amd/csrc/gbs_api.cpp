@@ -410,7 +410,41 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
                           sBp, 0, czero<cplx32>(), (cplx32*)Cp, ldc, sCp, batch);
     return zgemm<CT>(st, Mr, Nc, K, cone<CT>(), Ap, lda, sAp, opA, Bp, ldb, sBp, 0, czero<CT>(), Cp, ldc, sCp, batch);
   };
+  // Interior sites of equal shape whose FP64 tensors lie back to back in
+  // the PCO buffer go through in runs of up to kRun: one conversion and two
+  // batched products per run (Y = A^m U_m as one (a d) x b by b x r_m
+  // product per site, then U_{m-1}^H Y), instead of a launch sequence per
+  // site.
+  constexpr int kRun = 16;
+  CT *AmR = nullptr, *TcR = nullptr;
+  auto run_end = [&](int m0) {
+    int e = m0;
+    while (e < M && e - m0 < kRun && cl[e] == cl[m0] && cr[e] == cr[m0] && r[e - 1] == r[m0 - 1] &&
+           r[e] == r[m0] && A[e] == (C*)(T64 + t64off[e]) &&
+           (e == m0 || t64off[e] - t64off[e - 1] == (long)cl[m0] * d * cr[m0]))
+      ++e;
+    return e;
+  };
   for (int m = 1; m <= M; ++m) {
+    if (m > 1 && m < M) {
+      const int e = run_end(m);
+      if (e - m >= 2) {
+        const int a = cl[m], b = cr[m], ra = r[m - 1], rb = r[m], ns = e - m;
+        if (!AmR) {
+          HIP_CHECK_RET(dalloc(tmp, &AmR, (size_t)kRun * eld * d * eld));
+          HIP_CHECK_RET(dalloc(tmp, &TcR, (size_t)kRun * eld * d * eld));
+        }
+        HIP_CHECK_RET(convert<CT, cplx64>(st, AmR, A[m], (long)ns * a * d * b));
+        HIP_CHECK_RET(gemm_ct(a * d, rb, b, AmR, b, (long)a * d * b, 0, Ub + (long)m * eld * eld, eld, eld * eld, TcR,
+                              rb, (long)a * d * rb, ns));
+        HIP_CHECK_RET(gemm_ct(ra, d * rb, a, Ub + (long)(m - 1) * eld * eld, eld, eld * eld, 2, TcR, (long)d * rb,
+                              (long)a * d * rb, out + h->toff[m], (long)d * rb, (long)ra * d * rb, ns));
+        for (int k = m; k < e; ++k)
+          HIP_CHECK_RET(gauge_scale<CT>(st, out + h->toff[k], ra, d, rb, W64 + (long)(k - 1) * eld, W64 + (long)k * eld));
+        m = e - 1;
+        continue;
+      }
+    }
     int a = cl[m], b = cr[m], ra = r[m - 1], rb = r[m];
     HIP_CHECK_RET(convert<CT, cplx64>(st, Am, A[m], (long)a * d * b));
     // Y = A^m[p] U_m  (a x d x rb)
