@@ -390,6 +390,7 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
   __shared__ double tL[GBS_GSVD_N2_MAX], tauL[GBS_GSVD_N2_MAX];
   __shared__ double sig0[GBS_GSVD_N2_MAX / 2], sigR[GBS_GSVD_N2_MAX / 2];
   __shared__ int first[GBS_GSVD_N2_MAX / 2];
+  __shared__ int vblk[GBS_GSVD_N2_MAX / 2];  // block of the split tridiagonal form holding each sorted vector
   __shared__ int bad;
   const long ld = a.ld_ws;
   const bool in_lds = N2 <= GBS_GSVD_LDS_N2;
@@ -711,7 +712,10 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
       const int i = (int)(e / n), u = (int)(e % n);
       Zs[(long)i * n + first[u]] = Z[e];
     }
-    for (int u = tid; u < n; u += nt) sigR[first[u]] = sig0[u];
+    for (int u = tid; u < n; u += nt) {
+      sigR[first[u]] = sig0[u];
+      vblk[first[u]] = block_of(u);
+    }
     wg_sync();
     for (long e = tid; e < (long)N2 * n; e += nt) Z[e] = Zs[e];
     for (int u = tid; u < n; u += nt) sig0[u] = sigR[u];
@@ -726,8 +730,10 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
   // The members of a cluster are orthonormalised in order by one wave
   // (modified Gram-Schmidt): their solves resolve directions whose
   // eigenvalues are further apart than the shifts' error, and within a
-  // degenerate set any orthonormal basis is an eigenbasis (members from
-  // different blocks are orthogonal already).
+  // degenerate set any orthonormal basis is an eigenbasis.  Members from
+  // different blocks of the split form have disjoint support, so their
+  // products are exact zeros and are skipped (the vacuum modes of a start
+  // from Gamma form one large cluster spread over many blocks).
   {
     const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
     auto wave_sum = [&](double x) {
@@ -741,6 +747,7 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
       while (qe < n && first[qe] == q) ++qe;
       for (int u = q; u < qe; ++u) {
         for (int v2 = q; v2 < u; ++v2) {
+          if (vblk[v2] != vblk[u]) continue;
           double c = 0.0;
           for (int i = lane; i < N2; i += 64) c += Z[(long)i * n + v2] * Z[(long)i * n + u];
           c = wave_sum(c);

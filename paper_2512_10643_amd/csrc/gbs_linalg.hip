@@ -222,8 +222,10 @@ hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long 
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   const long tiles = (long)((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT) * batch;
   int ksplit = 1;
-  // a long K over few output tiles: slice K across workgroups (with a workspace)
-  while (ws && tiles * ksplit < 256 && K / (2 * ksplit) >= 4 * kGK * 4 &&
+  // a long K over few output tiles: slice K across workgroups (with a
+  // workspace), to about two workgroups per CU so that one hides the
+  // other's waits
+  while (ws && tiles * ksplit < 512 && K / (2 * ksplit) >= 4 * kGK * 4 &&
          (long)(2 * ksplit) * batch * M * N <= ws_elems)
     ksplit *= 2;
   dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, batch * ksplit);
