@@ -494,15 +494,12 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
       const double piv = P[pk(j, j)];
       for (int i = j + 1 + tid; i < N2; i += nt) P[pk(i, j)] /= piv;
       wg_sync();
-      const int rem = N2 - j - 1;
-      const long ntri = (long)rem * (rem + 1) / 2;
-      for (long e = tid; e < ntri; e += nt) {
-        int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-        while ((long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
-        while ((long)ii * (ii + 1) / 2 > e) --ii;
-        int kk = (int)(e - (long)ii * (ii + 1) / 2);
-        int i = j + 1 + ii, k = j + 1 + kk;
-        P[pk(i, k)] -= P[pk(i, j)] * P[pk(k, j)];
+      // trailing update, a row of the packed triangle per group of 32 lanes
+      // (row i is contiguous in k)
+      for (int i = j + 1 + (tid >> 5); i < N2; i += nt >> 5) {
+        const double lij = P[pk(i, j)];
+        double* Pi = P + (long)i * (i + 1) / 2;
+        for (int k = j + 1 + (tid & 31); k <= i; k += 32) Pi[k] -= lij * P[pk(k, j)];
       }
       wg_sync();
     }
