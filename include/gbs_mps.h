@@ -167,7 +167,7 @@ int gbs_mps_sample(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, void* 
 /* gbs_mps_sample for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same arguments, samples and errors as gbs_mps_sample (bit-identical
- * output), but the sweep's buffers (left vectors, norms, parities, running
+ * output), but the sweep's buffers (left vectors, parities, running
  * sums, shot partitions) come from one static device array of
  * GBS_SAMPLE_NOALLOC_SCRATCH_BYTES that each GPU holds for the life of the
  * process, so the call makes no hipMalloc, hipFree or allocating library

@@ -1486,8 +1486,7 @@ namespace {
 
 // Device buffers of one sampling call, sized for `chunk` shots per sweep.
 struct SampleBufs {
-  float* fb[2] = {nullptr, nullptr};  // MFMA sweep: left vectors (ping-pong)
-  float* sb[2] = {nullptr, nullptr};  // their inverse norms
+  float* fb[2] = {nullptr, nullptr};  // MFMA sweep: left vectors (ping-pong), unit norm
   int8_t *par = nullptr, *key = nullptr;
   float* cum = nullptr;
   int32_t *perm = nullptr, *cnt = nullptr, *perm2 = nullptr, *cnt2 = nullptr, *bcnt = nullptr;
@@ -1514,12 +1513,11 @@ struct SampleAlloc {
 hipError_t sample_buffers(const gbs_mps_s* h, int64_t chunk, SampleAlloc& a, SampleBufs& b) {
   if (h->packed) {
     // MFMA path: left vectors as interleaved floats in sector-local indices,
-    // rows padded to 16 complex, plus one inverse row norm per shot; parities
+    // rows padded to 16 complex; parities
     // and their partition (sector layout); key, running sums and the
     // partition of the shots left undecided by a site's first pass
     for (int i = 0; i < 2; ++i) {
       hipError_t e = a.get((void**)&b.fb[i], (size_t)chunk * h->ldl2 * sizeof(float));
-      if (e == hipSuccess) e = a.get((void**)&b.sb[i], (size_t)chunk * sizeof(float));
       if (e != hipSuccess) return e;
     }
     const size_t permb = (size_t)(chunk + sampler_shots_per_block()) * sizeof(int32_t);
@@ -1575,10 +1573,9 @@ int sample_sweep(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, hipStrea
         const SamplerGeom& G = h->sgeo[m];
         const bool more = G.npass[0] > 1 || G.npass[1] > 1;
         const float* P = h->packed + h->poff[m];
-        const float* sin = m == 1 ? nullptr : b.sb[cur];
         // first pass (outcome 0) for every shot
         if (clk) HIP_CHECK_RET(clk->mark(clk->first));
-        HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], sin, b.fb[1 - cur], b.sb[1 - cur], ldl2,
+        HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], b.fb[1 - cur], ldl2,
                                          part ? b.perm : nullptr, part ? b.cnt : nullptr, next ? b.par : nullptr,
                                          more ? b.cum : nullptr, more ? b.key : nullptr, 0, 1, s0, n, m, seed, out, M));
         if (clk) HIP_CHECK_RET(clk->mark(clk->first));
@@ -1586,9 +1583,9 @@ int sample_sweep(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, hipStrea
           // the other passes for the shots the first one left undecided
           HIP_CHECK_RET(launch_sampler_partition(st, b.key, n, b.bcnt, b.perm2, b.cnt2));
           if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
-          HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], sin, b.fb[1 - cur], b.sb[1 - cur],
-                                           ldl2, b.perm2, b.cnt2, next ? b.par : nullptr, b.cum, nullptr, 1,
-                                           kSamplerMaxOutcomes, s0, n, m, seed, out, M));
+          HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], b.fb[1 - cur], ldl2, b.perm2,
+                                           b.cnt2, next ? b.par : nullptr, b.cum, nullptr, 1, kSamplerMaxOutcomes, s0,
+                                           n, m, seed, out, M));
           if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
         }
         if (next) HIP_CHECK_RET(launch_sampler_partition(st, b.par, n, b.bcnt, b.perm, b.cnt));
@@ -1708,10 +1705,7 @@ __attribute__((visibility("hidden"))) int gbs_batch_prepare(gbs_mps h, int64_t s
   d->packed = h->packed;
   d->poff = h->poff_dev;
   d->geo = h->sgeo_dev;
-  for (int i = 0; i < 2; ++i) {
-    d->fb[i] = b.fb[i];
-    d->sb[i] = b.sb[i];
-  }
+  for (int i = 0; i < 2; ++i) d->fb[i] = b.fb[i];
   d->par = b.par;
   d->perm = b.perm;
   d->cnt = b.cnt;

@@ -77,8 +77,8 @@ hipError_t launch_sampler_init(hipStream_t st, float* l, long ldl2, int k0, int6
 
 // Passes [qbeg, qend) of one conditional-sampling step at `site` for nshots
 // shots (chunk-local rows of lin/lout, row stride ldl2 floats).  Rows of lin
-// are scaled by sin (NULL: 1); lout receives the unnormalised row of each
-// shot's outcome and sout its inverse norm.  perm == NULL: every shot is in
+// enter as they are; lout receives the row of each shot's outcome scaled to
+// unit norm (zero if the outcome has weight zero).  perm == NULL: every shot is in
 // sector 0 and workgroup b takes shots [128 b, 128 b + 128).  Otherwise
 // perm / cnt come from launch_sampler_partition and the grid covers both
 // sector groups.  par_out (may be NULL) receives the parity of each shot's
@@ -88,7 +88,7 @@ hipError_t launch_sampler_init(hipStream_t st, float* l, long ldl2, int k0, int6
 // undecided shot, and a second launch with qbeg = 1 takes the undecided
 // shots from the partition of key and continues from cum.
 hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom& g, const SamplerGeom* gd,
-                              const float* lin, const float* sin, float* lout, float* sout, long ldl2,
+                              const float* lin, float* lout, long ldl2,
                               const int32_t* perm, const int32_t* cnt, int8_t* par_out, float* cum, int8_t* key,
                               int qbeg, int qend, int64_t shot0, int64_t nshots, int site, uint64_t seed, int32_t* out,
                               int M);
@@ -105,15 +105,14 @@ hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t n
 // One request of a batched sampling sweep at its current site (device copy
 // read by the batched kernels).  The request's shots are numbered from 0
 // (Philox counter and output row), its left-vector rows ping-pong between
-// fb[0] / fb[1] (site m reads fb[(m - 1) & 1]) with their inverse norms in
-// sb, and par / perm / cnt / bcnt are its parity partition buffers (sized as
+// fb[0] / fb[1] (site m reads fb[(m - 1) & 1]), and par / perm / cnt / bcnt
+// are its parity partition buffers (sized as
 // for a single-request sweep of nshots).
 struct SampleBatchDesc {
   const float* packed;      // packed operand of the handle
   const long* poff;         // device, M + 1 offsets into packed (floats), by site
   const SamplerGeom* geo;   // device, M + 1 site geometries
   float* fb[2];
-  float* sb[2];
   int8_t* par;
   int32_t* perm;
   int32_t* cnt;

@@ -30,8 +30,8 @@
 // Workgroup: 8 waves x 16 shots, two waves per SIMD.  Each wave keeps the
 // row block of its 16 shots for all outcomes of a pass in MFMA accumulators
 // (v_mfma_f32_16x16x4f32 tiles) and reduces the squared norms across lanes.
-// Rows are stored unnormalised; the next site multiplies its A operand by
-// the stored 1/|T_p|.  B' arrives in LDS in K-chunks of 32 real rows, double
+// Rows are stored normalised (each scaled by 1/|T_p| as it is written), so
+// they enter the next site as they are.  B' arrives in LDS in K-chunks of 32 real rows, double
 // buffered by the LDS DMA path into two separate LDS arrays (so reads of one
 // need not wait for the DMA into the other), in the lane order the B operand
 // needs, four k-steps per 16-byte LDS read.
@@ -230,10 +230,13 @@ __device__ __forceinline__ void pass_draws(const floatx4 (&acc)[NT], int j0, int
     if (valid) {
       const uint32_t own = (shi >= 32 ? 0xffffffffu : ((1u << shi) - 1u)) &
                            ~(slo >= 32 ? 0xffffffffu : ((1u << slo) - 1u));
+      // the row of outcome psel, normalised (a row of zero weight stays zero)
+      const float sc = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
       float* orow = orow0 - 16 * slo;
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        if ((own >> t) & 1u) *(float4*)(orow + 16 * t) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+        if ((own >> t) & 1u)
+          *(float4*)(orow + 16 * t) = make_float4(acc[t][0] * sc, acc[t][1] * sc, acc[t][2] * sc, acc[t][3] * sc);
     }
   }
 }
@@ -248,11 +251,11 @@ template <int NT>
 __device__ __forceinline__ void sample_passes(
     float* __restrict__ Bs0, float* __restrict__ Bs1, int* __restrict__ wdone, int64_t blk,
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
-    const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
-    float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend, int64_t shot0, int64_t nshots,
-    int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    float* __restrict__ lout, long ldl2, const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt,
+    int8_t* __restrict__ par_out, float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend,
+    int64_t shot0, int64_t nshots, int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, scalar
   const int grp = lane >> 4;   // k sub-block of the left vector; column quad of the output
   const int col = lane & 15;   // shot within the wave
   // sector of this workgroup and the end of its slot range
@@ -280,7 +283,6 @@ __device__ __forceinline__ void sample_passes(
     // no rows in this left sector: outcome 0 with weight zero (a shot cannot
     // reach an empty sector with positive probability)
     if (valid && grp == 0 && qbeg == 0) {
-      sout[shot] = 0.f;
       out[(shot0 + shot) * (int64_t)M + (site - 1)] = 0;
       if (par_out) par_out[shot] = (int8_t)pi;
       if (key) key[shot] = 2;
@@ -291,7 +293,6 @@ __device__ __forceinline__ void sample_passes(
   const bool halfk = geo->half[pi] != 0;  // last chunk of each pass is half
   const int nte = geo->nt[pi], nto = geo->nt[pi ^ 1];
   const float* arow_ptr = lin + shot * ldl2 + 4 * grp;
-  const float ascale = (sin && valid) ? sin[shot] : 1.f;
   // the shot's uniform (every lane of the shot draws the same one) and the
   // running sum of its conditional probabilities
   float ur, csum = (qbeg > 0 && valid) ? cum[shot] : 0.f;
@@ -308,17 +309,17 @@ __device__ __forceinline__ void sample_passes(
   int psel = 0;
   float wsel = 0.f;
   floatx4 acc[NT];
-  // A rows arrive raw and are scaled only when they become the current
-  // operand, so nothing waits on the loads before the end of the chunk.  A
-  // lane past the end of the slot range reads row 0 (in bounds); it feeds
-  // only its own output column, which is never stored.
+  // A rows are loaded into `an` and copied to the operand only when they
+  // become current, so nothing waits on the loads before the end of the
+  // chunk.  A lane past the end of the slot range reads row 0 (in bounds); it
+  // feeds only its own output column, which is never stored.
   auto load_a = [&](int c, float4* r) {
     r[0] = *(const float4*)(arow_ptr + 32 * c);       // k-half 0: rows 32c + 4 grp + (0..3)
     r[1] = *(const float4*)(arow_ptr + 32 * c + 16);  // k-half 1: 16 rows further
   };
-  auto scale_a = [&](const float4* r, float* a) {
-    a[0] = r[0].x * ascale; a[1] = r[0].y * ascale; a[2] = r[0].z * ascale; a[3] = r[0].w * ascale;
-    a[4] = r[1].x * ascale; a[5] = r[1].y * ascale; a[6] = r[1].z * ascale; a[7] = r[1].w * ascale;
+  auto take_a = [&](const float4* r, float* a) {
+    a[0] = r[0].x; a[1] = r[0].y; a[2] = r[0].z; a[3] = r[0].w;
+    a[4] = r[1].x; a[5] = r[1].y; a[6] = r[1].z; a[7] = r[1].w;
   };
   // global -> LDS by the DMA path: lane l carries 16 bytes to block base + 16 l.
   // Chunks run as one sequence over (pass, c), so the first chunk of the next
@@ -359,7 +360,7 @@ __device__ __forceinline__ void sample_passes(
   advance_next();
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  scale_a(an, a);
+  take_a(an, a);
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   // chunk g of the sequence over (pass, c): MFMAs on one buffer while chunk
@@ -380,7 +381,7 @@ __device__ __forceinline__ void sample_passes(
       // its LDS reads of chunk g are done, before any wave goes on
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_s_barrier();
-      if (g + 1 < total) scale_a(an, a);
+      if (g + 1 < total) take_a(an, a);
       if (c == nchunk - 1) {
         pass_draws<NT>(acc, geo->j0[pi][q], geo->j0[pi][q + 1], nte, nto, ur, csum, done, wrote, psel, wsel, valid,
                        lout + shot * ldl2 + 4 * grp);
@@ -410,10 +411,9 @@ __device__ __forceinline__ void sample_passes(
     }
   }
   if (valid && grp == 0) {
-    // row scale, sample and the parity of the new bond index of the outcome
+    // sample and the parity of the new bond index of the outcome
     // stored here; an undecided shot hands its running sum to the next launch
     if (wrote) {
-      sout[shot] = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
       out[(shot0 + shot) * (int64_t)M + (site - 1)] = psel;
       if (par_out) par_out[shot] = (int8_t)((pi + psel) & 1);
     }
@@ -426,15 +426,14 @@ __device__ __forceinline__ void sample_passes(
 template <int NT>
 __global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
-    const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
-    float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend, int64_t shot0, int64_t nshots,
-    int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
+    float* __restrict__ lout, long ldl2, const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt,
+    int8_t* __restrict__ par_out, float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend,
+    int64_t shot0, int64_t nshots, int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
   __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
   __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
   __shared__ int wdone[kWaves];
-  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, P, geo, lin, sin, lout, sout, ldl2, perm, cnt, par_out, cum, key,
-                    qbeg, qend, shot0, nshots, site, k0, k1, out, M);
+  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, P, geo, lin, lout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend,
+                    shot0, nshots, site, k0, k1, out, M);
 }
 
 // Batched sweep: one site step of several sampling requests in one launch.
@@ -453,10 +452,9 @@ __global__ __launch_bounds__(64 * kWaves) void sample_batch_kernel(const SampleB
   const int64_t blocks = (D.nshots + kShotsPerWg - 1) / kShotsPerWg + (part ? 1 : 0);
   if ((int64_t)blockIdx.x >= blocks) return;  // whole workgroup
   const int cur = (m - 1) & 1;
-  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, D.packed + D.poff[m], D.geo + m, D.fb[cur],
-                    m == 1 ? nullptr : D.sb[cur], D.fb[1 - cur], D.sb[1 - cur], D.ldl2, part ? D.perm : nullptr,
-                    part ? D.cnt : nullptr, next ? D.par : nullptr, nullptr, nullptr, 0, kSamplerMaxOutcomes, 0,
-                    D.nshots, m, D.k0, D.k1, D.out, D.M);
+  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, D.packed + D.poff[m], D.geo + m, D.fb[cur], D.fb[1 - cur],
+                    D.ldl2, part ? D.perm : nullptr, part ? D.cnt : nullptr, next ? D.par : nullptr, nullptr, nullptr,
+                    0, kSamplerMaxOutcomes, 0, D.nshots, m, D.k0, D.k1, D.out, D.M);
 }
 
 // The first pass of a site (outcome 0, plus any outcomes sharing its pass)
@@ -468,13 +466,13 @@ __global__ __launch_bounds__(64 * kWaves) void sample_batch_kernel(const SampleB
 template <int NT>
 __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
-    const float* __restrict__ sin, float* __restrict__ lout, float* __restrict__ sout, long ldl2,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt, int8_t* __restrict__ par_out,
-    float* __restrict__ cum, int8_t* __restrict__ key, int64_t shot0, int64_t nshots, int site, uint32_t k0,
-    uint32_t k1, int32_t* __restrict__ out, int M) {
+    float* __restrict__ lout, long ldl2, const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt,
+    int8_t* __restrict__ par_out, float* __restrict__ cum, int8_t* __restrict__ key, int64_t shot0, int64_t nshots,
+    int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
   __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
   __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, scalar
   const int grp = lane >> 4, col = lane & 15;
   int64_t c0 = nshots, c1 = 0;
   if (perm) {
@@ -491,7 +489,6 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
     bool halfk, valid;
     long base;
     int64_t shot;
-    float ascale;
   };
   auto setup = [&](int64_t bb) {
     Blk s;
@@ -504,7 +501,6 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
     s.halfk = geo->half[s.pi] != 0;
     s.T = geo->tiles[s.pi][0];
     s.base = geo->base[s.pi][0];
-    s.ascale = (sin && s.valid) ? sin[s.shot] : 1.f;
     return s;
   };
   // the first block at or after bb whose sector has rows; the shots of a
@@ -516,7 +512,6 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
       if (geo->npass[pb] > 0) break;
       const Blk s = setup(bb);
       if (s.valid && grp == 0) {
-        sout[s.shot] = 0.f;
         out[(shot0 + s.shot) * (int64_t)M + (site - 1)] = 0;
         if (par_out) par_out[s.shot] = (int8_t)pb;
         if (key) key[s.shot] = 2;
@@ -529,9 +524,9 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
     r[0] = *(const float4*)(row);       // k-half 0: rows 32c + 4 grp + (0..3)
     r[1] = *(const float4*)(row + 16);  // k-half 1: 16 rows further
   };
-  auto scale_a = [&](const float4* r, float sc, float* a) {
-    a[0] = r[0].x * sc; a[1] = r[0].y * sc; a[2] = r[0].z * sc; a[3] = r[0].w * sc;
-    a[4] = r[1].x * sc; a[5] = r[1].y * sc; a[6] = r[1].z * sc; a[7] = r[1].w * sc;
+  auto take_a = [&](const float4* r, float* a) {
+    a[0] = r[0].x; a[1] = r[0].y; a[2] = r[0].z; a[3] = r[0].w;
+    a[4] = r[1].x; a[5] = r[1].y; a[6] = r[1].z; a[7] = r[1].w;
   };
   auto issue = [&](const Blk& s, int c, float* dst) {
     const float* src = P + s.base + 512L * s.T * c;
@@ -558,7 +553,7 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
   load_a(cur, 0, an);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  scale_a(an, cur.ascale, a);
+  take_a(an, a);
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   int c = 0;  // chunk of the current block in the buffer being multiplied
@@ -584,7 +579,7 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
       // and its LDS reads of this chunk are done, before any wave goes on
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_s_barrier();
-      if (fetch) scale_a(an, fnext ? nxt.ascale : cur.ascale, a);
+      if (fetch) take_a(an, a);
       if (!fnext) {
         ++c;
         continue;
@@ -607,7 +602,6 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
                      done, wrote, psel, wsel, cur.valid, lout + cur.shot * ldl2 + 4 * grp);
       if (cur.valid && grp == 0) {
         // outcome 0 is in the first pass, so every shot has a row stored
-        sout[cur.shot] = wsel > 0.f ? 1.f / sqrtf(wsel) : 0.f;
         out[(shot0 + cur.shot) * (int64_t)M + (site - 1)] = psel;
         if (par_out) par_out[cur.shot] = (int8_t)((cur.pi + psel) & 1);
         const bool fin = done || geo->npass[cur.pi] <= 1;
@@ -868,7 +862,7 @@ static int64_t persistent_grid(const void* kernel) {
 }
 
 hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom& g, const SamplerGeom* gd,
-                              const float* lin, const float* sin, float* lout, float* sout, long ldl2,
+                              const float* lin, float* lout, long ldl2,
                               const int32_t* perm, const int32_t* cnt, int8_t* par_out, float* cum, int8_t* key,
                               int qbeg, int qend, int64_t shot0, int64_t nshots, int site, uint64_t seed, int32_t* out,
                               int M) {
@@ -897,11 +891,11 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom&
   case NTV:                                                                                                       \
     if (qbeg == 0 && qend == 1) {                                                                                 \
       const dim3 pg((unsigned)std::min<int64_t>(grid.x, persistent_grid((const void*)sample_first_kernel<NTV>))); \
-      hipLaunchKernelGGL((sample_first_kernel<NTV>), pg, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout, sout,   \
-                         ldl2, perm, cnt, par_out, cum, key, shot0, nshots, site, k0, k1, out, M);                \
+      hipLaunchKernelGGL((sample_first_kernel<NTV>), pg, dim3(64 * kWaves), 0, st, P, gd, lin, lout, ldl2, perm,   \
+                         cnt, par_out, cum, key, shot0, nshots, site, k0, k1, out, M);                            \
     } else {                                                                                                      \
-      hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, sin, lout, sout,  \
-                         ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M);    \
+      hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, lout, ldl2, perm,  \
+                         cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M);                \
     }                                                                                                             \
     break;
   switch (nt) {
