@@ -38,8 +38,27 @@ template <> struct mma_traits<cplx32> {
   static __device__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// Tile (x, y, z) of this workgroup.  The device deals workgroups to its
+// eight XCDs (each with its own L2) in turn by launch index, so launch index
+// L runs tile (L mod 8) * (count / 8) + L / 8 of the x-fastest order: each
+// XCD gets a contiguous eighth of the tiles (whole problems, or whole
+// K-slices), whose operands then stay in its L2 instead of every XCD
+// streaming all of them.
+__device__ inline void xcd_tile(int& tx, int& ty, int& tz) {
+  const unsigned nxy = gridDim.x * gridDim.y, ntot = nxy * gridDim.z;
+  unsigned L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if ((ntot & 7u) == 0) L = (L & 7u) * (ntot >> 3) + (L >> 3);
+  tx = (int)(L % gridDim.x);
+  ty = (int)((L / gridDim.x) % gridDim.y);
+  tz = (int)(L / nxy);
+}
+
 namespace {
 constexpr int kGT = 32;   // output tile (complex) per workgroup
+// LDS row pitch of the staged operand blocks: one element more than the tile,
+// so that the lanes writing one row of A (or of B^T) down the K direction
+// land in different banks instead of all in the same ones
+constexpr int kGP = kGT + 1;
 constexpr int kGK = 16;   // K block per stage
 }  // namespace
 
@@ -52,18 +71,20 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
   typedef typename T::R R;
   typedef typename T::R4 R4;
   typedef typename T::V2 V2;
-  // per wave: As[kGK][kGT] and Bs[kGK][kGT]; reused for the 4 partial tiles
-  __shared__ V2 lds[4 * 2 * kGK * kGT];
-  // blockIdx.z = problem * ksplit + slice: a slice of K per workgroup when the
+  // per wave: As[kGK][kGP] and Bs[kGK][kGP]; reused for the 4 partial tiles
+  __shared__ V2 lds[4 * 2 * kGK * kGP];
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  // tz = problem * ksplit + slice: a slice of K per workgroup when the
   // output has too few tiles to fill the device (partials summed afterwards)
-  const int bz = blockIdx.z / ksplit, ks = blockIdx.z % ksplit;
+  const int bz = tz / ksplit, ks = tz % ksplit;
   A += (long)bz * sA;
   B += (long)bz * sB;
   Cm += (long)bz * sC;
-  const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+  const int i0 = ty * kGT, j0 = tx * kGT;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  V2* As = lds + w * 2 * kGK * kGT;
-  V2* Bs = As + kGK * kGT;
+  V2* As = lds + w * 2 * kGK * kGP;
+  V2* Bs = As + kGK * kGP;
   // this wave's K range within the workgroup's slice
   const int ksl = ((K + ksplit * kGK - 1) / (ksplit * kGK)) * kGK;
   const int k_lo = ks * ksl, k_hi = min(K, k_lo + ksl);
@@ -119,14 +140,14 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
       const int e = lane + 64 * r;
       int ii, kk;
       if (opA == 0) { ii = e / kGK; kk = e % kGK; } else { kk = e / kGT; ii = e % kGT; }
-      As[kk * kGT + ii] = ra[r];
+      As[kk * kGP + ii] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int e = lane + 64 * r;
       int jj, kk;
       if (opB == 0) { kk = e / kGT; jj = e % kGT; } else { jj = e / kGK; kk = e % kGK; }
-      Bs[kk * kGT + jj] = rb[r];
+      Bs[kk * kGP + jj] = rb[r];
     }
   };
   if (kb < ke) fetch(kb);
@@ -144,8 +165,8 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
       V2 av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = As[kk * kGT + 16 * t + (lane & 15)];
-        bv[t] = Bs[kk * kGT + 16 * t + (lane & 15)];
+        av[t] = As[kk * kGP + 16 * t + (lane & 15)];
+        bv[t] = Bs[kk * kGP + 16 * t + (lane & 15)];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -216,10 +237,57 @@ __global__ void zgemm_reduce_kernel(int M, int N, int batch, int ksplit, C alpha
   *c = v;
 }
 
+// One-row products (M = 1, a vector times a matrix): a 32 x 32 tile would
+// leave 31 of its rows idle and stream K through four waves one block at a
+// time, so these take a kernel of their own.  A workgroup owns 64 output
+// columns and 16 K-slices (one thread each); the slices are summed through
+// LDS in slice order, so results are deterministic.
+template <typename C>
+__global__ __launch_bounds__(1024) void zgemv_kernel(int N, int K, C alpha, const C* __restrict__ A, long lda,
+                                                     long sA, int opA, const C* __restrict__ B, long ldb, long sB,
+                                                     int opB, C beta, C* __restrict__ Cm, long sC) {
+  typedef typename real_of<C>::type R;
+  __shared__ C part[16][64];
+  const int bz = blockIdx.y;
+  A += (long)bz * sA;
+  B += (long)bz * sB;
+  Cm += (long)bz * sC;
+  const int jl = threadIdx.x & 63, ks = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
+  const int kq = (K + 15) / 16;
+  const int k0 = ks * kq, k1 = min(K, k0 + kq);
+  const long xs = opA == 0 ? 1 : lda;  // op(A) is 1 x K
+  R sr = 0, si = 0;
+  if (j < N) {
+    for (int k = k0; k < k1; ++k) {
+      C a = A[(long)k * xs];
+      C b = opB == 0 ? B[(long)k * ldb + j] : B[(long)j * ldb + k];
+      if (opA == 2) a.im = -a.im;
+      if (opB == 2) b.im = -b.im;
+      sr += a.re * b.re - a.im * b.im;
+      si += a.re * b.im + a.im * b.re;
+    }
+  }
+  part[ks][jl] = cmake<C>(sr, si);
+  __syncthreads();
+  if (ks != 0 || j >= N) return;
+  C acc = part[0][jl];
+  for (int q = 1; q < 16; ++q) acc = cadd(acc, part[q][jl]);
+  C v = cmul(alpha, acc);
+  if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, Cm[j]));
+  Cm[j] = v;
+}
+
 template <typename C>
 hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long lda, long sA, int opA, const C* B,
                  long ldb, long sB, int opB, C beta, C* Cm, long ldc, long sC, int batch, C* ws, long ws_elems) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (M == 1) {
+    if (batch > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zgemv_kernel<C>, dim3((unsigned)((N + 63) / 64), (unsigned)batch), dim3(1024), 0, st, N, K,
+                       alpha, A, lda, sA, opA, B, ldb, sB, opB, beta, Cm, sC);
+    return hipGetLastError();
+  }
   const long tiles = (long)((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT) * batch;
   int ksplit = 1;
   // a long K over few output tiles: slice K across workgroups (with a
@@ -272,15 +340,17 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
                                                            const cplx32* __restrict__ B, long ldb, long sB, int opB,
                                                            cplx32 beta, cplx32* __restrict__ Cm, long ldc, long sC,
                                                            int ksplit, cplx32* __restrict__ part_out) {
-  __shared__ float2 lds[4 * 2 * kXK * kGT];
-  const int bz = blockIdx.z / ksplit, ks = blockIdx.z % ksplit;
+  __shared__ float2 lds[4 * 2 * kXK * kGP];
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  const int bz = tz / ksplit, ks = tz % ksplit;
   A += (long)bz * sA;
   B += (long)bz * sB;
   Cm += (long)bz * sC;
-  const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+  const int i0 = ty * kGT, j0 = tx * kGT;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  float2* As = lds + w * 2 * kXK * kGT;
-  float2* Bs = As + kXK * kGT;
+  float2* As = lds + w * 2 * kXK * kGP;
+  float2* Bs = As + kXK * kGP;
   const int ksl = ((K + ksplit * kXK - 1) / (ksplit * kXK)) * kXK;
   const int k_lo = ks * ksl, k_hi = min(K, k_lo + ksl);
   const int kq = ((max(0, k_hi - k_lo) + 4 * kXK - 1) / (4 * kXK)) * kXK;
@@ -329,14 +399,14 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
       const int e = lane + 64 * r;
       int ii, kk;
       if (opA == 0) { ii = e / kXK; kk = e % kXK; } else { kk = e / kGT; ii = e % kGT; }
-      As[kk * kGT + ii] = ra[r];
+      As[kk * kGP + ii] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int e = lane + 64 * r;
       int jj, kk;
       if (opB == 0) { kk = e / kGT; jj = e % kGT; } else { jj = e / kXK; kk = e % kXK; }
-      Bs[kk * kGT + jj] = rb[r];
+      Bs[kk * kGP + jj] = rb[r];
     }
   };
   if (kb < ke) fetch(kb);
@@ -352,8 +422,8 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int kk = 8 * (lane >> 4) + e;
-        const float2 av = As[kk * kGT + 16 * t + (lane & 15)];
-        const float2 bv = Bs[kk * kGT + 16 * t + (lane & 15)];
+        const float2 av = As[kk * kGP + 16 * t + (lane & 15)];
+        const float2 bv = Bs[kk * kGP + 16 * t + (lane & 15)];
         __bf16 h, l;
         split_bf16(av.x, h, l); arh[t][e] = h; arl[t][e] = l;
         split_bf16(av.y, h, l); aih[t][e] = h; ail[t][e] = l; naih[t][e] = -h; nail[t][e] = -l;
