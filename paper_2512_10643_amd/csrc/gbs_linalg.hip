@@ -836,40 +836,58 @@ __global__ __launch_bounds__(512) void bj_solve_kernel(const cplx64* __restrict_
         rz[lane] = z;
       }
       __syncthreads();
-      // rows: S <- J^H S   (y_p = c x_p - s e^{i phi} x_q, y_q = s x_p + c e^{i phi} x_q)
-      for (int e = lane; e < (kBP / 2) * kBP; e += nth) {
-        const int pi = e / kBP, j = e % kBP;
-        const double sn = rs[pi];
-        if (sn == 0.0) continue;
-        const double c = rc[pi];
-        const cplx64 ep = cconj(rz[pi]);
-        const int p = rp[pi], q = rq[pi];
-        const cplx64 xp = S[p][j], xq = S[q][j];
-        S[p][j] = csub(cscale(xp, c), cmul(cscale(xq, sn), ep));
-        S[q][j] = cadd(cscale(xp, sn), cmul(cscale(xq, c), ep));
+      // The round's 16 rotations act on disjoint index pairs, so S <- J^H S J
+      // splits into independent 2 x 2 blocks (rows of pair P, columns of pair
+      // Q): each is updated in one step, rows first, then columns, as the
+      // two-sided product takes them, and V <- V J by pairs of columns.
+      //   rows:    y_p = c x_p - s e^{i phi} x_q,  y_q = s x_p + c e^{i phi} x_q
+      //   columns: y_p = c x_p - s e^{-i phi} x_q, y_q = s x_p + c e^{-i phi} x_q
+      if (lane < (kBP / 2) * (kBP / 2)) {
+        const int P = lane / (kBP / 2), Q = lane % (kBP / 2);
+        const double sP = rs[P], sQ = rs[Q];
+        if (sP != 0.0 || sQ != 0.0) {
+          const int p = rp[P], q = rq[P], u = rp[Q], v = rq[Q];
+          cplx64 x00 = S[p][u], x01 = S[p][v], x10 = S[q][u], x11 = S[q][v];
+          if (sP != 0.0) {
+            const double c = rc[P];
+            const cplx64 ep = cconj(rz[P]);
+            const cplx64 y00 = csub(cscale(x00, c), cmul(cscale(x10, sP), ep));
+            const cplx64 y10 = cadd(cscale(x00, sP), cmul(cscale(x10, c), ep));
+            const cplx64 y01 = csub(cscale(x01, c), cmul(cscale(x11, sP), ep));
+            const cplx64 y11 = cadd(cscale(x01, sP), cmul(cscale(x11, c), ep));
+            x00 = y00; x10 = y10; x01 = y01; x11 = y11;
+          }
+          if (sQ != 0.0) {
+            const double c = rc[Q];
+            const cplx64 em = rz[Q];
+            const cplx64 y00 = csub(cscale(x00, c), cmul(cscale(x01, sQ), em));
+            const cplx64 y01 = cadd(cscale(x00, sQ), cmul(cscale(x01, c), em));
+            const cplx64 y10 = csub(cscale(x10, c), cmul(cscale(x11, sQ), em));
+            const cplx64 y11 = cadd(cscale(x10, sQ), cmul(cscale(x11, c), em));
+            x00 = y00; x10 = y10; x01 = y01; x11 = y11;
+          }
+          if (P == Q) {  // the rotated pair: its off-diagonal entries vanish
+            x01 = cmake<cplx64>(0.0, 0.0);
+            x10 = cmake<cplx64>(0.0, 0.0);
+            x00.im = 0.0;
+            x11.im = 0.0;
+          }
+          S[p][u] = x00;
+          S[p][v] = x01;
+          S[q][u] = x10;
+          S[q][v] = x11;
+        }
       }
-      __syncthreads();
-      // columns: S <- S J and V <- V J   (y_p = c x_p - s e^{-i phi} x_q, y_q = s x_p + c e^{-i phi} x_q)
-      for (int e = lane; e < 2 * (kBP / 2) * kBP; e += nth) {
-        const int mat = e / ((kBP / 2) * kBP), rem = e % ((kBP / 2) * kBP);
-        const int pi = rem / kBP, i = rem % kBP;
+      for (int e = lane; e < (kBP / 2) * kBP; e += nth) {
+        const int pi = e / kBP, i = e % kBP;
         const double sn = rs[pi];
         if (sn == 0.0) continue;
         const double c = rc[pi];
         const cplx64 em = rz[pi];
         const int p = rp[pi], q = rq[pi];
-        cplx64(*X)[kBP + 1] = mat ? V : S;
-        const cplx64 xp = X[i][p], xq = X[i][q];
-        X[i][p] = csub(cscale(xp, c), cmul(cscale(xq, sn), em));
-        X[i][q] = cadd(cscale(xp, sn), cmul(cscale(xq, c), em));
-      }
-      __syncthreads();
-      if (lane < kBP / 2 && rs[lane] != 0.0) {
-        const int p = rp[lane], q = rq[lane];
-        S[p][q] = cmake<cplx64>(0.0, 0.0);
-        S[q][p] = cmake<cplx64>(0.0, 0.0);
-        S[p][p].im = 0.0;
-        S[q][q].im = 0.0;
+        const cplx64 xp = V[i][p], xq = V[i][q];
+        V[i][p] = csub(cscale(xp, c), cmul(cscale(xq, sn), em));
+        V[i][q] = cadd(cscale(xp, sn), cmul(cscale(xq, c), em));
       }
       __syncthreads();
     }
