@@ -237,6 +237,148 @@ __global__ void zgemm_reduce_kernel(int M, int N, int batch, int ksplit, C alpha
   *c = v;
 }
 
+namespace {
+constexpr int kWT = 64;        // output tile (complex) of the wide kernel
+constexpr int kWP = kWT + 1;   // its LDS row pitch (see kGP)
+}  // namespace
+
+// Wide tiles, for products with enough output to fill the device: a
+// workgroup owns a 64 x 64 complex tile over the whole K range, its four
+// waves own 32 x 32 quadrants (the same MFMA steps as above) and share the
+// 16-deep operand blocks (64 x 16 of op(A), 16 x 64 of op(B)) through LDS,
+// double buffered: the block after next is loaded into registers while the
+// current one is multiplied, and written to the free buffer before the
+// barrier that ends the step.  Each operand element is fetched once per
+// workgroup, a quarter of the traffic per flop of the 32 x 32 tiles whose
+// waves split K.
+template <typename C>
+__global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C alpha, const C* __restrict__ A,
+                                                         long lda, long sA, int opA, const C* __restrict__ B,
+                                                         long ldb, long sB, int opB, C beta, C* __restrict__ Cm,
+                                                         long ldc, long sC) {
+  typedef mma_traits<C> T;
+  typedef typename T::R R;
+  typedef typename T::R4 R4;
+  typedef typename T::V2 V2;
+  __shared__ V2 lds[2][2][kGK][kWP];  // [buffer][op(A) | op(B)][k][row or column]
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  A += (long)tz * sA;
+  B += (long)tz * sB;
+  Cm += (long)tz * sC;
+  const int i0 = ty * kWT, j0 = tx * kWT;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int qi = w >> 1, qj = w & 1;  // this wave's quadrant
+  R4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = R4{0, 0, 0, 0};
+      cim[a][b] = R4{0, 0, 0, 0};
+    }
+  // staging: 1024 complex of each operand per block, 4 per thread
+  V2 ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int ii, kk;
+      if (opA == 0) { ii = e / kGK; kk = e % kGK; } else { kk = e / kWT; ii = e % kWT; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      V2 v;
+      v.x = 0;
+      v.y = 0;
+      if (gi < M && gk < K) {
+        const C z = opA == 0 ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi];
+        v.x = z.re;
+        v.y = opA == 2 ? -z.im : z.im;
+      }
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int jj, kk;
+      if (opB == 0) { kk = e / kWT; jj = e % kWT; } else { jj = e / kGK; kk = e % kGK; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      V2 v;
+      v.x = 0;
+      v.y = 0;
+      if (gj < N && gk < K) {
+        const C z = opB == 0 ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk];
+        v.x = z.re;
+        v.y = opB == 2 ? -z.im : z.im;
+      }
+      rb[r] = v;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int ii, kk;
+      if (opA == 0) { ii = e / kGK; kk = e % kGK; } else { kk = e / kWT; ii = e % kWT; }
+      lds[buf][0][kk][ii] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int jj, kk;
+      if (opB == 0) { kk = e / kWT; jj = e % kWT; } else { jj = e / kGK; kk = e % kGK; }
+      lds[buf][1][kk][jj] = rb[r];
+    }
+  };
+  const int nk = (K + kGK - 1) / kGK;
+  if (nk > 0) {
+    fetch(0);
+    stage(0);
+  }
+  if (nk > 1) fetch(kGK);
+  __syncthreads();
+  for (int kb = 0; kb < nk; ++kb) {
+    const int buf = kb & 1;
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const int kk = 4 * ks + (lane >> 4);
+      V2 av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = lds[buf][0][kk][32 * qi + 16 * t + (lane & 15)];
+        bv[t] = lds[buf][1][kk][32 * qj + 16 * t + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cre[a][b] = T::mma(av[a].x, bv[b].x, cre[a][b]);
+          cre[a][b] = T::mma(-av[a].y, bv[b].y, cre[a][b]);
+          cim[a][b] = T::mma(av[a].x, bv[b].y, cim[a][b]);
+          cim[a][b] = T::mma(av[a].y, bv[b].x, cim[a][b]);
+        }
+    }
+    // the other buffer was last read in the previous step, before the
+    // barrier that ended it
+    if (kb + 1 < nk) {
+      stage(buf ^ 1);
+      if (kb + 2 < nk) fetch((kb + 2) * kGK);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + 32 * qi + 16 * a + T::row(lane, v), gj = j0 + 32 * qj + 16 * b + (lane & 15);
+        if (gi >= M || gj >= N) continue;
+        C z = cmul(alpha, cmake<C>(cre[a][b][v], cim[a][b][v]));
+        if (beta.re != (R)0 || beta.im != (R)0) z = cadd(z, cmul(beta, Cm[(long)gi * ldc + gj]));
+        Cm[(long)gi * ldc + gj] = z;
+      }
+}
+
 // One-row products (M = 1, a vector times a matrix): a 32 x 32 tile would
 // leave 31 of its rows idle and stream K through four waves one block at a
 // time, so these take a kernel of their own.  A workgroup owns 64 output
@@ -286,6 +428,13 @@ hipError_t zgemm(hipStream_t st, int M, int N, int K, C alpha, const C* A, long 
     if (batch > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zgemv_kernel<C>, dim3((unsigned)((N + 63) / 64), (unsigned)batch), dim3(1024), 0, st, N, K,
                        alpha, A, lda, sA, opA, B, ldb, sB, opB, beta, Cm, sC);
+    return hipGetLastError();
+  }
+  const long wide = (long)((N + kWT - 1) / kWT) * ((M + kWT - 1) / kWT) * batch;
+  if (wide >= 512 && K >= 4 * kGK) {
+    if (batch > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zgemm_wide_kernel<C>, dim3((N + kWT - 1) / kWT, (M + kWT - 1) / kWT, batch), dim3(256), 0, st,
+                       M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB, beta, Cm, ldc, sC);
     return hipGetLastError();
   }
   const long tiles = (long)((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT) * batch;
