@@ -83,7 +83,7 @@ typedef enum {
 #define GBS_DENSE_SAMPLER 2u
 #define GBS_CHAIN_GSVD 4u
 /* GBS_KEPT_HEAP: enumerate every kept basis with the sequential best-first
- * heap.  Bases of D >= 1024 states are otherwise enumerated in parallel
+ * heap.  Bases of D >= 256 states are otherwise enumerated in parallel
  * (threshold search on the entanglement energy, then a sort by the same
  * key), which gives the heap's basis and order exactly; the flag is there
  * to compare the two. */

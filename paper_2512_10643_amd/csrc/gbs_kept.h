@@ -45,7 +45,7 @@ hipError_t launch_kept(hipStream_t st, const KeptArgs& a, int ncuts, int chi);
 // Parallel enumeration of large bases, exactly the heap's order: cuts with
 // chi >= kKeptParallelMin, one workgroup each.  kept_enum_bytes: workspace
 // of one cut (chi states, ne modes).
-constexpr int kKeptParallelMin = 1024;
+constexpr int kKeptParallelMin = 256;
 constexpr int kKeptEnumNeMax = 300;   // modes the parallel enumeration takes
 size_t kept_enum_bytes(int chi, int ne);
 hipError_t launch_kept_enum(hipStream_t st, const KeptArgs& a, int ncuts);

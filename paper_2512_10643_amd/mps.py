@@ -184,7 +184,8 @@ def build_site(gamma: torch.Tensor, d: int, chi: int, site: int, dstar: float = 
 
 def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, precision: str = "fp64",
           keep_raw: bool = False, trunc_rel: float = 0.0, dense_sampler: bool = False,
-          eps_target: float = 0.0, chi_build: int = 0, chain_gsvd: bool = False, stream=None) -> GaussianMPS:
+          eps_target: float = 0.0, chi_build: int = 0, chain_gsvd: bool = False, kept_heap: bool = False,
+          stream=None) -> GaussianMPS:
     """Convert the pure Gaussian state with covariance `gamma` (2M x 2M FP64
     CUDA tensor, xxpp, vacuum = I/2) into an MPS with cutoff d and bond chi.
     dense_sampler: FP32 sampling over whole bonds instead of photon-parity
@@ -192,7 +193,8 @@ def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, pre
     weight is at most eps_target (at most chi).  chi_build > chi: kept bases
     and PCO tensors at chi_build states per cut, recompressed to chi by the
     truncation sweep.  chain_gsvd: run the Gaussian SVD as the sequential
-    chain instead of every site on its own."""
+    chain instead of every site on its own.  kept_heap: enumerate every kept
+    basis with the sequential heap (for comparison)."""
     if not isinstance(gamma, torch.Tensor) or not gamma.is_cuda or gamma.dtype != torch.float64:
         raise ValueError("gamma must be a CUDA float64 tensor")
     if gamma.dim() != 2 or gamma.shape[0] != gamma.shape[1] or gamma.shape[0] % 2:
@@ -201,7 +203,7 @@ def build(gamma: torch.Tensor, d: int, chi: int, dstar: float = 1.0 + 1e-10, pre
     M = gamma.shape[0] // 2
     opts = BuildOpts(d=d, chi=chi, dstar=dstar, prec=_lib.PRECISIONS[precision],
                      flags=(_lib.GBS_KEEP_RAW if keep_raw else 0) | (_lib.GBS_DENSE_SAMPLER if dense_sampler else 0)
-                     | (_lib.GBS_CHAIN_GSVD if chain_gsvd else 0),
+                     | (_lib.GBS_CHAIN_GSVD if chain_gsvd else 0) | (_lib.GBS_KEPT_HEAP if kept_heap else 0),
                      trunc_rel=trunc_rel, eps_target=eps_target, chi_build=chi_build)
     h = ctypes.c_void_p()
     check(lib().gbs_mps_build(ctypes.c_void_p(gamma.data_ptr()), M, ctypes.byref(opts), _stream_handle(stream),

@@ -647,9 +647,38 @@ def _tmsv_pairs_gamma(npair, r):
     return W.gamma_of_circuit(rr, u.astype(np.complex128))
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,chi", [("c2", 256), ("c3", 256)])
+def test_full_build_kept_bases_parallel_equal_the_heap(torch_cuda, name, chi):
+    """A full build enumerates the kept basis of every cut with D >= 256
+    states in parallel; the same build with the sequential heap gives the
+    same bases state by state, the same bond dimensions and the same
+    amplitudes to rounding (FP64)."""
+    w = W.workload(name)
+    gt = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
+    from paper_2512_10643_amd import mps as gmps
+    hp = gmps.build(gt, w.d, chi)
+    hh = gmps.build(gt, w.d, chi, kept_heap=True)
+    try:
+        ip, ih = hp.info(), hh.info()
+        _say(f"case: {name} full build: kept bases parallel {ip['t_kept_ms']:.1f} ms, heap {ih['t_kept_ms']:.1f} ms")
+        assert ip["bond"] == ih["bond"] and ip["ne"] == ih["ne"]
+        for m in range(1, w.M):
+            assert np.array_equal(hp.export(m, "basis"), hh.export(m, "basis")), m
+        rng = np.random.default_rng(3)
+        pats = rng.integers(0, 2, size=(64, w.M)) * (rng.random((64, w.M)) < 0.05)
+        pats[:, 0] += pats.sum(1) % 2  # even totals
+        p = torch_cuda.tensor(pats, dtype=torch_cuda.int32, device="cuda")
+        ap, ah = hp.amplitude(p).cpu().numpy(), hh.amplitude(p).cpu().numpy()
+        assert np.max(np.abs(ap - ah)) <= 1e-12
+    finally:
+        hp.free()
+        hh.free()
+
+
 @pytest.mark.parametrize("case", ["few_squeezed_1e4", "ties_2000", "eps_4096"])
 def test_parallel_kept_enumeration_equals_the_heap(torch_cuda, case):
-    """Bases of D >= 1024 states are enumerated in parallel (energy threshold
+    """Bases of D >= 256 states are enumerated in parallel (energy threshold
     by counting, then a sort by the key); the sequential heap is the
     reference order.  Both give the same basis, state by state, and the same
     kept count: at D=10^4 (five squeezed modes), with exact energy ties
