@@ -325,17 +325,24 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
     C one = cone<C>();
     HIP_CHECK_RET(hipMemcpyAsync(Ec, &one, sizeof(C), hipMemcpyHostToDevice, st));
     int cur = 0;
+    // FP64 environments are written straight into their slots of E64 (and
+    // read back from there for the next step); others go through Ec
+    constexpr bool direct = std::is_same<C, cplx64>::value;
     for (int m = M; m >= 2; --m) {
       int a = cl[m], b = cr[m];
       C* Ein = Ec + (long)cur * eld * eld;
       C* Eout = Ec + (long)(1 - cur) * eld * eld;
+      if (direct) {
+        if (m < M) Ein = (C*)(E64 + (long)m * eld * eld);
+        Eout = (C*)(E64 + (long)(m - 1) * eld * eld);
+      }
       // Tb[:, p, :] = A^m[:, p, :] E_m   (batched over p)
       HIP_CHECK_RET(zgemm<C>(st, a, b, b, cone<C>(), A[m], (long)d * b, b, 0, Ein, eld, 0, 0, czero<C>(), Tb,
                              (long)d * b, b, d));
       // E_{m-1} = Tb (a x d b) * A^m^H, stored with leading dimension eld
       HIP_CHECK_RET(zgemm<C>(st, a, a, d * b, cone<C>(), Tb, (long)d * b, 0, 0, A[m], (long)d * b, 0, 2, czero<C>(),
                              Eout, eld, 0, 1, gws, gws_elems));
-      HIP_CHECK_RET(convert<cplx64, C>(st, E64 + (long)(m - 1) * eld * eld, Eout, (long)a * eld));
+      if (!direct) HIP_CHECK_RET(convert<cplx64, C>(st, E64 + (long)(m - 1) * eld * eld, Eout, (long)a * eld));
       edim[m - 1] = a;
       cur = 1 - cur;
     }

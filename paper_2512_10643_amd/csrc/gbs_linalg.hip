@@ -150,15 +150,20 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
       Bs[kk * kGP + jj] = rb[r];
     }
   };
-  if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += kGK) {
+  // the wave's K blocks from the last to the first (the partial tiles are
+  // summed in the same direction below): the chain products run over kept
+  // states in order of decreasing weight, so the small terms are summed
+  // before the large ones join them
+  const int nbk = ke > kb ? (ke - kb + kGK - 1) / kGK : 0;
+  if (nbk > 0) fetch(kb + (nbk - 1) * kGK);
+  for (int jb = nbk - 1; jb >= 0; --jb) {
     stage();
     // the wave's own LDS writes complete before its lanes read each other's
     // entries (lgkmcnt(0); the loop trip count differs between waves, so no
     // workgroup barrier here)
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
-    if (k0 + kGK < ke) fetch(k0 + kGK);
+    if (jb > 0) fetch(kb + (jb - 1) * kGK);
 #pragma unroll
     for (int ks = 0; ks < kGK / 4; ++ks) {
       const int kk = 4 * ks + (lane >> 4);
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
     if (gi >= M || gj >= N) continue;
     R sr = 0, si = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 3; q >= 0; --q) {  // the last K range first
       const V2 z = lds[q * kGT * kGT + e];
       sr += z.x;
       si += z.y;
@@ -218,7 +223,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, C 
   }
 }
 
-// Sum of the K-slice partials in slice order, then alpha / beta.
+// Sum of the K-slice partials, the last slice first, then alpha / beta.
 template <typename C>
 __global__ void zgemm_reduce_kernel(int M, int N, int batch, int ksplit, C alpha, C beta, const C* __restrict__ part,
                                     C* __restrict__ Cm, long ldc, long sC) {
@@ -230,7 +235,7 @@ __global__ void zgemm_reduce_kernel(int M, int N, int batch, int ksplit, C alpha
   const long r = e % per;
   const int gi = (int)(r / N), gj = (int)(r % N);
   C acc = cmake<C>((R)0, (R)0);
-  for (int ks = 0; ks < ksplit; ++ks) acc = cadd(acc, part[((long)ks * batch + bz) * per + r]);
+  for (int ks = ksplit - 1; ks >= 0; --ks) acc = cadd(acc, part[((long)ks * batch + bz) * per + r]);  // last slice first
   C v = cmul(alpha, acc);
   C* c = Cm + (long)bz * sC + (long)gi * ldc + gj;
   if (beta.re != (R)0 || beta.im != (R)0) v = cadd(v, cmul(beta, *c));
@@ -269,14 +274,21 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
   const int i0 = ty * kWT, j0 = tx * kWT;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int qi = w >> 1, qj = w & 1;  // this wave's quadrant
-  R4 cre[2][2], cim[2][2];
+  // FP32 accumulates the four k-steps of a block in four separate sets,
+  // summed at the end (four partial sums over K, as the 32 x 32 kernel's
+  // waves make): one running sum over a long K loses accuracy that the
+  // reduced-precision builds need
+  constexpr int NS = 1;  // accumulator sets (one: the K order below is what accuracy needs)
+  R4 cre[NS][2][2], cim[NS][2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int q = 0; q < NS; ++q)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cre[a][b] = R4{0, 0, 0, 0};
-      cim[a][b] = R4{0, 0, 0, 0};
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cre[q][a][b] = R4{0, 0, 0, 0};
+        cim[q][a][b] = R4{0, 0, 0, 0};
+      }
   // staging: 1024 complex of each operand per block, 4 per thread
   V2 ra[4], rb[4];
   auto fetch = [&](int k0) {
@@ -329,12 +341,16 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
       lds[buf][1][kk][jj] = rb[r];
     }
   };
+  // K blocks from the last to the first: the chain products run over kept
+  // states in order of decreasing weight, so the small terms are summed
+  // before the large ones join them
   const int nk = (K + kGK - 1) / kGK;
+  auto kofs = [&](int kb) { return (nk - 1 - kb) * kGK; };
   if (nk > 0) {
-    fetch(0);
+    fetch(kofs(0));
     stage(0);
   }
-  if (nk > 1) fetch(kGK);
+  if (nk > 1) fetch(kofs(1));
   __syncthreads();
   for (int kb = 0; kb < nk; ++kb) {
     const int buf = kb & 1;
@@ -347,21 +363,22 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
         av[t] = lds[buf][0][kk][32 * qi + 16 * t + (lane & 15)];
         bv[t] = lds[buf][1][kk][32 * qj + 16 * t + (lane & 15)];
       }
+      const int q = ks % NS;
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          cre[a][b] = T::mma(av[a].x, bv[b].x, cre[a][b]);
-          cre[a][b] = T::mma(-av[a].y, bv[b].y, cre[a][b]);
-          cim[a][b] = T::mma(av[a].x, bv[b].y, cim[a][b]);
-          cim[a][b] = T::mma(av[a].y, bv[b].x, cim[a][b]);
+          cre[q][a][b] = T::mma(av[a].x, bv[b].x, cre[q][a][b]);
+          cre[q][a][b] = T::mma(-av[a].y, bv[b].y, cre[q][a][b]);
+          cim[q][a][b] = T::mma(av[a].x, bv[b].y, cim[q][a][b]);
+          cim[q][a][b] = T::mma(av[a].y, bv[b].x, cim[q][a][b]);
         }
     }
     // the other buffer was last read in the previous step, before the
     // barrier that ended it
     if (kb + 1 < nk) {
       stage(buf ^ 1);
-      if (kb + 2 < nk) fetch((kb + 2) * kGK);
+      if (kb + 2 < nk) fetch(kofs(kb + 2));
     }
     __syncthreads();
   }
@@ -373,7 +390,13 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
       for (int v = 0; v < 4; ++v) {
         const int gi = i0 + 32 * qi + 16 * a + T::row(lane, v), gj = j0 + 32 * qj + 16 * b + (lane & 15);
         if (gi >= M || gj >= N) continue;
-        C z = cmul(alpha, cmake<C>(cre[a][b][v], cim[a][b][v]));
+        R sr = cre[0][a][b][v], si = cim[0][a][b][v];
+#pragma unroll
+        for (int q = 1; q < NS; ++q) {
+          sr += cre[q][a][b][v];
+          si += cim[q][a][b][v];
+        }
+        C z = cmul(alpha, cmake<C>(sr, si));
         if (beta.re != (R)0 || beta.im != (R)0) z = cadd(z, cmul(beta, Cm[(long)gi * ldc + gj]));
         Cm[(long)gi * ldc + gj] = z;
       }
@@ -558,12 +581,14 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
       Bs[kk * kGP + jj] = rb[r];
     }
   };
-  if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += kXK) {
+  // K blocks from the last to the first, as in zgemm_mfma_kernel
+  const int nbk = ke > kb ? (ke - kb + kXK - 1) / kXK : 0;
+  if (nbk > 0) fetch(kb + (nbk - 1) * kXK);
+  for (int jb = nbk - 1; jb >= 0; --jb) {
     stage();
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
-    if (k0 + kXK < ke) fetch(k0 + kXK);
+    if (jb > 0) fetch(kb + (jb - 1) * kXK);
     // split operands: for quadrant t, A rows 16 t + lane % 16, B columns 16 t + lane % 16
     bf16x8 arh[2], arl[2], aih[2], ail[2], naih[2], nail[2], brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
@@ -620,7 +645,7 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(int M, int N, int K, 
     if (gi >= M || gj >= N) continue;
     float sr = 0.f, si = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 3; q >= 0; --q) {  // the last K range first
       const float2 z = lds[q * kGT * kGT + e];
       sr += z.x;
       si += z.y;
