@@ -1062,3 +1062,36 @@ def test_weak_bond_modes_run_the_chain(torch_cuda, name):
     pats = low_patterns(w.M, w.d, 6)[:1500]
     assert np.max(np.abs(gpu_amps(torch_cuda, h, pats) - omps.amplitudes(o.tensors, pats))) <= 1e-10
     h.free()
+
+
+@pytest.mark.gpu
+def test_ragged_bonds_stay_right_canonical(torch_cuda):
+    """C3 truncated to chi = 200, so the truncation sweep's transform
+    products (64 x 64 tiles over runs of 16 sites) end mid-tile.  Every site
+    after the first is right-canonical, sum_p B_p B_p^H = I, which this
+    checks weighted by the left bond's Schmidt values s (s G s against s^2,
+    relative to s_0^2: 1e-10 in FP64, 1e-5 in FP32), since rows of tiny
+    weight carry the rounding of the products amplified by 1/s; the MPS has
+    unit norm, and the FP32 build's fidelity with the FP64 build is within
+    1e-6 of one."""
+    from paper_2512_10643_amd import mps as gmps
+    w = W.workload("c3")
+    gt = torch_cuda.tensor(w.gamma, dtype=torch_cuda.float64, device="cuda")
+    h64 = gmps.build(gt, w.d, 200)
+    h32 = gmps.build(gt, w.d, 200, precision="fp32")
+    try:
+        assert max(h64.info()["bond"]) == 200
+        for h, tol in ((h64, 1e-10), (h32, 1e-5)):
+            for m in (2, 3, 40, 72, 110, 143, w.M):
+                B = h.export(m, "tensor")
+                sv = h.export(m - 1, "svals")[: B.shape[0]]
+                G = np.einsum("ipj,kpj->ik", B, B.conj())
+                err = np.max(np.abs(sv[:, None] * G * sv[None, :] - np.diag(sv ** 2))) / sv[0] ** 2
+                assert err <= tol, (m, err)
+            assert abs(h.overlap(h).real - 1) <= tol
+        f = h32.fidelity(h64)
+        _say(f"case: C3 at chi=200: 1 - F(fp32, fp64) = {1 - f:.2e}")
+        assert 1 - f <= 1e-6
+    finally:
+        h64.free()
+        h32.free()
