@@ -1176,12 +1176,17 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
       HIP_CHECK_RET(dalloc(h->keep, &h->packed, (size_t)tot));
       HIP_CHECK_RET(dalloc(h->keep, &h->poff_dev, (size_t)(M + 1)));
       HIP_CHECK_RET(hipMemcpyAsync(h->poff_dev, h->poff.data(), (M + 1) * sizeof(long), hipMemcpyHostToDevice, st));
+      // every site's operand in one launch
+      std::vector<SamplerPackDesc> pd(M);
       for (int m = 1; m <= M; ++m)
-        HIP_CHECK_RET(launch_pack(st, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
-                                  h->ssite[m], h->sgeo[m], h->sgeo_dev + m,
-                                  split ? dmaps + (long)(m - 1) * mb : nullptr,
-                                  split ? dmaps + (long)m * mb : nullptr, h->packed + h->poff[m]));
-      HIP_CHECK_RET(hipStreamSynchronize(st));
+        pd[m - 1] = SamplerPackDesc{(const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m], 0,
+                                    h->ssite[m], h->sgeo_dev + m, split ? dmaps + (long)(m - 1) * mb : nullptr,
+                                    split ? dmaps + (long)m * mb : nullptr, h->packed + h->poff[m]};
+      SamplerPackDesc* pd_dev = nullptr;
+      HIP_CHECK_RET(dalloc(tmp, &pd_dev, (size_t)M));
+      HIP_CHECK_RET(hipMemcpyAsync(pd_dev, pd.data(), M * sizeof(SamplerPackDesc), hipMemcpyHostToDevice, st));
+      HIP_CHECK_RET(launch_pack_batch(st, pd.data(), pd_dev, M, h->sgeo.data() + 1));
+      HIP_CHECK_RET(hipStreamSynchronize(st));  // pd is read by the copy
     }
   }
   h->t_svd = now_ms() - t3;

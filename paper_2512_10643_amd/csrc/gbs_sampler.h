@@ -70,6 +70,21 @@ hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, con
                        const SamplerGeom& g, const SamplerGeom* gd, const int32_t* mapL, const int32_t* mapR,
                        float* P);
 // Shots per workgroup of the sampling kernel.
+// One site's packing (the arguments of launch_pack) for a batched launch.
+struct SamplerPackDesc {
+  const cplx32* B;
+  int K, d, N, pad;
+  SamplerSite s;
+  const SamplerGeom* g;     // device
+  const int32_t* mapL;
+  const int32_t* mapR;
+  float* P;
+};
+// launch_pack for n sites in one launch: host and dev hold the same n
+// descriptors (dev: a device copy the launch reads), geo_host their
+// geometries (host copies, for the grid and the checks).
+hipError_t launch_pack_batch(hipStream_t st, const SamplerPackDesc* host, const SamplerPackDesc* dev, int n,
+                             const SamplerGeom* geo_host);
 int sampler_shots_per_block();
 // Left vectors of the first site (bond dimension k0, normally 1): row r of
 // `l` (stride ldl2 floats) becomes e_0 over 2 pad(k0) floats.

@@ -58,9 +58,9 @@ constexpr int kShotsPerWg = 16 * kWaves;
 // tiles.  c: chunk of 32 real K rows, t: 16-column tile, h: half of the
 // chunk (16 rows, 4 k-steps), j: k-step within the half (4 per 16-byte
 // read).  A half last chunk stores only its h = 0 blocks.
-__global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerSite s,
-                            const SamplerGeom* __restrict__ g, const int32_t* __restrict__ mapL,
-                            const int32_t* __restrict__ mapR, float* __restrict__ P) {
+__device__ __forceinline__ void pack_body(const cplx32* __restrict__ B, int d, int N, const SamplerSite& s,
+                                          const SamplerGeom* __restrict__ g, const int32_t* __restrict__ mapL,
+                                          const int32_t* __restrict__ mapR, float* __restrict__ P) {
   const int pi = blockIdx.y / kSamplerMaxOutcomes, q = blockIdx.y % kSamplerMaxOutcomes;
   if (s.nL[pi] == 0 || q >= g->npass[pi]) return;
   const int T = g->tiles[pi][q];
@@ -99,6 +99,18 @@ __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerS
     v = (a == 0) ? (bcol == 0 ? z.re : z.im) : (bcol == 0 ? -z.im : z.re);
   }
   P[g->base[pi][q] + e] = v;
+}
+
+__global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerSite s,
+                            const SamplerGeom* __restrict__ g, const int32_t* __restrict__ mapL,
+                            const int32_t* __restrict__ mapR, float* __restrict__ P) {
+  pack_body(B, d, N, s, g, mapL, mapR, P);
+}
+
+// Every site's packing in one launch (site blockIdx.z).
+__global__ void pack_batch_kernel(const SamplerPackDesc* __restrict__ desc) {
+  const SamplerPackDesc& q = desc[blockIdx.z];
+  pack_body(q.B, q.d, q.N, q.s, q.g, q.mapL, q.mapR, q.P);
 }
 
 // One thread per column b and a slice of the (a, p) rows; see launch_sector_mask.
@@ -840,6 +852,26 @@ hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, con
   if (mx == 0) return hipSuccess;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((mx + 255) / 256), (unsigned)(2 * kSamplerMaxOutcomes)), dim3(256),
                      0, st, B, d, N, s, gd, mapL, mapR, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batch(hipStream_t st, const SamplerPackDesc* host, const SamplerPackDesc* dev, int n,
+                             const SamplerGeom* geo_host) {
+  long mx = 0;
+  for (int i = 0; i < n; ++i) {
+    const SamplerPackDesc& q = host[i];
+    const SamplerGeom& g = geo_host[i];
+    if (q.s.nL[0] + q.s.nL[1] > q.K || (q.mapR && q.s.nR[0] + q.s.nR[1] > q.N) ||
+        (!q.mapR && (q.s.nR[0] > q.N || q.s.nR[1] > q.N)))
+      return hipErrorInvalidValue;
+    for (int pi = 0; pi < 2; ++pi)
+      for (int p = 0; p < g.npass[pi]; ++p) mx = std::max(mx, 512L * g.nchunk[pi] * g.tiles[pi][p]);  // bound
+  }
+  if (mx == 0 || n <= 0) return hipSuccess;
+  if (n > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pack_batch_kernel, dim3((unsigned)((mx + 255) / 256), (unsigned)(2 * kSamplerMaxOutcomes),
+                                             (unsigned)n),
+                     dim3(256), 0, st, dev);
   return hipGetLastError();
 }
 
