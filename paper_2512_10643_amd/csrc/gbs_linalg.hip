@@ -274,21 +274,14 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
   const int i0 = ty * kWT, j0 = tx * kWT;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int qi = w >> 1, qj = w & 1;  // this wave's quadrant
-  // FP32 accumulates the four k-steps of a block in four separate sets,
-  // summed at the end (four partial sums over K, as the 32 x 32 kernel's
-  // waves make): one running sum over a long K loses accuracy that the
-  // reduced-precision builds need
-  constexpr int NS = 1;  // accumulator sets (one: the K order below is what accuracy needs)
-  R4 cre[NS][2][2], cim[NS][2][2];
+  R4 cre[2][2], cim[2][2];
 #pragma unroll
-  for (int q = 0; q < NS; ++q)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cre[q][a][b] = R4{0, 0, 0, 0};
-        cim[q][a][b] = R4{0, 0, 0, 0};
-      }
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = R4{0, 0, 0, 0};
+      cim[a][b] = R4{0, 0, 0, 0};
+    }
   // staging: 1024 complex of each operand per block, 4 per thread
   V2 ra[4], rb[4];
   auto fetch = [&](int k0) {
@@ -341,9 +334,10 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
       lds[buf][1][kk][jj] = rb[r];
     }
   };
-  // K blocks from the last to the first: the chain products run over kept
-  // states in order of decreasing weight, so the small terms are summed
-  // before the large ones join them
+  // K blocks from the last to the first: the truncation products run over
+  // kept states in order of decreasing weight, so the small terms are summed
+  // before the large ones join them (one running sum from the first block
+  // cost the FP32 builds two orders of magnitude in 1 - F)
   const int nk = (K + kGK - 1) / kGK;
   auto kofs = [&](int kb) { return (nk - 1 - kb) * kGK; };
   if (nk > 0) {
@@ -363,15 +357,14 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
         av[t] = lds[buf][0][kk][32 * qi + 16 * t + (lane & 15)];
         bv[t] = lds[buf][1][kk][32 * qj + 16 * t + (lane & 15)];
       }
-      const int q = ks % NS;
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          cre[q][a][b] = T::mma(av[a].x, bv[b].x, cre[q][a][b]);
-          cre[q][a][b] = T::mma(-av[a].y, bv[b].y, cre[q][a][b]);
-          cim[q][a][b] = T::mma(av[a].x, bv[b].y, cim[q][a][b]);
-          cim[q][a][b] = T::mma(av[a].y, bv[b].x, cim[q][a][b]);
+          cre[a][b] = T::mma(av[a].x, bv[b].x, cre[a][b]);
+          cre[a][b] = T::mma(-av[a].y, bv[b].y, cre[a][b]);
+          cim[a][b] = T::mma(av[a].x, bv[b].y, cim[a][b]);
+          cim[a][b] = T::mma(av[a].y, bv[b].x, cim[a][b]);
         }
     }
     // the other buffer was last read in the previous step, before the
@@ -390,13 +383,7 @@ __global__ __launch_bounds__(256) void zgemm_wide_kernel(int M, int N, int K, C 
       for (int v = 0; v < 4; ++v) {
         const int gi = i0 + 32 * qi + 16 * a + T::row(lane, v), gj = j0 + 32 * qj + 16 * b + (lane & 15);
         if (gi >= M || gj >= N) continue;
-        R sr = cre[0][a][b][v], si = cim[0][a][b][v];
-#pragma unroll
-        for (int q = 1; q < NS; ++q) {
-          sr += cre[q][a][b][v];
-          si += cim[q][a][b][v];
-        }
-        C z = cmul(alpha, cmake<C>(sr, si));
+        C z = cmul(alpha, cmake<C>(cre[a][b][v], cim[a][b][v]));
         if (beta.re != (R)0 || beta.im != (R)0) z = cadd(z, cmul(beta, Cm[(long)gi * ldc + gj]));
         Cm[(long)gi * ldc + gj] = z;
       }
