@@ -58,29 +58,39 @@ constexpr int kShotsPerWg = 16 * kWaves;
 // tiles.  c: chunk of 32 real K rows, t: 16-column tile, h: half of the
 // chunk (16 rows, 4 k-steps), j: k-step within the half (4 per 16-byte
 // read).  A half last chunk stores only its h = 0 blocks.
+//
+// One thread per complex entry z of B: its 2 x 2 real block [[re, im],
+// [-im, re]] (rows a, columns b of the embedding) sits at lanes 2l, 2l + 1
+// and k-steps 2m, 2m + 1 of the layout, i.e. two float2 pairs 4 floats
+// apart.  Thread order within a chunk is (t, h, l, m), so a wave writes 1 KB
+// of P contiguously and reads 8 complex rows of 8 adjacent columns of B.
 __device__ __forceinline__ void pack_body(const cplx32* __restrict__ B, int d, int N, const SamplerSite& s,
                                           const SamplerGeom* __restrict__ g, const int32_t* __restrict__ mapL,
                                           const int32_t* __restrict__ mapR, float* __restrict__ P) {
   const int pi = blockIdx.y / kSamplerMaxOutcomes, q = blockIdx.y % kSamplerMaxOutcomes;
   if (s.nL[pi] == 0 || q >= g->npass[pi]) return;
   const int T = g->tiles[pi][q];
-  const long per_chunk = 512L * T;
+  const long per_chunk = 128L * T;  // complex entries of a full chunk
   const int nfull = g->nchunk[pi] - g->half[pi];
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= per_chunk * nfull + (g->half[pi] ? 256L * T : 0)) return;
+  if (e >= per_chunk * nfull + (g->half[pi] ? 64L * T : 0)) return;
   int c, r, h, t;
+  long o;  // float offset of the thread's first pair within the pass
   if (e < per_chunk * nfull) {
     c = (int)(e / per_chunk);
     r = (int)(e % per_chunk);
-    h = (r >> 8) & 1;
-    t = r >> 9;
+    h = (r >> 6) & 1;
+    t = r >> 7;
+    o = 512L * T * c + ((long)t << 9) + (h << 8);
   } else {  // half chunk: blocks (t, h = 0) only
     c = nfull;
     r = (int)(e - per_chunk * nfull);
     h = 0;
-    t = r >> 8;
+    t = r >> 6;
+    o = 512L * T * c + ((long)t << 8);
   }
-  const int j = r & 3, lane = (r >> 2) & 63;
+  const int m = r & 1, l = (r >> 1) & 31;  // k-step pair, lane pair
+  o += (l << 3) + (m << 1);
   // the outcome owning tile t
   int p = g->j0[pi][q], sig = pi ^ (p & 1);
   while (t >= g->nt[sig]) {
@@ -88,17 +98,19 @@ __device__ __forceinline__ void pack_body(const cplx32* __restrict__ B, int d, i
     ++p;
     sig = pi ^ (p & 1);
   }
-  const int kr = 32 * c + 16 * h + 4 * (lane >> 4) + j;  // real row of B'
-  const int nr = 16 * t + (lane & 15);                  // real column within outcome p
-  const int k = kr >> 1, a = kr & 1, jj = nr >> 1, bcol = nr & 1;
-  float v = 0.f;
+  const int k = 16 * c + 8 * h + 2 * (l >> 3) + m;  // complex row of B restricted to sector pi
+  const int jj = 8 * t + (l & 7);                   // complex column within outcome p
+  float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
   if (k < s.nL[pi] && jj < s.nR[sig]) {
     const int al = mapL ? mapL[(pi ? s.nL[0] : 0) + k] : k;
     const int be = mapR ? mapR[(sig ? s.nR[0] : 0) + jj] : jj;
     const cplx32 z = B[((long)al * d + p) * N + be];
-    v = (a == 0) ? (bcol == 0 ? z.re : z.im) : (bcol == 0 ? -z.im : z.re);
+    lo = make_float2(z.re, -z.im);  // column b = 0: rows a = 0, 1
+    hi = make_float2(z.im, z.re);   // column b = 1
   }
-  P[g->base[pi][q] + e] = v;
+  float* dst = P + g->base[pi][q] + o;
+  *(float2*)dst = lo;
+  *(float2*)(dst + 4) = hi;
 }
 
 __global__ void pack_kernel(const cplx32* __restrict__ B, int d, int N, SamplerSite s,
@@ -848,7 +860,7 @@ hipError_t launch_pack(hipStream_t st, const cplx32* B, int K, int d, int N, con
     return hipErrorInvalidValue;
   long mx = 0;
   for (int pi = 0; pi < 2; ++pi)
-    for (int q = 0; q < g.npass[pi]; ++q) mx = std::max(mx, 512L * g.nchunk[pi] * g.tiles[pi][q]);  // bound
+    for (int q = 0; q < g.npass[pi]; ++q) mx = std::max(mx, 128L * g.nchunk[pi] * g.tiles[pi][q]);  // bound
   if (mx == 0) return hipSuccess;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((mx + 255) / 256), (unsigned)(2 * kSamplerMaxOutcomes)), dim3(256),
                      0, st, B, d, N, s, gd, mapL, mapR, P);
@@ -865,7 +877,7 @@ hipError_t launch_pack_batch(hipStream_t st, const SamplerPackDesc* host, const 
         (!q.mapR && (q.s.nR[0] > q.N || q.s.nR[1] > q.N)))
       return hipErrorInvalidValue;
     for (int pi = 0; pi < 2; ++pi)
-      for (int p = 0; p < g.npass[pi]; ++p) mx = std::max(mx, 512L * g.nchunk[pi] * g.tiles[pi][p]);  // bound
+      for (int p = 0; p < g.npass[pi]; ++p) mx = std::max(mx, 128L * g.nchunk[pi] * g.tiles[pi][p]);  // bound
   }
   if (mx == 0 || n <= 0) return hipSuccess;
   if (n > 65535) return hipErrorInvalidValue;
