@@ -1593,14 +1593,14 @@ int sample_sweep(gbs_mps h, int64_t shots, uint64_t seed, int32_t* out, hipStrea
         if (clk) HIP_CHECK_RET(clk->mark(clk->first));
         if (more) {
           // the other passes for the shots the first one left undecided
-          HIP_CHECK_RET(launch_sampler_partition(st, b.key, n, b.bcnt, b.perm2, b.cnt2));
+          HIP_CHECK_RET(launch_sampler_partition(st, b.key, n, b.bcnt, b.perm2, b.cnt2, true));
           if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
           HIP_CHECK_RET(launch_sample_mfma(st, P, G, h->sgeo_dev + m, b.fb[cur], b.fb[1 - cur], ldl2, b.perm2,
                                            b.cnt2, next ? b.par : nullptr, b.cum, nullptr, 1, kSamplerMaxOutcomes, s0,
                                            n, m, seed, out, M));
           if (clk) HIP_CHECK_RET(clk->mark(clk->rest));
         }
-        if (next) HIP_CHECK_RET(launch_sampler_partition(st, b.par, n, b.bcnt, b.perm, b.cnt));
+        if (next) HIP_CHECK_RET(launch_sampler_partition(st, b.par, n, b.bcnt, b.perm, b.cnt, false));
         cur = 1 - cur;
       }
     }

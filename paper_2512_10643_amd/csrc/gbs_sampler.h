@@ -99,23 +99,26 @@ hipError_t launch_sampler_init(hipStream_t st, float* l, long ldl2, int k0, int6
 // sector groups.  par_out (may be NULL) receives the parity of each shot's
 // new bond index.  A launch with qbeg = 0 starts every shot's cumulative
 // probability at 0; if it stops before a sector's last pass, it writes key
-// (2: decided, else the shot's left sector) and the running sum cum of each
+// (127: decided, else 4 x the shot's left sector + a bucket 0..3 of how far
+// its uniform lies past the running sum) and the running sum cum of each
 // undecided shot, and a second launch with qbeg = 1 takes the undecided
-// shots from the partition of key and continues from cum.
+// shots from the bucketed partition of key and continues from cum.
 hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom& g, const SamplerGeom* gd,
                               const float* lin, float* lout, long ldl2,
                               const int32_t* perm, const int32_t* cnt, int8_t* par_out, float* cum, int8_t* key,
                               int qbeg, int qend, int64_t shot0, int64_t nshots, int site, uint64_t seed, int32_t* out,
                               int M);
 
-// Stable partition of shots by a key in {0, 1, other}: perm[0, c0) lists the
-// shots with key 0 in order, perm[E, E + c1) those with key 1, E = c0 rounded
-// up to a multiple of 128; other keys are left out; cnt = {c0, c1}.  perm
-// holds nshots + 128 ints; bcnt is a workspace of sampler_partition_ws(nshots)
-// ints.
+// Stable partition of shots by sector.  Without buckets the key is the
+// sector in {0, 1}; with buckets it is 4 x sector + bucket (0..3) and each
+// sector's shots are sorted by bucket (stable within a bucket).  Other keys
+// are left out.  perm[0, c0) lists the sector-0 shots, perm[E, E + c1) the
+// sector-1 shots, E = c0 rounded up to a multiple of 128; cnt = {c0, c1}.
+// perm holds nshots + 128 ints; bcnt is a workspace of
+// sampler_partition_ws(nshots) ints.
 int64_t sampler_partition_ws(int64_t nshots);
 hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t nshots, int32_t* bcnt,
-                                    int32_t* perm, int32_t* cnt);
+                                    int32_t* perm, int32_t* cnt, bool buckets);
 
 // One request of a batched sampling sweep at its current site (device copy
 // read by the batched kernels).  The request's shots are numbered from 0

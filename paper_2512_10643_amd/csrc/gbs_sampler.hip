@@ -48,6 +48,17 @@ namespace {
 
 constexpr int kWaves = 8;              // waves per workgroup
 constexpr int kShotsPerWg = 16 * kWaves;
+// Waves per workgroup of the launches after a site's first (the few shots
+// the first pass leaves undecided): workgroups of 64 shots stop sooner than
+// 128 and spread those shots over more compute units.  Their grid is
+// kRestGridMult times the resident workgroups, so the device hands blocks
+// to compute units as they free up (blocks of hard shots run longer).
+constexpr int kRestWaves = 4;
+constexpr int kRestGridMult = 4;
+// Key of a shot after a site's first launch: kKeyDone once decided, else
+// its left sector and one of kKeyBuckets buckets (see shot_key)
+constexpr int kKeyBuckets = 4;
+constexpr int8_t kKeyDone = 127;
 
 // Packed layout of B' for one site, per left sector pi and pass q, one 1 KiB
 // block per (c, t, h):
@@ -142,6 +153,18 @@ __global__ __launch_bounds__(256) void sector_mask_kernel(const cplx32* __restri
     }
   }
   if (m) atomicOr(&mask_r[b], m);
+}
+
+// An undecided shot's bucket measures how far its uniform ur lies past the
+// running sum csum, relative to the probability still to come (1 - csum,
+// rows being of unit norm): thresholds 1/2, 3/4 and 9/10.  The remaining
+// launch takes the shots sorted by bucket, so its workgroups of low buckets,
+// which mostly need one more outcome, stop early.
+__device__ __forceinline__ int8_t shot_key(bool fin, int pi, float ur, float csum) {
+  if (fin) return kKeyDone;
+  const float dlt = ur - csum, rest = 1.f - csum;
+  const int b = (dlt >= 0.5f * rest) + (dlt >= 0.75f * rest) + (dlt >= 0.9f * rest);
+  return (int8_t)(pi * kKeyBuckets + b);
 }
 
 // One MFMA step with the B' fragment as the A operand and the left vectors as
@@ -270,8 +293,10 @@ __device__ __forceinline__ void pass_draws(const floatx4 (&acc)[NT], int j0, int
 // undecided, and, over all passes, by the batched sweep).  Bs0, Bs1: the
 // kernel's two LDS operand buffers (512 NT floats each, two separate arrays
 // so the compiler can tell the buffer being read from the one the DMA is
-// filling); wdone: kWaves ints of LDS.
-template <int NT>
+// filling); wdone: W ints of LDS.  W waves of 16 shots per workgroup (W
+// divides kWaves, so a block never straddles the 128-aligned start of the
+// sector-1 slots).
+template <int NT, int W>
 __device__ __forceinline__ void sample_passes(
     float* __restrict__ Bs0, float* __restrict__ Bs1, int* __restrict__ wdone, int64_t blk,
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
@@ -283,8 +308,9 @@ __device__ __forceinline__ void sample_passes(
   const int grp = lane >> 4;   // k sub-block of the left vector; column quad of the output
   const int col = lane & 15;   // shot within the wave
   // sector of this workgroup and the end of its slot range
+  static_assert(kWaves % W == 0, "W must divide kWaves");
   int pi = 0;
-  const int64_t slot0 = blk * kShotsPerWg;
+  const int64_t slot0 = blk * 16 * W;
   int64_t send = nshots;
   if (perm) {
     const int64_t c0 = cnt[0], c1 = cnt[1];
@@ -309,7 +335,7 @@ __device__ __forceinline__ void sample_passes(
     if (valid && grp == 0 && qbeg == 0) {
       out[(shot0 + shot) * (int64_t)M + (site - 1)] = 0;
       if (par_out) par_out[shot] = (int8_t)pi;
-      if (key) key[shot] = 2;
+      if (key) key[shot] = kKeyDone;
     }
     return;  // uniform over the workgroup
   }
@@ -350,11 +376,11 @@ __device__ __forceinline__ void sample_passes(
   // pass is in flight while this pass's draws are made.
   auto issue = [&](const float* src, int T, float* dst, bool halfc) {
     if (halfc) {  // blocks (t, h = 0) of a half chunk land where a full chunk has them
-      for (int blk = w; blk < T; blk += kWaves)
+      for (int blk = w; blk < T; blk += W)
         __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
                                          (void __attribute__((address_space(3)))*)(dst + 2 * blk * 256), 16, 0, 0);
     } else {
-      for (int blk = w; blk < 2 * T; blk += kWaves)  // uniform per wave
+      for (int blk = w; blk < 2 * T; blk += W)  // uniform per wave
         __builtin_amdgcn_global_load_lds((const void*)(src + blk * 256 + lane * 4),
                                          (void __attribute__((address_space(3)))*)(dst + blk * 256), 16, 0, 0);
     }
@@ -420,7 +446,7 @@ __device__ __forceinline__ void sample_passes(
           __syncthreads();
           int all = 1;
 #pragma unroll
-          for (int i = 0; i < kWaves; ++i) all &= wdone[i];
+          for (int i = 0; i < W; ++i) all &= wdone[i];
           if (all) {
             __builtin_amdgcn_s_waitcnt(0);
             stop = true;
@@ -442,22 +468,33 @@ __device__ __forceinline__ void sample_passes(
       if (par_out) par_out[shot] = (int8_t)((pi + psel) & 1);
     }
     const bool fin = done || qlast >= npass;
-    if (key) key[shot] = fin ? 2 : (int8_t)pi;
+    if (key) key[shot] = shot_key(fin, pi, ur, csum);
     if (!fin) cum[shot] = csum;
   }
 }
 
-template <int NT>
-__global__ __launch_bounds__(64 * kWaves) void sample_mfma_kernel(
+// Passes [qbeg, qend) for blocks of 16 W slots; the workgroups of the grid
+// loop over the blocks that hold shots (with a partition, the counts come
+// from cnt), so the grid need not match the shot count.
+template <int NT, int W>
+__global__ __launch_bounds__(64 * W) void sample_mfma_kernel(
     const float* __restrict__ P, const SamplerGeom* __restrict__ geo, const float* __restrict__ lin,
     float* __restrict__ lout, long ldl2, const int32_t* __restrict__ perm, const int32_t* __restrict__ cnt,
     int8_t* __restrict__ par_out, float* __restrict__ cum, int8_t* __restrict__ key, int qbeg, int qend,
     int64_t shot0, int64_t nshots, int site, uint32_t k0, uint32_t k1, int32_t* __restrict__ out, int M) {
   __shared__ __attribute__((aligned(16))) float Bs0[512 * NT];
   __shared__ __attribute__((aligned(16))) float Bs1[512 * NT];
-  __shared__ int wdone[kWaves];
-  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, P, geo, lin, lout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend,
-                    shot0, nshots, site, k0, k1, out, M);
+  __shared__ int wdone[W];
+  constexpr int kS = 16 * W;
+  int64_t nblk = (nshots + kS - 1) / kS;
+  if (perm) {
+    const int64_t c0 = cnt[0], c1 = cnt[1];
+    const int64_t e = (c0 + kShotsPerWg - 1) / kShotsPerWg * kShotsPerWg;
+    nblk = e / kS + (c1 + kS - 1) / kS;
+  }
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
+    sample_passes<NT, W>(Bs0, Bs1, wdone, blk, P, geo, lin, lout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend,
+                         shot0, nshots, site, k0, k1, out, M);
 }
 
 // Batched sweep: one site step of several sampling requests in one launch.
@@ -476,7 +513,7 @@ __global__ __launch_bounds__(64 * kWaves) void sample_batch_kernel(const SampleB
   const int64_t blocks = (D.nshots + kShotsPerWg - 1) / kShotsPerWg + (part ? 1 : 0);
   if ((int64_t)blockIdx.x >= blocks) return;  // whole workgroup
   const int cur = (m - 1) & 1;
-  sample_passes<NT>(Bs0, Bs1, wdone, blockIdx.x, D.packed + D.poff[m], D.geo + m, D.fb[cur], D.fb[1 - cur],
+  sample_passes<NT, kWaves>(Bs0, Bs1, wdone, blockIdx.x, D.packed + D.poff[m], D.geo + m, D.fb[cur], D.fb[1 - cur],
                     D.ldl2, part ? D.perm : nullptr, part ? D.cnt : nullptr, next ? D.par : nullptr, nullptr, nullptr,
                     0, kSamplerMaxOutcomes, 0, D.nshots, m, D.k0, D.k1, D.out, D.M);
 }
@@ -538,7 +575,7 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
       if (s.valid && grp == 0) {
         out[(shot0 + s.shot) * (int64_t)M + (site - 1)] = 0;
         if (par_out) par_out[s.shot] = (int8_t)pb;
-        if (key) key[s.shot] = 2;
+        if (key) key[s.shot] = kKeyDone;
       }
     }
     return bb;
@@ -629,7 +666,7 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
         out[(shot0 + cur.shot) * (int64_t)M + (site - 1)] = psel;
         if (par_out) par_out[cur.shot] = (int8_t)((cur.pi + psel) & 1);
         const bool fin = done || geo->npass[cur.pi] <= 1;
-        if (key) key[cur.shot] = fin ? 2 : (int8_t)cur.pi;
+        if (key) key[cur.shot] = shot_key(fin, cur.pi, ur, csum);
         if (!fin) cum[cur.shot] = csum;
       }
 #pragma unroll
@@ -660,92 +697,132 @@ __device__ inline int block_sum256(int v, int* sh) {
 
 constexpr int kPartElems = 1024;  // parities per partition block (256 threads x 4)
 
+// Classes k = sector * B + bucket, B buckets per sector; any other value is
+// left out.  part_count: per block of kPartElems shots, the count of each
+// class; part_scatter: the stable counting sort by class, sector 0's classes
+// from slot 0 and sector 1's from slot E (sector 0's total rounded up to a
+// whole workgroup), so a workgroup never mixes sectors.
+template <int B>
 __device__ __forceinline__ void part_count(const int8_t* __restrict__ par, int64_t n, int32_t* __restrict__ bcnt,
                                            int64_t blk, int* sh) {
+  constexpr int K = 2 * B;
   const int64_t base = blk * kPartElems + 4 * threadIdx.x;
-  int c0 = 0, c1 = 0;
+  int c[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int v = base + j < n ? (int)par[base + j] : -1;
-    c0 += v == 0;
-    c1 += v == 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] += v == k;
   }
-  c0 = block_sum256(c0, sh);
-  c1 = block_sum256(c1, sh);
-  if (threadIdx.x == 0) {
-    bcnt[2 * blk] = c0;
-    bcnt[2 * blk + 1] = c1;
-  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] = block_sum256(c[k], sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) bcnt[K * blk + k] = c[k];
 }
 
+template <int B>
 __device__ __forceinline__ void part_scatter(const int8_t* __restrict__ par, int64_t n,
                                              const int32_t* __restrict__ bcnt, int nblk, int32_t* __restrict__ perm,
                                              int32_t* __restrict__ cnt, int blk, int* sh, int* wtot) {
+  constexpr int K = 2 * B, KP = (K + 1) / 2;  // classes, 16-bit pairs of them
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int before = 0, before1 = 0, tot = 0, tot1 = 0;
+  int before[K], tot[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) before[k] = tot[k] = 0;
   for (int i = tid; i < nblk; i += 256) {
-    const int v = bcnt[2 * i], v1 = bcnt[2 * i + 1];
-    tot += v;
-    tot1 += v1;
-    if (i < blk) {
-      before += v;
-      before1 += v1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int v = bcnt[K * i + k];
+      tot[k] += v;
+      if (i < blk) before[k] += v;
     }
   }
-  before = block_sum256(before, sh);
-  before1 = block_sum256(before1, sh);
-  tot = block_sum256(tot, sh);
-  tot1 = block_sum256(tot1, sh);
-  const int64_t c0 = tot;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    before[k] = block_sum256(before[k], sh);
+    tot[k] = block_sum256(tot[k], sh);
+  }
+  int64_t c0 = 0, c1 = 0;
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    c0 += tot[k];
+    c1 += tot[B + k];
+  }
   const int64_t e = (c0 + kShotsPerWg - 1) / kShotsPerWg * kShotsPerWg;
-  const int64_t blk0 = (int64_t)blk * kPartElems;
-  const int64_t base = blk0 + 4 * tid;
+  // first slot of each class for this block's shots
+  int64_t start[K];
+  {
+    int64_t run0 = 0, run1 = e;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      start[k] = run0 + before[k];
+      run0 += tot[k];
+      start[B + k] = run1 + before[B + k];
+      run1 += tot[B + k];
+    }
+  }
+  const int64_t base = (int64_t)blk * kPartElems + 4 * tid;
   int q[4];
-  int ne = 0, no = 0;
+  int pk[KP];  // this thread's class counts, two per int in 16-bit halves
+#pragma unroll
+  for (int i = 0; i < KP; ++i) pk[i] = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     q[j] = base + j < n ? (int)par[base + j] : -1;
-    ne += q[j] == 0;
-    no += q[j] == 1;
-  }
-  // exclusive scan of (even, odd) counts packed in 16-bit halves
-  const int v = ne | (no << 16);
-  int x = v;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
+    for (int k = 0; k < K; ++k)
+      if (q[j] == k) pk[k >> 1] += 1 << (16 * (k & 1));
   }
-  if (lane == 63) wtot[w] = x;
-  __syncthreads();
-  int wpre = 0;
-  for (int i = 0; i < w; ++i) wpre += wtot[i];
-  const int ex = x - v + wpre;
-  int64_t re = before + (ex & 0xffff);
-  int64_t ro = e + before1 + (ex >> 16);
+  // exclusive scan over the block of the packed counts (at most 1024 per
+  // class, so the halves never carry into each other)
+  int ex[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    int x = pk[i];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    int wpre = 0;
+    for (int v = 0; v < w; ++v) wpre += wtot[v];
+    ex[i] = x - pk[i] + wpre;
+  }
+  int64_t pos[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) pos[k] = start[k] + ((ex[k >> 1] >> (16 * (k & 1))) & 0xffff);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (q[j] == 0) perm[re++] = (int32_t)(base + j);
-    else if (q[j] == 1) perm[ro++] = (int32_t)(base + j);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (q[j] == k) perm[pos[k]++] = (int32_t)(base + j);
   }
   if (blk == 0 && tid == 0) {
     cnt[0] = (int32_t)c0;
-    cnt[1] = (int32_t)tot1;
+    cnt[1] = (int32_t)c1;
   }
 }
 
+template <int B>
 __global__ __launch_bounds__(256) void part_count_kernel(const int8_t* __restrict__ par, int64_t n,
                                                          int32_t* __restrict__ bcnt) {
   __shared__ int sh[4];
-  part_count(par, n, bcnt, blockIdx.x, sh);
+  part_count<B>(par, n, bcnt, blockIdx.x, sh);
 }
 
+template <int B>
 __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restrict__ par, int64_t n,
                                                            const int32_t* __restrict__ bcnt, int nblk,
                                                            int32_t* __restrict__ perm, int32_t* __restrict__ cnt) {
   __shared__ int sh[4];
   __shared__ int wtot[4];
-  part_scatter(par, n, bcnt, nblk, perm, cnt, blockIdx.x, sh, wtot);
+  part_scatter<B>(par, n, bcnt, nblk, perm, cnt, blockIdx.x, sh, wtot);
 }
 
 // Partition by the parities of request y's outcomes at its current site,
@@ -755,7 +832,7 @@ __global__ __launch_bounds__(256) void part_count_batch_kernel(const SampleBatch
   const SampleBatchDesc& D = desc[blockIdx.y];
   const int64_t nblk = (D.nshots + kPartElems - 1) / kPartElems;
   if (!D.psplit || D.site >= D.M || (int64_t)blockIdx.x >= nblk) return;
-  part_count(D.par, D.nshots, D.bcnt, blockIdx.x, sh);
+  part_count<1>(D.par, D.nshots, D.bcnt, blockIdx.x, sh);
 }
 
 __global__ __launch_bounds__(256) void part_scatter_batch_kernel(const SampleBatchDesc* __restrict__ desc) {
@@ -764,7 +841,7 @@ __global__ __launch_bounds__(256) void part_scatter_batch_kernel(const SampleBat
   const SampleBatchDesc& D = desc[blockIdx.y];
   const int64_t nblk = (D.nshots + kPartElems - 1) / kPartElems;
   if (!D.psplit || D.site >= D.M || (int64_t)blockIdx.x >= nblk) return;
-  part_scatter(D.par, D.nshots, D.bcnt, (int)nblk, D.perm, D.cnt, blockIdx.x, sh, wtot);
+  part_scatter<1>(D.par, D.nshots, D.bcnt, (int)nblk, D.perm, D.cnt, blockIdx.x, sh, wtot);
 }
 
 // First left vectors: L = e_0 (the site-1 left bond has dimension 1), as
@@ -889,7 +966,7 @@ hipError_t launch_pack_batch(hipStream_t st, const SamplerPackDesc* host, const 
 
 // Workgroups of a persistent launch: as many as the device runs at once
 // (resident workgroups per CU times the CU count), counted once per kernel.
-static int64_t persistent_grid(const void* kernel) {
+static int64_t persistent_grid(const void* kernel, int threads = 64 * kWaves) {
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, int64_t> known;
   int dev = 0;
@@ -899,7 +976,7 @@ static int64_t persistent_grid(const void* kernel) {
   if (it != known.end()) return it->second;
   int ncu = 0, per = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 64 * kWaves, 0) != hipSuccess || per < 1) per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
   const int64_t g = (int64_t)ncu * per;
   known[{dev, kernel}] = g;
   return g;
@@ -938,8 +1015,11 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom&
       hipLaunchKernelGGL((sample_first_kernel<NTV>), pg, dim3(64 * kWaves), 0, st, P, gd, lin, lout, ldl2, perm,   \
                          cnt, par_out, cum, key, shot0, nshots, site, k0, k1, out, M);                            \
     } else {                                                                                                      \
-      hipLaunchKernelGGL((sample_mfma_kernel<NTV>), grid, dim3(64 * kWaves), 0, st, P, gd, lin, lout, ldl2, perm,  \
-                         cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M);                \
+      const void* kf = (const void*)sample_mfma_kernel<NTV, kRestWaves>;                                          \
+      const int64_t nb = (nshots + 16 * kRestWaves - 1) / (16 * kRestWaves) + (perm ? kWaves / kRestWaves : 0);   \
+      const dim3 rg((unsigned)std::min<int64_t>(nb, kRestGridMult * persistent_grid(kf, 64 * kRestWaves)));       \
+      hipLaunchKernelGGL((sample_mfma_kernel<NTV, kRestWaves>), rg, dim3(64 * kRestWaves), 0, st, P, gd, lin,     \
+                         lout, ldl2, perm, cnt, par_out, cum, key, qbeg, qend, shot0, nshots, site, k0, k1, out, M); \
     }                                                                                                             \
     break;
   switch (nt) {
@@ -954,16 +1034,24 @@ hipError_t launch_sample_mfma(hipStream_t st, const float* P, const SamplerGeom&
   return hipGetLastError();
 }
 
-int64_t sampler_partition_ws(int64_t nshots) { return 2 * ((nshots + kPartElems - 1) / kPartElems); }
+int64_t sampler_partition_ws(int64_t nshots) {
+  return 2 * kKeyBuckets * ((nshots + kPartElems - 1) / kPartElems);
+}
 
 hipError_t launch_sampler_partition(hipStream_t st, const int8_t* par, int64_t nshots, int32_t* bcnt,
-                                    int32_t* perm, int32_t* cnt) {
+                                    int32_t* perm, int32_t* cnt, bool buckets) {
   if (nshots <= 0) return hipSuccess;
   if (nshots > INT32_MAX - 256) return hipErrorInvalidValue;
   const int nblk = (int)((nshots + kPartElems - 1) / kPartElems);
-  hipLaunchKernelGGL(part_count_kernel, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt);
-  hipLaunchKernelGGL(part_scatter_kernel, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt, nblk, perm,
-                     cnt);
+  if (buckets) {
+    hipLaunchKernelGGL(part_count_kernel<kKeyBuckets>, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt);
+    hipLaunchKernelGGL(part_scatter_kernel<kKeyBuckets>, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt,
+                       nblk, perm, cnt);
+  } else {
+    hipLaunchKernelGGL(part_count_kernel<1>, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt);
+    hipLaunchKernelGGL(part_scatter_kernel<1>, dim3((unsigned)nblk), dim3(256), 0, st, par, nshots, bcnt, nblk,
+                       perm, cnt);
+  }
   return hipGetLastError();
 }
 
