@@ -1061,54 +1061,129 @@ __global__ __launch_bounds__(512) void bj_solve_kernel(const cplx64* __restrict_
   for (int e = lane; e < kBP * kBP; e += nth) vo[e] = V[e / kBP][e % kBP];
 }
 
-// One half of the round's update, on FP64 matrix cores.  ROWS: the rows of
-// pair P of A, 32 columns at a time: A[P, c] <- V_P^H A[P, c].  COLS: the
-// columns of pair P, 32 rows at a time: A[c, P] <- A[c, P] V_P for y < nch,
-// and the same on the eigenvector matrix W for y >= nch.  Each wave forms one
-// 16 x 16 quadrant of the 32 x 32 complex tile (4 real MFMAs per complex
-// k-step).
-template <bool ROWS>
-__global__ __launch_bounds__(256) void bj_pass_kernel(cplx64* __restrict__ A, cplx64* __restrict__ Wv,
-                                                      const int* __restrict__ dims, long ld, long sA, int npb,
-                                                      int round, const cplx64* __restrict__ Vs,
-                                                      const int* __restrict__ vid, int nch) {
+// The eigenvector side of a round, on FP64 matrix cores: the columns of
+// pair P of W, 32 rows at a time, W[c, P] <- W[c, P] V_P.  Each wave forms
+// one 16 x 16 quadrant of the 32 x 32 complex tile (4 real MFMAs per complex
+// k-step), its fragments of V_P loaded straight into registers.
+__global__ __launch_bounds__(256) void bj_w_kernel(cplx64* __restrict__ Wv, const int* __restrict__ dims, long ld,
+                                                   long sA, int npb, int round, const cplx64* __restrict__ Vs,
+                                                   const int* __restrict__ vid) {
   typedef mma_traits<cplx64> T;
-  const int P = blockIdx.x, y = blockIdx.y, b = blockIdx.z;
+  const int P = blockIdx.x, b = blockIdx.z;
   const int n = dims ? dims[b] : (int)ld;
   const int npairs = npb / 2;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  __shared__ cplx64 X[kBP][kBP + 1], VP[kBP][kBP + 1];
+  __shared__ cplx64 X[kBP][kBP + 1];
   __shared__ int ip[kBP];
-  const bool onW = !ROWS && y >= nch;
-  const int c0 = kBP * (onW ? y - nch : y);
+  const int c0 = kBP * blockIdx.y;
   if (c0 >= n) return;
   if (vid[(long)b * npairs + P]) return;  // V_P = I
   if (tid == 0) bj_pair_idx(npb, round, P, n, ip);
   __syncthreads();
   if (ip[0] < 0 && ip[kBJ] < 0) return;  // pair entirely beyond n (uniform)
-  cplx64* m = (onW ? Wv : A) + (long)b * sA;
+  cplx64* m = Wv + (long)b * sA;
   const cplx64* vp = Vs + ((long)b * npairs + P) * kBP * kBP;
   for (int e = tid; e < kBP * kBP; e += 256) {
     const int i = e / kBP, j = e % kBP;
-    VP[i][j] = vp[e];
-    int gi, gj;
-    if (ROWS) { gi = ip[i]; gj = c0 + j; } else { gi = c0 + i; gj = ip[j]; }
-    X[i][j] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? m[(long)gi * ld + gj] : cmake<cplx64>(0.0, 0.0);
+    const int gi = c0 + i, gj = ip[j];
+    X[i][j] = (gi < n && gj >= 0) ? m[(long)gi * ld + gj] : cmake<cplx64>(0.0, 0.0);
   }
-  __syncthreads();
   const int qi = w >> 1, qj = w & 1;
+  cplx64 fv[kBP / 4];
+#pragma unroll
+  for (int s = 0; s < kBP / 4; ++s) fv[s] = vp[(4 * s + (lane >> 4)) * kBP + 16 * qj + (lane & 15)];
+  __syncthreads();
   T::R4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
 #pragma unroll
   for (int k0 = 0; k0 < kBP; k0 += 4) {
     const int k = k0 + (lane >> 4);
-    cplx64 av, bv;
-    if (ROWS) {
-      av = cconj(VP[k][16 * qi + (lane & 15)]);   // (V_P^H)[i][k]
-      bv = X[k][16 * qj + (lane & 15)];
-    } else {
-      av = X[16 * qi + (lane & 15)][k];
-      bv = VP[k][16 * qj + (lane & 15)];
-    }
+    const cplx64 av = X[16 * qi + (lane & 15)][k];
+    const cplx64 bv = fv[k0 / 4];
+    re = T::mma(av.re, bv.re, re);
+    re = T::mma(-av.im, bv.im, re);
+    im = T::mma(av.re, bv.im, im);
+    im = T::mma(av.im, bv.re, im);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gi = c0 + 16 * qi + T::row(lane, v), gj = ip[16 * qj + (lane & 15)];
+    if (gi < n && gj >= 0) m[(long)gi * ld + gj] = cmake<cplx64>(re[v], im[v]);
+  }
+}
+
+// The round's whole two-sided update A <- V^H A V of a Hermitian matrix, by
+// pair blocks: workgroup (P, Q), P <= Q, forms R = V_P^H A[P, Q] V_Q (rows
+// of pair P, columns of pair Q) and writes R and, for P < Q, its conjugate
+// transpose as block (Q, P); block (P, P) is written exactly Hermitian.  Each
+// entry of A is then read about half a time and written once per round
+// (the row and column passes read and write it twice each).  A pair whose
+// subproblem needed no rotation has V = I (its Vs slot is not written).
+__global__ __launch_bounds__(256) void bj_sym_kernel(cplx64* __restrict__ A, const int* __restrict__ dims, long ld,
+                                                     long sA, int npb, int round, const cplx64* __restrict__ Vs,
+                                                     const int* __restrict__ vid) {
+  typedef mma_traits<cplx64> T;
+  const int b = blockIdx.y;
+  const int n = dims ? dims[b] : (int)ld;
+  const int npairs = npb / 2;
+  int P = 0, r = blockIdx.x;
+  while (r >= npairs - P) {
+    r -= npairs - P;
+    ++P;
+  }
+  const int Q = P + r;
+  const int idP = vid[(long)b * npairs + P], idQ = vid[(long)b * npairs + Q];
+  if (idP && idQ) return;  // both identity: the block keeps its values
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  __shared__ cplx64 X[kBP][kBP + 1];
+  __shared__ int ipP[kBP], ipQ[kBP];
+  if (tid == 0) bj_pair_idx(npb, round, P, n, ipP);
+  if (tid == 1) bj_pair_idx(npb, round, Q, n, ipQ);
+  __syncthreads();
+  if ((ipP[0] < 0 && ipP[kBJ] < 0) || (ipQ[0] < 0 && ipQ[kBJ] < 0)) return;  // uniform
+  cplx64* m = A + (long)b * sA;
+  const cplx64* vp = Vs + ((long)b * npairs + P) * kBP * kBP;
+  const cplx64* vq = Vs + ((long)b * npairs + Q) * kBP * kBP;
+  for (int e = tid; e < kBP * kBP; e += 256) {
+    const int i = e / kBP, j = e % kBP;
+    const int gi = ipP[i], gj = ipQ[j];
+    X[i][j] = (gi >= 0 && gj >= 0) ? m[(long)gi * ld + gj] : cmake<cplx64>(0.0, 0.0);
+  }
+  const int qi = w >> 1, qj = w & 1;
+  // this lane's MFMA fragments of V_Q (column 16 qj + lane % 16) and V_P
+  // (column 16 qi + lane % 16), rows k = 4 s + lane / 16, straight from
+  // memory into registers
+  cplx64 fq[kBP / 4], fp[kBP / 4];
+#pragma unroll
+  for (int s = 0; s < kBP / 4; ++s) {
+    const int k = 4 * s + (lane >> 4), jq = 16 * qj + (lane & 15), jp = 16 * qi + (lane & 15);
+    fq[s] = idQ ? cmake<cplx64>(k == jq ? 1.0 : 0.0, 0.0) : vq[k * kBP + jq];
+    fp[s] = idP ? cmake<cplx64>(k == jp ? 1.0 : 0.0, 0.0) : vp[k * kBP + jp];
+  }
+  __syncthreads();
+  // Y = X V_Q, this wave's 16 x 16 quadrant
+  T::R4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll
+  for (int k0 = 0; k0 < kBP; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    const cplx64 av = X[16 * qi + (lane & 15)][k];
+    const cplx64 bv = fq[k0 / 4];
+    re = T::mma(av.re, bv.re, re);
+    re = T::mma(-av.im, bv.im, re);
+    im = T::mma(av.re, bv.im, im);
+    im = T::mma(av.im, bv.re, im);
+  }
+  __syncthreads();  // every wave is done reading X
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[16 * qi + T::row(lane, v)][16 * qj + (lane & 15)] = cmake<cplx64>(re[v], im[v]);
+  __syncthreads();
+  // R = V_P^H Y
+  re = T::R4{0, 0, 0, 0};
+  im = T::R4{0, 0, 0, 0};
+#pragma unroll
+  for (int k0 = 0; k0 < kBP; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    const cplx64 av = cconj(fp[k0 / 4]);
+    const cplx64 bv = X[k][16 * qj + (lane & 15)];
     re = T::mma(av.re, bv.re, re);
     re = T::mma(-av.im, bv.im, re);
     im = T::mma(av.re, bv.im, im);
@@ -1116,11 +1191,23 @@ __global__ __launch_bounds__(256) void bj_pass_kernel(cplx64* __restrict__ A, cp
   }
   __syncthreads();
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = 16 * qi + T::row(lane, v), j = 16 * qj + (lane & 15);
-    int gi, gj;
-    if (ROWS) { gi = ip[i]; gj = c0 + j; } else { gi = c0 + i; gj = ip[j]; }
-    if (gi >= 0 && gi < n && gj >= 0 && gj < n) m[(long)gi * ld + gj] = cmake<cplx64>(re[v], im[v]);
+  for (int v = 0; v < 4; ++v) X[16 * qi + T::row(lane, v)][16 * qj + (lane & 15)] = cmake<cplx64>(re[v], im[v]);
+  __syncthreads();
+  for (int e = tid; e < kBP * kBP; e += 256) {
+    const int i = e / kBP, j = e % kBP;
+    const int gi = ipP[i], gj = ipQ[j];
+    if (gi < 0 || gj < 0) continue;
+    // block (P, P): entry (i, j) below the diagonal from (j, i), so the
+    // stored matrix stays exactly Hermitian
+    m[(long)gi * ld + gj] = (P == Q && i > j) ? cconj(X[j][i]) : X[i][j];
+  }
+  if (P != Q) {
+    for (int e = tid; e < kBP * kBP; e += 256) {
+      const int j = e / kBP, i = e % kBP;  // row j of block (Q, P), columns i
+      const int gi = ipP[i], gj = ipQ[j];
+      if (gi < 0 || gj < 0) continue;
+      m[(long)gj * ld + gi] = cconj(X[i][j]);
+    }
   }
 }
 
@@ -1156,10 +1243,11 @@ hipError_t jacobi_herm_blocked(hipStream_t st, cplx64* A, cplx64* Vtmp, double* 
       hipLaunchKernelGGL(bj_solve_kernel, dim3(npairs, batch), dim3(512), 0, st, A, dims, ld, sA, npb, r, dm, 1e-15,
                          1, Vs, active, vid);
       const int nch = (nmax + kBP - 1) / kBP;
-      hipLaunchKernelGGL(bj_pass_kernel<true>, dim3(npairs, nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld, sA,
-                         npb, r, Vs, vid, nch);
-      hipLaunchKernelGGL(bj_pass_kernel<false>, dim3(npairs, 2 * nch, batch), dim3(256), 0, st, A, Vtmp, dims, ld,
-                         sA, npb, r, Vs, vid, nch);
+      // A <- V^H A V by pair blocks, then the eigenvector matrix W <- W V
+      hipLaunchKernelGGL(bj_sym_kernel, dim3(npairs * (npairs + 1) / 2, batch), dim3(256), 0, st, A, dims, ld, sA,
+                         npb, r, Vs, vid);
+      hipLaunchKernelGGL(bj_w_kernel, dim3(npairs, nch, batch), dim3(256), 0, st, Vtmp, dims, ld, sA, npb, r, Vs,
+                         vid);
     }
     e = hipMemcpyAsync(act.data(), active, batch * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
