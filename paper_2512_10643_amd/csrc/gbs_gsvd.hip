@@ -478,6 +478,68 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
       if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_NOT_PD);
       return;
     }
+  } else if (!in_lds) {
+    // Cholesky by block columns of kCholB (right looking) when the packed
+    // triangle lives in device memory: each block column is factored in LDS
+    // (the dynamic LDS is free on this path), written back once, and the
+    // trailing triangle takes its rank-kCholB update in one read and write,
+    // instead of one per column.
+    constexpr int kCholB = 16, kCP = kCholB + 1;  // block width, LDS row pitch
+    double* pan = lds;  // rows J..N2-1 of block column J, row-major
+    for (int J = 0; J < N2; J += kCholB) {
+      const int jb = min(kCholB, N2 - J), nr = N2 - J;
+      for (int e = tid; e < nr * jb; e += nt) {
+        const int i = e / jb, c = e % jb;
+        pan[i * kCP + c] = (i >= jb || c <= i) ? P[pk(J + i, J + c)] : 0.0;
+      }
+      wg_sync();
+      for (int c = 0; c < jb; ++c) {
+        if (tid == 0) {
+          const double dj = pan[c * kCP + c];
+          bad = !(dj > 0.0);
+          pan[c * kCP + c] = dj > 0.0 ? sqrt(dj) : 1.0;
+        }
+        wg_sync();
+        if (bad) {
+          if (tid == 0) gbs_set_error(a.err, GBS_DEVERR_NOT_PD);
+          return;
+        }
+        const double piv = pan[c * kCP + c];
+        for (int i = c + 1 + tid; i < nr; i += nt) pan[i * kCP + c] /= piv;
+        wg_sync();
+        // the block column's later columns t (rows i >= t)
+        const int w2 = jb - c - 1;
+        if (w2 > 0)
+          for (int e = tid; e < (nr - c - 1) * w2; e += nt) {
+            const int i = c + 1 + e / w2, t = c + 1 + e % w2;
+            if (t <= i) pan[i * kCP + t] -= pan[i * kCP + c] * pan[t * kCP + c];
+          }
+        wg_sync();
+      }
+      for (int e = tid; e < nr * jb; e += nt) {
+        const int i = e / jb, c = e % jb;
+        if (i >= jb || c <= i) P[pk(J + i, J + c)] = pan[i * kCP + c];
+      }
+      // trailing triangle, a packed row per group of 32 lanes (contiguous in k)
+      for (int i = jb + (tid >> 5); i < nr; i += nt >> 5) {
+        double li[kCholB];
+#pragma unroll
+        for (int c = 0; c < kCholB; ++c) li[c] = c < jb ? pan[i * kCP + c] : 0.0;
+        double* Pi = P + (long)(J + i) * (J + i + 1) / 2 + J;
+        for (int k = jb + (tid & 31); k <= i; k += 32) {
+          double acc = 0.0;
+#pragma unroll
+          for (int c = 0; c < kCholB; ++c)
+            if (c < jb) acc = fma(li[c], pan[k * kCP + c], acc);
+          Pi[k] -= acc;
+        }
+      }
+      wg_sync();
+    }
+    for (long e = tid; e < (long)N2 * N2; e += nt) {
+      int i = (int)(e / N2), j = (int)(e % N2);
+      Lm[(long)i * ld + j] = j <= i ? P[pk(i, j)] : 0.0;
+    }
   } else {
     // Cholesky (right looking, packed lower triangle).
     for (int j = 0; j < N2; ++j) {
