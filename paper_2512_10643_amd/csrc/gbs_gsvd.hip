@@ -877,37 +877,60 @@ __device__ void stage1_body(const GsvdArgs& a, int m) {
     const double sg = ((i >> 1) & 1) ? -1.41421356237309515 : 1.41421356237309515;
     XU[e] = (i & 1) ? 0.0 : sg * Z[(long)i * n + q];
   }
-  // With XU in LDS and room beside it, a column belongs to an aligned group
-  // of Gp lanes of one wave and each lane to a fixed set of rows (i = g mod
-  // Gp), so a reflector needs no barrier: the dot product is reduced by
-  // shuffles within the group and every lane updates only its own rows.  The
-  // reflectors are staged into LDS a few at a time (two barriers per group).
+  // With the columns in LDS and room beside them, a column belongs to an
+  // aligned group of Gp lanes of one wave and each lane to a fixed set of
+  // rows (i = g mod Gp), so a reflector needs no barrier: the dot product is
+  // reduced by shuffles within the group and every lane updates only its own
+  // rows.  The reflectors are staged into LDS a few at a time (two barriers
+  // per group).  When U lives in device memory (wide blocks), the columns go
+  // through LDS in chunks that leave room for 8 staged reflectors, each chunk
+  // taking every reflector (the columns are independent).
   const long lds_cap = (long)GBS_GSVD_LDS_N2 * (GBS_GSVD_LDS_N2 + 1) / 2;
-  const int nst = XU == lds ? (int)min(8L, (lds_cap - (long)n * N2) / N2) : 0;
-  if (nst >= 2 && n <= nt) {
-    int Gp = 64;
-    while (Gp > 1 && Gp * n > nt) Gp >>= 1;
-    const int cq = tid / Gp, gq = tid % Gp;
-    double* VS = lds + (long)n * N2;  // staged reflectors, slot s at VS[s N2 + j]
-    double* xc = XU + (long)cq * N2;
-    for (int kb = N2 - 3; kb >= 0; kb -= nst) {
-      const int kl = max(0, kb - nst + 1);
-      wg_sync();
-      for (int e = tid; e < (kb - kl + 1) * N2; e += nt) {
-        const int sl = e / N2, j = e % N2, k = kb - sl;
-        VS[e] = j < N2 - k - 1 ? Vh[(long)k * ld + j] : 0.0;
+  int nst = XU == lds ? (int)min(8L, (lds_cap - (long)n * N2) / N2) : 0;
+  int nc = n;
+  if (XU != lds) {
+    const int room = (int)(lds_cap / N2) - 8;  // columns per chunk
+    if (room >= 1) {
+      const int np = (n + room - 1) / room;
+      nc = (n + np - 1) / np;
+      nst = 8;
+    }
+  }
+  if (nst >= 2 && nc <= nt) {
+    for (int q0 = 0; q0 < n; q0 += nc) {
+      const int ncc = min(nc, n - q0);
+      if (XU != lds) {
+        wg_sync();
+        for (long e = tid; e < (long)ncc * N2; e += nt) lds[e] = XU[(long)q0 * N2 + e];
       }
-      wg_sync();
-      if (cq < n) {
-        for (int k = kb; k >= kl; --k) {
-          const double* v = VS + (long)(kb - k) * N2 - (k + 1);  // v[i]: entry of row i
-          const int i0 = k + 1 <= gq ? gq : gq + (k + 1 - gq + Gp - 1) / Gp * Gp;
-          double acc = 0.0;
-          for (int i = i0; i < N2; i += Gp) acc += v[i] * xc[i];
-          for (int off = Gp >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-          const double w = acc * tauL[k];
-          for (int i = i0; i < N2; i += Gp) xc[i] -= w * v[i];
+      int Gp = 64;
+      while (Gp > 1 && Gp * ncc > nt) Gp >>= 1;
+      const int cq = tid / Gp, gq = tid % Gp;
+      double* VS = lds + (long)ncc * N2;  // staged reflectors, slot s at VS[s N2 + j]
+      double* xc = lds + (long)cq * N2;
+      for (int kb = N2 - 3; kb >= 0; kb -= nst) {
+        const int kl = max(0, kb - nst + 1);
+        wg_sync();
+        for (int e = tid; e < (kb - kl + 1) * N2; e += nt) {
+          const int sl = e / N2, j = e % N2, k = kb - sl;
+          VS[e] = j < N2 - k - 1 ? Vh[(long)k * ld + j] : 0.0;
         }
+        wg_sync();
+        if (cq < ncc) {
+          for (int k = kb; k >= kl; --k) {
+            const double* v = VS + (long)(kb - k) * N2 - (k + 1);  // v[i]: entry of row i
+            const int i0 = k + 1 <= gq ? gq : gq + (k + 1 - gq + Gp - 1) / Gp * Gp;
+            double acc = 0.0;
+            for (int i = i0; i < N2; i += Gp) acc += v[i] * xc[i];
+            for (int off = Gp >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            const double w = acc * tauL[k];
+            for (int i = i0; i < N2; i += Gp) xc[i] -= w * v[i];
+          }
+        }
+      }
+      if (XU != lds) {
+        wg_sync();
+        for (long e = tid; e < (long)ncc * N2; e += nt) XU[(long)q0 * N2 + e] = lds[e];
       }
     }
   } else {
