@@ -68,19 +68,43 @@ hipError_t ensure_pool(hipStream_t st) {
 // Owning device allocation list.  With a stream, allocations are stream
 // ordered (hipMallocAsync / hipFreeAsync on that stream), so releasing a
 // temporary arena never waits for other streams; without one they are plain
-// hipMalloc / hipFree (buffers owned by a handle).
+// hipMalloc / hipFree (buffers owned by a handle).  A temporary arena (made
+// with a stream) hands out buffers below kArenaChunk from chunks of that
+// size by a bump pointer, so a build makes a few pool calls instead of one
+// allocation and one free per buffer (each costs tens of microseconds of
+// host time, and the frees at the end of a build leave the device idle);
+// its buffers are all freed together.
+constexpr size_t kArenaChunk = 64ull << 20;
 struct DevArena {
   std::vector<void*> ptrs;
   int64_t bytes = 0;
   hipStream_t st = nullptr;
   bool ordered = false;
+  bool pack = false;         // sub-allocate small buffers (temporary arenas)
+  char* cur = nullptr;       // free space left in the current chunk
+  size_t left = 0;
   DevArena() = default;
-  explicit DevArena(hipStream_t s) : st(s), ordered(true) {}
+  explicit DevArena(hipStream_t s) : st(s), ordered(true), pack(true) {}
   DevArena(const DevArena&) = delete;
   DevArena& operator=(const DevArena&) = delete;
   hipError_t alloc(void** p, size_t n) {
     if (n == 0) n = 16;
     n = (n + 255) & ~(size_t)255;
+    if (pack && n <= kArenaChunk / 2) {
+      if (n > left) {
+        void* c = nullptr;
+        hipError_t e = hipMallocAsync(&c, kArenaChunk, st);
+        if (e != hipSuccess) return e;
+        ptrs.push_back(c);
+        cur = (char*)c;
+        left = kArenaChunk;
+      }
+      *p = cur;
+      cur += n;
+      left -= n;
+      bytes += (int64_t)n;
+      return hipSuccess;
+    }
     hipError_t e = ordered ? hipMallocAsync(p, n, st) : hipMalloc(p, n);
     if (e == hipSuccess) {
       ptrs.push_back(*p);
@@ -88,7 +112,8 @@ struct DevArena {
     }
     return e;
   }
-  void release(void* p) {  // one buffer of this arena
+  void release(void* p) {  // one buffer of an arena that does not sub-allocate
+    if (pack) return;       // its buffers go with the arena
     for (size_t i = 0; i < ptrs.size(); ++i)
       if (ptrs[i] == p) {
         (void)(ordered ? hipFreeAsync(p, st) : hipFree(p));
@@ -100,6 +125,8 @@ struct DevArena {
     for (void* p : ptrs) (void)(ordered ? hipFreeAsync(p, st) : hipFree(p));
     ptrs.clear();
     bytes = 0;
+    cur = nullptr;
+    left = 0;
   }
   ~DevArena() { release_all(); }
 };
