@@ -222,8 +222,70 @@ C czero() {
 // eigenvalues are the squared singular values, and their eigen-decompositions,
 // are FP64; the gauge transforms that produce the stored tensors run in the
 // build precision CT.
+// A second stream of the calling thread on the current device (default
+// priority), kept for the life of the thread, for work that overlaps a
+// build's own stream.
+hipError_t side_stream(hipStream_t* out) {
+  thread_local std::vector<std::pair<int, hipStream_t>> own;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  for (auto& pr : own)
+    if (pr.first == dev) {
+      *out = pr.second;
+      return hipSuccess;
+    }
+  hipStream_t s = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  own.push_back({dev, s});
+  *out = s;
+  return hipSuccess;
+}
+
+// The sampler's photon-parity masks of a reduced-precision build (a chain of
+// small launches, bond after bond) run on a side stream while the build's
+// own stream runs the FP64 norm chain; the normalisation of site 1 waits for
+// the side stream to be done reading site 1.  The destructor waits for the
+// side stream, so its work never outlives the build's temporaries.
+struct MaskJob {
+  hipStream_t side = nullptr;
+  int32_t* mask = nullptr;      // (M + 1) x maxbond ints
+  hipEvent_t ready = nullptr;   // final tensors on the build's stream
+  hipEvent_t site1 = nullptr;   // side stream past site 1
+  bool launched = false;
+  MaskJob() = default;
+  MaskJob(const MaskJob&) = delete;
+  MaskJob& operator=(const MaskJob&) = delete;
+  ~MaskJob() {
+    if (launched) (void)hipStreamSynchronize(side);
+    if (ready) (void)hipEventDestroy(ready);
+    if (site1) (void)hipEventDestroy(site1);
+  }
+};
+
+hipError_t launch_masks(gbs_mps_s* h, hipStream_t st, DevArena& tmp, MaskJob& mj) {
+  const int M = h->M, d = h->d, mb = h->maxbond;
+  const size_t bytes = (size_t)(M + 1) * mb * sizeof(int32_t);
+  hipError_t e = tmp.alloc((void**)&mj.mask, bytes);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&mj.ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&mj.site1, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(mj.ready, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(mj.side, mj.ready, 0);
+  if (e != hipSuccess) return e;
+  mj.launched = true;
+  e = hipMemsetAsync(mj.mask, 0, bytes, mj.side);
+  for (int m = 1; m <= M && e == hipSuccess; ++m) {
+    e = launch_sector_mask(mj.side, (const cplx32*)h->tens + h->toff[m], h->bond[m - 1], d, h->bond[m],
+                           m == 1 ? nullptr : mj.mask + (long)(m - 1) * mb, mj.mask + (long)m * mb);
+    if (e == hipSuccess && m == 1) e = hipEventRecord(mj.site1, mj.side);
+  }
+  return e;
+}
+
 template <typename CT>
-int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64, const std::vector<long>& t64off) {
+int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64, const std::vector<long>& t64off,
+                 MaskJob* mj) {
   typedef cplx64 C;
   const int M = h->M, d = h->d;
   const double tau = h->trunc_rel > 0 ? h->trunc_rel * h->trunc_rel : (std::is_same<CT, cplx64>::value ? 1e-24 : 1e-16);
@@ -502,6 +564,9 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
   // (6) normalise and fix the phase
   h->bond = r;
   h->maxbond = *std::max_element(r.begin(), r.end());
+  if (mj && mj->side && !std::is_same<CT, cplx64>::value && h->maxbond <= 2 * kSamplerMaxSector &&
+      d <= kSamplerMaxOutcomes && !(h->flags & GBS_DENSE_SAMPLER))
+    HIP_CHECK_RET(launch_masks(h, st, tmp, *mj));
   HIP_CHECK_RET(dalloc(h->keep, &h->bond_dev, M + 1));
   HIP_CHECK_RET(hipMemcpyAsync(h->bond_dev, r.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   std::vector<void*> ptrs(M);
@@ -553,6 +618,7 @@ int canonicalize(gbs_mps_s* h, hipStream_t st, DevArena& tmp, const cplx64* T64,
     cur = 1 - cur;
   }
   if (reduced) nrm2_dev = (const double*)(Lb + (long)cur * eld * eld);  // real part of the 1 x 1 L_M
+  if (mj && mj->launched) HIP_CHECK_RET(hipStreamWaitEvent(st, mj->site1, 0));
   HIP_CHECK_RET(normalize_mps<CT>(st, out + h->toff[1], d * r[1], vac + (long)cur * eld, nrm2_dev, nrm));
   HIP_CHECK_RET(hipMemcpyAsync(&h->norm_raw, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK_RET(hipStreamSynchronize(st));
@@ -1126,8 +1192,10 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     return GBS_OK;
   }
   // ---- truncation sweep and canonical form
-  int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off)
-                                 : canonicalize<cplx32>(h, st, tmp, T64, t64off);
+  MaskJob mj;
+  if (h->prec != GBS_FP64) HIP_CHECK_RET(side_stream(&mj.side));
+  int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off, nullptr)
+                                 : canonicalize<cplx32>(h, st, tmp, T64, t64off, &mj);
   if (rc) return rc;
   if (h->prec != GBS_FP64 && h->maxbond <= 2 * kSamplerMaxSector && d <= kSamplerMaxOutcomes) {
     // Photon-parity sector of every bond index, read off the site tensors
@@ -1137,7 +1205,11 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     const int mb = h->maxbond;
     bool split = !(h->flags & GBS_DENSE_SAMPLER);
     std::vector<int32_t> hm((size_t)(M + 1) * mb, 0);
-    if (split) {
+    if (split && mj.launched) {
+      // the masks ran beside the norm chain
+      HIP_CHECK_RET(hipMemcpyAsync(hm.data(), mj.mask, hm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, mj.side));
+      HIP_CHECK_RET(hipStreamSynchronize(mj.side));
+    } else if (split) {
       int32_t* mask = nullptr;
       HIP_CHECK_RET(tmp.alloc((void**)&mask, hm.size() * sizeof(int32_t)));
       HIP_CHECK_RET(hipMemsetAsync(mask, 0, hm.size() * sizeof(int32_t), st));
