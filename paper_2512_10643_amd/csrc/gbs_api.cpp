@@ -1192,8 +1192,10 @@ int build_impl(const double* gamma, int M, const gbs_build_opts* opt, hipStream_
     return GBS_OK;
   }
   // ---- truncation sweep and canonical form
+  // (served builds, whose keep arena is stream ordered, stay on their own
+  // stream: concurrent slots already share the device's hardware queues)
   MaskJob mj;
-  if (h->prec != GBS_FP64) HIP_CHECK_RET(side_stream(&mj.side));
+  if (h->prec != GBS_FP64 && !h->keep.ordered) HIP_CHECK_RET(side_stream(&mj.side));
   int rc = (h->prec == GBS_FP64) ? canonicalize<cplx64>(h, st, tmp, T64, t64off, nullptr)
                                  : canonicalize<cplx32>(h, st, tmp, T64, t64off, &mj);
   if (rc) return rc;
