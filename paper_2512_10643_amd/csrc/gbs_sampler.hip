@@ -685,17 +685,24 @@ __global__ __launch_bounds__(64 * kWaves) void sample_first_kernel(
 }
 #undef GBS_MF
 
-// Sum over the 256 threads of a block (every thread gets the total).
-__device__ inline int block_sum256(int v, int* sh) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return sh[0] + sh[1] + sh[2] + sh[3];
-}
-
 constexpr int kPartElems = 1024;  // parities per partition block (256 threads x 4)
+
+// N sums over the 256 threads of a block at once (every thread gets all N):
+// one exchange through LDS (sh: 4 N ints) instead of one per value.
+template <int N>
+__device__ inline void block_sums256(int (&v)[N], int* sh) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[(threadIdx.x >> 6) * N + i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = sh[i] + sh[N + i] + sh[2 * N + i] + sh[3 * N + i];
+}
 
 // Classes k = sector * B + bucket, B buckets per sector; any other value is
 // left out.  part_count: per block of kPartElems shots, the count of each
@@ -716,8 +723,7 @@ __device__ __forceinline__ void part_count(const int8_t* __restrict__ par, int64
 #pragma unroll
     for (int k = 0; k < K; ++k) c[k] += v == k;
   }
-#pragma unroll
-  for (int k = 0; k < K; ++k) c[k] = block_sum256(c[k], sh);
+  block_sums256<K>(c, sh);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < K; ++k) bcnt[K * blk + k] = c[k];
@@ -740,11 +746,8 @@ __device__ __forceinline__ void part_scatter(const int8_t* __restrict__ par, int
       if (i < blk) before[k] += v;
     }
   }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    before[k] = block_sum256(before[k], sh);
-    tot[k] = block_sum256(tot[k], sh);
-  }
+  block_sums256<K>(before, sh);
+  block_sums256<K>(tot, sh);
   int64_t c0 = 0, c1 = 0;
 #pragma unroll
   for (int k = 0; k < B; ++k) {
@@ -812,7 +815,7 @@ __device__ __forceinline__ void part_scatter(const int8_t* __restrict__ par, int
 template <int B>
 __global__ __launch_bounds__(256) void part_count_kernel(const int8_t* __restrict__ par, int64_t n,
                                                          int32_t* __restrict__ bcnt) {
-  __shared__ int sh[4];
+  __shared__ int sh[8 * B];
   part_count<B>(par, n, bcnt, blockIdx.x, sh);
 }
 
@@ -820,7 +823,7 @@ template <int B>
 __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restrict__ par, int64_t n,
                                                            const int32_t* __restrict__ bcnt, int nblk,
                                                            int32_t* __restrict__ perm, int32_t* __restrict__ cnt) {
-  __shared__ int sh[4];
+  __shared__ int sh[8 * B];
   __shared__ int wtot[4];
   part_scatter<B>(par, n, bcnt, nblk, perm, cnt, blockIdx.x, sh, wtot);
 }
@@ -828,7 +831,7 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int8_t* __restr
 // Partition by the parities of request y's outcomes at its current site,
 // for the next site (requests at their last site, or without sectors, skip).
 __global__ __launch_bounds__(256) void part_count_batch_kernel(const SampleBatchDesc* __restrict__ desc) {
-  __shared__ int sh[4];
+  __shared__ int sh[8];  // 4 x (2 classes)
   const SampleBatchDesc& D = desc[blockIdx.y];
   const int64_t nblk = (D.nshots + kPartElems - 1) / kPartElems;
   if (!D.psplit || D.site >= D.M || (int64_t)blockIdx.x >= nblk) return;
@@ -836,7 +839,7 @@ __global__ __launch_bounds__(256) void part_count_batch_kernel(const SampleBatch
 }
 
 __global__ __launch_bounds__(256) void part_scatter_batch_kernel(const SampleBatchDesc* __restrict__ desc) {
-  __shared__ int sh[4];
+  __shared__ int sh[8];  // 4 x (2 classes)
   __shared__ int wtot[4];
   const SampleBatchDesc& D = desc[blockIdx.y];
   const int64_t nblk = (D.nshots + kPartElems - 1) / kPartElems;
